@@ -1,0 +1,199 @@
+/*
+ * fmm.h -- C-ABI of the MI355X (gfx950) fast multipole library for 3D Laplace
+ * potentials and forces, after Yokota & Barba, "Hierarchical N-body
+ * simulations with auto-tuning for heterogeneous systems" (arXiv 1108.5815).
+ *
+ * What is computed (paper: introduction; "Results", Laplace potential and
+ * force): for N particles with positions x_i and charges q_i,
+ *     phi_i = sum_{j != i, x_j != x_i} q_j / |x_i - x_j|
+ *     E_i   = -grad phi_i = sum_{j != i, x_j != x_i} q_j (x_i - x_j) / |x_i - x_j|^3
+ * approximated by a hierarchical method: adaptive octree (cells hold at most
+ * ncrit particles), dual tree traversal with the acceptance criterion
+ * theta = (r_t + r_s)/R ("Dual tree traversal"; "Results"), and spherical
+ * harmonic expansions of order p (degrees 0..p) for the far field, with
+ * particle-particle sums for the near field.
+ *
+ * Conventions shared by every entry point
+ *  - A context owns every internal device buffer and is bound to one device
+ *    and one HIP stream.  All device work is enqueued on that stream.
+ *  - Pointers named "device" must be device (or managed) memory readable by
+ *    the context's device; pointers named "host" are ordinary host memory.
+ *  - Arrays are structure-of-arrays, one value per particle, in the caller's
+ *    particle order, contiguous, of the element type named by the dtype
+ *    argument (FMM_F32 = float, FMM_F64 = double).
+ *  - Every call returns an fmm_status and never aborts.  On error the context
+ *    stays valid; fmm_last_error() returns a message owned by the context,
+ *    valid until the next call on it.  A context is not thread-safe; distinct
+ *    contexts are independent.
+ */
+#ifndef FMM_H_
+#define FMM_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fmm_ctx_s *fmm_ctx;
+
+typedef enum {
+    FMM_OK = 0,
+    FMM_ERR_INVALID_ARG = 1,   /* bad size, pointer, parameter or non-finite input */
+    FMM_ERR_OUT_OF_MEMORY = 2, /* a device allocation failed */
+    FMM_ERR_DEVICE = 3,        /* a HIP call or kernel launch failed */
+    FMM_ERR_STATE = 4,         /* call made out of order (e.g. evaluate before traverse) */
+    FMM_ERR_UNSUPPORTED = 5    /* valid request this build does not implement */
+} fmm_status;
+
+/* Choice of interaction for each accepted cell pair ("Kernel pre-calculation";
+ * "Results"): the FMM always converts multipoles into local expansions
+ * (cell-cell, M2L); the treecode always evaluates multipoles at the target
+ * particles (cell-particle, M2P); the hybrid picks, per pair, the kind of
+ * smallest modelled time among M2L, M2P and particle-particle (P2P). */
+typedef enum {
+    FMM_POLICY_FMM = 0,
+    FMM_POLICY_TREECODE = 1,
+    FMM_POLICY_HYBRID_TIMED = 2, /* unit costs from fmm_tune() or fmm_set_costs() */
+    FMM_POLICY_HYBRID_MLP = 3    /* learned cost model */
+} fmm_policy;
+
+typedef enum {
+    FMM_PREC_FP32 = 0,       /* FP32 kernels, FP64 per-target final sum */
+    FMM_PREC_SPLIT_BF16 = 1, /* M2L as split-BF16 products on MFMA, FP32 accumulate */
+    FMM_PREC_FP64 = 2
+} fmm_precision;
+
+typedef enum { FMM_F32 = 0, FMM_F64 = 1 } fmm_dtype;
+
+enum { FMM_LIST_M2L = 0, FMM_LIST_M2P = 1, FMM_LIST_P2P = 2 };
+
+/* Largest supported expansion order. */
+#define FMM_P_MAX 16
+
+/* Create a context on HIP device `device`, enqueueing on `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  *out receives the handle. */
+fmm_status fmm_create(fmm_ctx *out, int device, void *hip_stream);
+
+/* Release every buffer of the context.  NULL is accepted. */
+void fmm_destroy(fmm_ctx ctx);
+
+/* Message of the last failed call on ctx ("" if none). */
+const char *fmm_last_error(fmm_ctx ctx);
+
+/* Re-bind the context to another stream of the same device. */
+fmm_status fmm_set_stream(fmm_ctx ctx, void *hip_stream);
+
+/*
+ * Tree build (paper: "Hierarchical N-body algorithms", clustering into a
+ * hierarchy of cells; "Results", N_crit is the maximum number of particles
+ * per cell).
+ *   n            number of particles, 0 <= n < 2^31 (n = 0 is a no-op)
+ *   dtype        element type of x, y, z, q
+ *   x, y, z, q   device arrays of n values; read during the call and copied
+ *                into the context (Morton-sorted), so they may be reused or
+ *                freed once the context's stream has passed this call
+ *   ncrit        leaf capacity, >= 1: a cell holding more than ncrit particles
+ *                splits into its non-empty octants (not below level 21)
+ * The bounding cube is anchored at the minimum corner with side equal to the
+ * largest extent; coordinates are quantised to 21 bits per axis in FP64 and
+ * interleaved into 63-bit Morton keys (x lowest).  Particles are sorted by
+ * (key, original index).  Non-finite coordinates give FMM_ERR_INVALID_ARG.
+ * Synchronises the stream once per tree level.
+ */
+fmm_status fmm_build_tree(fmm_ctx ctx, int64_t n, int dtype, const void *x, const void *y,
+                          const void *z, const void *q, int32_t ncrit);
+
+/*
+ * Dual tree traversal (paper: "Dual tree traversal"; "Results" for the
+ * criterion): from the root pair, the larger cell of each pair is split
+ * (both when of equal size); a new pair is accepted when
+ * (r_t + r_s)^2 <= theta^2 R^2 with r the half side of each cube and R the
+ * distance between cube centres; a pair of leaves that is not accepted is a
+ * particle-particle interaction; any other pair is split again.  Accepted
+ * pairs get M2L, M2P or P2P by `policy`.
+ *   p      expansion order, 0 <= p <= FMM_P_MAX (degrees 0..p)
+ *   theta  in (0, 1)
+ * Requires a built tree.  Synchronises the stream once per traversal level.
+ */
+fmm_status fmm_traverse(fmm_ctx ctx, int32_t p, double theta, int32_t policy);
+
+/*
+ * Evaluation: P2M at leaves, M2M upward, M2L / M2P / P2P over the lists,
+ * L2L downward, L2P at leaves, and the per-target sum, written in the
+ * caller's original particle order.
+ *   precision  an fmm_precision
+ *   out_dtype  element type of the outputs (FMM_F32 or FMM_F64)
+ *   phi, ex, ey, ez  device arrays of n values (caller-owned); E = -grad phi
+ * Requires a completed traversal.  Asynchronous on the context stream.
+ */
+fmm_status fmm_evaluate(fmm_ctx ctx, int32_t precision, int32_t out_dtype, void *phi, void *ex,
+                        void *ey, void *ez);
+
+/*
+ * Unit costs of the timed hybrid (paper: "Kernel pre-calculation"): the
+ * modelled time of an accepted pair is c_m2l for M2L, c_m2p * n_t for M2P and
+ * (c_p2p * n_t) * n_s for P2P (n_t, n_s = particles of the target and source
+ * cell, FP64); the least wins, ties go to M2L, then M2P.  All > 0.
+ */
+fmm_status fmm_set_costs(fmm_ctx ctx, double c_m2l, double c_m2p, double c_p2p);
+fmm_status fmm_get_costs(fmm_ctx ctx, double *costs3_host);
+
+/*
+ * Kernel pre-calculation (paper: "Kernel pre-calculation"): time the M2L, M2P
+ * and P2P kernels on artificial coordinates, charges and expansions at order
+ * p and store the unit costs used by FMM_POLICY_HYBRID_TIMED.  Needs no tree.
+ */
+fmm_status fmm_tune(fmm_ctx ctx, int32_t p, int32_t precision);
+
+/* ---------------- introspection (host outputs, for checking) ---------------- */
+
+/* Counts after the last build/traverse.  Any pointer may be NULL. */
+fmm_status fmm_get_sizes(fmm_ctx ctx, int64_t *n_cells, int64_t *n_m2l, int64_t *n_m2p,
+                         int64_t *n_p2p);
+
+/* M2L pairs after the last traversal, split into those converted by the
+ * batched same-level GEMM (matrix cores) and those converted one by one
+ * (mixed levels or offsets outside the per-octant tables).  NULL allowed. */
+fmm_status fmm_get_m2l_split(fmm_ctx ctx, int64_t *n_batched, int64_t *n_general);
+
+/* Bounding cube: lo3_host[3] minimum corner, side_host[1] side. */
+fmm_status fmm_get_bbox(fmm_ctx ctx, double *lo3_host, double *side_host);
+
+/* Sorted Morton keys and permutation (perm[k] = original index of the k-th
+ * sorted particle); host arrays of n entries. */
+fmm_status fmm_get_keys(fmm_ctx ctx, uint64_t *sorted_keys_host, int32_t *perm_host);
+
+/* Cells in breadth-first (level, key) order; host arrays of n_cells entries
+ * (centre_h: 3 per cell, half-grid units of side/2^22; radius_h: half side in
+ * the same units).  Any pointer may be NULL. */
+fmm_status fmm_get_cells(fmm_ctx ctx, int32_t *level, uint64_t *prefix, int32_t *begin,
+                         int32_t *end, int32_t *parent, int32_t *first_child, int32_t *nchild,
+                         int32_t *centre_h, int32_t *radius_h);
+
+/* Interaction list `kind` (FMM_LIST_*) as (target cell, source cell) pairs,
+ * grouped by target in increasing order; host arrays of the list's size. */
+fmm_status fmm_get_list(fmm_ctx ctx, int32_t kind, int32_t *tgt_host, int32_t *src_host);
+
+/* Scaled expansions after fmm_evaluate: per cell (p+1)^2 reals, degree n at
+ * offset n*n as [Re c_n^0, Re c_n^1, Im c_n^1, ..., Re c_n^n, Im c_n^n], in
+ * the Greengard-Rokhlin normalisation, multipoles divided by r^n and locals
+ * multiplied by r^(n+1) (r = cell half side).  Host arrays n_cells*(p+1)^2. */
+fmm_status fmm_get_expansions(fmm_ctx ctx, float *multipole_host, float *local_host);
+
+/* Milliseconds of the phases of the last build/traverse/evaluate (recorded
+ * only while timing is enabled), in the order: bbox+keys, sort, tree,
+ * traverse, lists, p2m+m2m, m2l (batched GEMM), m2l (general pairs), l2l,
+ * p2p, far+final.  Writes min(cap, 11) values; returns their count in
+ * *count. */
+fmm_status fmm_get_timings(fmm_ctx ctx, double *ms_host, int32_t cap, int32_t *count);
+
+/* Enable (1) or disable (0) per-phase timing events (adds synchronisation). */
+fmm_status fmm_set_timing(fmm_ctx ctx, int32_t enabled);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FMM_H_ */

@@ -77,10 +77,15 @@ def lib():
         L.ora_local_series.argtypes = [ctypes.c_int, vp, vp, vp]
         L.ora_bbox.argtypes = [I64, vp, vp, vp, vp, vp]
         L.ora_morton.argtypes = [I64, vp, vp, vp, vp, ctypes.c_double, vp]
+        L.ora_num_threads.restype = ctypes.c_int
         L.ora_interleave.restype = ctypes.c_uint64
         L.ora_interleave.argtypes = [ctypes.c_uint64] * 3
         _lib = L
     return _lib
+
+
+def num_threads() -> int:
+    return int(lib().ora_num_threads())
 
 
 def _p(a: np.ndarray):

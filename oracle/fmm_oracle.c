@@ -33,8 +33,21 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef double complex cplx;
+
+/* threads the OpenMP loops of the oracle use */
+int ora_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 #define ORA_MAXLEVEL 21
 #define ORA_PMAX 40
@@ -431,23 +444,26 @@ void ora_get_list(void *hv, int kind, int32_t *t, int32_t *s)
 /*  Coefficient arrays hold all m = -n..n at index n*n + n + m.         */
 /* ------------------------------------------------------------------ */
 static double FACT[171];
+static double ATAB[2 * ORA_PMAX + 2][2 * ORA_PMAX + 2];
 static int fact_ready = 0;
 
+/* factorials and the table of A_n^m = (-1)^n / sqrt((n-m)!(n+m)!), 0 <= m <= n */
 static void init_fact(void)
 {
     if (fact_ready) return;
     FACT[0] = 1.0;
     for (int k = 1; k <= 170; k++) FACT[k] = FACT[k - 1] * (double)k;
+    for (int n = 0; n <= 2 * ORA_PMAX + 1; n++)
+        for (int m = 0; m <= n; m++)
+            ATAB[n][m] = ((n & 1) ? -1.0 : 1.0) / sqrt(FACT[n - m] * FACT[n + m]);
     fact_ready = 1;
 }
 
 static inline int cidx(int n, int m) { return n * n + n + m; }
 
-static double Anm(int n, int m)
-{
-    double s = (n & 1) ? -1.0 : 1.0;
-    return s / sqrt(FACT[n - m] * FACT[n + m]);
-}
+static inline double Anm(int n, int m) { return ATAB[n][m]; }
+
+__attribute__((constructor)) static void ora_init(void) { init_fact(); }
 
 static cplx ipow(int e)
 {

@@ -1,0 +1,214 @@
+"""ctypes binding of ``libfmm.so``; names follow the C entry points of ``include/fmm.h``.
+
+The library must have been built (``python -m paper_1108_5815_amd.build``); a
+missing library raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libfmm.so")
+
+POLICY_FMM, POLICY_TREECODE, POLICY_HYBRID_TIMED, POLICY_HYBRID_MLP = 0, 1, 2, 3
+PREC_FP32, PREC_SPLIT_BF16, PREC_FP64 = 0, 1, 2
+F32, F64 = 0, 1
+LIST_M2L, LIST_M2P, LIST_P2P = 0, 1, 2
+
+_STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "DEVICE", 4: "STATE", 5: "UNSUPPORTED"}
+
+_lib = None
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+class FMMError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+def lib():
+    """Load libfmm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(f"{_LIB_PATH} is missing: build it with `python -m paper_1108_5815_amd.build`")
+    L = ctypes.CDLL(_LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "fmm_create": ([ctypes.POINTER(vp), ctypes.c_int, vp], ctypes.c_int),
+        "fmm_destroy": ([vp], None),
+        "fmm_last_error": ([vp], ctypes.c_char_p),
+        "fmm_set_stream": ([vp, vp], ctypes.c_int),
+        "fmm_build_tree": ([vp, i64, ctypes.c_int, vp, vp, vp, vp, i32], ctypes.c_int),
+        "fmm_traverse": ([vp, i32, dbl, i32], ctypes.c_int),
+        "fmm_evaluate": ([vp, i32, i32, vp, vp, vp, vp], ctypes.c_int),
+        "fmm_set_costs": ([vp, dbl, dbl, dbl], ctypes.c_int),
+        "fmm_get_costs": ([vp, vp], ctypes.c_int),
+        "fmm_tune": ([vp, i32, i32], ctypes.c_int),
+        "fmm_get_sizes": ([vp, vp, vp, vp, vp], ctypes.c_int),
+        "fmm_get_bbox": ([vp, vp, vp], ctypes.c_int),
+        "fmm_get_m2l_split": ([vp, vp, vp], ctypes.c_int),
+        "fmm_get_keys": ([vp, vp, vp], ctypes.c_int),
+        "fmm_get_cells": ([vp] + [vp] * 9, ctypes.c_int),
+        "fmm_get_list": ([vp, i32, vp, vp], ctypes.c_int),
+        "fmm_get_expansions": ([vp, vp, vp], ctypes.c_int),
+        "fmm_get_timings": ([vp, vp, i32, vp], ctypes.c_int),
+        "fmm_set_timing": ([vp, i32], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class FMM:
+    """One context of the library on one device and stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self._torch = torch
+        self.device = int(device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+        h = ctypes.c_void_p()
+        st = lib().fmm_create(ctypes.byref(h), self.device, ctypes.c_void_p(stream))
+        if st != 0:
+            raise FMMError(st, "fmm_create failed")
+        self.h = h
+        self.n = 0
+        self.p = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().fmm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _ck(self, st):
+        if st != 0:
+            msg = lib().fmm_last_error(self.h)
+            raise FMMError(st, msg.decode() if msg else "")
+
+    # ------------------------------------------------------------ method
+    def build_tree(self, x, y, z, q, ncrit: int):
+        t = self._torch
+        dt = x.dtype
+        if dt not in (t.float32, t.float64):
+            raise TypeError("positions must be float32 or float64")
+        for a in (x, y, z, q):
+            if a.dtype != dt or not a.is_cuda or not a.is_contiguous() or a.numel() != x.numel():
+                raise ValueError("x, y, z, q must be contiguous device tensors of one dtype and length")
+        self.n = x.numel()
+        self._ck(lib().fmm_build_tree(self.h, self.n, F64 if dt == t.float64 else F32, x.data_ptr(),
+                                      y.data_ptr(), z.data_ptr(), q.data_ptr(), int(ncrit)))
+
+    def traverse(self, p: int, theta: float, policy: int = POLICY_FMM):
+        self._ck(lib().fmm_traverse(self.h, int(p), float(theta), int(policy)))
+        self.p = int(p)
+
+    def evaluate(self, precision: int = PREC_FP32, out_dtype=None, out=None):
+        """Returns (phi, E) as device tensors in the input particle order."""
+        t = self._torch
+        if out is None:
+            od = t.float32 if out_dtype is None else out_dtype
+            phi = t.empty(self.n, dtype=od, device=f"cuda:{self.device}")
+            E = t.empty((3, self.n), dtype=od, device=f"cuda:{self.device}")
+        else:
+            phi, E = out
+        od = F64 if phi.dtype == t.float64 else F32
+        self._ck(lib().fmm_evaluate(self.h, int(precision), od, phi.data_ptr(), E[0].data_ptr(),
+                                    E[1].data_ptr(), E[2].data_ptr()))
+        return phi, E
+
+    def set_costs(self, c_m2l: float, c_m2p: float, c_p2p: float):
+        self._ck(lib().fmm_set_costs(self.h, float(c_m2l), float(c_m2p), float(c_p2p)))
+
+    def costs(self):
+        out = np.zeros(3)
+        self._ck(lib().fmm_get_costs(self.h, _ptr(out)))
+        return out
+
+    def tune(self, p: int, precision: int = PREC_FP32):
+        self._ck(lib().fmm_tune(self.h, int(p), int(precision)))
+
+    def set_timing(self, on: bool):
+        self._ck(lib().fmm_set_timing(self.h, 1 if on else 0))
+
+    # ------------------------------------------------------------ introspection
+    def sizes(self):
+        v = [ctypes.c_int64() for _ in range(4)]
+        self._ck(lib().fmm_get_sizes(self.h, *(ctypes.byref(a) for a in v)))
+        return dict(cells=v[0].value, m2l=v[1].value, m2p=v[2].value, p2p=v[3].value)
+
+    def m2l_split(self):
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        self._ck(lib().fmm_get_m2l_split(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def general_pairs(self) -> int:
+        return self.m2l_split()[1]
+
+    def bbox(self):
+        lo = np.zeros(3)
+        side = np.zeros(1)
+        self._ck(lib().fmm_get_bbox(self.h, _ptr(lo), _ptr(side)))
+        return lo, float(side[0])
+
+    def keys(self):
+        k = np.zeros(self.n, dtype=np.uint64)
+        perm = np.zeros(self.n, dtype=np.int32)
+        self._ck(lib().fmm_get_keys(self.h, _ptr(k), _ptr(perm)))
+        return k, perm
+
+    def cells(self) -> dict:
+        c = self.sizes()["cells"]
+        out = dict(level=np.zeros(c, np.int32), prefix=np.zeros(c, np.uint64), begin=np.zeros(c, np.int32),
+                   end=np.zeros(c, np.int32), parent=np.zeros(c, np.int32), first_child=np.zeros(c, np.int32),
+                   nchild=np.zeros(c, np.int32), centre_h=np.zeros((c, 3), np.int32),
+                   radius_h=np.zeros(c, np.int32))
+        self._ck(lib().fmm_get_cells(self.h, *(_ptr(out[k]) for k in
+                                              ("level", "prefix", "begin", "end", "parent", "first_child",
+                                               "nchild", "centre_h", "radius_h"))))
+        return out
+
+    def list(self, kind: int):
+        m = self.sizes()[{0: "m2l", 1: "m2p", 2: "p2p"}[kind]]
+        t = np.zeros(m, np.int32)
+        s = np.zeros(m, np.int32)
+        self._ck(lib().fmm_get_list(self.h, int(kind), _ptr(t), _ptr(s)))
+        return t, s
+
+    def expansions(self):
+        c = self.sizes()["cells"]
+        K = (self.p + 1) ** 2
+        M = np.zeros(c * K, np.float32)
+        L = np.zeros(c * K, np.float32)
+        self._ck(lib().fmm_get_expansions(self.h, _ptr(M), _ptr(L)))
+        return M.reshape(c, K), L.reshape(c, K)
+
+    def timings(self) -> dict:
+        ms = np.zeros(11)
+        cnt = ctypes.c_int32()
+        self._ck(lib().fmm_get_timings(self.h, _ptr(ms), 11, ctypes.byref(cnt)))
+        names = ["keys", "sort", "tree", "traverse", "lists", "p2m_m2m", "m2l_gemm", "m2l_general", "l2l", "p2p",
+                 "far_final"]
+        return dict(zip(names, ms[:cnt.value].tolist()))

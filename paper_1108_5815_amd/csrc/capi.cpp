@@ -1,0 +1,816 @@
+// capi.cpp -- context, device buffers and phase orchestration behind fmm.h.
+//
+// Phases (paper: tree construction, dual tree traversal, kernel evaluation;
+// "Results"): build_tree = bounding cube -> Morton keys -> stable radix sort
+// -> permuted points -> adaptive octree level by level -> geometry;
+// traverse = frontier expansion level by level -> lists grouped by target ->
+// batching of same-level M2L; evaluate = P2M -> M2M (bottom-up) -> M2L
+// (GEMM + general) -> L2L (top-down) -> P2P -> L2P + M2P + final sum.
+// Everything runs on the context's stream; the host reads back only sizes
+// (one small copy per tree level and per traversal level).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/fmm.h"
+#include "fmm_internal.h"
+#include "host_ops.h"
+
+using namespace fmm;
+
+namespace {
+
+struct Buf {
+    void* p = nullptr;
+    size_t cap = 0;
+};
+
+enum { PH_KEYS, PH_SORT, PH_TREE, PH_TRAV, PH_LISTS, PH_UP, PH_M2L, PH_M2LG, PH_DOWN, PH_P2P, PH_FAR, PH_N };
+
+}  // namespace
+
+struct fmm_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    std::vector<Buf*> bufs;
+
+    // timing
+    bool timing = false;
+    hipEvent_t ev[PH_N + 1] = {};
+    double ms[PH_N] = {};
+
+    // particles and tree
+    int64_t n = 0;
+    int dtype = 0;
+    int32_t ncrit = 0;
+    double lo[3] = {0, 0, 0}, side = 1;
+    bool built = false, traversed = false;
+    int32_t ncell = 0, nleaf = 0;
+    std::vector<int32_t> lvl;  // cells of level L: [lvl[L], lvl[L+1])
+    Buf keys, keys2, idx, idx2, pts, ws, small;
+    Buf c_begin, c_end, c_parent, c_child, c_nchild, c_level, c_prefix, c_geo, c_ctr, leaves, tmp1, tmp2;
+
+    // traversal
+    int p = -1;
+    double theta = 0;
+    int policy = 0;
+    double costs[3] = {0, 0, 0};
+    bool costs_set = false;
+    Buf fr0, fr1, cnt, off4;
+    Buf raw[3], tgt[3], src[3], off[3];
+    int64_t nlist[3] = {0, 0, 0};
+    Buf tgt2, src2;
+
+    // same-level M2L batching
+    M2LPlan plan;
+    Buf d_slot, d_offid, d_T;
+    Buf has_fast, rkey, rval, rkey2, rval2, rowof, gather, general;
+    GemmPlan gp{};
+    int ntiles = 0;
+    int64_t nrows = 0;
+    int64_t ngeneral = 0;
+    bool gemm_on = false;
+
+    // operator tables
+    HostTables ht;
+    Buf d_m2m, d_l2l, d_w, d_g, d_h, d_rc;
+
+    // learned cost model weights (device)
+    Buf d_mlp;
+    bool mlp_ready = false;
+
+    // expansions and near-field partials
+    Buf M, L, nearb;
+
+    // pinned host staging
+    void* host = nullptr;
+
+    fmm_ctx_s() {
+        Buf* all[] = {&keys, &keys2, &idx, &idx2, &pts, &ws, &small, &c_begin, &c_end, &c_parent, &c_child,
+                      &c_nchild, &c_level, &c_prefix, &c_geo, &c_ctr, &leaves, &tmp1, &tmp2, &fr0, &fr1,
+                      &cnt, &off4, &raw[0], &raw[1], &raw[2], &tgt[0], &tgt[1], &tgt[2], &src[0], &src[1],
+                      &src[2], &off[0], &off[1], &off[2], &tgt2, &src2, &d_slot, &d_offid, &d_T, &has_fast,
+                      &rkey, &rval, &rkey2, &rval2, &rowof, &gather, &general, &d_m2m, &d_l2l, &d_w, &d_g,
+                      &d_h, &d_rc, &d_mlp, &M, &L, &nearb};
+        for (Buf* b : all) bufs.push_back(b);
+    }
+};
+
+namespace {
+
+struct Fail {
+    fmm_status st;
+    std::string msg;
+};
+
+[[noreturn]] void fail(fmm_status st, const std::string& m) { throw Fail{st, m}; }
+
+void ck(hipError_t e, const char* what) {
+    if (e != hipSuccess) fail(FMM_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void check_launch(const char* what) { ck(hipGetLastError(), what); }
+
+// grow-only device buffer; contents are not preserved
+template <class T>
+T* need(fmm_ctx c, Buf& b, size_t count) {
+    size_t bytes = std::max<size_t>(count * sizeof(T), 256);
+    if (b.cap >= bytes) return (T*)b.p;
+    if (b.p) {
+        ck(hipStreamSynchronize(c->stream), "sync");
+        ck(hipFree(b.p), "hipFree");
+    }
+    b.p = nullptr;
+    b.cap = 0;
+    size_t nb = bytes + bytes / 4;
+    hipError_t e = hipMalloc(&b.p, nb);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        b.p = nullptr;
+        fail(FMM_ERR_OUT_OF_MEMORY, "device allocation of " + std::to_string(nb) + " bytes failed");
+    }
+    b.cap = nb;
+    return (T*)b.p;
+}
+
+// grow-only buffer that keeps its first `keep` bytes
+template <class T>
+T* need_keep(fmm_ctx c, Buf& b, size_t count, size_t keep_count) {
+    size_t bytes = std::max<size_t>(count * sizeof(T), 256);
+    if (b.cap >= bytes) return (T*)b.p;
+    size_t nb = bytes + bytes / 2;
+    void* np = nullptr;
+    hipError_t e = hipMalloc(&np, nb);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(FMM_ERR_OUT_OF_MEMORY, "device allocation of " + std::to_string(nb) + " bytes failed");
+    }
+    if (b.p && keep_count) ck(hipMemcpyAsync(np, b.p, keep_count * sizeof(T), hipMemcpyDeviceToDevice, c->stream), "copy");
+    if (b.p) {
+        ck(hipStreamSynchronize(c->stream), "sync");
+        ck(hipFree(b.p), "hipFree");
+    }
+    b.p = np;
+    b.cap = nb;
+    return (T*)b.p;
+}
+
+void* host_stage(fmm_ctx c) {
+    if (!c->host) ck(hipHostMalloc(&c->host, 1 << 16, hipHostMallocDefault), "hipHostMalloc");
+    return c->host;
+}
+
+template <class T>
+void to_host(fmm_ctx c, T* dst, const void* src, size_t count) {
+    if (count == 0) return;
+    ck(hipMemcpyAsync(dst, src, count * sizeof(T), hipMemcpyDeviceToHost, c->stream), "D2H");
+    ck(hipStreamSynchronize(c->stream), "sync");
+}
+
+template <class T>
+void to_dev(fmm_ctx c, void* dst, const T* src, size_t count) {
+    if (count == 0) return;
+    ck(hipMemcpyAsync(dst, src, count * sizeof(T), hipMemcpyHostToDevice, c->stream), "H2D");
+    ck(hipStreamSynchronize(c->stream), "sync");
+}
+
+CellArrays cells_of(fmm_ctx c) {
+    CellArrays a;
+    a.begin = (int32_t*)c->c_begin.p;
+    a.end = (int32_t*)c->c_end.p;
+    a.parent = (int32_t*)c->c_parent.p;
+    a.child = (int32_t*)c->c_child.p;
+    a.nchild = (int32_t*)c->c_nchild.p;
+    a.level = (int32_t*)c->c_level.p;
+    a.prefix = (uint64_t*)c->c_prefix.p;
+    a.geo = (int4*)c->c_geo.p;
+    a.ctr = (double4*)c->c_ctr.p;
+    return a;
+}
+
+void ensure_cells(fmm_ctx c, size_t count, size_t keep) {
+    need_keep<int32_t>(c, c->c_begin, count, keep);
+    need_keep<int32_t>(c, c->c_end, count, keep);
+    need_keep<int32_t>(c, c->c_parent, count, keep);
+    need_keep<int32_t>(c, c->c_child, count, keep);
+    need_keep<int32_t>(c, c->c_nchild, count, keep);
+    need_keep<int32_t>(c, c->c_level, count, keep);
+    need_keep<uint64_t>(c, c->c_prefix, count, keep);
+}
+
+void mark(fmm_ctx c, int ph) {
+    if (c->timing) ck(hipEventRecord(c->ev[ph], c->stream), "event");
+}
+
+Tables tables_of(fmm_ctx c) {
+    Tables t;
+    t.m2m = (const float*)c->d_m2m.p;
+    t.l2l = (const float*)c->d_l2l.p;
+    t.wm2l = (const float*)c->d_w.p;
+    t.gl2p = (const float*)c->d_g.p;
+    t.hm2p = (const float*)c->d_h.p;
+    t.rcoef = (const float*)c->d_rc.p;
+    return t;
+}
+
+template <class F>
+fmm_status guarded(fmm_ctx c, F f) {
+    if (!c) return FMM_ERR_INVALID_ARG;
+    c->err.clear();
+    try {
+        ck(hipSetDevice(c->device), "hipSetDevice");
+        f();
+        return FMM_OK;
+    } catch (const Fail& e) {
+        c->err = e.msg;
+        return e.st;
+    } catch (const std::bad_alloc&) {
+        c->err = "host allocation failed";
+        return FMM_ERR_OUT_OF_MEMORY;
+    } catch (const std::exception& e) {
+        c->err = e.what();
+        return FMM_ERR_INVALID_ARG;
+    }
+}
+
+int bits_for(int64_t v) {
+    int b = 1;
+    while (b < 32 && ((int64_t)1 << b) <= v) b++;
+    return b;
+}
+
+// ------------------------------------------------------------------ build
+void build_tree_impl(fmm_ctx c, int64_t n, int dtype, const void* x, const void* y, const void* z,
+                     const void* q, int32_t ncrit) {
+    if (n < 0 || n >= ((int64_t)1 << 31)) fail(FMM_ERR_INVALID_ARG, "n out of range");
+    if (ncrit < 1) fail(FMM_ERR_INVALID_ARG, "ncrit must be >= 1");
+    if (dtype != FMM_F32 && dtype != FMM_F64) fail(FMM_ERR_INVALID_ARG, "dtype must be FMM_F32 or FMM_F64");
+    if (n > 0 && (!x || !y || !z || !q)) fail(FMM_ERR_INVALID_ARG, "null input pointer");
+    c->built = false;
+    c->traversed = false;
+    c->n = n;
+    c->dtype = dtype;
+    c->ncrit = ncrit;
+    c->ncell = 0;
+    c->nleaf = 0;
+    c->lvl.assign(1, 0);
+    if (n == 0) {
+        c->lo[0] = c->lo[1] = c->lo[2] = 0;
+        c->side = 1;
+        c->built = true;
+        return;
+    }
+    hipStream_t s = c->stream;
+    mark(c, PH_KEYS);
+    size_t wsb = std::max({sort_ws_bytes(n), bbox_ws_bytes(n), scan_ws_bytes(n)});
+    void* ws = need<char>(c, c->ws, wsb);
+    double* d6 = need<double>(c, c->small, 32);
+    uint32_t* dbad = (uint32_t*)(d6 + 8);
+    bbox(x, y, z, dtype, n, d6, dbad, ws, s);
+    check_launch("bbox");
+    double* h = (double*)host_stage(c);
+    to_host<double>(c, h, d6, 9);
+    uint32_t bad = ((uint32_t*)(h + 8))[0];
+    if (bad) fail(FMM_ERR_INVALID_ARG, "non-finite coordinate in input");
+    double sd = 0;
+    for (int d = 0; d < 3; d++) {
+        c->lo[d] = h[d];
+        double e = h[3 + d] - h[d];
+        if (e > sd) sd = e;
+    }
+    if (sd == 0.0) sd = 1.0;
+    c->side = sd;
+    double scale = 2097152.0 / sd;
+    uint64_t* keys = need<uint64_t>(c, c->keys, n);
+    uint64_t* keys2 = need<uint64_t>(c, c->keys2, n);
+    uint32_t* idx = need<uint32_t>(c, c->idx, n);
+    uint32_t* idx2 = need<uint32_t>(c, c->idx2, n);
+    morton_keys(x, y, z, dtype, n, c->lo[0], c->lo[1], c->lo[2], scale, keys, idx, s);
+    check_launch("morton");
+    mark(c, PH_SORT);
+    sort_u64(keys, idx, keys2, idx2, n, 0, 63, ws, s);
+    check_launch("sort");
+    float4* pts = need<float4>(c, c->pts, n);
+    permute_points(x, y, z, q, dtype, n, idx, pts, s);
+    check_launch("permute");
+    mark(c, PH_TREE);
+    // root
+    size_t cap = (size_t)std::max<int64_t>(1024, 2 * n / std::max(ncrit, 1) + 1024);
+    ensure_cells(c, cap, 0);
+    {
+        int32_t* hi = (int32_t*)host_stage(c);
+        hi[0] = 0;
+        hi[1] = (int32_t)n;
+        hi[2] = -1;
+        hi[3] = 0;
+        hi[4] = -1;
+        hi[5] = 0;
+        ck(hipMemcpyAsync(c->c_begin.p, hi + 0, 4, hipMemcpyHostToDevice, s), "H2D");
+        ck(hipMemcpyAsync(c->c_end.p, hi + 1, 4, hipMemcpyHostToDevice, s), "H2D");
+        ck(hipMemcpyAsync(c->c_parent.p, hi + 2, 4, hipMemcpyHostToDevice, s), "H2D");
+        ck(hipMemcpyAsync(c->c_level.p, hi + 3, 4, hipMemcpyHostToDevice, s), "H2D");
+        ck(hipMemcpyAsync(c->c_child.p, hi + 4, 4, hipMemcpyHostToDevice, s), "H2D");
+        ck(hipMemcpyAsync(c->c_nchild.p, hi + 5, 4, hipMemcpyHostToDevice, s), "H2D");
+        ck(hipMemsetAsync(c->c_prefix.p, 0, 8, s), "memset");
+        ck(hipStreamSynchronize(s), "sync");
+    }
+    int32_t total = 1;
+    for (int L = 0; L < kMaxLevel + 1; L++) {
+        int32_t c0 = c->lvl[L], c1 = total;
+        int32_t m = c1 - c0;
+        uint32_t* nsplit = need<uint32_t>(c, c->tmp1, m + 1);
+        uint32_t* choff = need<uint32_t>(c, c->tmp2, m + 1);
+        CellArrays ca = cells_of(c);
+        tree_count(keys, ca, c0, c1, L, ncrit, nsplit, s);
+        scan_u32(nsplit, choff, (uint32_t*)(d6 + 12), m, ws, s);
+        check_launch("tree count");
+        uint32_t* hh = (uint32_t*)host_stage(c);
+        to_host<uint32_t>(c, hh, d6 + 12, 1);
+        uint32_t nnew = hh[0];
+        if ((size_t)c1 + nnew > c->c_begin.cap / sizeof(int32_t)) ensure_cells(c, (size_t)c1 + nnew, c1);
+        ca = cells_of(c);
+        tree_emit(keys, ca, c0, c1, L, nsplit, choff, s);
+        check_launch("tree emit");
+        c->lvl.push_back(c1);
+        total = c1 + (int32_t)nnew;
+        if (nnew == 0) break;
+    }
+    c->ncell = total;
+    if (c->lvl.back() != total) c->lvl.push_back(total);
+    need<int4>(c, c->c_geo, total);
+    need<double4>(c, c->c_ctr, total);
+    cell_geometry(cells_of(c), total, c->lo[0], c->lo[1], c->lo[2], c->side, s);
+    check_launch("geometry");
+    // leaves in cell order
+    uint32_t* flag = need<uint32_t>(c, c->tmp1, total + 1);
+    uint32_t* pos = need<uint32_t>(c, c->tmp2, total + 1);
+    if (scan_ws_bytes(total) > c->ws.cap) {
+        ws = need<char>(c, c->ws, scan_ws_bytes(total));
+        d6 = (double*)c->small.p;
+    }
+    leaf_flags(cells_of(c), total, flag, s);
+    scan_u32(flag, pos, (uint32_t*)(d6 + 12), total, ws, s);
+    int32_t* lv = need<int32_t>(c, c->leaves, total);
+    leaf_write(cells_of(c), total, pos, lv, s);
+    check_launch("leaves");
+    uint32_t* hh = (uint32_t*)host_stage(c);
+    to_host<uint32_t>(c, hh, d6 + 12, 1);
+    c->nleaf = (int32_t)hh[0];
+    mark(c, PH_TRAV);
+    c->built = true;
+}
+
+// ------------------------------------------------------------------ traverse
+void upload_tables(fmm_ctx c, int p) {
+    if (c->ht.p == p) return;
+    build_tables(p, c->ht);
+    HostTables& t = c->ht;
+    to_dev(c, need<float>(c, c->d_m2m, t.m2m.size()), t.m2m.data(), t.m2m.size());
+    to_dev(c, need<float>(c, c->d_l2l, t.l2l.size()), t.l2l.data(), t.l2l.size());
+    to_dev(c, need<float>(c, c->d_w, t.wm2l.size()), t.wm2l.data(), t.wm2l.size());
+    to_dev(c, need<float>(c, c->d_g, t.gl2p.size()), t.gl2p.data(), t.gl2p.size());
+    to_dev(c, need<float>(c, c->d_h, t.hm2p.size()), t.hm2p.data(), t.hm2p.size());
+    to_dev(c, need<float>(c, c->d_rc, t.rcoef.size()), t.rcoef.data(), t.rcoef.size());
+}
+
+void upload_plan(fmm_ctx c, int p, double theta) {
+    if (c->plan.p == p && c->plan.theta == theta) return;
+    build_m2l_plan(p, theta, c->plan);
+    M2LPlan& pl = c->plan;
+    to_dev(c, need<int32_t>(c, c->d_slot, pl.slot_of.size()), pl.slot_of.data(), pl.slot_of.size());
+    to_dev(c, need<int32_t>(c, c->d_offid, pl.offid.size()), pl.offid.data(), pl.offid.size());
+    to_dev(c, need<float>(c, c->d_T, pl.T.size()), pl.T.data(), pl.T.size());
+}
+
+void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
+    if (!c->built) fail(FMM_ERR_STATE, "fmm_traverse before fmm_build_tree");
+    if (p < 0 || p > FMM_P_MAX) fail(FMM_ERR_INVALID_ARG, "p out of range");
+    if (!(theta > 0.0 && theta < 1.0)) fail(FMM_ERR_INVALID_ARG, "theta must lie in (0, 1)");
+    if (policy < 0 || policy > 3) fail(FMM_ERR_INVALID_ARG, "unknown policy");
+    if (policy == FMM_POLICY_HYBRID_TIMED && !c->costs_set)
+        fail(FMM_ERR_STATE, "timed hybrid needs unit costs (fmm_tune or fmm_set_costs)");
+    if (policy == FMM_POLICY_HYBRID_MLP && !c->mlp_ready)
+        fail(FMM_ERR_STATE, "learned hybrid needs a trained cost model");
+    c->traversed = false;
+    c->p = p;
+    c->theta = theta;
+    c->policy = policy;
+    for (int k = 0; k < 3; k++) c->nlist[k] = 0;
+    hipStream_t s = c->stream;
+    upload_tables(c, p);
+    int32_t nc = c->ncell;
+    if (nc == 0) {
+        c->traversed = true;
+        return;
+    }
+    TravParams tp;
+    tp.theta2 = theta * theta;
+    tp.policy = policy;
+    tp.c_m2l = c->costs[0];
+    tp.c_m2p = c->costs[1];
+    tp.c_p2p = c->costs[2];
+    tp.mlp = policy == FMM_POLICY_HYBRID_MLP ? (const float*)c->d_mlp.p : nullptr;
+    CellArrays ca = cells_of(c);
+    void* ws = c->ws.p;
+    double* d6 = (double*)c->small.p;
+    int64_t nf = 0;
+    int2* fr = need<int2>(c, c->fr0, 1024);
+    if (nc == 1) {
+        // the root is a leaf: one particle-particle interaction with itself
+        int2* r = need<int2>(c, c->raw[2], 1);
+        int2 h2 = make_int2(0, 0);
+        to_dev(c, r, &h2, 1);
+        c->nlist[2] = 1;
+    } else {
+        int2 h2 = make_int2(0, 0);
+        to_dev(c, fr, &h2, 1);
+        nf = 1;
+    }
+    while (nf > 0) {
+        size_t need_ws = scan_ws_bytes(nf);
+        if (need_ws > c->ws.cap) {
+            ck(hipStreamSynchronize(s), "sync");
+            ws = need<char>(c, c->ws, std::max(need_ws, c->ws.cap));
+        }
+        uint4* cnt = need<uint4>(c, c->cnt, nf);
+        uint4* off = need<uint4>(c, c->off4, nf);
+        fr = (int2*)c->fr0.p;
+        trav_count(fr, nf, ca, tp, cnt, s);
+        scan_u32x4(cnt, off, (uint4*)(d6 + 16), nf, ws, s);
+        check_launch("traverse count");
+        uint32_t* hh = (uint32_t*)host_stage(c);
+        to_host<uint32_t>(c, hh, d6 + 16, 4);
+        int64_t add[4] = {hh[0], hh[1], hh[2], hh[3]};
+        int2* lists[3];
+        for (int k = 0; k < 3; k++)
+            lists[k] = need_keep<int2>(c, c->raw[k], c->nlist[k] + add[k] + 1, c->nlist[k]);
+        int2* next = need<int2>(c, c->fr1, add[3] + 1);
+        trav_emit(fr, nf, ca, tp, off, c->nlist[0], c->nlist[1], c->nlist[2], lists[0], lists[1], lists[2],
+                  next, s);
+        check_launch("traverse emit");
+        for (int k = 0; k < 3; k++) c->nlist[k] += add[k];
+        std::swap(c->fr0, c->fr1);
+        nf = add[3];
+    }
+    mark(c, PH_LISTS);
+    int bits = bits_for(nc);
+    for (int k = 0; k < 3; k++) {
+        int64_t m = c->nlist[k];
+        uint32_t* tg = need<uint32_t>(c, c->tgt[k], m + 1);
+        uint32_t* sr = need<uint32_t>(c, c->src[k], m + 1);
+        int32_t* of = need<int32_t>(c, c->off[k], (size_t)nc + 1);
+        if (m > 0) {
+            size_t wsn = sort_ws_bytes(m);
+            if (wsn > c->ws.cap) {
+                ck(hipStreamSynchronize(s), "sync");
+                ws = need<char>(c, c->ws, wsn);
+            }
+            uint32_t* tg2 = need<uint32_t>(c, c->tgt2, m);
+            uint32_t* sr2 = need<uint32_t>(c, c->src2, m);
+            split_pairs((int2*)c->raw[k].p, m, tg, sr, s);
+            sort_u32(tg, sr, tg2, sr2, m, 0, bits, ws, s);
+        }
+        csr_offsets(tg, m, nc, of, s);
+        check_launch("lists");
+    }
+    // same-level M2L batching for the matrix cores
+    c->gemm_on = m2l_gemm_supported(p) && c->nlist[0] > 0;
+    c->ntiles = 0;
+    c->nrows = 0;
+    c->ngeneral = 0;
+    int64_t nm = c->nlist[0];
+    uint32_t* gen = need<uint32_t>(c, c->general, nm + 1);
+    if (c->gemm_on) {
+        upload_plan(c, p, theta);
+        int R = c->plan.R, J = c->plan.J;
+        uint32_t* hf = need<uint32_t>(c, c->has_fast, nc);
+        ck(hipMemsetAsync(hf, 0, (size_t)nc * 4, s), "memset");
+        m2l_mark_targets((uint32_t*)c->tgt[0].p, (uint32_t*)c->src[0].p, nm, ca, (int32_t*)c->d_slot.p, R, hf, s);
+        uint32_t* rk = need<uint32_t>(c, c->rkey, nc);
+        uint32_t* rv = need<uint32_t>(c, c->rval, nc);
+        uint32_t* rk2 = need<uint32_t>(c, c->rkey2, nc);
+        uint32_t* rv2 = need<uint32_t>(c, c->rval2, nc);
+        row_class_keys(hf, ca, nc, rk, rv, s);
+        size_t wsn = sort_ws_bytes(nc);
+        if (wsn > c->ws.cap) {
+            ck(hipStreamSynchronize(s), "sync");
+            ws = need<char>(c, c->ws, wsn);
+        }
+        sort_u32(rk, rv, rk2, rv2, nc, 0, 8, ws, s);
+        int32_t* d9 = (int32_t*)(d6 + 20);
+        class_bounds(rk, nc, d9, s);
+        check_launch("m2l classes");
+        int32_t* h9 = (int32_t*)host_stage(c);
+        to_host<int32_t>(c, h9, d9, 9);
+        int tiles = 0;
+        for (int k = 0; k < 9; k++) {
+            c->gp.class_row0[k] = h9[k];
+            c->gp.class_tile0[k] = tiles;
+            if (k < 8) tiles += (h9[k + 1] - h9[k] + kGemmTile - 1) / kGemmTile;
+        }
+        c->gp.J = J;
+        c->ntiles = tiles;
+        c->nrows = h9[8];
+        int32_t* ro = need<int32_t>(c, c->rowof, nc);
+        fill_i32(ro, -1, nc, s);
+        rows_inverse(rv, c->nrows, ro, s);
+        int32_t* ga = need<int32_t>(c, c->gather, (size_t)std::max<int64_t>(c->nrows, 1) * J);
+        fill_i32(ga, -1, c->nrows * J, s);
+        m2l_fill_gather((uint32_t*)c->tgt[0].p, (uint32_t*)c->src[0].p, nm, ca, (int32_t*)c->d_slot.p, R, ro, J,
+                        ga, gen, s);
+        check_launch("m2l gather");
+        uint32_t* gtmp = need<uint32_t>(c, c->tgt2, nm + 1);
+        size_t wsg = scan_ws_bytes(nm);
+        if (wsg > c->ws.cap) {
+            ck(hipStreamSynchronize(s), "sync");
+            ws = need<char>(c, c->ws, wsg);
+        }
+        scan_u32(gen, gtmp, (uint32_t*)(d6 + 12), nm, ws, s);
+        uint32_t* hg = (uint32_t*)host_stage(c);
+        to_host<uint32_t>(c, hg, d6 + 12, 1);
+        c->ngeneral = hg[0];
+    } else if (nm > 0) {
+        // every pair through the general kernel
+        fill_i32((int32_t*)gen, 1, nm, s);
+        c->ngeneral = nm;
+    }
+    ck(hipStreamSynchronize(s), "sync");
+    c->traversed = true;
+}
+
+// ------------------------------------------------------------------ evaluate
+void evaluate_impl(fmm_ctx c, int32_t precision, int32_t out_dtype, void* phi, void* ex, void* ey, void* ez) {
+    if (!c->traversed) fail(FMM_ERR_STATE, "fmm_evaluate before fmm_traverse");
+    if (precision < 0 || precision > 2) fail(FMM_ERR_INVALID_ARG, "unknown precision");
+    if (precision != FMM_PREC_FP32) fail(FMM_ERR_UNSUPPORTED, "only FMM_PREC_FP32 is implemented");
+    if (out_dtype != FMM_F32 && out_dtype != FMM_F64) fail(FMM_ERR_INVALID_ARG, "out_dtype must be F32 or F64");
+    if (c->n > 0 && (!phi || !ex || !ey || !ez)) fail(FMM_ERR_INVALID_ARG, "null output pointer");
+    if (c->n == 0) return;
+    hipStream_t s = c->stream;
+    int p = c->p, KP = kpad(p);
+    int32_t nc = c->ncell;
+    CellArrays ca = cells_of(c);
+    Tables tb = tables_of(c);
+    float* M = need<float>(c, c->M, (size_t)nc * KP);
+    float* L = need<float>(c, c->L, (size_t)nc * KP);
+    double4* nr = need<double4>(c, c->nearb, c->n);
+    mark(c, PH_UP);
+    p2m((float4*)c->pts.p, ca, (int32_t*)c->leaves.p, c->nleaf, p, KP, tb.rcoef, M, s);
+    int nlev = (int)c->lvl.size() - 1;
+    for (int Lv = nlev - 2; Lv >= 0; Lv--) m2m(ca, c->lvl[Lv], c->lvl[Lv + 1], p, KP, tb, M, s);
+    check_launch("upward");
+    ck(hipMemsetAsync(L, 0, (size_t)nc * KP * sizeof(float), s), "memset");
+    mark(c, PH_M2L);
+    if (c->gemm_on && c->ntiles > 0)
+        m2l_gemm((float*)c->d_T.p, (int32_t*)c->d_offid.p, (int32_t*)c->gather.p, (uint32_t*)c->rval.p, c->gp, p, KP,
+                 M, L, c->ntiles, precision, s);
+    mark(c, PH_M2LG);
+    if (c->nlist[0] > 0)
+        m2l_general((int32_t*)c->off[0].p, (uint32_t*)c->src[0].p, (uint32_t*)c->general.p, ca, nc, p, KP, tb, M, L,
+                    s);
+    check_launch("m2l");
+    mark(c, PH_DOWN);
+    for (int Lv = 1; Lv < nlev; Lv++) l2l(ca, c->lvl[Lv], c->lvl[Lv + 1], p, KP, tb, L, s);
+    check_launch("downward");
+    mark(c, PH_P2P);
+    p2p((float4*)c->pts.p, ca, (int32_t*)c->leaves.p, c->nleaf, (int32_t*)c->off[2].p, (uint32_t*)c->src[2].p,
+        c->dtype == FMM_F64 ? 1 : 0, nr, s);
+    check_launch("p2p");
+    mark(c, PH_FAR);
+    far_final((float4*)c->pts.p, (uint32_t*)c->idx.p, ca, (int32_t*)c->leaves.p, c->nleaf, (int32_t*)c->off[1].p,
+              (uint32_t*)c->src[1].p, p, KP, tb, M, L, nr, out_dtype, phi, ex, ey, ez, s);
+    check_launch("far field");
+    mark(c, PH_N);
+    if (c->timing) {
+        ck(hipEventSynchronize(c->ev[PH_N]), "event sync");
+        for (int k = PH_UP; k < PH_N; k++) {
+            float t = 0;
+            ck(hipEventElapsedTime(&t, c->ev[k], c->ev[k + 1]), "elapsed");
+            c->ms[k] = t;
+        }
+    }
+}
+
+}  // namespace
+
+// ================================================================== C-ABI
+extern "C" {
+
+fmm_status fmm_create(fmm_ctx* out, int device, void* hip_stream) {
+    if (!out) return FMM_ERR_INVALID_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+        (void)hipGetLastError();
+        return ndev == 0 ? FMM_ERR_DEVICE : FMM_ERR_INVALID_ARG;
+    }
+    fmm_ctx c = new (std::nothrow) fmm_ctx_s();
+    if (!c) return FMM_ERR_OUT_OF_MEMORY;
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    fmm_status st = guarded(c, [&] {
+        for (int k = 0; k <= PH_N; k++) ck(hipEventCreate(&c->ev[k]), "hipEventCreate");
+    });
+    if (st != FMM_OK) {
+        fmm_destroy(c);
+        return st;
+    }
+    *out = c;
+    return FMM_OK;
+}
+
+void fmm_destroy(fmm_ctx c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    for (Buf* b : c->bufs)
+        if (b->p) (void)hipFree(b->p);
+    for (int k = 0; k <= PH_N; k++)
+        if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
+    if (c->host) (void)hipHostFree(c->host);
+    delete c;
+}
+
+const char* fmm_last_error(fmm_ctx c) { return c ? c->err.c_str() : "null context"; }
+
+fmm_status fmm_set_stream(fmm_ctx c, void* hip_stream) {
+    return guarded(c, [&] { c->stream = (hipStream_t)hip_stream; });
+}
+
+fmm_status fmm_build_tree(fmm_ctx c, int64_t n, int dtype, const void* x, const void* y, const void* z,
+                          const void* q, int32_t ncrit) {
+    return guarded(c, [&] {
+        build_tree_impl(c, n, dtype, x, y, z, q, ncrit);
+        if (c->timing && c->n > 0) {
+            ck(hipEventRecord(c->ev[PH_TRAV], c->stream), "event");
+            ck(hipEventSynchronize(c->ev[PH_TRAV]), "event sync");
+            for (int k = PH_KEYS; k < PH_TRAV; k++) {
+                float t = 0;
+                ck(hipEventElapsedTime(&t, c->ev[k], c->ev[k + 1]), "elapsed");
+                c->ms[k] = t;
+            }
+        }
+    });
+}
+
+fmm_status fmm_traverse(fmm_ctx c, int32_t p, double theta, int32_t policy) {
+    return guarded(c, [&] {
+        if (c->timing) ck(hipEventRecord(c->ev[PH_TRAV], c->stream), "event");
+        traverse_impl(c, p, theta, policy);
+        if (c->timing && c->n > 0) {
+            ck(hipEventRecord(c->ev[PH_UP], c->stream), "event");
+            ck(hipEventSynchronize(c->ev[PH_UP]), "event sync");
+            float t = 0;
+            ck(hipEventElapsedTime(&t, c->ev[PH_TRAV], c->ev[PH_LISTS]), "elapsed");
+            c->ms[PH_TRAV] = t;
+            ck(hipEventElapsedTime(&t, c->ev[PH_LISTS], c->ev[PH_UP]), "elapsed");
+            c->ms[PH_LISTS] = t;
+        }
+    });
+}
+
+fmm_status fmm_evaluate(fmm_ctx c, int32_t precision, int32_t out_dtype, void* phi, void* ex, void* ey,
+                        void* ez) {
+    return guarded(c, [&] { evaluate_impl(c, precision, out_dtype, phi, ex, ey, ez); });
+}
+
+fmm_status fmm_set_costs(fmm_ctx c, double c_m2l, double c_m2p, double c_p2p) {
+    return guarded(c, [&] {
+        if (!(c_m2l > 0) || !(c_m2p > 0) || !(c_p2p > 0)) fail(FMM_ERR_INVALID_ARG, "unit costs must be > 0");
+        c->costs[0] = c_m2l;
+        c->costs[1] = c_m2p;
+        c->costs[2] = c_p2p;
+        c->costs_set = true;
+    });
+}
+
+fmm_status fmm_get_costs(fmm_ctx c, double* costs3) {
+    return guarded(c, [&] {
+        if (!costs3) fail(FMM_ERR_INVALID_ARG, "null pointer");
+        if (!c->costs_set) fail(FMM_ERR_STATE, "no unit costs yet");
+        for (int k = 0; k < 3; k++) costs3[k] = c->costs[k];
+    });
+}
+
+fmm_status fmm_tune(fmm_ctx c, int32_t p, int32_t precision) {
+    return guarded(c, [&] {
+        (void)p;
+        (void)precision;
+        fail(FMM_ERR_UNSUPPORTED, "kernel pre-calculation is not built yet");
+    });
+}
+
+fmm_status fmm_get_sizes(fmm_ctx c, int64_t* n_cells, int64_t* n_m2l, int64_t* n_m2p, int64_t* n_p2p) {
+    return guarded(c, [&] {
+        if (n_cells) *n_cells = c->built ? c->ncell : 0;
+        if (n_m2l) *n_m2l = c->traversed ? c->nlist[0] : 0;
+        if (n_m2p) *n_m2p = c->traversed ? c->nlist[1] : 0;
+        if (n_p2p) *n_p2p = c->traversed ? c->nlist[2] : 0;
+    });
+}
+
+fmm_status fmm_get_m2l_split(fmm_ctx c, int64_t* n_batched, int64_t* n_general) {
+    return guarded(c, [&] {
+        if (!c->traversed) fail(FMM_ERR_STATE, "no traversal");
+        if (n_batched) *n_batched = c->nlist[0] - c->ngeneral;
+        if (n_general) *n_general = c->ngeneral;
+    });
+}
+
+fmm_status fmm_get_bbox(fmm_ctx c, double* lo3, double* side) {
+    return guarded(c, [&] {
+        if (!c->built) fail(FMM_ERR_STATE, "no tree");
+        if (!lo3 || !side) fail(FMM_ERR_INVALID_ARG, "null pointer");
+        for (int d = 0; d < 3; d++) lo3[d] = c->lo[d];
+        *side = c->side;
+    });
+}
+
+fmm_status fmm_get_keys(fmm_ctx c, uint64_t* keys, int32_t* perm) {
+    return guarded(c, [&] {
+        if (!c->built) fail(FMM_ERR_STATE, "no tree");
+        if (c->n == 0) return;
+        if (keys) to_host<uint64_t>(c, keys, c->keys.p, c->n);
+        if (perm) to_host<int32_t>(c, perm, c->idx.p, c->n);
+    });
+}
+
+fmm_status fmm_get_cells(fmm_ctx c, int32_t* level, uint64_t* prefix, int32_t* begin, int32_t* end, int32_t* parent,
+                         int32_t* first_child, int32_t* nchild, int32_t* centre_h, int32_t* radius_h) {
+    return guarded(c, [&] {
+        if (!c->built) fail(FMM_ERR_STATE, "no tree");
+        size_t m = c->ncell;
+        if (m == 0) return;
+        if (level) to_host<int32_t>(c, level, c->c_level.p, m);
+        if (prefix) to_host<uint64_t>(c, prefix, c->c_prefix.p, m);
+        if (begin) to_host<int32_t>(c, begin, c->c_begin.p, m);
+        if (end) to_host<int32_t>(c, end, c->c_end.p, m);
+        if (parent) to_host<int32_t>(c, parent, c->c_parent.p, m);
+        if (first_child) to_host<int32_t>(c, first_child, c->c_child.p, m);
+        if (nchild) to_host<int32_t>(c, nchild, c->c_nchild.p, m);
+        if (centre_h || radius_h) {
+            std::vector<int4> g(m);
+            to_host<int4>(c, g.data(), c->c_geo.p, m);
+            for (size_t i = 0; i < m; i++) {
+                if (centre_h) {
+                    centre_h[3 * i] = g[i].x;
+                    centre_h[3 * i + 1] = g[i].y;
+                    centre_h[3 * i + 2] = g[i].z;
+                }
+                if (radius_h) radius_h[i] = g[i].w;
+            }
+        }
+    });
+}
+
+fmm_status fmm_get_list(fmm_ctx c, int32_t kind, int32_t* tgt, int32_t* src) {
+    return guarded(c, [&] {
+        if (!c->traversed) fail(FMM_ERR_STATE, "no traversal");
+        if (kind < 0 || kind > 2) fail(FMM_ERR_INVALID_ARG, "unknown list kind");
+        size_t m = c->nlist[kind];
+        if (m == 0) return;
+        if (tgt) to_host<int32_t>(c, tgt, c->tgt[kind].p, m);
+        if (src) to_host<int32_t>(c, src, c->src[kind].p, m);
+    });
+}
+
+fmm_status fmm_get_expansions(fmm_ctx c, float* mp, float* lc) {
+    return guarded(c, [&] {
+        if (!c->traversed || !c->M.p) fail(FMM_ERR_STATE, "no evaluation");
+        int K = ncoef(c->p), KP = kpad(c->p);
+        size_t m = c->ncell;
+        std::vector<float> tmp(m * KP);
+        if (mp) {
+            to_host<float>(c, tmp.data(), c->M.p, m * KP);
+            for (size_t i = 0; i < m; i++) std::memcpy(mp + i * K, tmp.data() + i * KP, K * sizeof(float));
+        }
+        if (lc) {
+            to_host<float>(c, tmp.data(), c->L.p, m * KP);
+            for (size_t i = 0; i < m; i++) std::memcpy(lc + i * K, tmp.data() + i * KP, K * sizeof(float));
+        }
+    });
+}
+
+fmm_status fmm_get_timings(fmm_ctx c, double* ms, int32_t cap, int32_t* count) {
+    return guarded(c, [&] {
+        if (!ms && cap > 0) fail(FMM_ERR_INVALID_ARG, "null pointer");
+        int k = std::min<int>(cap, PH_N);
+        for (int i = 0; i < k; i++) ms[i] = c->ms[i];
+        if (count) *count = k;
+    });
+}
+
+fmm_status fmm_set_timing(fmm_ctx c, int32_t enabled) {
+    return guarded(c, [&] { c->timing = enabled != 0; });
+}
+
+}  // extern "C"

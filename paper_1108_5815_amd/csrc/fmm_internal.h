@@ -1,0 +1,154 @@
+// fmm_internal.h -- device data layout and kernel launchers of the gfx950 FMM.
+//
+// Layout in HBM (all arrays indexed by sorted particle k or cell c):
+//   pts[k]      float4 (x, y, z, q) in Morton order, FP32
+//   keys[k]     uint64 Morton key;  perm[k] original index
+//   cells       SoA: begin, end, parent, child (first child or -1), nchild,
+//               level (int32), prefix (uint64), geo (int4: half-grid centre
+//               x,y,z and half side r), ctr (double4: physical centre, r)
+//   expansions  M[c][KP], L[c][KP] FP32, KP = (p+1)^2 rounded up to 32 with
+//               zero padding; degree n at offset n*n as
+//               [Re c_n^0, Re c_n^1, Im c_n^1, ..., Re c_n^n, Im c_n^n],
+//               Greengard-Rokhlin normalisation, M scaled by r^-n, L by r^(n+1)
+//   lists       (target, source) int32 pairs grouped by target; CSR offsets
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace fmm {
+
+constexpr int kMaxP = 16;
+constexpr int kMaxLevel = 21;
+
+struct CellArrays {
+    int32_t* begin;
+    int32_t* end;
+    int32_t* parent;
+    int32_t* child;
+    int32_t* nchild;
+    int32_t* level;
+    uint64_t* prefix;
+    int4* geo;       // half-grid centre (x, y, z) and half side r
+    double4* ctr;    // physical centre (x, y, z) and half side r
+};
+
+inline int ncoef(int p) { return (p + 1) * (p + 1); }
+inline int kpad(int p) { return ((ncoef(p) + 31) / 32) * 32; }
+
+// ------------------------------------------------------------------ utilities
+// Exclusive prefix sums.  `total` (device, may be null) receives the sum.
+size_t scan_ws_bytes(int64_t n);
+void scan_u32(const uint32_t* in, uint32_t* out, uint32_t* total, int64_t n, void* ws,
+              hipStream_t s);
+void scan_u32x4(const uint4* in, uint4* out, uint4* total, int64_t n, void* ws, hipStream_t s);
+
+// Stable LSD radix sort on key bits [bit0, bit1), 8 bits per pass.  Result in
+// (keys_a, vals_a) on return; (keys_b, vals_b) is scratch of the same size.
+size_t sort_ws_bytes(int64_t n);
+void sort_u64(uint64_t* keys_a, uint32_t* vals_a, uint64_t* keys_b, uint32_t* vals_b, int64_t n,
+              int bit0, int bit1, void* ws, hipStream_t s);
+void sort_u32(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b, int64_t n,
+              int bit0, int bit1, void* ws, hipStream_t s);
+
+void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+void iota_u32(uint32_t* p, int64_t n, hipStream_t s);
+
+// ------------------------------------------------------------------ tree
+// bbox: out6 = {lo x,y,z, hi x,y,z} (double), bad = count of non-finite values
+size_t bbox_ws_bytes(int64_t n);
+void bbox(const void* x, const void* y, const void* z, int dtype, int64_t n, double* out6,
+          uint32_t* bad, void* ws, hipStream_t s);
+void morton_keys(const void* x, const void* y, const void* z, int dtype, int64_t n,
+                 double lox, double loy, double loz, double scale, uint64_t* keys, uint32_t* idx,
+                 hipStream_t s);
+void permute_points(const void* x, const void* y, const void* z, const void* q, int dtype,
+                    int64_t n, const uint32_t* idx, float4* pts, hipStream_t s);
+// one level of the adaptive tree: cells [c0, c1) at level L.  nsplit[c-c0] =
+// number of children of cell c (0 if it does not split).
+void tree_count(const uint64_t* keys, CellArrays cells, int32_t c0, int32_t c1, int L,
+                int32_t ncrit, uint32_t* nsplit, hipStream_t s);
+// child_off = exclusive scan of nsplit; children get ids c1 + child_off[c-c0]
+void tree_emit(const uint64_t* keys, CellArrays cells, int32_t c0, int32_t c1, int L,
+               const uint32_t* nsplit, const uint32_t* child_off, hipStream_t s);
+void cell_geometry(CellArrays cells, int32_t ncell, double lox, double loy, double loz,
+                   double side, hipStream_t s);
+
+// ------------------------------------------------------------------ traversal
+struct TravParams {
+    double theta2;
+    int policy;
+    double c_m2l, c_m2p, c_p2p;
+    const float* mlp;   // learned cost model weights (device) or null
+};
+// per frontier pair: counts of new (M2L, M2P, P2P, SPLIT) pairs
+void trav_count(const int2* frontier, int64_t nf, CellArrays cells, TravParams tp, uint4* cnt,
+                hipStream_t s);
+void trav_emit(const int2* frontier, int64_t nf, CellArrays cells, TravParams tp,
+               const uint4* off, int64_t base_m2l, int64_t base_m2p, int64_t base_p2p,
+               int2* m2l, int2* m2p, int2* p2p, int2* next, hipStream_t s);
+void split_pairs(const int2* pairs, int64_t n, uint32_t* tgt, uint32_t* src, hipStream_t s);
+// offsets[c] = first index in the sorted target array with target >= c, c in [0, ncell]
+void csr_offsets(const uint32_t* tgt_sorted, int64_t n, int32_t ncell, int32_t* offsets,
+                 hipStream_t s);
+
+// M2L same-level batching: classify each M2L pair (sorted by target).
+//   slot_of   lookup table [8][(2R+1)^3] (offset -> slot or -1)
+//   rowof     [ncell] GEMM row of the target or -1
+//   gather    [nrows][J] source cell or -1
+//   general   flag per pair (1 = not handled by the GEMM)
+void m2l_mark_targets(const uint32_t* tgt, const uint32_t* src, int64_t n, CellArrays cells,
+                      const int32_t* slot_of, int R, uint32_t* has_fast, hipStream_t s);
+void m2l_fill_gather(const uint32_t* tgt, const uint32_t* src, int64_t n, CellArrays cells,
+                     const int32_t* slot_of, int R, const int32_t* rowof, int32_t J,
+                     int32_t* gather, uint32_t* general, hipStream_t s);
+void row_class_keys(const uint32_t* has_fast, CellArrays cells, int32_t ncell, uint32_t* key,
+                    uint32_t* val, hipStream_t s);
+void rows_inverse(const uint32_t* rowcell, int64_t nrows, int32_t* rowof, hipStream_t s);
+// out9[c] = first index of the sorted class keys with key >= c, c = 0..8
+void class_bounds(const uint32_t* key_sorted, int64_t n, int32_t* out9, hipStream_t s);
+// leaf cells (nchild == 0) in cell order; flag/pos are scratch of ncell entries
+void leaf_flags(CellArrays cells, int32_t ncell, uint32_t* flag, hipStream_t s);
+void leaf_write(CellArrays cells, int32_t ncell, const uint32_t* pos, int32_t* leaves, hipStream_t s);
+
+// ------------------------------------------------------------------ expansions
+struct Tables {
+    // all device pointers, FP32
+    const float* m2m;    // [8][K][K] k-major (input index major)
+    const float* l2l;    // [8][K][K] k-major
+    const float* wm2l;   // [(p+1)(p+2)/2][K]  general M2L weights, (j,k) x (n, m+n)
+    const float* gl2p;   // [2][K] gradient weights of L2P, (k) x (n, m+n)
+    const float* hm2p;   // [2][K] gradient weights of M2P
+    const float* rcoef;  // recurrence constants, see expansions kernels
+};
+void p2m(const float4* pts, CellArrays cells, const int32_t* leaves, int32_t nleaves, int p,
+         int KP, const float* rc, float* M, hipStream_t s);
+void m2m(CellArrays cells, int32_t c0, int32_t c1, int p, int KP, Tables t, float* M,
+         hipStream_t s);
+void l2l(CellArrays cells, int32_t c0, int32_t c1, int p, int KP, Tables t, float* L,
+         hipStream_t s);
+void m2l_general(const int32_t* off, const uint32_t* src, const uint32_t* general, CellArrays cells,
+                 int32_t ncell, int p, int KP, Tables t, const float* M, float* L, hipStream_t s);
+void far_final(const float4* pts, const uint32_t* perm, CellArrays cells, const int32_t* leaves,
+               int32_t nleaves, const int32_t* m2p_off, const uint32_t* m2p_src, int p, int KP,
+               Tables t, const float* M, const float* L, const double4* near, int out_dtype,
+               void* phi, void* ex, void* ey, void* ez, hipStream_t s);
+void p2p(const float4* pts, CellArrays cells, const int32_t* leaves, int32_t nleaves,
+         const int32_t* p2p_off, const uint32_t* p2p_src, int guard_all, double4* near,
+         hipStream_t s);
+
+// same-level M2L on MFMA: L[rowcell[r]] = sum_j T[offid[class][j]] * M[gather[r][j]]
+struct GemmPlan {
+    int32_t class_row0[9];   // rows of class c: [class_row0[c], class_row0[c+1])
+    int32_t class_tile0[9];  // first tile of class c
+    int32_t J;               // slots per class
+};
+void m2l_gemm(const float* T, const int32_t* offid, const int32_t* gather, const uint32_t* rowcell,
+              GemmPlan plan, int p, int KP, const float* M, float* L, int ntiles, int precision,
+              hipStream_t s);
+constexpr int kGemmTile = 64;  // targets per GEMM tile
+bool m2l_gemm_supported(int p);
+
+}  // namespace fmm

@@ -1,0 +1,47 @@
+// host_ops.h -- FP64 host construction of the translation operators used by
+// the kernels (radius-scaled, real layout; see fmm_internal.h).
+#pragma once
+
+#include <array>
+#include <cstdint>
+#include <vector>
+
+namespace fmm {
+
+// Recurrence constants shared by the harmonic kernels (float table):
+//   A(n,m) = (2n-1)/sqrt((n-m)(n+m)),  B(n,m) = sqrt((n-m-1)(n+m-1)/((n-m)(n+m)))
+//   C1(m) = sqrt((2m-1)/(2m)),          C2(m) = sqrt(2m+1)
+constexpr int kRcN = 2 * 16 + 2;                     // highest degree tabulated
+constexpr int kRcTri = (kRcN + 1) * (kRcN + 2) / 2;  // entries per triangle
+constexpr int kRcA = 0, kRcB = kRcTri, kRcC1 = 2 * kRcTri, kRcC2 = 2 * kRcTri + 40;
+constexpr int kRcSize = 2 * kRcTri + 80;
+
+struct HostTables {
+    int p = -1, K = 0, KP = 0;
+    std::vector<float> m2m;    // [8][K][K], element (oct, k, j) at (oct*K + k)*K + j
+    std::vector<float> l2l;    // same layout
+    std::vector<float> wm2l;   // [(p+1)(p+2)/2][K]
+    std::vector<float> gl2p;   // [2][K]
+    std::vector<float> hm2p;   // [2][K]
+    std::vector<float> rcoef;  // kRcSize
+};
+
+struct M2LPlan {
+    int p = -1;
+    double theta = 0;
+    int R = 0;                               // offsets lie in [-R, R]^3
+    int J = 0;                               // accepted offsets per octant class
+    std::vector<int32_t> slot_of;            // [8][(2R+1)^3] -> slot or -1
+    std::vector<int32_t> offid;              // [8][J] -> unique offset index
+    std::vector<std::array<int, 3>> offsets; // unique offsets
+    std::vector<float> T;                    // [noff][KP][KP], element (o, k, j) at (o*KP + k)*KP + j
+};
+
+void build_tables(int p, HostTables& t);
+void build_m2l_plan(int p, double theta, M2LPlan& plan);
+
+// Real-form operator of a general M2L: Ltilde = T Mtilde with source radius
+// ratio rs/rt and offset (source centre - target centre) / rt.  Row-major K x K.
+void m2l_operator(int p, const double q[3], double ratio, std::vector<double>& out);
+
+}  // namespace fmm

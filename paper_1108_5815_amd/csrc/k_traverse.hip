@@ -1,0 +1,304 @@
+// k_traverse.hip -- dual tree traversal as a level-synchronous frontier.
+//
+// Paper ("Dual tree traversal"): a stack holds (target, source) cell pairs;
+// a popped pair has its larger cell split, each new pair is tested with the
+// acceptance criterion ("Results": theta = (r_t + r_s)/R), accepted pairs
+// interact, pairs of leaves that fail become particle-particle sums, and the
+// rest are pushed again.  The children of a pair depend only on that pair,
+// so the set of emitted interactions does not depend on the order in which
+// pairs are processed.  Here every pair of the current frontier is expanded
+// at once: one pass counts the new pairs of each kind, a scan places them,
+// a second pass writes them; the order is deterministic (frontier order,
+// then child order).
+//
+// Readings fixed here and in the oracle: r = half side of the cube, R between
+// cube centres, accept iff (r_t + r_s)^2 <= theta^2 R^2 (integer half-grid
+// geometry, one FP64 product), split the cell of lower level (both when
+// levels are equal), only accepted pairs choose an interaction kind.
+#include "fmm_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace fmm {
+namespace {
+
+enum { KIND_M2L = 0, KIND_M2P = 1, KIND_P2P = 2, KIND_SPLIT = 3 };
+
+__device__ inline bool is_leaf(const CellArrays& c, int32_t i) { return c.nchild[i] == 0; }
+
+// Learned cost model: 6 -> 64 -> 64 -> 3 MLP with ReLU, predicting the log
+// time of M2L, M2P and P2P for a pair.  Weight layout (floats):
+// W1[64][6], b1[64], W2[64][64], b2[64], W3[3][64], b3[3].
+__device__ inline int mlp_choose(const float* __restrict__ w, const float f[6]) {
+    const float* W1 = w;
+    const float* b1 = W1 + 64 * 6;
+    const float* W2 = b1 + 64;
+    const float* b2 = W2 + 64 * 64;
+    const float* W3 = b2 + 64;
+    const float* b3 = W3 + 3 * 64;
+    float h1[64];
+    for (int i = 0; i < 64; i++) {
+        float a = b1[i];
+        for (int k = 0; k < 6; k++) a = fmaf(W1[i * 6 + k], f[k], a);
+        h1[i] = fmaxf(a, 0.f);
+    }
+    float o[3] = {b3[0], b3[1], b3[2]};
+    for (int i = 0; i < 64; i++) {
+        float a = b2[i];
+        for (int k = 0; k < 64; k++) a = fmaf(W2[i * 64 + k], h1[k], a);
+        a = fmaxf(a, 0.f);
+        o[0] = fmaf(W3[i], a, o[0]);
+        o[1] = fmaf(W3[64 + i], a, o[1]);
+        o[2] = fmaf(W3[128 + i], a, o[2]);
+    }
+    int k = 0;
+    float best = o[0];
+    if (o[1] < best) { best = o[1]; k = 1; }
+    if (o[2] < best) k = 2;
+    return k;
+}
+
+__device__ inline int classify(const CellArrays& c, int32_t t, int32_t s, const TravParams& tp) {
+    int4 gt = c.geo[t], gs = c.geo[s];
+    int64_t dx = (int64_t)gt.x - gs.x, dy = (int64_t)gt.y - gs.y, dz = (int64_t)gt.z - gs.z;
+    int64_t R2 = dx * dx + dy * dy + dz * dz;
+    int64_t rr = (int64_t)gt.w + gs.w;
+    if ((double)(rr * rr) <= __dmul_rn(tp.theta2, (double)R2)) {
+        if (tp.policy == 0) return KIND_M2L;
+        if (tp.policy == 1) return KIND_M2P;
+        double nt = (double)(c.end[t] - c.begin[t]);
+        double ns = (double)(c.end[s] - c.begin[s]);
+        if (tp.policy == 3 && tp.mlp) {
+            double R = sqrt((double)R2);
+            float f[6] = {(float)log2((double)gt.w / R), (float)log2((double)gs.w / R), (float)log2(nt),
+                          (float)log2(ns), 0.f, (float)((double)rr / R)};
+            return mlp_choose(tp.mlp, f);
+        }
+        double c0 = tp.c_m2l;
+        double c1 = __dmul_rn(tp.c_m2p, nt);
+        double c2 = __dmul_rn(__dmul_rn(tp.c_p2p, nt), ns);
+        int k = KIND_M2L;
+        double best = c0;
+        if (c1 < best) { best = c1; k = KIND_M2P; }
+        if (c2 < best) k = KIND_P2P;
+        return k;
+    }
+    if (is_leaf(c, t) && is_leaf(c, s)) return KIND_P2P;
+    return KIND_SPLIT;
+}
+
+__device__ inline void split_ranges(const CellArrays& c, int32_t T, int32_t S, int32_t& t0, int32_t& t1,
+                                    int32_t& s0, int32_t& s1) {
+    bool lt = is_leaf(c, T), ls = is_leaf(c, S);
+    int vt = c.level[T], vs = c.level[S];
+    bool splitT = !lt && (ls || vt <= vs);
+    bool splitS = !ls && (lt || vs <= vt);
+    t0 = splitT ? c.child[T] : T;
+    t1 = splitT ? c.child[T] + c.nchild[T] : T + 1;
+    s0 = splitS ? c.child[S] : S;
+    s1 = splitS ? c.child[S] + c.nchild[S] : S + 1;
+}
+
+__global__ void k_trav_count(const int2* __restrict__ fr, int64_t nf, CellArrays c, TravParams tp,
+                             uint4* __restrict__ cnt) {
+    int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nf) return;
+    int2 pr = fr[f];
+    int32_t t0, t1, s0, s1;
+    split_ranges(c, pr.x, pr.y, t0, t1, s0, s1);
+    uint32_t n[4] = {0, 0, 0, 0};
+    for (int32_t t = t0; t < t1; t++)
+        for (int32_t s = s0; s < s1; s++) n[classify(c, t, s, tp)]++;
+    cnt[f] = make_uint4(n[0], n[1], n[2], n[3]);
+}
+
+__global__ void k_trav_emit(const int2* __restrict__ fr, int64_t nf, CellArrays c, TravParams tp,
+                            const uint4* __restrict__ off, int64_t b0, int64_t b1, int64_t b2,
+                            int2* __restrict__ m2l, int2* __restrict__ m2p, int2* __restrict__ p2p,
+                            int2* __restrict__ next) {
+    int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nf) return;
+    int2 pr = fr[f];
+    int32_t t0, t1, s0, s1;
+    split_ranges(c, pr.x, pr.y, t0, t1, s0, s1);
+    uint4 o = off[f];
+    int64_t w0 = b0 + o.x, w1 = b1 + o.y, w2 = b2 + o.z, w3 = o.w;
+    for (int32_t t = t0; t < t1; t++)
+        for (int32_t s = s0; s < s1; s++) {
+            int k = classify(c, t, s, tp);
+            int2 v = make_int2(t, s);
+            if (k == KIND_M2L) m2l[w0++] = v;
+            else if (k == KIND_M2P) m2p[w1++] = v;
+            else if (k == KIND_P2P) p2p[w2++] = v;
+            else next[w3++] = v;
+        }
+}
+
+__global__ void k_split_pairs(const int2* __restrict__ pairs, int64_t n, uint32_t* __restrict__ tgt,
+                              uint32_t* __restrict__ src) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int2 v = pairs[i];
+    tgt[i] = (uint32_t)v.x;
+    src[i] = (uint32_t)v.y;
+}
+
+__global__ void k_csr(const uint32_t* __restrict__ tgt, int64_t n, int32_t ncell, int32_t* __restrict__ off) {
+    int32_t c = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (c > ncell) return;
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if ((int32_t)tgt[mid] < c) lo = mid + 1;
+        else hi = mid;
+    }
+    off[c] = (int32_t)lo;
+}
+
+// slot of a same-level pair in its target's offset class, or -1
+__device__ inline int32_t fast_slot(const CellArrays& c, int32_t t, int32_t s, const int32_t* slot_of, int R) {
+    int lv = c.level[t];
+    if (lv < 1 || c.level[s] != lv) return -1;
+    int4 gt = c.geo[t], gs = c.geo[s];
+    int32_t side = 2 * gt.w;
+    int32_t ox = (gs.x - gt.x) / side, oy = (gs.y - gt.y) / side, oz = (gs.z - gt.z) / side;
+    if (ox < -R || ox > R || oy < -R || oy > R || oz < -R || oz > R) return -1;
+    int W = 2 * R + 1;
+    int cls = (int)(c.prefix[t] & 7u);
+    return slot_of[(size_t)cls * W * W * W + ((size_t)(ox + R) * W + (oy + R)) * W + (oz + R)];
+}
+
+__global__ void k_mark_targets(const uint32_t* __restrict__ tgt, const uint32_t* __restrict__ src, int64_t n,
+                               CellArrays c, const int32_t* __restrict__ slot_of, int R,
+                               uint32_t* __restrict__ has_fast) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t t = (int32_t)tgt[i];
+    if (fast_slot(c, t, (int32_t)src[i], slot_of, R) >= 0) has_fast[t] = 1u;
+}
+
+__global__ void k_fill_gather(const uint32_t* __restrict__ tgt, const uint32_t* __restrict__ src, int64_t n,
+                              CellArrays c, const int32_t* __restrict__ slot_of, int R,
+                              const int32_t* __restrict__ rowof, int32_t J, int32_t* __restrict__ gather,
+                              uint32_t* __restrict__ general) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t t = (int32_t)tgt[i], s = (int32_t)src[i];
+    int32_t sl = fast_slot(c, t, s, slot_of, R);
+    if (sl >= 0) {
+        gather[(int64_t)rowof[t] * J + sl] = s;
+        general[i] = 0u;
+    } else {
+        general[i] = 1u;
+    }
+}
+
+__global__ void k_row_class_keys(const uint32_t* __restrict__ has_fast, CellArrays c, int32_t ncell,
+                                 uint32_t* __restrict__ key, uint32_t* __restrict__ val) {
+    int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= ncell) return;
+    key[i] = has_fast[i] ? (uint32_t)(c.prefix[i] & 7u) : 8u;
+    val[i] = (uint32_t)i;
+}
+
+__global__ void k_rows_inverse(const uint32_t* __restrict__ rowcell, int64_t nrows, int32_t* __restrict__ rowof) {
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrows) return;
+    rowof[rowcell[r]] = (int32_t)r;
+}
+
+inline unsigned grid(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+void trav_count(const int2* frontier, int64_t nf, CellArrays cells, TravParams tp, uint4* cnt, hipStream_t s) {
+    if (nf <= 0) return;
+    k_trav_count<<<grid(nf), 256, 0, s>>>(frontier, nf, cells, tp, cnt);
+}
+
+void trav_emit(const int2* frontier, int64_t nf, CellArrays cells, TravParams tp, const uint4* off,
+               int64_t base_m2l, int64_t base_m2p, int64_t base_p2p, int2* m2l, int2* m2p, int2* p2p,
+               int2* next, hipStream_t s) {
+    if (nf <= 0) return;
+    k_trav_emit<<<grid(nf), 256, 0, s>>>(frontier, nf, cells, tp, off, base_m2l, base_m2p, base_p2p, m2l,
+                                         m2p, p2p, next);
+}
+
+void split_pairs(const int2* pairs, int64_t n, uint32_t* tgt, uint32_t* src, hipStream_t s) {
+    if (n <= 0) return;
+    k_split_pairs<<<grid(n), 256, 0, s>>>(pairs, n, tgt, src);
+}
+
+void csr_offsets(const uint32_t* tgt_sorted, int64_t n, int32_t ncell, int32_t* offsets, hipStream_t s) {
+    k_csr<<<grid((int64_t)ncell + 1), 256, 0, s>>>(tgt_sorted, n, ncell, offsets);
+}
+
+void m2l_mark_targets(const uint32_t* tgt, const uint32_t* src, int64_t n, CellArrays cells,
+                      const int32_t* slot_of, int R, uint32_t* has_fast, hipStream_t s) {
+    if (n <= 0) return;
+    k_mark_targets<<<grid(n), 256, 0, s>>>(tgt, src, n, cells, slot_of, R, has_fast);
+}
+
+void m2l_fill_gather(const uint32_t* tgt, const uint32_t* src, int64_t n, CellArrays cells,
+                     const int32_t* slot_of, int R, const int32_t* rowof, int32_t J, int32_t* gather,
+                     uint32_t* general, hipStream_t s) {
+    if (n <= 0) return;
+    k_fill_gather<<<grid(n), 256, 0, s>>>(tgt, src, n, cells, slot_of, R, rowof, J, gather, general);
+}
+
+void row_class_keys(const uint32_t* has_fast, CellArrays cells, int32_t ncell, uint32_t* key, uint32_t* val,
+                    hipStream_t s) {
+    if (ncell <= 0) return;
+    k_row_class_keys<<<grid(ncell), 256, 0, s>>>(has_fast, cells, ncell, key, val);
+}
+
+void rows_inverse(const uint32_t* rowcell, int64_t nrows, int32_t* rowof, hipStream_t s) {
+    if (nrows <= 0) return;
+    k_rows_inverse<<<grid(nrows), 256, 0, s>>>(rowcell, nrows, rowof);
+}
+
+}  // namespace fmm
+
+namespace fmm {
+namespace {
+
+__global__ void k_class_bounds(const uint32_t* __restrict__ key, int64_t n, int32_t* __restrict__ out9) {
+    int c = threadIdx.x;
+    if (c > 8) return;
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (key[mid] < (uint32_t)c) lo = mid + 1;
+        else hi = mid;
+    }
+    out9[c] = (int32_t)lo;
+}
+
+__global__ void k_leaf_flags(CellArrays c, int32_t ncell, uint32_t* __restrict__ flag) {
+    int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < ncell) flag[i] = c.nchild[i] == 0 ? 1u : 0u;
+}
+
+__global__ void k_leaf_write(CellArrays c, int32_t ncell, const uint32_t* __restrict__ pos,
+                             int32_t* __restrict__ leaves) {
+    int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < ncell && c.nchild[i] == 0) leaves[pos[i]] = i;
+}
+
+}  // namespace
+
+void class_bounds(const uint32_t* key_sorted, int64_t n, int32_t* out9, hipStream_t s) {
+    k_class_bounds<<<1, 64, 0, s>>>(key_sorted, n, out9);
+}
+
+void leaf_flags(CellArrays cells, int32_t ncell, uint32_t* flag, hipStream_t s) {
+    if (ncell <= 0) return;
+    k_leaf_flags<<<(ncell + 255) / 256, 256, 0, s>>>(cells, ncell, flag);
+}
+
+void leaf_write(CellArrays cells, int32_t ncell, const uint32_t* pos, int32_t* leaves, hipStream_t s) {
+    if (ncell <= 0) return;
+    k_leaf_write<<<(ncell + 255) / 256, 256, 0, s>>>(cells, ncell, pos, leaves);
+}
+
+}  // namespace fmm

@@ -1,0 +1,252 @@
+// k_tree.hip -- bounding cube, Morton keys, particle permutation and the
+// level-by-level adaptive octree.
+//
+// Tree (paper: "Hierarchical N-body algorithms" clustering into cells;
+// "Results": N_crit is the maximum number of particles per cell, the tree is
+// adaptive): a cell at level L < 21 holding more than ncrit particles splits
+// into its non-empty octants.  Because particles are sorted by Morton key, the
+// octants of a cell are contiguous runs; their boundaries are found by binary
+// search for the 8 child key prefixes, so one thread handles one cell.
+// Cells are numbered level by level in key order (breadth-first).
+#include "fmm_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace fmm {
+namespace {
+
+constexpr int BB = 256;
+
+template <class F>
+__global__ void k_bbox(const F* __restrict__ x, const F* __restrict__ y, const F* __restrict__ z,
+                       int64_t n, double* __restrict__ part, uint32_t* __restrict__ bad) {
+    __shared__ double red[6][BB];
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    uint32_t nb = 0;
+    for (int64_t i = (int64_t)blockIdx.x * BB + threadIdx.x; i < n; i += (int64_t)gridDim.x * BB) {
+        double v[3] = {(double)x[i], (double)y[i], (double)z[i]};
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            if (!isfinite(v[d])) {
+                nb++;
+                continue;
+            }
+            lo[d] = fmin(lo[d], v[d]);
+            hi[d] = fmax(hi[d], v[d]);
+        }
+    }
+    if (nb) atomicAdd(bad, nb);
+    for (int d = 0; d < 3; d++) {
+        red[d][threadIdx.x] = lo[d];
+        red[3 + d][threadIdx.x] = hi[d];
+    }
+    __syncthreads();
+    for (int st = BB / 2; st > 0; st >>= 1) {
+        if (threadIdx.x < st)
+            for (int d = 0; d < 3; d++) {
+                red[d][threadIdx.x] = fmin(red[d][threadIdx.x], red[d][threadIdx.x + st]);
+                red[3 + d][threadIdx.x] = fmax(red[3 + d][threadIdx.x], red[3 + d][threadIdx.x + st]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void k_bbox_final(const double* __restrict__ part, int nb, double* __restrict__ out6) {
+    int d = threadIdx.x;
+    if (d >= 6) return;
+    double v = d < 3 ? INFINITY : -INFINITY;
+    for (int b = 0; b < nb; b++) v = d < 3 ? fmin(v, part[b * 6 + d]) : fmax(v, part[b * 6 + d]);
+    out6[d] = v;
+}
+
+__device__ inline uint64_t spread3(uint64_t v) {
+    v &= 0x1FFFFFull;
+    v = (v | (v << 32)) & 0x1F00000000FFFFull;
+    v = (v | (v << 16)) & 0x1F0000FF0000FFull;
+    v = (v | (v << 8)) & 0x100F00F00F00F00Full;
+    v = (v | (v << 4)) & 0x10C30C30C30C30C3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
+}
+
+// 21-bit quantisation: one FP64 subtraction, one FP64 multiplication, floor
+__device__ inline uint64_t quantise(double v, double lo, double scale) {
+    double t = __dmul_rn(__dsub_rn(v, lo), scale);
+    double f = floor(t);
+    uint64_t q = f <= 0.0 ? 0ull : (uint64_t)f;
+    return q > 2097151ull ? 2097151ull : q;
+}
+
+template <class F>
+__global__ void k_morton(const F* __restrict__ x, const F* __restrict__ y, const F* __restrict__ z,
+                         int64_t n, double lox, double loy, double loz, double scale,
+                         uint64_t* __restrict__ keys, uint32_t* __restrict__ idx) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint64_t qx = quantise((double)x[i], lox, scale);
+    uint64_t qy = quantise((double)y[i], loy, scale);
+    uint64_t qz = quantise((double)z[i], loz, scale);
+    keys[i] = spread3(qx) | (spread3(qy) << 1) | (spread3(qz) << 2);
+    idx[i] = (uint32_t)i;
+}
+
+template <class F>
+__global__ void k_permute(const F* __restrict__ x, const F* __restrict__ y, const F* __restrict__ z,
+                          const F* __restrict__ q, int64_t n, const uint32_t* __restrict__ idx,
+                          float4* __restrict__ pts) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    uint32_t i = idx[k];
+    pts[k] = make_float4((float)x[i], (float)y[i], (float)z[i], (float)q[i]);
+}
+
+// first index in [lo, hi) with keys[i] >= v
+__device__ inline int32_t lower_bound_u64(const uint64_t* keys, int32_t lo, int32_t hi, uint64_t v) {
+    while (lo < hi) {
+        int32_t mid = lo + ((hi - lo) >> 1);
+        if (keys[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ inline void octant_bounds(const uint64_t* keys, int32_t b, int32_t e, uint64_t prefix,
+                                     int L, int32_t bnd[9]) {
+    int sh = 3 * (20 - L);  // bit position of the level-(L+1) digit
+    bnd[0] = b;
+    bnd[8] = e;
+    for (int o = 1; o < 8; o++) bnd[o] = lower_bound_u64(keys, b, e, ((prefix << 3) | (uint64_t)o) << sh);
+}
+
+__global__ void k_tree_count(const uint64_t* __restrict__ keys, CellArrays cells, int32_t c0,
+                             int32_t c1, int L, int32_t ncrit, uint32_t* __restrict__ nsplit) {
+    int32_t c = c0 + (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (c >= c1) return;
+    int32_t b = cells.begin[c], e = cells.end[c];
+    uint32_t cnt = 0;
+    if (e - b > ncrit && L < kMaxLevel) {
+        int32_t bnd[9];
+        octant_bounds(keys, b, e, cells.prefix[c], L, bnd);
+        for (int o = 0; o < 8; o++) cnt += bnd[o + 1] > bnd[o] ? 1u : 0u;
+    }
+    nsplit[c - c0] = cnt;
+}
+
+__global__ void k_tree_emit(const uint64_t* __restrict__ keys, CellArrays cells, int32_t c0,
+                            int32_t c1, int L, const uint32_t* __restrict__ nsplit,
+                            const uint32_t* __restrict__ off) {
+    int32_t c = c0 + (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (c >= c1) return;
+    uint32_t cnt = nsplit[c - c0];
+    if (cnt == 0) {
+        cells.child[c] = -1;
+        cells.nchild[c] = 0;
+        return;
+    }
+    int32_t first = c1 + (int32_t)off[c - c0];
+    cells.child[c] = first;
+    cells.nchild[c] = (int32_t)cnt;
+    int32_t bnd[9];
+    uint64_t prefix = cells.prefix[c];
+    octant_bounds(keys, cells.begin[c], cells.end[c], prefix, L, bnd);
+    int32_t k = first;
+    for (int o = 0; o < 8; o++) {
+        if (bnd[o + 1] <= bnd[o]) continue;
+        cells.begin[k] = bnd[o];
+        cells.end[k] = bnd[o + 1];
+        cells.parent[k] = c;
+        cells.level[k] = L + 1;
+        cells.prefix[k] = (prefix << 3) | (uint64_t)o;
+        cells.child[k] = -1;
+        cells.nchild[k] = 0;
+        k++;
+    }
+}
+
+__global__ void k_geometry(CellArrays cells, int32_t ncell, double lox, double loy, double loz,
+                           double h) {
+    int32_t c = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (c >= ncell) return;
+    int L = cells.level[c];
+    uint64_t pre = cells.prefix[c];
+    int32_t a[3] = {0, 0, 0};
+    for (int b = 0; b < L; b++) {
+        a[0] |= (int32_t)((pre >> (3 * b)) & 1u) << b;
+        a[1] |= (int32_t)((pre >> (3 * b + 1)) & 1u) << b;
+        a[2] |= (int32_t)((pre >> (3 * b + 2)) & 1u) << b;
+    }
+    int32_t r = 1 << (kMaxLevel - L);
+    int4 g = make_int4((2 * a[0] + 1) * r, (2 * a[1] + 1) * r, (2 * a[2] + 1) * r, r);
+    cells.geo[c] = g;
+    double4 ph;
+    ph.x = __dadd_rn(lox, __dmul_rn((double)g.x, h));
+    ph.y = __dadd_rn(loy, __dmul_rn((double)g.y, h));
+    ph.z = __dadd_rn(loz, __dmul_rn((double)g.z, h));
+    ph.w = __dmul_rn((double)r, h);
+    cells.ctr[c] = ph;
+}
+
+}  // namespace
+
+size_t bbox_ws_bytes(int64_t) { return 1024 * 6 * sizeof(double) + 64; }
+
+void bbox(const void* x, const void* y, const void* z, int dtype, int64_t n, double* out6,
+          uint32_t* bad, void* ws, hipStream_t s) {
+    int nb = (int)std::min<int64_t>(1024, (n + BB - 1) / BB);
+    if (nb < 1) nb = 1;
+    double* part = (double*)ws;
+    hipMemsetAsync(bad, 0, sizeof(uint32_t), s);
+    if (dtype == 1)
+        k_bbox<double><<<nb, BB, 0, s>>>((const double*)x, (const double*)y, (const double*)z, n, part, bad);
+    else
+        k_bbox<float><<<nb, BB, 0, s>>>((const float*)x, (const float*)y, (const float*)z, n, part, bad);
+    k_bbox_final<<<1, 64, 0, s>>>(part, nb, out6);
+}
+
+void morton_keys(const void* x, const void* y, const void* z, int dtype, int64_t n, double lox,
+                 double loy, double loz, double scale, uint64_t* keys, uint32_t* idx, hipStream_t s) {
+    if (n <= 0) return;
+    unsigned g = (unsigned)((n + 255) / 256);
+    if (dtype == 1)
+        k_morton<double><<<g, 256, 0, s>>>((const double*)x, (const double*)y, (const double*)z, n, lox,
+                                           loy, loz, scale, keys, idx);
+    else
+        k_morton<float><<<g, 256, 0, s>>>((const float*)x, (const float*)y, (const float*)z, n, lox, loy,
+                                          loz, scale, keys, idx);
+}
+
+void permute_points(const void* x, const void* y, const void* z, const void* q, int dtype, int64_t n,
+                    const uint32_t* idx, float4* pts, hipStream_t s) {
+    if (n <= 0) return;
+    unsigned g = (unsigned)((n + 255) / 256);
+    if (dtype == 1)
+        k_permute<double><<<g, 256, 0, s>>>((const double*)x, (const double*)y, (const double*)z,
+                                            (const double*)q, n, idx, pts);
+    else
+        k_permute<float><<<g, 256, 0, s>>>((const float*)x, (const float*)y, (const float*)z,
+                                           (const float*)q, n, idx, pts);
+}
+
+void tree_count(const uint64_t* keys, CellArrays cells, int32_t c0, int32_t c1, int L, int32_t ncrit,
+                uint32_t* nsplit, hipStream_t s) {
+    int32_t m = c1 - c0;
+    if (m <= 0) return;
+    k_tree_count<<<(m + 255) / 256, 256, 0, s>>>(keys, cells, c0, c1, L, ncrit, nsplit);
+}
+
+void tree_emit(const uint64_t* keys, CellArrays cells, int32_t c0, int32_t c1, int L,
+               const uint32_t* nsplit, const uint32_t* child_off, hipStream_t s) {
+    int32_t m = c1 - c0;
+    if (m <= 0) return;
+    k_tree_emit<<<(m + 255) / 256, 256, 0, s>>>(keys, cells, c0, c1, L, nsplit, child_off);
+}
+
+void cell_geometry(CellArrays cells, int32_t ncell, double lox, double loy, double loz, double side,
+                   hipStream_t s) {
+    if (ncell <= 0) return;
+    double h = side / 4194304.0;
+    k_geometry<<<(ncell + 255) / 256, 256, 0, s>>>(cells, ncell, lox, loy, loz, h);
+}
+
+}  // namespace fmm

@@ -1,0 +1,324 @@
+// k_util.hip -- device-wide exclusive scans and a stable LSD radix sort.
+//
+// Scan: reduce tiles -> scan tile sums in one workgroup -> scan within tiles.
+// Radix sort: 8-bit digits; per tile a digit histogram, a scan of the
+// digit-major histogram table, then a stable scatter in which each wave ranks
+// its 64 keys per round with 8 ballots (lanes holding the same digit form a
+// mask; rank = popcount of the lower lanes of that mask).  Tiles are 4096
+// keys: 4 waves x 16 rounds x 64 lanes, processed in index order, so equal
+// digits keep their input order.
+#include "fmm_internal.h"
+
+namespace fmm {
+namespace {
+
+constexpr int SB = 256;          // scan threads per block
+constexpr int SI = 8;            // items per thread
+constexpr int ST = SB * SI;      // items per tile
+
+__device__ inline uint32_t wave_incl_u32(uint32_t v, int lane) {
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t t = __shfl_up(v, d, 64);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+struct U1 {
+    uint32_t a;
+};
+
+template <class T>
+struct Ops;
+
+template <>
+struct Ops<uint32_t> {
+    static constexpr int C = 1;
+    __device__ static uint32_t get(const uint32_t& v, int) { return v; }
+    __device__ static void set(uint32_t& v, int, uint32_t x) { v = x; }
+};
+
+template <>
+struct Ops<uint4> {
+    static constexpr int C = 4;
+    __device__ static uint32_t get(const uint4& v, int c) {
+        return c == 0 ? v.x : c == 1 ? v.y : c == 2 ? v.z : v.w;
+    }
+    __device__ static void set(uint4& v, int c, uint32_t x) {
+        if (c == 0) v.x = x;
+        else if (c == 1) v.y = x;
+        else if (c == 2) v.z = x;
+        else v.w = x;
+    }
+};
+
+// block-wide exclusive scan of one u32 per thread (SB threads); returns the
+// exclusive prefix and writes the block total into *tot (all threads).
+__device__ inline uint32_t block_excl_u32(uint32_t v, uint32_t* lds, uint32_t* tot) {
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t inc = wave_incl_u32(v, lane);
+    if (lane == 63) lds[w] = inc;
+    __syncthreads();
+    uint32_t pre = 0, all = 0;
+#pragma unroll
+    for (int i = 0; i < SB / 64; i++) {
+        uint32_t t = lds[i];
+        if (i < w) pre += t;
+        all += t;
+    }
+    __syncthreads();
+    *tot = all;
+    return pre + inc - v;
+}
+
+template <class T>
+__global__ void k_scan_reduce(const T* __restrict__ in, int64_t n, T* __restrict__ part) {
+    __shared__ uint32_t lds[SB / 64];
+    int64_t base = (int64_t)blockIdx.x * ST;
+    T out;
+    for (int c = 0; c < Ops<T>::C; c++) {
+        uint32_t acc = 0;
+        for (int i = threadIdx.x; i < ST; i += SB) {
+            int64_t g = base + i;
+            if (g < n) acc += Ops<T>::get(in[g], c);
+        }
+        uint32_t tot;
+        block_excl_u32(acc, lds, &tot);
+        Ops<T>::set(out, c, tot);
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = out;
+}
+
+// one workgroup of SB threads scans the nb tile sums in place (exclusive)
+template <class T>
+__global__ void k_scan_partials(T* part, int64_t nb, T* total) {
+    __shared__ uint32_t lds[SB / 64];
+    for (int c = 0; c < Ops<T>::C; c++) {
+        uint32_t carry = 0;
+        for (int64_t b0 = 0; b0 < nb; b0 += SB) {
+            int64_t g = b0 + threadIdx.x;
+            uint32_t v = g < nb ? Ops<T>::get(part[g], c) : 0u;
+            uint32_t tot;
+            uint32_t ex = block_excl_u32(v, lds, &tot);
+            if (g < nb) {
+                T t = part[g];
+                Ops<T>::set(t, c, ex + carry);
+                part[g] = t;
+            }
+            carry += tot;
+        }
+        if (threadIdx.x == 0 && total) {
+            T t = *total;
+            Ops<T>::set(t, c, carry);
+            *total = t;
+        }
+        __syncthreads();
+    }
+}
+
+template <class T>
+__global__ void k_scan_down(const T* __restrict__ in, T* __restrict__ out, int64_t n,
+                            const T* __restrict__ part) {
+    __shared__ uint32_t lds[SB / 64];
+    int64_t base = (int64_t)blockIdx.x * ST + (int64_t)threadIdx.x * SI;
+    T v[SI];
+#pragma unroll
+    for (int j = 0; j < SI; j++) {
+        int64_t g = base + j;
+        if (g < n) v[j] = in[g];
+        else
+            for (int c = 0; c < Ops<T>::C; c++) Ops<T>::set(v[j], c, 0u);
+    }
+    T pb = part[blockIdx.x];
+    T res[SI];
+    for (int c = 0; c < Ops<T>::C; c++) {
+        uint32_t s = 0;
+#pragma unroll
+        for (int j = 0; j < SI; j++) s += Ops<T>::get(v[j], c);
+        uint32_t tot;
+        uint32_t run = block_excl_u32(s, lds, &tot) + Ops<T>::get(pb, c);
+#pragma unroll
+        for (int j = 0; j < SI; j++) {
+            Ops<T>::set(res[j], c, run);
+            run += Ops<T>::get(v[j], c);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < SI; j++) {
+        int64_t g = base + j;
+        if (g < n) out[g] = res[j];
+    }
+}
+
+template <class T>
+void scan_impl(const T* in, T* out, T* total, int64_t n, void* ws, hipStream_t s) {
+    if (n <= 0) {
+        if (total) hipMemsetAsync(total, 0, sizeof(T), s);
+        return;
+    }
+    int64_t nb = (n + ST - 1) / ST;
+    T* part = (T*)ws;
+    k_scan_reduce<T><<<(unsigned)nb, SB, 0, s>>>(in, n, part);
+    k_scan_partials<T><<<1, SB, 0, s>>>(part, nb, total);
+    k_scan_down<T><<<(unsigned)nb, SB, 0, s>>>(in, out, n, part);
+}
+
+// ------------------------------------------------------------------ radix sort
+constexpr int RB = 256;
+constexpr int RW = RB / 64;
+constexpr int RR = 16;
+constexpr int RT = RB * RR;
+
+template <class K>
+__device__ inline uint32_t digit_of(K k, int shift) {
+    return (uint32_t)(k >> shift) & 255u;
+}
+
+template <class K>
+__global__ void k_rs_hist(const K* __restrict__ keys, int64_t n, int shift,
+                          uint32_t* __restrict__ ghist, int64_t nb) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t base = (int64_t)blockIdx.x * RT;
+    for (int i = threadIdx.x; i < RT; i += RB) {
+        int64_t g = base + i;
+        if (g < n) atomicAdd(&h[digit_of(keys[g], shift)], 1u);
+    }
+    __syncthreads();
+    ghist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+}
+
+template <class K>
+__global__ void k_rs_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
+                             K* __restrict__ kout, uint32_t* __restrict__ vout, int64_t n,
+                             int shift, const uint32_t* __restrict__ goff, int64_t nb) {
+    __shared__ uint32_t wc[RW][256];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int i = threadIdx.x; i < RW * 256; i += RB) (&wc[0][0])[i] = 0;
+    __syncthreads();
+    const int64_t wbase = (int64_t)blockIdx.x * RT + (int64_t)w * (RR * 64);
+    for (int r = 0; r < RR; r++) {
+        int64_t g = wbase + r * 64 + lane;
+        if (g < n) atomicAdd(&wc[w][digit_of(kin[g], shift)], 1u);
+    }
+    __syncthreads();
+    {
+        int d = threadIdx.x;  // RB == 256 digits
+        uint32_t run = goff[(int64_t)d * nb + blockIdx.x];
+        for (int ww = 0; ww < RW; ww++) {
+            uint32_t c = wc[ww][d];
+            wc[ww][d] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    for (int r = 0; r < RR; r++) {
+        int64_t g = wbase + r * 64 + lane;
+        bool valid = g < n;
+        K k = 0;
+        uint32_t v = 0, d = 0;
+        if (valid) {
+            k = kin[g];
+            v = vin[g];
+            d = digit_of(k, shift);
+        }
+        uint64_t mask = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; b++) {
+            bool bit = (d >> b) & 1u;
+            uint64_t bb = __ballot(valid && bit);
+            mask &= bit ? bb : ~bb;
+        }
+        uint32_t rank = (uint32_t)__popcll(mask & lt);
+        uint32_t basev = valid ? wc[w][d] : 0u;
+        if (valid) {
+            kout[basev + rank] = k;
+            vout[basev + rank] = v;
+        }
+        bool leader = valid && ((mask >> lane) == 1ull);
+        if (leader) wc[w][d] = basev + (uint32_t)__popcll(mask);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+template <class K>
+void sort_impl(K* ka, uint32_t* va, K* kb, uint32_t* vb, int64_t n, int bit0, int bit1, void* ws,
+               hipStream_t s) {
+    if (n <= 1 || bit1 <= bit0) return;
+    int64_t nb = (n + RT - 1) / RT;
+    uint32_t* ghist = (uint32_t*)ws;
+    uint32_t* goff = ghist + 256 * nb;
+    void* sws = goff + 256 * nb;
+    K *ki = ka, *ko = kb;
+    uint32_t *vi = va, *vo = vb;
+    int passes = 0;
+    for (int sh = bit0; sh < bit1; sh += 8) {
+        k_rs_hist<K><<<(unsigned)nb, RB, 0, s>>>(ki, n, sh, ghist, nb);
+        scan_impl<uint32_t>(ghist, goff, nullptr, 256 * nb, sws, s);
+        k_rs_scatter<K><<<(unsigned)nb, RB, 0, s>>>(ki, vi, ko, vo, n, sh, goff, nb);
+        K* tk = ki; ki = ko; ko = tk;
+        uint32_t* tv = vi; vi = vo; vo = tv;
+        passes++;
+    }
+    if (passes & 1) {
+        hipMemcpyAsync(ka, ki, n * sizeof(K), hipMemcpyDeviceToDevice, s);
+        hipMemcpyAsync(va, vi, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
+    }
+}
+
+__global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_iota_u32(uint32_t* p, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = (uint32_t)i;
+}
+
+}  // namespace
+
+size_t scan_ws_bytes(int64_t n) {
+    int64_t nb = (n + ST - 1) / ST + 1;
+    return (size_t)nb * sizeof(uint4) + 256;
+}
+
+void scan_u32(const uint32_t* in, uint32_t* out, uint32_t* total, int64_t n, void* ws,
+              hipStream_t s) {
+    scan_impl<uint32_t>(in, out, total, n, ws, s);
+}
+
+void scan_u32x4(const uint4* in, uint4* out, uint4* total, int64_t n, void* ws, hipStream_t s) {
+    scan_impl<uint4>(in, out, total, n, ws, s);
+}
+
+size_t sort_ws_bytes(int64_t n) {
+    int64_t nb = (n + RT - 1) / RT + 1;
+    return (size_t)2 * 256 * nb * sizeof(uint32_t) + scan_ws_bytes(256 * nb) + 256;
+}
+
+void sort_u64(uint64_t* ka, uint32_t* va, uint64_t* kb, uint32_t* vb, int64_t n, int bit0,
+              int bit1, void* ws, hipStream_t s) {
+    sort_impl<uint64_t>(ka, va, kb, vb, n, bit0, bit1, ws, s);
+}
+
+void sort_u32(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int64_t n, int bit0,
+              int bit1, void* ws, hipStream_t s) {
+    sort_impl<uint32_t>(ka, va, kb, vb, n, bit0, bit1, ws, s);
+}
+
+void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    k_fill_i32<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, v, n);
+}
+
+void iota_u32(uint32_t* p, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    k_iota_u32<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, n);
+}
+
+}  // namespace fmm
