@@ -158,7 +158,7 @@ def test_expansions_match_oracle():
     Mg, Lg = f.expansions()
     _, _, tr = ora.fmm(x, y, z, q, 8, 0.5, 20)
     Mo, Lo = tr.expansions()
-    r = tr.cells()["radius"][:, None]
+    r = tr.cells()["radius"]
     Mref = to_real_scaled(Mo, 8, r, -1)
     Lref = to_real_scaled(Lo, 8, r, +1)
     assert np.abs(Mg - Mref).max() <= 1e-5 * np.abs(Mref).max()
