@@ -72,7 +72,8 @@ struct fmm_ctx_s {
     // same-level M2L batching
     M2LPlan plan;
     Buf d_slot, d_offid, d_T;
-    Buf has_fast, rkey, rval, rkey2, rval2, rowof, gather, general;
+    Buf has_fast, rkey, rval, rkey2, rval2, rowof, gather, general, gtg, gsr, goff;
+    bool m2l_sorted = false;
     GemmPlan gp{};
     int ntiles = 0;
     int64_t nrows = 0;
@@ -90,6 +91,9 @@ struct fmm_ctx_s {
     // expansions and near-field partials
     Buf M, L, nearb;
 
+    // kernel pre-calculation inputs/outputs
+    Buf tune_pts, tune_out;
+
     // pinned host staging
     void* host = nullptr;
 
@@ -98,8 +102,8 @@ struct fmm_ctx_s {
                       &c_nchild, &c_level, &c_prefix, &c_geo, &c_ctr, &leaves, &tmp1, &tmp2, &fr0, &fr1,
                       &cnt, &off4, &raw[0], &raw[1], &raw[2], &tgt[0], &tgt[1], &tgt[2], &src[0], &src[1],
                       &src[2], &off[0], &off[1], &off[2], &tgt2, &src2, &d_slot, &d_offid, &d_T, &has_fast,
-                      &rkey, &rval, &rkey2, &rval2, &rowof, &gather, &general, &d_m2m, &d_l2l, &d_w, &d_g,
-                      &d_h, &d_rc, &d_mlp, &M, &L, &nearb};
+                      &rkey, &rval, &rkey2, &rval2, &rowof, &gather, &general, &gtg, &gsr, &goff, &d_m2m, &d_l2l, &d_w, &d_g,
+                      &d_h, &d_rc, &d_mlp, &M, &L, &nearb, &tune_pts, &tune_out};
         for (Buf* b : all) bufs.push_back(b);
     }
 };
@@ -462,48 +466,50 @@ void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
     }
     mark(c, PH_LISTS);
     int bits = bits_for(nc);
-    for (int k = 0; k < 3; k++) {
-        int64_t m = c->nlist[k];
-        uint32_t* tg = need<uint32_t>(c, c->tgt[k], m + 1);
-        uint32_t* sr = need<uint32_t>(c, c->src[k], m + 1);
-        int32_t* of = need<int32_t>(c, c->off[k], (size_t)nc + 1);
+    // split + stable sort by target + CSR offsets
+    auto sort_into = [&](const int2* raw, int64_t m, Buf& TG, Buf& SR, Buf& OF) {
+        uint32_t* tg = need<uint32_t>(c, TG, m + 1);
+        uint32_t* sr = need<uint32_t>(c, SR, m + 1);
+        int32_t* of = need<int32_t>(c, OF, (size_t)nc + 1);
         if (m > 0) {
             size_t wsn = sort_ws_bytes(m);
-            if (wsn > c->ws.cap) {
-                ck(hipStreamSynchronize(s), "sync");
-                ws = need<char>(c, c->ws, wsn);
-            }
+            if (wsn > c->ws.cap) ws = need<char>(c, c->ws, wsn);
             uint32_t* tg2 = need<uint32_t>(c, c->tgt2, m);
             uint32_t* sr2 = need<uint32_t>(c, c->src2, m);
-            split_pairs((int2*)c->raw[k].p, m, tg, sr, s);
+            if (raw) split_pairs(raw, m, tg, sr, s);
             sort_u32(tg, sr, tg2, sr2, m, 0, bits, ws, s);
         }
         csr_offsets(tg, m, nc, of, s);
         check_launch("lists");
-    }
-    // same-level M2L batching for the matrix cores
+    };
+    // cell-particle and particle-particle lists: the kernels walk them by target
+    sort_into((int2*)c->raw[1].p, c->nlist[1], c->tgt[1], c->src[1], c->off[1]);
+    sort_into((int2*)c->raw[2].p, c->nlist[2], c->tgt[2], c->src[2], c->off[2]);
+    // cell-cell list: kept in emission order; same-level pairs go to the GEMM
+    // gather table, the rest are compacted and grouped by target
+    c->m2l_sorted = false;
     c->gemm_on = m2l_gemm_supported(p) && c->nlist[0] > 0;
     c->ntiles = 0;
     c->nrows = 0;
     c->ngeneral = 0;
     int64_t nm = c->nlist[0];
+    uint32_t* tg0 = need<uint32_t>(c, c->tgt[0], nm + 1);
+    uint32_t* sr0 = need<uint32_t>(c, c->src[0], nm + 1);
     uint32_t* gen = need<uint32_t>(c, c->general, nm + 1);
+    if (nm > 0) split_pairs((int2*)c->raw[0].p, nm, tg0, sr0, s);
     if (c->gemm_on) {
         upload_plan(c, p, theta);
         int R = c->plan.R, J = c->plan.J;
         uint32_t* hf = need<uint32_t>(c, c->has_fast, nc);
         ck(hipMemsetAsync(hf, 0, (size_t)nc * 4, s), "memset");
-        m2l_mark_targets((uint32_t*)c->tgt[0].p, (uint32_t*)c->src[0].p, nm, ca, (int32_t*)c->d_slot.p, R, hf, s);
+        m2l_mark_targets(tg0, sr0, nm, ca, (int32_t*)c->d_slot.p, R, hf, s);
         uint32_t* rk = need<uint32_t>(c, c->rkey, nc);
         uint32_t* rv = need<uint32_t>(c, c->rval, nc);
         uint32_t* rk2 = need<uint32_t>(c, c->rkey2, nc);
         uint32_t* rv2 = need<uint32_t>(c, c->rval2, nc);
         row_class_keys(hf, ca, nc, rk, rv, s);
         size_t wsn = sort_ws_bytes(nc);
-        if (wsn > c->ws.cap) {
-            ck(hipStreamSynchronize(s), "sync");
-            ws = need<char>(c, c->ws, wsn);
-        }
+        if (wsn > c->ws.cap) ws = need<char>(c, c->ws, wsn);
         sort_u32(rk, rv, rk2, rv2, nc, 0, 8, ws, s);
         int32_t* d9 = (int32_t*)(d6 + 20);
         class_bounds(rk, nc, d9, s);
@@ -511,10 +517,11 @@ void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
         int32_t* h9 = (int32_t*)host_stage(c);
         to_host<int32_t>(c, h9, d9, 9);
         int tiles = 0;
+        const int tc = gemm_tile_cols(p);
         for (int k = 0; k < 9; k++) {
             c->gp.class_row0[k] = h9[k];
             c->gp.class_tile0[k] = tiles;
-            if (k < 8) tiles += (h9[k + 1] - h9[k] + kGemmTile - 1) / kGemmTile;
+            if (k < 8) tiles += (h9[k + 1] - h9[k] + tc - 1) / tc;
         }
         c->gp.J = J;
         c->ntiles = tiles;
@@ -524,23 +531,26 @@ void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
         rows_inverse(rv, c->nrows, ro, s);
         int32_t* ga = need<int32_t>(c, c->gather, (size_t)std::max<int64_t>(c->nrows, 1) * J);
         fill_i32(ga, -1, c->nrows * J, s);
-        m2l_fill_gather((uint32_t*)c->tgt[0].p, (uint32_t*)c->src[0].p, nm, ca, (int32_t*)c->d_slot.p, R, ro, J,
-                        ga, gen, s);
+        m2l_fill_gather(tg0, sr0, nm, ca, (int32_t*)c->d_slot.p, R, ro, J, ga, gen, s);
         check_launch("m2l gather");
-        uint32_t* gtmp = need<uint32_t>(c, c->tgt2, nm + 1);
+    } else if (nm > 0) {
+        fill_i32((int32_t*)gen, 1, nm, s);
+    }
+    if (nm > 0) {
         size_t wsg = scan_ws_bytes(nm);
-        if (wsg > c->ws.cap) {
-            ck(hipStreamSynchronize(s), "sync");
-            ws = need<char>(c, c->ws, wsg);
-        }
-        scan_u32(gen, gtmp, (uint32_t*)(d6 + 12), nm, ws, s);
+        if (wsg > c->ws.cap) ws = need<char>(c, c->ws, wsg);
+        uint32_t* pos = need<uint32_t>(c, c->tgt2, nm + 1);
+        scan_u32(gen, pos, (uint32_t*)(d6 + 12), nm, ws, s);
         uint32_t* hg = (uint32_t*)host_stage(c);
         to_host<uint32_t>(c, hg, d6 + 12, 1);
         c->ngeneral = hg[0];
-    } else if (nm > 0) {
-        // every pair through the general kernel
-        fill_i32((int32_t*)gen, 1, nm, s);
-        c->ngeneral = nm;
+    }
+    {
+        int64_t ng = c->ngeneral;
+        uint32_t* gt = need<uint32_t>(c, c->gtg, ng + 1);
+        uint32_t* gs = need<uint32_t>(c, c->gsr, ng + 1);
+        if (ng > 0) compact_pairs(tg0, sr0, gen, (uint32_t*)c->tgt2.p, nm, gt, gs, s);
+        sort_into(nullptr, ng, c->gtg, c->gsr, c->goff);
     }
     ck(hipStreamSynchronize(s), "sync");
     c->traversed = true;
@@ -573,9 +583,7 @@ void evaluate_impl(fmm_ctx c, int32_t precision, int32_t out_dtype, void* phi, v
         m2l_gemm((float*)c->d_T.p, (int32_t*)c->d_offid.p, (int32_t*)c->gather.p, (uint32_t*)c->rval.p, c->gp, p, KP,
                  M, L, c->ntiles, precision, s);
     mark(c, PH_M2LG);
-    if (c->nlist[0] > 0)
-        m2l_general((int32_t*)c->off[0].p, (uint32_t*)c->src[0].p, (uint32_t*)c->general.p, ca, nc, p, KP, tb, M, L,
-                    s);
+    if (c->ngeneral > 0) m2l_general((int32_t*)c->goff.p, (uint32_t*)c->gsr.p, ca, nc, p, KP, tb, M, L, s);
     check_launch("m2l");
     mark(c, PH_DOWN);
     for (int Lv = 1; Lv < nlev; Lv++) l2l(ca, c->lvl[Lv], c->lvl[Lv + 1], p, KP, tb, L, s);
@@ -701,11 +709,72 @@ fmm_status fmm_get_costs(fmm_ctx c, double* costs3) {
     });
 }
 
+// Kernel pre-calculation ("Kernel pre-calculation"): every kernel is run on
+// artificial coordinates and charges (and the multipoles they produce) in a
+// private context with event timing, and the unit costs are the measured
+// times divided by the work units: M2L pairs of the batched GEMM, target
+// particles of M2P pairs, particle pairs of P2P.  The instance is large
+// enough to fill the GPU, because small pre-tests mispredict on a GPU
+// ("Results").
 fmm_status fmm_tune(fmm_ctx c, int32_t p, int32_t precision) {
     return guarded(c, [&] {
-        (void)p;
-        (void)precision;
-        fail(FMM_ERR_UNSUPPORTED, "kernel pre-calculation is not built yet");
+        if (p < 0 || p > FMM_P_MAX) fail(FMM_ERR_INVALID_ARG, "p out of range");
+        if (precision != FMM_PREC_FP32) fail(FMM_ERR_UNSUPPORTED, "only FMM_PREC_FP32 is implemented");
+        const int64_t n = 1 << 19;
+        const int32_t ncrit = 32;
+        const double theta = 0.5;
+        float* pts = need<float>(c, c->tune_pts, (size_t)4 * n);
+        artificial_points(n, 12345, pts, pts + n, pts + 2 * n, pts + 3 * n, c->stream);
+        float* out = need<float>(c, c->tune_out, (size_t)4 * n);
+        check_launch("artificial points");
+        fmm_ctx t = nullptr;
+        fmm_status st = fmm_create(&t, c->device, c->stream);
+        if (st != FMM_OK) fail(st, "calibration context");
+        struct Del {
+            fmm_ctx t;
+            ~Del() { fmm_destroy(t); }
+        } del{t};
+        t->timing = true;
+        double tm[2][PH_N] = {};
+        int64_t units[3] = {0, 0, 0};
+        for (int pol = 0; pol < 2; pol++) {
+            build_tree_impl(t, n, FMM_F32, pts, pts + n, pts + 2 * n, pts + 3 * n, ncrit);
+            traverse_impl(t, p, theta, pol == 0 ? FMM_POLICY_FMM : FMM_POLICY_TREECODE);
+            for (int rep = 0; rep < 3; rep++) {
+                evaluate_impl(t, precision, FMM_F32, out, out + n, out + 2 * n, out + 3 * n);
+                if (rep > 0)
+                    for (int k = 0; k < PH_N; k++) tm[pol][k] += t->ms[k] / 2;
+            }
+            // work units from the lists and the cells' particle counts
+            std::vector<int32_t> b(t->ncell), e(t->ncell);
+            to_host<int32_t>(t, b.data(), t->c_begin.p, t->ncell);
+            to_host<int32_t>(t, e.data(), t->c_end.p, t->ncell);
+            int kind = pol == 0 ? 2 : 1;
+            int64_t m = t->nlist[kind];
+            std::vector<uint32_t> tg(m), sr(m);
+            to_host<uint32_t>(t, tg.data(), t->tgt[kind].p, m);
+            to_host<uint32_t>(t, sr.data(), t->src[kind].p, m);
+            int64_t u = 0;
+            for (int64_t i = 0; i < m; i++) {
+                int64_t nt = e[tg[i]] - b[tg[i]], ns = e[sr[i]] - b[sr[i]];
+                u += kind == 2 ? nt * ns : nt;
+            }
+            if (pol == 0) {
+                units[0] = t->nlist[0] - t->ngeneral;
+                units[2] = u;
+            } else {
+                units[1] = u;
+            }
+        }
+        if (units[0] <= 0 || units[1] <= 0 || units[2] <= 0) fail(FMM_ERR_DEVICE, "calibration produced no work");
+        // ms -> ns per unit
+        double c_m2l = tm[0][PH_M2L] * 1e6 / (double)units[0];
+        double c_p2p = tm[0][PH_P2P] * 1e6 / (double)units[2];
+        double c_m2p = std::max(tm[1][PH_FAR] - tm[0][PH_FAR], 1e-6) * 1e6 / (double)units[1];
+        c->costs[0] = c_m2l;
+        c->costs[1] = c_m2p;
+        c->costs[2] = c_p2p;
+        c->costs_set = true;
     });
 }
 
@@ -778,6 +847,17 @@ fmm_status fmm_get_list(fmm_ctx c, int32_t kind, int32_t* tgt, int32_t* src) {
         if (kind < 0 || kind > 2) fail(FMM_ERR_INVALID_ARG, "unknown list kind");
         size_t m = c->nlist[kind];
         if (m == 0) return;
+        if (kind == 0 && !c->m2l_sorted) {
+            // the cell-cell list is grouped by target only on request
+            void* ws = need<char>(c, c->ws, std::max(sort_ws_bytes(m), c->ws.cap));
+            uint32_t* tg = need<uint32_t>(c, c->tgt[0], m + 1);
+            uint32_t* sr = need<uint32_t>(c, c->src[0], m + 1);
+            split_pairs((int2*)c->raw[0].p, m, tg, sr, c->stream);
+            sort_u32(tg, sr, need<uint32_t>(c, c->tgt2, m), need<uint32_t>(c, c->src2, m), m, 0,
+                     bits_for(c->ncell), ws, c->stream);
+            check_launch("sort list");
+            c->m2l_sorted = true;
+        }
         if (tgt) to_host<int32_t>(c, tgt, c->tgt[kind].p, m);
         if (src) to_host<int32_t>(c, src, c->src[kind].p, m);
     });

@@ -18,6 +18,8 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "host_ops.h"
+
 namespace fmm {
 
 constexpr int kMaxP = 16;
@@ -36,7 +38,6 @@ struct CellArrays {
 };
 
 inline int ncoef(int p) { return (p + 1) * (p + 1); }
-inline int kpad(int p) { return ((ncoef(p) + 31) / 32) * 32; }
 
 // ------------------------------------------------------------------ utilities
 // Exclusive prefix sums.  `total` (device, may be null) receives the sum.
@@ -54,6 +55,8 @@ void sort_u32(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* va
               int bit0, int bit1, void* ws, hipStream_t s);
 
 void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+// artificial particles for the kernel pre-calculation: uniform in [0,1)^3, charges +-1
+void artificial_points(int64_t n, uint64_t seed, float* x, float* y, float* z, float* q, hipStream_t s);
 void iota_u32(uint32_t* p, int64_t n, hipStream_t s);
 
 // ------------------------------------------------------------------ tree
@@ -107,6 +110,9 @@ void m2l_fill_gather(const uint32_t* tgt, const uint32_t* src, int64_t n, CellAr
 void row_class_keys(const uint32_t* has_fast, CellArrays cells, int32_t ncell, uint32_t* key,
                     uint32_t* val, hipStream_t s);
 void rows_inverse(const uint32_t* rowcell, int64_t nrows, int32_t* rowof, hipStream_t s);
+// keep the pairs whose flag is set: out[pos[i]] = pair i (pos = exclusive scan of flag)
+void compact_pairs(const uint32_t* tgt, const uint32_t* src, const uint32_t* flag, const uint32_t* pos, int64_t n,
+                   uint32_t* otgt, uint32_t* osrc, hipStream_t s);
 // out9[c] = first index of the sorted class keys with key >= c, c = 0..8
 void class_bounds(const uint32_t* key_sorted, int64_t n, int32_t* out9, hipStream_t s);
 // leaf cells (nchild == 0) in cell order; flag/pos are scratch of ncell entries
@@ -129,8 +135,9 @@ void m2m(CellArrays cells, int32_t c0, int32_t c1, int p, int KP, Tables t, floa
          hipStream_t s);
 void l2l(CellArrays cells, int32_t c0, int32_t c1, int p, int KP, Tables t, float* L,
          hipStream_t s);
-void m2l_general(const int32_t* off, const uint32_t* src, const uint32_t* general, CellArrays cells,
-                 int32_t ncell, int p, int KP, Tables t, const float* M, float* L, hipStream_t s);
+// M2L of the pairs outside the batched GEMM, given as a CSR list by target
+void m2l_general(const int32_t* goff, const uint32_t* gsrc, CellArrays cells, int32_t ncell, int p, int KP,
+                 Tables t, const float* M, float* L, hipStream_t s);
 void far_final(const float4* pts, const uint32_t* perm, CellArrays cells, const int32_t* leaves,
                int32_t nleaves, const int32_t* m2p_off, const uint32_t* m2p_src, int p, int KP,
                Tables t, const float* M, const float* L, const double4* near, int out_dtype,
@@ -148,7 +155,7 @@ struct GemmPlan {
 void m2l_gemm(const float* T, const int32_t* offid, const int32_t* gather, const uint32_t* rowcell,
               GemmPlan plan, int p, int KP, const float* M, float* L, int ntiles, int precision,
               hipStream_t s);
-constexpr int kGemmTile = 64;  // targets per GEMM tile
 bool m2l_gemm_supported(int p);
+int gemm_tile_cols(int p);  // targets per GEMM tile for order p
 
 }  // namespace fmm

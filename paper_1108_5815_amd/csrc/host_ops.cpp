@@ -169,7 +169,7 @@ void build_tables(int p, HostTables& t) {
     int K = (p + 1) * (p + 1);
     t.p = p;
     t.K = K;
-    t.KP = ((K + 31) / 32) * 32;
+    t.KP = kpad(p);
     t.m2m.assign((size_t)8 * K * K, 0.f);
     t.l2l.assign((size_t)8 * K * K, 0.f);
     std::vector<double> Mt;
@@ -276,7 +276,7 @@ void build_m2l_plan(int p, double theta, M2LPlan& plan) {
             plan.slot_of[(size_t)ct * W * W * W + ix] = s;
         }
     int K = (p + 1) * (p + 1);
-    int KP = ((K + 31) / 32) * 32;
+    int KP = kpad(p);
     size_t noff = plan.offsets.size();
     plan.T.assign(noff * KP * KP, 0.f);
     std::vector<double> Mt;

@@ -8,6 +8,16 @@
 
 namespace fmm {
 
+// Row stride of the coefficient arrays for order p: (p+1)^2 rounded up to a
+// multiple of 32, except that 160 and 224 become 192 and 256 so that every
+// stride has a matrix-core tiling (see k_m2l_gemm.hip).
+inline int kpad(int p) {
+    int k = (((p + 1) * (p + 1) + 31) / 32) * 32;
+    if (k == 160) return 192;
+    if (k == 224) return 256;
+    return k;
+}
+
 // Recurrence constants shared by the harmonic kernels (float table):
 //   A(n,m) = (2n-1)/sqrt((n-m)(n+m)),  B(n,m) = sqrt((n-m-1)(n+m-1)/((n-m)(n+m)))
 //   C1(m) = sqrt((2m-1)/(2m)),          C2(m) = sqrt(2m+1)

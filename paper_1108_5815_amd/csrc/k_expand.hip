@@ -202,53 +202,65 @@ __global__ __launch_bounds__(128) void k_l2l(CellArrays c, int32_t c0, int p, in
 }
 
 // ---------------------------------------------------------------- general M2L
-// One workgroup per target cell; the pairs not handled by the batched GEMM
-// (mixed levels, offsets outside the class tables) are converted one by one:
-// irregular harmonics of the offset (in units of the target half side) up to
-// degree 2p into LDS, then every output (j, k) sums
-// W(j,k,n,m) (rs/rt)^n O(n,m) J(j+n, m-k) over (n, m).
-__global__ __launch_bounds__(256) void k_m2l_general(const int32_t* __restrict__ off,
-                                                     const uint32_t* __restrict__ src,
-                                                     const uint32_t* __restrict__ general, CellArrays c,
-                                                     int p, int KP, const float* __restrict__ W,
+// Pairs not handled by the batched GEMM (mixed levels, offsets outside the
+// per-class tables), one workgroup per target cell.  Each of the 4 waves
+// takes every 4th pair of the target: its lanes build the irregular harmonics
+// of the offset (in units of the target half side) up to degree 2p in the
+// wave's LDS area, one column m per lane, then every lane sums
+// W(j,k,n,m) (rs/rt)^n O(n,m) J(j+n, m-k) over (n, m) for its outputs (j, k).
+// The four partial sums are added in wave order: deterministic, no atomics.
+__global__ __launch_bounds__(256) void k_m2l_general(const int32_t* __restrict__ goff,
+                                                     const uint32_t* __restrict__ gsrc, CellArrays c, int p,
+                                                     int KP, const float* __restrict__ W, int w_lds,
                                                      const float* __restrict__ rc, const float* __restrict__ M,
                                                      float* __restrict__ L) {
     extern __shared__ float sh[];
     const int t = blockIdx.x;
-    const int32_t a0 = off[t], a1 = off[t + 1];
-    bool any = false;
-    for (int32_t a = a0; a < a1; a++) any |= general[a] != 0u;
-    if (!any) return;
+    const int32_t a0 = goff[t], a1 = goff[t + 1];
+    if (a0 == a1) return;
     const int K = (p + 1) * (p + 1);
     const int P2 = 2 * p;
-    float* Ms = sh;                 // KP
-    float* Jh = sh + KP;            // 2 * tri(P2)
+    const int TRI = (P2 + 1) * (P2 + 2) / 2;
     const int njk = (p + 1) * (p + 2) / 2;
-    const int jk = threadIdx.x;
-    int j = 0, k = 0;
-    if (jk < njk) {
-        while ((j + 1) * (j + 2) / 2 <= jk) j++;
-        k = jk - j * (j + 1) / 2;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    float* Wl = sh;
+    float* base = sh + (w_lds ? njk * K : 0);
+    float* Ms = base + w * (KP + 2 * TRI);
+    float* Jh = Ms + KP;
+    float* red = base + 4 * (KP + 2 * TRI);
+    if (w_lds)
+        for (int i = threadIdx.x; i < njk * K; i += 256) Wl[i] = W[i];
+    __syncthreads();
+    const float* Wp = w_lds ? Wl : W;
+    int oj[3], ok[3];
+    float are[3] = {0.f, 0.f, 0.f}, aim[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int u = 0; u < 3; u++) {
+        int jk = lane + 64 * u, j = 0;
+        if (jk < njk) {
+            while ((j + 1) * (j + 2) / 2 <= jk) j++;
+            oj[u] = j;
+            ok[u] = jk - j * (j + 1) / 2;
+        } else {
+            oj[u] = -1;
+            ok[u] = 0;
+        }
     }
-    float are = 0.f, aim = 0.f;
     const int4 gt = c.geo[t];
-    for (int32_t a = a0; a < a1; a++) {
-        if (!general[a]) continue;
-        const int s = (int)src[a];
+    const float inv = 1.f / (float)gt.w;
+    for (int32_t a = a0 + w; a < a1; a += 4) {
+        const int s = (int)gsrc[a];
         const int4 gs = c.geo[s];
-        const float inv = 1.f / (float)gt.w;
         const float qx = (float)(gs.x - gt.x) * inv, qy = (float)(gs.y - gt.y) * inv,
                     qz = (float)(gs.z - gt.z) * inv;
         const float ratio = (float)gs.w * inv;
-        __syncthreads();
-        for (int i = threadIdx.x; i < K; i += blockDim.x) Ms[i] = M[(size_t)s * KP + i];
-        // column m of the irregular table: thread m walks n = m .. P2
-        for (int m = threadIdx.x; m <= P2; m += blockDim.x) {
-            float r2 = qx * qx + qy * qy + qz * qz, ir2 = 1.f / r2;
+        for (int i = lane; i < K; i += 64) Ms[i] = M[(size_t)s * KP + i];
+        for (int m = lane; m <= P2; m += 64) {
+            const float r2 = qx * qx + qy * qy + qz * qz, ir2 = 1.f / r2;
             float mre = sqrtf(ir2), mim = 0.f;
             for (int mm = 1; mm <= m; mm++) {
-                float cc = rc[kRcC1 + mm] * ir2;
-                float nre = cc * (qx * mre - qy * mim), nim = cc * (qx * mim + qy * mre);
+                const float cc = rc[kRcC1 + mm] * ir2;
+                const float nre = cc * (qx * mre - qy * mim), nim = cc * (qx * mim + qy * mre);
                 mre = nre;
                 mim = nim;
             }
@@ -256,17 +268,17 @@ __global__ __launch_bounds__(256) void k_m2l_general(const int32_t* __restrict__
             Jh[2 * tt] = mre;
             Jh[2 * tt + 1] = mim;
             if (m < P2) {
-                float c2 = rc[kRcC2 + m] * qz * ir2;
+                const float c2 = rc[kRcC2 + m] * qz * ir2;
                 float p1re = c2 * mre, p1im = c2 * mim, p0re = mre, p0im = mim;
                 tt = (m + 1) * (m + 2) / 2 + m;
                 Jh[2 * tt] = p1re;
                 Jh[2 * tt + 1] = p1im;
                 for (int n = m + 2; n <= P2; n++) {
-                    int u = n * (n + 1) / 2 + m;
-                    float A = rc[kRcA + u] * qz * ir2, B = rc[kRcB + u] * ir2;
-                    float nre = A * p1re - B * p0re, nim = A * p1im - B * p0im;
-                    Jh[2 * u] = nre;
-                    Jh[2 * u + 1] = nim;
+                    const int uu = n * (n + 1) / 2 + m;
+                    const float A = rc[kRcA + uu] * qz * ir2, B = rc[kRcB + uu] * ir2;
+                    const float nre = A * p1re - B * p0re, nim = A * p1im - B * p0im;
+                    Jh[2 * uu] = nre;
+                    Jh[2 * uu + 1] = nim;
                     p0re = p1re;
                     p0im = p1im;
                     p1re = nre;
@@ -274,154 +286,57 @@ __global__ __launch_bounds__(256) void k_m2l_general(const int32_t* __restrict__
                 }
             }
         }
-        __syncthreads();
-        if (jk < njk) {
-            const float* w = W + (size_t)jk * K;
-            float rn = 1.f;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int u = 0; u < 3; u++) {
+            if (oj[u] < 0) continue;
+            const int j = oj[u], k = ok[u];
+            const float* wr = Wp + (size_t)(j * (j + 1) / 2 + k) * K;
+            float rn = 1.f, tre = 0.f, tim = 0.f;
             for (int n = 0; n <= p; n++) {
                 float sre = 0.f, sim = 0.f;
                 for (int m = -n; m <= n; m++) {
-                    cf O = hat(Ms, n, m);
-                    int q = j + n, mk = m - k;
-                    int u = q * (q + 1) / 2 + (mk < 0 ? -mk : mk);
-                    cf Jv = {Jh[2 * u], mk < 0 ? -Jh[2 * u + 1] : Jh[2 * u + 1]};
-                    cf pr = cmul(O, Jv);
-                    float ww = w[n * n + n + m];
-                    sre += ww * pr.re;
-                    sim += ww * pr.im;
+                    const cf O = hat(Ms, n, m);
+                    const int q = j + n, mk = m - k;
+                    const int uu = q * (q + 1) / 2 + (mk < 0 ? -mk : mk);
+                    const float jre = Jh[2 * uu], jim = mk < 0 ? -Jh[2 * uu + 1] : Jh[2 * uu + 1];
+                    const float ww = wr[n * n + n + m];
+                    sre += ww * (O.re * jre - O.im * jim);
+                    sim += ww * (O.re * jim + O.im * jre);
                 }
-                are += rn * sre;
-                aim += rn * sim;
+                tre += rn * sre;
+                tim += rn * sim;
                 rn *= ratio;
             }
+            are[u] += tre;
+            aim[u] += tim;
         }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    if (jk < njk) {
-        int ix = idx_re(j, k);
-        L[(size_t)t * KP + ix] += are;
-        if (k > 0) L[(size_t)t * KP + ix + 1] += aim;
+#pragma unroll
+    for (int u = 0; u < 3; u++) {
+        if (oj[u] < 0) continue;
+        const int jk = lane + 64 * u;
+        red[(w * njk + jk) * 2] = are[u];
+        red[(w * njk + jk) * 2 + 1] = aim[u];
     }
-}
-
-// ---------------------------------------------------------------- far field + final sum
-// One workgroup per target leaf, one lane per target particle: L2P of the
-// leaf's local expansion, M2P of every cell-particle source of the leaf and
-// of its ancestors, plus the particle-particle part computed earlier, summed
-// in FP64 and written in the caller's order.
-__global__ void k_far_final(const float4* __restrict__ pts, const uint32_t* __restrict__ perm, CellArrays c,
-                            const int32_t* __restrict__ leaves, const int32_t* __restrict__ m2p_off,
-                            const uint32_t* __restrict__ m2p_src, int p, int KP, const float* __restrict__ gl2p,
-                            const float* __restrict__ hm2p, const float* __restrict__ rc,
-                            const float* __restrict__ M, const float* __restrict__ L,
-                            const double4* __restrict__ near, int out_dtype, void* __restrict__ ophi,
-                            void* __restrict__ oex, void* __restrict__ oey, void* __restrict__ oez) {
-    extern __shared__ float sh[];
-    const int K = (p + 1) * (p + 1);
-    const int STR = ((p + 2) * (p + 2)) | 1;
-    const int NT = blockDim.x;
-    float* Lt = sh;
-    float* Ms = sh + KP;
-    float* row = sh + 2 * KP + threadIdx.x * STR;
-    const int cell = leaves[blockIdx.x];
-    const int32_t b = c.begin[cell], e = c.end[cell];
-    const double4 ct = c.ctr[cell];
-    for (int i = threadIdx.x; i < K; i += NT) Lt[i] = L[(size_t)cell * KP + i];
     __syncthreads();
-    const float s2 = 1.41421356237309505f;
-    for (int32_t ch = b; ch < e; ch += NT) {
-        const int32_t i = ch + threadIdx.x;
-        const bool valid = i < e;
-        const float4 P = pts[valid ? i : b];
-        double4 acc = valid ? near[i] : make_double4(0, 0, 0, 0);
-        {
-            const double ir = 1.0 / ct.w;
-            float x = (float)(((double)P.x - ct.x) * ir), y = (float)(((double)P.y - ct.y) * ir),
-                  z = (float)(((double)P.z - ct.z) * ir);
-            regular_walk(p, x, y, z, rc, [&](int n, int m, float re, float im) {
-                if (m == 0) row[n * n] = re;
-                else {
-                    row[n * n + 2 * m - 1] = re;
-                    row[n * n + 2 * m] = im;
-                }
-            });
-            float phi = 0.f, l10 = 0.f, l1re = 0.f, l1im = 0.f;
-            for (int n = 0; n <= p; n++)
-                for (int m = -n; m <= n; m++) {
-                    cf Lc = hat(Lt, n, m);
-                    cf Sc = hat(row, n, m);
-                    phi += Lc.re * Sc.re - Lc.im * Sc.im;
-                    if (n >= 1) {
-                        int am = m < 0 ? -m : m;
-                        if (am <= n - 1) {
-                            cf S1 = hat(row, n - 1, m);
-                            l10 += gl2p[n * n + n + m] * (Lc.re * S1.re - Lc.im * S1.im);
-                        }
-                        int m1 = m - 1, am1 = m1 < 0 ? -m1 : m1;
-                        if (am1 <= n - 1) {
-                            cf t = cmul(Lc, hat(row, n - 1, m1));
-                            float g = gl2p[K + n * n + n + m];
-                            l1re += g * t.re;
-                            l1im += g * t.im;
-                        }
-                    }
-                }
-            const double r1 = ct.w, r2 = ct.w * ct.w;
-            acc.x += (double)phi / r1;
-            acc.y += (double)(-s2 * l1re) / r2;
-            acc.z += (double)(s2 * l1im) / r2;
-            acc.w += (double)(-l10) / r2;
+    for (int jk = threadIdx.x; jk < njk; jk += 256) {
+        int j = 0;
+        while ((j + 1) * (j + 2) / 2 <= jk) j++;
+        const int k = jk - j * (j + 1) / 2;
+        float sre = 0.f, sim = 0.f;
+        for (int ww = 0; ww < 4; ww++) {
+            sre += red[(ww * njk + jk) * 2];
+            sim += red[(ww * njk + jk) * 2 + 1];
         }
-        for (int A = cell; A >= 0; A = c.parent[A]) {
-            for (int32_t a = m2p_off[A]; a < m2p_off[A + 1]; a++) {
-                const int s = (int)m2p_src[a];
-                const double4 cs = c.ctr[s];
-                __syncthreads();
-                for (int u = threadIdx.x; u < K; u += NT) Ms[u] = M[(size_t)s * KP + u];
-                __syncthreads();
-                const double ir = 1.0 / cs.w;
-                float x = (float)(((double)P.x - cs.x) * ir), y = (float)(((double)P.y - cs.y) * ir),
-                      z = (float)(((double)P.z - cs.z) * ir);
-                irregular_walk(p + 1, x, y, z, rc, [&](int n, int m, float re, float im) {
-                    if (m == 0) row[n * n] = re;
-                    else {
-                        row[n * n + 2 * m - 1] = re;
-                        row[n * n + 2 * m] = im;
-                    }
-                });
-                float phi = 0.f, l10 = 0.f, l1re = 0.f, l1im = 0.f;
-                for (int n = 0; n <= p; n++)
-                    for (int m = -n; m <= n; m++) {
-                        cf Mc = hat(Ms, n, m);
-                        cf Jc = hat(row, n, m);
-                        phi += Mc.re * Jc.re - Mc.im * Jc.im;
-                        cf J0 = hat(row, n + 1, m);
-                        l10 += hm2p[n * n + n + m] * (Mc.re * J0.re - Mc.im * J0.im);
-                        cf t = cmul(Mc, hat(row, n + 1, m - 1));
-                        float h = hm2p[K + n * n + n + m];
-                        l1re += h * t.re;
-                        l1im += h * t.im;
-                    }
-                const double r1 = cs.w, r2 = cs.w * cs.w;
-                acc.x += (double)phi / r1;
-                acc.y += (double)(-s2 * l1re) / r2;
-                acc.z += (double)(s2 * l1im) / r2;
-                acc.w += (double)(-l10) / r2;
-            }
-        }
-        if (valid) {
-            uint32_t o = perm[i];
-            if (out_dtype == 1) {
-                ((double*)ophi)[o] = acc.x;
-                ((double*)oex)[o] = acc.y;
-                ((double*)oey)[o] = acc.z;
-                ((double*)oez)[o] = acc.w;
-            } else {
-                ((float*)ophi)[o] = (float)acc.x;
-                ((float*)oex)[o] = (float)acc.y;
-                ((float*)oey)[o] = (float)acc.z;
-                ((float*)oez)[o] = (float)acc.w;
-            }
-        }
+        const int ix = idx_re(j, k);
+        L[(size_t)t * KP + ix] += sre;
+        if (k > 0) L[(size_t)t * KP + ix + 1] += sim;
     }
 }
 
@@ -445,24 +360,15 @@ void l2l(CellArrays cells, int32_t c0, int32_t c1, int p, int KP, Tables t, floa
     k_l2l<<<c1 - c0, 128, (size_t)KP * sizeof(float), s>>>(cells, c0, p, KP, t.l2l, L);
 }
 
-void m2l_general(const int32_t* off, const uint32_t* src, const uint32_t* general, CellArrays cells,
-                 int32_t ncell, int p, int KP, Tables t, const float* M, float* L, hipStream_t s) {
+void m2l_general(const int32_t* goff, const uint32_t* gsrc, CellArrays cells, int32_t ncell, int p, int KP,
+                 Tables t, const float* M, float* L, hipStream_t s) {
     if (ncell <= 0) return;
-    int P2 = 2 * p;
-    size_t lds = ((size_t)KP + 2 * (size_t)(P2 + 1) * (P2 + 2) / 2) * sizeof(float);
-    k_m2l_general<<<ncell, 256, lds, s>>>(off, src, general, cells, p, KP, t.wm2l, t.rcoef, M, L);
-}
-
-void far_final(const float4* pts, const uint32_t* perm, CellArrays cells, const int32_t* leaves,
-               int32_t nleaves, const int32_t* m2p_off, const uint32_t* m2p_src, int p, int KP, Tables t,
-               const float* M, const float* L, const double4* near, int out_dtype, void* phi, void* ex,
-               void* ey, void* ez, hipStream_t s) {
-    if (nleaves <= 0) return;
-    int STR = ((p + 2) * (p + 2)) | 1;
-    int NT = (64 * STR + 2 * KP) * 4 <= 60000 ? 64 : 32;
-    size_t lds = ((size_t)2 * KP + (size_t)NT * STR) * sizeof(float);
-    k_far_final<<<nleaves, NT, lds, s>>>(pts, perm, cells, leaves, m2p_off, m2p_src, p, KP, t.gl2p, t.hm2p,
-                                         t.rcoef, M, L, near, out_dtype, phi, ex, ey, ez);
+    const int P2 = 2 * p;
+    const int njk = (p + 1) * (p + 2) / 2, K = (p + 1) * (p + 1);
+    const size_t per = 4 * ((size_t)KP + (size_t)(P2 + 1) * (P2 + 2)) + 8 * (size_t)njk;
+    const int w_lds = ((size_t)njk * K + per) * sizeof(float) <= 65536 ? 1 : 0;
+    const size_t lds = ((w_lds ? (size_t)njk * K : 0) + per) * sizeof(float);
+    k_m2l_general<<<ncell, 256, lds, s>>>(goff, gsrc, cells, p, KP, t.wm2l, w_lds, t.rcoef, M, L);
 }
 
 }  // namespace fmm

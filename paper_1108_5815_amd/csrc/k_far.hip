@@ -1,0 +1,273 @@
+// k_far.hip -- far-field evaluation at the target particles and the final sum.
+//
+// For each target particle of a leaf: L2P of the leaf's local expansion, M2P
+// of every cell-particle source paired with the leaf or one of its ancestors
+// (treecode and hybrid policies, "Results"), plus the particle-particle part,
+// summed in FP64 and written in the caller's particle order.
+//
+// Potential and gradient come from re-centring the expansion at the target
+// point (Greengard & Rokhlin theorems 3.4/3.5): the potential is the degree-0
+// term and the gradient the degree-1 terms, whose weights are tabulated on
+// the host.  The order p is a template parameter, so every loop unrolls and
+// each solid harmonic is consumed by the contraction as soon as the Cartesian
+// recurrence produces it: nothing per particle goes to LDS, only the leaf's
+// local expansion and the current source multipole (read as broadcasts).
+#include "fmm_internal.h"
+
+namespace fmm {
+namespace {
+
+struct cf {
+    float re, im;
+};
+
+// coefficient (n, m), any sign of m, from a real-layout array (conj for m < 0)
+__device__ inline cf hat(const float* row, int n, int m) {
+    if (m == 0) return {row[n * n], 0.f};
+    if (m > 0) return {row[n * n + 2 * m - 1], row[n * n + 2 * m]};
+    return {row[n * n - 2 * m - 1], -row[n * n - 2 * m]};
+}
+
+template <int P, class Fn>
+__device__ inline void regular_walk_t(float x, float y, float z, const float* __restrict__ rc, Fn f) {
+    const float r2 = x * x + y * y + z * z;
+    float mre = 1.f, mim = 0.f;
+#pragma unroll
+    for (int m = 0; m <= P; m++) {
+        if (m > 0) {
+            const float c = rc[kRcC1 + m];
+            const float nre = c * (x * mre - y * mim), nim = c * (x * mim + y * mre);
+            mre = nre;
+            mim = nim;
+        }
+        f(m, m, mre, mim);
+        if (m < P) {
+            const float c2 = rc[kRcC2 + m] * z;
+            float p1re = c2 * mre, p1im = c2 * mim, p0re = mre, p0im = mim;
+            f(m + 1, m, p1re, p1im);
+#pragma unroll
+            for (int n = m + 2; n <= P; n++) {
+                const int t = n * (n + 1) / 2 + m;
+                const float A = rc[kRcA + t] * z, B = rc[kRcB + t] * r2;
+                const float nre = A * p1re - B * p0re, nim = A * p1im - B * p0im;
+                f(n, m, nre, nim);
+                p0re = p1re;
+                p0im = p1im;
+                p1re = nre;
+                p1im = nim;
+            }
+        }
+    }
+}
+
+template <int P, class Fn>
+__device__ inline void irregular_walk_t(float x, float y, float z, const float* __restrict__ rc, Fn f) {
+    const float r2 = x * x + y * y + z * z;
+    const float ir2 = 1.f / r2;
+    float mre = sqrtf(ir2), mim = 0.f;
+#pragma unroll
+    for (int m = 0; m <= P; m++) {
+        if (m > 0) {
+            const float c = rc[kRcC1 + m] * ir2;
+            const float nre = c * (x * mre - y * mim), nim = c * (x * mim + y * mre);
+            mre = nre;
+            mim = nim;
+        }
+        f(m, m, mre, mim);
+        if (m < P) {
+            const float c2 = rc[kRcC2 + m] * z * ir2;
+            float p1re = c2 * mre, p1im = c2 * mim, p0re = mre, p0im = mim;
+            f(m + 1, m, p1re, p1im);
+#pragma unroll
+            for (int n = m + 2; n <= P; n++) {
+                const int t = n * (n + 1) / 2 + m;
+                const float A = rc[kRcA + t] * z * ir2, B = rc[kRcB + t] * ir2;
+                const float nre = A * p1re - B * p0re, nim = A * p1im - B * p0im;
+                f(n, m, nre, nim);
+                p0re = p1re;
+                p0im = p1im;
+                p1re = nre;
+                p1im = nim;
+            }
+        }
+    }
+}
+
+// Local expansion Lt (scaled, real layout) at the point x-hat = (x - c)/r:
+// phi-hat and the degree-1 terms of the expansion re-centred at the point.
+template <int P>
+__device__ inline void l2p_point(const float* Lt, const float* __restrict__ g, float x, float y, float z,
+                                 const float* __restrict__ rc, float& phi, float& l10, float& l1re, float& l1im) {
+    constexpr int K = (P + 1) * (P + 1);
+    regular_walk_t<P>(x, y, z, rc, [&](int a, int b, float sre, float sim) {
+        const cf L = hat(Lt, a, b);
+        phi += (b == 0 ? 1.f : 2.f) * (L.re * sre - L.im * sim);
+        if (a + 1 <= P) {
+            const int n = a + 1;
+            const float G0 = g[n * n + n + b] + (b > 0 ? g[n * n + n - b] : 0.f);
+            const cf Ln = hat(Lt, n, b);
+            l10 += G0 * (Ln.re * sre - Ln.im * sim);
+            const float g1 = g[K + n * n + n + b + 1];
+            const cf L1 = hat(Lt, n, b + 1);
+            l1re += g1 * (L1.re * sre - L1.im * sim);
+            l1im += g1 * (L1.re * sim + L1.im * sre);
+            if (b >= 1) {
+                const float g2 = g[K + n * n + n + 1 - b];
+                const cf L2 = hat(Lt, n, 1 - b);
+                l1re += g2 * (L2.re * sre + L2.im * sim);
+                l1im += g2 * (L2.im * sre - L2.re * sim);
+            }
+        }
+    });
+}
+
+// Multipole Ms (scaled, real layout) at x-hat = (x - c)/r: phi-hat and the
+// degree-1 terms of its conversion into a local expansion at the point.
+template <int P>
+__device__ inline void m2p_point(const float* Ms, const float* __restrict__ h, float x, float y, float z,
+                                 const float* __restrict__ rc, float& phi, float& l10, float& l1re, float& l1im) {
+    constexpr int K = (P + 1) * (P + 1);
+    irregular_walk_t<P + 1>(x, y, z, rc, [&](int a, int b, float jre, float jim) {
+        if (a <= P) {
+            const cf Mc = hat(Ms, a, b);
+            phi += (b == 0 ? 1.f : 2.f) * (Mc.re * jre - Mc.im * jim);
+        }
+        if (a >= 1) {
+            const int n = a - 1;
+            if (b <= n) {
+                const float H0 = h[n * n + n + b] + (b > 0 ? h[n * n + n - b] : 0.f);
+                const cf Mn = hat(Ms, n, b);
+                l10 += H0 * (Mn.re * jre - Mn.im * jim);
+            }
+            if (b + 1 <= n) {
+                const float h1 = h[K + n * n + n + b + 1];
+                const cf M1 = hat(Ms, n, b + 1);
+                l1re += h1 * (M1.re * jre - M1.im * jim);
+                l1im += h1 * (M1.re * jim + M1.im * jre);
+            }
+            if (b >= 1 && b - 1 <= n) {
+                const float h2 = h[K + n * n + n + 1 - b];
+                const cf M2 = hat(Ms, n, 1 - b);
+                l1re += h2 * (M2.re * jre + M2.im * jim);
+                l1im += h2 * (M2.im * jre - M2.re * jim);
+            }
+        }
+    });
+}
+
+template <int P>
+__global__ __launch_bounds__(64) void k_far(const float4* __restrict__ pts, const uint32_t* __restrict__ perm,
+                                            CellArrays c, const int32_t* __restrict__ leaves,
+                                            const int32_t* __restrict__ m2p_off, const uint32_t* __restrict__ m2p_src,
+                                            int KP, const float* __restrict__ gl2p, const float* __restrict__ hm2p,
+                                            const float* __restrict__ rc, const float* __restrict__ M,
+                                            const float* __restrict__ L, const double4* __restrict__ near,
+                                            int out_dtype, void* __restrict__ ophi, void* __restrict__ oex,
+                                            void* __restrict__ oey, void* __restrict__ oez) {
+    constexpr int K = (P + 1) * (P + 1);
+    __shared__ float Lt[K];
+    __shared__ float Ms[K];
+    const int cell = leaves[blockIdx.x];
+    const int32_t b = c.begin[cell], e = c.end[cell];
+    const double4 ct = c.ctr[cell];
+    for (int i = threadIdx.x; i < K; i += 64) Lt[i] = L[(size_t)cell * KP + i];
+    __syncthreads();
+    const float s2 = 1.41421356237309505f;
+    for (int32_t ch = b; ch < e; ch += 64) {
+        const int32_t i = ch + threadIdx.x;
+        const bool valid = i < e;
+        const float4 Pt = pts[valid ? i : b];
+        double4 acc = valid ? near[i] : make_double4(0, 0, 0, 0);
+        {
+            const double ir = 1.0 / ct.w;
+            const float x = (float)(((double)Pt.x - ct.x) * ir), y = (float)(((double)Pt.y - ct.y) * ir),
+                        z = (float)(((double)Pt.z - ct.z) * ir);
+            float phi = 0.f, l10 = 0.f, l1re = 0.f, l1im = 0.f;
+            l2p_point<P>(Lt, gl2p, x, y, z, rc, phi, l10, l1re, l1im);
+            const double r1 = ct.w, r2 = ct.w * ct.w;
+            acc.x += (double)phi / r1;
+            acc.y += (double)(-s2 * l1re) / r2;
+            acc.z += (double)(s2 * l1im) / r2;
+            acc.w += (double)(-l10) / r2;
+        }
+        for (int A = cell; A >= 0; A = c.parent[A]) {
+            for (int32_t a = m2p_off[A]; a < m2p_off[A + 1]; a++) {
+                const int s = (int)m2p_src[a];
+                const double4 cs = c.ctr[s];
+                __syncthreads();
+                for (int u = threadIdx.x; u < K; u += 64) Ms[u] = M[(size_t)s * KP + u];
+                __syncthreads();
+                const double ir = 1.0 / cs.w;
+                const float x = (float)(((double)Pt.x - cs.x) * ir), y = (float)(((double)Pt.y - cs.y) * ir),
+                            z = (float)(((double)Pt.z - cs.z) * ir);
+                float phi = 0.f, l10 = 0.f, l1re = 0.f, l1im = 0.f;
+                m2p_point<P>(Ms, hm2p, x, y, z, rc, phi, l10, l1re, l1im);
+                const double r1 = cs.w, r2 = cs.w * cs.w;
+                acc.x += (double)phi / r1;
+                acc.y += (double)(-s2 * l1re) / r2;
+                acc.z += (double)(s2 * l1im) / r2;
+                acc.w += (double)(-l10) / r2;
+            }
+        }
+        if (valid) {
+            const uint32_t o = perm[i];
+            if (out_dtype == 1) {
+                ((double*)ophi)[o] = acc.x;
+                ((double*)oex)[o] = acc.y;
+                ((double*)oey)[o] = acc.z;
+                ((double*)oez)[o] = acc.w;
+            } else {
+                ((float*)ophi)[o] = (float)acc.x;
+                ((float*)oex)[o] = (float)acc.y;
+                ((float*)oey)[o] = (float)acc.z;
+                ((float*)oez)[o] = (float)acc.w;
+            }
+        }
+    }
+}
+
+template <int P>
+void launch_far(const float4* pts, const uint32_t* perm, CellArrays cells, const int32_t* leaves, int32_t nleaves,
+                const int32_t* m2p_off, const uint32_t* m2p_src, int KP, Tables t, const float* M, const float* L,
+                const double4* near, int out_dtype, void* phi, void* ex, void* ey, void* ez, hipStream_t s) {
+    k_far<P><<<nleaves, 64, 0, s>>>(pts, perm, cells, leaves, m2p_off, m2p_src, KP, t.gl2p, t.hm2p, t.rcoef, M, L,
+                                     near, out_dtype, phi, ex, ey, ez);
+}
+
+}  // namespace
+
+void far_final(const float4* pts, const uint32_t* perm, CellArrays cells, const int32_t* leaves, int32_t nleaves,
+               const int32_t* m2p_off, const uint32_t* m2p_src, int p, int KP, Tables t, const float* M,
+               const float* L, const double4* near, int out_dtype, void* phi, void* ex, void* ey, void* ez,
+               hipStream_t s) {
+    if (nleaves <= 0) return;
+#define FMM_FAR_CASE(PP)                                                                                          \
+    case PP:                                                                                                      \
+        launch_far<PP>(pts, perm, cells, leaves, nleaves, m2p_off, m2p_src, KP, t, M, L, near, out_dtype, phi, ex, \
+                       ey, ez, s);                                                                                \
+        break;
+    switch (p) {
+        FMM_FAR_CASE(0)
+        FMM_FAR_CASE(1)
+        FMM_FAR_CASE(2)
+        FMM_FAR_CASE(3)
+        FMM_FAR_CASE(4)
+        FMM_FAR_CASE(5)
+        FMM_FAR_CASE(6)
+        FMM_FAR_CASE(7)
+        FMM_FAR_CASE(8)
+        FMM_FAR_CASE(9)
+        FMM_FAR_CASE(10)
+        FMM_FAR_CASE(11)
+        FMM_FAR_CASE(12)
+        FMM_FAR_CASE(13)
+        FMM_FAR_CASE(14)
+        FMM_FAR_CASE(15)
+        FMM_FAR_CASE(16)
+        default:
+            break;
+    }
+#undef FMM_FAR_CASE
+}
+
+}  // namespace fmm

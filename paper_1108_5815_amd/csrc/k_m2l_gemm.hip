@@ -12,11 +12,15 @@
 // sources are zero columns.  Each workgroup owns its tile's outputs, so the
 // sum over slots is done in registers, with no atomics, in slot order.
 //
-// Tiling (gfx950, wave64): a 256-lane workgroup computes KP x 64 outputs with
-// v_mfma_f32_32x32x2f32; wave w owns the 32 x 32 blocks w, w+4, ...  Per slot
-// the 64 gathered source vectors are staged in LDS (row stride KP+1, conflict
-// free column reads) and the operator is read from global memory in k-major
-// layout so that each half-wave load is one 128-byte line.
+// Tiling (gfx950, wave64, v_mfma_f32_32x32x2f32): a 256-lane workgroup owns
+// KP x NT outputs split over a RW x CW grid of waves; each wave keeps
+// NRB x NCB 32x32 accumulator blocks.  The K index of step s, half h of the
+// wave, is h*KS + s, so each lane reads its source vector contiguously
+// (float4 LDS reads cover 4 steps).  Operator fragments stream from global
+// memory (k-major, one 128-byte line per half-wave) through a register
+// pipeline one 16-step chunk ahead; the next slot's 64 or 128 gathered source
+// vectors are loaded into registers during the current slot and written to
+// the other half of a double-buffered LDS tile.
 #include "fmm_internal.h"
 
 namespace fmm {
@@ -24,93 +28,154 @@ namespace {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-template <int KP>
+template <int KP, int NT, int RW, int CW>
 __global__ __launch_bounds__(256) void k_m2l_gemm(const float* __restrict__ T, const int32_t* __restrict__ offid,
                                                   const int32_t* __restrict__ gather,
                                                   const uint32_t* __restrict__ rowcell, GemmPlan plan, int K,
                                                   const float* __restrict__ M, float* __restrict__ L) {
-    constexpr int NT = kGemmTile;
-    constexpr int STR = KP + 1;
-    constexpr int RB = KP / 32;
-    constexpr int NBLK = RB * (NT / 32);
-    constexpr int PER = (NBLK + 3) / 4;
-    __shared__ float Bs[NT * STR];
-    __shared__ int32_t srcs[NT];
+    constexpr int KS = KP / 2;
+    constexpr int RB = KP / 32, CB = NT / 32;
+    static_assert(RB % RW == 0 && CB % CW == 0 && RW * CW == 4, "wave grid");
+    constexpr int NRB = RB / RW, NCB = CB / CW;
+    constexpr int STR = KP + 4;
+    constexpr int CH = 16;
+    constexpr int NCH = KS / CH;
+    constexpr int BV = NT * KP / 1024;  // float4 per thread per source tile
+    static_assert(KS % CH == 0 && (NT * KP) % 1024 == 0, "tile shape");
+    __shared__ __attribute__((aligned(16))) float Bs[2][NT * STR];
 
     const int tile = blockIdx.x;
     int cls = 0;
     while (cls < 7 && tile >= plan.class_tile0[cls + 1]) cls++;
     const int r0 = plan.class_row0[cls] + (tile - plan.class_tile0[cls]) * NT;
-    const int r1 = min(r0 + NT, plan.class_row0[cls + 1]);
-    const int nrow = r1 - r0;
+    const int nrow = min(NT, plan.class_row0[cls + 1] - r0);
     const int J = plan.J;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int l32 = lane & 31, khalf = lane >> 5;
+    const int l32 = lane & 31, h = lane >> 5;
+    const int wr = w % RW, wc = w / RW;
+    const int32_t* oid = offid + (size_t)cls * J;
 
-    int rbs[PER], cbs[PER];
-    bool act[PER];
-    floatx16 acc[PER];
+    floatx16 acc[NRB][NCB];
 #pragma unroll
-    for (int i = 0; i < PER; i++) {
-        int b = w + 4 * i;
-        act[i] = b < NBLK;
-        rbs[i] = b % RB;
-        cbs[i] = b / RB;
+    for (int i = 0; i < NRB; i++)
 #pragma unroll
-        for (int r = 0; r < 16; r++) acc[i][r] = 0.f;
-    }
-    const int Ke = (K + 1) & ~1;
-    for (int j = 0; j < J; j++) {
-        if (threadIdx.x < NT)
-            srcs[threadIdx.x] = (int)threadIdx.x < nrow ? gather[(size_t)(r0 + threadIdx.x) * J + j] : -1;
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < NT * (KP / 4); idx += 256) {
+        for (int b = 0; b < NCB; b++)
+#pragma unroll
+            for (int r = 0; r < 16; r++) acc[i][b][r] = 0.f;
+
+    float4 breg[BV];
+    auto load_B = [&](int j) {
+#pragma unroll
+        for (int v = 0; v < BV; v++) {
+            int idx = threadIdx.x + 256 * v;
             int col = idx / (KP / 4), k4 = idx - col * (KP / 4);
-            int s = srcs[col];
-            float4 v = s >= 0 ? reinterpret_cast<const float4*>(M + (size_t)s * KP)[k4] : make_float4(0.f, 0.f, 0.f, 0.f);
-            float* d = Bs + col * STR + 4 * k4;
-            d[0] = v.x;
-            d[1] = v.y;
-            d[2] = v.z;
-            d[3] = v.w;
+            int s = col < nrow ? gather[(size_t)(r0 + col) * J + j] : -1;
+            breg[v] = s >= 0 ? reinterpret_cast<const float4*>(M + (size_t)s * KP)[k4]
+                             : make_float4(0.f, 0.f, 0.f, 0.f);
         }
-        __syncthreads();
-        const float* A = T + (size_t)offid[cls * J + j] * KP * KP;
-        for (int k0 = 0; k0 < Ke; k0 += 2) {
-            const int kk = k0 + khalf;
+    };
+    auto store_B = [&](int buf) {
 #pragma unroll
-            for (int i = 0; i < PER; i++) {
-                if (!act[i]) continue;
-                float a = A[(size_t)kk * KP + rbs[i] * 32 + l32];
-                float bv = Bs[(cbs[i] * 32 + l32) * STR + kk];
-                acc[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bv, acc[i], 0, 0, 0);
+        for (int v = 0; v < BV; v++) {
+            int idx = threadIdx.x + 256 * v;
+            int col = idx / (KP / 4), k4 = idx - col * (KP / 4);
+            *reinterpret_cast<float4*>(&Bs[buf][col * STR + 4 * k4]) = breg[v];
+        }
+    };
+    float a0[NRB][CH], a1[NRB][CH];
+    auto load_A = [&](const float* A, int c, float (&a)[NRB][CH]) {
+#pragma unroll
+        for (int i = 0; i < NRB; i++)
+#pragma unroll
+            for (int t = 0; t < CH; t++)
+                a[i][t] = A[(size_t)(h * KS + c * CH + t) * KP + (wr + RW * i) * 32 + l32];
+    };
+    auto compute = [&](int buf, int c, const float (&a)[NRB][CH]) {
+#pragma unroll
+        for (int t = 0; t < CH; t += 4) {
+            float4 b4[NCB];
+#pragma unroll
+            for (int b = 0; b < NCB; b++) {
+                int col = (wc + CW * b) * 32 + l32;
+                b4[b] = *reinterpret_cast<const float4*>(&Bs[buf][col * STR + h * KS + c * CH + t]);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++)
+#pragma unroll
+                for (int b = 0; b < NCB; b++) {
+                    float bv = u == 0 ? b4[b].x : u == 1 ? b4[b].y : u == 2 ? b4[b].z : b4[b].w;
+#pragma unroll
+                    for (int i = 0; i < NRB; i++)
+                        acc[i][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][t + u], bv, acc[i][b], 0, 0, 0);
+                }
+        }
+    };
+
+    load_B(0);
+    store_B(0);
+    load_A(T + (size_t)oid[0] * KP * KP, 0, a0);
+    __syncthreads();
+    for (int j = 0; j < J; j++) {
+        const int buf = j & 1;
+        const bool more = j + 1 < J;
+        if (more) load_B(j + 1);
+        const float* Aj = T + (size_t)oid[j] * KP * KP;
+        const float* An = T + (size_t)oid[more ? j + 1 : j] * KP * KP;
+        // chunk pipeline: chunk c computes from the register set loaded one chunk earlier
+#pragma unroll
+        for (int c = 0; c < NCH; c++) {
+            if ((c & 1) == 0) {
+                if (c + 1 < NCH) load_A(Aj, c + 1, a1);
+                else load_A(An, 0, a1);
+                compute(buf, c, a0);
+            } else {
+                if (c + 1 < NCH) load_A(Aj, c + 1, a0);
+                else load_A(An, 0, a0);
+                compute(buf, c, a1);
             }
         }
+        if (NCH & 1) {
+#pragma unroll
+            for (int i = 0; i < NRB; i++)
+#pragma unroll
+                for (int t = 0; t < CH; t++) a0[i][t] = a1[i][t];
+        }
+        if (more) store_B(buf ^ 1);
         __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i < PER; i++) {
-        if (!act[i]) continue;
-        int col = cbs[i] * 32 + l32;
+    for (int b = 0; b < NCB; b++) {
+        int col = (wc + CW * b) * 32 + l32;
         if (col >= nrow) continue;
         size_t base = (size_t)rowcell[r0 + col] * KP;
 #pragma unroll
-        for (int r = 0; r < 16; r++) {
-            int row = rbs[i] * 32 + 8 * (r >> 2) + 4 * khalf + (r & 3);
-            if (row < K) L[base + row] = acc[i][r];
-        }
+        for (int i = 0; i < NRB; i++)
+#pragma unroll
+            for (int r = 0; r < 16; r++) {
+                int row = (wr + RW * i) * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+                if (row < K) L[base + row] = acc[i][b][r];
+            }
     }
 }
 
-template <int KP>
+template <int KP, int NT, int RW, int CW>
 void launch(const float* T, const int32_t* offid, const int32_t* gather, const uint32_t* rowcell, GemmPlan plan,
             int K, const float* M, float* L, int ntiles, hipStream_t s) {
-    k_m2l_gemm<KP><<<ntiles, 256, 0, s>>>(T, offid, gather, rowcell, plan, K, M, L);
+    k_m2l_gemm<KP, NT, RW, CW><<<ntiles, 256, 0, s>>>(T, offid, gather, rowcell, plan, K, M, L);
 }
 
 }  // namespace
 
-bool m2l_gemm_supported(int p) { return kpad(p) <= 224; }
+bool m2l_gemm_supported(int p) { return gemm_tile_cols(p) > 0; }
+
+// targets per tile for the storage width of order p (0 = no GEMM path)
+int gemm_tile_cols(int p) {
+    switch (kpad(p)) {
+        case 32: case 64: case 96: return 128;
+        case 128: case 192: case 256: return 64;
+        default: return 0;
+    }
+}
 
 void m2l_gemm(const float* T, const int32_t* offid, const int32_t* gather, const uint32_t* rowcell, GemmPlan plan,
               int p, int KP, const float* M, float* L, int ntiles, int precision, hipStream_t s) {
@@ -118,13 +183,12 @@ void m2l_gemm(const float* T, const int32_t* offid, const int32_t* gather, const
     if (ntiles <= 0) return;
     int K = ncoef(p);
     switch (KP) {
-        case 32: launch<32>(T, offid, gather, rowcell, plan, K, M, L, ntiles, s); break;
-        case 64: launch<64>(T, offid, gather, rowcell, plan, K, M, L, ntiles, s); break;
-        case 96: launch<96>(T, offid, gather, rowcell, plan, K, M, L, ntiles, s); break;
-        case 128: launch<128>(T, offid, gather, rowcell, plan, K, M, L, ntiles, s); break;
-        case 160: launch<160>(T, offid, gather, rowcell, plan, K, M, L, ntiles, s); break;
-        case 192: launch<192>(T, offid, gather, rowcell, plan, K, M, L, ntiles, s); break;
-        case 224: launch<224>(T, offid, gather, rowcell, plan, K, M, L, ntiles, s); break;
+        case 32: launch<32, 128, 1, 4>(T, offid, gather, rowcell, plan, K, M, L, ntiles, s); break;
+        case 64: launch<64, 128, 2, 2>(T, offid, gather, rowcell, plan, K, M, L, ntiles, s); break;
+        case 96: launch<96, 128, 1, 4>(T, offid, gather, rowcell, plan, K, M, L, ntiles, s); break;
+        case 128: launch<128, 64, 4, 1>(T, offid, gather, rowcell, plan, K, M, L, ntiles, s); break;
+        case 192: launch<192, 64, 2, 2>(T, offid, gather, rowcell, plan, K, M, L, ntiles, s); break;
+        case 256: launch<256, 64, 4, 1>(T, offid, gather, rowcell, plan, K, M, L, ntiles, s); break;
         default: break;
     }
 }

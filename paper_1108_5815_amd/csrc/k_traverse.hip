@@ -302,3 +302,25 @@ void leaf_write(CellArrays cells, int32_t ncell, const uint32_t* pos, int32_t* l
 }
 
 }  // namespace fmm
+
+namespace fmm {
+namespace {
+
+__global__ void k_compact_pairs(const uint32_t* __restrict__ tgt, const uint32_t* __restrict__ src,
+                                const uint32_t* __restrict__ flag, const uint32_t* __restrict__ pos, int64_t n,
+                                uint32_t* __restrict__ otgt, uint32_t* __restrict__ osrc) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !flag[i]) return;
+    otgt[pos[i]] = tgt[i];
+    osrc[pos[i]] = src[i];
+}
+
+}  // namespace
+
+void compact_pairs(const uint32_t* tgt, const uint32_t* src, const uint32_t* flag, const uint32_t* pos, int64_t n,
+                   uint32_t* otgt, uint32_t* osrc, hipStream_t s) {
+    if (n <= 0) return;
+    k_compact_pairs<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(tgt, src, flag, pos, n, otgt, osrc);
+}
+
+}  // namespace fmm

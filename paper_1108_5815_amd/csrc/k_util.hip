@@ -322,3 +322,34 @@ void iota_u32(uint32_t* p, int64_t n, hipStream_t s) {
 }
 
 }  // namespace fmm
+
+namespace fmm {
+namespace {
+
+__device__ inline uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Artificial coordinates (uniform in the unit cube) and charges (+-1) for the
+// kernel pre-calculation: a SplitMix64 finaliser of (seed, index, component).
+__global__ void k_artificial(int64_t n, uint64_t seed, float* __restrict__ x, float* __restrict__ y,
+                             float* __restrict__ z, float* __restrict__ q) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint64_t b = seed * 0x9E3779B97F4A7C15ull + (uint64_t)i * 4;
+    x[i] = (float)(mix64(b + 1) >> 40) * (1.0f / 16777216.0f);
+    y[i] = (float)(mix64(b + 2) >> 40) * (1.0f / 16777216.0f);
+    z[i] = (float)(mix64(b + 3) >> 40) * (1.0f / 16777216.0f);
+    q[i] = (mix64(b + 4) >> 63) ? 1.f : -1.f;
+}
+
+}  // namespace
+
+void artificial_points(int64_t n, uint64_t seed, float* x, float* y, float* z, float* q, hipStream_t s) {
+    if (n <= 0) return;
+    k_artificial<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, seed, x, y, z, q);
+}
+
+}  // namespace fmm
