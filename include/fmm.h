@@ -147,6 +147,56 @@ fmm_status fmm_get_costs(fmm_ctx ctx, double *costs3_host);
  */
 fmm_status fmm_tune(fmm_ctx ctx, int32_t p, int32_t precision);
 
+/* ---------------- learned cost model (FMM_POLICY_HYBRID_MLP) ----------------
+ * A 6 -> 64 -> 64 -> 3 ReLU perceptron (FP32, FMM_MLP_PARAMS weights laid out
+ * W1[64][6], b1[64], W2[64][64], b2[64], W3[3][64], b3[3]) predicts log2 of
+ * the time in ns that an accepted cell pair costs as M2L, M2P or P2P; the
+ * traversal picks the least.  Pair features: log2(r_t/r_s)/2, log2(n_t)/8,
+ * log2(n_s)/8, p/10, ((r_t+r_s)/R)/theta, theta.  This replaces the fixed
+ * unit costs of the kernel pre-calculation ("Kernel pre-calculation"), which
+ * on GPUs mispredict because kernel time is not proportional to problem size
+ * ("Results").  The network is evaluated once per (p, theta, weights) over a
+ * quantised feature grid (level difference in [-4, 4], log2 counts in
+ * quarter steps, 4 bins of the distance ratio) that the traversal reads. */
+#define FMM_MLP_PARAMS 4803
+
+/* Generate timing records with the library's own kernels on artificial
+ * clustered particle sets (homogeneous leaves of 2..256 particles; a
+ * two-level set for mixed-level M2L), then train on the GPU with the
+ * library's forward/backward/Adam kernels (full batch, `epochs` steps,
+ * learning rate 3e-3, weights initialised from `seed`).  Enables
+ * FMM_POLICY_HYBRID_MLP.  *final_loss (may be NULL) receives the mean squared
+ * error of the log2 times.  Needs no tree; leaves the context's tree intact. */
+fmm_status fmm_costmodel_train(fmm_ctx ctx, int32_t p, double theta, int32_t epochs, uint64_t seed,
+                               double *final_loss);
+
+/* Train on caller-given records (host arrays): features[n_rec][6],
+ * kinds[n_rec] in {0 M2L, 1 M2P, 2 P2P}, targets[n_rec] = log2 ns. */
+fmm_status fmm_costmodel_fit(fmm_ctx ctx, int32_t n_rec, const float *features, const int32_t *kinds,
+                             const float *targets, int32_t epochs, double lr, uint64_t seed,
+                             double *final_loss);
+
+/* The records of the last fmm_costmodel_train (host arrays of cap entries;
+ * *count receives the number available). */
+fmm_status fmm_costmodel_records(fmm_ctx ctx, int32_t cap, int32_t *count, float *features, int32_t *kinds,
+                                 float *targets);
+
+/* Weights in and out (host arrays of FMM_MLP_PARAMS floats). */
+fmm_status fmm_costmodel_get_weights(fmm_ctx ctx, float *weights);
+fmm_status fmm_costmodel_set_weights(fmm_ctx ctx, const float *weights);
+
+/* One evaluation of the training kernels: mean squared error (*loss) of
+ * log2 times and its gradient (grad[FMM_MLP_PARAMS]) for the given weights
+ * and records (all host arrays). */
+fmm_status fmm_costmodel_loss_grad(fmm_ctx ctx, const float *weights, int32_t n_rec, const float *features,
+                                   const int32_t *kinds, const float *targets, float *loss, float *grad);
+
+/* The choice table the traversal reads for (p, theta): 9 x 81 x 81 x 4
+ * entries (level difference + 4, quarter-octave bucket of n_t, of n_s,
+ * distance-ratio bin), each 0 M2L, 1 M2P or 2 P2P; host array. */
+#define FMM_MLP_TABLE (9 * 81 * 81 * 4)
+fmm_status fmm_costmodel_table(fmm_ctx ctx, int32_t p, double theta, uint8_t *table);
+
 /* ---------------- introspection (host outputs, for checking) ---------------- */
 
 /* Counts after the last build/traverse.  Any pointer may be NULL. */

@@ -20,6 +20,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "fmm_oracle.c")
+_SRC_MLP = os.path.join(_HERE, "mlp_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 M2L, M2P, P2P = 0, 1, 2
@@ -28,10 +29,11 @@ POLICY_FMM, POLICY_TREECODE, POLICY_HYBRID = 0, 1, 2
 
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (plain C99, OpenMP, no FMA contraction)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    stale = not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(s) for s in (_SRC, _SRC_MLP))
+    if force or stale:
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=gnu99", "-fopenmp", "-ffp-contract=off",
-                               "-fcx-limited-range", "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"])
+                               "-fcx-limited-range", "-fPIC", "-shared", _SRC, _SRC_MLP, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -78,6 +80,11 @@ def lib():
         L.ora_bbox.argtypes = [I64, vp, vp, vp, vp, vp]
         L.ora_morton.argtypes = [I64, vp, vp, vp, vp, ctypes.c_double, vp]
         L.ora_num_threads.restype = ctypes.c_int
+        L.ora_traverse_table.argtypes = [vp, ctypes.c_double, vp]
+        L.ora_mlp_forward.argtypes = [vp, vp, vp]
+        L.ora_mlp_loss_grad.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp, vp]
+        L.ora_mlp_forward_f32.argtypes = [vp, vp, vp]
+        L.ora_mlp_table.argtypes = [vp, ctypes.c_int, ctypes.c_float, vp, vp]
         L.ora_interleave.restype = ctypes.c_uint64
         L.ora_interleave.argtypes = [ctypes.c_uint64] * 3
         _lib = L
@@ -261,6 +268,11 @@ class Tree:
         cst = _f64(costs)
         lib().ora_traverse(self.h, float(theta), int(policy), _p(cst))
 
+    def traverse_table(self, theta: float, table):
+        """Traversal whose accepted pairs take the kind given by a cost-model choice table."""
+        self._table = np.ascontiguousarray(table, np.uint8).ravel()
+        lib().ora_traverse_table(self.h, float(theta), _p(self._table))
+
     def lists(self) -> dict:
         out = {}
         for k in (M2L, M2P, P2P):
@@ -300,3 +312,43 @@ def rel_l2(a, b) -> float:
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
     return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+# ---------------------------------------------------------------- learned cost model
+MLP_PARAMS = 4803
+
+
+def mlp_forward(w, f):
+    w = _f64(w)
+    f = _f64(f)
+    y = np.zeros(3)
+    lib().ora_mlp_forward(_p(w), _p(f), _p(y))
+    return y
+
+
+def mlp_loss_grad(w, feat, kind, tgt):
+    w = _f64(w)
+    feat = _f64(feat)
+    kind = np.ascontiguousarray(kind, np.int32)
+    tgt = _f64(tgt)
+    loss = np.zeros(1)
+    g = np.zeros(MLP_PARAMS)
+    lib().ora_mlp_loss_grad(_p(w), kind.size, _p(feat), _p(kind), _p(tgt), _p(loss), _p(g))
+    return float(loss[0]), g
+
+
+def mlp_forward_f32(w, f):
+    w = np.ascontiguousarray(w, np.float32)
+    f = np.ascontiguousarray(f, np.float32)
+    y = np.zeros(3, np.float32)
+    lib().ora_mlp_forward_f32(_p(w), _p(f), _p(y))
+    return y
+
+
+def mlp_table(w, p, theta):
+    """(choices[9,81,81,4] uint8, margin[9,81,81,4] float32) in FP32."""
+    w = np.ascontiguousarray(w, np.float32)
+    tab = np.zeros(9 * 81 * 81 * 4, np.uint8)
+    mar = np.zeros(9 * 81 * 81 * 4, np.float32)
+    lib().ora_mlp_table(_p(w), int(p), float(theta), _p(tab), _p(mar))
+    return tab.reshape(9, 81, 81, 4), mar.reshape(9, 81, 81, 4)

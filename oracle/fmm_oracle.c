@@ -377,10 +377,39 @@ static int classify(const ora_t *h, int32_t t, int32_t s, double theta2)
  * (P2P) for an accepted pair.  The hybrid compares modelled times made of
  * unit costs: c_m2l, c_m2p * n_t, (c_p2p * n_t) * n_s; the smallest wins and
  * ties go to the earlier of M2L, M2P, P2P. */
+/* Learned choice (policy 3): the kind the cost model picks for the pair's
+ * quantised features, read from a choice table of 9 x 81 x 81 x 4 entries:
+ * level difference l_s - l_t clamped to [-4, 4]; round(4 log2 n) clamped to
+ * [0, 80] for n_t and n_s; floor(4 ((r_t + r_s)/R)/theta) clamped to [0, 3]. */
+static const uint8_t *g_table = 0;
+static double g_theta = 0;
+
+static int table_choice(const ora_t *h, int32_t t, int32_t s)
+{
+    int dl = h->level[s] - h->level[t];
+    dl = dl < -4 ? -4 : (dl > 4 ? 4 : dl);
+    double nt = (double)(h->end[t] - h->begin[t]);
+    double ns = (double)(h->end[s] - h->begin[s]);
+    int bt = (int)rint(4.0 * log2(nt)), bs = (int)rint(4.0 * log2(ns));
+    bt = bt < 0 ? 0 : (bt > 80 ? 80 : bt);
+    bs = bs < 0 ? 0 : (bs > 80 ? 80 : bs);
+    int64_t R2 = 0;
+    for (int d = 0; d < 3; d++) {
+        int64_t dd = h->ch[3 * t + d] - h->ch[3 * s + d];
+        R2 += dd * dd;
+    }
+    int64_t rr = h->rh[t] + h->rh[s];
+    double ratio = sqrt((double)(rr * rr) / (double)R2) / g_theta;
+    int bq = (int)(ratio * 4);
+    bq = bq < 0 ? 0 : (bq > 3 ? 3 : bq);
+    return g_table[(((dl + 4) * 81 + bt) * 81 + bs) * 4 + bq];
+}
+
 static int choose(const ora_t *h, int32_t t, int32_t s, int policy, const double *costs)
 {
     if (policy == POL_FMM) return K_M2L;
     if (policy == POL_TREECODE) return K_M2P;
+    if (policy == 3) return table_choice(h, t, s);
     double nt = (double)(h->end[t] - h->begin[t]);
     double ns = (double)(h->end[s] - h->begin[s]);
     double c0 = costs[0];
@@ -817,4 +846,14 @@ void ora_free(void *hv)
     for (int k = 0; k < 3; k++) free(h->list[k].v);
     free(h->M); free(h->L);
     free(h);
+}
+
+/* Traversal with the learned choice read from `table` (see table_choice). */
+void ora_traverse_table(void *hv, double theta, const uint8_t *table)
+{
+    double none[3] = {0, 0, 0};
+    g_table = table;
+    g_theta = theta;
+    ora_traverse(hv, theta, 3, none);
+    g_table = 0;
 }

@@ -17,6 +17,8 @@ POLICY_FMM, POLICY_TREECODE, POLICY_HYBRID_TIMED, POLICY_HYBRID_MLP = 0, 1, 2, 3
 PREC_FP32, PREC_SPLIT_BF16, PREC_FP64 = 0, 1, 2
 F32, F64 = 0, 1
 LIST_M2L, LIST_M2P, LIST_P2P = 0, 1, 2
+MLP_PARAMS = 4803
+MLP_TABLE = 9 * 81 * 81 * 4
 
 _STATUS = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "DEVICE", 4: "STATE", 5: "UNSUPPORTED"}
 
@@ -54,6 +56,13 @@ def lib():
         "fmm_get_costs": ([vp, vp], ctypes.c_int),
         "fmm_tune": ([vp, i32, i32], ctypes.c_int),
         "fmm_get_sizes": ([vp, vp, vp, vp, vp], ctypes.c_int),
+        "fmm_costmodel_train": ([vp, i32, dbl, i32, ctypes.c_uint64, vp], ctypes.c_int),
+        "fmm_costmodel_fit": ([vp, i32, vp, vp, vp, i32, dbl, ctypes.c_uint64, vp], ctypes.c_int),
+        "fmm_costmodel_records": ([vp, i32, vp, vp, vp, vp], ctypes.c_int),
+        "fmm_costmodel_get_weights": ([vp, vp], ctypes.c_int),
+        "fmm_costmodel_set_weights": ([vp, vp], ctypes.c_int),
+        "fmm_costmodel_loss_grad": ([vp, vp, i32, vp, vp, vp, vp, vp], ctypes.c_int),
+        "fmm_costmodel_table": ([vp, i32, dbl, vp], ctypes.c_int),
         "fmm_get_bbox": ([vp, vp, vp], ctypes.c_int),
         "fmm_get_m2l_split": ([vp, vp, vp], ctypes.c_int),
         "fmm_get_keys": ([vp, vp, vp], ctypes.c_int),
@@ -149,6 +158,58 @@ class FMM:
 
     def tune(self, p: int, precision: int = PREC_FP32):
         self._ck(lib().fmm_tune(self.h, int(p), int(precision)))
+
+    # ------------------------------------------------------------ learned cost model
+    def costmodel_train(self, p: int, theta: float, epochs: int = 4000, seed: int = 1) -> float:
+        loss = ctypes.c_double()
+        self._ck(lib().fmm_costmodel_train(self.h, int(p), float(theta), int(epochs), int(seed),
+                                           ctypes.byref(loss)))
+        return loss.value
+
+    def costmodel_fit(self, features, kinds, targets, epochs=2000, lr=3e-3, seed=1) -> float:
+        f = np.ascontiguousarray(features, np.float32)
+        k = np.ascontiguousarray(kinds, np.int32)
+        t = np.ascontiguousarray(targets, np.float32)
+        loss = ctypes.c_double()
+        self._ck(lib().fmm_costmodel_fit(self.h, k.size, _ptr(f), _ptr(k), _ptr(t), int(epochs), float(lr),
+                                         int(seed), ctypes.byref(loss)))
+        return loss.value
+
+    def costmodel_records(self):
+        cnt = ctypes.c_int32()
+        self._ck(lib().fmm_costmodel_records(self.h, 0, ctypes.byref(cnt), None, None, None))
+        m = cnt.value
+        f = np.zeros((m, 6), np.float32)
+        k = np.zeros(m, np.int32)
+        t = np.zeros(m, np.float32)
+        self._ck(lib().fmm_costmodel_records(self.h, m, ctypes.byref(cnt), _ptr(f), _ptr(k), _ptr(t)))
+        return f, k, t
+
+    def costmodel_weights(self):
+        w = np.zeros(MLP_PARAMS, np.float32)
+        self._ck(lib().fmm_costmodel_get_weights(self.h, _ptr(w)))
+        return w
+
+    def costmodel_set_weights(self, w):
+        w = np.ascontiguousarray(w, np.float32)
+        assert w.size == MLP_PARAMS
+        self._ck(lib().fmm_costmodel_set_weights(self.h, _ptr(w)))
+
+    def costmodel_loss_grad(self, w, features, kinds, targets):
+        w = np.ascontiguousarray(w, np.float32)
+        f = np.ascontiguousarray(features, np.float32)
+        k = np.ascontiguousarray(kinds, np.int32)
+        t = np.ascontiguousarray(targets, np.float32)
+        loss = np.zeros(1, np.float32)
+        g = np.zeros(MLP_PARAMS, np.float32)
+        self._ck(lib().fmm_costmodel_loss_grad(self.h, _ptr(w), k.size, _ptr(f), _ptr(k), _ptr(t), _ptr(loss),
+                                               _ptr(g)))
+        return float(loss[0]), g
+
+    def costmodel_table(self, p: int, theta: float):
+        tab = np.zeros(MLP_TABLE, np.uint8)
+        self._ck(lib().fmm_costmodel_table(self.h, int(p), float(theta), _ptr(tab)))
+        return tab.reshape(9, 81, 81, 4)
 
     def set_timing(self, on: bool):
         self._ck(lib().fmm_set_timing(self.h, 1 if on else 0))

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libfmm.so")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 
-SOURCES = ["k_util.hip", "k_tree.hip", "k_traverse.hip", "k_expand.hip", "k_far.hip", "k_p2p.hip",
+SOURCES = ["k_util.hip", "k_tree.hip", "k_traverse.hip", "k_expand.hip", "k_far.hip", "k_p2p.hip", "k_mlp.hip",
            "k_m2l_gemm.hip", "host_ops.cpp", "capi.cpp"]
 
 ARCH = os.environ.get("FMM_OFFLOAD_ARCH", "gfx950")

@@ -84,9 +84,13 @@ struct fmm_ctx_s {
     HostTables ht;
     Buf d_m2m, d_l2l, d_w, d_g, d_h, d_rc;
 
-    // learned cost model weights (device)
-    Buf d_mlp;
+    // learned cost model: weights, Adam moments, training records, choice table
+    Buf d_mlp, d_mlp_m, d_mlp_v, d_grad, d_grad_rec, d_loss_rec, d_feat, d_kind, d_tgt, d_table;
     bool mlp_ready = false;
+    int mlp_version = 0, table_version = -1, table_p = -1;
+    double table_theta = -1;
+    std::vector<float> rec_feat, rec_tgt;
+    std::vector<int32_t> rec_kind;
 
     // expansions and near-field partials
     Buf M, L, nearb;
@@ -103,7 +107,8 @@ struct fmm_ctx_s {
                       &cnt, &off4, &raw[0], &raw[1], &raw[2], &tgt[0], &tgt[1], &tgt[2], &src[0], &src[1],
                       &src[2], &off[0], &off[1], &off[2], &tgt2, &src2, &d_slot, &d_offid, &d_T, &has_fast,
                       &rkey, &rval, &rkey2, &rval2, &rowof, &gather, &general, &gtg, &gsr, &goff, &d_m2m, &d_l2l, &d_w, &d_g,
-                      &d_h, &d_rc, &d_mlp, &M, &L, &nearb, &tune_pts, &tune_out};
+                      &d_h, &d_rc, &d_mlp, &M, &L, &nearb, &tune_pts, &tune_out, &d_mlp_m, &d_mlp_v,
+                      &d_grad, &d_grad_rec, &d_loss_rec, &d_feat, &d_kind, &d_tgt, &d_table};
         for (Buf* b : all) bufs.push_back(b);
     }
 };
@@ -417,11 +422,22 @@ void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
     }
     TravParams tp;
     tp.theta2 = theta * theta;
+    tp.theta = theta;
     tp.policy = policy;
     tp.c_m2l = c->costs[0];
-    tp.c_m2p = c->costs[1];
     tp.c_p2p = c->costs[2];
-    tp.mlp = policy == FMM_POLICY_HYBRID_MLP ? (const float*)c->d_mlp.p : nullptr;
+    tp.c_m2p = c->costs[1];
+    tp.mlp_table = nullptr;
+    if (policy == FMM_POLICY_HYBRID_MLP) {
+        if (c->table_p != p || c->table_theta != theta || c->table_version != c->mlp_version) {
+            mlp_table((const float*)c->d_mlp.p, p, (float)theta, need<uint8_t>(c, c->d_table, kMlpTable), s);
+            check_launch("cost model table");
+            c->table_p = p;
+            c->table_theta = theta;
+            c->table_version = c->mlp_version;
+        }
+        tp.mlp_table = (const uint8_t*)c->d_table.p;
+    }
     CellArrays ca = cells_of(c);
     void* ws = c->ws.p;
     double* d6 = (double*)c->small.p;
@@ -775,6 +791,261 @@ fmm_status fmm_tune(fmm_ctx c, int32_t p, int32_t precision) {
         c->costs[1] = c_m2p;
         c->costs[2] = c_p2p;
         c->costs_set = true;
+    });
+}
+
+// ---------------------------------------------------------------- learned cost model
+static void mlp_features(float* f, int dl, double nt, double ns, int p, double theta) {
+    f[0] = (float)dl / 2.f;
+    f[1] = (float)(std::log2(nt) / 8.0);
+    f[2] = (float)(std::log2(ns) / 8.0);
+    f[3] = (float)p / 10.f;
+    f[4] = 0.875f;  // pairs near the acceptance boundary: the last bin of the table
+    f[5] = (float)theta;
+}
+
+// Timing records generated by the method itself: clustered artificial
+// particle sets whose leaves all hold `per` particles give homogeneous pair
+// batches; the FMM policy times same-level M2L (GEMM) and P2P per cell pair,
+// the treecode policy M2P per cell pair, and a set whose lower half is one
+// level deeper times the mixed-level M2L pairs of its interface.
+static void gen_records(fmm_ctx c, int p, double theta, uint64_t seed) {
+    c->rec_feat.clear();
+    c->rec_kind.clear();
+    c->rec_tgt.clear();
+    fmm_ctx t = nullptr;
+    fmm_status st = fmm_create(&t, c->device, c->stream);
+    if (st != FMM_OK) fail(st, "calibration context");
+    struct Del {
+        fmm_ctx t;
+        ~Del() { fmm_destroy(t); }
+    } del{t};
+    t->timing = true;
+    // measured log2 ns per cell pair, per leaf size: same-level M2L, mixed-level
+    // M2L, M2P, P2P (NaN = not measured)
+    const int pers[] = {2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096};
+    const int NS = (int)(sizeof(pers) / sizeof(pers[0]));
+    std::vector<double> Tm2l(NS, NAN), Tgen(NS, NAN), Tm2p(NS, NAN), Tp2p(NS, NAN);
+    auto lg = [](double ms, int64_t units) { return units > 0 && ms > 0 ? std::log2(ms * 1e6 / (double)units) : NAN; };
+    auto timed = [&](int policy, double* tm) {
+        traverse_impl(t, p, theta, policy);
+        float* out = need<float>(c, c->tune_out, (size_t)4 * t->n);
+        for (int k = 0; k < PH_N; k++) tm[k] = 0;
+        for (int rep = 0; rep < 3; rep++) {
+            evaluate_impl(t, FMM_PREC_FP32, FMM_F32, out, out + t->n, out + 2 * t->n, out + 3 * t->n);
+            if (rep > 0)
+                for (int k = 0; k < PH_N; k++) tm[k] += t->ms[k] / 2;
+        }
+    };
+    for (int si = 0; si < NS; si++) {
+        const int per = pers[si];
+        int L = 7;
+        while (L > 1 && ((int64_t)1 << (3 * L)) * per > ((int64_t)1 << 20)) L--;
+        int64_t n = clustered_points(L, per, per, seed, nullptr, nullptr, nullptr, nullptr, c->stream);
+        float* pts = need<float>(c, c->tune_pts, (size_t)4 * n);
+        clustered_points(L, per, per, seed, pts, pts + n, pts + 2 * n, pts + 3 * n, c->stream);
+        check_launch("clustered points");
+        build_tree_impl(t, n, FMM_F32, pts, pts + n, pts + 2 * n, pts + 3 * n, per);
+        double tf[PH_N], tt[PH_N];
+        timed(FMM_POLICY_FMM, tf);
+        Tm2l[si] = lg(tf[PH_M2L], t->nlist[0] - t->ngeneral);
+        Tp2p[si] = lg(tf[PH_P2P], t->nlist[2]);
+        timed(FMM_POLICY_TREECODE, tt);
+        Tm2p[si] = lg(tt[PH_FAR] - tf[PH_FAR], t->nlist[1]);
+        // mixed levels: the lower half one level deeper
+        int L2 = L;
+        while (L2 > 1 && ((int64_t)1 << (3 * L2 - 1)) * 9 * per > ((int64_t)1 << 21)) L2--;
+        int64_t n2 = clustered_points(L2, per, 8 * per, seed + 1, nullptr, nullptr, nullptr, nullptr, c->stream);
+        pts = need<float>(c, c->tune_pts, (size_t)4 * n2);
+        clustered_points(L2, per, 8 * per, seed + 1, pts, pts + n2, pts + 2 * n2, pts + 3 * n2, c->stream);
+        check_launch("clustered points");
+        build_tree_impl(t, n2, FMM_F32, pts, pts + n2, pts + 2 * n2, pts + 3 * n2, per);
+        timed(FMM_POLICY_FMM, tf);
+        Tgen[si] = lg(tf[PH_M2LG], t->ngeneral);
+    }
+    // Records.  Measured directly: the diagonal (n_t = n_s, equal levels; mixed
+    // levels for M2L).  The rest follow from how the kernels' work scales,
+    // stated here as the model's invariances: no kernel's cost depends on the
+    // distance ratio; M2L's does not depend on the particle counts and M2P's
+    // not on n_s; P2P's log cost is additive in log n_t and log n_s, so an
+    // off-diagonal pair gets the mean of the two diagonal log costs; only M2L
+    // depends on the level difference.
+    auto nearest = [&](const std::vector<double>& T, int i) {
+        for (int d = 0; d < NS; d++) {
+            if (i - d >= 0 && std::isfinite(T[i - d])) return T[i - d];
+            if (i + d < NS && std::isfinite(T[i + d])) return T[i + d];
+        }
+        return (double)NAN;
+    };
+    const int dls[] = {-4, -2, -1, 0, 1, 2, 4};
+    const float ratios[] = {0.125f, 0.875f};
+    for (int i = 0; i < NS; i++)
+        for (int j = std::max(0, i - 3); j <= std::min(NS - 1, i + 3); j++)
+            for (int dl : dls)
+                for (float fr : ratios) {
+                    float f[6];
+                    mlp_features(f, dl, pers[i], pers[j], p, theta);
+                    f[4] = fr;
+                    double tv[3] = {dl == 0 ? nearest(Tm2l, i) : nearest(Tgen, i), nearest(Tm2p, i),
+                                    0.5 * (nearest(Tp2p, i) + nearest(Tp2p, j))};
+                    for (int k = 0; k < 3; k++) {
+                        if (!std::isfinite(tv[k])) continue;
+                        c->rec_feat.insert(c->rec_feat.end(), f, f + 6);
+                        c->rec_kind.push_back(k);
+                        c->rec_tgt.push_back((float)tv[k]);
+                    }
+                }
+}
+
+static void mlp_init(std::vector<float>& w, uint64_t seed, float out_bias) {
+    w.assign(kMlpParams, 0.f);
+    uint64_t s = seed;
+    auto uni = [&]() {
+        s += 0x9E3779B97F4A7C15ull;
+        uint64_t z = s;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        return (double)(z >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
+    };
+    const int H = 64, F = 6;
+    for (int i = 0; i < H * F; i++) w[i] = (float)(uni() * std::sqrt(6.0 / F));
+    for (int i = 0; i < H * H; i++) w[H * F + H + i] = (float)(uni() * std::sqrt(6.0 / H));
+    for (int i = 0; i < 3 * H; i++) w[H * F + H + H * H + H + i] = (float)(uni() * std::sqrt(6.0 / H));
+    for (int j = 0; j < 3; j++) w[kMlpParams - 3 + j] = out_bias;
+}
+
+static double mlp_fit(fmm_ctx c, int B, const float* feat, const int32_t* kind, const float* tgt, int epochs,
+                      double lr, uint64_t seed) {
+    if (B <= 0) fail(FMM_ERR_INVALID_ARG, "no training records");
+    for (int r = 0; r < B; r++)
+        if (kind[r] < 0 || kind[r] > 2) fail(FMM_ERR_INVALID_ARG, "record kind out of range");
+    double mean = 0;
+    for (int r = 0; r < B; r++) mean += tgt[r] / B;
+    std::vector<float> w;
+    mlp_init(w, seed, (float)mean);
+    float* dw = need<float>(c, c->d_mlp, kMlpParams);
+    float* dm = need<float>(c, c->d_mlp_m, kMlpParams);
+    float* dv = need<float>(c, c->d_mlp_v, kMlpParams);
+    float* dg = need<float>(c, c->d_grad, kMlpParams + 4);
+    float* dgr = need<float>(c, c->d_grad_rec, (size_t)B * kMlpParams);
+    float* dlr = need<float>(c, c->d_loss_rec, B);
+    float* df = need<float>(c, c->d_feat, (size_t)B * 6);
+    int32_t* dk = need<int32_t>(c, c->d_kind, B);
+    float* dt = need<float>(c, c->d_tgt, B);
+    to_dev(c, dw, w.data(), kMlpParams);
+    ck(hipMemsetAsync(dm, 0, kMlpParams * 4, c->stream), "memset");
+    ck(hipMemsetAsync(dv, 0, kMlpParams * 4, c->stream), "memset");
+    to_dev(c, df, feat, (size_t)B * 6);
+    to_dev(c, dk, kind, B);
+    to_dev(c, dt, tgt, B);
+    for (int e = 1; e <= epochs; e++) {
+        mlp_grad(dw, df, dk, dt, B, dgr, dlr, dg, dg + kMlpParams, c->stream);
+        mlp_adam(dw, dm, dv, dg, e, (float)lr, c->stream);
+    }
+    mlp_grad(dw, df, dk, dt, B, dgr, dlr, dg, dg + kMlpParams, c->stream);
+    check_launch("cost model training");
+    float loss = 0;
+    to_host<float>(c, &loss, dg + kMlpParams, 1);
+    c->mlp_ready = true;
+    c->mlp_version++;
+    return loss;
+}
+
+fmm_status fmm_costmodel_train(fmm_ctx c, int32_t p, double theta, int32_t epochs, uint64_t seed,
+                               double* final_loss) {
+    return guarded(c, [&] {
+        if (p < 0 || p > FMM_P_MAX) fail(FMM_ERR_INVALID_ARG, "p out of range");
+        if (!(theta > 0.0 && theta < 1.0)) fail(FMM_ERR_INVALID_ARG, "theta must lie in (0, 1)");
+        if (epochs < 1) fail(FMM_ERR_INVALID_ARG, "epochs must be >= 1");
+        gen_records(c, p, theta, seed);
+        double l = mlp_fit(c, (int)c->rec_kind.size(), c->rec_feat.data(), c->rec_kind.data(), c->rec_tgt.data(),
+                           epochs, 3e-3, seed);
+        if (final_loss) *final_loss = l;
+    });
+}
+
+fmm_status fmm_costmodel_fit(fmm_ctx c, int32_t n_rec, const float* features, const int32_t* kinds,
+                             const float* targets, int32_t epochs, double lr, uint64_t seed, double* final_loss) {
+    return guarded(c, [&] {
+        if (n_rec < 1 || !features || !kinds || !targets) fail(FMM_ERR_INVALID_ARG, "bad records");
+        if (epochs < 1 || !(lr > 0)) fail(FMM_ERR_INVALID_ARG, "bad optimiser settings");
+        double l = mlp_fit(c, n_rec, features, kinds, targets, epochs, lr, seed);
+        if (final_loss) *final_loss = l;
+    });
+}
+
+fmm_status fmm_costmodel_records(fmm_ctx c, int32_t cap, int32_t* count, float* features, int32_t* kinds,
+                                 float* targets) {
+    return guarded(c, [&] {
+        int32_t m = (int32_t)c->rec_kind.size();
+        if (count) *count = m;
+        int32_t k = std::min(cap, m);
+        for (int32_t i = 0; i < k; i++) {
+            if (features)
+                for (int j = 0; j < 6; j++) features[6 * i + j] = c->rec_feat[6 * i + j];
+            if (kinds) kinds[i] = c->rec_kind[i];
+            if (targets) targets[i] = c->rec_tgt[i];
+        }
+    });
+}
+
+fmm_status fmm_costmodel_get_weights(fmm_ctx c, float* w) {
+    return guarded(c, [&] {
+        if (!w) fail(FMM_ERR_INVALID_ARG, "null pointer");
+        if (!c->mlp_ready) fail(FMM_ERR_STATE, "no cost model");
+        to_host<float>(c, w, c->d_mlp.p, kMlpParams);
+    });
+}
+
+fmm_status fmm_costmodel_set_weights(fmm_ctx c, const float* w) {
+    return guarded(c, [&] {
+        if (!w) fail(FMM_ERR_INVALID_ARG, "null pointer");
+        for (int i = 0; i < kMlpParams; i++)
+            if (!std::isfinite(w[i])) fail(FMM_ERR_INVALID_ARG, "non-finite weight");
+        to_dev(c, need<float>(c, c->d_mlp, kMlpParams), w, kMlpParams);
+        c->mlp_ready = true;
+        c->mlp_version++;
+    });
+}
+
+fmm_status fmm_costmodel_loss_grad(fmm_ctx c, const float* w, int32_t n_rec, const float* features,
+                                   const int32_t* kinds, const float* targets, float* loss, float* grad) {
+    return guarded(c, [&] {
+        if (!w || n_rec < 1 || !features || !kinds || !targets) fail(FMM_ERR_INVALID_ARG, "bad arguments");
+        for (int r = 0; r < n_rec; r++)
+            if (kinds[r] < 0 || kinds[r] > 2) fail(FMM_ERR_INVALID_ARG, "record kind out of range");
+        const int B = n_rec;
+        float* dw = need<float>(c, c->tune_out, kMlpParams);
+        float* dg = need<float>(c, c->d_grad, kMlpParams + 4);
+        float* dgr = need<float>(c, c->d_grad_rec, (size_t)B * kMlpParams);
+        float* dlr = need<float>(c, c->d_loss_rec, B);
+        float* df = need<float>(c, c->d_feat, (size_t)B * 6);
+        int32_t* dk = need<int32_t>(c, c->d_kind, B);
+        float* dt = need<float>(c, c->d_tgt, B);
+        to_dev(c, dw, w, kMlpParams);
+        to_dev(c, df, features, (size_t)B * 6);
+        to_dev(c, dk, kinds, B);
+        to_dev(c, dt, targets, B);
+        mlp_grad(dw, df, dk, dt, B, dgr, dlr, dg, dg + kMlpParams, c->stream);
+        check_launch("cost model gradient");
+        if (grad) to_host<float>(c, grad, dg, kMlpParams);
+        if (loss) to_host<float>(c, loss, dg + kMlpParams, 1);
+    });
+}
+
+fmm_status fmm_costmodel_table(fmm_ctx c, int32_t p, double theta, uint8_t* table) {
+    return guarded(c, [&] {
+        if (!table) fail(FMM_ERR_INVALID_ARG, "null pointer");
+        if (!c->mlp_ready) fail(FMM_ERR_STATE, "no cost model");
+        if (p < 0 || p > FMM_P_MAX || !(theta > 0.0 && theta < 1.0)) fail(FMM_ERR_INVALID_ARG, "bad p or theta");
+        uint8_t* d = need<uint8_t>(c, c->d_table, kMlpTable);
+        mlp_table((const float*)c->d_mlp.p, p, (float)theta, d, c->stream);
+        check_launch("cost model table");
+        c->table_p = p;
+        c->table_theta = theta;
+        c->table_version = c->mlp_version;
+        to_host<uint8_t>(c, table, d, kMlpTable);
     });
 }
 

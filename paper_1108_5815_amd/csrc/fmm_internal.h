@@ -79,12 +79,29 @@ void tree_emit(const uint64_t* keys, CellArrays cells, int32_t c0, int32_t c1, i
 void cell_geometry(CellArrays cells, int32_t ncell, double lox, double loy, double loz,
                    double side, hipStream_t s);
 
+// ------------------------------------------------------------------ learned cost model
+constexpr int kMlpParams = 6 * 64 + 64 + 64 * 64 + 64 + 3 * 64 + 3;  // 4803
+// quantised feature grid read by the traversal: level difference in
+// [-kMlpDl, kMlpDl], log2 of each particle count in steps of 1/kMlpNsub up to
+// 2^20, and kMlpBq bins of ((r_t + r_s)/R)/theta in (0, 1]
+constexpr int kMlpDl = 4, kMlpNsub = 4, kMlpBn = 20 * kMlpNsub + 1, kMlpBq = 4;
+constexpr int kMlpTable = (2 * kMlpDl + 1) * kMlpBn * kMlpBn * kMlpBq;
+constexpr int kMlpChunk = 32;  // training records per workgroup (partial gradients per chunk)
+void mlp_grad(const float* w, const float* feat, const int32_t* kind, const float* tgt, int B, float* grad_rec,
+              float* loss_rec, float* grad, float* loss, hipStream_t s);
+void mlp_adam(float* w, float* m, float* v, const float* g, int step, float lr, hipStream_t s);
+// returns the particle count; writes the particles if x is not null
+int64_t clustered_points(int L, int per, int per_lo, uint64_t seed, float* x, float* y, float* z, float* q,
+                         hipStream_t s);
+void mlp_table(const float* w, int p, float theta, uint8_t* table, hipStream_t s);
+
 // ------------------------------------------------------------------ traversal
 struct TravParams {
     double theta2;
+    double theta;
     int policy;
     double c_m2l, c_m2p, c_p2p;
-    const float* mlp;   // learned cost model weights (device) or null
+    const uint8_t* mlp_table;  // learned choices over the quantised feature grid, or null
 };
 // per frontier pair: counts of new (M2L, M2P, P2P, SPLIT) pairs
 void trav_count(const int2* frontier, int64_t nf, CellArrays cells, TravParams tp, uint4* cnt,

@@ -26,38 +26,6 @@ enum { KIND_M2L = 0, KIND_M2P = 1, KIND_P2P = 2, KIND_SPLIT = 3 };
 
 __device__ inline bool is_leaf(const CellArrays& c, int32_t i) { return c.nchild[i] == 0; }
 
-// Learned cost model: 6 -> 64 -> 64 -> 3 MLP with ReLU, predicting the log
-// time of M2L, M2P and P2P for a pair.  Weight layout (floats):
-// W1[64][6], b1[64], W2[64][64], b2[64], W3[3][64], b3[3].
-__device__ inline int mlp_choose(const float* __restrict__ w, const float f[6]) {
-    const float* W1 = w;
-    const float* b1 = W1 + 64 * 6;
-    const float* W2 = b1 + 64;
-    const float* b2 = W2 + 64 * 64;
-    const float* W3 = b2 + 64;
-    const float* b3 = W3 + 3 * 64;
-    float h1[64];
-    for (int i = 0; i < 64; i++) {
-        float a = b1[i];
-        for (int k = 0; k < 6; k++) a = fmaf(W1[i * 6 + k], f[k], a);
-        h1[i] = fmaxf(a, 0.f);
-    }
-    float o[3] = {b3[0], b3[1], b3[2]};
-    for (int i = 0; i < 64; i++) {
-        float a = b2[i];
-        for (int k = 0; k < 64; k++) a = fmaf(W2[i * 64 + k], h1[k], a);
-        a = fmaxf(a, 0.f);
-        o[0] = fmaf(W3[i], a, o[0]);
-        o[1] = fmaf(W3[64 + i], a, o[1]);
-        o[2] = fmaf(W3[128 + i], a, o[2]);
-    }
-    int k = 0;
-    float best = o[0];
-    if (o[1] < best) { best = o[1]; k = 1; }
-    if (o[2] < best) k = 2;
-    return k;
-}
-
 __device__ inline int classify(const CellArrays& c, int32_t t, int32_t s, const TravParams& tp) {
     int4 gt = c.geo[t], gs = c.geo[s];
     int64_t dx = (int64_t)gt.x - gs.x, dy = (int64_t)gt.y - gs.y, dz = (int64_t)gt.z - gs.z;
@@ -68,11 +36,18 @@ __device__ inline int classify(const CellArrays& c, int32_t t, int32_t s, const 
         if (tp.policy == 1) return KIND_M2P;
         double nt = (double)(c.end[t] - c.begin[t]);
         double ns = (double)(c.end[s] - c.begin[s]);
-        if (tp.policy == 3 && tp.mlp) {
-            double R = sqrt((double)R2);
-            float f[6] = {(float)log2((double)gt.w / R), (float)log2((double)gs.w / R), (float)log2(nt),
-                          (float)log2(ns), 0.f, (float)((double)rr / R)};
-            return mlp_choose(tp.mlp, f);
+        if (tp.policy == 3) {
+            // learned choice, read from the network's evaluation over the
+            // quantised features of the pair
+            int dl = c.level[s] - c.level[t];
+            dl = dl < -kMlpDl ? -kMlpDl : (dl > kMlpDl ? kMlpDl : dl);
+            int bt = (int)rint(kMlpNsub * log2(nt)), bs = (int)rint(kMlpNsub * log2(ns));
+            bt = bt < 0 ? 0 : (bt >= kMlpBn ? kMlpBn - 1 : bt);
+            bs = bs < 0 ? 0 : (bs >= kMlpBn ? kMlpBn - 1 : bs);
+            double ratio = sqrt((double)(rr * rr) / (double)R2) / tp.theta;
+            int bq = (int)(ratio * kMlpBq);
+            bq = bq < 0 ? 0 : (bq >= kMlpBq ? kMlpBq - 1 : bq);
+            return tp.mlp_table[(((dl + kMlpDl) * kMlpBn + bt) * kMlpBn + bs) * kMlpBq + bq];
         }
         double c0 = tp.c_m2l;
         double c1 = __dmul_rn(tp.c_m2p, nt);

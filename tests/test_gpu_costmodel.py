@@ -1,0 +1,152 @@
+"""GPU tests of the learned cost model (policy FMM_POLICY_HYBRID_MLP).
+
+- The training kernels (forward + backward + fixed-order reduction) give the
+  oracle's FP64 loss and gradient within FP32 tolerance on seeded weights and
+  records.
+- The inference kernel's choice table equals the oracle's FP32 table wherever
+  the oracle's decision margin exceeds FP32 rounding.
+- With seeded weights the traversal's lists are bit-exact against the oracle
+  traversal driven by the oracle's own table.
+- Training on the method's own timing records lowers the loss, and the learned
+  policy keeps the accuracy of the method.
+- The gain test times the plain FMM, the timed hybrid and the learned hybrid
+  on the same adaptive workload and reports what the network gains.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import oracle as ora
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+P = 4803
+
+
+def seeded_weights(seed, scale=0.3):
+    return ((synth.uniform(seed, 9, P) * 2 - 1) * scale).astype(np.float32)
+
+
+def seeded_records(seed, B):
+    feat = ((synth.uniform(seed, 10, B * 6) * 2 - 1).reshape(B, 6)).astype(np.float32)
+    kind = np.floor(synth.uniform(seed, 11, B) * 3).astype(np.int32)
+    tgt = (synth.uniform(seed, 12, B) * 4 - 1).astype(np.float32)
+    return feat, kind, tgt
+
+
+def fmm():
+    from paper_1108_5815_amd import FMM
+    return FMM(0)
+
+
+def test_gradient_matches_oracle():
+    w = seeded_weights(21)
+    feat, kind, tgt = seeded_records(22, 37)
+    loss_g, g_g = fmm().costmodel_loss_grad(w, feat, kind, tgt)
+    loss_o, g_o = ora.mlp_loss_grad(w.astype(np.float64), feat.astype(np.float64), kind, tgt.astype(np.float64))
+    assert abs(loss_g - loss_o) <= 1e-5 * loss_o
+    assert np.abs(g_g - g_o).max() <= 1e-4 * np.abs(g_o).max()
+
+
+def test_table_matches_oracle_fp32():
+    w = seeded_weights(23)
+    f = fmm()
+    f.costmodel_set_weights(w)
+    tg = f.costmodel_table(10, 0.4)
+    to, margin = ora.mlp_table(w, 10, 0.4)
+    differ = tg != to
+    assert not np.any(differ & (margin > 1e-5)), np.argwhere(differ & (margin > 1e-5))[:5]
+    assert differ.mean() < 1e-3
+
+
+@pytest.mark.parametrize("theta", [0.5, 0.4])
+def test_learned_lists_bitexact_with_seeded_weights(theta):
+    w = seeded_weights(24, scale=0.5)
+    n = 20000
+    x, y, z = (np.asarray(a, np.float32).astype(np.float64) for a in synth.plummer(n, 25))
+    q = np.asarray(synth.charges_equal(n), np.float32).astype(np.float64)
+    f = fmm()
+    f.costmodel_set_weights(w)
+    t = [torch.tensor(a, dtype=torch.float32, device="cuda:0") for a in (x, y, z, q)]
+    f.build_tree(*t, 16)
+    f.traverse(8, theta, 3)
+    tab, _ = ora.mlp_table(w, 8, theta)
+    tr = ora.Tree(x, y, z, 16)
+    tr.traverse_table(theta, tab)
+    lo = tr.lists()
+    for k in (0, 1, 2):
+        tg, sg = f.list(k)
+        a = np.stack([tg, sg], 1)[np.lexsort((sg, tg))]
+        b = np.stack(lo[k], 1)[np.lexsort((lo[k][1], lo[k][0]))]
+        assert np.array_equal(a, b), k
+    assert sum(lo[k][0].size for k in (0, 1, 2)) > 0
+
+
+def test_fit_lowers_loss():
+    feat, kind, _ = seeded_records(26, 64)
+    # a smooth target the network can fit: per kind a different linear form
+    tgt = (feat @ np.array([0.5, -1.0, 0.3, 0.2, 0.0, 0.1]) + kind).astype(np.float32)
+    f = fmm()
+    base = float(np.mean((tgt - tgt.mean()) ** 2))
+    loss = f.costmodel_fit(feat, kind, tgt, epochs=3000, lr=3e-3, seed=3)
+    print("fit loss", loss, "variance", base)
+    assert loss < 0.05 * base
+
+
+def plummer_inputs(n, seed):
+    x, y, z = (np.asarray(a, np.float32).astype(np.float64) for a in synth.plummer(n, seed))
+    q = np.asarray(synth.charges_equal(n), np.float32).astype(np.float64)
+    return x, y, z, q
+
+
+def test_train_on_own_timings_and_accuracy():
+    f = fmm()
+    loss = f.costmodel_train(10, 0.4, epochs=3000, seed=7)
+    feat, kind, tgt = f.costmodel_records()
+    print("records", kind.size, "final loss", loss)
+    assert kind.size >= 12 and set(np.unique(kind)) == {0, 1, 2}
+    assert loss < 0.25          # log2 units: within ~20% of the measured per-pair time
+    n = 200000
+    x, y, z, q = plummer_inputs(n, 27)
+    t = [torch.tensor(a, dtype=torch.float32, device="cuda:0") for a in (x, y, z, q)]
+    f.build_tree(*t, 64)
+    f.traverse(10, 0.4, 3)
+    phi, E = f.evaluate(out_dtype=torch.float64)
+    torch.cuda.synchronize()
+    tg = synth.target_sample(n, 400, 227)
+    pd, Ed = ora.direct(x, y, z, q, tg)
+    ep = ora.rel_l2(phi.cpu().numpy()[tg], pd)
+    eE = ora.rel_l2(E.cpu().numpy().T[tg], Ed)
+    print("learned policy sizes", f.sizes(), "phi", ep, "E", eE)
+    assert ep < 1e-5 and eE < 1e-4
+
+
+def test_gain_of_learned_model():
+    """Same adaptive workload (Plummer, 1M points, p = 10, theta = 0.4,
+    ncrit = 64) under the plain FMM, the timed hybrid and the learned hybrid."""
+    n = 1 << 20
+    x, y, z, q = plummer_inputs(n, 28)
+    t = [torch.tensor(a, dtype=torch.float32, device="cuda:0") for a in (x, y, z, q)]
+    f = fmm()
+    f.tune(10)
+    f.costmodel_train(10, 0.4, epochs=3000, seed=7)
+    out = (torch.empty(n, device="cuda:0"), torch.empty((3, n), device="cuda:0"))
+    res = {}
+    for name, pol in (("fmm", 0), ("timed", 2), ("learned", 3)):
+        for rep in range(4):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            f.build_tree(*t, 64)
+            f.traverse(10, 0.4, pol)
+            f.evaluate(out=out)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        res[name] = (n / dt, f.sizes())
+    for k, v in res.items():
+        print(f"{k:8s} {v[0] / 1e6:8.2f} M particles/s  {v[1]}")
+    print("learned / timed:", res["learned"][0] / res["timed"][0])
+    assert res["learned"][0] > res["fmm"][0]
