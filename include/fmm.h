@@ -61,8 +61,10 @@ typedef enum {
 
 typedef enum {
     FMM_PREC_FP32 = 0,       /* FP32 kernels, FP64 per-target final sum */
-    FMM_PREC_SPLIT_BF16 = 1, /* M2L as split-BF16 products on MFMA, FP32 accumulate */
-    FMM_PREC_FP64 = 2
+    FMM_PREC_SPLIT_BF16 = 1, /* as FP32, but same-level M2L as three BF16 products per
+                                FP32 product (hi*hi + hi*lo + lo*hi) on the matrix cores
+                                with FP32 accumulation; p <= 10 */
+    FMM_PREC_FP64 = 2        /* reserved: not implemented (FMM_ERR_UNSUPPORTED) */
 } fmm_precision;
 
 typedef enum { FMM_F32 = 0, FMM_F64 = 1 } fmm_dtype;
@@ -165,10 +167,13 @@ fmm_status fmm_tune(fmm_ctx ctx, int32_t p, int32_t precision);
  * two-level set for mixed-level M2L), then train on the GPU with the
  * library's forward/backward/Adam kernels (full batch, `epochs` steps,
  * learning rate 3e-3, weights initialised from `seed`).  Enables
- * FMM_POLICY_HYBRID_MLP.  *final_loss (may be NULL) receives the mean squared
- * error of the log2 times.  Needs no tree; leaves the context's tree intact. */
-fmm_status fmm_costmodel_train(fmm_ctx ctx, int32_t p, double theta, int32_t epochs, uint64_t seed,
-                               double *final_loss);
+ * FMM_POLICY_HYBRID_MLP.  The timings are taken with the M2L kernel of
+ * `precision` (FMM_PREC_FP32 or FMM_PREC_SPLIT_BF16), which evaluations using
+ * the model should then use.  *final_loss (may be NULL) receives the mean
+ * squared error of the log2 times.  Needs no tree; leaves the context's tree
+ * intact. */
+fmm_status fmm_costmodel_train(fmm_ctx ctx, int32_t p, double theta, int32_t precision, int32_t epochs,
+                               uint64_t seed, double *final_loss);
 
 /* Train on caller-given records (host arrays): features[n_rec][6],
  * kinds[n_rec] in {0 M2L, 1 M2P, 2 P2P}, targets[n_rec] = log2 ns. */
@@ -207,6 +212,11 @@ fmm_status fmm_get_sizes(fmm_ctx ctx, int64_t *n_cells, int64_t *n_m2l, int64_t 
  * batched same-level GEMM (matrix cores) and those converted one by one
  * (mixed levels or offsets outside the per-octant tables).  NULL allowed. */
 fmm_status fmm_get_m2l_split(fmm_ctx ctx, int64_t *n_batched, int64_t *n_general);
+
+/* Work of the last traversal's lists: particle pairs of the P2P list
+ * (sum of n_t * n_s, self pairs included) and target particles of the M2P
+ * list (sum of n_t).  Either pointer may be NULL. */
+fmm_status fmm_get_work(fmm_ctx ctx, int64_t *p2p_particle_pairs, int64_t *m2p_targets);
 
 /* Bounding cube: lo3_host[3] minimum corner, side_host[1] side. */
 fmm_status fmm_get_bbox(fmm_ctx ctx, double *lo3_host, double *side_host);

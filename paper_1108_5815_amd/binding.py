@@ -56,7 +56,7 @@ def lib():
         "fmm_get_costs": ([vp, vp], ctypes.c_int),
         "fmm_tune": ([vp, i32, i32], ctypes.c_int),
         "fmm_get_sizes": ([vp, vp, vp, vp, vp], ctypes.c_int),
-        "fmm_costmodel_train": ([vp, i32, dbl, i32, ctypes.c_uint64, vp], ctypes.c_int),
+        "fmm_costmodel_train": ([vp, i32, dbl, i32, i32, ctypes.c_uint64, vp], ctypes.c_int),
         "fmm_costmodel_fit": ([vp, i32, vp, vp, vp, i32, dbl, ctypes.c_uint64, vp], ctypes.c_int),
         "fmm_costmodel_records": ([vp, i32, vp, vp, vp, vp], ctypes.c_int),
         "fmm_costmodel_get_weights": ([vp, vp], ctypes.c_int),
@@ -65,6 +65,7 @@ def lib():
         "fmm_costmodel_table": ([vp, i32, dbl, vp], ctypes.c_int),
         "fmm_get_bbox": ([vp, vp, vp], ctypes.c_int),
         "fmm_get_m2l_split": ([vp, vp, vp], ctypes.c_int),
+        "fmm_get_work": ([vp, vp, vp], ctypes.c_int),
         "fmm_get_keys": ([vp, vp, vp], ctypes.c_int),
         "fmm_get_cells": ([vp] + [vp] * 9, ctypes.c_int),
         "fmm_get_list": ([vp, i32, vp, vp], ctypes.c_int),
@@ -160,9 +161,10 @@ class FMM:
         self._ck(lib().fmm_tune(self.h, int(p), int(precision)))
 
     # ------------------------------------------------------------ learned cost model
-    def costmodel_train(self, p: int, theta: float, epochs: int = 4000, seed: int = 1) -> float:
+    def costmodel_train(self, p: int, theta: float, epochs: int = 4000, seed: int = 1,
+                        precision: int = PREC_FP32) -> float:
         loss = ctypes.c_double()
-        self._ck(lib().fmm_costmodel_train(self.h, int(p), float(theta), int(epochs), int(seed),
+        self._ck(lib().fmm_costmodel_train(self.h, int(p), float(theta), int(precision), int(epochs), int(seed),
                                            ctypes.byref(loss)))
         return loss.value
 
@@ -224,6 +226,11 @@ class FMM:
         a, b = ctypes.c_int64(), ctypes.c_int64()
         self._ck(lib().fmm_get_m2l_split(self.h, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
+
+    def work(self):
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        self._ck(lib().fmm_get_work(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return dict(p2p_particle_pairs=a.value, m2p_targets=b.value)
 
     def general_pairs(self) -> int:
         return self.m2l_split()[1]

@@ -71,7 +71,8 @@ struct fmm_ctx_s {
 
     // same-level M2L batching
     M2LPlan plan;
-    Buf d_slot, d_offid, d_T;
+    Buf d_slot, d_offid, d_T, d_Thi, d_Tlo;
+    bool plan_bf16 = false;
     Buf has_fast, rkey, rval, rkey2, rval2, rowof, gather, general, gtg, gsr, goff;
     bool m2l_sorted = false;
     GemmPlan gp{};
@@ -108,7 +109,7 @@ struct fmm_ctx_s {
                       &src[2], &off[0], &off[1], &off[2], &tgt2, &src2, &d_slot, &d_offid, &d_T, &has_fast,
                       &rkey, &rval, &rkey2, &rval2, &rowof, &gather, &general, &gtg, &gsr, &goff, &d_m2m, &d_l2l, &d_w, &d_g,
                       &d_h, &d_rc, &d_mlp, &M, &L, &nearb, &tune_pts, &tune_out, &d_mlp_m, &d_mlp_v,
-                      &d_grad, &d_grad_rec, &d_loss_rec, &d_feat, &d_kind, &d_tgt, &d_table};
+                      &d_grad, &d_grad_rec, &d_loss_rec, &d_feat, &d_kind, &d_tgt, &d_table, &d_Thi, &d_Tlo};
         for (Buf* b : all) bufs.push_back(b);
     }
 };
@@ -397,6 +398,17 @@ void upload_plan(fmm_ctx c, int p, double theta) {
     to_dev(c, need<int32_t>(c, c->d_slot, pl.slot_of.size()), pl.slot_of.data(), pl.slot_of.size());
     to_dev(c, need<int32_t>(c, c->d_offid, pl.offid.size()), pl.offid.data(), pl.offid.size());
     to_dev(c, need<float>(c, c->d_T, pl.T.size()), pl.T.data(), pl.T.size());
+    c->plan_bf16 = false;
+}
+
+// split-BF16 copies of the same-level operators, made on first use
+void upload_plan_bf16(fmm_ctx c) {
+    if (c->plan_bf16) return;
+    std::vector<uint16_t> hi, lo;
+    split_bf16_kblocked(c->plan.T, c->plan.offsets.size(), kpad(c->plan.p), hi, lo);
+    to_dev(c, need<uint16_t>(c, c->d_Thi, hi.size()), hi.data(), hi.size());
+    to_dev(c, need<uint16_t>(c, c->d_Tlo, lo.size()), lo.data(), lo.size());
+    c->plan_bf16 = true;
 }
 
 void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
@@ -576,12 +588,15 @@ void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
 void evaluate_impl(fmm_ctx c, int32_t precision, int32_t out_dtype, void* phi, void* ex, void* ey, void* ez) {
     if (!c->traversed) fail(FMM_ERR_STATE, "fmm_evaluate before fmm_traverse");
     if (precision < 0 || precision > 2) fail(FMM_ERR_INVALID_ARG, "unknown precision");
-    if (precision != FMM_PREC_FP32) fail(FMM_ERR_UNSUPPORTED, "only FMM_PREC_FP32 is implemented");
+    if (precision == FMM_PREC_FP64) fail(FMM_ERR_UNSUPPORTED, "FMM_PREC_FP64 is not implemented");
+    if (precision == FMM_PREC_SPLIT_BF16 && !m2l_bf16_supported(c->p))
+        fail(FMM_ERR_UNSUPPORTED, "split-BF16 M2L is implemented for p <= 10");
     if (out_dtype != FMM_F32 && out_dtype != FMM_F64) fail(FMM_ERR_INVALID_ARG, "out_dtype must be F32 or F64");
     if (c->n > 0 && (!phi || !ex || !ey || !ez)) fail(FMM_ERR_INVALID_ARG, "null output pointer");
     if (c->n == 0) return;
     hipStream_t s = c->stream;
     int p = c->p, KP = kpad(p);
+    if (precision == FMM_PREC_SPLIT_BF16 && c->gemm_on) upload_plan_bf16(c);
     int32_t nc = c->ncell;
     CellArrays ca = cells_of(c);
     Tables tb = tables_of(c);
@@ -596,8 +611,14 @@ void evaluate_impl(fmm_ctx c, int32_t precision, int32_t out_dtype, void* phi, v
     ck(hipMemsetAsync(L, 0, (size_t)nc * KP * sizeof(float), s), "memset");
     mark(c, PH_M2L);
     if (c->gemm_on && c->ntiles > 0)
-        m2l_gemm((float*)c->d_T.p, (int32_t*)c->d_offid.p, (int32_t*)c->gather.p, (uint32_t*)c->rval.p, c->gp, p, KP,
-                 M, L, c->ntiles, precision, s);
+    {
+        if (precision == FMM_PREC_SPLIT_BF16)
+            m2l_gemm_bf16((uint16_t*)c->d_Thi.p, (uint16_t*)c->d_Tlo.p, (int32_t*)c->d_offid.p, (int32_t*)c->gather.p,
+                          (uint32_t*)c->rval.p, c->gp, p, KP, M, L, c->ntiles, s);
+        else
+            m2l_gemm((float*)c->d_T.p, (int32_t*)c->d_offid.p, (int32_t*)c->gather.p, (uint32_t*)c->rval.p, c->gp, p,
+                     KP, M, L, c->ntiles, precision, s);
+    }
     mark(c, PH_M2LG);
     if (c->ngeneral > 0) m2l_general((int32_t*)c->goff.p, (uint32_t*)c->gsr.p, ca, nc, p, KP, tb, M, L, s);
     check_launch("m2l");
@@ -735,7 +756,8 @@ fmm_status fmm_get_costs(fmm_ctx c, double* costs3) {
 fmm_status fmm_tune(fmm_ctx c, int32_t p, int32_t precision) {
     return guarded(c, [&] {
         if (p < 0 || p > FMM_P_MAX) fail(FMM_ERR_INVALID_ARG, "p out of range");
-        if (precision != FMM_PREC_FP32) fail(FMM_ERR_UNSUPPORTED, "only FMM_PREC_FP32 is implemented");
+        if (precision != FMM_PREC_FP32 && precision != FMM_PREC_SPLIT_BF16)
+            fail(FMM_ERR_UNSUPPORTED, "tuning is implemented for FP32 and split-BF16");
         const int64_t n = 1 << 19;
         const int32_t ncrit = 32;
         const double theta = 0.5;
@@ -809,7 +831,7 @@ static void mlp_features(float* f, int dl, double nt, double ns, int p, double t
 // batches; the FMM policy times same-level M2L (GEMM) and P2P per cell pair,
 // the treecode policy M2P per cell pair, and a set whose lower half is one
 // level deeper times the mixed-level M2L pairs of its interface.
-static void gen_records(fmm_ctx c, int p, double theta, uint64_t seed) {
+static void gen_records(fmm_ctx c, int p, double theta, int precision, uint64_t seed) {
     c->rec_feat.clear();
     c->rec_kind.clear();
     c->rec_tgt.clear();
@@ -832,7 +854,7 @@ static void gen_records(fmm_ctx c, int p, double theta, uint64_t seed) {
         float* out = need<float>(c, c->tune_out, (size_t)4 * t->n);
         for (int k = 0; k < PH_N; k++) tm[k] = 0;
         for (int rep = 0; rep < 3; rep++) {
-            evaluate_impl(t, FMM_PREC_FP32, FMM_F32, out, out + t->n, out + 2 * t->n, out + 3 * t->n);
+            evaluate_impl(t, precision, FMM_F32, out, out + t->n, out + 2 * t->n, out + 3 * t->n);
             if (rep > 0)
                 for (int k = 0; k < PH_N; k++) tm[k] += t->ms[k] / 2;
         }
@@ -952,13 +974,17 @@ static double mlp_fit(fmm_ctx c, int B, const float* feat, const int32_t* kind, 
     return loss;
 }
 
-fmm_status fmm_costmodel_train(fmm_ctx c, int32_t p, double theta, int32_t epochs, uint64_t seed,
-                               double* final_loss) {
+fmm_status fmm_costmodel_train(fmm_ctx c, int32_t p, double theta, int32_t precision, int32_t epochs,
+                               uint64_t seed, double* final_loss) {
     return guarded(c, [&] {
         if (p < 0 || p > FMM_P_MAX) fail(FMM_ERR_INVALID_ARG, "p out of range");
         if (!(theta > 0.0 && theta < 1.0)) fail(FMM_ERR_INVALID_ARG, "theta must lie in (0, 1)");
         if (epochs < 1) fail(FMM_ERR_INVALID_ARG, "epochs must be >= 1");
-        gen_records(c, p, theta, seed);
+        if (precision != FMM_PREC_FP32 && precision != FMM_PREC_SPLIT_BF16)
+            fail(FMM_ERR_UNSUPPORTED, "training is implemented for FP32 and split-BF16");
+        if (precision == FMM_PREC_SPLIT_BF16 && !m2l_bf16_supported(p))
+            fail(FMM_ERR_UNSUPPORTED, "split-BF16 M2L is implemented for p <= 10");
+        gen_records(c, p, theta, precision, seed);
         double l = mlp_fit(c, (int)c->rec_kind.size(), c->rec_feat.data(), c->rec_kind.data(), c->rec_tgt.data(),
                            epochs, 3e-3, seed);
         if (final_loss) *final_loss = l;
@@ -1055,6 +1081,26 @@ fmm_status fmm_get_sizes(fmm_ctx c, int64_t* n_cells, int64_t* n_m2l, int64_t* n
         if (n_m2l) *n_m2l = c->traversed ? c->nlist[0] : 0;
         if (n_m2p) *n_m2p = c->traversed ? c->nlist[1] : 0;
         if (n_p2p) *n_p2p = c->traversed ? c->nlist[2] : 0;
+    });
+}
+
+fmm_status fmm_get_work(fmm_ctx c, int64_t* p2p_particle_pairs, int64_t* m2p_targets) {
+    return guarded(c, [&] {
+        if (!c->traversed) fail(FMM_ERR_STATE, "no traversal");
+        uint64_t* d = (uint64_t*)need<double>(c, c->small, 32) + 28;
+        uint64_t h[2] = {0, 0};
+        if (p2p_particle_pairs) {
+            pair_work((uint32_t*)c->tgt[2].p, (uint32_t*)c->src[2].p, c->nlist[2], cells_of(c), 1, d, c->stream);
+            check_launch("work count");
+            to_host<uint64_t>(c, h, d, 1);
+            *p2p_particle_pairs = (int64_t)h[0];
+        }
+        if (m2p_targets) {
+            pair_work((uint32_t*)c->tgt[1].p, (uint32_t*)c->src[1].p, c->nlist[1], cells_of(c), 0, d, c->stream);
+            check_launch("work count");
+            to_host<uint64_t>(c, h + 1, d, 1);
+            *m2p_targets = (int64_t)h[1];
+        }
     });
 }
 

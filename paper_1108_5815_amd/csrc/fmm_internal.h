@@ -79,6 +79,10 @@ void tree_emit(const uint64_t* keys, CellArrays cells, int32_t c0, int32_t c1, i
 void cell_geometry(CellArrays cells, int32_t ncell, double lox, double loy, double loz,
                    double side, hipStream_t s);
 
+// sum over (tgt, src) pairs of n_t * n_s (both = 1) or n_t (both = 0) into *out (device)
+void pair_work(const uint32_t* tgt, const uint32_t* src, int64_t n, CellArrays cells, int both, uint64_t* out,
+               hipStream_t s);
+
 // ------------------------------------------------------------------ learned cost model
 constexpr int kMlpParams = 6 * 64 + 64 + 64 * 64 + 64 + 3 * 64 + 3;  // 4803
 // quantised feature grid read by the traversal: level difference in
@@ -173,6 +177,11 @@ void m2l_gemm(const float* T, const int32_t* offid, const int32_t* gather, const
               GemmPlan plan, int p, int KP, const float* M, float* L, int ntiles, int precision,
               hipStream_t s);
 bool m2l_gemm_supported(int p);
+// split-BF16 variant (Thi/Tlo: k-blocked BF16 halves of the operators)
+void m2l_gemm_bf16(const uint16_t* Thi, const uint16_t* Tlo, const int32_t* offid, const int32_t* gather,
+                   const uint32_t* rowcell, GemmPlan plan, int p, int KP, const float* M, float* L, int ntiles,
+                   hipStream_t s);
+bool m2l_bf16_supported(int p);
 int gemm_tile_cols(int p);  // targets per GEMM tile for order p
 
 }  // namespace fmm

@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstring>
 #include <map>
 #include <stdexcept>
 
@@ -162,6 +163,37 @@ void m2l_operator(int p, const double q[3], double ratio, std::vector<double>& M
                 rn *= ratio;
             }
         }
+}
+
+static uint16_t bf16_rne(float x) {
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+static float bf16_value(uint16_t h) {
+    uint32_t u = (uint32_t)h << 16;
+    float x;
+    std::memcpy(&x, &u, 4);
+    return x;
+}
+
+void split_bf16_kblocked(const std::vector<float>& T, size_t noff, int KP, std::vector<uint16_t>& hi,
+                         std::vector<uint16_t>& lo) {
+    const size_t KB = KP / 8;
+    hi.assign(noff * KP * KP, 0);
+    lo.assign(noff * KP * KP, 0);
+    for (size_t o = 0; o < noff; o++)
+        for (int k = 0; k < KP; k++)
+            for (int j = 0; j < KP; j++) {
+                const float v = T[(o * KP + k) * KP + j];
+                const uint16_t h = bf16_rne(v);
+                const uint16_t l = bf16_rne(v - bf16_value(h));
+                const size_t ix = ((o * KB + k / 8) * KP + j) * 8 + k % 8;
+                hi[ix] = h;
+                lo[ix] = l;
+            }
 }
 
 void build_tables(int p, HostTables& t) {

@@ -47,6 +47,12 @@ struct M2LPlan {
     std::vector<float> T;                    // [noff][KP][KP], element (o, k, j) at (o*KP + k)*KP + j
 };
 
+// Split the same-level operators T ([noff][KP][KP] k-major FP32) into
+// BF16 hi = bf16(T) and lo = bf16(T - hi) (round to nearest even), stored
+// k-blocked: element (o, k, j) at ((o*KP/8 + k/8)*KP + j)*8 + k%8.
+void split_bf16_kblocked(const std::vector<float>& T, size_t noff, int KP, std::vector<uint16_t>& hi,
+                         std::vector<uint16_t>& lo);
+
 void build_tables(int p, HostTables& t);
 void build_m2l_plan(int p, double theta, M2LPlan& plan);
 
