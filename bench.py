@@ -22,6 +22,9 @@ The JSON line also carries:
                 library's stream in a separate pass
   cpu_baseline  the oracle (FP64 CPU, all host threads) on a bounded sample
                 of the same workload
+``--workload batch256_p8`` times the batch form instead: 256 independent
+instances of uneven size in one fmm_evaluate_batch per step, beside the same
+instances evaluated one after another.
 ``--gpus`` above 1 is rejected: this build runs on one GPU.
 """
 from __future__ import annotations
@@ -118,6 +121,119 @@ def accuracy(x, y, z, q, tg, phi, E):
             "reference": "FP64 direct sum (oracle)"}
 
 
+def run_batch(args):
+    """Batch workload: one step = fmm_evaluate_batch over every instance (one
+    forest, each phase one pass over all instances); compared with the same
+    instances evaluated one after another through the single-instance calls."""
+    import torch
+
+    import synth
+    from paper_1108_5815_amd import FMM
+    x, y, z, q, off, kinds, tg, w = synth.make_batch(args.workload, args.n_inst)
+    n, p, theta, ncrit = w["n"], w["p"], w["theta"], w["ncrit"]
+    dev = "cuda:0"
+    X, Y, Z, Q = (torch.tensor(a, dtype=torch.float32, device=dev) for a in (x, y, z, q))
+    phi = torch.empty(n, dtype=torch.float32, device=dev)
+    E = torch.empty((3, n), dtype=torch.float32, device=dev)
+    f = FMM(0)
+    prep = {}
+    if args.policy == 2:
+        f.tune(p, args.precision)
+        prep["unit_costs_ns"] = f.costs().tolist()
+    elif args.policy == 3:
+        t0 = time.perf_counter()
+        f.costmodel_train(p, theta, epochs=3000, seed=7, precision=args.precision)
+        prep["training_s"] = time.perf_counter() - t0
+
+    def step():
+        f.evaluate_batch(off, X, Y, Z, Q, ncrit, p, theta, args.policy, args.precision, out=(phi, E))
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    f.set_timing(True)
+    ph = {}
+    for _ in range(3):
+        step()
+        for k, v in f.timings().items():
+            ph[k] = ph.get(k, 0.0) + v / 3
+    f.set_timing(False)
+    torch.cuda.synchronize()
+    res = {"ms_per_step": ms, "value": n / (ms * 1e-3), "phase_ms": {k: round(v, 4) for k, v in ph.items()},
+           "sizes": f.sizes(), "m2l_split": dict(zip(("batched", "general"), f.m2l_split())), "work": f.work(),
+           "policy": POLICIES[args.policy], "precision": PRECISIONS[args.precision], "prep": prep}
+    # the same instances one by one (single-instance calls, one context)
+    g = FMM(0)
+    if args.policy == 2:
+        g.set_costs(*f.costs())
+    elif args.policy == 3:
+        g.costmodel_set_weights(f.costmodel_weights())
+    views = [(int(off[k]), int(off[k + 1])) for k in range(len(off) - 1)]
+
+    def loop():
+        for b, e in views:
+            g.build_tree(X[b:e], Y[b:e], Z[b:e], Q[b:e], ncrit)
+            g.traverse(p, theta, args.policy)
+            g.evaluate(args.precision, out=(phi[b:e], E[:, b:e]))
+
+    loop()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = max(1, min(args.steps, 3))
+    for _ in range(reps):
+        loop()
+    torch.cuda.synchronize()
+    ms_loop = (time.perf_counter() - t0) * 1e3 / reps
+    res["one_by_one"] = {"ms_per_step": ms_loop, "value": n / (ms_loop * 1e-3),
+                         "speedup_of_batch": ms_loop / ms}
+    step()
+    acc = None
+    if not args.no_cpu_baseline:
+        import oracle
+        xs, ys, zs, qs = (np.asarray(a, dtype=np.float32).astype(np.float64) for a in (x, y, z, q))
+        ph_ = phi.double().cpu().numpy()
+        Eg = E.double().cpu().numpy().T
+        num = den = nE = dE = 0.0
+        for b, e in views:
+            t = tg[(tg >= b) & (tg < e)] - b
+            pd, Ed = oracle.direct(xs[b:e], ys[b:e], zs[b:e], qs[b:e], t)
+            num += float(np.sum((ph_[b + t] - pd) ** 2))
+            den += float(np.sum(pd ** 2))
+            nE += float(np.sum((Eg[b + t] - Ed) ** 2))
+            dE += float(np.sum(Ed ** 2))
+        acc = {"phi_rel_l2": (num / den) ** 0.5, "E_rel_l2": (nE / dE) ** 0.5, "targets": int(tg.size),
+               "reference": "FP64 direct sum of each instance (oracle)"}
+    out = {
+        "metric": "FMM particles/sec over a batch of independent instances",
+        "value": res["value"], "unit": "particles/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+bf16" if args.precision == 1 else "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "n_inst": int(len(off) - 1), "n": n, "p": p, "theta": theta,
+                   "ncrit": ncrit, "policy": res["policy"], "precision": res["precision"]},
+        "accuracy": acc, "form": res, "roofline": roofline(res, p, args.precision),
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        ns, k, t = 0, 0, 0.0
+        while ns < args.cpu_sample and k < len(views):
+            b, e = views[k]
+            xs_, ys_, zs_, qs_ = (np.asarray(a[b:e], dtype=np.float32).astype(np.float64) for a in (x, y, z, q))
+            t0 = time.perf_counter()
+            oracle.fmm(xs_, ys_, zs_, qs_, p, theta, ncrit)
+            t += time.perf_counter() - t0
+            ns += e - b
+            k += 1
+        out["cpu_baseline"] = {"value": ns / t, "unit": "particles/s", "cores": oracle.num_threads(),
+                               "kind": "oracle",
+                               "sample": f"oracle FP64 FMM on the first {k} instances ({ns} points, {t:.1f} s)"}
+    print(json.dumps(out))
+
+
 def cpu_baseline(w, workload, sample):
     import oracle
     import synth
@@ -139,6 +255,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="plummer4m_p10")
     ap.add_argument("--n", type=int, default=None, help="override particle count")
+    ap.add_argument("--n-inst", type=int, default=None, help="batch workloads: first n instances only")
     ap.add_argument("--policy", type=int, default=3, help="0 fmm, 1 treecode, 2 timed hybrid, 3 learned hybrid")
     ap.add_argument("--precision", type=int, default=1, help="0 fp32, 1 split-bf16 M2L")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain (timed FP32) comparison")
@@ -154,6 +271,9 @@ def main():
     import synth
     from paper_1108_5815_amd import FMM
 
+    if synth.WORKLOADS[args.workload]["dist"] == "batch":
+        run_batch(args)
+        return
     x, y, z, q, tg, w = synth.make_workload(args.workload, args.n)
     n, p = w["n"], w["p"]
     dev = "cuda:0"

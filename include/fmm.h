@@ -134,6 +134,32 @@ fmm_status fmm_evaluate(fmm_ctx ctx, int32_t precision, int32_t out_dtype, void 
                         void *ey, void *ez);
 
 /*
+ * Batches of independent problems of uneven size (many instances evaluated
+ * together so that each phase is one pass over all of them):
+ * instance k owns particles [offsets[k], offsets[k+1]) of x, y, z, q and no
+ * interaction crosses instances.  Each instance gets its own bounding cube,
+ * Morton keys and root exactly as fmm_build_tree would give it alone, so its
+ * cells, lists and results are those of a build of that instance by itself.
+ * fmm_traverse and fmm_evaluate then work on the whole forest.
+ *   n_inst        >= 1
+ *   offsets_host  n_inst + 1 non-decreasing values, offsets[0] = 0,
+ *                 offsets[n_inst] = total particles < 2^31; empty instances
+ *                 are allowed
+ * Other arguments and errors as fmm_build_tree.  Introspection then reports
+ * the forest: cells of all instances (the roots first, in instance order),
+ * keys sorted by (instance, key, original index), lists over all instances.
+ */
+fmm_status fmm_build_tree_batch(fmm_ctx ctx, int32_t n_inst, const int64_t *offsets_host, int dtype,
+                                const void *x, const void *y, const void *z, const void *q, int32_t ncrit);
+
+/* fmm_build_tree_batch, fmm_traverse and fmm_evaluate in one call; outputs
+ * are device arrays of offsets[n_inst] values in the input order. */
+fmm_status fmm_evaluate_batch(fmm_ctx ctx, int32_t n_inst, const int64_t *offsets_host, int dtype,
+                              const void *x, const void *y, const void *z, const void *q, int32_t ncrit,
+                              int32_t p, double theta, int32_t policy, int32_t precision, int32_t out_dtype,
+                              void *phi, void *ex, void *ey, void *ez);
+
+/*
  * Unit costs of the timed hybrid (paper: "Kernel pre-calculation"): the
  * modelled time of an accepted pair is c_m2l for M2L, c_m2p * n_t for M2P and
  * (c_p2p * n_t) * n_s for P2P (n_t, n_s = particles of the target and source
@@ -218,8 +244,14 @@ fmm_status fmm_get_m2l_split(fmm_ctx ctx, int64_t *n_batched, int64_t *n_general
  * list (sum of n_t).  Either pointer may be NULL. */
 fmm_status fmm_get_work(fmm_ctx ctx, int64_t *p2p_particle_pairs, int64_t *m2p_targets);
 
-/* Bounding cube: lo3_host[3] minimum corner, side_host[1] side. */
+/* Bounding cube: lo3_host[3] minimum corner, side_host[1] side (of instance
+ * 0 after a batch build). */
 fmm_status fmm_get_bbox(fmm_ctx ctx, double *lo3_host, double *side_host);
+
+/* Bounding cubes of the first n_inst instances of the last build:
+ * lo_side_host[4k .. 4k+2] minimum corner, [4k+3] side; an empty instance
+ * reports (0, 0, 0, 1).  n_inst must not exceed the built count. */
+fmm_status fmm_get_bboxes(fmm_ctx ctx, int32_t n_inst, double *lo_side_host);
 
 /* Sorted Morton keys and permutation (perm[k] = original index of the k-th
  * sorted particle); host arrays of n entries. */

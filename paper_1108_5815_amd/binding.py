@@ -50,6 +50,10 @@ def lib():
         "fmm_last_error": ([vp], ctypes.c_char_p),
         "fmm_set_stream": ([vp, vp], ctypes.c_int),
         "fmm_build_tree": ([vp, i64, ctypes.c_int, vp, vp, vp, vp, i32], ctypes.c_int),
+        "fmm_build_tree_batch": ([vp, i32, vp, ctypes.c_int, vp, vp, vp, vp, i32], ctypes.c_int),
+        "fmm_evaluate_batch": ([vp, i32, vp, ctypes.c_int, vp, vp, vp, vp, i32, i32, dbl, i32, i32, i32,
+                                vp, vp, vp, vp], ctypes.c_int),
+        "fmm_get_bboxes": ([vp, i32, vp], ctypes.c_int),
         "fmm_traverse": ([vp, i32, dbl, i32], ctypes.c_int),
         "fmm_evaluate": ([vp, i32, i32, vp, vp, vp, vp], ctypes.c_int),
         "fmm_set_costs": ([vp, dbl, dbl, dbl], ctypes.c_int),
@@ -120,6 +124,12 @@ class FMM:
 
     # ------------------------------------------------------------ method
     def build_tree(self, x, y, z, q, ncrit: int):
+        dt = self._check_inputs(x, y, z, q)
+        self.n = x.numel()
+        self._ck(lib().fmm_build_tree(self.h, self.n, dt, x.data_ptr(), y.data_ptr(), z.data_ptr(),
+                                      q.data_ptr(), int(ncrit)))
+
+    def _check_inputs(self, x, y, z, q):
         t = self._torch
         dt = x.dtype
         if dt not in (t.float32, t.float64):
@@ -127,9 +137,52 @@ class FMM:
         for a in (x, y, z, q):
             if a.dtype != dt or not a.is_cuda or not a.is_contiguous() or a.numel() != x.numel():
                 raise ValueError("x, y, z, q must be contiguous device tensors of one dtype and length")
+        return F64 if dt == t.float64 else F32
+
+    @staticmethod
+    def _offsets(offsets, n):
+        off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        if off.ndim != 1 or off.size < 2 or off[-1] != n:
+            raise ValueError("offsets must hold n_inst + 1 values ending at the particle count")
+        return off
+
+    def build_tree_batch(self, offsets, x, y, z, q, ncrit: int):
+        """Forest of independent instances: instance k owns particles
+        [offsets[k], offsets[k+1])."""
+        dt = self._check_inputs(x, y, z, q)
+        off = self._offsets(offsets, x.numel())
         self.n = x.numel()
-        self._ck(lib().fmm_build_tree(self.h, self.n, F64 if dt == t.float64 else F32, x.data_ptr(),
-                                      y.data_ptr(), z.data_ptr(), q.data_ptr(), int(ncrit)))
+        self._ck(lib().fmm_build_tree_batch(self.h, off.size - 1, _ptr(off), dt, x.data_ptr(), y.data_ptr(),
+                                            z.data_ptr(), q.data_ptr(), int(ncrit)))
+        self.n_inst = off.size - 1
+
+    def evaluate_batch(self, offsets, x, y, z, q, ncrit: int, p: int, theta: float, policy: int = POLICY_FMM,
+                       precision: int = PREC_FP32, out_dtype=None, out=None):
+        """Build, traverse and evaluate a batch in one call; (phi, E) in input order."""
+        t = self._torch
+        dt = self._check_inputs(x, y, z, q)
+        off = self._offsets(offsets, x.numel())
+        n = x.numel()
+        if out is None:
+            od = t.float32 if out_dtype is None else out_dtype
+            phi = t.empty(n, dtype=od, device=f"cuda:{self.device}")
+            E = t.empty((3, n), dtype=od, device=f"cuda:{self.device}")
+        else:
+            phi, E = out
+        od = F64 if phi.dtype == t.float64 else F32
+        self.n = n
+        self._ck(lib().fmm_evaluate_batch(self.h, off.size - 1, _ptr(off), dt, x.data_ptr(), y.data_ptr(),
+                                          z.data_ptr(), q.data_ptr(), int(ncrit), int(p), float(theta),
+                                          int(policy), int(precision), od, phi.data_ptr(), E[0].data_ptr(),
+                                          E[1].data_ptr(), E[2].data_ptr()))
+        self.n_inst = off.size - 1
+        self.p = int(p)
+        return phi, E
+
+    def bboxes(self, n_inst: int):
+        out = np.zeros((n_inst, 4))
+        self._ck(lib().fmm_get_bboxes(self.h, int(n_inst), _ptr(out)))
+        return out
 
     def traverse(self, p: int, theta: float, policy: int = POLICY_FMM):
         self._ck(lib().fmm_traverse(self.h, int(p), float(theta), int(policy)))

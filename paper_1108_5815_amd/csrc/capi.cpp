@@ -51,8 +51,13 @@ struct fmm_ctx_s {
     int64_t n = 0;
     int dtype = 0;
     int32_t ncrit = 0;
-    double lo[3] = {0, 0, 0}, side = 1;
+    double lo[3] = {0, 0, 0}, side = 1;  // instance 0's bounding cube
     bool built = false, traversed = false;
+    // batch: instance offsets, frames, roots (cells [0, nroot))
+    std::vector<int64_t> hseg;
+    std::vector<Frame> frames;
+    int32_t nroot = 0;
+    Buf d_seg, d_bt, d_pb, d_box, d_frame, inst, bsort;
     int32_t ncell = 0, nleaf = 0;
     std::vector<int32_t> lvl;  // cells of level L: [lvl[L], lvl[L+1])
     Buf keys, keys2, idx, idx2, pts, ws, small;
@@ -109,7 +114,8 @@ struct fmm_ctx_s {
                       &src[2], &off[0], &off[1], &off[2], &tgt2, &src2, &d_slot, &d_offid, &d_T, &has_fast,
                       &rkey, &rval, &rkey2, &rval2, &rowof, &gather, &general, &gtg, &gsr, &goff, &d_m2m, &d_l2l, &d_w, &d_g,
                       &d_h, &d_rc, &d_mlp, &M, &L, &nearb, &tune_pts, &tune_out, &d_mlp_m, &d_mlp_v,
-                      &d_grad, &d_grad_rec, &d_loss_rec, &d_feat, &d_kind, &d_tgt, &d_table, &d_Thi, &d_Tlo};
+                      &d_grad, &d_grad_rec, &d_loss_rec, &d_feat, &d_kind, &d_tgt, &d_table, &d_Thi, &d_Tlo,
+                      &d_seg, &d_bt, &d_pb, &d_box, &d_frame, &inst, &bsort};
         for (Buf* b : all) bufs.push_back(b);
     }
 };
@@ -258,8 +264,17 @@ int bits_for(int64_t v) {
 }
 
 // ------------------------------------------------------------------ build
-void build_tree_impl(fmm_ctx c, int64_t n, int dtype, const void* x, const void* y, const void* z,
-                     const void* q, int32_t ncrit) {
+// Build the forest of a batch: instance k owns input particles
+// [hseg[k], hseg[k+1]) (host array of nseg + 1 offsets); a single problem is
+// the batch of one.  Each instance gets its own bounding cube, keys relative
+// to it, and its own root; the sort orders by (instance, key, input index).
+void build_forest_impl(fmm_ctx c, int32_t nseg, const int64_t* hseg, int dtype, const void* x, const void* y,
+                       const void* z, const void* q, int32_t ncrit) {
+    if (nseg < 1 || !hseg) fail(FMM_ERR_INVALID_ARG, "need at least one instance");
+    if (hseg[0] != 0) fail(FMM_ERR_INVALID_ARG, "offsets[0] must be 0");
+    for (int32_t k = 0; k < nseg; k++)
+        if (hseg[k + 1] < hseg[k]) fail(FMM_ERR_INVALID_ARG, "offsets must be non-decreasing");
+    const int64_t n = hseg[nseg];
     if (n < 0 || n >= ((int64_t)1 << 31)) fail(FMM_ERR_INVALID_ARG, "n out of range");
     if (ncrit < 1) fail(FMM_ERR_INVALID_ARG, "ncrit must be >= 1");
     if (dtype != FMM_F32 && dtype != FMM_F64) fail(FMM_ERR_INVALID_ARG, "dtype must be FMM_F32 or FMM_F64");
@@ -271,68 +286,122 @@ void build_tree_impl(fmm_ctx c, int64_t n, int dtype, const void* x, const void*
     c->ncrit = ncrit;
     c->ncell = 0;
     c->nleaf = 0;
+    c->nroot = 0;
     c->lvl.assign(1, 0);
+    c->hseg.assign(hseg, hseg + nseg + 1);
+    c->frames.assign(nseg, Frame{0, 0, 0, 1, 2097152.0, 1.0 / 4194304.0, 0, 0});
+    c->lo[0] = c->lo[1] = c->lo[2] = 0;
+    c->side = 1;
     if (n == 0) {
-        c->lo[0] = c->lo[1] = c->lo[2] = 0;
-        c->side = 1;
         c->built = true;
         return;
     }
     hipStream_t s = c->stream;
     mark(c, PH_KEYS);
-    size_t wsb = std::max({sort_ws_bytes(n), bbox_ws_bytes(n), scan_ws_bytes(n)});
+    // bounding cube per instance: blocks of at most `chunk` particles
+    const int64_t chunk = std::max<int64_t>(4096, (n + 1023) / 1024);
+    std::vector<int64_t> bt;
+    std::vector<int32_t> pb(nseg + 1, 0);
+    for (int32_t k = 0; k < nseg; k++) {
+        pb[k] = (int32_t)(bt.size() / 2);
+        for (int64_t i = hseg[k]; i < hseg[k + 1]; i += chunk) {
+            bt.push_back(i);
+            bt.push_back(std::min(i + chunk, hseg[k + 1]));
+        }
+    }
+    pb[nseg] = (int32_t)(bt.size() / 2);
+    const int nblk = pb[nseg];
+    int64_t* dseg = need<int64_t>(c, c->d_seg, nseg + 1);
+    to_dev(c, dseg, hseg, nseg + 1);
+    int64_t* dbt = need<int64_t>(c, c->d_bt, bt.size());
+    to_dev(c, dbt, bt.data(), bt.size());
+    int32_t* dpb = need<int32_t>(c, c->d_pb, nseg + 1);
+    to_dev(c, dpb, pb.data(), nseg + 1);
+    size_t wsb = std::max({sort_ws_bytes(n), scan_ws_bytes(n), (size_t)nblk * 6 * sizeof(double) + 256});
     void* ws = need<char>(c, c->ws, wsb);
     double* d6 = need<double>(c, c->small, 32);
     uint32_t* dbad = (uint32_t*)(d6 + 8);
-    bbox(x, y, z, dtype, n, d6, dbad, ws, s);
+    double* box = need<double>(c, c->d_box, (size_t)nseg * 6);
+    bbox(x, y, z, dtype, dbt, nblk, dpb, nseg, (double*)ws, box, dbad, s);
     check_launch("bbox");
-    double* h = (double*)host_stage(c);
-    to_host<double>(c, h, d6, 9);
-    uint32_t bad = ((uint32_t*)(h + 8))[0];
+    std::vector<double> hb((size_t)nseg * 6);
+    to_host<double>(c, hb.data(), box, hb.size());
+    uint32_t bad = 0;
+    to_host<uint32_t>(c, &bad, dbad, 1);
     if (bad) fail(FMM_ERR_INVALID_ARG, "non-finite coordinate in input");
-    double sd = 0;
-    for (int d = 0; d < 3; d++) {
-        c->lo[d] = h[d];
-        double e = h[3 + d] - h[d];
-        if (e > sd) sd = e;
+    for (int32_t k = 0; k < nseg; k++) {
+        if (hseg[k + 1] == hseg[k]) continue;
+        Frame& f = c->frames[k];
+        double sd = 0;
+        for (int d = 0; d < 3; d++) {
+            double e = hb[k * 6 + 3 + d] - hb[k * 6 + d];
+            if (e > sd) sd = e;
+        }
+        if (sd == 0.0) sd = 1.0;
+        f.lox = hb[k * 6 + 0];
+        f.loy = hb[k * 6 + 1];
+        f.loz = hb[k * 6 + 2];
+        f.side = sd;
+        f.scale = 2097152.0 / sd;
+        f.h = sd / 4194304.0;
     }
-    if (sd == 0.0) sd = 1.0;
-    c->side = sd;
-    double scale = 2097152.0 / sd;
+    {
+        const Frame& f0 = c->frames[0];
+        c->lo[0] = f0.lox;
+        c->lo[1] = f0.loy;
+        c->lo[2] = f0.loz;
+        c->side = f0.side;
+    }
+    Frame* dfr = need<Frame>(c, c->d_frame, nseg);
+    to_dev(c, dfr, c->frames.data(), nseg);
     uint64_t* keys = need<uint64_t>(c, c->keys, n);
     uint64_t* keys2 = need<uint64_t>(c, c->keys2, n);
     uint32_t* idx = need<uint32_t>(c, c->idx, n);
     uint32_t* idx2 = need<uint32_t>(c, c->idx2, n);
-    morton_keys(x, y, z, dtype, n, c->lo[0], c->lo[1], c->lo[2], scale, keys, idx, s);
+    uint32_t* inst = nseg > 1 ? need<uint32_t>(c, c->inst, n) : nullptr;
+    morton_keys(x, y, z, dtype, n, dseg, nseg, dfr, keys, idx, inst, s);
     check_launch("morton");
     mark(c, PH_SORT);
     sort_u64(keys, idx, keys2, idx2, n, 0, 63, ws, s);
+    if (nseg > 1) {
+        uint32_t* ik = need<uint32_t>(c, c->bsort, 4 * (size_t)n);
+        uint32_t *iv = ik + n, *ik2 = ik + 2 * n, *iv2 = ik + 3 * n;
+        inst_keys(idx, inst, n, ik, iv, s);
+        sort_u32(ik, iv, ik2, iv2, n, 0, bits_for(nseg - 1), ws, s);
+        gather_sorted(keys, idx, iv, n, keys2, idx2, s);
+        std::swap(c->keys, c->keys2);
+        std::swap(c->idx, c->idx2);
+        keys = (uint64_t*)c->keys.p;
+        idx = (uint32_t*)c->idx.p;
+    }
     check_launch("sort");
     float4* pts = need<float4>(c, c->pts, n);
     permute_points(x, y, z, q, dtype, n, idx, pts, s);
     check_launch("permute");
     mark(c, PH_TREE);
-    // root
-    size_t cap = (size_t)std::max<int64_t>(1024, 2 * n / std::max(ncrit, 1) + 1024);
+    // one root per non-empty instance, in instance order
+    std::vector<int32_t> rb, re;
+    for (int32_t k = 0; k < nseg; k++)
+        if (hseg[k + 1] > hseg[k]) {
+            rb.push_back((int32_t)hseg[k]);
+            re.push_back((int32_t)hseg[k + 1]);
+        }
+    const int32_t nroot = (int32_t)rb.size();
+    c->nroot = nroot;
+    size_t cap = (size_t)std::max<int64_t>(1024, 2 * n / std::max(ncrit, 1) + 1024) + nroot;
     ensure_cells(c, cap, 0);
     {
-        int32_t* hi = (int32_t*)host_stage(c);
-        hi[0] = 0;
-        hi[1] = (int32_t)n;
-        hi[2] = -1;
-        hi[3] = 0;
-        hi[4] = -1;
-        hi[5] = 0;
-        ck(hipMemcpyAsync(c->c_begin.p, hi + 0, 4, hipMemcpyHostToDevice, s), "H2D");
-        ck(hipMemcpyAsync(c->c_end.p, hi + 1, 4, hipMemcpyHostToDevice, s), "H2D");
-        ck(hipMemcpyAsync(c->c_parent.p, hi + 2, 4, hipMemcpyHostToDevice, s), "H2D");
-        ck(hipMemcpyAsync(c->c_level.p, hi + 3, 4, hipMemcpyHostToDevice, s), "H2D");
-        ck(hipMemcpyAsync(c->c_child.p, hi + 4, 4, hipMemcpyHostToDevice, s), "H2D");
-        ck(hipMemcpyAsync(c->c_nchild.p, hi + 5, 4, hipMemcpyHostToDevice, s), "H2D");
-        ck(hipMemsetAsync(c->c_prefix.p, 0, 8, s), "memset");
-        ck(hipStreamSynchronize(s), "sync");
+        std::vector<int32_t> neg(nroot, -1), zero(nroot, 0);
+        std::vector<uint64_t> z64(nroot, 0);
+        to_dev(c, c->c_begin.p, rb.data(), nroot);
+        to_dev(c, c->c_end.p, re.data(), nroot);
+        to_dev(c, c->c_parent.p, neg.data(), nroot);
+        to_dev(c, c->c_level.p, zero.data(), nroot);
+        to_dev(c, c->c_child.p, neg.data(), nroot);
+        to_dev(c, c->c_nchild.p, zero.data(), nroot);
+        to_dev(c, c->c_prefix.p, z64.data(), nroot);
     }
-    int32_t total = 1;
+    int32_t total = nroot;
     for (int L = 0; L < kMaxLevel + 1; L++) {
         int32_t c0 = c->lvl[L], c1 = total;
         int32_t m = c1 - c0;
@@ -357,7 +426,7 @@ void build_tree_impl(fmm_ctx c, int64_t n, int dtype, const void* x, const void*
     if (c->lvl.back() != total) c->lvl.push_back(total);
     need<int4>(c, c->c_geo, total);
     need<double4>(c, c->c_ctr, total);
-    cell_geometry(cells_of(c), total, c->lo[0], c->lo[1], c->lo[2], c->side, s);
+    cell_geometry(cells_of(c), total, (const int64_t*)c->d_seg.p, nseg, (const Frame*)c->d_frame.p, s);
     check_launch("geometry");
     // leaves in cell order
     uint32_t* flag = need<uint32_t>(c, c->tmp1, total + 1);
@@ -376,6 +445,13 @@ void build_tree_impl(fmm_ctx c, int64_t n, int dtype, const void* x, const void*
     c->nleaf = (int32_t)hh[0];
     mark(c, PH_TRAV);
     c->built = true;
+}
+
+void build_tree_impl(fmm_ctx c, int64_t n, int dtype, const void* x, const void* y, const void* z,
+                     const void* q, int32_t ncrit) {
+    if (n < 0 || n >= ((int64_t)1 << 31)) fail(FMM_ERR_INVALID_ARG, "n out of range");
+    const int64_t seg[2] = {0, n};
+    build_forest_impl(c, 1, seg, dtype, x, y, z, q, ncrit);
 }
 
 // ------------------------------------------------------------------ traverse
@@ -453,19 +529,21 @@ void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
     CellArrays ca = cells_of(c);
     void* ws = c->ws.p;
     double* d6 = (double*)c->small.p;
-    int64_t nf = 0;
-    int2* fr = need<int2>(c, c->fr0, 1024);
-    if (nc == 1) {
-        // the root is a leaf: one particle-particle interaction with itself
-        int2* r = need<int2>(c, c->raw[2], 1);
-        int2 h2 = make_int2(0, 0);
-        to_dev(c, r, &h2, 1);
-        c->nlist[2] = 1;
-    } else {
-        int2 h2 = make_int2(0, 0);
-        to_dev(c, fr, &h2, 1);
-        nf = 1;
+    // one (root, root) pair per instance: a root that is a leaf interacts with
+    // itself directly, any other starts the frontier
+    const int32_t nr = c->nroot;
+    std::vector<int32_t> rch(nr);
+    to_host<int32_t>(c, rch.data(), c->c_nchild.p, nr);
+    std::vector<int2> self, start;
+    for (int32_t r = 0; r < nr; r++) (rch[r] == 0 ? self : start).push_back(make_int2(r, r));
+    int2* fr = need<int2>(c, c->fr0, std::max<size_t>(1024, start.size()));
+    if (!self.empty()) {
+        int2* r = need<int2>(c, c->raw[2], self.size());
+        to_dev(c, r, self.data(), self.size());
+        c->nlist[2] = (int64_t)self.size();
     }
+    if (!start.empty()) to_dev(c, fr, start.data(), start.size());
+    int64_t nf = (int64_t)start.size();
     while (nf > 0) {
         size_t need_ws = scan_ws_bytes(nf);
         if (need_ws > c->ws.cap) {
@@ -691,20 +769,44 @@ fmm_status fmm_set_stream(fmm_ctx c, void* hip_stream) {
     return guarded(c, [&] { c->stream = (hipStream_t)hip_stream; });
 }
 
+namespace {
+void build_timings(fmm_ctx c) {
+    if (c->timing && c->n > 0) {
+        ck(hipEventRecord(c->ev[PH_TRAV], c->stream), "event");
+        ck(hipEventSynchronize(c->ev[PH_TRAV]), "event sync");
+        for (int k = PH_KEYS; k < PH_TRAV; k++) {
+            float t = 0;
+            ck(hipEventElapsedTime(&t, c->ev[k], c->ev[k + 1]), "elapsed");
+            c->ms[k] = t;
+        }
+    }
+}
+}  // namespace
+
 fmm_status fmm_build_tree(fmm_ctx c, int64_t n, int dtype, const void* x, const void* y, const void* z,
                           const void* q, int32_t ncrit) {
     return guarded(c, [&] {
         build_tree_impl(c, n, dtype, x, y, z, q, ncrit);
-        if (c->timing && c->n > 0) {
-            ck(hipEventRecord(c->ev[PH_TRAV], c->stream), "event");
-            ck(hipEventSynchronize(c->ev[PH_TRAV]), "event sync");
-            for (int k = PH_KEYS; k < PH_TRAV; k++) {
-                float t = 0;
-                ck(hipEventElapsedTime(&t, c->ev[k], c->ev[k + 1]), "elapsed");
-                c->ms[k] = t;
-            }
-        }
+        build_timings(c);
     });
+}
+
+fmm_status fmm_build_tree_batch(fmm_ctx c, int32_t n_inst, const int64_t* offsets, int dtype, const void* x,
+                                const void* y, const void* z, const void* q, int32_t ncrit) {
+    return guarded(c, [&] {
+        build_forest_impl(c, n_inst, offsets, dtype, x, y, z, q, ncrit);
+        build_timings(c);
+    });
+}
+
+fmm_status fmm_evaluate_batch(fmm_ctx c, int32_t n_inst, const int64_t* offsets, int dtype, const void* x,
+                              const void* y, const void* z, const void* q, int32_t ncrit, int32_t p, double theta,
+                              int32_t policy, int32_t precision, int32_t out_dtype, void* phi, void* ex, void* ey,
+                              void* ez) {
+    fmm_status st = fmm_build_tree_batch(c, n_inst, offsets, dtype, x, y, z, q, ncrit);
+    if (st == FMM_OK) st = fmm_traverse(c, p, theta, policy);
+    if (st == FMM_OK) st = fmm_evaluate(c, precision, out_dtype, phi, ex, ey, ez);
+    return st;
 }
 
 fmm_status fmm_traverse(fmm_ctx c, int32_t p, double theta, int32_t policy) {
@@ -1118,6 +1220,20 @@ fmm_status fmm_get_bbox(fmm_ctx c, double* lo3, double* side) {
         if (!lo3 || !side) fail(FMM_ERR_INVALID_ARG, "null pointer");
         for (int d = 0; d < 3; d++) lo3[d] = c->lo[d];
         *side = c->side;
+    });
+}
+
+fmm_status fmm_get_bboxes(fmm_ctx c, int32_t n_inst, double* lo_side) {
+    return guarded(c, [&] {
+        if (!c->built) fail(FMM_ERR_STATE, "no tree");
+        if (!lo_side || n_inst < 0 || (size_t)n_inst > c->frames.size()) fail(FMM_ERR_INVALID_ARG, "bad n_inst");
+        for (int32_t k = 0; k < n_inst; k++) {
+            const Frame& f = c->frames[k];
+            lo_side[4 * k + 0] = f.lox;
+            lo_side[4 * k + 1] = f.loy;
+            lo_side[4 * k + 2] = f.loz;
+            lo_side[4 * k + 3] = f.side;
+        }
     });
 }
 

@@ -60,13 +60,25 @@ void artificial_points(int64_t n, uint64_t seed, float* x, float* y, float* z, f
 void iota_u32(uint32_t* p, int64_t n, hipStream_t s);
 
 // ------------------------------------------------------------------ tree
-// bbox: out6 = {lo x,y,z, hi x,y,z} (double), bad = count of non-finite values
-size_t bbox_ws_bytes(int64_t n);
-void bbox(const void* x, const void* y, const void* z, int dtype, int64_t n, double* out6,
-          uint32_t* bad, void* ws, hipStream_t s);
-void morton_keys(const void* x, const void* y, const void* z, int dtype, int64_t n,
-                 double lox, double loy, double loz, double scale, uint64_t* keys, uint32_t* idx,
-                 hipStream_t s);
+// A batch of independent instances: instance k owns particles [seg[k],
+// seg[k+1]) of the input (and, after the sort, of the sorted order).  Its
+// frame is its bounding cube: lower corner, side, the 21-bit quantisation
+// scale 2^21 / side and the half-grid unit side / 2^22.
+struct Frame {
+    double lox, loy, loz, side, scale, h, pad0, pad1;
+};
+// bbox: block b reduces particles [bt[2b], bt[2b+1]); instance k's blocks are
+// [pb[k], pb[k+1]); out[6k..6k+6) = {lo x,y,z, hi x,y,z}; part holds 6 doubles
+// per block; bad = count of non-finite values
+void bbox(const void* x, const void* y, const void* z, int dtype, const int64_t* bt, int nblk,
+          const int32_t* pb, int nseg, double* part, double* out, uint32_t* bad, hipStream_t s);
+// keys from each particle's instance frame; inst (may be null) = instance of particle i
+void morton_keys(const void* x, const void* y, const void* z, int dtype, int64_t n, const int64_t* seg, int nseg,
+                 const Frame* fr, uint64_t* keys, uint32_t* idx, uint32_t* inst, hipStream_t s);
+// batch sort, second pass: ik[k] = instance of the k-th key-sorted particle, iv[k] = k
+void inst_keys(const uint32_t* idx, const uint32_t* inst, int64_t n, uint32_t* ik, uint32_t* iv, hipStream_t s);
+void gather_sorted(const uint64_t* keys, const uint32_t* idx, const uint32_t* perm, int64_t n, uint64_t* keys2,
+                   uint32_t* idx2, hipStream_t s);
 void permute_points(const void* x, const void* y, const void* z, const void* q, int dtype,
                     int64_t n, const uint32_t* idx, float4* pts, hipStream_t s);
 // one level of the adaptive tree: cells [c0, c1) at level L.  nsplit[c-c0] =
@@ -76,8 +88,7 @@ void tree_count(const uint64_t* keys, CellArrays cells, int32_t c0, int32_t c1, 
 // child_off = exclusive scan of nsplit; children get ids c1 + child_off[c-c0]
 void tree_emit(const uint64_t* keys, CellArrays cells, int32_t c0, int32_t c1, int L,
                const uint32_t* nsplit, const uint32_t* child_off, hipStream_t s);
-void cell_geometry(CellArrays cells, int32_t ncell, double lox, double loy, double loz,
-                   double side, hipStream_t s);
+void cell_geometry(CellArrays cells, int32_t ncell, const int64_t* seg, int nseg, const Frame* fr, hipStream_t s);
 
 // sum over (tgt, src) pairs of n_t * n_s (both = 1) or n_t (both = 0) into *out (device)
 void pair_work(const uint32_t* tgt, const uint32_t* src, int64_t n, CellArrays cells, int both, uint64_t* out,

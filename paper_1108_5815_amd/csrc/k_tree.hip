@@ -17,13 +17,29 @@ namespace {
 
 constexpr int BB = 256;
 
+// Instance k of a batch owns input particles [seg[k], seg[k+1]) (a single
+// problem is the batch of one); the same ranges hold its particles after the
+// sort, which orders by (instance, key, input index).
+// Largest k in [0, nseg) with seg[k] <= i: the non-empty instance holding i.
+__device__ inline int seg_of(const int64_t* __restrict__ seg, int nseg, int64_t i) {
+    int lo = 0, hi = nseg;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (seg[mid] <= i) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Block b reduces particles [bt[2b], bt[2b+1]) (one instance) to part[6b..6b+6).
 template <class F>
 __global__ void k_bbox(const F* __restrict__ x, const F* __restrict__ y, const F* __restrict__ z,
-                       int64_t n, double* __restrict__ part, uint32_t* __restrict__ bad) {
+                       const int64_t* __restrict__ bt, double* __restrict__ part, uint32_t* __restrict__ bad) {
     __shared__ double red[6][BB];
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     uint32_t nb = 0;
-    for (int64_t i = (int64_t)blockIdx.x * BB + threadIdx.x; i < n; i += (int64_t)gridDim.x * BB) {
+    const int64_t i1 = bt[2 * blockIdx.x + 1];
+    for (int64_t i = bt[2 * blockIdx.x] + threadIdx.x; i < i1; i += BB) {
         double v[3] = {(double)x[i], (double)y[i], (double)z[i]};
 #pragma unroll
         for (int d = 0; d < 3; d++) {
@@ -52,12 +68,16 @@ __global__ void k_bbox(const F* __restrict__ x, const F* __restrict__ y, const F
     if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = red[threadIdx.x][0];
 }
 
-__global__ void k_bbox_final(const double* __restrict__ part, int nb, double* __restrict__ out6) {
-    int d = threadIdx.x;
-    if (d >= 6) return;
-    double v = d < 3 ? INFINITY : -INFINITY;
-    for (int b = 0; b < nb; b++) v = d < 3 ? fmin(v, part[b * 6 + d]) : fmax(v, part[b * 6 + d]);
-    out6[d] = v;
+// Instance k: min / max over its blocks [pb[k], pb[k+1]) into out[6k..6k+6).
+__global__ void k_bbox_final(const double* __restrict__ part, const int32_t* __restrict__ pb, int nseg,
+                             double* __restrict__ out) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nseg) return;
+    for (int d = 0; d < 6; d++) {
+        double v = d < 3 ? INFINITY : -INFINITY;
+        for (int b = pb[k]; b < pb[k + 1]; b++) v = d < 3 ? fmin(v, part[b * 6 + d]) : fmax(v, part[b * 6 + d]);
+        out[k * 6 + d] = v;
+    }
 }
 
 __device__ inline uint64_t spread3(uint64_t v) {
@@ -80,15 +100,38 @@ __device__ inline uint64_t quantise(double v, double lo, double scale) {
 
 template <class F>
 __global__ void k_morton(const F* __restrict__ x, const F* __restrict__ y, const F* __restrict__ z,
-                         int64_t n, double lox, double loy, double loz, double scale,
-                         uint64_t* __restrict__ keys, uint32_t* __restrict__ idx) {
+                         int64_t n, const int64_t* __restrict__ seg, int nseg, const Frame* __restrict__ fr,
+                         uint64_t* __restrict__ keys, uint32_t* __restrict__ idx, uint32_t* __restrict__ inst) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    uint64_t qx = quantise((double)x[i], lox, scale);
-    uint64_t qy = quantise((double)y[i], loy, scale);
-    uint64_t qz = quantise((double)z[i], loz, scale);
+    const int k = nseg > 1 ? seg_of(seg, nseg, i) : 0;
+    const Frame f = fr[k];
+    uint64_t qx = quantise((double)x[i], f.lox, f.scale);
+    uint64_t qy = quantise((double)y[i], f.loy, f.scale);
+    uint64_t qz = quantise((double)z[i], f.loz, f.scale);
     keys[i] = spread3(qx) | (spread3(qy) << 1) | (spread3(qz) << 2);
     idx[i] = (uint32_t)i;
+    if (inst) inst[i] = (uint32_t)k;
+}
+
+// Second, stable pass of the batch sort: (instance of the k-th key-sorted
+// particle, k), sorted by instance, gives the (instance, key, index) order.
+__global__ void k_inst_keys(const uint32_t* __restrict__ idx, const uint32_t* __restrict__ inst, int64_t n,
+                            uint32_t* __restrict__ ik, uint32_t* __restrict__ iv) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    ik[k] = inst[idx[k]];
+    iv[k] = (uint32_t)k;
+}
+
+__global__ void k_gather_sorted(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ idx,
+                                const uint32_t* __restrict__ perm, int64_t n, uint64_t* __restrict__ keys2,
+                                uint32_t* __restrict__ idx2) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const uint32_t j = perm[k];
+    keys2[k] = keys[j];
+    idx2[k] = idx[j];
 }
 
 template <class F>
@@ -164,10 +207,12 @@ __global__ void k_tree_emit(const uint64_t* __restrict__ keys, CellArrays cells,
     }
 }
 
-__global__ void k_geometry(CellArrays cells, int32_t ncell, double lox, double loy, double loz,
-                           double h) {
+__global__ void k_geometry(CellArrays cells, int32_t ncell, const int64_t* __restrict__ seg, int nseg,
+                           const Frame* __restrict__ fr) {
     int32_t c = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
     if (c >= ncell) return;
+    const Frame f = fr[nseg > 1 ? seg_of(seg, nseg, cells.begin[c]) : 0];
+    const double lox = f.lox, loy = f.loy, loz = f.loz, h = f.h;
     int L = cells.level[c];
     uint64_t pre = cells.prefix[c];
     int32_t a[3] = {0, 0, 0};
@@ -189,31 +234,39 @@ __global__ void k_geometry(CellArrays cells, int32_t ncell, double lox, double l
 
 }  // namespace
 
-size_t bbox_ws_bytes(int64_t) { return 1024 * 6 * sizeof(double) + 64; }
-
-void bbox(const void* x, const void* y, const void* z, int dtype, int64_t n, double* out6,
-          uint32_t* bad, void* ws, hipStream_t s) {
-    int nb = (int)std::min<int64_t>(1024, (n + BB - 1) / BB);
-    if (nb < 1) nb = 1;
-    double* part = (double*)ws;
+void bbox(const void* x, const void* y, const void* z, int dtype, const int64_t* bt, int nblk,
+          const int32_t* pb, int nseg, double* part, double* out, uint32_t* bad, hipStream_t s) {
     hipMemsetAsync(bad, 0, sizeof(uint32_t), s);
-    if (dtype == 1)
-        k_bbox<double><<<nb, BB, 0, s>>>((const double*)x, (const double*)y, (const double*)z, n, part, bad);
-    else
-        k_bbox<float><<<nb, BB, 0, s>>>((const float*)x, (const float*)y, (const float*)z, n, part, bad);
-    k_bbox_final<<<1, 64, 0, s>>>(part, nb, out6);
+    if (nblk > 0) {
+        if (dtype == 1)
+            k_bbox<double><<<nblk, BB, 0, s>>>((const double*)x, (const double*)y, (const double*)z, bt, part, bad);
+        else
+            k_bbox<float><<<nblk, BB, 0, s>>>((const float*)x, (const float*)y, (const float*)z, bt, part, bad);
+    }
+    k_bbox_final<<<(nseg + 63) / 64, 64, 0, s>>>(part, pb, nseg, out);
 }
 
-void morton_keys(const void* x, const void* y, const void* z, int dtype, int64_t n, double lox,
-                 double loy, double loz, double scale, uint64_t* keys, uint32_t* idx, hipStream_t s) {
+void morton_keys(const void* x, const void* y, const void* z, int dtype, int64_t n, const int64_t* seg, int nseg,
+                 const Frame* fr, uint64_t* keys, uint32_t* idx, uint32_t* inst, hipStream_t s) {
     if (n <= 0) return;
     unsigned g = (unsigned)((n + 255) / 256);
     if (dtype == 1)
-        k_morton<double><<<g, 256, 0, s>>>((const double*)x, (const double*)y, (const double*)z, n, lox,
-                                           loy, loz, scale, keys, idx);
+        k_morton<double><<<g, 256, 0, s>>>((const double*)x, (const double*)y, (const double*)z, n, seg, nseg, fr,
+                                           keys, idx, inst);
     else
-        k_morton<float><<<g, 256, 0, s>>>((const float*)x, (const float*)y, (const float*)z, n, lox, loy,
-                                          loz, scale, keys, idx);
+        k_morton<float><<<g, 256, 0, s>>>((const float*)x, (const float*)y, (const float*)z, n, seg, nseg, fr, keys,
+                                          idx, inst);
+}
+
+void inst_keys(const uint32_t* idx, const uint32_t* inst, int64_t n, uint32_t* ik, uint32_t* iv, hipStream_t s) {
+    if (n <= 0) return;
+    k_inst_keys<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(idx, inst, n, ik, iv);
+}
+
+void gather_sorted(const uint64_t* keys, const uint32_t* idx, const uint32_t* perm, int64_t n, uint64_t* keys2,
+                   uint32_t* idx2, hipStream_t s) {
+    if (n <= 0) return;
+    k_gather_sorted<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(keys, idx, perm, n, keys2, idx2);
 }
 
 void permute_points(const void* x, const void* y, const void* z, const void* q, int dtype, int64_t n,
@@ -242,11 +295,9 @@ void tree_emit(const uint64_t* keys, CellArrays cells, int32_t c0, int32_t c1, i
     k_tree_emit<<<(m + 255) / 256, 256, 0, s>>>(keys, cells, c0, c1, L, nsplit, child_off);
 }
 
-void cell_geometry(CellArrays cells, int32_t ncell, double lox, double loy, double loz, double side,
-                   hipStream_t s) {
+void cell_geometry(CellArrays cells, int32_t ncell, const int64_t* seg, int nseg, const Frame* fr, hipStream_t s) {
     if (ncell <= 0) return;
-    double h = side / 4194304.0;
-    k_geometry<<<(ncell + 255) / 256, 256, 0, s>>>(cells, ncell, lox, loy, loz, h);
+    k_geometry<<<(ncell + 255) / 256, 256, 0, s>>>(cells, ncell, seg, nseg, fr);
 }
 
 }  // namespace fmm

@@ -135,4 +135,4 @@ def batch_sizes(n_inst: int, seed: int, lo: int = 1024, hi: int = 262144):
     return sizes, kinds
 
 
-from .workloads import WORKLOADS, make_workload  # noqa: E402,F401
+from .workloads import WORKLOADS, make_batch, make_workload  # noqa: E402,F401
