@@ -87,6 +87,7 @@ def run_form(f, X, Y, Z, Q, phi, E, w, policy, precision, steps, warmup):
     work = f.work()
     return {"ms_per_step": ms, "value": n / (ms * 1e-3), "phase_ms": {k: round(v, 4) for k, v in ph.items()},
             "sizes": sizes, "m2l_split": {"batched": batched, "general": general}, "work": work,
+            "gemm_shape": f.gemm_shape(),
             "policy": POLICIES[policy], "precision": PRECISIONS[precision], "prep": prep}
 
 
@@ -166,6 +167,7 @@ def run_batch(args):
     torch.cuda.synchronize()
     res = {"ms_per_step": ms, "value": n / (ms * 1e-3), "phase_ms": {k: round(v, 4) for k, v in ph.items()},
            "sizes": f.sizes(), "m2l_split": dict(zip(("batched", "general"), f.m2l_split())), "work": f.work(),
+           "gemm_shape": f.gemm_shape(),
            "policy": POLICIES[args.policy], "precision": PRECISIONS[args.precision], "prep": prep}
     # the same instances one by one (single-instance calls, one context)
     g = FMM(0)
@@ -261,6 +263,9 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain (timed FP32) comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle legs (accuracy, CPU timing)")
     ap.add_argument("--cpu-sample", type=int, default=16384)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="before the steps, copy this many MiB with one elementwise kernel (the reference "
+                         "launch that scales hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -271,6 +276,12 @@ def main():
     import synth
     from paper_1108_5815_amd import FMM
 
+    if args.copy_probe_mib > 0:
+        a = torch.ones(args.copy_probe_mib * 262144, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        del a, b
     if synth.WORKLOADS[args.workload]["dist"] == "batch":
         run_batch(args)
         return

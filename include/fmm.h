@@ -239,6 +239,12 @@ fmm_status fmm_get_sizes(fmm_ctx ctx, int64_t *n_cells, int64_t *n_m2l, int64_t 
  * (mixed levels or offsets outside the per-octant tables).  NULL allowed. */
 fmm_status fmm_get_m2l_split(fmm_ctx ctx, int64_t *n_batched, int64_t *n_general);
 
+/* Shape of the batched same-level M2L after the last traversal: the number
+ * of GEMM tiles (targets of one octant class, 64 or 128 per tile), tiles x
+ * slots per class, and the slots actually multiplied (those used by at least
+ * one target of the tile).  NULL allowed. */
+fmm_status fmm_get_gemm_shape(fmm_ctx ctx, int64_t *tiles, int64_t *slots, int64_t *active_slots);
+
 /* Work of the last traversal's lists: particle pairs of the P2P list
  * (sum of n_t * n_s, self pairs included) and target particles of the M2P
  * list (sum of n_t).  Either pointer may be NULL. */
@@ -281,8 +287,38 @@ fmm_status fmm_get_expansions(fmm_ctx ctx, float *multipole_host, float *local_h
  * *count. */
 fmm_status fmm_get_timings(fmm_ctx ctx, double *ms_host, int32_t cap, int32_t *count);
 
-/* Enable (1) or disable (0) per-phase timing events (adds synchronisation). */
+/* Enable (1) or disable (0) per-phase timing events (adds synchronisation).
+ * With overlap on, the P2P entry is the kernel's own duration on the second
+ * stream; the phases then add up to more than the evaluation. */
 fmm_status fmm_set_timing(fmm_ctx ctx, int32_t enabled);
+
+/* Near field concurrent with the far field (1, the default): fmm_evaluate
+ * runs P2P on a second stream of the context (default priority) that forks
+ * from and joins back into the context stream, while P2M, M2M, M2L and L2L
+ * run on the context stream; 0 runs everything in order on the context
+ * stream.  Results are identical either way. */
+fmm_status fmm_set_overlap(fmm_ctx ctx, int32_t on);
+
+/*
+ * Autotuner for tile shapes and schedule, on the context's current tree and
+ * lists (e.g. the batch about to be evaluated repeatedly).  Leaves fall in
+ * four size classes (at most 8, 16, 32 or more particles); for each class it
+ * times the P2P kernel with 1, 2 and 4 targets per lane (`reps` launches
+ * each, events on the context stream) and keeps the fastest, then times
+ * fmm_evaluate at `precision` with the near field concurrent and in order and
+ * keeps the faster schedule.  The schedule does not change results; the
+ * tile shape changes how each target's P2P sum is split into FP32 partials,
+ * so results move by rounding only (each choice is itself deterministic).
+ * Requires a completed traversal.  Default before tuning: 4 targets per lane,
+ * concurrent.
+ */
+fmm_status fmm_autotune(fmm_ctx ctx, int32_t precision, int32_t reps);
+
+/* The tile shapes in use (p2p_tpl[4], host) and the schedule (*overlap);
+ * either pointer may be NULL.  fmm_set_tile_config sets the shapes (each 1, 2
+ * or 4). */
+fmm_status fmm_get_tile_config(fmm_ctx ctx, int32_t *p2p_tpl, int32_t *overlap);
+fmm_status fmm_set_tile_config(fmm_ctx ctx, const int32_t *p2p_tpl);
 
 #ifdef __cplusplus
 }

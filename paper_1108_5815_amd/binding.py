@@ -70,12 +70,17 @@ def lib():
         "fmm_get_bbox": ([vp, vp, vp], ctypes.c_int),
         "fmm_get_m2l_split": ([vp, vp, vp], ctypes.c_int),
         "fmm_get_work": ([vp, vp, vp], ctypes.c_int),
+        "fmm_get_gemm_shape": ([vp, vp, vp, vp], ctypes.c_int),
         "fmm_get_keys": ([vp, vp, vp], ctypes.c_int),
         "fmm_get_cells": ([vp] + [vp] * 9, ctypes.c_int),
         "fmm_get_list": ([vp, i32, vp, vp], ctypes.c_int),
         "fmm_get_expansions": ([vp, vp, vp], ctypes.c_int),
         "fmm_get_timings": ([vp, vp, i32, vp], ctypes.c_int),
         "fmm_set_timing": ([vp, i32], ctypes.c_int),
+        "fmm_set_overlap": ([vp, i32], ctypes.c_int),
+        "fmm_autotune": ([vp, i32, i32], ctypes.c_int),
+        "fmm_get_tile_config": ([vp, vp, vp], ctypes.c_int),
+        "fmm_set_tile_config": ([vp, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -269,6 +274,24 @@ class FMM:
     def set_timing(self, on: bool):
         self._ck(lib().fmm_set_timing(self.h, 1 if on else 0))
 
+    def set_overlap(self, on: bool):
+        self._ck(lib().fmm_set_overlap(self.h, 1 if on else 0))
+
+    def autotune(self, precision: int = PREC_FP32, reps: int = 3):
+        """Pick P2P tile shapes per leaf-size class and the schedule by timing."""
+        self._ck(lib().fmm_autotune(self.h, int(precision), int(reps)))
+        return self.tile_config()
+
+    def tile_config(self) -> dict:
+        tpl = np.zeros(4, np.int32)
+        ov = ctypes.c_int32()
+        self._ck(lib().fmm_get_tile_config(self.h, _ptr(tpl), ctypes.byref(ov)))
+        return {"p2p_targets_per_lane": tpl.tolist(), "overlap": bool(ov.value)}
+
+    def set_tile_config(self, tpl):
+        a = np.ascontiguousarray(np.asarray(tpl, dtype=np.int32))
+        self._ck(lib().fmm_set_tile_config(self.h, _ptr(a)))
+
     # ------------------------------------------------------------ introspection
     def sizes(self):
         v = [ctypes.c_int64() for _ in range(4)]
@@ -279,6 +302,11 @@ class FMM:
         a, b = ctypes.c_int64(), ctypes.c_int64()
         self._ck(lib().fmm_get_m2l_split(self.h, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
+
+    def gemm_shape(self) -> dict:
+        t, sl, a = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        self._ck(lib().fmm_get_gemm_shape(self.h, ctypes.byref(t), ctypes.byref(sl), ctypes.byref(a)))
+        return {"tiles": t.value, "slots": sl.value, "active_slots": a.value}
 
     def work(self):
         a, b = ctypes.c_int64(), ctypes.c_int64()

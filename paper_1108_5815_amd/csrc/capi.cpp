@@ -47,6 +47,11 @@ struct fmm_ctx_s {
     hipEvent_t ev[PH_N + 1] = {};
     double ms[PH_N] = {};
 
+    // near field on a second stream, concurrent with the far-field chain
+    bool overlap = true;
+    hipStream_t s2 = nullptr;
+    hipEvent_t e_fork = nullptr, e_join = nullptr, e_p2p0 = nullptr, e_p2p1 = nullptr;
+
     // particles and tree
     int64_t n = 0;
     int dtype = 0;
@@ -58,6 +63,10 @@ struct fmm_ctx_s {
     std::vector<Frame> frames;
     int32_t nroot = 0;
     Buf d_seg, d_bt, d_pb, d_box, d_frame, inst, bsort;
+    // leaves grouped by P2P size class, and the tile shape (targets per lane) of each class
+    Buf leaves_cls, lkey, lval, lkey2, lval2;
+    int32_t leaf_cls[kLeafClasses + 1] = {};
+    int p2p_tpl[kLeafClasses] = {4, 4, 4, 4};
     int32_t ncell = 0, nleaf = 0;
     std::vector<int32_t> lvl;  // cells of level L: [lvl[L], lvl[L+1])
     Buf keys, keys2, idx, idx2, pts, ws, small;
@@ -78,7 +87,7 @@ struct fmm_ctx_s {
     M2LPlan plan;
     Buf d_slot, d_offid, d_T, d_Thi, d_Tlo;
     bool plan_bf16 = false;
-    Buf has_fast, rkey, rval, rkey2, rval2, rowof, gather, general, gtg, gsr, goff;
+    Buf has_fast, rkey, rval, rkey2, rval2, rowof, gather, general, gtg, gsr, goff, tact, tnact;
     bool m2l_sorted = false;
     GemmPlan gp{};
     int ntiles = 0;
@@ -102,7 +111,7 @@ struct fmm_ctx_s {
     Buf M, L, nearb;
 
     // kernel pre-calculation inputs/outputs
-    Buf tune_pts, tune_out;
+    Buf tune_pts, tune_out, at_out;
 
     // pinned host staging
     void* host = nullptr;
@@ -115,7 +124,8 @@ struct fmm_ctx_s {
                       &rkey, &rval, &rkey2, &rval2, &rowof, &gather, &general, &gtg, &gsr, &goff, &d_m2m, &d_l2l, &d_w, &d_g,
                       &d_h, &d_rc, &d_mlp, &M, &L, &nearb, &tune_pts, &tune_out, &d_mlp_m, &d_mlp_v,
                       &d_grad, &d_grad_rec, &d_loss_rec, &d_feat, &d_kind, &d_tgt, &d_table, &d_Thi, &d_Tlo,
-                      &d_seg, &d_bt, &d_pb, &d_box, &d_frame, &inst, &bsort};
+                      &d_seg, &d_bt, &d_pb, &d_box, &d_frame, &inst, &bsort, &tact, &tnact,
+                      &leaves_cls, &lkey, &lval, &lkey2, &lval2, &at_out};
         for (Buf* b : all) bufs.push_back(b);
     }
 };
@@ -443,6 +453,28 @@ void build_forest_impl(fmm_ctx c, int32_t nseg, const int64_t* hseg, int dtype, 
     uint32_t* hh = (uint32_t*)host_stage(c);
     to_host<uint32_t>(c, hh, d6 + 12, 1);
     c->nleaf = (int32_t)hh[0];
+    {
+        // leaves grouped by P2P size class (cell order within a class)
+        const int32_t nl = c->nleaf;
+        uint32_t* lk = need<uint32_t>(c, c->lkey, nl);
+        uint32_t* lvv = need<uint32_t>(c, c->lval, nl);
+        uint32_t* lk2 = need<uint32_t>(c, c->lkey2, nl);
+        uint32_t* lv2 = need<uint32_t>(c, c->lval2, nl);
+        if (sort_ws_bytes(nl) > c->ws.cap) {
+            ws = need<char>(c, c->ws, sort_ws_bytes(nl));
+            d6 = (double*)c->small.p;
+        }
+        leaf_class_keys(cells_of(c), lv, nl, lk, lvv, s);
+        sort_u32(lk, lvv, lk2, lv2, nl, 0, 8, ws, s);
+        int32_t* d9 = (int32_t*)(d6 + 20);
+        class_bounds(lk, nl, d9, s);
+        check_launch("leaf classes");
+        int32_t h9[9];
+        to_host<int32_t>(c, h9, d9, 9);
+        for (int k = 0; k <= kLeafClasses; k++) c->leaf_cls[k] = h9[k];
+        int32_t* lc = need<int32_t>(c, c->leaves_cls, nl);
+        ck(hipMemcpyAsync(lc, lvv, (size_t)nl * sizeof(int32_t), hipMemcpyDeviceToDevice, s), "copy");
+    }
     mark(c, PH_TRAV);
     c->built = true;
 }
@@ -639,6 +671,12 @@ void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
         fill_i32(ga, -1, c->nrows * J, s);
         m2l_fill_gather(tg0, sr0, nm, ca, (int32_t*)c->d_slot.p, R, ro, J, ga, gen, s);
         check_launch("m2l gather");
+        int32_t* act = need<int32_t>(c, c->tact, (size_t)std::max(tiles, 1) * J);
+        int32_t* nact = need<int32_t>(c, c->tnact, (size_t)std::max(tiles, 1));
+        c->gp.act = act;
+        c->gp.nact = nact;
+        tile_slots(ga, c->gp, tc, tiles, act, nact, s);
+        check_launch("m2l tile slots");
     } else if (nm > 0) {
         fill_i32((int32_t*)gen, 1, nm, s);
     }
@@ -662,6 +700,17 @@ void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
     c->traversed = true;
 }
 
+// P2P over the leaves of each size class with that class's tile shape
+void run_p2p(fmm_ctx c, double4* near, hipStream_t st) {
+    for (int k = 0; k < kLeafClasses; k++) {
+        const int32_t b = c->leaf_cls[k], e = c->leaf_cls[k + 1];
+        if (e <= b) continue;
+        p2p((float4*)c->pts.p, cells_of(c), (int32_t*)c->leaves_cls.p + b, e - b, (int32_t*)c->off[2].p,
+            (uint32_t*)c->src[2].p, c->dtype == FMM_F64 ? 1 : 0, c->p2p_tpl[k], near, st);
+    }
+    check_launch("p2p");
+}
+
 // ------------------------------------------------------------------ evaluate
 void evaluate_impl(fmm_ctx c, int32_t precision, int32_t out_dtype, void* phi, void* ex, void* ey, void* ez) {
     if (!c->traversed) fail(FMM_ERR_STATE, "fmm_evaluate before fmm_traverse");
@@ -681,6 +730,23 @@ void evaluate_impl(fmm_ctx c, int32_t precision, int32_t out_dtype, void* phi, v
     float* M = need<float>(c, c->M, (size_t)nc * KP);
     float* L = need<float>(c, c->L, (size_t)nc * KP);
     double4* nr = need<double4>(c, c->nearb, c->n);
+    // P2P depends only on the tree and its list: with overlap on it runs on
+    // the second stream while the expansions are formed and translated, and
+    // the final sum waits for it
+    const bool ovl = c->overlap && c->nleaf > 0;
+    if (ovl) {
+        if (!c->s2) {
+            ck(hipStreamCreateWithFlags(&c->s2, hipStreamNonBlocking), "hipStreamCreate");
+            for (hipEvent_t* e : {&c->e_fork, &c->e_join, &c->e_p2p0, &c->e_p2p1})
+                ck(hipEventCreate(e), "hipEventCreate");
+        }
+        ck(hipEventRecord(c->e_fork, s), "event");
+        ck(hipStreamWaitEvent(c->s2, c->e_fork, 0), "wait");
+        if (c->timing) ck(hipEventRecord(c->e_p2p0, c->s2), "event");
+        run_p2p(c, nr, c->s2);
+        if (c->timing) ck(hipEventRecord(c->e_p2p1, c->s2), "event");
+        ck(hipEventRecord(c->e_join, c->s2), "event");
+    }
     mark(c, PH_UP);
     p2m((float4*)c->pts.p, ca, (int32_t*)c->leaves.p, c->nleaf, p, KP, tb.rcoef, M, s);
     int nlev = (int)c->lvl.size() - 1;
@@ -704,9 +770,11 @@ void evaluate_impl(fmm_ctx c, int32_t precision, int32_t out_dtype, void* phi, v
     for (int Lv = 1; Lv < nlev; Lv++) l2l(ca, c->lvl[Lv], c->lvl[Lv + 1], p, KP, tb, L, s);
     check_launch("downward");
     mark(c, PH_P2P);
-    p2p((float4*)c->pts.p, ca, (int32_t*)c->leaves.p, c->nleaf, (int32_t*)c->off[2].p, (uint32_t*)c->src[2].p,
-        c->dtype == FMM_F64 ? 1 : 0, nr, s);
-    check_launch("p2p");
+    if (ovl) {
+        ck(hipStreamWaitEvent(s, c->e_join, 0), "wait");
+    } else {
+        run_p2p(c, nr, s);
+    }
     mark(c, PH_FAR);
     far_final((float4*)c->pts.p, (uint32_t*)c->idx.p, ca, (int32_t*)c->leaves.p, c->nleaf, (int32_t*)c->off[1].p,
               (uint32_t*)c->src[1].p, p, KP, tb, M, L, nr, out_dtype, phi, ex, ey, ez, s);
@@ -718,6 +786,12 @@ void evaluate_impl(fmm_ctx c, int32_t precision, int32_t out_dtype, void* phi, v
             float t = 0;
             ck(hipEventElapsedTime(&t, c->ev[k], c->ev[k + 1]), "elapsed");
             c->ms[k] = t;
+        }
+        if (ovl) {
+            // the P2P kernel's own duration on the second stream
+            float t = 0;
+            ck(hipEventElapsedTime(&t, c->e_p2p0, c->e_p2p1), "elapsed");
+            c->ms[PH_P2P] = t;
         }
     }
 }
@@ -759,6 +833,12 @@ void fmm_destroy(fmm_ctx c) {
         if (b->p) (void)hipFree(b->p);
     for (int k = 0; k <= PH_N; k++)
         if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
+    if (c->s2) {
+        (void)hipStreamSynchronize(c->s2);
+        (void)hipStreamDestroy(c->s2);
+    }
+    for (hipEvent_t e : {c->e_fork, c->e_join, c->e_p2p0, c->e_p2p1})
+        if (e) (void)hipEventDestroy(e);
     if (c->host) (void)hipHostFree(c->host);
     delete c;
 }
@@ -875,6 +955,7 @@ fmm_status fmm_tune(fmm_ctx c, int32_t p, int32_t precision) {
             ~Del() { fmm_destroy(t); }
         } del{t};
         t->timing = true;
+        t->overlap = false;  // each kernel timed alone
         double tm[2][PH_N] = {};
         int64_t units[3] = {0, 0, 0};
         for (int pol = 0; pol < 2; pol++) {
@@ -945,6 +1026,7 @@ static void gen_records(fmm_ctx c, int p, double theta, int precision, uint64_t 
         ~Del() { fmm_destroy(t); }
     } del{t};
     t->timing = true;
+    t->overlap = false;  // each kernel timed alone
     // measured log2 ns per cell pair, per leaf size: same-level M2L, mixed-level
     // M2L, M2P, P2P (NaN = not measured)
     const int pers[] = {2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096};
@@ -1223,6 +1305,22 @@ fmm_status fmm_get_bbox(fmm_ctx c, double* lo3, double* side) {
     });
 }
 
+fmm_status fmm_get_gemm_shape(fmm_ctx c, int64_t* tiles, int64_t* slots, int64_t* active_slots) {
+    return guarded(c, [&] {
+        if (!c->traversed) fail(FMM_ERR_STATE, "no traversal");
+        const int64_t nt = c->gemm_on ? c->ntiles : 0;
+        int64_t a = 0;
+        if (nt > 0) {
+            std::vector<int32_t> h(nt);
+            to_host<int32_t>(c, h.data(), c->tnact.p, nt);
+            for (int32_t v : h) a += v;
+        }
+        if (tiles) *tiles = nt;
+        if (slots) *slots = nt * (c->gemm_on ? c->gp.J : 0);
+        if (active_slots) *active_slots = a;
+    });
+}
+
 fmm_status fmm_get_bboxes(fmm_ctx c, int32_t n_inst, double* lo_side) {
     return guarded(c, [&] {
         if (!c->built) fail(FMM_ERR_STATE, "no tree");
@@ -1320,6 +1418,85 @@ fmm_status fmm_get_timings(fmm_ctx c, double* ms, int32_t cap, int32_t* count) {
         for (int i = 0; i < k; i++) ms[i] = c->ms[i];
         if (count) *count = k;
     });
+}
+
+fmm_status fmm_autotune(fmm_ctx c, int32_t precision, int32_t reps) {
+    return guarded(c, [&] {
+        if (!c->traversed) fail(FMM_ERR_STATE, "fmm_autotune before fmm_traverse");
+        if (c->n == 0) return;
+        reps = std::max(1, std::min(reps, 1000));
+        hipStream_t s = c->stream;
+        struct Ev {
+            hipEvent_t a = nullptr, b = nullptr;
+            ~Ev() {
+                if (a) (void)hipEventDestroy(a);
+                if (b) (void)hipEventDestroy(b);
+            }
+        } ev;
+        ck(hipEventCreate(&ev.a), "hipEventCreate");
+        ck(hipEventCreate(&ev.b), "hipEventCreate");
+        auto timed = [&](auto&& work) {
+            work();
+            ck(hipEventRecord(ev.a, s), "event");
+            for (int r = 0; r < reps; r++) work();
+            ck(hipEventRecord(ev.b, s), "event");
+            ck(hipEventSynchronize(ev.b), "event sync");
+            float t = 0;
+            ck(hipEventElapsedTime(&t, ev.a, ev.b), "elapsed");
+            return (double)t / reps;
+        };
+        // tile shape per leaf-size class: targets per lane of the P2P kernel
+        double4* nr = need<double4>(c, c->nearb, c->n);
+        for (int k = 0; k < kLeafClasses; k++) {
+            const int32_t b = c->leaf_cls[k], e = c->leaf_cls[k + 1];
+            if (e <= b) continue;
+            double best = INFINITY;
+            for (int tpl : {1, 2, 4}) {
+                double t = timed([&] {
+                    p2p((float4*)c->pts.p, cells_of(c), (int32_t*)c->leaves_cls.p + b, e - b, (int32_t*)c->off[2].p,
+                        (uint32_t*)c->src[2].p, c->dtype == FMM_F64 ? 1 : 0, tpl, nr, s);
+                    check_launch("p2p");
+                });
+                if (t < best) {
+                    best = t;
+                    c->p2p_tpl[k] = tpl;
+                }
+            }
+        }
+        // schedule: P2P concurrent with the far field, or everything in order
+        float* o = need<float>(c, c->at_out, (size_t)4 * c->n);
+        const bool timing = c->timing;
+        c->timing = false;
+        double tb[2];
+        for (int ov = 0; ov < 2; ov++) {
+            c->overlap = ov == 1;
+            tb[ov] = timed([&] { evaluate_impl(c, precision, FMM_F32, o, o + c->n, o + 2 * c->n, o + 3 * c->n); });
+        }
+        c->timing = timing;
+        c->overlap = tb[1] <= tb[0];
+    });
+}
+
+fmm_status fmm_get_tile_config(fmm_ctx c, int32_t* p2p_tpl, int32_t* overlap) {
+    return guarded(c, [&] {
+        if (p2p_tpl)
+            for (int k = 0; k < kLeafClasses; k++) p2p_tpl[k] = c->p2p_tpl[k];
+        if (overlap) *overlap = c->overlap ? 1 : 0;
+    });
+}
+
+fmm_status fmm_set_tile_config(fmm_ctx c, const int32_t* p2p_tpl) {
+    return guarded(c, [&] {
+        if (!p2p_tpl) fail(FMM_ERR_INVALID_ARG, "null pointer");
+        for (int k = 0; k < kLeafClasses; k++)
+            if (p2p_tpl[k] != 1 && p2p_tpl[k] != 2 && p2p_tpl[k] != 4)
+                fail(FMM_ERR_INVALID_ARG, "targets per lane must be 1, 2 or 4");
+        for (int k = 0; k < kLeafClasses; k++) c->p2p_tpl[k] = p2p_tpl[k];
+    });
+}
+
+fmm_status fmm_set_overlap(fmm_ctx c, int32_t on) {
+    return guarded(c, [&] { c->overlap = on != 0; });
 }
 
 fmm_status fmm_set_timing(fmm_ctx c, int32_t enabled) {

@@ -175,15 +175,24 @@ void far_final(const float4* pts, const uint32_t* perm, CellArrays cells, const 
                Tables t, const float* M, const float* L, const double4* near, int out_dtype,
                void* phi, void* ex, void* ey, void* ez, hipStream_t s);
 void p2p(const float4* pts, CellArrays cells, const int32_t* leaves, int32_t nleaves,
-         const int32_t* p2p_off, const uint32_t* p2p_src, int guard_all, double4* near,
+         const int32_t* p2p_off, const uint32_t* p2p_src, int guard_all, int tpl, double4* near,
          hipStream_t s);
+// P2P size class of each leaf (0: <= 8, 1: <= 16, 2: <= 32, 3: more targets), val = the leaf's cell
+void leaf_class_keys(CellArrays cells, const int32_t* leaves, int32_t nleaf, uint32_t* key, uint32_t* val,
+                     hipStream_t s);
+constexpr int kLeafClasses = 4;
 
 // same-level M2L on MFMA: L[rowcell[r]] = sum_j T[offid[class][j]] * M[gather[r][j]]
 struct GemmPlan {
     int32_t class_row0[9];   // rows of class c: [class_row0[c], class_row0[c+1])
     int32_t class_tile0[9];  // first tile of class c
     int32_t J;               // slots per class
+    const int32_t* act;      // per tile: the slots some row uses ([tile][J], in slot order)
+    const int32_t* nact;     // per tile: how many
 };
+// act[tile * J + k], k < nact[tile]: the slots of tile `tile` that some row uses
+void tile_slots(const int32_t* gather, GemmPlan plan, int NT, int ntiles, int32_t* act, int32_t* nact,
+                hipStream_t s);
 void m2l_gemm(const float* T, const int32_t* offid, const int32_t* gather, const uint32_t* rowcell,
               GemmPlan plan, int p, int KP, const float* M, float* L, int ntiles, int precision,
               hipStream_t s);

@@ -54,6 +54,10 @@ __global__ __launch_bounds__(256) void k_m2l_bf16(const uint4* __restrict__ Thi,
     const int l32 = lane & 31, h = lane >> 5;
     const int wr = w % RW, wc = w / RW;
     const int32_t* oid = offid + (size_t)cls * J;
+    // the slots that some row of the tile uses (at least one for every tile)
+    const int32_t* act = plan.act + (size_t)tile * J;
+    const int na = plan.nact[tile];
+    if (na <= 0) return;
 
     floatx16 acc[NRB][NCB];
 #pragma unroll
@@ -64,7 +68,8 @@ __global__ __launch_bounds__(256) void k_m2l_bf16(const uint4* __restrict__ Thi,
             for (int r = 0; r < 16; r++) acc[i][b][r] = 0.f;
 
     float4 breg[BV];
-    auto load_B = [&](int j) {
+    auto load_B = [&](int k) {
+        const int j = act[k];
 #pragma unroll
         for (int v = 0; v < BV; v++) {
             int idx = threadIdx.x + 256 * v;
@@ -98,8 +103,8 @@ __global__ __launch_bounds__(256) void k_m2l_bf16(const uint4* __restrict__ Thi,
     // operator fragments of one slot: step s, half h -> K block 2s + h
     constexpr int NA = DBA ? 2 : 1;
     uint4 ah[NA][NRB][KS], al[NA][NRB][KS];
-    auto load_A = [&](int j, int buf) {
-        const size_t base = (size_t)oid[j] * KB * KP;
+    auto load_A = [&](int k, int buf) {
+        const size_t base = (size_t)oid[act[k]] * KB * KP;
 #pragma unroll
         for (int i = 0; i < NRB; i++)
 #pragma unroll
@@ -137,29 +142,29 @@ __global__ __launch_bounds__(256) void k_m2l_bf16(const uint4* __restrict__ Thi,
     __syncthreads();
     if constexpr (DBA) {
         // operator fragments of the next slot load while this slot computes
-        for (int j = 0; j < J; j += 2) {
-            if (j + 1 < J) {
-                load_B(j + 1);
-                load_A(j + 1, 1);
+        for (int k = 0; k < na; k += 2) {
+            if (k + 1 < na) {
+                load_B(k + 1);
+                load_A(k + 1, 1);
             }
             compute(0, 0);
-            if (j + 1 < J) store_B(1);
+            if (k + 1 < na) store_B(1);
             __syncthreads();
-            if (j + 1 >= J) break;
-            if (j + 2 < J) {
-                load_B(j + 2);
-                load_A(j + 2, 0);
+            if (k + 1 >= na) break;
+            if (k + 2 < na) {
+                load_B(k + 2);
+                load_A(k + 2, 0);
             }
             compute(1, 1);
-            if (j + 2 < J) store_B(0);
+            if (k + 2 < na) store_B(0);
             __syncthreads();
         }
     } else {
-        for (int j = 0; j < J; j++) {
-            if (j > 0) load_A(j, 0);
-            if (j + 1 < J) load_B(j + 1);
-            compute(j & 1, 0);
-            if (j + 1 < J) store_B((j & 1) ^ 1);
+        for (int k = 0; k < na; k++) {
+            if (k > 0) load_A(k, 0);
+            if (k + 1 < na) load_B(k + 1);
+            compute(k & 1, 0);
+            if (k + 1 < na) store_B((k & 1) ^ 1);
             __syncthreads();
         }
     }

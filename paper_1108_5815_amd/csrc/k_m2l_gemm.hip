@@ -54,6 +54,10 @@ __global__ __launch_bounds__(256) void k_m2l_gemm(const float* __restrict__ T, c
     const int l32 = lane & 31, h = lane >> 5;
     const int wr = w % RW, wc = w / RW;
     const int32_t* oid = offid + (size_t)cls * J;
+    // the slots that some row of the tile uses (at least one for every tile)
+    const int32_t* act = plan.act + (size_t)tile * J;
+    const int na = plan.nact[tile];
+    if (na <= 0) return;
 
     floatx16 acc[NRB][NCB];
 #pragma unroll
@@ -64,7 +68,8 @@ __global__ __launch_bounds__(256) void k_m2l_gemm(const float* __restrict__ T, c
             for (int r = 0; r < 16; r++) acc[i][b][r] = 0.f;
 
     float4 breg[BV];
-    auto load_B = [&](int j) {
+    auto load_B = [&](int k) {
+        const int j = act[k];
 #pragma unroll
         for (int v = 0; v < BV; v++) {
             int idx = threadIdx.x + 256 * v;
@@ -113,14 +118,14 @@ __global__ __launch_bounds__(256) void k_m2l_gemm(const float* __restrict__ T, c
 
     load_B(0);
     store_B(0);
-    load_A(T + (size_t)oid[0] * KP * KP, 0, a0);
+    load_A(T + (size_t)oid[act[0]] * KP * KP, 0, a0);
     __syncthreads();
-    for (int j = 0; j < J; j++) {
-        const int buf = j & 1;
-        const bool more = j + 1 < J;
-        if (more) load_B(j + 1);
-        const float* Aj = T + (size_t)oid[j] * KP * KP;
-        const float* An = T + (size_t)oid[more ? j + 1 : j] * KP * KP;
+    for (int k = 0; k < na; k++) {
+        const int buf = k & 1;
+        const bool more = k + 1 < na;
+        if (more) load_B(k + 1);
+        const float* Aj = T + (size_t)oid[act[k]] * KP * KP;
+        const float* An = T + (size_t)oid[act[more ? k + 1 : k]] * KP * KP;
         // chunk pipeline: chunk c computes from the register set loaded one chunk earlier
 #pragma unroll
         for (int c = 0; c < NCH; c++) {

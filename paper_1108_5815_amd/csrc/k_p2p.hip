@@ -18,6 +18,9 @@
 // adds the chunk's partial into FP64 per-target sums; the groups are summed
 // in group order at the end, so results do not depend on timing.
 //
+// TPL (1, 2 or 4) is a tile shape chosen per leaf-size class by the
+// library's autotuner; leaves are launched grouped by class.
+//
 // Only the leaf's own cell (or every cell for FP64 input, where distinct
 // points may round to one FP32 point) needs the r = 0 guard: it is staged as
 // a chunk of its own and left out of the stream.
@@ -26,9 +29,6 @@
 namespace fmm {
 namespace {
 
-#ifndef FMM_P2P_TPL
-#define FMM_P2P_TPL 4     // targets per lane
-#endif
 
 template <bool GUARD>
 __device__ inline void interact(const float3 P, const float4 Q, float4& f) {
@@ -214,15 +214,42 @@ __global__ __launch_bounds__(64) void k_p2p(const float4* __restrict__ pts, Cell
     }
 }
 
+// P2P size class of a leaf: at most 8, 16, 32 or more targets
+__global__ void k_leaf_class(CellArrays c, const int32_t* __restrict__ leaves, int32_t nleaf,
+                             uint32_t* __restrict__ key, uint32_t* __restrict__ val) {
+    int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= nleaf) return;
+    const int32_t cell = leaves[i];
+    const int32_t nt = c.end[cell] - c.begin[cell];
+    key[i] = nt <= 8 ? 0u : nt <= 16 ? 1u : nt <= 32 ? 2u : 3u;
+    val[i] = (uint32_t)cell;
+}
+
+template <int TPL>
+void launch(const float4* pts, CellArrays cells, const int32_t* leaves, int32_t nleaves, const int32_t* off,
+            const uint32_t* src, int guard_all, double4* near, hipStream_t s) {
+    if (guard_all)
+        k_p2p<TPL, true><<<nleaves, 64, 0, s>>>(pts, cells, leaves, off, src, near);
+    else
+        k_p2p<TPL, false><<<nleaves, 64, 0, s>>>(pts, cells, leaves, off, src, near);
+}
+
 }  // namespace
 
+void leaf_class_keys(CellArrays cells, const int32_t* leaves, int32_t nleaf, uint32_t* key, uint32_t* val,
+                     hipStream_t s) {
+    if (nleaf <= 0) return;
+    k_leaf_class<<<(nleaf + 255) / 256, 256, 0, s>>>(cells, leaves, nleaf, key, val);
+}
+
 void p2p(const float4* pts, CellArrays cells, const int32_t* leaves, int32_t nleaves, const int32_t* p2p_off,
-         const uint32_t* p2p_src, int guard_all, double4* near, hipStream_t s) {
+         const uint32_t* p2p_src, int guard_all, int tpl, double4* near, hipStream_t s) {
     if (nleaves <= 0) return;
-    if (guard_all)
-        k_p2p<FMM_P2P_TPL, true><<<nleaves, 64, 0, s>>>(pts, cells, leaves, p2p_off, p2p_src, near);
-    else
-        k_p2p<FMM_P2P_TPL, false><<<nleaves, 64, 0, s>>>(pts, cells, leaves, p2p_off, p2p_src, near);
+    switch (tpl) {
+        case 1: launch<1>(pts, cells, leaves, nleaves, p2p_off, p2p_src, guard_all, near, s); break;
+        case 2: launch<2>(pts, cells, leaves, nleaves, p2p_off, p2p_src, guard_all, near, s); break;
+        default: launch<4>(pts, cells, leaves, nleaves, p2p_off, p2p_src, guard_all, near, s); break;
+    }
 }
 
 }  // namespace fmm

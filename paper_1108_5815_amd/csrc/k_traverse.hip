@@ -182,6 +182,39 @@ __global__ void k_rows_inverse(const uint32_t* __restrict__ rowcell, int64_t nro
     rowof[rowcell[r]] = (int32_t)r;
 }
 
+// Active slots of each GEMM tile (NT consecutive rows of one octant class):
+// the slots at which at least one row of the tile has a same-level source, in
+// slot order.  The GEMM runs over these only; a slot no row uses would add a
+// zero column block.
+__global__ __launch_bounds__(256) void k_tile_slots(const int32_t* __restrict__ gather, GemmPlan plan, int NT,
+                                                    int32_t* __restrict__ act, int32_t* __restrict__ nact) {
+    __shared__ int32_t wtot[4];
+    const int tile = blockIdx.x;
+    int cls = 0;
+    while (cls < 7 && tile >= plan.class_tile0[cls + 1]) cls++;
+    const int r0 = plan.class_row0[cls] + (tile - plan.class_tile0[cls]) * NT;
+    const int nrow = min(NT, plan.class_row0[cls + 1] - r0);
+    const int J = plan.J;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    int base = 0;
+    for (int j0 = 0; j0 < J; j0 += 256) {
+        const int j = j0 + (int)threadIdx.x;
+        bool a = false;
+        if (j < J)
+            for (int r = 0; r < nrow && !a; r++) a = gather[(size_t)(r0 + r) * J + j] >= 0;
+        const uint64_t m = __ballot(a);
+        if (lane == 0) wtot[w] = __popcll(m);
+        __syncthreads();
+        int off = base;
+        for (int q = 0; q < w; q++) off += wtot[q];
+        if (a) act[(size_t)tile * J + off + __popcll(m & below)] = j;
+        base += wtot[0] + wtot[1] + wtot[2] + wtot[3];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) nact[tile] = base;
+}
+
 inline unsigned grid(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
@@ -212,6 +245,12 @@ void m2l_mark_targets(const uint32_t* tgt, const uint32_t* src, int64_t n, CellA
                       const int32_t* slot_of, int R, uint32_t* has_fast, hipStream_t s) {
     if (n <= 0) return;
     k_mark_targets<<<grid(n), 256, 0, s>>>(tgt, src, n, cells, slot_of, R, has_fast);
+}
+
+void tile_slots(const int32_t* gather, GemmPlan plan, int NT, int ntiles, int32_t* act, int32_t* nact,
+                hipStream_t s) {
+    if (ntiles <= 0) return;
+    k_tile_slots<<<ntiles, 256, 0, s>>>(gather, plan, NT, act, nact);
 }
 
 void m2l_fill_gather(const uint32_t* tgt, const uint32_t* src, int64_t n, CellArrays cells,

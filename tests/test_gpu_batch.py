@@ -192,3 +192,26 @@ def test_full_batch256_p8_sampled():
         g.traverse(8, 0.5, 0)
         p1, _ = g.evaluate()
         assert np.array_equal(phi[b:e], p1.double().cpu().numpy()), k
+
+
+def test_autotune_choices_and_accuracy():
+    """The autotuner picks a tile shape per leaf-size class and a schedule; the
+    tuned evaluation stays within the parity bar of the oracle."""
+    from paper_1108_5815_amd import FMM
+    x, y, z, q, off, kinds, tg, w = synth.make_batch("batch256_p8", n_inst=10)
+    x, y, z, q = (f32(a) for a in (x, y, z, q))
+    f = FMM(0)
+    f.build_tree_batch(off, dev(x), dev(y), dev(z), dev(q), 64)
+    f.traverse(8, 0.5, 0)
+    cfg = f.autotune(0, reps=2)
+    assert all(t in (1, 2, 4) for t in cfg["p2p_targets_per_lane"])
+    phi, E = f.evaluate(out_dtype=torch.float64)
+    phi, E = phi.cpu().numpy(), E.cpu().numpy().T
+    for k in (1, 4):
+        b, e = int(off[k]), int(off[k + 1])
+        po, Eo, _ = ora.fmm(x[b:e], y[b:e], z[b:e], q[b:e], 8, 0.5, 64)
+        assert ora.rel_l2(phi[b:e], po) < 1e-5 and ora.rel_l2(E[b:e], Eo) < 1e-4
+    for tpl in ([1, 1, 1, 1], [2, 2, 2, 2], [4, 4, 4, 4]):
+        f.set_tile_config(tpl)
+        p2, _ = f.evaluate(out_dtype=torch.float64)
+        assert ora.rel_l2(p2.cpu().numpy(), phi) < 1e-6
