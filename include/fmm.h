@@ -292,12 +292,13 @@ fmm_status fmm_get_timings(fmm_ctx ctx, double *ms_host, int32_t cap, int32_t *c
  * stream; the phases then add up to more than the evaluation. */
 fmm_status fmm_set_timing(fmm_ctx ctx, int32_t enabled);
 
-/* Near field concurrent with the far field (1, the default): fmm_evaluate
- * runs P2P on a second stream of the context (default priority) that forks
- * from and joins back into the context stream, while P2M, M2M, M2L and L2L
- * run on the context stream; 0 runs everything in order on the context
- * stream.  Results are identical either way. */
-fmm_status fmm_set_overlap(fmm_ctx ctx, int32_t on);
+/* Schedule of the near field: 0 runs every kernel in order on the context
+ * stream; 1 runs P2P on a second stream of the context (default priority)
+ * forked at the start of fmm_evaluate; 2 (the default) forks it after the
+ * upward pass, so that it overlaps the M2L and L2L kernels.  The second
+ * stream joins back into the context stream before the final sum.  Results
+ * are identical under every schedule. */
+fmm_status fmm_set_overlap(fmm_ctx ctx, int32_t schedule);
 
 /*
  * Autotuner for tile shapes and schedule, on the context's current tree and
@@ -305,16 +306,17 @@ fmm_status fmm_set_overlap(fmm_ctx ctx, int32_t on);
  * four size classes (at most 8, 16, 32 or more particles); for each class it
  * times the P2P kernel with 1, 2 and 4 targets per lane (`reps` launches
  * each, events on the context stream) and keeps the fastest, then times
- * fmm_evaluate at `precision` with the near field concurrent and in order and
- * keeps the faster schedule.  The schedule does not change results; the
+ * fmm_evaluate at `precision` under the three schedules of fmm_set_overlap
+ * and keeps the fastest.  The schedule does not change results; the
  * tile shape changes how each target's P2P sum is split into FP32 partials,
  * so results move by rounding only (each choice is itself deterministic).
  * Requires a completed traversal.  Default before tuning: 4 targets per lane,
- * concurrent.
+ * schedule 2.
  */
 fmm_status fmm_autotune(fmm_ctx ctx, int32_t precision, int32_t reps);
 
-/* The tile shapes in use (p2p_tpl[4], host) and the schedule (*overlap);
+/* The tile shapes in use (p2p_tpl[4], host) and the schedule (*overlap, as
+ * fmm_set_overlap);
  * either pointer may be NULL.  fmm_set_tile_config sets the shapes (each 1, 2
  * or 4). */
 fmm_status fmm_get_tile_config(fmm_ctx ctx, int32_t *p2p_tpl, int32_t *overlap);

@@ -274,8 +274,11 @@ class FMM:
     def set_timing(self, on: bool):
         self._ck(lib().fmm_set_timing(self.h, 1 if on else 0))
 
-    def set_overlap(self, on: bool):
-        self._ck(lib().fmm_set_overlap(self.h, 1 if on else 0))
+    def set_overlap(self, schedule):
+        """0 in order; 1 P2P concurrent from the start; 2 (default) P2P concurrent after the upward pass.
+        True means 2, False 0."""
+        sc = (2 if schedule else 0) if isinstance(schedule, bool) else int(schedule)
+        self._ck(lib().fmm_set_overlap(self.h, sc))
 
     def autotune(self, precision: int = PREC_FP32, reps: int = 3):
         """Pick P2P tile shapes per leaf-size class and the schedule by timing."""
@@ -286,7 +289,7 @@ class FMM:
         tpl = np.zeros(4, np.int32)
         ov = ctypes.c_int32()
         self._ck(lib().fmm_get_tile_config(self.h, _ptr(tpl), ctypes.byref(ov)))
-        return {"p2p_targets_per_lane": tpl.tolist(), "overlap": bool(ov.value)}
+        return {"p2p_targets_per_lane": tpl.tolist(), "schedule": int(ov.value)}
 
     def set_tile_config(self, tpl):
         a = np.ascontiguousarray(np.asarray(tpl, dtype=np.int32))

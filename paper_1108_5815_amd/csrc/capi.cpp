@@ -47,8 +47,9 @@ struct fmm_ctx_s {
     hipEvent_t ev[PH_N + 1] = {};
     double ms[PH_N] = {};
 
-    // near field on a second stream, concurrent with the far-field chain
-    bool overlap = true;
+    // near field on a second stream, concurrent with the far-field chain:
+    // 0 in order, 1 from the start of the evaluation, 2 after the upward pass
+    int schedule = 2;
     hipStream_t s2 = nullptr;
     hipEvent_t e_fork = nullptr, e_join = nullptr, e_p2p0 = nullptr, e_p2p1 = nullptr;
 
@@ -730,11 +731,12 @@ void evaluate_impl(fmm_ctx c, int32_t precision, int32_t out_dtype, void* phi, v
     float* M = need<float>(c, c->M, (size_t)nc * KP);
     float* L = need<float>(c, c->L, (size_t)nc * KP);
     double4* nr = need<double4>(c, c->nearb, c->n);
-    // P2P depends only on the tree and its list: with overlap on it runs on
-    // the second stream while the expansions are formed and translated, and
-    // the final sum waits for it
-    const bool ovl = c->overlap && c->nleaf > 0;
-    if (ovl) {
+    // P2P depends only on the tree and its list: under a concurrent schedule it
+    // runs on the second stream (forked at the start, or after the upward
+    // pass) while the expansions are formed and translated, and the final sum
+    // waits for it
+    const int sched = c->nleaf > 0 ? c->schedule : 0;
+    auto fork_p2p = [&] {
         if (!c->s2) {
             ck(hipStreamCreateWithFlags(&c->s2, hipStreamNonBlocking), "hipStreamCreate");
             for (hipEvent_t* e : {&c->e_fork, &c->e_join, &c->e_p2p0, &c->e_p2p1})
@@ -746,12 +748,14 @@ void evaluate_impl(fmm_ctx c, int32_t precision, int32_t out_dtype, void* phi, v
         run_p2p(c, nr, c->s2);
         if (c->timing) ck(hipEventRecord(c->e_p2p1, c->s2), "event");
         ck(hipEventRecord(c->e_join, c->s2), "event");
-    }
+    };
+    if (sched == 1) fork_p2p();
     mark(c, PH_UP);
     p2m((float4*)c->pts.p, ca, (int32_t*)c->leaves.p, c->nleaf, p, KP, tb.rcoef, M, s);
     int nlev = (int)c->lvl.size() - 1;
     for (int Lv = nlev - 2; Lv >= 0; Lv--) m2m(ca, c->lvl[Lv], c->lvl[Lv + 1], p, KP, tb, M, s);
     check_launch("upward");
+    if (sched == 2) fork_p2p();
     ck(hipMemsetAsync(L, 0, (size_t)nc * KP * sizeof(float), s), "memset");
     mark(c, PH_M2L);
     if (c->gemm_on && c->ntiles > 0)
@@ -770,7 +774,7 @@ void evaluate_impl(fmm_ctx c, int32_t precision, int32_t out_dtype, void* phi, v
     for (int Lv = 1; Lv < nlev; Lv++) l2l(ca, c->lvl[Lv], c->lvl[Lv + 1], p, KP, tb, L, s);
     check_launch("downward");
     mark(c, PH_P2P);
-    if (ovl) {
+    if (sched) {
         ck(hipStreamWaitEvent(s, c->e_join, 0), "wait");
     } else {
         run_p2p(c, nr, s);
@@ -787,7 +791,7 @@ void evaluate_impl(fmm_ctx c, int32_t precision, int32_t out_dtype, void* phi, v
             ck(hipEventElapsedTime(&t, c->ev[k], c->ev[k + 1]), "elapsed");
             c->ms[k] = t;
         }
-        if (ovl) {
+        if (sched) {
             // the P2P kernel's own duration on the second stream
             float t = 0;
             ck(hipEventElapsedTime(&t, c->e_p2p0, c->e_p2p1), "elapsed");
@@ -955,7 +959,7 @@ fmm_status fmm_tune(fmm_ctx c, int32_t p, int32_t precision) {
             ~Del() { fmm_destroy(t); }
         } del{t};
         t->timing = true;
-        t->overlap = false;  // each kernel timed alone
+        t->schedule = 0;  // each kernel timed alone
         double tm[2][PH_N] = {};
         int64_t units[3] = {0, 0, 0};
         for (int pol = 0; pol < 2; pol++) {
@@ -1026,7 +1030,7 @@ static void gen_records(fmm_ctx c, int p, double theta, int precision, uint64_t 
         ~Del() { fmm_destroy(t); }
     } del{t};
     t->timing = true;
-    t->overlap = false;  // each kernel timed alone
+    t->schedule = 0;  // each kernel timed alone
     // measured log2 ns per cell pair, per leaf size: same-level M2L, mixed-level
     // M2L, M2P, P2P (NaN = not measured)
     const int pers[] = {2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096};
@@ -1467,13 +1471,18 @@ fmm_status fmm_autotune(fmm_ctx c, int32_t precision, int32_t reps) {
         float* o = need<float>(c, c->at_out, (size_t)4 * c->n);
         const bool timing = c->timing;
         c->timing = false;
-        double tb[2];
-        for (int ov = 0; ov < 2; ov++) {
-            c->overlap = ov == 1;
-            tb[ov] = timed([&] { evaluate_impl(c, precision, FMM_F32, o, o + c->n, o + 2 * c->n, o + 3 * c->n); });
+        double best = INFINITY;
+        int pick = 0;
+        for (int sc = 0; sc < 3; sc++) {
+            c->schedule = sc;
+            double t = timed([&] { evaluate_impl(c, precision, FMM_F32, o, o + c->n, o + 2 * c->n, o + 3 * c->n); });
+            if (t < best) {
+                best = t;
+                pick = sc;
+            }
         }
         c->timing = timing;
-        c->overlap = tb[1] <= tb[0];
+        c->schedule = pick;
     });
 }
 
@@ -1481,7 +1490,7 @@ fmm_status fmm_get_tile_config(fmm_ctx c, int32_t* p2p_tpl, int32_t* overlap) {
     return guarded(c, [&] {
         if (p2p_tpl)
             for (int k = 0; k < kLeafClasses; k++) p2p_tpl[k] = c->p2p_tpl[k];
-        if (overlap) *overlap = c->overlap ? 1 : 0;
+        if (overlap) *overlap = c->schedule;
     });
 }
 
@@ -1495,8 +1504,11 @@ fmm_status fmm_set_tile_config(fmm_ctx c, const int32_t* p2p_tpl) {
     });
 }
 
-fmm_status fmm_set_overlap(fmm_ctx c, int32_t on) {
-    return guarded(c, [&] { c->overlap = on != 0; });
+fmm_status fmm_set_overlap(fmm_ctx c, int32_t schedule) {
+    return guarded(c, [&] {
+        if (schedule < 0 || schedule > 2) fail(FMM_ERR_INVALID_ARG, "schedule must be 0, 1 or 2");
+        c->schedule = schedule;
+    });
 }
 
 fmm_status fmm_set_timing(fmm_ctx c, int32_t enabled) {

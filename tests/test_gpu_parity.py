@@ -244,19 +244,20 @@ def test_full_size_uniform_1m_p10_sampled():
     assert ep < 1e-5 and eE < 1e-4
 
 
-def test_overlap_off_is_identical():
-    """P2P on the second stream (default) or in order on the context stream: same bits."""
+def test_schedules_are_identical():
+    """P2P in order, or on the second stream from the start or after the upward pass: same bits."""
     from paper_1108_5815_amd import FMM
     x, y, z = synth.plummer(30000, 17)
     q = synth.charges_uniform(30000, 117)
     t = [torch.tensor(a, dtype=torch.float32, device="cuda:0") for a in (x, y, z, q)]
     out = []
-    for ovl in (True, False):
+    for sched in (0, 1, 2):
         f = FMM(0)
-        f.set_overlap(ovl)
+        f.set_overlap(sched)
         f.build_tree(*t, 32)
         f.traverse(8, 0.5, 0)
         phi, E = f.evaluate()
         torch.cuda.synchronize()
         out.append((phi.cpu().numpy(), E.cpu().numpy()))
-    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    for k in (1, 2):
+        assert np.array_equal(out[0][0], out[k][0]) and np.array_equal(out[0][1], out[k][1])
