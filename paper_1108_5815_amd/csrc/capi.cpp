@@ -88,7 +88,7 @@ struct fmm_ctx_s {
     M2LPlan plan;
     Buf d_slot, d_offid, d_T, d_Thi, d_Tlo;
     bool plan_bf16 = false;
-    Buf has_fast, rkey, rval, rkey2, rval2, rowof, gather, general, gtg, gsr, goff, tact, tnact;
+    Buf has_fast, rkey, rval, rkey2, rval2, rowof, gather, general, gtg, gsr, goff, tact, tnact, m2l_part, Msplit;
     bool m2l_sorted = false;
     GemmPlan gp{};
     int ntiles = 0;
@@ -126,7 +126,7 @@ struct fmm_ctx_s {
                       &d_h, &d_rc, &d_mlp, &M, &L, &nearb, &tune_pts, &tune_out, &d_mlp_m, &d_mlp_v,
                       &d_grad, &d_grad_rec, &d_loss_rec, &d_feat, &d_kind, &d_tgt, &d_table, &d_Thi, &d_Tlo,
                       &d_seg, &d_bt, &d_pb, &d_box, &d_frame, &inst, &bsort, &tact, &tnact,
-                      &leaves_cls, &lkey, &lval, &lkey2, &lval2, &at_out};
+                      &leaves_cls, &lkey, &lval, &lkey2, &lval2, &at_out, &m2l_part, &Msplit};
         for (Buf* b : all) bufs.push_back(b);
     }
 };
@@ -663,6 +663,9 @@ void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
             if (k < 8) tiles += (h9[k + 1] - h9[k] + tc - 1) / tc;
         }
         c->gp.J = J;
+        c->gp.G = gemm_slot_groups(J);
+        c->gp.ntiles = tiles;
+        c->gp.nrows = h9[8];
         c->ntiles = tiles;
         c->nrows = h9[8];
         int32_t* ro = need<int32_t>(c, c->rowof, nc);
@@ -728,7 +731,10 @@ void evaluate_impl(fmm_ctx c, int32_t precision, int32_t out_dtype, void* phi, v
     int32_t nc = c->ncell;
     CellArrays ca = cells_of(c);
     Tables tb = tables_of(c);
-    float* M = need<float>(c, c->M, (size_t)nc * KP);
+    // one extra, all-zero multipole row (index nc): the M2L GEMM reads it for absent sources
+    float* M = need<float>(c, c->M, (size_t)(nc + 1) * KP);
+    ck(hipMemsetAsync(M + (size_t)nc * KP, 0, (size_t)KP * sizeof(float), s), "memset");
+    c->gp.zcell = nc;
     float* L = need<float>(c, c->L, (size_t)nc * KP);
     double4* nr = need<double4>(c, c->nearb, c->n);
     // P2P depends only on the tree and its list: under a concurrent schedule it
@@ -760,12 +766,14 @@ void evaluate_impl(fmm_ctx c, int32_t precision, int32_t out_dtype, void* phi, v
     mark(c, PH_M2L);
     if (c->gemm_on && c->ntiles > 0)
     {
+        float* part = need<float>(c, c->m2l_part, (size_t)c->gp.G * c->gp.nrows * KP);
         if (precision == FMM_PREC_SPLIT_BF16)
             m2l_gemm_bf16((uint16_t*)c->d_Thi.p, (uint16_t*)c->d_Tlo.p, (int32_t*)c->d_offid.p, (int32_t*)c->gather.p,
-                          (uint32_t*)c->rval.p, c->gp, p, KP, M, L, c->ntiles, s);
+                          (uint32_t*)c->rval.p, c->gp, p, KP, M, nc, need<uint4>(c, c->Msplit, (size_t)(nc + 1) * KP / 4),
+                          part, L, s);
         else
             m2l_gemm((float*)c->d_T.p, (int32_t*)c->d_offid.p, (int32_t*)c->gather.p, (uint32_t*)c->rval.p, c->gp, p,
-                     KP, M, L, c->ntiles, precision, s);
+                     KP, M, part, L, s);
     }
     mark(c, PH_M2LG);
     if (c->ngeneral > 0) m2l_general((int32_t*)c->goff.p, (uint32_t*)c->gsr.p, ca, nc, p, KP, tb, M, L, s);

@@ -189,18 +189,29 @@ struct GemmPlan {
     int32_t J;               // slots per class
     const int32_t* act;      // per tile: the slots some row uses ([tile][J], in slot order)
     const int32_t* nact;     // per tile: how many
+    int32_t G;               // slot groups per tile (a multiple of 8: group g runs on XCD g mod 8)
+    int32_t ntiles;          // tiles
+    int32_t nrows;           // rows (targets) over all classes
+    int32_t zcell;           // a cell index whose multipole row is all zero (absent sources read it)
 };
+// slot groups for J slots per class: each group's operators (J/G blocks of
+// 64 KB at storage width 128) should stay well inside one XCD's 4 MB L2
+int gemm_slot_groups(int J);
 // act[tile * J + k], k < nact[tile]: the slots of tile `tile` that some row uses
 void tile_slots(const int32_t* gather, GemmPlan plan, int NT, int ntiles, int32_t* act, int32_t* nact,
                 hipStream_t s);
+// part: G * nrows * KP floats of per-group partial locals, summed into L in group order
 void m2l_gemm(const float* T, const int32_t* offid, const int32_t* gather, const uint32_t* rowcell,
-              GemmPlan plan, int p, int KP, const float* M, float* L, int ntiles, int precision,
-              hipStream_t s);
+              GemmPlan plan, int p, int KP, const float* M, float* part, float* L, hipStream_t s);
 bool m2l_gemm_supported(int p);
 // split-BF16 variant (Thi/Tlo: k-blocked BF16 halves of the operators)
+// Ms: scratch of ncell * KP * 4 bytes for the split multipoles
 void m2l_gemm_bf16(const uint16_t* Thi, const uint16_t* Tlo, const int32_t* offid, const int32_t* gather,
-                   const uint32_t* rowcell, GemmPlan plan, int p, int KP, const float* M, float* L, int ntiles,
-                   hipStream_t s);
+                   const uint32_t* rowcell, GemmPlan plan, int p, int KP, const float* M, int64_t ncell, uint4* Ms,
+                   float* part, float* L, hipStream_t s);
+// L[rowcell[r]][k] = sum over g in order of part[g][r][k], k < K
+void m2l_reduce_groups(const float* part, GemmPlan plan, const uint32_t* rowcell, int KP, int K, float* L,
+                       hipStream_t s);
 bool m2l_bf16_supported(int p);
 int gemm_tile_cols(int p);  // targets per GEMM tile for order p
 

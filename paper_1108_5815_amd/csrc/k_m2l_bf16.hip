@@ -1,7 +1,8 @@
 // k_m2l_bf16.hip -- same-level M2L GEMMs in split-BF16 on the matrix cores.
 //
 // The batching is that of k_m2l_gemm.hip (one octant class and a tile of
-// targets per workgroup, K running over (slot, coefficient)).  Here every
+// targets per workgroup, K running over (slot, coefficient); the slots of a
+// tile cut into XCD-local groups whose partials are summed in group order).  Here every
 // FP32 operand a is split into a_hi = bf16(a) and a_lo = bf16(a - a_hi)
 // (round to nearest even), and each product is formed from three BF16
 // products on v_mfma_f32_32x32x16_bf16 with FP32 accumulation:
@@ -9,14 +10,19 @@
 // The dropped a_lo b_lo term and the residual of the two-term split bound
 // the relative error of each product by about 2^-16.  The operators are split
 // once on the host and stored k-blocked ([offset][KP/8][KP][8] bf16) so that
-// a lane's 8 consecutive K values for its row are one 16-byte load; the
-// gathered source vectors are split when staged into LDS.
+// a lane's 8 consecutive K values for its row are one 16-byte load.  The
+// multipoles are split once per evaluation (k_split_cells: [cell][hi, lo]
+// [KP/8] blocks of 8 bf16), so staging a gathered source vector into LDS is a
+// plain copy.
 #include "fmm_internal.h"
 
 namespace fmm {
 namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+// 16 bytes as a native vector (copies stay in registers; HIP's uint4 struct
+// copies can be lowered through private memory)
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 __device__ inline uint16_t bf16_rne(float x) {
@@ -27,24 +33,32 @@ __device__ inline uint16_t bf16_rne(float x) {
 
 __device__ inline float bf16_to_f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
+// work item of block b: b = (h * ntiles + tile) * 8 + x, group g = x + 8 h
+__device__ inline void gemm_item(const GemmPlan& plan, int& tile, int& g) {
+    const unsigned b = blockIdx.x;
+    const unsigned rest = b >> 3;
+    tile = (int)(rest % (unsigned)plan.ntiles);
+    g = (int)(b & 7u) + 8 * (int)(rest / (unsigned)plan.ntiles);
+}
+
 template <int KP, int NT, int RW, int CW, bool DBA>
 __global__ __launch_bounds__(256) void k_m2l_bf16(const uint4* __restrict__ Thi, const uint4* __restrict__ Tlo,
                                                   const int32_t* __restrict__ offid,
-                                                  const int32_t* __restrict__ gather,
-                                                  const uint32_t* __restrict__ rowcell, GemmPlan plan, int K,
-                                                  const float* __restrict__ M, float* __restrict__ L) {
+                                                  const int32_t* __restrict__ gather, GemmPlan plan,
+                                                  const uint4* __restrict__ Ms, float* __restrict__ part) {
     constexpr int KB = KP / 8;          // 8-wide K blocks
     constexpr int KS = KP / 16;         // MFMA K steps (16 values each)
     constexpr int RB = KP / 32, CB = NT / 32;
     static_assert(RB % RW == 0 && CB % CW == 0 && RW * CW == 4, "wave grid");
     constexpr int NRB = RB / RW, NCB = CB / CW;
     constexpr int STR = KB + 1;         // LDS row stride in 16-byte units
-    constexpr int BV = NT * KP / 1024;  // float4 per thread per source tile
-    static_assert((NT * KP) % 1024 == 0, "tile shape");
-    __shared__ uint4 Bhi[2][NT * STR];
-    __shared__ uint4 Blo[2][NT * STR];
+    constexpr int BV = NT * 2 * KB / 256;  // 16-byte blocks per thread per source tile (hi and lo)
+    static_assert((NT * 2 * KB) % 256 == 0, "tile shape");
+    __shared__ u32x4 Bhi[2][NT * STR];
+    __shared__ u32x4 Blo[2][NT * STR];
 
-    const int tile = blockIdx.x;
+    int tile, g;
+    gemm_item(plan, tile, g);
     int cls = 0;
     while (cls < 7 && tile >= plan.class_tile0[cls + 1]) cls++;
     const int r0 = plan.class_row0[cls] + (tile - plan.class_tile0[cls]) * NT;
@@ -54,10 +68,10 @@ __global__ __launch_bounds__(256) void k_m2l_bf16(const uint4* __restrict__ Thi,
     const int l32 = lane & 31, h = lane >> 5;
     const int wr = w % RW, wc = w / RW;
     const int32_t* oid = offid + (size_t)cls * J;
-    // the slots that some row of the tile uses (at least one for every tile)
+    // this group's share of the slots some row of the tile uses
     const int32_t* act = plan.act + (size_t)tile * J;
     const int na = plan.nact[tile];
-    if (na <= 0) return;
+    const int k0 = (int)(((int64_t)g * na) / plan.G), k1 = (int)(((int64_t)(g + 1) * na) / plan.G);
 
     floatx16 acc[NRB][NCB];
 #pragma unroll
@@ -67,42 +81,37 @@ __global__ __launch_bounds__(256) void k_m2l_bf16(const uint4* __restrict__ Thi,
 #pragma unroll
             for (int r = 0; r < 16; r++) acc[i][b][r] = 0.f;
 
-    float4 breg[BV];
+    u32x4 breg[BV];
+    // gathered sources of slot k: all index loads first, then unconditional
+    // data loads (absent sources read the zero row), so they overlap
     auto load_B = [&](int k) {
         const int j = act[k];
+        int sidx[BV];
 #pragma unroll
         for (int v = 0; v < BV; v++) {
-            int idx = threadIdx.x + 256 * v;
-            int col = idx / (KP / 4), k4 = idx - col * (KP / 4);
-            int s = col < nrow ? gather[(size_t)(r0 + col) * J + j] : -1;
-            breg[v] = s >= 0 ? reinterpret_cast<const float4*>(M + (size_t)s * KP)[k4]
-                             : make_float4(0.f, 0.f, 0.f, 0.f);
+            const int col = (threadIdx.x + 256 * v) / (2 * KB);
+            sidx[v] = gather[(size_t)(r0 + min(col, nrow - 1)) * J + j];
+        }
+#pragma unroll
+        for (int v = 0; v < BV; v++) {
+            const int idx = threadIdx.x + 256 * v;
+            const int col = idx / (2 * KB), rem = idx - col * (2 * KB);
+            const int s = (col < nrow && sidx[v] >= 0) ? sidx[v] : plan.zcell;
+            breg[v] = reinterpret_cast<const u32x4*>(Ms)[(size_t)s * 2 * KB + rem];
         }
     };
-    // each thread holds 4 consecutive K values of one column: half a 16-byte block
     auto store_B = [&](int buf) {
 #pragma unroll
         for (int v = 0; v < BV; v++) {
-            int idx = threadIdx.x + 256 * v;
-            int col = idx / (KP / 4), k4 = idx - col * (KP / 4);
-            float xs[4] = {breg[v].x, breg[v].y, breg[v].z, breg[v].w};
-            uint16_t hi[4], lo[4];
-#pragma unroll
-            for (int e = 0; e < 4; e++) {
-                hi[e] = bf16_rne(xs[e]);
-                lo[e] = bf16_rne(xs[e] - bf16_to_f(hi[e]));
-            }
-            uint2 ph = make_uint2((uint32_t)hi[0] | ((uint32_t)hi[1] << 16), (uint32_t)hi[2] | ((uint32_t)hi[3] << 16));
-            uint2 pl = make_uint2((uint32_t)lo[0] | ((uint32_t)lo[1] << 16), (uint32_t)lo[2] | ((uint32_t)lo[3] << 16));
-            uint2* dh = reinterpret_cast<uint2*>(&Bhi[buf][col * STR + (k4 >> 1)]) + (k4 & 1);
-            uint2* dl = reinterpret_cast<uint2*>(&Blo[buf][col * STR + (k4 >> 1)]) + (k4 & 1);
-            *dh = ph;
-            *dl = pl;
+            const int idx = threadIdx.x + 256 * v;
+            const int col = idx / (2 * KB), rem = idx - col * (2 * KB);
+            if (rem < KB) Bhi[buf][col * STR + rem] = breg[v];
+            else Blo[buf][col * STR + rem - KB] = breg[v];
         }
     };
     // operator fragments of one slot: step s, half h -> K block 2s + h
     constexpr int NA = DBA ? 2 : 1;
-    uint4 ah[NA][NRB][KS], al[NA][NRB][KS];
+    u32x4 ah[NA][NRB][KS], al[NA][NRB][KS];
     auto load_A = [&](int k, int buf) {
         const size_t base = (size_t)oid[act[k]] * KB * KP;
 #pragma unroll
@@ -110,8 +119,8 @@ __global__ __launch_bounds__(256) void k_m2l_bf16(const uint4* __restrict__ Thi,
 #pragma unroll
             for (int s = 0; s < KS; s++) {
                 const size_t ix = base + (size_t)(2 * s + h) * KP + (wr + RW * i) * 32 + l32;
-                ah[buf][i][s] = Thi[ix];
-                al[buf][i][s] = Tlo[ix];
+                ah[buf][i][s] = reinterpret_cast<const u32x4*>(Thi)[ix];
+                al[buf][i][s] = reinterpret_cast<const u32x4*>(Tlo)[ix];
             }
     };
     auto compute = [&](int bbuf, int abuf) {
@@ -120,8 +129,8 @@ __global__ __launch_bounds__(256) void k_m2l_bf16(const uint4* __restrict__ Thi,
 #pragma unroll
             for (int b = 0; b < NCB; b++) {
                 const int col = (wc + CW * b) * 32 + l32;
-                const uint4 bh = Bhi[bbuf][col * STR + 2 * s + h];
-                const uint4 bl = Blo[bbuf][col * STR + 2 * s + h];
+                const u32x4 bh = Bhi[bbuf][col * STR + 2 * s + h];
+                const u32x4 bl = Blo[bbuf][col * STR + 2 * s + h];
                 const bf16x8 vbh = __builtin_bit_cast(bf16x8, bh);
                 const bf16x8 vbl = __builtin_bit_cast(bf16x8, bl);
 #pragma unroll
@@ -136,74 +145,101 @@ __global__ __launch_bounds__(256) void k_m2l_bf16(const uint4* __restrict__ Thi,
         }
     };
 
-    load_B(0);
-    store_B(0);
-    load_A(0, 0);
-    __syncthreads();
-    if constexpr (DBA) {
-        // operator fragments of the next slot load while this slot computes
-        for (int k = 0; k < na; k += 2) {
-            if (k + 1 < na) {
-                load_B(k + 1);
-                load_A(k + 1, 1);
+    if (k1 > k0) {
+        load_B(k0);
+        store_B(0);
+        load_A(k0, 0);
+        __syncthreads();
+        if constexpr (DBA) {
+            // operator fragments of the next slot load while this slot computes
+            for (int k = k0; k < k1; k += 2) {
+                if (k + 1 < k1) {
+                    load_B(k + 1);
+                    load_A(k + 1, 1);
+                }
+                compute(0, 0);
+                if (k + 1 < k1) store_B(1);
+                __syncthreads();
+                if (k + 1 >= k1) break;
+                if (k + 2 < k1) {
+                    load_B(k + 2);
+                    load_A(k + 2, 0);
+                }
+                compute(1, 1);
+                if (k + 2 < k1) store_B(0);
+                __syncthreads();
             }
-            compute(0, 0);
-            if (k + 1 < na) store_B(1);
-            __syncthreads();
-            if (k + 1 >= na) break;
-            if (k + 2 < na) {
-                load_B(k + 2);
-                load_A(k + 2, 0);
+        } else {
+            for (int k = k0; k < k1; k++) {
+                if (k > k0) load_A(k, 0);
+                if (k + 1 < k1) load_B(k + 1);
+                compute((k - k0) & 1, 0);
+                if (k + 1 < k1) store_B(((k - k0) & 1) ^ 1);
+                __syncthreads();
             }
-            compute(1, 1);
-            if (k + 2 < na) store_B(0);
-            __syncthreads();
-        }
-    } else {
-        for (int k = 0; k < na; k++) {
-            if (k > 0) load_A(k, 0);
-            if (k + 1 < na) load_B(k + 1);
-            compute(k & 1, 0);
-            if (k + 1 < na) store_B((k & 1) ^ 1);
-            __syncthreads();
         }
     }
+    // partial locals of this group (zero when it has no slots)
 #pragma unroll
     for (int b = 0; b < NCB; b++) {
         int col = (wc + CW * b) * 32 + l32;
         if (col >= nrow) continue;
-        size_t base = (size_t)rowcell[r0 + col] * KP;
+        float* dst = part + ((size_t)g * plan.nrows + r0 + col) * KP;
 #pragma unroll
         for (int i = 0; i < NRB; i++)
 #pragma unroll
-            for (int r = 0; r < 16; r++) {
-                int row = (wr + RW * i) * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-                if (row < K) L[base + row] = acc[i][b][r];
-            }
+            for (int r = 0; r < 16; r++) dst[(wr + RW * i) * 32 + 8 * (r >> 2) + 4 * h + (r & 3)] = acc[i][b][r];
     }
 }
 
 template <int KP, int NT, int RW, int CW, bool DBA>
-void launch(const uint16_t* Thi, const uint16_t* Tlo, const int32_t* offid, const int32_t* gather,
-            const uint32_t* rowcell, GemmPlan plan, int K, const float* M, float* L, int ntiles, hipStream_t s) {
-    k_m2l_bf16<KP, NT, RW, CW, DBA><<<ntiles, 256, 0, s>>>((const uint4*)Thi, (const uint4*)Tlo, offid, gather, rowcell,
-                                                     plan, K, M, L);
+void launch(const uint16_t* Thi, const uint16_t* Tlo, const int32_t* offid, const int32_t* gather, GemmPlan plan,
+            const uint4* Ms, float* part, hipStream_t s) {
+    k_m2l_bf16<KP, NT, RW, CW, DBA><<<plan.ntiles * plan.G, 256, 0, s>>>((const uint4*)Thi, (const uint4*)Tlo, offid,
+                                                                         gather, plan, Ms, part);
+}
+
+// Multipoles of every cell split into bf16 hi and lo: Ms[cell][0][kb] = hi of
+// coefficients 8 kb .. 8 kb + 7, Ms[cell][1][kb] = lo (round to nearest even).
+__global__ void k_split_cells(const float4* __restrict__ M, int64_t ncell, int KB, uint4* __restrict__ Ms) {
+    // ncell rows including the trailing zero row
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ncell * KB) return;
+    const int64_t c = i / KB;
+    const int kb = (int)(i - c * KB);
+    const float4 a = M[2 * i], b = M[2 * i + 1];
+    const float x[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+    uint16_t hi[8], lo[8];
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+        hi[e] = bf16_rne(x[e]);
+        lo[e] = bf16_rne(x[e] - bf16_to_f(hi[e]));
+    }
+    auto pack = [](const uint16_t* v) {
+        return make_uint4((uint32_t)v[0] | ((uint32_t)v[1] << 16), (uint32_t)v[2] | ((uint32_t)v[3] << 16),
+                          (uint32_t)v[4] | ((uint32_t)v[5] << 16), (uint32_t)v[6] | ((uint32_t)v[7] << 16));
+    };
+    Ms[c * 2 * KB + kb] = pack(hi);
+    Ms[c * 2 * KB + KB + kb] = pack(lo);
 }
 
 }  // namespace
 
 void m2l_gemm_bf16(const uint16_t* Thi, const uint16_t* Tlo, const int32_t* offid, const int32_t* gather,
-                   const uint32_t* rowcell, GemmPlan plan, int p, int KP, const float* M, float* L, int ntiles,
-                   hipStream_t s) {
-    if (ntiles <= 0) return;
-    int K = ncoef(p);
+                   const uint32_t* rowcell, GemmPlan plan, int p, int KP, const float* M, int64_t ncell, uint4* Ms,
+                   float* part, float* L, hipStream_t s) {
+    if (plan.ntiles <= 0) return;
+    const int KB = KP / 8;
+    const int64_t nb = (ncell + 1) * KB;  // with the zero row
+    k_split_cells<<<(unsigned)((nb + 255) / 256), 256, 0, s>>>((const float4*)M, ncell + 1, KB, Ms);
     switch (KP) {
-        case 32: launch<32, 128, 1, 4, true>(Thi, Tlo, offid, gather, rowcell, plan, K, M, L, ntiles, s); break;
-        case 64: launch<64, 128, 2, 2, true>(Thi, Tlo, offid, gather, rowcell, plan, K, M, L, ntiles, s); break;
-        case 96: launch<96, 128, 1, 4, false>(Thi, Tlo, offid, gather, rowcell, plan, K, M, L, ntiles, s); break;
-        case 128: launch<128, 64, 4, 1, true>(Thi, Tlo, offid, gather, rowcell, plan, K, M, L, ntiles, s); break;
-        default: break;
+        case 32: launch<32, 128, 1, 4, true>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
+        case 64: launch<64, 128, 2, 2, true>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
+        case 96: launch<96, 128, 1, 4, false>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
+        case 128: launch<128, 64, 4, 1, false>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
+        default: return;
     }
+    m2l_reduce_groups(part, plan, rowcell, KP, ncoef(p), L, s);
 }
 
 bool m2l_bf16_supported(int p) {

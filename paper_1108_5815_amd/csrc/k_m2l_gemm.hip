@@ -12,6 +12,16 @@
 // sources are zero columns.  Each workgroup owns its tile's outputs, so the
 // sum over slots is done in registers, with no atomics, in slot order.
 //
+// Slot groups (XCD-aware): the operators of one class take J x 64 KB at
+// storage width 128 (36 MB at theta = 0.4), far more than one XCD's 4 MB L2,
+// and tiles that run at the same time drift apart in slot, so streaming every
+// slot through every tile makes each operator block an L2 miss.  Instead the
+// active slots of a tile are cut into G groups (G a multiple of 8) and work
+// item (tile, group g) runs on XCD g mod 8 (workgroups are dealt to the 8
+// XCDs round robin by block index): each XCD then touches only its own slice
+// of the operators, which stays in its L2.  Each item writes its partial
+// locals to part[g][row]; m2l_reduce_groups sums the groups in order.
+//
 // Tiling (gfx950, wave64, v_mfma_f32_32x32x2f32): a 256-lane workgroup owns
 // KP x NT outputs split over a RW x CW grid of waves; each wave keeps
 // NRB x NCB 32x32 accumulator blocks.  The K index of step s, half h of the
@@ -21,18 +31,30 @@
 // pipeline one 16-step chunk ahead; the next slot's 64 or 128 gathered source
 // vectors are loaded into registers during the current slot and written to
 // the other half of a double-buffered LDS tile.
+#include <algorithm>
+
 #include "fmm_internal.h"
 
 namespace fmm {
 namespace {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+// 16 bytes as a native vector (copies stay in registers; HIP's float4 struct
+// copies can be lowered through private memory)
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// work item of block b: b = (h * ntiles + tile) * 8 + x, group g = x + 8 h
+__device__ inline void gemm_item(const GemmPlan& plan, int& tile, int& g) {
+    const unsigned b = blockIdx.x;
+    const unsigned rest = b >> 3;
+    tile = (int)(rest % (unsigned)plan.ntiles);
+    g = (int)(b & 7u) + 8 * (int)(rest / (unsigned)plan.ntiles);
+}
 
 template <int KP, int NT, int RW, int CW>
 __global__ __launch_bounds__(256) void k_m2l_gemm(const float* __restrict__ T, const int32_t* __restrict__ offid,
-                                                  const int32_t* __restrict__ gather,
-                                                  const uint32_t* __restrict__ rowcell, GemmPlan plan, int K,
-                                                  const float* __restrict__ M, float* __restrict__ L) {
+                                                  const int32_t* __restrict__ gather, GemmPlan plan,
+                                                  const float* __restrict__ M, float* __restrict__ part) {
     constexpr int KS = KP / 2;
     constexpr int RB = KP / 32, CB = NT / 32;
     static_assert(RB % RW == 0 && CB % CW == 0 && RW * CW == 4, "wave grid");
@@ -44,7 +66,8 @@ __global__ __launch_bounds__(256) void k_m2l_gemm(const float* __restrict__ T, c
     static_assert(KS % CH == 0 && (NT * KP) % 1024 == 0, "tile shape");
     __shared__ __attribute__((aligned(16))) float Bs[2][NT * STR];
 
-    const int tile = blockIdx.x;
+    int tile, g;
+    gemm_item(plan, tile, g);
     int cls = 0;
     while (cls < 7 && tile >= plan.class_tile0[cls + 1]) cls++;
     const int r0 = plan.class_row0[cls] + (tile - plan.class_tile0[cls]) * NT;
@@ -54,10 +77,10 @@ __global__ __launch_bounds__(256) void k_m2l_gemm(const float* __restrict__ T, c
     const int l32 = lane & 31, h = lane >> 5;
     const int wr = w % RW, wc = w / RW;
     const int32_t* oid = offid + (size_t)cls * J;
-    // the slots that some row of the tile uses (at least one for every tile)
+    // this group's share of the slots some row of the tile uses
     const int32_t* act = plan.act + (size_t)tile * J;
     const int na = plan.nact[tile];
-    if (na <= 0) return;
+    const int k0 = (int)(((int64_t)g * na) / plan.G), k1 = (int)(((int64_t)(g + 1) * na) / plan.G);
 
     floatx16 acc[NRB][NCB];
 #pragma unroll
@@ -67,16 +90,23 @@ __global__ __launch_bounds__(256) void k_m2l_gemm(const float* __restrict__ T, c
 #pragma unroll
             for (int r = 0; r < 16; r++) acc[i][b][r] = 0.f;
 
-    float4 breg[BV];
+    f32x4 breg[BV];
+    // gathered sources of slot k: all index loads first, then unconditional
+    // data loads (absent sources read the zero row), so they overlap
     auto load_B = [&](int k) {
         const int j = act[k];
+        int sidx[BV];
 #pragma unroll
         for (int v = 0; v < BV; v++) {
-            int idx = threadIdx.x + 256 * v;
-            int col = idx / (KP / 4), k4 = idx - col * (KP / 4);
-            int s = col < nrow ? gather[(size_t)(r0 + col) * J + j] : -1;
-            breg[v] = s >= 0 ? reinterpret_cast<const float4*>(M + (size_t)s * KP)[k4]
-                             : make_float4(0.f, 0.f, 0.f, 0.f);
+            const int col = (threadIdx.x + 256 * v) / (KP / 4);
+            sidx[v] = gather[(size_t)(r0 + min(col, nrow - 1)) * J + j];
+        }
+#pragma unroll
+        for (int v = 0; v < BV; v++) {
+            const int idx = threadIdx.x + 256 * v;
+            const int col = idx / (KP / 4), k4 = idx - col * (KP / 4);
+            const int s = (col < nrow && sidx[v] >= 0) ? sidx[v] : plan.zcell;
+            breg[v] = reinterpret_cast<const f32x4*>(M + (size_t)s * KP)[k4];
         }
     };
     auto store_B = [&](int buf) {
@@ -84,7 +114,7 @@ __global__ __launch_bounds__(256) void k_m2l_gemm(const float* __restrict__ T, c
         for (int v = 0; v < BV; v++) {
             int idx = threadIdx.x + 256 * v;
             int col = idx / (KP / 4), k4 = idx - col * (KP / 4);
-            *reinterpret_cast<float4*>(&Bs[buf][col * STR + 4 * k4]) = breg[v];
+            *reinterpret_cast<f32x4*>(&Bs[buf][col * STR + 4 * k4]) = breg[v];
         }
     };
     float a0[NRB][CH], a1[NRB][CH];
@@ -98,17 +128,17 @@ __global__ __launch_bounds__(256) void k_m2l_gemm(const float* __restrict__ T, c
     auto compute = [&](int buf, int c, const float (&a)[NRB][CH]) {
 #pragma unroll
         for (int t = 0; t < CH; t += 4) {
-            float4 b4[NCB];
+            f32x4 b4[NCB];
 #pragma unroll
             for (int b = 0; b < NCB; b++) {
                 int col = (wc + CW * b) * 32 + l32;
-                b4[b] = *reinterpret_cast<const float4*>(&Bs[buf][col * STR + h * KS + c * CH + t]);
+                b4[b] = *reinterpret_cast<const f32x4*>(&Bs[buf][col * STR + h * KS + c * CH + t]);
             }
 #pragma unroll
             for (int u = 0; u < 4; u++)
 #pragma unroll
                 for (int b = 0; b < NCB; b++) {
-                    float bv = u == 0 ? b4[b].x : u == 1 ? b4[b].y : u == 2 ? b4[b].z : b4[b].w;
+                    float bv = b4[b][u];
 #pragma unroll
                     for (int i = 0; i < NRB; i++)
                         acc[i][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][t + u], bv, acc[i][b], 0, 0, 0);
@@ -116,13 +146,14 @@ __global__ __launch_bounds__(256) void k_m2l_gemm(const float* __restrict__ T, c
         }
     };
 
-    load_B(0);
+    if (k1 > k0) {
+    load_B(k0);
     store_B(0);
-    load_A(T + (size_t)oid[act[0]] * KP * KP, 0, a0);
+    load_A(T + (size_t)oid[act[k0]] * KP * KP, 0, a0);
     __syncthreads();
-    for (int k = 0; k < na; k++) {
-        const int buf = k & 1;
-        const bool more = k + 1 < na;
+    for (int k = k0; k < k1; k++) {
+        const int buf = (k - k0) & 1;
+        const bool more = k + 1 < k1;
         if (more) load_B(k + 1);
         const float* Aj = T + (size_t)oid[act[k]] * KP * KP;
         const float* An = T + (size_t)oid[act[more ? k + 1 : k]] * KP * KP;
@@ -148,25 +179,46 @@ __global__ __launch_bounds__(256) void k_m2l_gemm(const float* __restrict__ T, c
         if (more) store_B(buf ^ 1);
         __syncthreads();
     }
+    }
+    // partial locals of this group (zero when it has no slots)
 #pragma unroll
     for (int b = 0; b < NCB; b++) {
         int col = (wc + CW * b) * 32 + l32;
         if (col >= nrow) continue;
-        size_t base = (size_t)rowcell[r0 + col] * KP;
+        float* dst = part + ((size_t)g * plan.nrows + r0 + col) * KP;
 #pragma unroll
         for (int i = 0; i < NRB; i++)
 #pragma unroll
-            for (int r = 0; r < 16; r++) {
-                int row = (wr + RW * i) * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-                if (row < K) L[base + row] = acc[i][b][r];
-            }
+            for (int r = 0; r < 16; r++) dst[(wr + RW * i) * 32 + 8 * (r >> 2) + 4 * h + (r & 3)] = acc[i][b][r];
     }
 }
 
+// L[rowcell[r]][k] = sum_g part[g][r][k] for k < K, groups in order
+__global__ void k_reduce_groups(const float4* __restrict__ part, int G, int nrows, int KP4, int K,
+                                const uint32_t* __restrict__ rowcell, float* __restrict__ L) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)nrows * KP4) return;
+    const int64_t r = i / KP4;
+    const int k4 = (int)(i - r * KP4);
+    float4 s = part[i];
+    for (int g = 1; g < G; g++) {
+        const float4 v = part[(int64_t)g * nrows * KP4 + i];
+        s.x += v.x;
+        s.y += v.y;
+        s.z += v.z;
+        s.w += v.w;
+    }
+    float* dst = L + (size_t)rowcell[r] * KP4 * 4 + 4 * k4;
+    const float vals[4] = {s.x, s.y, s.z, s.w};
+#pragma unroll
+    for (int e = 0; e < 4; e++)
+        if (4 * k4 + e < K) dst[e] = vals[e];
+}
+
 template <int KP, int NT, int RW, int CW>
-void launch(const float* T, const int32_t* offid, const int32_t* gather, const uint32_t* rowcell, GemmPlan plan,
-            int K, const float* M, float* L, int ntiles, hipStream_t s) {
-    k_m2l_gemm<KP, NT, RW, CW><<<ntiles, 256, 0, s>>>(T, offid, gather, rowcell, plan, K, M, L);
+void launch(const float* T, const int32_t* offid, const int32_t* gather, GemmPlan plan, const float* M, float* part,
+            hipStream_t s) {
+    k_m2l_gemm<KP, NT, RW, CW><<<plan.ntiles * plan.G, 256, 0, s>>>(T, offid, gather, plan, M, part);
 }
 
 }  // namespace
@@ -182,20 +234,29 @@ int gemm_tile_cols(int p) {
     }
 }
 
+int gemm_slot_groups(int J) { return 8 * std::max(1, (J + 255) / 256); }
+
+void m2l_reduce_groups(const float* part, GemmPlan plan, const uint32_t* rowcell, int KP, int K, float* L,
+                       hipStream_t s) {
+    const int64_t n = (int64_t)plan.nrows * (KP / 4);
+    if (n <= 0) return;
+    k_reduce_groups<<<(unsigned)((n + 255) / 256), 256, 0, s>>>((const float4*)part, plan.G, plan.nrows, KP / 4, K,
+                                                               rowcell, L);
+}
+
 void m2l_gemm(const float* T, const int32_t* offid, const int32_t* gather, const uint32_t* rowcell, GemmPlan plan,
-              int p, int KP, const float* M, float* L, int ntiles, int precision, hipStream_t s) {
-    (void)precision;
-    if (ntiles <= 0) return;
-    int K = ncoef(p);
+              int p, int KP, const float* M, float* part, float* L, hipStream_t s) {
+    if (plan.ntiles <= 0) return;
     switch (KP) {
-        case 32: launch<32, 128, 1, 4>(T, offid, gather, rowcell, plan, K, M, L, ntiles, s); break;
-        case 64: launch<64, 128, 2, 2>(T, offid, gather, rowcell, plan, K, M, L, ntiles, s); break;
-        case 96: launch<96, 128, 1, 4>(T, offid, gather, rowcell, plan, K, M, L, ntiles, s); break;
-        case 128: launch<128, 64, 4, 1>(T, offid, gather, rowcell, plan, K, M, L, ntiles, s); break;
-        case 192: launch<192, 64, 2, 2>(T, offid, gather, rowcell, plan, K, M, L, ntiles, s); break;
-        case 256: launch<256, 64, 4, 1>(T, offid, gather, rowcell, plan, K, M, L, ntiles, s); break;
-        default: break;
+        case 32: launch<32, 128, 1, 4>(T, offid, gather, plan, M, part, s); break;
+        case 64: launch<64, 128, 2, 2>(T, offid, gather, plan, M, part, s); break;
+        case 96: launch<96, 128, 1, 4>(T, offid, gather, plan, M, part, s); break;
+        case 128: launch<128, 64, 4, 1>(T, offid, gather, plan, M, part, s); break;
+        case 192: launch<192, 64, 2, 2>(T, offid, gather, plan, M, part, s); break;
+        case 256: launch<256, 64, 4, 1>(T, offid, gather, plan, M, part, s); break;
+        default: return;
     }
+    m2l_reduce_groups(part, plan, rowcell, KP, ncoef(p), L, s);
 }
 
 }  // namespace fmm
