@@ -97,7 +97,29 @@ def run_form(f, X, Y, Z, Q, phi, E, w, policy, precision, steps, warmup):
             "policy": POLICIES[policy], "precision": PRECISIONS[precision], "prep": prep}
 
 
-def roofline(res, p, precision):
+KERNEL_SOURCES = {"k_m2l_bf16": "k_m2l_bf16.hip", "k_m2l_gemm": "k_m2l_gemm.hip", "k_p2p": "k_p2p.hip"}
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from the committed hardware-counter summary
+    (profiles/fmm_<workload>_traffic.md), or None when there is none or the
+    kernel's source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"fmm_{workload}_traffic.md")
+    if kernel not in KERNEL_SOURCES or not os.path.exists(path):
+        return None
+    src = os.path.join(ROOT, "paper_1108_5815_amd", "csrc", KERNEL_SOURCES[kernel])
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:12]
+    for line in open(path):
+        t = line.split()
+        if len(t) == 5 and t[0] == "traffic_per_launch" and t[1] == kernel:
+            kv = dict(x.split("=", 1) for x in t[2:])
+            if kv.get("workload") == workload and kv.get("sha") == sha:
+                return int(kv["bytes"])
+    return None
+
+
+def roofline(res, p, precision, workload=None):
     ph = res["phase_ms"]
     p2p_flops = 20.0 * res["work"]["p2p_particle_pairs"]
     m2l_flops = 2.0 * (p + 1) ** 4 * res["m2l_split"]["batched"]
@@ -110,7 +132,7 @@ def roofline(res, p, precision):
              "peak": peak_m2l / 1e12, "unit": "TFLOP/s", "avg_ms": ph["m2l_gemm"], "flops_per_launch": m2l_flops}
     for k in (k_p2p, k_m2l):
         k["frac"] = k["achieved"] / k["peak"]
-        k["traffic"] = None
+        k["traffic"] = measured_traffic(k["kernel"], workload) if workload else None
     dom = k_p2p if ph["p2p"] >= ph["m2l_gemm"] else k_m2l
     other = k_m2l if dom is k_p2p else k_p2p
     out = dict(dom)
@@ -226,7 +248,7 @@ def run_batch(args):
         "dtype": "f32+bf16" if args.precision == 1 else "f32", "data": "synthetic",
         "config": {"workload": args.workload, "n_inst": int(len(off) - 1), "n": n, "p": p, "theta": theta,
                    "ncrit": ncrit, "policy": res["policy"], "precision": res["precision"]},
-        "accuracy": acc, "form": res, "roofline": roofline(res, p, args.precision),
+        "accuracy": acc, "form": res, "roofline": roofline(res, p, args.precision, args.workload),
     }
     if not args.no_cpu_baseline:
         import oracle
@@ -329,7 +351,7 @@ def main():
         "accuracy": acc_main,
         "form": main_res,
         "plain": plain,
-        "roofline": roofline(main_res, p, args.precision),
+        "roofline": roofline(main_res, p, args.precision, args.workload),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.workload, args.cpu_sample)
