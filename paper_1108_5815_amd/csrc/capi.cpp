@@ -88,7 +88,7 @@ struct fmm_ctx_s {
     M2LPlan plan;
     Buf d_slot, d_offid, d_T, d_Thi, d_Tlo;
     bool plan_bf16 = false;
-    Buf has_fast, rkey, rval, rkey2, rval2, rowof, gather, general, gtg, gsr, goff, tact, tnact, m2l_part, Msplit;
+    Buf has_fast, rkey, rval, rkey2, rval2, rowof, gather, general, gtg, gsr, goff, tact, tnact, m2l_part, Msplit, nbucket, kinds;
     bool m2l_sorted = false;
     GemmPlan gp{};
     int ntiles = 0;
@@ -126,7 +126,7 @@ struct fmm_ctx_s {
                       &d_h, &d_rc, &d_mlp, &M, &L, &nearb, &tune_pts, &tune_out, &d_mlp_m, &d_mlp_v,
                       &d_grad, &d_grad_rec, &d_loss_rec, &d_feat, &d_kind, &d_tgt, &d_table, &d_Thi, &d_Tlo,
                       &d_seg, &d_bt, &d_pb, &d_box, &d_frame, &inst, &bsort, &tact, &tnact,
-                      &leaves_cls, &lkey, &lval, &lkey2, &lval2, &at_out, &m2l_part, &Msplit};
+                      &leaves_cls, &lkey, &lval, &lkey2, &lval2, &at_out, &m2l_part, &Msplit, &nbucket, &kinds};
         for (Buf* b : all) bufs.push_back(b);
     }
 };
@@ -549,6 +549,7 @@ void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
     tp.c_p2p = c->costs[2];
     tp.c_m2p = c->costs[1];
     tp.mlp_table = nullptr;
+    tp.nbucket = nullptr;
     if (policy == FMM_POLICY_HYBRID_MLP) {
         if (c->table_p != p || c->table_theta != theta || c->table_version != c->mlp_version) {
             mlp_table((const float*)c->d_mlp.p, p, (float)theta, need<uint8_t>(c, c->d_table, kMlpTable), s);
@@ -558,7 +559,13 @@ void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
             c->table_version = c->mlp_version;
         }
         tp.mlp_table = (const uint8_t*)c->d_table.p;
+        uint8_t* nb = need<uint8_t>(c, c->nbucket, nc);
+        cell_buckets(cells_of(c), nc, nb, s);
+        tp.nbucket = nb;
     }
+    // the learned policy reads both tables in every classification
+    if (policy == FMM_POLICY_HYBRID_MLP && (!tp.mlp_table || !tp.nbucket))
+        fail(FMM_ERR_STATE, "learned traversal without its choice table or count buckets");
     CellArrays ca = cells_of(c);
     void* ws = c->ws.p;
     double* d6 = (double*)c->small.p;
@@ -586,7 +593,8 @@ void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
         uint4* cnt = need<uint4>(c, c->cnt, nf);
         uint4* off = need<uint4>(c, c->off4, nf);
         fr = (int2*)c->fr0.p;
-        trav_count(fr, nf, ca, tp, cnt, s);
+        uint4* kinds = need<uint4>(c, c->kinds, nf);
+        trav_count(fr, nf, ca, tp, cnt, kinds, s);
         scan_u32x4(cnt, off, (uint4*)(d6 + 16), nf, ws, s);
         check_launch("traverse count");
         uint32_t* hh = (uint32_t*)host_stage(c);
@@ -596,7 +604,7 @@ void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
         for (int k = 0; k < 3; k++)
             lists[k] = need_keep<int2>(c, c->raw[k], c->nlist[k] + add[k] + 1, c->nlist[k]);
         int2* next = need<int2>(c, c->fr1, add[3] + 1);
-        trav_emit(fr, nf, ca, tp, off, c->nlist[0], c->nlist[1], c->nlist[2], lists[0], lists[1], lists[2],
+        trav_emit(fr, nf, ca, kinds, off, c->nlist[0], c->nlist[1], c->nlist[2], lists[0], lists[1], lists[2],
                   next, s);
         check_launch("traverse emit");
         for (int k = 0; k < 3; k++) c->nlist[k] += add[k];

@@ -117,11 +117,15 @@ struct TravParams {
     int policy;
     double c_m2l, c_m2p, c_p2p;
     const uint8_t* mlp_table;  // learned choices over the quantised feature grid, or null
+    const uint8_t* nbucket;    // per cell: quantised log2 of its particle count (learned policy)
 };
-// per frontier pair: counts of new (M2L, M2P, P2P, SPLIT) pairs
-void trav_count(const int2* frontier, int64_t nf, CellArrays cells, TravParams tp, uint4* cnt,
+// per cell: the particle-count bucket of the learned cost model's feature grid
+void cell_buckets(CellArrays cells, int32_t ncell, uint8_t* nbucket, hipStream_t s);
+// per frontier pair: counts of new (M2L, M2P, P2P, SPLIT) pairs, and the kind
+// of each child pair (2 bits each, at most 64 children, in emission order)
+void trav_count(const int2* frontier, int64_t nf, CellArrays cells, TravParams tp, uint4* cnt, uint4* kinds,
                 hipStream_t s);
-void trav_emit(const int2* frontier, int64_t nf, CellArrays cells, TravParams tp,
+void trav_emit(const int2* frontier, int64_t nf, CellArrays cells, const uint4* kinds,
                const uint4* off, int64_t base_m2l, int64_t base_m2p, int64_t base_p2p,
                int2* m2l, int2* m2p, int2* p2p, int2* next, hipStream_t s);
 void split_pairs(const int2* pairs, int64_t n, uint32_t* tgt, uint32_t* src, hipStream_t s);

@@ -9,7 +9,8 @@
 // pairs are processed.  Here every pair of the current frontier is expanded
 // at once: one pass counts the new pairs of each kind, a scan places them,
 // a second pass writes them; the order is deterministic (frontier order,
-// then child order).
+// then child order).  The counting pass records the kind of every child pair
+// (2 bits each) so the writing pass does not classify again.
 //
 // Readings fixed here and in the oracle: r = half side of the cube, R between
 // cube centres, accept iff (r_t + r_s)^2 <= theta^2 R^2 (integer half-grid
@@ -38,12 +39,10 @@ __device__ inline int classify(const CellArrays& c, int32_t t, int32_t s, const 
         double ns = (double)(c.end[s] - c.begin[s]);
         if (tp.policy == 3) {
             // learned choice, read from the network's evaluation over the
-            // quantised features of the pair
+            // quantised features of the pair (count buckets precomputed per cell)
             int dl = c.level[s] - c.level[t];
             dl = dl < -kMlpDl ? -kMlpDl : (dl > kMlpDl ? kMlpDl : dl);
-            int bt = (int)rint(kMlpNsub * log2(nt)), bs = (int)rint(kMlpNsub * log2(ns));
-            bt = bt < 0 ? 0 : (bt >= kMlpBn ? kMlpBn - 1 : bt);
-            bs = bs < 0 ? 0 : (bs >= kMlpBn ? kMlpBn - 1 : bs);
+            const int bt = tp.nbucket[t], bs = tp.nbucket[s];
             double ratio = sqrt((double)(rr * rr) / (double)R2) / tp.theta;
             int bq = (int)(ratio * kMlpBq);
             bq = bq < 0 ? 0 : (bq >= kMlpBq ? kMlpBq - 1 : bq);
@@ -74,22 +73,37 @@ __device__ inline void split_ranges(const CellArrays& c, int32_t T, int32_t S, i
     s1 = splitS ? c.child[S] + c.nchild[S] : S + 1;
 }
 
+// quantised log2 of each cell's particle count: rint(kMlpNsub log2 n) clamped to the grid
+__global__ void k_cell_buckets(CellArrays c, int32_t ncell, uint8_t* __restrict__ nb) {
+    int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= ncell) return;
+    int b = (int)rint(kMlpNsub * log2((double)(c.end[i] - c.begin[i])));
+    nb[i] = (uint8_t)(b < 0 ? 0 : (b >= kMlpBn ? kMlpBn - 1 : b));
+}
+
 __global__ void k_trav_count(const int2* __restrict__ fr, int64_t nf, CellArrays c, TravParams tp,
-                             uint4* __restrict__ cnt) {
+                             uint4* __restrict__ cnt, uint4* __restrict__ kinds) {
     int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= nf) return;
     int2 pr = fr[f];
     int32_t t0, t1, s0, s1;
     split_ranges(c, pr.x, pr.y, t0, t1, s0, s1);
     uint32_t n[4] = {0, 0, 0, 0};
+    uint32_t w[4] = {0, 0, 0, 0};
+    int q = 0;
     for (int32_t t = t0; t < t1; t++)
-        for (int32_t s = s0; s < s1; s++) n[classify(c, t, s, tp)]++;
+        for (int32_t s = s0; s < s1; s++, q++) {
+            const int k = classify(c, t, s, tp);
+            n[k]++;
+            w[q >> 4] |= (uint32_t)k << (2 * (q & 15));
+        }
     cnt[f] = make_uint4(n[0], n[1], n[2], n[3]);
+    kinds[f] = make_uint4(w[0], w[1], w[2], w[3]);
 }
 
-__global__ void k_trav_emit(const int2* __restrict__ fr, int64_t nf, CellArrays c, TravParams tp,
-                            const uint4* __restrict__ off, int64_t b0, int64_t b1, int64_t b2,
-                            int2* __restrict__ m2l, int2* __restrict__ m2p, int2* __restrict__ p2p,
+__global__ void k_trav_emit(const int2* __restrict__ fr, int64_t nf, CellArrays c,
+                            const uint4* __restrict__ kinds, const uint4* __restrict__ off, int64_t b0, int64_t b1,
+                            int64_t b2, int2* __restrict__ m2l, int2* __restrict__ m2p, int2* __restrict__ p2p,
                             int2* __restrict__ next) {
     int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= nf) return;
@@ -97,10 +111,13 @@ __global__ void k_trav_emit(const int2* __restrict__ fr, int64_t nf, CellArrays 
     int32_t t0, t1, s0, s1;
     split_ranges(c, pr.x, pr.y, t0, t1, s0, s1);
     uint4 o = off[f];
+    const uint4 kw = kinds[f];
+    const uint32_t w[4] = {kw.x, kw.y, kw.z, kw.w};
     int64_t w0 = b0 + o.x, w1 = b1 + o.y, w2 = b2 + o.z, w3 = o.w;
+    int q = 0;
     for (int32_t t = t0; t < t1; t++)
-        for (int32_t s = s0; s < s1; s++) {
-            int k = classify(c, t, s, tp);
+        for (int32_t s = s0; s < s1; s++, q++) {
+            const int k = (int)((w[q >> 4] >> (2 * (q & 15))) & 3u);
             int2 v = make_int2(t, s);
             if (k == KIND_M2L) m2l[w0++] = v;
             else if (k == KIND_M2P) m2p[w1++] = v;
@@ -219,16 +236,22 @@ inline unsigned grid(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b
 
 }  // namespace
 
-void trav_count(const int2* frontier, int64_t nf, CellArrays cells, TravParams tp, uint4* cnt, hipStream_t s) {
-    if (nf <= 0) return;
-    k_trav_count<<<grid(nf), 256, 0, s>>>(frontier, nf, cells, tp, cnt);
+void cell_buckets(CellArrays cells, int32_t ncell, uint8_t* nbucket, hipStream_t s) {
+    if (ncell <= 0) return;
+    k_cell_buckets<<<grid(ncell), 256, 0, s>>>(cells, ncell, nbucket);
 }
 
-void trav_emit(const int2* frontier, int64_t nf, CellArrays cells, TravParams tp, const uint4* off,
+void trav_count(const int2* frontier, int64_t nf, CellArrays cells, TravParams tp, uint4* cnt, uint4* kinds,
+                hipStream_t s) {
+    if (nf <= 0) return;
+    k_trav_count<<<grid(nf), 256, 0, s>>>(frontier, nf, cells, tp, cnt, kinds);
+}
+
+void trav_emit(const int2* frontier, int64_t nf, CellArrays cells, const uint4* kinds, const uint4* off,
                int64_t base_m2l, int64_t base_m2p, int64_t base_p2p, int2* m2l, int2* m2p, int2* p2p,
                int2* next, hipStream_t s) {
     if (nf <= 0) return;
-    k_trav_emit<<<grid(nf), 256, 0, s>>>(frontier, nf, cells, tp, off, base_m2l, base_m2p, base_p2p, m2l,
+    k_trav_emit<<<grid(nf), 256, 0, s>>>(frontier, nf, cells, kinds, off, base_m2l, base_m2p, base_p2p, m2l,
                                          m2p, p2p, next);
 }
 

@@ -68,16 +68,24 @@ __global__ void k_bbox(const F* __restrict__ x, const F* __restrict__ y, const F
     if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = red[threadIdx.x][0];
 }
 
-// Instance k: min / max over its blocks [pb[k], pb[k+1]) into out[6k..6k+6).
+// Instance k (one workgroup each): min / max over its blocks [pb[k], pb[k+1]) into out[6k..6k+6).
 __global__ void k_bbox_final(const double* __restrict__ part, const int32_t* __restrict__ pb, int nseg,
                              double* __restrict__ out) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nseg) return;
-    for (int d = 0; d < 6; d++) {
-        double v = d < 3 ? INFINITY : -INFINITY;
-        for (int b = pb[k]; b < pb[k + 1]; b++) v = d < 3 ? fmin(v, part[b * 6 + d]) : fmax(v, part[b * 6 + d]);
-        out[k * 6 + d] = v;
+    __shared__ double red[6][BB];
+    const int k = blockIdx.x;
+    double v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (int b = pb[k] + (int)threadIdx.x; b < pb[k + 1]; b += BB)
+        for (int d = 0; d < 6; d++) v[d] = d < 3 ? fmin(v[d], part[b * 6 + d]) : fmax(v[d], part[b * 6 + d]);
+    for (int d = 0; d < 6; d++) red[d][threadIdx.x] = v[d];
+    __syncthreads();
+    for (int st = BB / 2; st > 0; st >>= 1) {
+        if (threadIdx.x < st)
+            for (int d = 0; d < 6; d++)
+                red[d][threadIdx.x] = d < 3 ? fmin(red[d][threadIdx.x], red[d][threadIdx.x + st])
+                                            : fmax(red[d][threadIdx.x], red[d][threadIdx.x + st]);
+        __syncthreads();
     }
+    if (threadIdx.x < 6) out[k * 6 + threadIdx.x] = red[threadIdx.x][0];
 }
 
 __device__ inline uint64_t spread3(uint64_t v) {
@@ -243,7 +251,7 @@ void bbox(const void* x, const void* y, const void* z, int dtype, const int64_t*
         else
             k_bbox<float><<<nblk, BB, 0, s>>>((const float*)x, (const float*)y, (const float*)z, bt, part, bad);
     }
-    k_bbox_final<<<(nseg + 63) / 64, 64, 0, s>>>(part, pb, nseg, out);
+    k_bbox_final<<<nseg, BB, 0, s>>>(part, pb, nseg, out);
 }
 
 void morton_keys(const void* x, const void* y, const void* z, int dtype, int64_t n, const int64_t* seg, int nseg,
