@@ -63,7 +63,7 @@ typedef enum {
     FMM_PREC_FP32 = 0,       /* FP32 kernels, FP64 per-target final sum */
     FMM_PREC_SPLIT_BF16 = 1, /* as FP32, but same-level M2L as three BF16 products per
                                 FP32 product (hi*hi + hi*lo + lo*hi) on the matrix cores
-                                with FP32 accumulation; p <= 10 */
+                                with FP32 accumulation; p <= 12 */
     FMM_PREC_FP64 = 2        /* reserved: not implemented (FMM_ERR_UNSUPPORTED) */
 } fmm_precision;
 

@@ -729,7 +729,7 @@ void evaluate_impl(fmm_ctx c, int32_t precision, int32_t out_dtype, void* phi, v
     if (precision < 0 || precision > 2) fail(FMM_ERR_INVALID_ARG, "unknown precision");
     if (precision == FMM_PREC_FP64) fail(FMM_ERR_UNSUPPORTED, "FMM_PREC_FP64 is not implemented");
     if (precision == FMM_PREC_SPLIT_BF16 && !m2l_bf16_supported(c->p))
-        fail(FMM_ERR_UNSUPPORTED, "split-BF16 M2L is implemented for p <= 10");
+        fail(FMM_ERR_UNSUPPORTED, "split-BF16 M2L is implemented for p <= 12");
     if (out_dtype != FMM_F32 && out_dtype != FMM_F64) fail(FMM_ERR_INVALID_ARG, "out_dtype must be F32 or F64");
     if (c->n > 0 && (!phi || !ex || !ey || !ez)) fail(FMM_ERR_INVALID_ARG, "null output pointer");
     if (c->n == 0) return;
@@ -1187,7 +1187,7 @@ fmm_status fmm_costmodel_train(fmm_ctx c, int32_t p, double theta, int32_t preci
         if (precision != FMM_PREC_FP32 && precision != FMM_PREC_SPLIT_BF16)
             fail(FMM_ERR_UNSUPPORTED, "training is implemented for FP32 and split-BF16");
         if (precision == FMM_PREC_SPLIT_BF16 && !m2l_bf16_supported(p))
-            fail(FMM_ERR_UNSUPPORTED, "split-BF16 M2L is implemented for p <= 10");
+            fail(FMM_ERR_UNSUPPORTED, "split-BF16 M2L is implemented for p <= 12");
         gen_records(c, p, theta, precision, seed);
         double l = mlp_fit(c, (int)c->rec_kind.size(), c->rec_feat.data(), c->rec_kind.data(), c->rec_tgt.data(),
                            epochs, 3e-3, seed);

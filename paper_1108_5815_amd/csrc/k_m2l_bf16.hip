@@ -41,7 +41,7 @@ __device__ inline void gemm_item(const GemmPlan& plan, int& tile, int& g) {
     g = (int)(b & 7u) + 8 * (int)(rest / (unsigned)plan.ntiles);
 }
 
-template <int KP, int NT, int RW, int CW, bool DBA>
+template <int KP, int NT, int RW, int CW>
 __global__ __launch_bounds__(256) void k_m2l_bf16(const uint4* __restrict__ Thi, const uint4* __restrict__ Tlo,
                                                   const int32_t* __restrict__ offid,
                                                   const int32_t* __restrict__ gather, GemmPlan plan,
@@ -109,28 +109,34 @@ __global__ __launch_bounds__(256) void k_m2l_bf16(const uint4* __restrict__ Thi,
             else Blo[buf][col * STR + rem - KB] = breg[v];
         }
     };
-    // operator fragments of one slot: step s, half h -> K block 2s + h
-    constexpr int NA = DBA ? 2 : 1;
-    u32x4 ah[NA][NRB][KS], al[NA][NRB][KS];
-    auto load_A = [&](int k, int buf) {
+    // operator fragments stream through two register buffers in NQ parts of a
+    // slot (SC steps each; NQ = 2, or 4 at the widest storage): the next part
+    // (of this slot, or the first part of the next slot) loads while the
+    // current part computes.  Step s, half h of the wave -> K block 2s + h.
+    constexpr int NQ = KP > 128 ? 4 : 2;
+    constexpr int SC = KS / NQ;
+    static_assert(KS % NQ == 0, "slot parts");
+    u32x4 ah[2][NRB][SC], al[2][NRB][SC];
+    auto load_A = [&](int k, int half, int buf) {
         const size_t base = (size_t)oid[act[k]] * KB * KP;
 #pragma unroll
         for (int i = 0; i < NRB; i++)
 #pragma unroll
-            for (int s = 0; s < KS; s++) {
-                const size_t ix = base + (size_t)(2 * s + h) * KP + (wr + RW * i) * 32 + l32;
+            for (int s = 0; s < SC; s++) {
+                const size_t ix = base + (size_t)(2 * (half * SC + s) + h) * KP + (wr + RW * i) * 32 + l32;
                 ah[buf][i][s] = reinterpret_cast<const u32x4*>(Thi)[ix];
                 al[buf][i][s] = reinterpret_cast<const u32x4*>(Tlo)[ix];
             }
     };
-    auto compute = [&](int bbuf, int abuf) {
+    auto compute = [&](int bbuf, int half, int abuf) {
 #pragma unroll
-        for (int s = 0; s < KS; s++) {
+        for (int s = 0; s < SC; s++) {
+            const int st = half * SC + s;
 #pragma unroll
             for (int b = 0; b < NCB; b++) {
                 const int col = (wc + CW * b) * 32 + l32;
-                const u32x4 bh = Bhi[bbuf][col * STR + 2 * s + h];
-                const u32x4 bl = Blo[bbuf][col * STR + 2 * s + h];
+                const u32x4 bh = Bhi[bbuf][col * STR + 2 * st + h];
+                const u32x4 bl = Blo[bbuf][col * STR + 2 * st + h];
                 const bf16x8 vbh = __builtin_bit_cast(bf16x8, bh);
                 const bf16x8 vbl = __builtin_bit_cast(bf16x8, bl);
 #pragma unroll
@@ -148,35 +154,20 @@ __global__ __launch_bounds__(256) void k_m2l_bf16(const uint4* __restrict__ Thi,
     if (k1 > k0) {
         load_B(k0);
         store_B(0);
-        load_A(k0, 0);
+        load_A(k0, 0, 0);
         __syncthreads();
-        if constexpr (DBA) {
-            // operator fragments of the next slot load while this slot computes
-            for (int k = k0; k < k1; k += 2) {
-                if (k + 1 < k1) {
-                    load_B(k + 1);
-                    load_A(k + 1, 1);
-                }
-                compute(0, 0);
-                if (k + 1 < k1) store_B(1);
-                __syncthreads();
-                if (k + 1 >= k1) break;
-                if (k + 2 < k1) {
-                    load_B(k + 2);
-                    load_A(k + 2, 0);
-                }
-                compute(1, 1);
-                if (k + 2 < k1) store_B(0);
-                __syncthreads();
+        for (int k = k0; k < k1; k++) {
+            const int bb = (k - k0) & 1;
+            const bool more = k + 1 < k1;
+            if (more) load_B(k + 1);
+#pragma unroll
+            for (int q = 0; q < NQ; q++) {
+                if (q + 1 < NQ) load_A(k, q + 1, (q + 1) & 1);
+                else if (more) load_A(k + 1, 0, 0);
+                compute(bb, q, q & 1);
             }
-        } else {
-            for (int k = k0; k < k1; k++) {
-                if (k > k0) load_A(k, 0);
-                if (k + 1 < k1) load_B(k + 1);
-                compute((k - k0) & 1, 0);
-                if (k + 1 < k1) store_B(((k - k0) & 1) ^ 1);
-                __syncthreads();
-            }
+            if (more) store_B(bb ^ 1);
+            __syncthreads();
         }
     }
     // partial locals of this group (zero when it has no slots)
@@ -192,10 +183,10 @@ __global__ __launch_bounds__(256) void k_m2l_bf16(const uint4* __restrict__ Thi,
     }
 }
 
-template <int KP, int NT, int RW, int CW, bool DBA>
+template <int KP, int NT, int RW, int CW>
 void launch(const uint16_t* Thi, const uint16_t* Tlo, const int32_t* offid, const int32_t* gather, GemmPlan plan,
             const uint4* Ms, float* part, hipStream_t s) {
-    k_m2l_bf16<KP, NT, RW, CW, DBA><<<plan.ntiles * plan.G, 256, 0, s>>>((const uint4*)Thi, (const uint4*)Tlo, offid,
+    k_m2l_bf16<KP, NT, RW, CW><<<plan.ntiles * plan.G, 256, 0, s>>>((const uint4*)Thi, (const uint4*)Tlo, offid,
                                                                          gather, plan, Ms, part);
 }
 
@@ -233,10 +224,11 @@ void m2l_gemm_bf16(const uint16_t* Thi, const uint16_t* Tlo, const int32_t* offi
     const int64_t nb = (ncell + 1) * KB;  // with the zero row
     k_split_cells<<<(unsigned)((nb + 255) / 256), 256, 0, s>>>((const float4*)M, ncell + 1, KB, Ms);
     switch (KP) {
-        case 32: launch<32, 128, 1, 4, true>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
-        case 64: launch<64, 128, 2, 2, true>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
-        case 96: launch<96, 128, 1, 4, false>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
-        case 128: launch<128, 64, 4, 1, false>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
+        case 32: launch<32, 128, 1, 4>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
+        case 64: launch<64, 128, 2, 2>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
+        case 96: launch<96, 128, 1, 4>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
+        case 128: launch<128, 64, 4, 1>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
+        case 192: launch<192, 64, 2, 2>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
         default: return;
     }
     m2l_reduce_groups(part, plan, rowcell, KP, ncoef(p), L, s);
@@ -244,7 +236,7 @@ void m2l_gemm_bf16(const uint16_t* Thi, const uint16_t* Tlo, const int32_t* offi
 
 bool m2l_bf16_supported(int p) {
     const int kp = kpad(p);
-    return kp == 32 || kp == 64 || kp == 96 || kp == 128;
+    return kp == 32 || kp == 64 || kp == 96 || kp == 128 || kp == 192;
 }
 
 }  // namespace fmm

@@ -7,7 +7,9 @@ sum of two BF16 values keeps 16 significand bits, so each product carries a
 relative error of order 2^-16 before accumulation; the bar stays the one of the
 FP32 form: potential within 1e-5 and field within 1e-4 relative L2 of the
 oracle's FMM on the same lists at p = 10, and of the FP64 direct sum at the
-full 4,194,304-particle Plummer size on seeded targets.
+full 4,194,304-particle Plummer size on seeded targets; at p = 12 (storage
+width 192) the same bar holds against the oracle's FMM and against the direct
+sum on 2,000 seeded targets of the full 16,777,216-particle Plummer set.
 """
 import numpy as np
 import pytest
@@ -36,9 +38,9 @@ def run(x, y, z, q, p, theta, ncrit, precision, policy=0, f=None):
     return f, phi.cpu().numpy(), E.cpu().numpy().T
 
 
-@pytest.mark.parametrize("p", [4, 7, 8, 10])
+@pytest.mark.parametrize("p", [4, 7, 8, 10, 12])
 def test_bf16_uniform_vs_oracle(p):
-    """Each supported padded width (32, 64, 96, 128 coefficients)."""
+    """Each supported padded width (32, 64, 96, 128, 192 coefficients)."""
     n = 24000
     x, y, z = (as_f32(a) for a in synth.uniform_cube(n, 21))
     q = as_f32(synth.charges_uniform(n, 121))
@@ -87,7 +89,7 @@ def test_bf16_unsupported_orders():
     f = FMM(0)
     x = torch.rand(2000, device="cuda:0")
     f.build_tree(x, x.flip(0), x * 0.5, x, 16)
-    for p in (11, 12, 16):
+    for p in (13, 16):
         f.traverse(p, 0.5, 0)
         with pytest.raises(FMMError) as e:
             f.evaluate(BF16)
@@ -107,4 +109,18 @@ def test_full_size_plummer4m_p10_bf16_sampled():
     pd, Ed = ora.direct(xs, ys, zs, qs, tg)
     ep, eE = ora.rel_l2(phi[tg], pd), ora.rel_l2(E[tg], Ed)
     print(f"plummer4m p10 split-bf16: phi rel L2 {ep:.3e}  E rel L2 {eE:.3e}")
+    assert ep < 1e-5 and eE < 1e-4
+
+
+def test_full_size_plummer16m_p12_bf16_sampled():
+    """16,777,216 Plummer points, FP32 inputs, p = 12, theta = 0.4, ncrit = 64,
+    split-BF16 M2L (the widest storage, 192 coefficients): 2,000 seeded targets
+    against the FP64 direct sum."""
+    x, y, z, q, tg, w = synth.make_workload("plummer16m_p12")
+    xs, ys, zs, qs = (as_f32(a) for a in (x, y, z, q))
+    f, phi, E = run(xs, ys, zs, qs, w["p"], w["theta"], w["ncrit"], BF16)
+    assert f.m2l_split()[0] > 0
+    pd, Ed = ora.direct(xs, ys, zs, qs, tg)
+    ep, eE = ora.rel_l2(phi[tg], pd), ora.rel_l2(E[tg], Ed)
+    print(f"plummer16m p12 split-bf16: phi rel L2 {ep:.3e}  E rel L2 {eE:.3e}")
     assert ep < 1e-5 and eE < 1e-4
