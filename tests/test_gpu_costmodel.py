@@ -150,3 +150,37 @@ def test_gain_of_learned_model():
         print(f"{k:8s} {v[0] / 1e6:8.2f} M particles/s  {v[1]}")
     print("learned / timed:", res["learned"][0] / res["timed"][0])
     assert res["learned"][0] > res["fmm"][0]
+
+
+def test_learned_split_bf16_plummer16m_p12():
+    """16,777,216 Plummer points, p = 12, theta = 0.4, ncrit = 64: the learned
+    hybrid trained on split-BF16 timings, evaluated in split-BF16, against the
+    FP64 direct sum on 2,000 seeded targets; and the same lists' values against
+    the oracle FMM at a size the oracle finishes (65,536 points of the set's
+    generator, same parameters)."""
+    x, y, z, q, tg, w = synth.make_workload("plummer16m_p12")
+    x, y, z, q = (np.asarray(a, np.float32).astype(np.float64) for a in (x, y, z, q))
+    f = fmm()
+    f.costmodel_train(12, 0.4, epochs=3000, seed=7, precision=1)
+    t = [torch.tensor(a, dtype=torch.float32, device="cuda:0") for a in (x, y, z, q)]
+    f.build_tree(*t, w["ncrit"])
+    f.traverse(12, 0.4, 3)
+    phi, E = f.evaluate(1, out_dtype=torch.float64)
+    torch.cuda.synchronize()
+    pd, Ed = ora.direct(x, y, z, q, tg)
+    ep = ora.rel_l2(phi.cpu().numpy()[tg], pd)
+    eE = ora.rel_l2(E.cpu().numpy().T[tg], Ed)
+    print("plummer16m p12 learned split-bf16 sizes", f.sizes(), "phi", ep, "E", eE)
+    assert ep < 1e-5 and eE < 1e-4
+    n = 65536
+    xs, ys, zs, qs, _, _ = synth.make_workload("plummer16m_p12", n)
+    xs, ys, zs, qs = (np.asarray(a, np.float32).astype(np.float64) for a in (xs, ys, zs, qs))
+    g = fmm()
+    g.costmodel_set_weights(f.costmodel_weights())
+    g.build_tree(*(torch.tensor(a, dtype=torch.float32, device="cuda:0") for a in (xs, ys, zs, qs)), 64)
+    g.traverse(12, 0.4, 3)
+    ph2, E2 = g.evaluate(1, out_dtype=torch.float64)
+    tr = ora.Tree(xs, ys, zs, 64)
+    tr.traverse_table(0.4, g.costmodel_table(12, 0.4))
+    po, Eo = tr.evaluate(12, qs)
+    assert ora.rel_l2(ph2.cpu().numpy(), po) < 1e-5 and ora.rel_l2(E2.cpu().numpy().T, Eo) < 1e-4
