@@ -468,7 +468,7 @@ void build_forest_impl(fmm_ctx c, int32_t nseg, const int64_t* hseg, int dtype, 
         leaf_class_keys(cells_of(c), lv, nl, lk, lvv, s);
         sort_u32(lk, lvv, lk2, lv2, nl, 0, 8, ws, s);
         int32_t* d9 = (int32_t*)(d6 + 20);
-        class_bounds(lk, nl, d9, s);
+        class_bounds(lk, nl, 0, d9, s);
         check_launch("leaf classes");
         int32_t h9[9];
         to_host<int32_t>(c, h9, d9, 9);
@@ -654,12 +654,12 @@ void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
         uint32_t* rv = need<uint32_t>(c, c->rval, nc);
         uint32_t* rk2 = need<uint32_t>(c, c->rkey2, nc);
         uint32_t* rv2 = need<uint32_t>(c, c->rval2, nc);
-        row_class_keys(hf, ca, nc, rk, rv, s);
+        row_class_keys(hf, ca, nc, J, rk, rv, s);
         size_t wsn = sort_ws_bytes(nc);
         if (wsn > c->ws.cap) ws = need<char>(c, c->ws, wsn);
-        sort_u32(rk, rv, rk2, rv2, nc, 0, 8, ws, s);
+        sort_u32(rk, rv, rk2, rv2, nc, 0, kRowMissBits + 4, ws, s);
         int32_t* d9 = (int32_t*)(d6 + 20);
-        class_bounds(rk, nc, d9, s);
+        class_bounds(rk, nc, kRowMissBits, d9, s);
         check_launch("m2l classes");
         int32_t* h9 = (int32_t*)host_stage(c);
         to_host<int32_t>(c, h9, d9, 9);

@@ -143,14 +143,19 @@ void m2l_mark_targets(const uint32_t* tgt, const uint32_t* src, int64_t n, CellA
 void m2l_fill_gather(const uint32_t* tgt, const uint32_t* src, int64_t n, CellArrays cells,
                      const int32_t* slot_of, int R, const int32_t* rowof, int32_t J,
                      int32_t* gather, uint32_t* general, hipStream_t s);
-void row_class_keys(const uint32_t* has_fast, CellArrays cells, int32_t ncell, uint32_t* key,
+// row keys of the M2L GEMM: (octant class << kRowMissBits) | missing slots
+// (densest first); cells without same-level pairs get class 8
+constexpr int kRowMissBits = 10;
+constexpr uint32_t kRowMissMax = (1u << kRowMissBits) - 1;
+void row_class_keys(const uint32_t* nfast, CellArrays cells, int32_t ncell, int32_t J, uint32_t* key,
                     uint32_t* val, hipStream_t s);
 void rows_inverse(const uint32_t* rowcell, int64_t nrows, int32_t* rowof, hipStream_t s);
 // keep the pairs whose flag is set: out[pos[i]] = pair i (pos = exclusive scan of flag)
 void compact_pairs(const uint32_t* tgt, const uint32_t* src, const uint32_t* flag, const uint32_t* pos, int64_t n,
                    uint32_t* otgt, uint32_t* osrc, hipStream_t s);
 // out9[c] = first index of the sorted class keys with key >= c, c = 0..8
-void class_bounds(const uint32_t* key_sorted, int64_t n, int32_t* out9, hipStream_t s);
+// out9[c] = first index whose key >> shift is >= c, c = 0..8
+void class_bounds(const uint32_t* key_sorted, int64_t n, int shift, int32_t* out9, hipStream_t s);
 // leaf cells (nchild == 0) in cell order; flag/pos are scratch of ncell entries
 void leaf_flags(CellArrays cells, int32_t ncell, uint32_t* flag, hipStream_t s);
 void leaf_write(CellArrays cells, int32_t ncell, const uint32_t* pos, int32_t* leaves, hipStream_t s);

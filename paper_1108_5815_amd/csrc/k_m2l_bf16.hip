@@ -33,6 +33,17 @@ __device__ inline uint16_t bf16_rne(float x) {
 
 __device__ inline float bf16_to_f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
+// first index k in [0, n) with act[k] >= j (act ascending), or n
+__device__ inline int lower_slot(const int32_t* act, int n, int j) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (act[mid] < j) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
 // work item of block b: b = (h * ntiles + tile) * 8 + x, group g = x + 8 h
 __device__ inline void gemm_item(const GemmPlan& plan, int& tile, int& g) {
     const unsigned b = blockIdx.x;
@@ -68,10 +79,13 @@ __global__ __launch_bounds__(256) void k_m2l_bf16(const uint4* __restrict__ Thi,
     const int l32 = lane & 31, h = lane >> 5;
     const int wr = w % RW, wc = w / RW;
     const int32_t* oid = offid + (size_t)cls * J;
-    // this group's share of the slots some row of the tile uses
+    // this group's slots [g J / G, (g + 1) J / G), restricted to those some row
+    // of the tile uses: fixed slot ranges make each row's partial independent
+    // of the other rows of its tile
     const int32_t* act = plan.act + (size_t)tile * J;
     const int na = plan.nact[tile];
-    const int k0 = (int)(((int64_t)g * na) / plan.G), k1 = (int)(((int64_t)(g + 1) * na) / plan.G);
+    const int k0 = lower_slot(act, na, (int)(((int64_t)g * J) / plan.G));
+    const int k1 = lower_slot(act, na, (int)(((int64_t)(g + 1) * J) / plan.G));
 
     floatx16 acc[NRB][NCB];
 #pragma unroll

@@ -16,11 +16,12 @@
 // storage width 128 (36 MB at theta = 0.4), far more than one XCD's 4 MB L2,
 // and tiles that run at the same time drift apart in slot, so streaming every
 // slot through every tile makes each operator block an L2 miss.  Instead the
-// active slots of a tile are cut into G groups (G a multiple of 8) and work
-// item (tile, group g) runs on XCD g mod 8 (workgroups are dealt to the 8
-// XCDs round robin by block index): each XCD then touches only its own slice
-// of the operators, which stays in its L2.  Each item writes its partial
-// locals to part[g][row]; m2l_reduce_groups sums the groups in order.
+// slots are cut into G fixed ranges (G a multiple of 8) and work item (tile,
+// group g) runs on XCD g mod 8 (workgroups are dealt to the 8 XCDs round
+// robin by block index): each XCD then touches only its own slice of the
+// operators, which stays in its L2.  Each item writes its partial locals to
+// part[g][row]; m2l_reduce_groups sums the groups in order.  A row's result
+// therefore depends only on its own sources, whatever rows share its tile.
 //
 // Tiling (gfx950, wave64, v_mfma_f32_32x32x2f32): a 256-lane workgroup owns
 // KP x NT outputs split over a RW x CW grid of waves; each wave keeps
@@ -42,6 +43,17 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 // 16 bytes as a native vector (copies stay in registers; HIP's float4 struct
 // copies can be lowered through private memory)
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// first index k in [0, n) with act[k] >= j (act ascending), or n
+__device__ inline int lower_slot(const int32_t* act, int n, int j) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (act[mid] < j) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
 
 // work item of block b: b = (h * ntiles + tile) * 8 + x, group g = x + 8 h
 __device__ inline void gemm_item(const GemmPlan& plan, int& tile, int& g) {
@@ -77,10 +89,13 @@ __global__ __launch_bounds__(256) void k_m2l_gemm(const float* __restrict__ T, c
     const int l32 = lane & 31, h = lane >> 5;
     const int wr = w % RW, wc = w / RW;
     const int32_t* oid = offid + (size_t)cls * J;
-    // this group's share of the slots some row of the tile uses
+    // this group's slots [g J / G, (g + 1) J / G), restricted to those some row
+    // of the tile uses: fixed slot ranges make each row's partial independent
+    // of the other rows of its tile
     const int32_t* act = plan.act + (size_t)tile * J;
     const int na = plan.nact[tile];
-    const int k0 = (int)(((int64_t)g * na) / plan.G), k1 = (int)(((int64_t)(g + 1) * na) / plan.G);
+    const int k0 = lower_slot(act, na, (int)(((int64_t)g * J) / plan.G));
+    const int k1 = lower_slot(act, na, (int)(((int64_t)(g + 1) * J) / plan.G));
 
     floatx16 acc[NRB][NCB];
 #pragma unroll

@@ -166,7 +166,7 @@ __global__ void k_mark_targets(const uint32_t* __restrict__ tgt, const uint32_t*
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int32_t t = (int32_t)tgt[i];
-    if (fast_slot(c, t, (int32_t)src[i], slot_of, R) >= 0) has_fast[t] = 1u;
+    if (fast_slot(c, t, (int32_t)src[i], slot_of, R) >= 0) atomicAdd(&has_fast[t], 1u);
 }
 
 __global__ void k_fill_gather(const uint32_t* __restrict__ tgt, const uint32_t* __restrict__ src, int64_t n,
@@ -185,11 +185,18 @@ __global__ void k_fill_gather(const uint32_t* __restrict__ tgt, const uint32_t* 
     }
 }
 
-__global__ void k_row_class_keys(const uint32_t* __restrict__ has_fast, CellArrays c, int32_t ncell,
+// Rows of the M2L GEMM: cells with same-level pairs, keyed by octant class and,
+// within a class, densest first (fewest missing slots), so that rows with
+// full slot sets share tiles and sparse rows do not spread zero columns over
+// dense tiles; the sort is stable, so cells of equal count keep their order.
+__global__ void k_row_class_keys(const uint32_t* __restrict__ nfast, CellArrays c, int32_t ncell, int32_t J,
                                  uint32_t* __restrict__ key, uint32_t* __restrict__ val) {
     int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
     if (i >= ncell) return;
-    key[i] = has_fast[i] ? (uint32_t)(c.prefix[i] & 7u) : 8u;
+    const uint32_t n = nfast[i];
+    const uint32_t miss = n >= (uint32_t)J ? 0u : (uint32_t)J - n;
+    key[i] = n ? ((uint32_t)(c.prefix[i] & 7u) << kRowMissBits) | (miss < kRowMissMax ? miss : kRowMissMax)
+               : (8u << kRowMissBits);
     val[i] = (uint32_t)i;
 }
 
@@ -283,10 +290,10 @@ void m2l_fill_gather(const uint32_t* tgt, const uint32_t* src, int64_t n, CellAr
     k_fill_gather<<<grid(n), 256, 0, s>>>(tgt, src, n, cells, slot_of, R, rowof, J, gather, general);
 }
 
-void row_class_keys(const uint32_t* has_fast, CellArrays cells, int32_t ncell, uint32_t* key, uint32_t* val,
+void row_class_keys(const uint32_t* nfast, CellArrays cells, int32_t ncell, int32_t J, uint32_t* key, uint32_t* val,
                     hipStream_t s) {
     if (ncell <= 0) return;
-    k_row_class_keys<<<grid(ncell), 256, 0, s>>>(has_fast, cells, ncell, key, val);
+    k_row_class_keys<<<grid(ncell), 256, 0, s>>>(nfast, cells, ncell, J, key, val);
 }
 
 void rows_inverse(const uint32_t* rowcell, int64_t nrows, int32_t* rowof, hipStream_t s) {
@@ -299,13 +306,13 @@ void rows_inverse(const uint32_t* rowcell, int64_t nrows, int32_t* rowof, hipStr
 namespace fmm {
 namespace {
 
-__global__ void k_class_bounds(const uint32_t* __restrict__ key, int64_t n, int32_t* __restrict__ out9) {
+__global__ void k_class_bounds(const uint32_t* __restrict__ key, int64_t n, int shift, int32_t* __restrict__ out9) {
     int c = threadIdx.x;
     if (c > 8) return;
     int64_t lo = 0, hi = n;
     while (lo < hi) {
         int64_t mid = (lo + hi) >> 1;
-        if (key[mid] < (uint32_t)c) lo = mid + 1;
+        if ((key[mid] >> shift) < (uint32_t)c) lo = mid + 1;
         else hi = mid;
     }
     out9[c] = (int32_t)lo;
@@ -324,8 +331,8 @@ __global__ void k_leaf_write(CellArrays c, int32_t ncell, const uint32_t* __rest
 
 }  // namespace
 
-void class_bounds(const uint32_t* key_sorted, int64_t n, int32_t* out9, hipStream_t s) {
-    k_class_bounds<<<1, 64, 0, s>>>(key_sorted, n, out9);
+void class_bounds(const uint32_t* key_sorted, int64_t n, int shift, int32_t* out9, hipStream_t s) {
+    k_class_bounds<<<1, 64, 0, s>>>(key_sorted, n, shift, out9);
 }
 
 void leaf_flags(CellArrays cells, int32_t ncell, uint32_t* flag, hipStream_t s) {
