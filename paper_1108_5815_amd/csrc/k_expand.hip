@@ -102,7 +102,8 @@ __device__ inline int degree_of(int j) {
 
 // ---------------------------------------------------------------- P2M
 // One workgroup of 64 lanes per leaf: each lane writes q * conj(S(x-c)/r) of
-// one particle into its LDS row, then lanes sum columns (fixed order).
+// one particle into its LDS row, then lanes sum columns (fixed order) over
+// the rows that hold a particle.
 __global__ __launch_bounds__(64) void k_p2m(const float4* __restrict__ pts, CellArrays c,
                                             const int32_t* __restrict__ leaves, int p, int KP,
                                             const float* __restrict__ rc, float* __restrict__ M) {
@@ -117,31 +118,27 @@ __global__ __launch_bounds__(64) void k_p2m(const float4* __restrict__ pts, Cell
     float acc[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
     float* row = sh + (threadIdx.x < CH ? threadIdx.x : 0) * STR;
     for (int32_t ch = b; ch < e; ch += CH) {
-        if (threadIdx.x < CH) {
-            int32_t i = ch + threadIdx.x;
-            if (i < e) {
-                float4 P = pts[i];
-                float x = (float)(((double)P.x - ct.x) * ir);
-                float y = (float)(((double)P.y - ct.y) * ir);
-                float z = (float)(((double)P.z - ct.z) * ir);
-                float q = P.w;
-                regular_walk(p, x, y, z, rc, [&](int n, int m, float re, float im) {
-                    if (m == 0) row[n * n] = q * re;
-                    else {
-                        row[n * n + 2 * m - 1] = q * re;
-                        row[n * n + 2 * m] = -q * im;
-                    }
-                });
-            } else {
-                for (int j = 0; j < K; j++) row[j] = 0.f;
-            }
+        const int nr = min(CH, e - ch);
+        if ((int)threadIdx.x < nr) {
+            float4 P = pts[ch + threadIdx.x];
+            float x = (float)(((double)P.x - ct.x) * ir);
+            float y = (float)(((double)P.y - ct.y) * ir);
+            float z = (float)(((double)P.z - ct.z) * ir);
+            float q = P.w;
+            regular_walk(p, x, y, z, rc, [&](int n, int m, float re, float im) {
+                if (m == 0) row[n * n] = q * re;
+                else {
+                    row[n * n + 2 * m - 1] = q * re;
+                    row[n * n + 2 * m] = -q * im;
+                }
+            });
         }
         __syncthreads();
         for (int u = 0; u < 5; u++) {
             int j = threadIdx.x + 64 * u;
             if (j < K) {
                 float s = 0.f;
-                for (int r = 0; r < CH; r++) s += sh[r * STR + j];
+                for (int r = 0; r < nr; r++) s += sh[r * STR + j];
                 acc[u] += s;
             }
         }

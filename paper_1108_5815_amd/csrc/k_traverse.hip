@@ -160,13 +160,35 @@ __device__ inline int32_t fast_slot(const CellArrays& c, int32_t t, int32_t s, c
     return slot_of[(size_t)cls * W * W * W + ((size_t)(ox + R) * W + (oy + R)) * W + (oz + R)];
 }
 
-__global__ void k_mark_targets(const uint32_t* __restrict__ tgt, const uint32_t* __restrict__ src, int64_t n,
-                               CellArrays c, const int32_t* __restrict__ slot_of, int R,
-                               uint32_t* __restrict__ has_fast) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int32_t t = (int32_t)tgt[i];
-    if (fast_slot(c, t, (int32_t)src[i], slot_of, R) >= 0) atomicAdd(&has_fast[t], 1u);
+// Same-level pairs per target.  Pairs come in emission order, where the
+// children of one frontier pair sit side by side, so a wave first sums its
+// runs of equal targets (segmented scan over the lanes) and adds each run
+// with one atomic (integer: the counts do not depend on timing).
+__global__ __launch_bounds__(256) void k_mark_targets(const uint32_t* __restrict__ tgt,
+                                                      const uint32_t* __restrict__ src, int64_t n, CellArrays c,
+                                                      const int32_t* __restrict__ slot_of, int R,
+                                                      uint32_t* __restrict__ nfast) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    int32_t t = -1;
+    int v = 0;
+    if (i < n) {
+        t = (int32_t)tgt[i];
+        v = fast_slot(c, t, (int32_t)src[i], slot_of, R) >= 0 ? 1 : 0;
+    }
+    const int32_t tp = __shfl_up(t, 1, 64);
+    int flag = (lane == 0 || tp != t) ? 1 : 0;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int v2 = __shfl_up(v, d, 64), f2 = __shfl_up(flag, d, 64);
+        if (lane >= d) {
+            if (!flag) v += v2;
+            flag |= f2;
+        }
+    }
+    const int32_t tn = __shfl_down(t, 1, 64);
+    const bool tail = lane == 63 || tn != t;
+    if (tail && t >= 0 && v > 0) atomicAdd(&nfast[t], (uint32_t)v);
 }
 
 __global__ void k_fill_gather(const uint32_t* __restrict__ tgt, const uint32_t* __restrict__ src, int64_t n,
