@@ -89,6 +89,9 @@ struct fmm_ctx_s {
     Buf d_slot, d_offid, d_T, d_Thi, d_Tlo;
     bool plan_bf16 = false;
     Buf has_fast, rkey, rval, rkey2, rval2, rowof, gather, general, gtg, gsr, goff, tact, tnact, m2l_part, Msplit, nbucket, kinds;
+    // pairs outside the same-level tables, batched by class
+    ClsPlan cp;
+    Buf ckey, ckey2, cval, cval2, chead, choff, cstart, cpos, csrcs, cnt_t, ctbase, ctile, cT, cskip, cls_part;
     bool m2l_sorted = false;
     GemmPlan gp{};
     int ntiles = 0;
@@ -126,7 +129,8 @@ struct fmm_ctx_s {
                       &d_h, &d_rc, &d_mlp, &M, &L, &nearb, &tune_pts, &tune_out, &d_mlp_m, &d_mlp_v,
                       &d_grad, &d_grad_rec, &d_loss_rec, &d_feat, &d_kind, &d_tgt, &d_table, &d_Thi, &d_Tlo,
                       &d_seg, &d_bt, &d_pb, &d_box, &d_frame, &inst, &bsort, &tact, &tnact,
-                      &leaves_cls, &lkey, &lval, &lkey2, &lval2, &at_out, &m2l_part, &Msplit, &nbucket, &kinds};
+                      &leaves_cls, &lkey, &lval, &lkey2, &lval2, &at_out, &m2l_part, &Msplit, &nbucket, &kinds, &ckey, &ckey2, &cval, &cval2,
+                      &chead, &choff, &cstart, &cpos, &csrcs, &cnt_t, &ctbase, &ctile, &cT, &cskip, &cls_part};
         for (Buf* b : all) bufs.push_back(b);
     }
 };
@@ -520,6 +524,69 @@ void upload_plan_bf16(fmm_ctx c) {
     c->plan_bf16 = true;
 }
 
+// The M2L pairs outside the same-level tables (CSR by target in gtg / gsr /
+// goff) keyed by class, sorted, and given one operator per class.
+void build_classes(fmm_ctx c, int p) {
+    c->cp = ClsPlan{};
+    const int64_t ng = c->ngeneral;
+    const int KP = kpad(p);
+    const int NT = cls_tile_cols(KP);
+    if (ng <= 0 || NT <= 0) return;
+    hipStream_t s = c->stream;
+    CellArrays ca = cells_of(c);
+    uint64_t* keys = need<uint64_t>(c, c->ckey, ng);
+    uint64_t* keys2 = need<uint64_t>(c, c->ckey2, ng);
+    uint32_t* cv = need<uint32_t>(c, c->cval, ng);
+    uint32_t* cv2 = need<uint32_t>(c, c->cval2, ng);
+    cls_keys((uint32_t*)c->gtg.p, (uint32_t*)c->gsr.p, ng, ca, keys, cv, s);
+    size_t wsn = std::max(sort_ws_bytes(ng), scan_ws_bytes(ng));
+    void* ws = wsn > c->ws.cap ? need<char>(c, c->ws, wsn) : c->ws.p;
+    double* d6 = (double*)c->small.p;
+    sort_u64(keys, cv, keys2, cv2, ng, 0, 64, ws, s);
+    uint32_t* head = need<uint32_t>(c, c->chead, ng + 1);
+    uint32_t* hoff = need<uint32_t>(c, c->choff, ng + 1);
+    cls_heads(keys, ng, head, s);
+    scan_u32(head, hoff, (uint32_t*)(d6 + 12), ng, ws, s);
+    check_launch("m2l classes: keys");
+    uint32_t ncls = 0;
+    to_host<uint32_t>(c, &ncls, d6 + 12, 1);
+    if (ncls == 0) return;
+    int32_t* start = need<int32_t>(c, c->cstart, (size_t)ncls + 1);
+    int32_t* pos = need<int32_t>(c, c->cpos, ng);
+    uint32_t* srcs = need<uint32_t>(c, c->csrcs, ng);
+    cls_index(head, hoff, ng, cv, (uint32_t*)c->gsr.p, start, pos, srcs, s);
+    cls_end(keys, ng, start, (int32_t)ncls, s);
+    uint32_t* nt = need<uint32_t>(c, c->cnt_t, (size_t)ncls + 1);
+    uint32_t* tb = need<uint32_t>(c, c->ctbase, (size_t)ncls + 1);
+    cls_ntiles(start, (int32_t)ncls, NT, nt, s);
+    if (scan_ws_bytes(ncls) > c->ws.cap) {
+        ws = need<char>(c, c->ws, scan_ws_bytes(ncls));
+        d6 = (double*)c->small.p;
+    }
+    scan_u32(nt, tb, (uint32_t*)(d6 + 12), ncls, ws, s);
+    check_launch("m2l classes: tiles");
+    uint32_t ntiles = 0;
+    int32_t nb = 0;
+    to_host<uint32_t>(c, &ntiles, d6 + 12, 1);
+    to_host<int32_t>(c, &nb, start + ncls, 1);
+    int32_t* tile_cls = need<int32_t>(c, c->ctile, std::max<size_t>(ntiles, 1));
+    cls_tiles(nt, tb, (int32_t)ncls, tile_cls, s);
+    float* T = need<float>(c, c->cT, (size_t)ncls * KP * KP);
+    ck(hipMemsetAsync(T, 0, (size_t)ncls * KP * KP * sizeof(float), s), "memset");
+    cls_ops(keys, start, (int32_t)ncls, p, KP, (const float*)c->d_w.p, T, s);
+    if (nb < ng) cls_skip(pos, ng, nb, need<uint8_t>(c, c->cskip, ng), s);
+    check_launch("m2l classes: operators");
+    ClsPlan& cp = c->cp;
+    cp.ncls = (int32_t)ncls;
+    cp.ntiles = (int32_t)ntiles;
+    cp.nbatched = nb;
+    cp.tile_cls = tile_cls;
+    cp.tbase = tb;
+    cp.start = start;
+    cp.srcs = srcs;
+    cp.pos = pos;
+}
+
 void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
     if (!c->built) fail(FMM_ERR_STATE, "fmm_traverse before fmm_build_tree");
     if (p < 0 || p > FMM_P_MAX) fail(FMM_ERR_INVALID_ARG, "p out of range");
@@ -708,6 +775,7 @@ void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
         if (ng > 0) compact_pairs(tg0, sr0, gen, (uint32_t*)c->tgt2.p, nm, gt, gs, s);
         sort_into(nullptr, ng, c->gtg, c->gsr, c->goff);
     }
+    build_classes(c, p);
     ck(hipStreamSynchronize(s), "sync");
     c->traversed = true;
 }
@@ -784,7 +852,15 @@ void evaluate_impl(fmm_ctx c, int32_t precision, int32_t out_dtype, void* phi, v
                      KP, M, part, L, s);
     }
     mark(c, PH_M2LG);
-    if (c->ngeneral > 0) m2l_general((int32_t*)c->goff.p, (uint32_t*)c->gsr.p, ca, nc, p, KP, tb, M, L, s);
+    if (c->cp.ntiles > 0) {
+        ClsPlan cp = c->cp;
+        cp.zcell = nc;
+        float* part2 = need<float>(c, c->cls_part, (size_t)cp.nbatched * KP);
+        m2l_cls((const float*)c->cT.p, cp, p, KP, M, part2, (int32_t*)c->goff.p, nc, L, s);
+    }
+    if (c->ngeneral > c->cp.nbatched)
+        m2l_general((int32_t*)c->goff.p, (uint32_t*)c->gsr.p, ca, nc, p, KP, tb, M, L,
+                    c->cp.nbatched > 0 ? (const uint8_t*)c->cskip.p : nullptr, s);
     check_launch("m2l");
     mark(c, PH_DOWN);
     for (int Lv = 1; Lv < nlev; Lv++) l2l(ca, c->lvl[Lv], c->lvl[Lv + 1], p, KP, tb, L, s);

@@ -176,9 +176,38 @@ void m2m(CellArrays cells, int32_t c0, int32_t c1, int p, int KP, Tables t, floa
          hipStream_t s);
 void l2l(CellArrays cells, int32_t c0, int32_t c1, int p, int KP, Tables t, float* L,
          hipStream_t s);
-// M2L of the pairs outside the batched GEMM, given as a CSR list by target
+// M2L of the pairs outside the batched GEMM, given as a CSR list by target,
+// one pair at a time (pairs with skip[a] != 0 are left out; skip may be null)
 void m2l_general(const int32_t* goff, const uint32_t* gsrc, CellArrays cells, int32_t ncell, int p, int KP,
-                 Tables t, const float* M, float* L, hipStream_t s);
+                 Tables t, const float* M, float* L, const uint8_t* skip, hipStream_t s);
+
+// The same pairs batched by class (level difference, integer offset): see k_m2l_cls.hip.
+struct ClsPlan {
+    int32_t ncls = 0, ntiles = 0, nbatched = 0, zcell = 0;
+    const int32_t* tile_cls = nullptr;  // class of each tile
+    const uint32_t* tbase = nullptr;    // first tile of each class
+    const int32_t* start = nullptr;     // first sorted pair of each class, start[ncls] = nbatched
+    const uint32_t* srcs = nullptr;     // source cell of each sorted pair
+    const int32_t* pos = nullptr;       // sorted position of each pair of the list
+};
+int cls_tile_cols(int KP);
+// key of each pair (class, or all ones when the offset does not fit); val = pair index
+void cls_keys(const uint32_t* gt, const uint32_t* gs, int64_t ng, CellArrays cells, uint64_t* key, uint32_t* val,
+              hipStream_t s);
+void cls_heads(const uint64_t* key, int64_t n, uint32_t* head, hipStream_t s);
+void cls_index(const uint32_t* head, const uint32_t* hoff, int64_t n, const uint32_t* val, const uint32_t* gs,
+               int32_t* start, int32_t* pos, uint32_t* srcs, hipStream_t s);
+// start[ncls] = first pair whose key does not fit (or n)
+void cls_end(const uint64_t* key, int64_t n, int32_t* start, int32_t ncls, hipStream_t s);
+void cls_ntiles(const int32_t* start, int32_t ncls, int NT, uint32_t* nt, hipStream_t s);
+void cls_tiles(const uint32_t* nt, const uint32_t* tbase, int32_t ncls, int32_t* tile_cls, hipStream_t s);
+// operators of all classes into T (ncls x KP x KP, zeroed beforehand)
+void cls_ops(const uint64_t* key, const int32_t* start, int32_t ncls, int p, int KP, const float* W, float* T,
+             hipStream_t s);
+void cls_skip(const int32_t* pos, int64_t ng, int32_t nbatched, uint8_t* skip, hipStream_t s);
+// the class GEMMs into part (nbatched x KP) and the per-target sums into L
+void m2l_cls(const float* T, const ClsPlan& cp, int p, int KP, const float* M, float* part, const int32_t* goff,
+             int32_t ncell, float* L, hipStream_t s);
 void far_final(const float4* pts, const uint32_t* perm, CellArrays cells, const int32_t* leaves,
                int32_t nleaves, const int32_t* m2p_off, const uint32_t* m2p_src, int p, int KP,
                Tables t, const float* M, const float* L, const double4* near, int out_dtype,

@@ -210,7 +210,7 @@ __global__ __launch_bounds__(256) void k_m2l_general(const int32_t* __restrict__
                                                      const uint32_t* __restrict__ gsrc, CellArrays c, int p,
                                                      int KP, const float* __restrict__ W, int w_lds,
                                                      const float* __restrict__ rc, const float* __restrict__ M,
-                                                     float* __restrict__ L) {
+                                                     float* __restrict__ L, const uint8_t* __restrict__ skip) {
     extern __shared__ float sh[];
     const int t = blockIdx.x;
     const int32_t a0 = goff[t], a1 = goff[t + 1];
@@ -246,6 +246,7 @@ __global__ __launch_bounds__(256) void k_m2l_general(const int32_t* __restrict__
     const int4 gt = c.geo[t];
     const float inv = 1.f / (float)gt.w;
     for (int32_t a = a0 + w; a < a1; a += 4) {
+        if (skip && skip[a]) continue;  // handled by the class-batched products
         const int s = (int)gsrc[a];
         const int4 gs = c.geo[s];
         const float qx = (float)(gs.x - gt.x) * inv, qy = (float)(gs.y - gt.y) * inv,
@@ -358,14 +359,14 @@ void l2l(CellArrays cells, int32_t c0, int32_t c1, int p, int KP, Tables t, floa
 }
 
 void m2l_general(const int32_t* goff, const uint32_t* gsrc, CellArrays cells, int32_t ncell, int p, int KP,
-                 Tables t, const float* M, float* L, hipStream_t s) {
+                 Tables t, const float* M, float* L, const uint8_t* skip, hipStream_t s) {
     if (ncell <= 0) return;
     const int P2 = 2 * p;
     const int njk = (p + 1) * (p + 2) / 2, K = (p + 1) * (p + 1);
     const size_t per = 4 * ((size_t)KP + (size_t)(P2 + 1) * (P2 + 2)) + 8 * (size_t)njk;
     const int w_lds = ((size_t)njk * K + per) * sizeof(float) <= 65536 ? 1 : 0;
     const size_t lds = ((w_lds ? (size_t)njk * K : 0) + per) * sizeof(float);
-    k_m2l_general<<<ncell, 256, lds, s>>>(goff, gsrc, cells, p, KP, t.wm2l, w_lds, t.rcoef, M, L);
+    k_m2l_general<<<ncell, 256, lds, s>>>(goff, gsrc, cells, p, KP, t.wm2l, w_lds, t.rcoef, M, L, skip);
 }
 
 }  // namespace fmm
