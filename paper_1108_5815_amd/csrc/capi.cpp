@@ -739,16 +739,18 @@ void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
         }
         c->gp.J = J;
         c->gp.G = gemm_slot_groups(J);
+        if (J / c->gp.G + 1 > kGemmMaxGroupSlots) fail(FMM_ERR_UNSUPPORTED, "M2L slot groups exceed the staged size");
         c->gp.ntiles = tiles;
         c->gp.nrows = h9[8];
         c->ntiles = tiles;
         c->nrows = h9[8];
         int32_t* ro = need<int32_t>(c, c->rowof, nc);
         fill_i32(ro, -1, nc, s);
-        rows_inverse(rv, c->nrows, ro, s);
-        int32_t* ga = need<int32_t>(c, c->gather, (size_t)std::max<int64_t>(c->nrows, 1) * J);
-        fill_i32(ga, -1, c->nrows * J, s);
-        m2l_fill_gather(tg0, sr0, nm, ca, (int32_t*)c->d_slot.p, R, ro, J, ga, gen, s);
+        rows_inverse(rv, c->nrows, c->gp, tc, ro, s);
+        const int64_t ngather = (int64_t)tiles * tc * J;
+        int32_t* ga = need<int32_t>(c, c->gather, (size_t)std::max<int64_t>(ngather, 1));
+        fill_i32(ga, -1, ngather, s);
+        m2l_fill_gather(tg0, sr0, nm, ca, (int32_t*)c->d_slot.p, R, ro, J, tc, ga, gen, s);
         check_launch("m2l gather");
         int32_t* act = need<int32_t>(c, c->tact, (size_t)std::max(tiles, 1) * J);
         int32_t* nact = need<int32_t>(c, c->tnact, (size_t)std::max(tiles, 1));

@@ -133,15 +133,18 @@ void split_pairs(const int2* pairs, int64_t n, uint32_t* tgt, uint32_t* src, hip
 void csr_offsets(const uint32_t* tgt_sorted, int64_t n, int32_t ncell, int32_t* offsets,
                  hipStream_t s);
 
+struct GemmPlan;
+
 // M2L same-level batching: classify each M2L pair (sorted by target).
 //   slot_of   lookup table [8][(2R+1)^3] (offset -> slot or -1)
-//   rowof     [ncell] GEMM row of the target or -1
-//   gather    [nrows][J] source cell or -1
+//   rowof     [ncell] tile * NT + column of the target's GEMM row, or -1
+//   gather    [ntiles][J][NT] source cell or -1 (per tile and slot, the
+//             tile's NT columns contiguous; padding columns stay -1)
 //   general   flag per pair (1 = not handled by the GEMM)
 void m2l_mark_targets(const uint32_t* tgt, const uint32_t* src, int64_t n, CellArrays cells,
                       const int32_t* slot_of, int R, uint32_t* has_fast, hipStream_t s);
 void m2l_fill_gather(const uint32_t* tgt, const uint32_t* src, int64_t n, CellArrays cells,
-                     const int32_t* slot_of, int R, const int32_t* rowof, int32_t J,
+                     const int32_t* slot_of, int R, const int32_t* rowof, int32_t J, int NT,
                      int32_t* gather, uint32_t* general, hipStream_t s);
 // row keys of the M2L GEMM: (octant class << kRowMissBits) | missing slots
 // (densest first); cells without same-level pairs get class 8
@@ -149,7 +152,8 @@ constexpr int kRowMissBits = 10;
 constexpr uint32_t kRowMissMax = (1u << kRowMissBits) - 1;
 void row_class_keys(const uint32_t* nfast, CellArrays cells, int32_t ncell, int32_t J, uint32_t* key,
                     uint32_t* val, hipStream_t s);
-void rows_inverse(const uint32_t* rowcell, int64_t nrows, int32_t* rowof, hipStream_t s);
+// rowof[rowcell[r]] = tile * NT + column of GEMM row r (plan's class tables set)
+void rows_inverse(const uint32_t* rowcell, int64_t nrows, GemmPlan plan, int NT, int32_t* rowof, hipStream_t s);
 // keep the pairs whose flag is set: out[pos[i]] = pair i (pos = exclusive scan of flag)
 void compact_pairs(const uint32_t* tgt, const uint32_t* src, const uint32_t* flag, const uint32_t* pos, int64_t n,
                    uint32_t* otgt, uint32_t* osrc, hipStream_t s);
@@ -235,6 +239,9 @@ struct GemmPlan {
 // slot groups for J slots per class: each group's operators (J/G blocks of
 // 64 KB at storage width 128) should stay well inside one XCD's 4 MB L2
 int gemm_slot_groups(int J);
+// a group holds at most J / G + 1 slots (33 with G = 8 ceil(J / 256)); the GEMM
+// kernels stage a group's slots and operator ids in LDS arrays of this size
+constexpr int kGemmMaxGroupSlots = 64;
 // act[tile * J + k], k < nact[tile]: the slots of tile `tile` that some row uses
 void tile_slots(const int32_t* gather, GemmPlan plan, int NT, int ntiles, int32_t* act, int32_t* nact,
                 hipStream_t s);

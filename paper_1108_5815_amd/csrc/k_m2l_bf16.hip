@@ -14,6 +14,8 @@
 // multipoles are split once per evaluation (k_split_cells: [cell][hi, lo]
 // [KP/8] blocks of 8 bf16), so staging a gathered source vector into LDS is a
 // plain copy.
+#include <type_traits>
+
 #include "fmm_internal.h"
 
 namespace fmm {
@@ -52,21 +54,23 @@ __device__ inline void gemm_item(const GemmPlan& plan, int& tile, int& g) {
     g = (int)(b & 7u) + 8 * (int)(rest / (unsigned)plan.ntiles);
 }
 
-template <int KP, int NT, int RW, int CW>
-__global__ __launch_bounds__(256) void k_m2l_bf16(const uint4* __restrict__ Thi, const uint4* __restrict__ Tlo,
+template <int KP, int NT, int RW, int CW, int NQ>
+__global__ __launch_bounds__(64 * RW * CW) void k_m2l_bf16(const uint4* __restrict__ Thi, const uint4* __restrict__ Tlo,
                                                   const int32_t* __restrict__ offid,
                                                   const int32_t* __restrict__ gather, GemmPlan plan,
                                                   const uint4* __restrict__ Ms, float* __restrict__ part) {
     constexpr int KB = KP / 8;          // 8-wide K blocks
     constexpr int KS = KP / 16;         // MFMA K steps (16 values each)
     constexpr int RB = KP / 32, CB = NT / 32;
-    static_assert(RB % RW == 0 && CB % CW == 0 && RW * CW == 4, "wave grid");
+    constexpr int NTH = 64 * RW * CW;   // lanes of the workgroup
+    static_assert(RB % RW == 0 && CB % CW == 0, "wave grid");
     constexpr int NRB = RB / RW, NCB = CB / CW;
     constexpr int STR = KB + 1;         // LDS row stride in 16-byte units
-    constexpr int BV = NT * 2 * KB / 256;  // 16-byte blocks per thread per source tile (hi and lo)
-    static_assert((NT * 2 * KB) % 256 == 0, "tile shape");
-    __shared__ u32x4 Bhi[2][NT * STR];
-    __shared__ u32x4 Blo[2][NT * STR];
+    constexpr int HL = NT * STR;        // one half (hi or lo) of a source tile
+    constexpr int BV = NT * 2 * KB / NTH;  // 16-byte blocks per thread per source tile (hi and lo)
+    static_assert((NT * 2 * KB) % NTH == 0, "tile shape");
+    __shared__ u32x4 Bs[2][2 * HL];     // [buffer][hi tile, lo tile]
+    __shared__ int32_t s_slot[kGemmMaxGroupSlots], s_op[kGemmMaxGroupSlots];
 
     int tile, g;
     gemm_item(plan, tile, g);
@@ -78,14 +82,20 @@ __global__ __launch_bounds__(256) void k_m2l_bf16(const uint4* __restrict__ Thi,
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int l32 = lane & 31, h = lane >> 5;
     const int wr = w % RW, wc = w / RW;
-    const int32_t* oid = offid + (size_t)cls * J;
     // this group's slots [g J / G, (g + 1) J / G), restricted to those some row
     // of the tile uses: fixed slot ranges make each row's partial independent
     // of the other rows of its tile
     const int32_t* act = plan.act + (size_t)tile * J;
     const int na = plan.nact[tile];
     const int k0 = lower_slot(act, na, (int)(((int64_t)g * J) / plan.G));
-    const int k1 = lower_slot(act, na, (int)(((int64_t)(g + 1) * J) / plan.G));
+    const int n = lower_slot(act, na, (int)(((int64_t)(g + 1) * J) / plan.G)) - k0;
+    // the group's slots and their operators, staged once (n <= J / G + 1)
+    for (int i = threadIdx.x; i < n; i += NTH) {
+        const int j = act[k0 + i];
+        s_slot[i] = j;
+        s_op[i] = offid[(size_t)cls * J + j];
+    }
+    __syncthreads();
 
     floatx16 acc[NRB][NCB];
 #pragma unroll
@@ -95,51 +105,54 @@ __global__ __launch_bounds__(256) void k_m2l_bf16(const uint4* __restrict__ Thi,
 #pragma unroll
             for (int r = 0; r < 16; r++) acc[i][b][r] = 0.f;
 
+    // Every load below is issued on every path, with the slot index clamped
+    // to the group's last slot where the pipeline runs past it: loads
+    // complete in issue order, and a load count that depends on the path
+    // would force the wait for one operator part to drain every later load.
     u32x4 breg[BV];
-    // gathered sources of slot k: all index loads first, then unconditional
-    // data loads (absent sources read the zero row), so they overlap
-    auto load_B = [&](int k) {
-        const int j = act[k];
-        int sidx[BV];
+    // gathered sources: the tile's source indices of a slot are contiguous
+    // (gather[tile][slot][NT], padding columns -1) and are loaded one slot
+    // before the data; the data loads read the zero row for absent sources
+    int sidx[BV];
+    auto load_idx = [&](int i) {
+        const int32_t* gk = gather + ((size_t)tile * J + s_slot[min(i, n - 1)]) * NT;
+#pragma unroll
+        for (int v = 0; v < BV; v++) sidx[v] = gk[(threadIdx.x + NTH * v) / (2 * KB)];
+    };
+    auto load_data = [&]() {
 #pragma unroll
         for (int v = 0; v < BV; v++) {
-            const int col = (threadIdx.x + 256 * v) / (2 * KB);
-            sidx[v] = gather[(size_t)(r0 + min(col, nrow - 1)) * J + j];
-        }
-#pragma unroll
-        for (int v = 0; v < BV; v++) {
-            const int idx = threadIdx.x + 256 * v;
+            const int idx = threadIdx.x + NTH * v;
             const int col = idx / (2 * KB), rem = idx - col * (2 * KB);
-            const int s = (col < nrow && sidx[v] >= 0) ? sidx[v] : plan.zcell;
+            const int s = sidx[v] >= 0 ? sidx[v] : plan.zcell;
             breg[v] = reinterpret_cast<const u32x4*>(Ms)[(size_t)s * 2 * KB + rem];
         }
     };
     auto store_B = [&](int buf) {
 #pragma unroll
         for (int v = 0; v < BV; v++) {
-            const int idx = threadIdx.x + 256 * v;
+            const int idx = threadIdx.x + NTH * v;
             const int col = idx / (2 * KB), rem = idx - col * (2 * KB);
-            if (rem < KB) Bhi[buf][col * STR + rem] = breg[v];
-            else Blo[buf][col * STR + rem - KB] = breg[v];
+            const int half = rem >= KB ? 1 : 0;
+            Bs[buf][half * HL + col * STR + rem - half * KB] = breg[v];
         }
     };
     // operator fragments stream through two register buffers in NQ parts of a
-    // slot (SC steps each; NQ = 2, or 4 at the widest storage): the next part
-    // (of this slot, or the first part of the next slot) loads while the
-    // current part computes.  Step s, half h of the wave -> K block 2s + h.
-    constexpr int NQ = KP > 128 ? 4 : 2;
+    // slot (SC steps each): the next part (of this slot, or the first part of
+    // the next slot) loads while the current part computes, so operator loads
+    // run one part ahead.  Step s, half h of the wave -> K block 2s + h.
     constexpr int SC = KS / NQ;
     static_assert(KS % NQ == 0, "slot parts");
     u32x4 ah[2][NRB][SC], al[2][NRB][SC];
-    auto load_A = [&](int k, int half, int buf) {
-        const size_t base = (size_t)oid[act[k]] * KB * KP;
+    auto load_A = [&](int op, int half, int buf) {
+        const size_t base = (size_t)op * KB * KP;
 #pragma unroll
-        for (int i = 0; i < NRB; i++)
+        for (int r = 0; r < NRB; r++)
 #pragma unroll
             for (int s = 0; s < SC; s++) {
-                const size_t ix = base + (size_t)(2 * (half * SC + s) + h) * KP + (wr + RW * i) * 32 + l32;
-                ah[buf][i][s] = reinterpret_cast<const u32x4*>(Thi)[ix];
-                al[buf][i][s] = reinterpret_cast<const u32x4*>(Tlo)[ix];
+                const size_t ix = base + (size_t)(2 * (half * SC + s) + h) * KP + (wr + RW * r) * 32 + l32;
+                ah[buf][r][s] = reinterpret_cast<const u32x4*>(Thi)[ix];
+                al[buf][r][s] = reinterpret_cast<const u32x4*>(Tlo)[ix];
             }
     };
     auto compute = [&](int bbuf, int half, int abuf) {
@@ -149,8 +162,8 @@ __global__ __launch_bounds__(256) void k_m2l_bf16(const uint4* __restrict__ Thi,
 #pragma unroll
             for (int b = 0; b < NCB; b++) {
                 const int col = (wc + CW * b) * 32 + l32;
-                const u32x4 bh = Bhi[bbuf][col * STR + 2 * st + h];
-                const u32x4 bl = Blo[bbuf][col * STR + 2 * st + h];
+                const u32x4 bh = Bs[bbuf][col * STR + 2 * st + h];
+                const u32x4 bl = Bs[bbuf][HL + col * STR + 2 * st + h];
                 const bf16x8 vbh = __builtin_bit_cast(bf16x8, bh);
                 const bf16x8 vbl = __builtin_bit_cast(bf16x8, bl);
 #pragma unroll
@@ -165,23 +178,46 @@ __global__ __launch_bounds__(256) void k_m2l_bf16(const uint4* __restrict__ Thi,
         }
     };
 
-    if (k1 > k0) {
-        load_B(k0);
-        store_B(0);
-        load_A(k0, 0, 0);
-        __syncthreads();
-        for (int k = k0; k < k1; k++) {
-            const int bb = (k - k0) & 1;
-            const bool more = k + 1 < k1;
-            if (more) load_B(k + 1);
+    // slot i of the group; P0 = register buffer of its first part (buffers
+    // alternate by part, so with an odd number of parts the slots alternate
+    // too).  The next slot's gathers (the slowest loads) are issued after
+    // this slot's second operator part, so waiting for that part does not
+    // wait for them; they are needed only at the slot's end.
+    auto slot = [&](int i, auto P0) {
+        constexpr int p0 = decltype(P0)::value;
+        const int bb = i & 1;
+        const int op = s_op[i], op_next = s_op[min(i + 1, n - 1)];
 #pragma unroll
-            for (int q = 0; q < NQ; q++) {
-                if (q + 1 < NQ) load_A(k, q + 1, (q + 1) & 1);
-                else if (more) load_A(k + 1, 0, 0);
-                compute(bb, q, q & 1);
+        for (int q = 0; q < NQ; q++) {
+            if (q + 1 < NQ) load_A(op, q + 1, (p0 + q + 1) & 1);
+            else load_A(op_next, 0, (p0 + q + 1) & 1);
+            if (q == 0) {
+                load_data();      // slot i + 1 (indices loaded during slot i - 1)
+                load_idx(i + 2);
             }
-            if (more) store_B(bb ^ 1);
-            __syncthreads();
+            // keep the loads ahead of this part's products (the scheduler
+            // would otherwise sink each load next to its first use)
+            __builtin_amdgcn_sched_barrier(0);
+            compute(bb, q, (p0 + q) & 1);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        store_B(bb ^ 1);          // past the last slot: a copy nobody reads
+        __syncthreads();
+    };
+    if (n > 0) {
+        load_idx(0);
+        load_data();
+        store_B(0);
+        load_idx(1);
+        load_A(s_op[0], 0, 0);
+        __syncthreads();
+        if constexpr (NQ % 2 == 0) {
+            for (int i = 0; i < n; i++) slot(i, std::integral_constant<int, 0>{});
+        } else {
+            for (int i = 0; i < n; i += 2) {
+                slot(i, std::integral_constant<int, 0>{});
+                if (i + 1 < n) slot(i + 1, std::integral_constant<int, 1>{});
+            }
         }
     }
     // partial locals of this group (zero when it has no slots)
@@ -197,10 +233,10 @@ __global__ __launch_bounds__(256) void k_m2l_bf16(const uint4* __restrict__ Thi,
     }
 }
 
-template <int KP, int NT, int RW, int CW>
+template <int KP, int NT, int RW, int CW, int NQ>
 void launch(const uint16_t* Thi, const uint16_t* Tlo, const int32_t* offid, const int32_t* gather, GemmPlan plan,
             const uint4* Ms, float* part, hipStream_t s) {
-    k_m2l_bf16<KP, NT, RW, CW><<<plan.ntiles * plan.G, 256, 0, s>>>((const uint4*)Thi, (const uint4*)Tlo, offid,
+    k_m2l_bf16<KP, NT, RW, CW, NQ><<<plan.ntiles * plan.G, 64 * RW * CW, 0, s>>>((const uint4*)Thi, (const uint4*)Tlo, offid,
                                                                          gather, plan, Ms, part);
 }
 
@@ -238,11 +274,11 @@ void m2l_gemm_bf16(const uint16_t* Thi, const uint16_t* Tlo, const int32_t* offi
     const int64_t nb = (ncell + 1) * KB;  // with the zero row
     k_split_cells<<<(unsigned)((nb + 255) / 256), 256, 0, s>>>((const float4*)M, ncell + 1, KB, Ms);
     switch (KP) {
-        case 32: launch<32, 128, 1, 4>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
-        case 64: launch<64, 128, 2, 2>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
-        case 96: launch<96, 128, 1, 4>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
-        case 128: launch<128, 64, 4, 1>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
-        case 192: launch<192, 64, 2, 2>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
+        case 32: launch<32, 128, 1, 4, 2>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
+        case 64: launch<64, 128, 2, 2, 2>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
+        case 96: launch<96, 128, 3, 4, 2>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
+        case 128: launch<128, 64, 4, 1, 2>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
+        case 192: launch<192, 64, 2, 2, 4>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
         default: return;
     }
     m2l_reduce_groups(part, plan, rowcell, KP, ncoef(p), L, s);

@@ -23,16 +23,20 @@
 // part[g][row]; m2l_reduce_groups sums the groups in order.  A row's result
 // therefore depends only on its own sources, whatever rows share its tile.
 //
-// Tiling (gfx950, wave64, v_mfma_f32_32x32x2f32): a 256-lane workgroup owns
-// KP x NT outputs split over a RW x CW grid of waves; each wave keeps
+// Tiling (gfx950, wave64, v_mfma_f32_32x32x2f32): a workgroup owns KP x NT
+// outputs split over a RW x CW grid of waves; each wave keeps
 // NRB x NCB 32x32 accumulator blocks.  The K index of step s, half h of the
 // wave, is h*KS + s, so each lane reads its source vector contiguously
 // (float4 LDS reads cover 4 steps).  Operator fragments stream from global
 // memory (k-major, one 128-byte line per half-wave) through a register
-// pipeline one 16-step chunk ahead; the next slot's 64 or 128 gathered source
+// pipeline one chunk (CH steps) ahead; the next slot's 64 or 128 gathered source
 // vectors are loaded into registers during the current slot and written to
-// the other half of a double-buffered LDS tile.
+// the other half of a double-buffered LDS tile.  At storage width 96 the
+// 3 x 4 wave grid gives each wave one accumulator block: every operator row
+// block is read by the 4 waves of its row (L1 hits after the first), and 12
+// waves per CU hide the load latency that one wave per SIMD could not.
 #include <algorithm>
+#include <type_traits>
 
 #include "fmm_internal.h"
 
@@ -63,20 +67,21 @@ __device__ inline void gemm_item(const GemmPlan& plan, int& tile, int& g) {
     g = (int)(b & 7u) + 8 * (int)(rest / (unsigned)plan.ntiles);
 }
 
-template <int KP, int NT, int RW, int CW>
-__global__ __launch_bounds__(256) void k_m2l_gemm(const float* __restrict__ T, const int32_t* __restrict__ offid,
+template <int KP, int NT, int RW, int CW, int CH>
+__global__ __launch_bounds__(64 * RW * CW) void k_m2l_gemm(const float* __restrict__ T, const int32_t* __restrict__ offid,
                                                   const int32_t* __restrict__ gather, GemmPlan plan,
                                                   const float* __restrict__ M, float* __restrict__ part) {
     constexpr int KS = KP / 2;
     constexpr int RB = KP / 32, CB = NT / 32;
-    static_assert(RB % RW == 0 && CB % CW == 0 && RW * CW == 4, "wave grid");
+    constexpr int NTH = 64 * RW * CW;   // lanes of the workgroup
+    static_assert(RB % RW == 0 && CB % CW == 0, "wave grid");
     constexpr int NRB = RB / RW, NCB = CB / CW;
     constexpr int STR = KP + 4;
-    constexpr int CH = 16;
-    constexpr int NCH = KS / CH;
-    constexpr int BV = NT * KP / 1024;  // float4 per thread per source tile
-    static_assert(KS % CH == 0 && (NT * KP) % 1024 == 0, "tile shape");
+    constexpr int NCH = KS / CH;        // operator chunks (CH steps each) per slot
+    constexpr int BV = NT * KP / (4 * NTH);  // float4 per thread per source tile
+    static_assert(KS % CH == 0 && CH % 4 == 0 && (NT * KP) % (4 * NTH) == 0, "tile shape");
     __shared__ __attribute__((aligned(16))) float Bs[2][NT * STR];
+    __shared__ int32_t s_slot[kGemmMaxGroupSlots], s_op[kGemmMaxGroupSlots];
 
     int tile, g;
     gemm_item(plan, tile, g);
@@ -88,14 +93,20 @@ __global__ __launch_bounds__(256) void k_m2l_gemm(const float* __restrict__ T, c
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int l32 = lane & 31, h = lane >> 5;
     const int wr = w % RW, wc = w / RW;
-    const int32_t* oid = offid + (size_t)cls * J;
     // this group's slots [g J / G, (g + 1) J / G), restricted to those some row
     // of the tile uses: fixed slot ranges make each row's partial independent
     // of the other rows of its tile
     const int32_t* act = plan.act + (size_t)tile * J;
     const int na = plan.nact[tile];
     const int k0 = lower_slot(act, na, (int)(((int64_t)g * J) / plan.G));
-    const int k1 = lower_slot(act, na, (int)(((int64_t)(g + 1) * J) / plan.G));
+    const int n = lower_slot(act, na, (int)(((int64_t)(g + 1) * J) / plan.G)) - k0;
+    // the group's slots and their operators, staged once (n <= J / G + 1)
+    for (int i = threadIdx.x; i < n; i += NTH) {
+        const int j = act[k0 + i];
+        s_slot[i] = j;
+        s_op[i] = offid[(size_t)cls * J + j];
+    }
+    __syncthreads();
 
     floatx16 acc[NRB][NCB];
 #pragma unroll
@@ -105,42 +116,47 @@ __global__ __launch_bounds__(256) void k_m2l_gemm(const float* __restrict__ T, c
 #pragma unroll
             for (int r = 0; r < 16; r++) acc[i][b][r] = 0.f;
 
+    // Every load below is issued on every path, with the slot index clamped
+    // to the group's last slot where the pipeline runs past it: loads
+    // complete in issue order, and a load count that depends on the path
+    // would force the wait for one operator chunk to drain every later load.
     f32x4 breg[BV];
-    // gathered sources of slot k: all index loads first, then unconditional
-    // data loads (absent sources read the zero row), so they overlap
-    auto load_B = [&](int k) {
-        const int j = act[k];
-        int sidx[BV];
+    // gathered sources: the tile's source indices of a slot are contiguous
+    // (gather[tile][slot][NT], padding columns -1) and are loaded one slot
+    // before the data; the data loads read the zero row for absent sources
+    int sidx[BV];
+    auto load_idx = [&](int i) {
+        const int32_t* gk = gather + ((size_t)tile * J + s_slot[min(i, n - 1)]) * NT;
+#pragma unroll
+        for (int v = 0; v < BV; v++) sidx[v] = gk[(threadIdx.x + NTH * v) / (KP / 4)];
+    };
+    auto load_data = [&]() {
 #pragma unroll
         for (int v = 0; v < BV; v++) {
-            const int col = (threadIdx.x + 256 * v) / (KP / 4);
-            sidx[v] = gather[(size_t)(r0 + min(col, nrow - 1)) * J + j];
-        }
-#pragma unroll
-        for (int v = 0; v < BV; v++) {
-            const int idx = threadIdx.x + 256 * v;
+            const int idx = threadIdx.x + NTH * v;
             const int col = idx / (KP / 4), k4 = idx - col * (KP / 4);
-            const int s = (col < nrow && sidx[v] >= 0) ? sidx[v] : plan.zcell;
+            const int s = sidx[v] >= 0 ? sidx[v] : plan.zcell;
             breg[v] = reinterpret_cast<const f32x4*>(M + (size_t)s * KP)[k4];
         }
     };
     auto store_B = [&](int buf) {
 #pragma unroll
         for (int v = 0; v < BV; v++) {
-            int idx = threadIdx.x + 256 * v;
+            int idx = threadIdx.x + NTH * v;
             int col = idx / (KP / 4), k4 = idx - col * (KP / 4);
             *reinterpret_cast<f32x4*>(&Bs[buf][col * STR + 4 * k4]) = breg[v];
         }
     };
-    float a0[NRB][CH], a1[NRB][CH];
-    auto load_A = [&](const float* A, int c, float (&a)[NRB][CH]) {
+    float ab[2][NRB][CH];
+    auto load_A = [&](int op, int c, int buf) {
+        const float* A = T + (size_t)op * KP * KP;
 #pragma unroll
-        for (int i = 0; i < NRB; i++)
+        for (int r = 0; r < NRB; r++)
 #pragma unroll
             for (int t = 0; t < CH; t++)
-                a[i][t] = A[(size_t)(h * KS + c * CH + t) * KP + (wr + RW * i) * 32 + l32];
+                ab[buf][r][t] = A[(size_t)(h * KS + c * CH + t) * KP + (wr + RW * r) * 32 + l32];
     };
-    auto compute = [&](int buf, int c, const float (&a)[NRB][CH]) {
+    auto compute = [&](int buf, int c, int abuf) {
 #pragma unroll
         for (int t = 0; t < CH; t += 4) {
             f32x4 b4[NCB];
@@ -156,44 +172,53 @@ __global__ __launch_bounds__(256) void k_m2l_gemm(const float* __restrict__ T, c
                     float bv = b4[b][u];
 #pragma unroll
                     for (int i = 0; i < NRB; i++)
-                        acc[i][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][t + u], bv, acc[i][b], 0, 0, 0);
+                        acc[i][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(ab[abuf][i][t + u], bv, acc[i][b], 0,
+                                                                         0, 0);
                 }
         }
     };
 
-    if (k1 > k0) {
-    load_B(k0);
-    store_B(0);
-    load_A(T + (size_t)oid[act[k0]] * KP * KP, 0, a0);
-    __syncthreads();
-    for (int k = k0; k < k1; k++) {
-        const int buf = (k - k0) & 1;
-        const bool more = k + 1 < k1;
-        if (more) load_B(k + 1);
-        const float* Aj = T + (size_t)oid[act[k]] * KP * KP;
-        const float* An = T + (size_t)oid[act[more ? k + 1 : k]] * KP * KP;
-        // chunk pipeline: chunk c computes from the register set loaded one chunk earlier
+    // slot i of the group; P0 = register buffer of its first chunk (buffers
+    // alternate by chunk, so with an odd number of chunks the slots alternate
+    // too).  The next slot's gathers (the slowest loads) are issued after
+    // this slot's second operator chunk, so waiting for that chunk does not
+    // wait for them; they are needed only at the slot's end.
+    auto slot = [&](int i, auto P0) {
+        constexpr int p0 = decltype(P0)::value;
+        const int buf = i & 1;
+        const int op = s_op[i], op_next = s_op[min(i + 1, n - 1)];
 #pragma unroll
         for (int c = 0; c < NCH; c++) {
-            if ((c & 1) == 0) {
-                if (c + 1 < NCH) load_A(Aj, c + 1, a1);
-                else load_A(An, 0, a1);
-                compute(buf, c, a0);
-            } else {
-                if (c + 1 < NCH) load_A(Aj, c + 1, a0);
-                else load_A(An, 0, a0);
-                compute(buf, c, a1);
+            if (c + 1 < NCH) load_A(op, c + 1, (p0 + c + 1) & 1);
+            else load_A(op_next, 0, (p0 + c + 1) & 1);
+            if (c == 0) {
+                load_data();      // slot i + 1 (indices loaded during slot i - 1)
+                load_idx(i + 2);
+            }
+            // keep the loads ahead of this chunk's products (the scheduler
+            // would otherwise sink each load next to its first use)
+            __builtin_amdgcn_sched_barrier(0);
+            compute(buf, c, (p0 + c) & 1);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        store_B(buf ^ 1);         // past the last slot: a copy nobody reads
+        __syncthreads();
+    };
+    if (n > 0) {
+        load_idx(0);
+        load_data();
+        store_B(0);
+        load_idx(1);
+        load_A(s_op[0], 0, 0);
+        __syncthreads();
+        if constexpr (NCH % 2 == 0) {
+            for (int i = 0; i < n; i++) slot(i, std::integral_constant<int, 0>{});
+        } else {
+            for (int i = 0; i < n; i += 2) {
+                slot(i, std::integral_constant<int, 0>{});
+                if (i + 1 < n) slot(i + 1, std::integral_constant<int, 1>{});
             }
         }
-        if (NCH & 1) {
-#pragma unroll
-            for (int i = 0; i < NRB; i++)
-#pragma unroll
-                for (int t = 0; t < CH; t++) a0[i][t] = a1[i][t];
-        }
-        if (more) store_B(buf ^ 1);
-        __syncthreads();
-    }
     }
     // partial locals of this group (zero when it has no slots)
 #pragma unroll
@@ -230,10 +255,10 @@ __global__ void k_reduce_groups(const float4* __restrict__ part, int G, int nrow
         if (4 * k4 + e < K) dst[e] = vals[e];
 }
 
-template <int KP, int NT, int RW, int CW>
+template <int KP, int NT, int RW, int CW, int CH>
 void launch(const float* T, const int32_t* offid, const int32_t* gather, GemmPlan plan, const float* M, float* part,
             hipStream_t s) {
-    k_m2l_gemm<KP, NT, RW, CW><<<plan.ntiles * plan.G, 256, 0, s>>>(T, offid, gather, plan, M, part);
+    k_m2l_gemm<KP, NT, RW, CW, CH><<<plan.ntiles * plan.G, 64 * RW * CW, 0, s>>>(T, offid, gather, plan, M, part);
 }
 
 }  // namespace
@@ -263,12 +288,12 @@ void m2l_gemm(const float* T, const int32_t* offid, const int32_t* gather, const
               int p, int KP, const float* M, float* part, float* L, hipStream_t s) {
     if (plan.ntiles <= 0) return;
     switch (KP) {
-        case 32: launch<32, 128, 1, 4>(T, offid, gather, plan, M, part, s); break;
-        case 64: launch<64, 128, 2, 2>(T, offid, gather, plan, M, part, s); break;
-        case 96: launch<96, 128, 1, 4>(T, offid, gather, plan, M, part, s); break;
-        case 128: launch<128, 64, 4, 1>(T, offid, gather, plan, M, part, s); break;
-        case 192: launch<192, 64, 2, 2>(T, offid, gather, plan, M, part, s); break;
-        case 256: launch<256, 64, 4, 1>(T, offid, gather, plan, M, part, s); break;
+        case 32: launch<32, 128, 1, 4, 16>(T, offid, gather, plan, M, part, s); break;
+        case 64: launch<64, 128, 2, 2, 16>(T, offid, gather, plan, M, part, s); break;
+        case 96: launch<96, 128, 3, 4, 8>(T, offid, gather, plan, M, part, s); break;
+        case 128: launch<128, 64, 4, 1, 16>(T, offid, gather, plan, M, part, s); break;
+        case 192: launch<192, 64, 2, 2, 8>(T, offid, gather, plan, M, part, s); break;
+        case 256: launch<256, 64, 4, 1, 8>(T, offid, gather, plan, M, part, s); break;
         default: return;
     }
     m2l_reduce_groups(part, plan, rowcell, KP, ncoef(p), L, s);

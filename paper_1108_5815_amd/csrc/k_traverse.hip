@@ -193,14 +193,16 @@ __global__ __launch_bounds__(256) void k_mark_targets(const uint32_t* __restrict
 
 __global__ void k_fill_gather(const uint32_t* __restrict__ tgt, const uint32_t* __restrict__ src, int64_t n,
                               CellArrays c, const int32_t* __restrict__ slot_of, int R,
-                              const int32_t* __restrict__ rowof, int32_t J, int32_t* __restrict__ gather,
+                              const int32_t* __restrict__ rowof, int32_t J, int NT, int32_t* __restrict__ gather,
                               uint32_t* __restrict__ general) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int32_t t = (int32_t)tgt[i], s = (int32_t)src[i];
     int32_t sl = fast_slot(c, t, s, slot_of, R);
     if (sl >= 0) {
-        gather[(int64_t)rowof[t] * J + sl] = s;
+        const int32_t pr = rowof[t];  // tile * NT + column
+        const int32_t tile = pr / NT;
+        gather[((int64_t)tile * J + sl) * NT + (pr - tile * NT)] = s;
         general[i] = 0u;
     } else {
         general[i] = 1u;
@@ -222,10 +224,17 @@ __global__ void k_row_class_keys(const uint32_t* __restrict__ nfast, CellArrays 
     val[i] = (uint32_t)i;
 }
 
-__global__ void k_rows_inverse(const uint32_t* __restrict__ rowcell, int64_t nrows, int32_t* __restrict__ rowof) {
+// rowof[cell of row r] = tile * NT + column of row r in its tile (tiles hold
+// NT consecutive rows of one class; the last tile of a class may be short)
+__global__ void k_rows_inverse(const uint32_t* __restrict__ rowcell, int64_t nrows, GemmPlan plan, int NT,
+                               int32_t* __restrict__ rowof) {
     int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nrows) return;
-    rowof[rowcell[r]] = (int32_t)r;
+    int cls = 0;
+    while (cls < 7 && r >= plan.class_row0[cls + 1]) cls++;
+    const int32_t local = (int32_t)r - plan.class_row0[cls];
+    const int32_t tile = plan.class_tile0[cls] + local / NT;
+    rowof[rowcell[r]] = tile * NT + local % NT;
 }
 
 // Active slots of each GEMM tile (NT consecutive rows of one octant class):
@@ -235,26 +244,32 @@ __global__ void k_rows_inverse(const uint32_t* __restrict__ rowcell, int64_t nro
 __global__ __launch_bounds__(256) void k_tile_slots(const int32_t* __restrict__ gather, GemmPlan plan, int NT,
                                                     int32_t* __restrict__ act, int32_t* __restrict__ nact) {
     __shared__ int32_t wtot[4];
+    __shared__ uint8_t used[256];
     const int tile = blockIdx.x;
-    int cls = 0;
-    while (cls < 7 && tile >= plan.class_tile0[cls + 1]) cls++;
-    const int r0 = plan.class_row0[cls] + (tile - plan.class_tile0[cls]) * NT;
-    const int nrow = min(NT, plan.class_row0[cls + 1] - r0);
     const int J = plan.J;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const int32_t* gt = gather + (size_t)tile * J * NT;  // [slot][NT] of this tile
     int base = 0;
     for (int j0 = 0; j0 < J; j0 += 256) {
-        const int j = j0 + (int)threadIdx.x;
-        bool a = false;
-        if (j < J)
-            for (int r = 0; r < nrow && !a; r++) a = gather[(size_t)(r0 + r) * J + j] >= 0;
+        // slot j is used if any of the tile's NT entries is a source (padding is -1):
+        // each wave tests whole slots with coalesced reads
+        for (int jj = w; jj < 256; jj += 4) {
+            const int j = j0 + jj;
+            bool a = false;
+            if (j < J)
+                for (int r = lane; r < NT; r += 64) a = a || gt[(size_t)j * NT + r] >= 0;
+            const uint64_t m = __ballot(a);
+            if (lane == 0) used[jj] = m != 0ull;
+        }
+        __syncthreads();
+        const bool a = used[threadIdx.x] != 0;
         const uint64_t m = __ballot(a);
         if (lane == 0) wtot[w] = __popcll(m);
         __syncthreads();
         int off = base;
         for (int q = 0; q < w; q++) off += wtot[q];
-        if (a) act[(size_t)tile * J + off + __popcll(m & below)] = j;
+        if (a) act[(size_t)tile * J + off + __popcll(m & below)] = j0 + (int)threadIdx.x;
         base += wtot[0] + wtot[1] + wtot[2] + wtot[3];
         __syncthreads();
     }
@@ -306,10 +321,10 @@ void tile_slots(const int32_t* gather, GemmPlan plan, int NT, int ntiles, int32_
 }
 
 void m2l_fill_gather(const uint32_t* tgt, const uint32_t* src, int64_t n, CellArrays cells,
-                     const int32_t* slot_of, int R, const int32_t* rowof, int32_t J, int32_t* gather,
+                     const int32_t* slot_of, int R, const int32_t* rowof, int32_t J, int NT, int32_t* gather,
                      uint32_t* general, hipStream_t s) {
     if (n <= 0) return;
-    k_fill_gather<<<grid(n), 256, 0, s>>>(tgt, src, n, cells, slot_of, R, rowof, J, gather, general);
+    k_fill_gather<<<grid(n), 256, 0, s>>>(tgt, src, n, cells, slot_of, R, rowof, J, NT, gather, general);
 }
 
 void row_class_keys(const uint32_t* nfast, CellArrays cells, int32_t ncell, int32_t J, uint32_t* key, uint32_t* val,
@@ -318,9 +333,9 @@ void row_class_keys(const uint32_t* nfast, CellArrays cells, int32_t ncell, int3
     k_row_class_keys<<<grid(ncell), 256, 0, s>>>(nfast, cells, ncell, J, key, val);
 }
 
-void rows_inverse(const uint32_t* rowcell, int64_t nrows, int32_t* rowof, hipStream_t s) {
+void rows_inverse(const uint32_t* rowcell, int64_t nrows, GemmPlan plan, int NT, int32_t* rowof, hipStream_t s) {
     if (nrows <= 0) return;
-    k_rows_inverse<<<grid(nrows), 256, 0, s>>>(rowcell, nrows, rowof);
+    k_rows_inverse<<<grid(nrows), 256, 0, s>>>(rowcell, nrows, plan, NT, rowof);
 }
 
 }  // namespace fmm
