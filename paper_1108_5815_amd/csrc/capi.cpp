@@ -88,6 +88,7 @@ struct fmm_ctx_s {
     M2LPlan plan;
     Buf d_slot, d_offid, d_T, d_Thi, d_Tlo;
     bool plan_bf16 = false;
+    Buf inner, leafpos;  // non-leaf cells in cell order; leaves before each cell
     Buf has_fast, rkey, rval, rkey2, rval2, rowof, gather, general, gtg, gsr, goff, tact, tnact, m2l_part, Msplit, nbucket, kinds;
     // pairs outside the same-level tables, batched by class
     ClsPlan cp;
@@ -129,7 +130,7 @@ struct fmm_ctx_s {
                       &d_h, &d_rc, &d_mlp, &M, &L, &nearb, &tune_pts, &tune_out, &d_mlp_m, &d_mlp_v,
                       &d_grad, &d_grad_rec, &d_loss_rec, &d_feat, &d_kind, &d_tgt, &d_table, &d_Thi, &d_Tlo,
                       &d_seg, &d_bt, &d_pb, &d_box, &d_frame, &inst, &bsort, &tact, &tnact,
-                      &leaves_cls, &lkey, &lval, &lkey2, &lval2, &at_out, &m2l_part, &Msplit, &nbucket, &kinds, &ckey, &ckey2, &cval, &cval2,
+                      &leaves_cls, &inner, &leafpos, &lkey, &lval, &lkey2, &lval2, &at_out, &m2l_part, &Msplit, &nbucket, &kinds, &ckey, &ckey2, &cval, &cval2,
                       &chead, &choff, &cstart, &cpos, &csrcs, &cnt_t, &ctbase, &ctile, &cT, &cskip, &cls_part};
         for (Buf* b : all) bufs.push_back(b);
     }
@@ -445,7 +446,7 @@ void build_forest_impl(fmm_ctx c, int32_t nseg, const int64_t* hseg, int dtype, 
     check_launch("geometry");
     // leaves in cell order
     uint32_t* flag = need<uint32_t>(c, c->tmp1, total + 1);
-    uint32_t* pos = need<uint32_t>(c, c->tmp2, total + 1);
+    uint32_t* pos = need<uint32_t>(c, c->leafpos, total + 1);  // kept: the level translations read it
     if (scan_ws_bytes(total) > c->ws.cap) {
         ws = need<char>(c, c->ws, scan_ws_bytes(total));
         d6 = (double*)c->small.p;
@@ -453,7 +454,8 @@ void build_forest_impl(fmm_ctx c, int32_t nseg, const int64_t* hseg, int dtype, 
     leaf_flags(cells_of(c), total, flag, s);
     scan_u32(flag, pos, (uint32_t*)(d6 + 12), total, ws, s);
     int32_t* lv = need<int32_t>(c, c->leaves, total);
-    leaf_write(cells_of(c), total, pos, lv, s);
+    int32_t* inr = need<int32_t>(c, c->inner, total);
+    leaf_write(cells_of(c), total, pos, lv, inr, s);
     check_launch("leaves");
     uint32_t* hh = (uint32_t*)host_stage(c);
     to_host<uint32_t>(c, hh, d6 + 12, 1);
@@ -837,7 +839,10 @@ void evaluate_impl(fmm_ctx c, int32_t precision, int32_t out_dtype, void* phi, v
     mark(c, PH_UP);
     p2m((float4*)c->pts.p, ca, (int32_t*)c->leaves.p, c->nleaf, p, KP, tb.rcoef, M, s);
     int nlev = (int)c->lvl.size() - 1;
-    for (int Lv = nlev - 2; Lv >= 0; Lv--) m2m(ca, c->lvl[Lv], c->lvl[Lv + 1], p, KP, tb, M, s);
+    const int32_t* inr = (const int32_t*)c->inner.p;
+    const uint32_t* lpos = (const uint32_t*)c->leafpos.p;
+    for (int Lv = nlev - 2; Lv >= 0; Lv--)
+        m2m(ca, inr, lpos, c->lvl[Lv], c->lvl[Lv + 1], c->ncell, c->nleaf, p, KP, tb, M, s);
     check_launch("upward");
     if (sched == 2) fork_p2p();
     ck(hipMemsetAsync(L, 0, (size_t)nc * KP * sizeof(float), s), "memset");
@@ -865,7 +870,8 @@ void evaluate_impl(fmm_ctx c, int32_t precision, int32_t out_dtype, void* phi, v
                     c->cp.nbatched > 0 ? (const uint8_t*)c->cskip.p : nullptr, s);
     check_launch("m2l");
     mark(c, PH_DOWN);
-    for (int Lv = 1; Lv < nlev; Lv++) l2l(ca, c->lvl[Lv], c->lvl[Lv + 1], p, KP, tb, L, s);
+    for (int Lv = 0; Lv + 1 < nlev; Lv++)
+        l2l(ca, inr, lpos, c->lvl[Lv], c->lvl[Lv + 1], c->ncell, c->nleaf, p, KP, tb, L, s);
     check_launch("downward");
     mark(c, PH_P2P);
     if (sched) {

@@ -162,7 +162,9 @@ void compact_pairs(const uint32_t* tgt, const uint32_t* src, const uint32_t* fla
 void class_bounds(const uint32_t* key_sorted, int64_t n, int shift, int32_t* out9, hipStream_t s);
 // leaf cells (nchild == 0) in cell order; flag/pos are scratch of ncell entries
 void leaf_flags(CellArrays cells, int32_t ncell, uint32_t* flag, hipStream_t s);
-void leaf_write(CellArrays cells, int32_t ncell, const uint32_t* pos, int32_t* leaves, hipStream_t s);
+// leaves[pos[i]] = i for leaves, inner[i - pos[i]] = i for the other cells
+void leaf_write(CellArrays cells, int32_t ncell, const uint32_t* pos, int32_t* leaves, int32_t* inner,
+                hipStream_t s);
 
 // ------------------------------------------------------------------ expansions
 struct Tables {
@@ -176,10 +178,15 @@ struct Tables {
 };
 void p2m(const float4* pts, CellArrays cells, const int32_t* leaves, int32_t nleaves, int p,
          int KP, const float* rc, float* M, hipStream_t s);
-void m2m(CellArrays cells, int32_t c0, int32_t c1, int p, int KP, Tables t, float* M,
-         hipStream_t s);
-void l2l(CellArrays cells, int32_t c0, int32_t c1, int p, int KP, Tables t, float* L,
-         hipStream_t s);
+// One level of octant translations: the parents are the non-leaf cells of
+// cells [c0, c1) (one tree level), listed in `inner` (non-leaf cells in cell
+// order); leafpos[i] = number of leaves among cells [0, i) (i < ncell), nleaf
+// in all.  m2m: parents' multipoles from their children; l2l: children's
+// locals += translated parent local.
+void m2m(CellArrays cells, const int32_t* inner, const uint32_t* leafpos, int32_t c0, int32_t c1, int32_t ncell,
+         int32_t nleaf, int p, int KP, Tables t, float* M, hipStream_t s);
+void l2l(CellArrays cells, const int32_t* inner, const uint32_t* leafpos, int32_t c0, int32_t c1, int32_t ncell,
+         int32_t nleaf, int p, int KP, Tables t, float* L, hipStream_t s);
 // M2L of the pairs outside the batched GEMM, given as a CSR list by target,
 // one pair at a time (pairs with skip[a] != 0 are left out; skip may be null)
 void m2l_general(const int32_t* goff, const uint32_t* gsrc, CellArrays cells, int32_t ncell, int p, int KP,

@@ -151,50 +151,147 @@ __global__ __launch_bounds__(64) void k_p2m(const float4* __restrict__ pts, Cell
 }
 
 // ---------------------------------------------------------------- M2M / L2L
-__global__ __launch_bounds__(128) void k_m2m(CellArrays c, int32_t c0, int p, int KP,
-                                             const float* __restrict__ mat, float* __restrict__ M) {
-    extern __shared__ float sh[];
-    const int cell = c0 + blockIdx.x;
-    const int nch = c.nchild[cell];
-    if (nch == 0) return;
-    const int K = (p + 1) * (p + 1);
-    const int first = c.child[cell];
-    for (int i = threadIdx.x; i < nch * K; i += blockDim.x) {
-        int ch = i / K, k = i - ch * K;
-        sh[ch * KP + k] = M[(size_t)(first + ch) * KP + k];
+// One level's octant translations on the VALU, NB non-leaf parents per
+// workgroup.  The inputs of the batch are staged in LDS (M2M: the children of
+// every octant; L2L: the parents' locals); thread j of an octant streams the
+// operator column T_o[., j] from memory (coalesced over j, loads issued two
+// blocks of 8 ahead) and keeps the NB dot products of output j, so each
+// operator element feeds NB FMAs and each input read (an LDS broadcast) four.
+// OW octants run side by side in separate waves (8 for the small levels near
+// the root, where there are few parents to batch).  Per parent and octant the
+// dot product runs over k ascending (terms whose degrees do not couple are
+// exact zeros and the blocks holding only such terms are skipped per wave);
+// M2M then adds the 8 octant products in octant order, L2L adds each into its
+// child.  A parent's result therefore does not depend on NB, OW or the other
+// parents of its batch.
+template <bool UP, int NB, int OW, int NJ>
+__global__ __launch_bounds__(OW * NJ) void k_translate(CellArrays c, const int32_t* __restrict__ inner,
+                                                        const uint32_t* __restrict__ leafpos, int32_t c0,
+                                                        int32_t c1, int32_t ncell, int32_t nleaf, int K, int KP,
+                                                        const float* __restrict__ mat, float* __restrict__ X) {
+    constexpr int NTH = OW * NJ;
+    constexpr int KB = 8;  // k block of the operator stream
+    extern __shared__ __attribute__((aligned(16))) float sh[];
+    __shared__ int32_t sIn[8][NB];  // child of octant o of each parent, or -1
+    __shared__ int32_t sPar[NB];
+    const int tid = threadIdx.x;
+    const int KS = (K + KB - 1) / KB * KB;  // staged input stride (zero padded)
+    // this level's non-leaf cells: inner[n0 .. n1) (cells are numbered level by
+    // level; leafpos[i] = leaves among cells [0, i))
+    const int32_t n0 = c0 - (int32_t)leafpos[c0];
+    const int32_t n1 = c1 - (c1 < ncell ? (int32_t)leafpos[c1] : nleaf);
+    const int32_t b0 = n0 + (int32_t)blockIdx.x * NB;
+    if (b0 >= n1) return;
+    const int nb = min(NB, n1 - b0);
+    for (int i = tid; i < NB; i += NTH) {
+        int ch[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
+        const int P = i < nb ? inner[b0 + i] : -1;
+        if (P >= 0) {
+            const int f = c.child[P], n = c.nchild[P];
+            for (int q = 0; q < n; q++) ch[c.prefix[f + q] & 7u] = f + q;
+        }
+        sPar[i] = P;
+#pragma unroll
+        for (int o = 0; o < 8; o++) sIn[o][i] = ch[o];
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < KP; j += blockDim.x) {
-        float acc = 0.f;
-        if (j < K) {
-            int d = degree_of(j);
-            int kmax = (d + 1) * (d + 1);
-            for (int ch = 0; ch < nch; ch++) {
-                int oct = (int)(c.prefix[first + ch] & 7u);
-                const float* A = mat + (size_t)oct * K * K;
-                const float* v = sh + ch * KP;
-                for (int k = 0; k < kmax; k++) acc += A[(size_t)k * K + j] * v[k];
+    // inputs: M2M sV[o][cc][k] (children), L2L sV[cc][k] (parents)
+    float* sV = sh;
+    const int nin = (UP ? 8 : 1) * NB * KS;
+    for (int i = tid; i < nin; i += NTH) {
+        const int row = i / KS, k = i - row * KS;
+        const int src = UP ? sIn[row / NB][row % NB] : sPar[row];
+        sV[i] = (src >= 0 && k < K) ? X[(size_t)src * KP + k] : 0.f;
+    }
+    float* part = sh + nin;  // M2M with OW > 1: octant products [8][NB][NJ]
+    __syncthreads();
+    const int og = tid / NJ, jt = tid - og * NJ;
+    const int wave = jt >> 6;
+    for (int jb = 0; jb < KP; jb += NJ) {
+        const int j = jb + jt;
+        // inputs that can couple to this wave's outputs: [klo, khi)
+        const int jlo = min(jb + 64 * wave, K - 1), jhi = min(jb + 64 * wave + 63, K - 1);
+        const int dlo = degree_of(jlo), dhi = degree_of(jhi);
+        const int klo = UP ? 0 : (dlo * dlo) / KB * KB;
+        const int khi = UP ? min((dhi + 1) * (dhi + 1), K) : K;
+        float tot[NB];
+#pragma unroll
+        for (int cc = 0; cc < NB; cc++) tot[cc] = 0.f;
+        for (int o = og; o < 8; o += OW) {
+            const float* Vo = UP ? sV + (size_t)o * NB * KS : sV;
+            const float* To = mat + (size_t)o * K * K;  // wave-uniform base, 32-bit lane offsets
+            const int jj = j < K ? j : 0;
+            float acc[NB];
+#pragma unroll
+            for (int cc = 0; cc < NB; cc++) acc[cc] = 0.f;
+            float t0[KB], t1[KB];
+            auto load = [&](int k, float (&t)[KB]) {
+#pragma unroll
+                for (int i = 0; i < KB; i++) t[i] = (k + i < K && j < K) ? To[(k + i) * K + jj] : 0.f;
+            };
+            auto dot = [&](int k, const float (&t)[KB]) {
+#pragma unroll
+                for (int i = 0; i < KB; i += 4) {
+#pragma unroll
+                    for (int cc = 0; cc < NB; cc++) {
+                        const float4 v = *reinterpret_cast<const float4*>(&Vo[cc * KS + k + i]);
+                        acc[cc] = fmaf(t[i], v.x, acc[cc]);
+                        acc[cc] = fmaf(t[i + 1], v.y, acc[cc]);
+                        acc[cc] = fmaf(t[i + 2], v.z, acc[cc]);
+                        acc[cc] = fmaf(t[i + 3], v.w, acc[cc]);
+                    }
+                }
+            };
+            // two register blocks: the loads of block k + 2 KB are issued
+            // before the products of block k
+            int k = klo;
+            if (k < khi) load(k, t0);
+            if (k + KB < khi) load(k + KB, t1);
+            for (; k < khi; k += 2 * KB) {
+                float u[KB];
+#pragma unroll
+                for (int i = 0; i < KB; i++) u[i] = t0[i];
+                if (k + 2 * KB < khi) load(k + 2 * KB, t0);
+                dot(k, u);
+                if (k + KB < khi) {
+#pragma unroll
+                    for (int i = 0; i < KB; i++) u[i] = t1[i];
+                    if (k + 3 * KB < khi) load(k + 3 * KB, t1);
+                    dot(k + KB, u);
+                }
+            }
+            if (UP) {
+                if (OW == 1) {
+#pragma unroll
+                    for (int cc = 0; cc < NB; cc++) tot[cc] += acc[cc];
+                } else {
+#pragma unroll
+                    for (int cc = 0; cc < NB; cc++) part[((size_t)o * NB + cc) * NJ + jt] = acc[cc];
+                }
+            } else {
+#pragma unroll
+                for (int cc = 0; cc < NB; cc++) {
+                    const int ch = sIn[o][cc];
+                    if (ch >= 0 && j < K) X[(size_t)ch * KP + j] += acc[cc];
+                }
             }
         }
-        M[(size_t)cell * KP + j] = acc;
-    }
-}
-
-__global__ __launch_bounds__(128) void k_l2l(CellArrays c, int32_t c0, int p, int KP,
-                                             const float* __restrict__ mat, float* __restrict__ L) {
-    extern __shared__ float sh[];
-    const int cell = c0 + blockIdx.x;
-    const int par = c.parent[cell];
-    const int K = (p + 1) * (p + 1);
-    for (int k = threadIdx.x; k < K; k += blockDim.x) sh[k] = L[(size_t)par * KP + k];
-    __syncthreads();
-    const int oct = (int)(c.prefix[cell] & 7u);
-    const float* A = mat + (size_t)oct * K * K;
-    for (int j = threadIdx.x; j < K; j += blockDim.x) {
-        int d = degree_of(j);
-        float acc = 0.f;
-        for (int k = d * d; k < K; k++) acc += A[(size_t)k * K + j] * sh[k];
-        L[(size_t)cell * KP + j] += acc;
+        if (UP) {
+            if (OW > 1) {
+                __syncthreads();
+                if (og == 0) {
+#pragma unroll
+                    for (int cc = 0; cc < NB; cc++)
+                        for (int o = 0; o < 8; o++) tot[cc] += part[((size_t)o * NB + cc) * NJ + jt];
+                }
+                __syncthreads();
+            }
+            if (og == 0) {
+#pragma unroll
+                for (int cc = 0; cc < NB; cc++)
+                    if (cc < nb && j < KP) X[(size_t)sPar[cc] * KP + j] = j < K ? tot[cc] : 0.f;
+            }
+        }
     }
 }
 
@@ -348,14 +445,39 @@ void p2m(const float4* pts, CellArrays cells, const int32_t* leaves, int32_t nle
     k_p2m<<<nleaves, 64, lds, s>>>(pts, cells, leaves, p, KP, rc, M);
 }
 
-void m2m(CellArrays cells, int32_t c0, int32_t c1, int p, int KP, Tables t, float* M, hipStream_t s) {
-    if (c1 <= c0) return;
-    k_m2m<<<c1 - c0, 128, (size_t)8 * KP * sizeof(float), s>>>(cells, c0, p, KP, t.m2m, M);
+template <bool UP, int NB, int OW, int NJ>
+void translate_launch(CellArrays cells, const int32_t* inner, const uint32_t* leafpos, int32_t c0, int32_t c1,
+                      int32_t ncell, int32_t nleaf, int K, int KP, const float* mat, float* X, hipStream_t s) {
+    const int32_t n = c1 - c0;  // bounds the level's non-leaf cells
+    const size_t KS = (size_t)(K + 7) / 8 * 8;
+    const size_t lds = ((UP ? 8 : 1) * NB * KS + (UP && OW > 1 ? (size_t)8 * NB * NJ : 0)) * sizeof(float);
+    k_translate<UP, NB, OW, NJ><<<(n + NB - 1) / NB, OW * NJ, lds, s>>>(cells, inner, leafpos, c0, c1, ncell, nleaf,
+                                                                         K, KP, mat, X);
 }
 
-void l2l(CellArrays cells, int32_t c0, int32_t c1, int p, int KP, Tables t, float* L, hipStream_t s) {
-    if (c1 <= c0) return;
-    k_l2l<<<c1 - c0, 128, (size_t)KP * sizeof(float), s>>>(cells, c0, p, KP, t.l2l, L);
+template <bool UP>
+void translate_level(CellArrays cells, const int32_t* inner, const uint32_t* leafpos, int32_t c0, int32_t c1,
+                     int32_t ncell, int32_t nleaf, int K, int KP, const float* mat, float* X, hipStream_t s) {
+    const int32_t n = c1 - c0;
+    if (n <= 0) return;
+    // levels near the root: few parents, the 8 octants side by side
+    if (K <= 128) {
+        if (n >= 256) translate_launch<UP, 8, 8, 128>(cells, inner, leafpos, c0, c1, ncell, nleaf, K, KP, mat, X, s);
+        else translate_launch<UP, 2, 8, 128>(cells, inner, leafpos, c0, c1, ncell, nleaf, K, KP, mat, X, s);
+    } else {
+        if (n >= 256) translate_launch<UP, 4, 1, 256>(cells, inner, leafpos, c0, c1, ncell, nleaf, K, KP, mat, X, s);
+        else translate_launch<UP, 1, 2, 256>(cells, inner, leafpos, c0, c1, ncell, nleaf, K, KP, mat, X, s);
+    }
+}
+
+void m2m(CellArrays cells, const int32_t* inner, const uint32_t* leafpos, int32_t c0, int32_t c1, int32_t ncell,
+         int32_t nleaf, int p, int KP, Tables t, float* M, hipStream_t s) {
+    translate_level<true>(cells, inner, leafpos, c0, c1, ncell, nleaf, (p + 1) * (p + 1), KP, t.m2m, M, s);
+}
+
+void l2l(CellArrays cells, const int32_t* inner, const uint32_t* leafpos, int32_t c0, int32_t c1, int32_t ncell,
+         int32_t nleaf, int p, int KP, Tables t, float* L, hipStream_t s) {
+    translate_level<false>(cells, inner, leafpos, c0, c1, ncell, nleaf, (p + 1) * (p + 1), KP, t.l2l, L, s);
 }
 
 void m2l_general(const int32_t* goff, const uint32_t* gsrc, CellArrays cells, int32_t ncell, int p, int KP,

@@ -361,9 +361,11 @@ __global__ void k_leaf_flags(CellArrays c, int32_t ncell, uint32_t* __restrict__
 }
 
 __global__ void k_leaf_write(CellArrays c, int32_t ncell, const uint32_t* __restrict__ pos,
-                             int32_t* __restrict__ leaves) {
+                             int32_t* __restrict__ leaves, int32_t* __restrict__ inner) {
     int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (i < ncell && c.nchild[i] == 0) leaves[pos[i]] = i;
+    if (i >= ncell) return;
+    if (c.nchild[i] == 0) leaves[pos[i]] = i;
+    else inner[i - (int32_t)pos[i]] = i;
 }
 
 }  // namespace
@@ -377,9 +379,10 @@ void leaf_flags(CellArrays cells, int32_t ncell, uint32_t* flag, hipStream_t s) 
     k_leaf_flags<<<(ncell + 255) / 256, 256, 0, s>>>(cells, ncell, flag);
 }
 
-void leaf_write(CellArrays cells, int32_t ncell, const uint32_t* pos, int32_t* leaves, hipStream_t s) {
+void leaf_write(CellArrays cells, int32_t ncell, const uint32_t* pos, int32_t* leaves, int32_t* inner,
+                hipStream_t s) {
     if (ncell <= 0) return;
-    k_leaf_write<<<(ncell + 255) / 256, 256, 0, s>>>(cells, ncell, pos, leaves);
+    k_leaf_write<<<(ncell + 255) / 256, 256, 0, s>>>(cells, ncell, pos, leaves, inner);
 }
 
 }  // namespace fmm
