@@ -89,6 +89,7 @@ struct fmm_ctx_s {
     Buf d_slot, d_offid, d_T, d_Thi, d_Tlo;
     bool plan_bf16 = false;
     Buf inner, leafpos;  // non-leaf cells in cell order; leaves before each cell
+    Buf m2pflag;         // per leaf: cell-particle sources on the leaf or an ancestor
     Buf has_fast, rkey, rval, rkey2, rval2, rowof, gather, general, gtg, gsr, goff, tact, tnact, m2l_part, Msplit, nbucket, kinds;
     // pairs outside the same-level tables, batched by class
     ClsPlan cp;
@@ -130,7 +131,7 @@ struct fmm_ctx_s {
                       &d_h, &d_rc, &d_mlp, &M, &L, &nearb, &tune_pts, &tune_out, &d_mlp_m, &d_mlp_v,
                       &d_grad, &d_grad_rec, &d_loss_rec, &d_feat, &d_kind, &d_tgt, &d_table, &d_Thi, &d_Tlo,
                       &d_seg, &d_bt, &d_pb, &d_box, &d_frame, &inst, &bsort, &tact, &tnact,
-                      &leaves_cls, &inner, &leafpos, &lkey, &lval, &lkey2, &lval2, &at_out, &m2l_part, &Msplit, &nbucket, &kinds, &ckey, &ckey2, &cval, &cval2,
+                      &leaves_cls, &inner, &leafpos, &m2pflag, &lkey, &lval, &lkey2, &lval2, &at_out, &m2l_part, &Msplit, &nbucket, &kinds, &ckey, &ckey2, &cval, &cval2,
                       &chead, &choff, &cstart, &cpos, &csrcs, &cnt_t, &ctbase, &ctile, &cT, &cskip, &cls_part};
         for (Buf* b : all) bufs.push_back(b);
     }
@@ -880,7 +881,8 @@ void evaluate_impl(fmm_ctx c, int32_t precision, int32_t out_dtype, void* phi, v
         run_p2p(c, nr, s);
     }
     mark(c, PH_FAR);
-    far_final((float4*)c->pts.p, (uint32_t*)c->idx.p, ca, (int32_t*)c->leaves.p, c->nleaf, (int32_t*)c->off[1].p,
+    uint8_t* mflag = need<uint8_t>(c, c->m2pflag, (size_t)std::max(c->nleaf, 1));
+    far_final((float4*)c->pts.p, (uint32_t*)c->idx.p, ca, (int32_t*)c->leaves.p, c->nleaf, mflag, (int32_t*)c->off[1].p,
               (uint32_t*)c->src[1].p, p, KP, tb, M, L, nr, out_dtype, phi, ex, ey, ez, s);
     check_launch("far field");
     mark(c, PH_N);

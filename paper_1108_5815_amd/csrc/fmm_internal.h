@@ -219,8 +219,9 @@ void cls_skip(const int32_t* pos, int64_t ng, int32_t nbatched, uint8_t* skip, h
 // the class GEMMs into part (nbatched x KP) and the per-target sums into L
 void m2l_cls(const float* T, const ClsPlan& cp, int p, int KP, const float* M, float* part, const int32_t* goff,
              int32_t ncell, float* L, hipStream_t s);
+// m2pflag: scratch of nleaves bytes
 void far_final(const float4* pts, const uint32_t* perm, CellArrays cells, const int32_t* leaves,
-               int32_t nleaves, const int32_t* m2p_off, const uint32_t* m2p_src, int p, int KP,
+               int32_t nleaves, uint8_t* m2pflag, const int32_t* m2p_off, const uint32_t* m2p_src, int p, int KP,
                Tables t, const float* M, const float* L, const double4* near, int out_dtype,
                void* phi, void* ex, void* ey, void* ez, hipStream_t s);
 void p2p(const float4* pts, CellArrays cells, const int32_t* leaves, int32_t nleaves,

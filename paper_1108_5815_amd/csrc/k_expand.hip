@@ -1,5 +1,5 @@
-// k_expand.hip -- P2M, M2M, L2L, the general M2L and the far-field
-// evaluation (L2P + M2P + final sum) of the spherical-harmonic expansions.
+// k_expand.hip -- M2M, L2L and the general M2L of the spherical-harmonic
+// expansions (P2M and the far-field evaluation are in k_far.hip).
 //
 // Expansions (paper: "Hybrid treecode/FMM algorithm" and "Results": all
 // methods use spherical harmonics) follow Greengard & Rokhlin, Acta Numerica
@@ -29,37 +29,6 @@ __device__ inline cf hat(const float* row, int n, int m) {
     if (m == 0) return {row[n * n], 0.f};
     if (m > 0) return {row[n * n + 2 * m - 1], row[n * n + 2 * m]};
     return {row[n * n - 2 * m - 1], -row[n * n - 2 * m]};
-}
-
-// Regular solid harmonics S_n^m = rho^n Y_n^m (m >= 0, n <= P) of (x,y,z),
-// each handed to f(n, m, re, im) as soon as it is formed.
-template <class Fn>
-__device__ inline void regular_walk(int P, float x, float y, float z, const float* __restrict__ rc, Fn f) {
-    float r2 = x * x + y * y + z * z;
-    float mre = 1.f, mim = 0.f;
-    for (int m = 0; m <= P; m++) {
-        if (m > 0) {
-            float c = rc[kRcC1 + m];
-            float nre = c * (x * mre - y * mim), nim = c * (x * mim + y * mre);
-            mre = nre;
-            mim = nim;
-        }
-        f(m, m, mre, mim);
-        if (m == P) break;
-        float c2 = rc[kRcC2 + m] * z;
-        float p1re = c2 * mre, p1im = c2 * mim, p0re = mre, p0im = mim;
-        f(m + 1, m, p1re, p1im);
-        for (int n = m + 2; n <= P; n++) {
-            int t = n * (n + 1) / 2 + m;
-            float A = rc[kRcA + t] * z, B = rc[kRcB + t] * r2;
-            float nre = A * p1re - B * p0re, nim = A * p1im - B * p0im;
-            f(n, m, nre, nim);
-            p0re = p1re;
-            p0im = p1im;
-            p1re = nre;
-            p1im = nim;
-        }
-    }
 }
 
 // Irregular solid harmonics J_n^m = Y_n^m / rho^(n+1) (m >= 0, n <= P).
@@ -98,56 +67,6 @@ __device__ inline int degree_of(int j) {
     while ((d + 1) * (d + 1) <= j) d++;
     while (d * d > j) d--;
     return d;
-}
-
-// ---------------------------------------------------------------- P2M
-// One workgroup of 64 lanes per leaf: each lane writes q * conj(S(x-c)/r) of
-// one particle into its LDS row, then lanes sum columns (fixed order) over
-// the rows that hold a particle.
-__global__ __launch_bounds__(64) void k_p2m(const float4* __restrict__ pts, CellArrays c,
-                                            const int32_t* __restrict__ leaves, int p, int KP,
-                                            const float* __restrict__ rc, float* __restrict__ M) {
-    extern __shared__ float sh[];
-    const int K = (p + 1) * (p + 1);
-    const int STR = K | 1;
-    const int CH = K <= 128 ? 64 : 32;
-    const int cell = leaves[blockIdx.x];
-    const int32_t b = c.begin[cell], e = c.end[cell];
-    const double4 ct = c.ctr[cell];
-    const double ir = 1.0 / ct.w;
-    float acc[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-    float* row = sh + (threadIdx.x < CH ? threadIdx.x : 0) * STR;
-    for (int32_t ch = b; ch < e; ch += CH) {
-        const int nr = min(CH, e - ch);
-        if ((int)threadIdx.x < nr) {
-            float4 P = pts[ch + threadIdx.x];
-            float x = (float)(((double)P.x - ct.x) * ir);
-            float y = (float)(((double)P.y - ct.y) * ir);
-            float z = (float)(((double)P.z - ct.z) * ir);
-            float q = P.w;
-            regular_walk(p, x, y, z, rc, [&](int n, int m, float re, float im) {
-                if (m == 0) row[n * n] = q * re;
-                else {
-                    row[n * n + 2 * m - 1] = q * re;
-                    row[n * n + 2 * m] = -q * im;
-                }
-            });
-        }
-        __syncthreads();
-        for (int u = 0; u < 5; u++) {
-            int j = threadIdx.x + 64 * u;
-            if (j < K) {
-                float s = 0.f;
-                for (int r = 0; r < nr; r++) s += sh[r * STR + j];
-                acc[u] += s;
-            }
-        }
-        __syncthreads();
-    }
-    for (int u = 0; u < 5; u++) {
-        int j = threadIdx.x + 64 * u;
-        if (j < KP) M[(size_t)cell * KP + j] = j < K ? acc[u] : 0.f;
-    }
 }
 
 // ---------------------------------------------------------------- M2M / L2L
@@ -436,14 +355,6 @@ __global__ __launch_bounds__(256) void k_m2l_general(const int32_t* __restrict__
 }
 
 }  // namespace
-
-void p2m(const float4* pts, CellArrays cells, const int32_t* leaves, int32_t nleaves, int p, int KP,
-         const float* rc, float* M, hipStream_t s) {
-    if (nleaves <= 0) return;
-    int K = (p + 1) * (p + 1);
-    size_t lds = (size_t)(K <= 128 ? 64 : 32) * (K | 1) * sizeof(float);
-    k_p2m<<<nleaves, 64, lds, s>>>(pts, cells, leaves, p, KP, rc, M);
-}
 
 template <bool UP, int NB, int OW, int NJ>
 void translate_launch(CellArrays cells, const int32_t* inner, const uint32_t* leafpos, int32_t c0, int32_t c1,

@@ -1,4 +1,5 @@
-// k_far.hip -- far-field evaluation at the target particles and the final sum.
+// k_far.hip -- P2M, and the far-field evaluation at the target particles with
+// the final sum.
 //
 // For each target particle of a leaf: L2P of the leaf's local expansion, M2P
 // of every cell-particle source paired with the leaf or one of its ancestors
@@ -155,9 +156,139 @@ __device__ inline void m2p_point(const float* Ms, const float* __restrict__ h, f
     });
 }
 
-template <int P>
+// Leaves [w LPW, w LPW + LPW) of the leaf list per 64-lane workgroup, their
+// particles flattened (leaf by leaf, in particle order) and taken 64 at a
+// time: leaves hold ~20 particles on average, so one leaf per wave would
+// leave two lanes in three idle.  Each leaf's work stays a function of its
+// own particles only (a forest gives the same per-leaf results as a single
+// instance).
+template <int LPW>
+struct LeafPack {
+    int32_t cell[LPW], beg[LPW], cnt[LPW], pre[LPW + 1];
+    double4 ctr[LPW];
+    int nq;
+    // cooperative: lanes 0 .. LPW-1 each load one leaf, then (after a
+    // barrier) lane 0 forms the prefix
+    __device__ void load_lane(CellArrays c, const int32_t* __restrict__ leaves, int32_t nleaves, int lane) {
+        const int32_t l = (int32_t)blockIdx.x * LPW + lane;
+        if (l < nleaves) {
+            const int32_t cl = leaves[l];
+            cell[lane] = cl;
+            beg[lane] = c.begin[cl];
+            cnt[lane] = c.end[cl] - beg[lane];
+            ctr[lane] = c.ctr[cl];
+        } else {
+            cell[lane] = -1;
+            beg[lane] = 0;
+            cnt[lane] = 0;
+        }
+    }
+    __device__ void finish(int32_t nleaves) {
+        nq = min(LPW, nleaves - (int32_t)blockIdx.x * LPW);
+        int acc = 0;
+        for (int q = 0; q < LPW; q++) {
+            pre[q] = acc;
+            acc += cnt[q];
+        }
+        pre[LPW] = acc;
+    }
+    // leaf (0 .. nq-1) of flattened position f < pre[LPW]
+    __device__ int leaf_of(int f) const {
+        int q = 0;
+        while (q + 1 < nq && pre[q + 1] <= f) q++;
+        return q;
+    }
+};
+
+// P2M: each lane writes q * conj(S(x-c)/r) of one particle into its LDS row,
+// then each leaf's rows are summed column by column in particle order,
+// continuing across rounds (one sequential sum per coefficient and leaf).
+template <int P, int LPW>
+__global__ __launch_bounds__(64) void k_p2m(const float4* __restrict__ pts, CellArrays c,
+                                            const int32_t* __restrict__ leaves, int32_t nleaves, int KP,
+                                            const float* __restrict__ rc, float* __restrict__ M) {
+    constexpr int K = (P + 1) * (P + 1);
+    constexpr int CH = K <= 128 ? 64 : 32;  // rows per round
+    constexpr int STR = K | 1;
+    constexpr int NU = (K + 63) / 64;
+    __shared__ float rows[CH * STR];
+    __shared__ LeafPack<LPW> lp;
+    const int lane = threadIdx.x;
+    if (lane < LPW) lp.load_lane(c, leaves, nleaves, lane);
+    __syncthreads();
+    if (lane == 0) lp.finish(nleaves);
+    __syncthreads();
+    const int total = lp.pre[LPW];
+    float acc[LPW][NU];
+#pragma unroll
+    for (int q = 0; q < LPW; q++)
+#pragma unroll
+        for (int u = 0; u < NU; u++) acc[q][u] = 0.f;
+    for (int r0 = 0; r0 < total; r0 += CH) {
+        const int nr = min(CH, total - r0);
+        if (lane < nr) {
+            const int f = r0 + lane;
+            const int q = lp.leaf_of(f);
+            const float4 Pt = pts[lp.beg[q] + (f - lp.pre[q])];
+            const double4 ct = lp.ctr[q];
+            const double ir = 1.0 / ct.w;
+            const float x = (float)(((double)Pt.x - ct.x) * ir), y = (float)(((double)Pt.y - ct.y) * ir),
+                        z = (float)(((double)Pt.z - ct.z) * ir);
+            const float qc = Pt.w;
+            float* row = rows + lane * STR;
+            regular_walk_t<P>(x, y, z, rc, [&](int n, int m, float re, float im) {
+                if (m == 0) {
+                    row[n * n] = qc * re;
+                } else {
+                    row[n * n + 2 * m - 1] = qc * re;
+                    row[n * n + 2 * m] = -qc * im;
+                }
+            });
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < LPW; q++) {
+            const int lo = max(lp.pre[q], r0) - r0, hi = min(lp.pre[q + 1], r0 + nr) - r0;
+#pragma unroll
+            for (int u = 0; u < NU; u++) {
+                const int j = lane + 64 * u;
+                if (j < K)
+                    for (int r = lo; r < hi; r++) acc[q][u] += rows[r * STR + j];
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < LPW; q++) {
+        if (q >= lp.nq) break;
+        for (int u = 0; 64 * u < KP; u++) {
+            const int j = lane + 64 * u;
+            float v = 0.f;
+#pragma unroll
+            for (int uu = 0; uu < NU; uu++)
+                if (uu == u) v = acc[q][uu];
+            if (j < KP) M[(size_t)lp.cell[q] * KP + j] = j < K ? v : 0.f;
+        }
+    }
+}
+
+// 1 where the leaf or one of its ancestors has cell-particle (M2P) sources
+__global__ void k_m2p_flags(CellArrays c, const int32_t* __restrict__ leaves, int32_t nleaves,
+                            const int32_t* __restrict__ m2p_off, uint8_t* __restrict__ flag) {
+    const int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= nleaves) return;
+    uint8_t f = 0;
+    for (int A = leaves[i]; A >= 0 && !f; A = c.parent[A]) f = m2p_off[A + 1] > m2p_off[A];
+    flag[i] = f;
+}
+
+// Far field and final sum for every particle: near part (FP64) + L2P of its
+// leaf's local + M2P of the sources paired with its leaf or an ancestor (in
+// that order, as one sequential FP64 sum), written in the caller's order.
+template <int P, int LPW>
 __global__ __launch_bounds__(64) void k_far(const float4* __restrict__ pts, const uint32_t* __restrict__ perm,
-                                            CellArrays c, const int32_t* __restrict__ leaves,
+                                            CellArrays c, const int32_t* __restrict__ leaves, int32_t nleaves,
+                                            const uint8_t* __restrict__ m2pflag,
                                             const int32_t* __restrict__ m2p_off, const uint32_t* __restrict__ m2p_src,
                                             int KP, const float* __restrict__ gl2p, const float* __restrict__ hm2p,
                                             const float* __restrict__ rc, const float* __restrict__ M,
@@ -165,48 +296,69 @@ __global__ __launch_bounds__(64) void k_far(const float4* __restrict__ pts, cons
                                             int out_dtype, void* __restrict__ ophi, void* __restrict__ oex,
                                             void* __restrict__ oey, void* __restrict__ oez) {
     constexpr int K = (P + 1) * (P + 1);
-    __shared__ float Lt[K];
+    __shared__ float Lt[LPW][K];
     __shared__ float Ms[K];
-    const int cell = leaves[blockIdx.x];
-    const int32_t b = c.begin[cell], e = c.end[cell];
-    const double4 ct = c.ctr[cell];
-    for (int i = threadIdx.x; i < K; i += 64) Lt[i] = L[(size_t)cell * KP + i];
+    __shared__ LeafPack<LPW> lp;
+    __shared__ uint8_t s_m2p[LPW];
+    const int lane = threadIdx.x;
+    if (lane < LPW) {
+        lp.load_lane(c, leaves, nleaves, lane);
+        const int32_t l = (int32_t)blockIdx.x * LPW + lane;
+        s_m2p[lane] = l < nleaves ? m2pflag[l] : 0;
+    }
+    __syncthreads();
+    if (lane == 0) lp.finish(nleaves);
+    __syncthreads();
+    for (int i = lane; i < LPW * K; i += 64) {
+        const int q = i / K, k = i - q * K;
+        Lt[q][k] = q < lp.nq ? L[(size_t)lp.cell[q] * KP + k] : 0.f;
+    }
     __syncthreads();
     const float s2 = 1.41421356237309505f;
-    for (int32_t ch = b; ch < e; ch += 64) {
-        const int32_t i = ch + threadIdx.x;
-        const bool valid = i < e;
-        const float4 Pt = pts[valid ? i : b];
+    const int total = lp.pre[LPW];
+    for (int r0 = 0; r0 < total; r0 += 64) {
+        const int f = r0 + lane;
+        const bool valid = f < total;
+        const int q = valid ? lp.leaf_of(f) : 0;
+        const int32_t i = lp.beg[q] + (f - lp.pre[q]);
+        const float4 Pt = pts[valid ? i : lp.beg[0]];
         double4 acc = valid ? near[i] : make_double4(0, 0, 0, 0);
         {
+            const double4 ct = lp.ctr[q];
             const double ir = 1.0 / ct.w;
             const float x = (float)(((double)Pt.x - ct.x) * ir), y = (float)(((double)Pt.y - ct.y) * ir),
                         z = (float)(((double)Pt.z - ct.z) * ir);
             float phi = 0.f, l10 = 0.f, l1re = 0.f, l1im = 0.f;
-            l2p_point<P>(Lt, gl2p, x, y, z, rc, phi, l10, l1re, l1im);
+            l2p_point<P>(Lt[q], gl2p, x, y, z, rc, phi, l10, l1re, l1im);
             const double r1 = ct.w, r2 = ct.w * ct.w;
             acc.x += (double)phi / r1;
             acc.y += (double)(-s2 * l1re) / r2;
             acc.z += (double)(s2 * l1im) / r2;
             acc.w += (double)(-l10) / r2;
         }
-        for (int A = cell; A >= 0; A = c.parent[A]) {
-            for (int32_t a = m2p_off[A]; a < m2p_off[A + 1]; a++) {
-                const int s = (int)m2p_src[a];
-                const double4 cs = c.ctr[s];
-                __syncthreads();
-                for (int u = threadIdx.x; u < K; u += 64) Ms[u] = M[(size_t)s * KP + u];
-                __syncthreads();
-                const double ir = 1.0 / cs.w;
-                const float x = (float)(((double)Pt.x - cs.x) * ir), y = (float)(((double)Pt.y - cs.y) * ir),
-                            z = (float)(((double)Pt.z - cs.z) * ir);
-                float phi = 0.f, l10 = 0.f, l1re = 0.f, l1im = 0.f;
-                m2p_point<P>(Ms, hm2p, x, y, z, rc, phi, l10, l1re, l1im);
-                const double r1 = cs.w, r2 = cs.w * cs.w;
-                acc.x += (double)phi / r1;
-                acc.y += (double)(-s2 * l1re) / r2;
-                acc.z += (double)(s2 * l1im) / r2;
-                acc.w += (double)(-l10) / r2;
+        // cell-particle sources, leaf by leaf (the wave takes each list in turn)
+        for (int qq = 0; qq < lp.nq; qq++) {
+            if (!s_m2p[qq] || lp.pre[qq + 1] <= r0 || lp.pre[qq] >= r0 + 64) continue;
+            for (int A = lp.cell[qq]; A >= 0; A = c.parent[A]) {
+                for (int32_t a = m2p_off[A]; a < m2p_off[A + 1]; a++) {
+                    const int s = (int)m2p_src[a];
+                    const double4 cs = c.ctr[s];
+                    __syncthreads();
+                    for (int u = lane; u < K; u += 64) Ms[u] = M[(size_t)s * KP + u];
+                    __syncthreads();
+                    if (valid && q == qq) {
+                        const double ir = 1.0 / cs.w;
+                        const float x = (float)(((double)Pt.x - cs.x) * ir), y = (float)(((double)Pt.y - cs.y) * ir),
+                                    z = (float)(((double)Pt.z - cs.z) * ir);
+                        float phi = 0.f, l10 = 0.f, l1re = 0.f, l1im = 0.f;
+                        m2p_point<P>(Ms, hm2p, x, y, z, rc, phi, l10, l1re, l1im);
+                        const double r1 = cs.w, r2 = cs.w * cs.w;
+                        acc.x += (double)phi / r1;
+                        acc.y += (double)(-s2 * l1re) / r2;
+                        acc.z += (double)(s2 * l1im) / r2;
+                        acc.w += (double)(-l10) / r2;
+                    }
+                }
             }
         }
         if (valid) {
@@ -226,25 +378,37 @@ __global__ __launch_bounds__(64) void k_far(const float4* __restrict__ pts, cons
     }
 }
 
+constexpr int kLeavesPerWave = 8;
+
 template <int P>
 void launch_far(const float4* pts, const uint32_t* perm, CellArrays cells, const int32_t* leaves, int32_t nleaves,
-                const int32_t* m2p_off, const uint32_t* m2p_src, int KP, Tables t, const float* M, const float* L,
-                const double4* near, int out_dtype, void* phi, void* ex, void* ey, void* ez, hipStream_t s) {
-    k_far<P><<<nleaves, 64, 0, s>>>(pts, perm, cells, leaves, m2p_off, m2p_src, KP, t.gl2p, t.hm2p, t.rcoef, M, L,
-                                     near, out_dtype, phi, ex, ey, ez);
+                uint8_t* m2pflag, const int32_t* m2p_off, const uint32_t* m2p_src, int KP, Tables t, const float* M,
+                const float* L, const double4* near, int out_dtype, void* phi, void* ex, void* ey, void* ez,
+                hipStream_t s) {
+    k_m2p_flags<<<(nleaves + 255) / 256, 256, 0, s>>>(cells, leaves, nleaves, m2p_off, m2pflag);
+    constexpr int W = kLeavesPerWave;
+    k_far<P, W><<<(nleaves + W - 1) / W, 64, 0, s>>>(pts, perm, cells, leaves, nleaves, m2pflag, m2p_off, m2p_src, KP,
+                                                     t.gl2p, t.hm2p, t.rcoef, M, L, near, out_dtype, phi, ex, ey, ez);
+}
+
+template <int P>
+void launch_p2m(const float4* pts, CellArrays cells, const int32_t* leaves, int32_t nleaves, int KP, const float* rc,
+                float* M, hipStream_t s) {
+    constexpr int W = kLeavesPerWave;
+    k_p2m<P, W><<<(nleaves + W - 1) / W, 64, 0, s>>>(pts, cells, leaves, nleaves, KP, rc, M);
 }
 
 }  // namespace
 
 void far_final(const float4* pts, const uint32_t* perm, CellArrays cells, const int32_t* leaves, int32_t nleaves,
-               const int32_t* m2p_off, const uint32_t* m2p_src, int p, int KP, Tables t, const float* M,
-               const float* L, const double4* near, int out_dtype, void* phi, void* ex, void* ey, void* ez,
-               hipStream_t s) {
+               uint8_t* m2pflag, const int32_t* m2p_off, const uint32_t* m2p_src, int p, int KP, Tables t,
+               const float* M, const float* L, const double4* near, int out_dtype, void* phi, void* ex, void* ey,
+               void* ez, hipStream_t s) {
     if (nleaves <= 0) return;
-#define FMM_FAR_CASE(PP)                                                                                          \
-    case PP:                                                                                                      \
-        launch_far<PP>(pts, perm, cells, leaves, nleaves, m2p_off, m2p_src, KP, t, M, L, near, out_dtype, phi, ex, \
-                       ey, ez, s);                                                                                \
+#define FMM_FAR_CASE(PP)                                                                                         \
+    case PP:                                                                                                     \
+        launch_far<PP>(pts, perm, cells, leaves, nleaves, m2pflag, m2p_off, m2p_src, KP, t, M, L, near, out_dtype, \
+                       phi, ex, ey, ez, s);                                                                      \
         break;
     switch (p) {
         FMM_FAR_CASE(0)
@@ -268,6 +432,37 @@ void far_final(const float4* pts, const uint32_t* perm, CellArrays cells, const 
             break;
     }
 #undef FMM_FAR_CASE
+}
+
+void p2m(const float4* pts, CellArrays cells, const int32_t* leaves, int32_t nleaves, int p, int KP, const float* rc,
+         float* M, hipStream_t s) {
+    if (nleaves <= 0) return;
+#define FMM_P2M_CASE(PP)                                              \
+    case PP:                                                          \
+        launch_p2m<PP>(pts, cells, leaves, nleaves, KP, rc, M, s); \
+        break;
+    switch (p) {
+        FMM_P2M_CASE(0)
+        FMM_P2M_CASE(1)
+        FMM_P2M_CASE(2)
+        FMM_P2M_CASE(3)
+        FMM_P2M_CASE(4)
+        FMM_P2M_CASE(5)
+        FMM_P2M_CASE(6)
+        FMM_P2M_CASE(7)
+        FMM_P2M_CASE(8)
+        FMM_P2M_CASE(9)
+        FMM_P2M_CASE(10)
+        FMM_P2M_CASE(11)
+        FMM_P2M_CASE(12)
+        FMM_P2M_CASE(13)
+        FMM_P2M_CASE(14)
+        FMM_P2M_CASE(15)
+        FMM_P2M_CASE(16)
+        default:
+            break;
+    }
+#undef FMM_P2M_CASE
 }
 
 }  // namespace fmm
