@@ -1,10 +1,12 @@
 // k_util.hip -- device-wide exclusive scans and a stable LSD radix sort.
 //
 // Scan: reduce tiles -> scan tile sums in one workgroup -> scan within tiles.
-// Radix sort: 8-bit digits; per tile a digit histogram, a scan of the
-// digit-major histogram table, then a stable scatter in which each wave ranks
-// its 64 keys per round with 8 ballots (lanes holding the same digit form a
-// mask; rank = popcount of the lower lanes of that mask).  Tiles are 4096
+// Radix sort: digits of at most 11 bits, the key bits spread evenly over the
+// passes (18-bit cell keys: 2 passes of 9); per tile a digit histogram, a
+// scan of the digit-major histogram table, then a stable scatter in which
+// each wave ranks its 64 keys per round with one ballot per digit bit (lanes
+// holding the same digit form a mask; rank = popcount of the lower lanes of
+// that mask).  Tiles are 4096
 // keys: 4 waves x 16 rounds x 64 lanes, processed in index order, so equal
 // digits keep their input order.
 #include "fmm_internal.h"
@@ -169,43 +171,46 @@ constexpr int RB = 256;
 constexpr int RW = RB / 64;
 constexpr int RR = 16;
 constexpr int RT = RB * RR;
+constexpr int kMaxDigitBits = 11;
 
+// digit of `w` bits at `shift`, counted in 2^DB buckets (w <= DB)
 template <class K>
-__device__ inline uint32_t digit_of(K k, int shift) {
-    return (uint32_t)(k >> shift) & 255u;
+__device__ inline uint32_t digit_of(K k, int shift, uint32_t mask) {
+    return (uint32_t)(k >> shift) & mask;
 }
 
-template <class K>
-__global__ void k_rs_hist(const K* __restrict__ keys, int64_t n, int shift,
+template <class K, int DB>
+__global__ void k_rs_hist(const K* __restrict__ keys, int64_t n, int shift, uint32_t mask,
                           uint32_t* __restrict__ ghist, int64_t nb) {
-    __shared__ uint32_t h[256];
-    h[threadIdx.x] = 0;
+    constexpr int ND = 1 << DB;
+    __shared__ uint32_t h[ND];
+    for (int d = threadIdx.x; d < ND; d += RB) h[d] = 0;
     __syncthreads();
     int64_t base = (int64_t)blockIdx.x * RT;
     for (int i = threadIdx.x; i < RT; i += RB) {
         int64_t g = base + i;
-        if (g < n) atomicAdd(&h[digit_of(keys[g], shift)], 1u);
+        if (g < n) atomicAdd(&h[digit_of(keys[g], shift, mask)], 1u);
     }
     __syncthreads();
-    ghist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+    for (int d = threadIdx.x; d < ND; d += RB) ghist[(int64_t)d * nb + blockIdx.x] = h[d];
 }
 
-template <class K>
+template <class K, int DB>
 __global__ void k_rs_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
                              K* __restrict__ kout, uint32_t* __restrict__ vout, int64_t n,
-                             int shift, const uint32_t* __restrict__ goff, int64_t nb) {
-    __shared__ uint32_t wc[RW][256];
+                             int shift, uint32_t mask, const uint32_t* __restrict__ goff, int64_t nb) {
+    constexpr int ND = 1 << DB;
+    __shared__ uint32_t wc[RW][ND];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int i = threadIdx.x; i < RW * 256; i += RB) (&wc[0][0])[i] = 0;
+    for (int i = threadIdx.x; i < RW * ND; i += RB) (&wc[0][0])[i] = 0;
     __syncthreads();
     const int64_t wbase = (int64_t)blockIdx.x * RT + (int64_t)w * (RR * 64);
     for (int r = 0; r < RR; r++) {
         int64_t g = wbase + r * 64 + lane;
-        if (g < n) atomicAdd(&wc[w][digit_of(kin[g], shift)], 1u);
+        if (g < n) atomicAdd(&wc[w][digit_of(kin[g], shift, mask)], 1u);
     }
     __syncthreads();
-    {
-        int d = threadIdx.x;  // RB == 256 digits
+    for (int d = threadIdx.x; d < ND; d += RB) {
         uint32_t run = goff[(int64_t)d * nb + blockIdx.x];
         for (int ww = 0; ww < RW; ww++) {
             uint32_t c = wc[ww][d];
@@ -223,46 +228,64 @@ __global__ void k_rs_scatter(const K* __restrict__ kin, const uint32_t* __restri
         if (valid) {
             k = kin[g];
             v = vin[g];
-            d = digit_of(k, shift);
+            d = digit_of(k, shift, mask);
         }
-        uint64_t mask = __ballot(valid);
+        uint64_t same = __ballot(valid);
 #pragma unroll
-        for (int b = 0; b < 8; b++) {
+        for (int b = 0; b < DB; b++) {
             bool bit = (d >> b) & 1u;
             uint64_t bb = __ballot(valid && bit);
-            mask &= bit ? bb : ~bb;
+            same &= bit ? bb : ~bb;
         }
-        uint32_t rank = (uint32_t)__popcll(mask & lt);
+        uint32_t rank = (uint32_t)__popcll(same & lt);
         uint32_t basev = valid ? wc[w][d] : 0u;
         if (valid) {
             kout[basev + rank] = k;
             vout[basev + rank] = v;
         }
-        bool leader = valid && ((mask >> lane) == 1ull);
-        if (leader) wc[w][d] = basev + (uint32_t)__popcll(mask);
+        bool leader = valid && ((same >> lane) == 1ull);
+        if (leader) wc[w][d] = basev + (uint32_t)__popcll(same);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
     }
 }
 
+template <class K, int DB>
+void rs_pass(const K* ki, const uint32_t* vi, K* ko, uint32_t* vo, int64_t n, int sh, int w, int64_t nb,
+             uint32_t* ghist, uint32_t* goff, void* sws, hipStream_t s) {
+    const uint32_t mask = (1u << w) - 1u;
+    k_rs_hist<K, DB><<<(unsigned)nb, RB, 0, s>>>(ki, n, sh, mask, ghist, nb);
+    scan_impl<uint32_t>(ghist, goff, nullptr, (int64_t)(1 << DB) * nb, sws, s);
+    k_rs_scatter<K, DB><<<(unsigned)nb, RB, 0, s>>>(ki, vi, ko, vo, n, sh, mask, goff, nb);
+}
+
+// LSD passes of at most kMaxDigitBits bits, the bits spread evenly over them
 template <class K>
 void sort_impl(K* ka, uint32_t* va, K* kb, uint32_t* vb, int64_t n, int bit0, int bit1, void* ws,
                hipStream_t s) {
     if (n <= 1 || bit1 <= bit0) return;
     int64_t nb = (n + RT - 1) / RT;
     uint32_t* ghist = (uint32_t*)ws;
-    uint32_t* goff = ghist + 256 * nb;
-    void* sws = goff + 256 * nb;
+    uint32_t* goff = ghist + ((size_t)1 << kMaxDigitBits) * nb;
+    void* sws = goff + ((size_t)1 << kMaxDigitBits) * nb;
     K *ki = ka, *ko = kb;
     uint32_t *vi = va, *vo = vb;
-    int passes = 0;
-    for (int sh = bit0; sh < bit1; sh += 8) {
-        k_rs_hist<K><<<(unsigned)nb, RB, 0, s>>>(ki, n, sh, ghist, nb);
-        scan_impl<uint32_t>(ghist, goff, nullptr, 256 * nb, sws, s);
-        k_rs_scatter<K><<<(unsigned)nb, RB, 0, s>>>(ki, vi, ko, vo, n, sh, goff, nb);
+    const int bits = bit1 - bit0;
+    const int passes = (bits + kMaxDigitBits - 1) / kMaxDigitBits;
+    int sh = bit0;
+    for (int ps = 0; ps < passes; ps++) {
+        const int w = (bit1 - sh + (passes - ps) - 1) / (passes - ps);  // ceil(remaining / passes left)
+        switch (w <= 6 ? 6 : w) {
+            case 6: rs_pass<K, 6>(ki, vi, ko, vo, n, sh, w, nb, ghist, goff, sws, s); break;
+            case 7: rs_pass<K, 7>(ki, vi, ko, vo, n, sh, w, nb, ghist, goff, sws, s); break;
+            case 8: rs_pass<K, 8>(ki, vi, ko, vo, n, sh, w, nb, ghist, goff, sws, s); break;
+            case 9: rs_pass<K, 9>(ki, vi, ko, vo, n, sh, w, nb, ghist, goff, sws, s); break;
+            case 10: rs_pass<K, 10>(ki, vi, ko, vo, n, sh, w, nb, ghist, goff, sws, s); break;
+            default: rs_pass<K, 11>(ki, vi, ko, vo, n, sh, w, nb, ghist, goff, sws, s); break;
+        }
+        sh += w;
         K* tk = ki; ki = ko; ko = tk;
         uint32_t* tv = vi; vi = vo; vo = tv;
-        passes++;
     }
     if (passes & 1) {
         hipMemcpyAsync(ka, ki, n * sizeof(K), hipMemcpyDeviceToDevice, s);
@@ -298,7 +321,8 @@ void scan_u32x4(const uint4* in, uint4* out, uint4* total, int64_t n, void* ws, 
 
 size_t sort_ws_bytes(int64_t n) {
     int64_t nb = (n + RT - 1) / RT + 1;
-    return (size_t)2 * 256 * nb * sizeof(uint32_t) + scan_ws_bytes(256 * nb) + 256;
+    const int64_t nd = (int64_t)1 << kMaxDigitBits;
+    return (size_t)2 * nd * nb * sizeof(uint32_t) + scan_ws_bytes(nd * nb) + 256;
 }
 
 void sort_u64(uint64_t* ka, uint32_t* va, uint64_t* kb, uint32_t* vb, int64_t n, int bit0,
