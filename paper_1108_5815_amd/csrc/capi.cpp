@@ -764,11 +764,15 @@ void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
     } else if (nm > 0) {
         fill_i32((int32_t*)gen, 1, nm, s);
     }
+    // pairs outside the GEMM tables, compacted in list order
+    const int64_t nct = compact_tiles(nm);
+    uint32_t* tcnt = need<uint32_t>(c, c->tgt2, (size_t)2 * nct + 2);
+    uint32_t* tbase = tcnt + nct + 1;
     if (nm > 0) {
-        size_t wsg = scan_ws_bytes(nm);
+        size_t wsg = scan_ws_bytes(nct);
         if (wsg > c->ws.cap) ws = need<char>(c, c->ws, wsg);
-        uint32_t* pos = need<uint32_t>(c, c->tgt2, nm + 1);
-        scan_u32(gen, pos, (uint32_t*)(d6 + 12), nm, ws, s);
+        flag_counts(gen, nm, tcnt, s);
+        scan_u32(tcnt, tbase, (uint32_t*)(d6 + 12), nct, ws, s);
         uint32_t* hg = (uint32_t*)host_stage(c);
         to_host<uint32_t>(c, hg, d6 + 12, 1);
         c->ngeneral = hg[0];
@@ -777,7 +781,7 @@ void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
         int64_t ng = c->ngeneral;
         uint32_t* gt = need<uint32_t>(c, c->gtg, ng + 1);
         uint32_t* gs = need<uint32_t>(c, c->gsr, ng + 1);
-        if (ng > 0) compact_pairs(tg0, sr0, gen, (uint32_t*)c->tgt2.p, nm, gt, gs, s);
+        if (ng > 0) compact_pairs(tg0, sr0, gen, tbase, nm, gt, gs, s);
         sort_into(nullptr, ng, c->gtg, c->gsr, c->goff);
     }
     build_classes(c, p);

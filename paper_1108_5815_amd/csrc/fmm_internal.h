@@ -154,8 +154,12 @@ void row_class_keys(const uint32_t* nfast, CellArrays cells, int32_t ncell, int3
                     uint32_t* val, hipStream_t s);
 // rowof[rowcell[r]] = tile * NT + column of GEMM row r (plan's class tables set)
 void rows_inverse(const uint32_t* rowcell, int64_t nrows, GemmPlan plan, int NT, int32_t* rowof, hipStream_t s);
-// keep the pairs whose flag is set: out[pos[i]] = pair i (pos = exclusive scan of flag)
-void compact_pairs(const uint32_t* tgt, const uint32_t* src, const uint32_t* flag, const uint32_t* pos, int64_t n,
+// keep the pairs whose flag is set, in order: flags are counted per tile of
+// 4096 (flag_counts, compact_tiles(n) counts), tbase = exclusive scan of the
+// counts, then compact_pairs writes each tile's pairs from its base
+int64_t compact_tiles(int64_t n);
+void flag_counts(const uint32_t* flag, int64_t n, uint32_t* cnt, hipStream_t s);
+void compact_pairs(const uint32_t* tgt, const uint32_t* src, const uint32_t* flag, const uint32_t* tbase, int64_t n,
                    uint32_t* otgt, uint32_t* osrc, hipStream_t s);
 // out9[c] = first index of the sorted class keys with key >= c, c = 0..8
 // out9[c] = first index whose key >> shift is >= c, c = 0..8

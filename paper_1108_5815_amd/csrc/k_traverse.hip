@@ -390,21 +390,68 @@ void leaf_write(CellArrays cells, int32_t ncell, const uint32_t* pos, int32_t* l
 namespace fmm {
 namespace {
 
-__global__ void k_compact_pairs(const uint32_t* __restrict__ tgt, const uint32_t* __restrict__ src,
-                                const uint32_t* __restrict__ flag, const uint32_t* __restrict__ pos, int64_t n,
-                                uint32_t* __restrict__ otgt, uint32_t* __restrict__ osrc) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n || !flag[i]) return;
-    otgt[pos[i]] = tgt[i];
-    osrc[pos[i]] = src[i];
+// flags in tiles of kCompactTile = 4 waves x 16 rounds x 64 lanes, in order
+constexpr int kCompactTile = 4096;
+
+__device__ inline uint32_t wave_flag_count(const uint32_t* __restrict__ flag, int64_t n, int64_t base, int lane) {
+    uint32_t c = 0;
+    for (int r = 0; r < 16; r++) {
+        const int64_t g = base + r * 64 + lane;
+        c += (uint32_t)__popcll(__ballot(g < n && flag[g] != 0u));
+    }
+    return c;
+}
+
+__global__ __launch_bounds__(256) void k_flag_counts(const uint32_t* __restrict__ flag, int64_t n,
+                                                     uint32_t* __restrict__ cnt) {
+    __shared__ uint32_t wsum[4];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint32_t c = wave_flag_count(flag, n, (int64_t)blockIdx.x * kCompactTile + w * 1024, lane);
+    if (lane == 0) wsum[w] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) cnt[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+}
+
+// flagged pairs of each tile written from the tile's base, in index order
+__global__ __launch_bounds__(256) void k_compact_pairs(const uint32_t* __restrict__ tgt, const uint32_t* __restrict__ src,
+                                                       const uint32_t* __restrict__ flag, const uint32_t* __restrict__ tbase,
+                                                       int64_t n, uint32_t* __restrict__ otgt,
+                                                       uint32_t* __restrict__ osrc) {
+    __shared__ uint32_t wsum[4];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t base = (int64_t)blockIdx.x * kCompactTile + w * 1024;
+    const uint32_t c = wave_flag_count(flag, n, base, lane);
+    if (lane == 0) wsum[w] = c;
+    __syncthreads();
+    uint32_t off = tbase[blockIdx.x];
+    for (int q = 0; q < w; q++) off += wsum[q];
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    for (int r = 0; r < 16; r++) {
+        const int64_t g = base + r * 64 + lane;
+        const bool f = g < n && flag[g] != 0u;
+        const uint64_t m = __ballot(f);
+        if (f) {
+            const uint32_t pos = off + (uint32_t)__popcll(m & lt);
+            otgt[pos] = tgt[g];
+            osrc[pos] = src[g];
+        }
+        off += (uint32_t)__popcll(m);
+    }
 }
 
 }  // namespace
 
-void compact_pairs(const uint32_t* tgt, const uint32_t* src, const uint32_t* flag, const uint32_t* pos, int64_t n,
+int64_t compact_tiles(int64_t n) { return (n + kCompactTile - 1) / kCompactTile; }
+
+void flag_counts(const uint32_t* flag, int64_t n, uint32_t* cnt, hipStream_t s) {
+    if (n <= 0) return;
+    k_flag_counts<<<(unsigned)compact_tiles(n), 256, 0, s>>>(flag, n, cnt);
+}
+
+void compact_pairs(const uint32_t* tgt, const uint32_t* src, const uint32_t* flag, const uint32_t* tbase, int64_t n,
                    uint32_t* otgt, uint32_t* osrc, hipStream_t s) {
     if (n <= 0) return;
-    k_compact_pairs<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(tgt, src, flag, pos, n, otgt, osrc);
+    k_compact_pairs<<<(unsigned)compact_tiles(n), 256, 0, s>>>(tgt, src, flag, tbase, n, otgt, osrc);
 }
 
 }  // namespace fmm
