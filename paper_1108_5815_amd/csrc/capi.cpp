@@ -90,6 +90,7 @@ struct fmm_ctx_s {
     bool plan_bf16 = false;
     Buf inner, leafpos;  // non-leaf cells in cell order; leaves before each cell
     Buf m2pflag;         // per leaf: cell-particle sources on the leaf or an ancestor
+    Buf m2lslot;         // per cell-cell pair: its GEMM slot or -1
     Buf has_fast, rkey, rval, rkey2, rval2, rowof, gather, general, gtg, gsr, goff, tact, tnact, m2l_part, Msplit, nbucket, kinds;
     // pairs outside the same-level tables, batched by class
     ClsPlan cp;
@@ -131,7 +132,7 @@ struct fmm_ctx_s {
                       &d_h, &d_rc, &d_mlp, &M, &L, &nearb, &tune_pts, &tune_out, &d_mlp_m, &d_mlp_v,
                       &d_grad, &d_grad_rec, &d_loss_rec, &d_feat, &d_kind, &d_tgt, &d_table, &d_Thi, &d_Tlo,
                       &d_seg, &d_bt, &d_pb, &d_box, &d_frame, &inst, &bsort, &tact, &tnact,
-                      &leaves_cls, &inner, &leafpos, &m2pflag, &lkey, &lval, &lkey2, &lval2, &at_out, &m2l_part, &Msplit, &nbucket, &kinds, &ckey, &ckey2, &cval, &cval2,
+                      &leaves_cls, &inner, &leafpos, &m2pflag, &m2lslot, &lkey, &lval, &lkey2, &lval2, &at_out, &m2l_part, &Msplit, &nbucket, &kinds, &ckey, &ckey2, &cval, &cval2,
                       &chead, &choff, &cstart, &cpos, &csrcs, &cnt_t, &ctbase, &ctile, &cT, &cskip, &cls_part};
         for (Buf* b : all) bufs.push_back(b);
     }
@@ -710,16 +711,15 @@ void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
     c->nrows = 0;
     c->ngeneral = 0;
     int64_t nm = c->nlist[0];
-    uint32_t* tg0 = need<uint32_t>(c, c->tgt[0], nm + 1);
-    uint32_t* sr0 = need<uint32_t>(c, c->src[0], nm + 1);
+    const int2* pr0 = (const int2*)c->raw[0].p;  // cell-cell pairs as emitted
     uint32_t* gen = need<uint32_t>(c, c->general, nm + 1);
-    if (nm > 0) split_pairs((int2*)c->raw[0].p, nm, tg0, sr0, s);
     if (c->gemm_on) {
         upload_plan(c, p, theta);
         int R = c->plan.R, J = c->plan.J;
         uint32_t* hf = need<uint32_t>(c, c->has_fast, nc);
         ck(hipMemsetAsync(hf, 0, (size_t)nc * 4, s), "memset");
-        m2l_mark_targets(tg0, sr0, nm, ca, (int32_t*)c->d_slot.p, R, hf, s);
+        int16_t* slot16 = need<int16_t>(c, c->m2lslot, nm + 1);
+        m2l_mark_targets(pr0, nm, ca, (int32_t*)c->d_slot.p, R, hf, slot16, s);
         uint32_t* rk = need<uint32_t>(c, c->rkey, nc);
         uint32_t* rv = need<uint32_t>(c, c->rval, nc);
         uint32_t* rk2 = need<uint32_t>(c, c->rkey2, nc);
@@ -753,7 +753,7 @@ void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
         const int64_t ngather = (int64_t)tiles * tc * J;
         int32_t* ga = need<int32_t>(c, c->gather, (size_t)std::max<int64_t>(ngather, 1));
         fill_i32(ga, -1, ngather, s);
-        m2l_fill_gather(tg0, sr0, nm, ca, (int32_t*)c->d_slot.p, R, ro, J, tc, ga, gen, s);
+        m2l_fill_gather(pr0, (const int16_t*)c->m2lslot.p, nm, ro, J, tc, ga, gen, s);
         check_launch("m2l gather");
         int32_t* act = need<int32_t>(c, c->tact, (size_t)std::max(tiles, 1) * J);
         int32_t* nact = need<int32_t>(c, c->tnact, (size_t)std::max(tiles, 1));
@@ -781,7 +781,7 @@ void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
         int64_t ng = c->ngeneral;
         uint32_t* gt = need<uint32_t>(c, c->gtg, ng + 1);
         uint32_t* gs = need<uint32_t>(c, c->gsr, ng + 1);
-        if (ng > 0) compact_pairs(tg0, sr0, gen, tbase, nm, gt, gs, s);
+        if (ng > 0) compact_pairs(pr0, gen, tbase, nm, gt, gs, s);
         sort_into(nullptr, ng, c->gtg, c->gsr, c->goff);
     }
     build_classes(c, p);

@@ -135,16 +135,16 @@ void csr_offsets(const uint32_t* tgt_sorted, int64_t n, int32_t ncell, int32_t* 
 
 struct GemmPlan;
 
-// M2L same-level batching: classify each M2L pair (sorted by target).
+// M2L same-level batching: classify each M2L pair (emission order; the
+// pairs as emitted, (target, source)); slot: per pair, its slot or -1.
 //   slot_of   lookup table [8][(2R+1)^3] (offset -> slot or -1)
 //   rowof     [ncell] tile * NT + column of the target's GEMM row, or -1
 //   gather    [ntiles][J][NT] source cell or -1 (per tile and slot, the
 //             tile's NT columns contiguous; padding columns stay -1)
 //   general   flag per pair (1 = not handled by the GEMM)
-void m2l_mark_targets(const uint32_t* tgt, const uint32_t* src, int64_t n, CellArrays cells,
-                      const int32_t* slot_of, int R, uint32_t* has_fast, hipStream_t s);
-void m2l_fill_gather(const uint32_t* tgt, const uint32_t* src, int64_t n, CellArrays cells,
-                     const int32_t* slot_of, int R, const int32_t* rowof, int32_t J, int NT,
+void m2l_mark_targets(const int2* pairs, int64_t n, CellArrays cells, const int32_t* slot_of, int R,
+                      uint32_t* has_fast, int16_t* slot, hipStream_t s);
+void m2l_fill_gather(const int2* pairs, const int16_t* slot, int64_t n, const int32_t* rowof, int32_t J, int NT,
                      int32_t* gather, uint32_t* general, hipStream_t s);
 // row keys of the M2L GEMM: (octant class << kRowMissBits) | missing slots
 // (densest first); cells without same-level pairs get class 8
@@ -159,8 +159,8 @@ void rows_inverse(const uint32_t* rowcell, int64_t nrows, GemmPlan plan, int NT,
 // counts, then compact_pairs writes each tile's pairs from its base
 int64_t compact_tiles(int64_t n);
 void flag_counts(const uint32_t* flag, int64_t n, uint32_t* cnt, hipStream_t s);
-void compact_pairs(const uint32_t* tgt, const uint32_t* src, const uint32_t* flag, const uint32_t* tbase, int64_t n,
-                   uint32_t* otgt, uint32_t* osrc, hipStream_t s);
+void compact_pairs(const int2* pairs, const uint32_t* flag, const uint32_t* tbase, int64_t n, uint32_t* otgt,
+                   uint32_t* osrc, hipStream_t s);
 // out9[c] = first index of the sorted class keys with key >= c, c = 0..8
 // out9[c] = first index whose key >> shift is >= c, c = 0..8
 void class_bounds(const uint32_t* key_sorted, int64_t n, int shift, int32_t* out9, hipStream_t s);

@@ -160,21 +160,24 @@ __device__ inline int32_t fast_slot(const CellArrays& c, int32_t t, int32_t s, c
     return slot_of[(size_t)cls * W * W * W + ((size_t)(ox + R) * W + (oy + R)) * W + (oz + R)];
 }
 
-// Same-level pairs per target.  Pairs come in emission order, where the
+// Same-level pairs per target, and the slot of every pair (-1 outside the
+// tables) for the gather fill.  Pairs come in emission order, where the
 // children of one frontier pair sit side by side, so a wave first sums its
 // runs of equal targets (segmented scan over the lanes) and adds each run
 // with one atomic (integer: the counts do not depend on timing).
-__global__ __launch_bounds__(256) void k_mark_targets(const uint32_t* __restrict__ tgt,
-                                                      const uint32_t* __restrict__ src, int64_t n, CellArrays c,
+__global__ __launch_bounds__(256) void k_mark_targets(const int2* __restrict__ pairs, int64_t n, CellArrays c,
                                                       const int32_t* __restrict__ slot_of, int R,
-                                                      uint32_t* __restrict__ nfast) {
+                                                      uint32_t* __restrict__ nfast, int16_t* __restrict__ slot) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
     int32_t t = -1;
     int v = 0;
     if (i < n) {
-        t = (int32_t)tgt[i];
-        v = fast_slot(c, t, (int32_t)src[i], slot_of, R) >= 0 ? 1 : 0;
+        const int2 pr = pairs[i];
+        t = pr.x;
+        const int32_t sl = fast_slot(c, t, pr.y, slot_of, R);
+        slot[i] = (int16_t)sl;
+        v = sl >= 0 ? 1 : 0;
     }
     const int32_t tp = __shfl_up(t, 1, 64);
     int flag = (lane == 0 || tp != t) ? 1 : 0;
@@ -191,18 +194,17 @@ __global__ __launch_bounds__(256) void k_mark_targets(const uint32_t* __restrict
     if (tail && t >= 0 && v > 0) atomicAdd(&nfast[t], (uint32_t)v);
 }
 
-__global__ void k_fill_gather(const uint32_t* __restrict__ tgt, const uint32_t* __restrict__ src, int64_t n,
-                              CellArrays c, const int32_t* __restrict__ slot_of, int R,
+__global__ void k_fill_gather(const int2* __restrict__ pairs, const int16_t* __restrict__ slot, int64_t n,
                               const int32_t* __restrict__ rowof, int32_t J, int NT, int32_t* __restrict__ gather,
                               uint32_t* __restrict__ general) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    int32_t t = (int32_t)tgt[i], s = (int32_t)src[i];
-    int32_t sl = fast_slot(c, t, s, slot_of, R);
+    const int32_t sl = slot[i];
     if (sl >= 0) {
-        const int32_t pr = rowof[t];  // tile * NT + column
-        const int32_t tile = pr / NT;
-        gather[((int64_t)tile * J + sl) * NT + (pr - tile * NT)] = s;
+        const int2 pr = pairs[i];
+        const int32_t pr_row = rowof[pr.x];  // tile * NT + column
+        const int32_t tile = pr_row / NT;
+        gather[((int64_t)tile * J + sl) * NT + (pr_row - tile * NT)] = pr.y;
         general[i] = 0u;
     } else {
         general[i] = 1u;
@@ -308,10 +310,10 @@ void csr_offsets(const uint32_t* tgt_sorted, int64_t n, int32_t ncell, int32_t* 
     k_csr<<<grid((int64_t)ncell + 1), 256, 0, s>>>(tgt_sorted, n, ncell, offsets);
 }
 
-void m2l_mark_targets(const uint32_t* tgt, const uint32_t* src, int64_t n, CellArrays cells,
-                      const int32_t* slot_of, int R, uint32_t* has_fast, hipStream_t s) {
+void m2l_mark_targets(const int2* pairs, int64_t n, CellArrays cells, const int32_t* slot_of, int R,
+                      uint32_t* has_fast, int16_t* slot, hipStream_t s) {
     if (n <= 0) return;
-    k_mark_targets<<<grid(n), 256, 0, s>>>(tgt, src, n, cells, slot_of, R, has_fast);
+    k_mark_targets<<<grid(n), 256, 0, s>>>(pairs, n, cells, slot_of, R, has_fast, slot);
 }
 
 void tile_slots(const int32_t* gather, GemmPlan plan, int NT, int ntiles, int32_t* act, int32_t* nact,
@@ -320,11 +322,10 @@ void tile_slots(const int32_t* gather, GemmPlan plan, int NT, int ntiles, int32_
     k_tile_slots<<<ntiles, 256, 0, s>>>(gather, plan, NT, act, nact);
 }
 
-void m2l_fill_gather(const uint32_t* tgt, const uint32_t* src, int64_t n, CellArrays cells,
-                     const int32_t* slot_of, int R, const int32_t* rowof, int32_t J, int NT, int32_t* gather,
-                     uint32_t* general, hipStream_t s) {
+void m2l_fill_gather(const int2* pairs, const int16_t* slot, int64_t n, const int32_t* rowof, int32_t J, int NT,
+                     int32_t* gather, uint32_t* general, hipStream_t s) {
     if (n <= 0) return;
-    k_fill_gather<<<grid(n), 256, 0, s>>>(tgt, src, n, cells, slot_of, R, rowof, J, NT, gather, general);
+    k_fill_gather<<<grid(n), 256, 0, s>>>(pairs, slot, n, rowof, J, NT, gather, general);
 }
 
 void row_class_keys(const uint32_t* nfast, CellArrays cells, int32_t ncell, int32_t J, uint32_t* key, uint32_t* val,
@@ -413,7 +414,7 @@ __global__ __launch_bounds__(256) void k_flag_counts(const uint32_t* __restrict_
 }
 
 // flagged pairs of each tile written from the tile's base, in index order
-__global__ __launch_bounds__(256) void k_compact_pairs(const uint32_t* __restrict__ tgt, const uint32_t* __restrict__ src,
+__global__ __launch_bounds__(256) void k_compact_pairs(const int2* __restrict__ pairs,
                                                        const uint32_t* __restrict__ flag, const uint32_t* __restrict__ tbase,
                                                        int64_t n, uint32_t* __restrict__ otgt,
                                                        uint32_t* __restrict__ osrc) {
@@ -432,8 +433,9 @@ __global__ __launch_bounds__(256) void k_compact_pairs(const uint32_t* __restric
         const uint64_t m = __ballot(f);
         if (f) {
             const uint32_t pos = off + (uint32_t)__popcll(m & lt);
-            otgt[pos] = tgt[g];
-            osrc[pos] = src[g];
+            const int2 pr = pairs[g];
+            otgt[pos] = (uint32_t)pr.x;
+            osrc[pos] = (uint32_t)pr.y;
         }
         off += (uint32_t)__popcll(m);
     }
@@ -448,10 +450,10 @@ void flag_counts(const uint32_t* flag, int64_t n, uint32_t* cnt, hipStream_t s) 
     k_flag_counts<<<(unsigned)compact_tiles(n), 256, 0, s>>>(flag, n, cnt);
 }
 
-void compact_pairs(const uint32_t* tgt, const uint32_t* src, const uint32_t* flag, const uint32_t* tbase, int64_t n,
-                   uint32_t* otgt, uint32_t* osrc, hipStream_t s) {
+void compact_pairs(const int2* pairs, const uint32_t* flag, const uint32_t* tbase, int64_t n, uint32_t* otgt,
+                   uint32_t* osrc, hipStream_t s) {
     if (n <= 0) return;
-    k_compact_pairs<<<(unsigned)compact_tiles(n), 256, 0, s>>>(tgt, src, flag, tbase, n, otgt, osrc);
+    k_compact_pairs<<<(unsigned)compact_tiles(n), 256, 0, s>>>(pairs, flag, tbase, n, otgt, osrc);
 }
 
 }  // namespace fmm
