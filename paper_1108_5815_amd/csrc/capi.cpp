@@ -887,7 +887,7 @@ void evaluate_impl(fmm_ctx c, int32_t precision, int32_t out_dtype, void* phi, v
     mark(c, PH_FAR);
     uint8_t* mflag = need<uint8_t>(c, c->m2pflag, (size_t)std::max(c->nleaf, 1));
     far_final((float4*)c->pts.p, (uint32_t*)c->idx.p, ca, (int32_t*)c->leaves.p, c->nleaf, mflag, (int32_t*)c->off[1].p,
-              (uint32_t*)c->src[1].p, p, KP, tb, M, L, nr, out_dtype, phi, ex, ey, ez, s);
+              (uint32_t*)c->src[1].p, c->nlist[1], p, KP, tb, M, L, nr, out_dtype, phi, ex, ey, ez, s);
     check_launch("far field");
     mark(c, PH_N);
     if (c->timing) {

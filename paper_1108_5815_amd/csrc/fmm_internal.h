@@ -223,10 +223,11 @@ void cls_skip(const int32_t* pos, int64_t ng, int32_t nbatched, uint8_t* skip, h
 // the class GEMMs into part (nbatched x KP) and the per-target sums into L
 void m2l_cls(const float* T, const ClsPlan& cp, int p, int KP, const float* M, float* part, const int32_t* goff,
              int32_t ncell, float* L, hipStream_t s);
-// m2pflag: scratch of nleaves bytes
+// m2pflag: scratch of nleaves bytes; n_m2p: cell-particle pairs in the list;
+// near is updated in place for the leaves with cell-particle sources
 void far_final(const float4* pts, const uint32_t* perm, CellArrays cells, const int32_t* leaves,
-               int32_t nleaves, uint8_t* m2pflag, const int32_t* m2p_off, const uint32_t* m2p_src, int p, int KP,
-               Tables t, const float* M, const float* L, const double4* near, int out_dtype,
+               int32_t nleaves, uint8_t* m2pflag, const int32_t* m2p_off, const uint32_t* m2p_src, int64_t n_m2p,
+               int p, int KP, Tables t, const float* M, const float* L, double4* near, int out_dtype,
                void* phi, void* ex, void* ey, void* ez, hipStream_t s);
 void p2p(const float4* pts, CellArrays cells, const int32_t* leaves, int32_t nleaves,
          const int32_t* p2p_off, const uint32_t* p2p_src, int guard_all, int tpl, double4* near,

@@ -292,12 +292,11 @@ __global__ __launch_bounds__(64) void k_far(const float4* __restrict__ pts, cons
                                             const int32_t* __restrict__ m2p_off, const uint32_t* __restrict__ m2p_src,
                                             int KP, const float* __restrict__ gl2p, const float* __restrict__ hm2p,
                                             const float* __restrict__ rc, const float* __restrict__ M,
-                                            const float* __restrict__ L, const double4* __restrict__ near,
+                                            const float* __restrict__ L, double4* __restrict__ near,
                                             int out_dtype, void* __restrict__ ophi, void* __restrict__ oex,
                                             void* __restrict__ oey, void* __restrict__ oez) {
     constexpr int K = (P + 1) * (P + 1);
     __shared__ float Lt[LPW][K];
-    __shared__ float Ms[K];
     __shared__ LeafPack<LPW> lp;
     __shared__ uint8_t s_m2p[LPW];
     const int lane = threadIdx.x;
@@ -336,29 +335,68 @@ __global__ __launch_bounds__(64) void k_far(const float4* __restrict__ pts, cons
             acc.z += (double)(s2 * l1im) / r2;
             acc.w += (double)(-l10) / r2;
         }
-        // cell-particle sources, leaf by leaf (the wave takes each list in turn)
-        for (int qq = 0; qq < lp.nq; qq++) {
-            if (!s_m2p[qq] || lp.pre[qq + 1] <= r0 || lp.pre[qq] >= r0 + 64) continue;
-            for (int A = lp.cell[qq]; A >= 0; A = c.parent[A]) {
-                for (int32_t a = m2p_off[A]; a < m2p_off[A + 1]; a++) {
-                    const int s = (int)m2p_src[a];
-                    const double4 cs = c.ctr[s];
-                    __syncthreads();
-                    for (int u = lane; u < K; u += 64) Ms[u] = M[(size_t)s * KP + u];
-                    __syncthreads();
-                    if (valid && q == qq) {
-                        const double ir = 1.0 / cs.w;
-                        const float x = (float)(((double)Pt.x - cs.x) * ir), y = (float)(((double)Pt.y - cs.y) * ir),
-                                    z = (float)(((double)Pt.z - cs.z) * ir);
-                        float phi = 0.f, l10 = 0.f, l1re = 0.f, l1im = 0.f;
-                        m2p_point<P>(Ms, hm2p, x, y, z, rc, phi, l10, l1re, l1im);
-                        const double r1 = cs.w, r2 = cs.w * cs.w;
-                        acc.x += (double)phi / r1;
-                        acc.y += (double)(-s2 * l1re) / r2;
-                        acc.z += (double)(s2 * l1im) / r2;
-                        acc.w += (double)(-l10) / r2;
-                    }
-                }
+        if (valid && s_m2p[q]) {
+            near[i] = acc;  // cell-particle sources follow (k_far_m2p)
+        } else if (valid) {
+            const uint32_t o = perm[i];
+            if (out_dtype == 1) {
+                ((double*)ophi)[o] = acc.x;
+                ((double*)oex)[o] = acc.y;
+                ((double*)oey)[o] = acc.z;
+                ((double*)oez)[o] = acc.w;
+            } else {
+                ((float*)ophi)[o] = (float)acc.x;
+                ((float*)oex)[o] = (float)acc.y;
+                ((float*)oey)[o] = (float)acc.z;
+                ((float*)oez)[o] = (float)acc.w;
+            }
+        }
+    }
+}
+
+// Cell-particle (M2P) part of the leaves flagged in m2pflag, one leaf per
+// workgroup: each particle continues the FP64 sum k_far stored in near[i]
+// with the sources of its leaf's list, then of each ancestor's, and writes
+// the result.  (The lists are walked by all lanes of the leaf together, each
+// source multipole staged once in LDS.)
+template <int P>
+__global__ __launch_bounds__(64) void k_far_m2p(const float4* __restrict__ pts, const uint32_t* __restrict__ perm,
+                                                CellArrays c, const int32_t* __restrict__ leaves,
+                                                const uint8_t* __restrict__ m2pflag,
+                                                const int32_t* __restrict__ m2p_off,
+                                                const uint32_t* __restrict__ m2p_src, int KP,
+                                                const float* __restrict__ hm2p, const float* __restrict__ rc,
+                                                const float* __restrict__ M, const double4* __restrict__ near,
+                                                int out_dtype, void* __restrict__ ophi, void* __restrict__ oex,
+                                                void* __restrict__ oey, void* __restrict__ oez) {
+    constexpr int K = (P + 1) * (P + 1);
+    __shared__ float Ms[K];
+    if (!m2pflag[blockIdx.x]) return;
+    const int cell = leaves[blockIdx.x];
+    const int32_t b = c.begin[cell], e = c.end[cell];
+    const float s2 = 1.41421356237309505f;
+    for (int32_t ch = b; ch < e; ch += 64) {
+        const int32_t i = ch + threadIdx.x;
+        const bool valid = i < e;
+        const float4 Pt = pts[valid ? i : b];
+        double4 acc = valid ? near[i] : make_double4(0, 0, 0, 0);
+        for (int A = cell; A >= 0; A = c.parent[A]) {
+            for (int32_t a = m2p_off[A]; a < m2p_off[A + 1]; a++) {
+                const int s = (int)m2p_src[a];
+                const double4 cs = c.ctr[s];
+                __syncthreads();
+                for (int u = threadIdx.x; u < K; u += 64) Ms[u] = M[(size_t)s * KP + u];
+                __syncthreads();
+                const double ir = 1.0 / cs.w;
+                const float x = (float)(((double)Pt.x - cs.x) * ir), y = (float)(((double)Pt.y - cs.y) * ir),
+                            z = (float)(((double)Pt.z - cs.z) * ir);
+                float phi = 0.f, l10 = 0.f, l1re = 0.f, l1im = 0.f;
+                m2p_point<P>(Ms, hm2p, x, y, z, rc, phi, l10, l1re, l1im);
+                const double r1 = cs.w, r2 = cs.w * cs.w;
+                acc.x += (double)phi / r1;
+                acc.y += (double)(-s2 * l1re) / r2;
+                acc.z += (double)(s2 * l1im) / r2;
+                acc.w += (double)(-l10) / r2;
             }
         }
         if (valid) {
@@ -383,12 +421,15 @@ constexpr int kLeavesPerWave = 8;
 template <int P>
 void launch_far(const float4* pts, const uint32_t* perm, CellArrays cells, const int32_t* leaves, int32_t nleaves,
                 uint8_t* m2pflag, const int32_t* m2p_off, const uint32_t* m2p_src, int KP, Tables t, const float* M,
-                const float* L, const double4* near, int out_dtype, void* phi, void* ex, void* ey, void* ez,
+                const float* L, double4* near, int out_dtype, void* phi, void* ex, void* ey, void* ez, bool any_m2p,
                 hipStream_t s) {
     k_m2p_flags<<<(nleaves + 255) / 256, 256, 0, s>>>(cells, leaves, nleaves, m2p_off, m2pflag);
     constexpr int W = kLeavesPerWave;
     k_far<P, W><<<(nleaves + W - 1) / W, 64, 0, s>>>(pts, perm, cells, leaves, nleaves, m2pflag, m2p_off, m2p_src, KP,
                                                      t.gl2p, t.hm2p, t.rcoef, M, L, near, out_dtype, phi, ex, ey, ez);
+    if (any_m2p)
+        k_far_m2p<P><<<nleaves, 64, 0, s>>>(pts, perm, cells, leaves, m2pflag, m2p_off, m2p_src, KP, t.hm2p, t.rcoef, M,
+                                            near, out_dtype, phi, ex, ey, ez);
 }
 
 template <int P>
@@ -401,14 +442,14 @@ void launch_p2m(const float4* pts, CellArrays cells, const int32_t* leaves, int3
 }  // namespace
 
 void far_final(const float4* pts, const uint32_t* perm, CellArrays cells, const int32_t* leaves, int32_t nleaves,
-               uint8_t* m2pflag, const int32_t* m2p_off, const uint32_t* m2p_src, int p, int KP, Tables t,
-               const float* M, const float* L, const double4* near, int out_dtype, void* phi, void* ex, void* ey,
+               uint8_t* m2pflag, const int32_t* m2p_off, const uint32_t* m2p_src, int64_t n_m2p, int p, int KP,
+               Tables t, const float* M, const float* L, double4* near, int out_dtype, void* phi, void* ex, void* ey,
                void* ez, hipStream_t s) {
     if (nleaves <= 0) return;
 #define FMM_FAR_CASE(PP)                                                                                         \
     case PP:                                                                                                     \
         launch_far<PP>(pts, perm, cells, leaves, nleaves, m2pflag, m2p_off, m2p_src, KP, t, M, L, near, out_dtype, \
-                       phi, ex, ey, ez, s);                                                                      \
+                       phi, ex, ey, ez, n_m2p > 0, s);                                                           \
         break;
     switch (p) {
         FMM_FAR_CASE(0)

@@ -81,49 +81,162 @@ __global__ void k_cell_buckets(CellArrays c, int32_t ncell, uint8_t* __restrict_
     nb[i] = (uint8_t)(b < 0 ? 0 : (b >= kMlpBn ? kMlpBn - 1 : b));
 }
 
-__global__ void k_trav_count(const int2* __restrict__ fr, int64_t nf, CellArrays c, TravParams tp,
-                             uint4* __restrict__ cnt, uint4* __restrict__ kinds) {
-    int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= nf) return;
-    int2 pr = fr[f];
-    int32_t t0, t1, s0, s1;
-    split_ranges(c, pr.x, pr.y, t0, t1, s0, s1);
-    uint32_t n[4] = {0, 0, 0, 0};
-    uint32_t w[4] = {0, 0, 0, 0};
-    int q = 0;
-    for (int32_t t = t0; t < t1; t++)
-        for (int32_t s = s0; s < s1; s++, q++) {
-            const int k = classify(c, t, s, tp);
-            n[k]++;
-            w[q >> 4] |= (uint32_t)k << (2 * (q & 15));
-        }
-    cnt[f] = make_uint4(n[0], n[1], n[2], n[3]);
-    kinds[f] = make_uint4(w[0], w[1], w[2], w[3]);
+// Count and emit work on the child pairs of a wave's 16 frontier entries,
+// flattened (entry by entry, child order) and taken 64 at a time, one child
+// pair per lane: an entry has 64 children when both cells split and 8 or
+// fewer when only one does, so one entry per lane left most of the child
+// loop serial and its stores scattered.  Kinds are kept per entry as two
+// 64-bit masks (bit q of `lo`/`hi` = low/high bit of child q's kind); a
+// child's place in its kind's output is its entry's offset plus the number
+// of earlier children of the same kind, so the emitted order is frontier
+// order, then child order, as before.
+constexpr int kEPW = 16;  // frontier entries per wave
+
+struct EntryRanges {
+    int32_t t0[kEPW], ns[kEPW], s0[kEPW], pre[kEPW + 1];
+    uint32_t mns[kEPW];  // ceil(2^16 / ns): q / ns = (q * mns) >> 16 for q < 64, ns <= 8
+};
+
+// entry ranges of the wave's frontier entries f0 .. f0+kEPW-1 into LDS;
+// returns the number of child pairs of the wave
+__device__ inline int wave_entries(const int2* __restrict__ fr, int64_t nf, int64_t f0, const CellArrays& c,
+                                   EntryRanges& er, int lane) {
+    const int64_t f = f0 + lane;
+    int nch = 0;
+    if (lane < kEPW && f < nf) {
+        const int2 pr = fr[f];
+        int32_t t0, t1, s0, s1;
+        split_ranges(c, pr.x, pr.y, t0, t1, s0, s1);
+        er.t0[lane] = t0;
+        er.s0[lane] = s0;
+        er.ns[lane] = s1 - s0;
+        er.mns[lane] = (65536u + (uint32_t)(s1 - s0) - 1u) / (uint32_t)(s1 - s0);
+        nch = (t1 - t0) * (s1 - s0);
+    }
+    int incl = nch;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int u = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += u;
+    }
+    if (lane < kEPW) er.pre[lane + 1] = incl;
+    if (lane == 0) er.pre[0] = 0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    return __shfl(incl, 63, 64);
 }
 
-__global__ void k_trav_emit(const int2* __restrict__ fr, int64_t nf, CellArrays c,
-                            const uint4* __restrict__ kinds, const uint4* __restrict__ off, int64_t b0, int64_t b1,
-                            int64_t b2, int2* __restrict__ m2l, int2* __restrict__ m2p, int2* __restrict__ p2p,
-                            int2* __restrict__ next) {
-    int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= nf) return;
-    int2 pr = fr[f];
-    int32_t t0, t1, s0, s1;
-    split_ranges(c, pr.x, pr.y, t0, t1, s0, s1);
-    uint4 o = off[f];
-    const uint4 kw = kinds[f];
-    const uint32_t w[4] = {kw.x, kw.y, kw.z, kw.w};
-    int64_t w0 = b0 + o.x, w1 = b1 + o.y, w2 = b2 + o.z, w3 = o.w;
-    int q = 0;
-    for (int32_t t = t0; t < t1; t++)
-        for (int32_t s = s0; s < s1; s++, q++) {
-            const int k = (int)((w[q >> 4] >> (2 * (q & 15))) & 3u);
-            int2 v = make_int2(t, s);
-            if (k == KIND_M2L) m2l[w0++] = v;
-            else if (k == KIND_M2P) m2p[w1++] = v;
-            else if (k == KIND_P2P) p2p[w2++] = v;
-            else next[w3++] = v;
+// entry (0..kEPW-1) holding flattened child c of the wave (last e with pre[e] <= c)
+__device__ inline int entry_of(const EntryRanges& er, int c) {
+    int lo = 0, hi = kEPW;
+#pragma unroll
+    for (int it = 0; (1 << it) < kEPW; it++) {
+        const int mid = (lo + hi) >> 1;
+        if (er.pre[mid] <= c) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_trav_count(const int2* __restrict__ fr, int64_t nf, CellArrays c,
+                                                    TravParams tp, uint4* __restrict__ cnt,
+                                                    uint4* __restrict__ kinds) {
+    __shared__ EntryRanges s_er[4];
+    __shared__ uint32_t s_n[4][kEPW][4];
+    __shared__ unsigned long long s_lo[4][kEPW], s_hi[4][kEPW];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t f0 = ((int64_t)blockIdx.x * 4 + w) * kEPW;
+    if (f0 >= nf) return;  // wave-uniform; no block barrier below
+    EntryRanges& er = s_er[w];
+    if (lane < kEPW) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) s_n[w][lane][k] = 0;
+        s_lo[w][lane] = 0;
+        s_hi[w][lane] = 0;
+    }
+    const int total = wave_entries(fr, nf, f0, c, er, lane);
+    for (int r0 = 0; r0 < total; r0 += 64) {
+        const int ch = r0 + lane;
+        const bool valid = ch < total;
+        int e = 0, q = 0, k = 0;
+        if (valid) {
+            e = entry_of(er, ch);
+            q = ch - er.pre[e];
+            const int qt = (int)(((uint32_t)q * er.mns[e]) >> 16);
+            k = classify(c, er.t0[e] + qt, er.s0[e] + (q - qt * er.ns[e]), tp);
         }
+        // kinds of the round by ballot; the first lane of each entry in the
+        // round folds its entry's lanes into the entry's counts and masks
+        const uint64_t mv = __ballot(valid), m1 = __ballot(valid && (k & 1)), m2 = __ballot(valid && (k & 2));
+        if (valid && (q == 0 || lane == 0)) {
+            const int last = min(63, er.pre[e + 1] - r0 - 1);
+            const uint64_t upto = last == 63 ? ~0ull : ((1ull << (last + 1)) - 1ull);
+            const uint64_t rng = upto & ~((1ull << lane) - 1ull);
+            const uint64_t lo = m1 & rng, hi = m2 & rng, all = mv & rng;
+            s_n[w][e][KIND_M2L] += (uint32_t)__popcll(all & ~lo & ~hi);
+            s_n[w][e][KIND_M2P] += (uint32_t)__popcll(lo & ~hi);
+            s_n[w][e][KIND_P2P] += (uint32_t)__popcll(~lo & hi);
+            s_n[w][e][KIND_SPLIT] += (uint32_t)__popcll(lo & hi);
+            s_lo[w][e] |= (lo >> lane) << q;
+            s_hi[w][e] |= (hi >> lane) << q;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int64_t f = f0 + lane;
+    if (lane < kEPW && f < nf) {
+        cnt[f] = make_uint4(s_n[w][lane][0], s_n[w][lane][1], s_n[w][lane][2], s_n[w][lane][3]);
+        const unsigned long long lo = s_lo[w][lane], hi = s_hi[w][lane];
+        kinds[f] = make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
+    }
+}
+
+__global__ __launch_bounds__(256) void k_trav_emit(const int2* __restrict__ fr, int64_t nf, CellArrays c,
+                                                   const uint4* __restrict__ kinds, const uint4* __restrict__ off,
+                                                   int64_t b0, int64_t b1, int64_t b2, int2* __restrict__ m2l,
+                                                   int2* __restrict__ m2p, int2* __restrict__ p2p,
+                                                   int2* __restrict__ next) {
+    __shared__ EntryRanges s_er[4];
+    __shared__ unsigned long long s_lo[4][kEPW], s_hi[4][kEPW];
+    __shared__ uint4 s_off[4][kEPW];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t f0 = ((int64_t)blockIdx.x * 4 + w) * kEPW;
+    if (f0 >= nf) return;  // wave-uniform; no block barrier below
+    EntryRanges& er = s_er[w];
+    {
+        const int64_t f = f0 + lane;
+        if (lane < kEPW && f < nf) {
+            const uint4 kw = kinds[f];
+            s_lo[w][lane] = (unsigned long long)kw.x | ((unsigned long long)kw.y << 32);
+            s_hi[w][lane] = (unsigned long long)kw.z | ((unsigned long long)kw.w << 32);
+            s_off[w][lane] = off[f];
+        }
+    }
+    const int total = wave_entries(fr, nf, f0, c, er, lane);
+    for (int r0 = 0; r0 < total; r0 += 64) {
+        const int ch = r0 + lane;
+        if (ch < total) {
+            const int e = entry_of(er, ch);
+            const int q = ch - er.pre[e];
+            const int ns = er.ns[e];
+            const int qt = q / ns;
+            const int2 v = make_int2(er.t0[e] + qt, er.s0[e] + (q - qt * ns));
+            const unsigned long long lo = s_lo[w][e], hi = s_hi[w][e];
+            const int k = (int)((lo >> q) & 1ull) | ((int)((hi >> q) & 1ull) << 1);
+            const unsigned long long same = ((k & 1) ? lo : ~lo) & ((k & 2) ? hi : ~hi);
+            const uint32_t rank = (uint32_t)__popcll(same & ((1ull << q) - 1ull));
+            const uint4 o = s_off[w][e];
+            if (k == KIND_M2L) m2l[b0 + o.x + rank] = v;
+            else if (k == KIND_M2P) m2p[b1 + o.y + rank] = v;
+            else if (k == KIND_P2P) p2p[b2 + o.z + rank] = v;
+            else next[(int64_t)o.w + rank] = v;
+        }
+    }
 }
 
 __global__ void k_split_pairs(const int2* __restrict__ pairs, int64_t n, uint32_t* __restrict__ tgt,
@@ -290,14 +403,14 @@ void cell_buckets(CellArrays cells, int32_t ncell, uint8_t* nbucket, hipStream_t
 void trav_count(const int2* frontier, int64_t nf, CellArrays cells, TravParams tp, uint4* cnt, uint4* kinds,
                 hipStream_t s) {
     if (nf <= 0) return;
-    k_trav_count<<<grid(nf), 256, 0, s>>>(frontier, nf, cells, tp, cnt, kinds);
+    k_trav_count<<<grid(nf, 4 * kEPW), 256, 0, s>>>(frontier, nf, cells, tp, cnt, kinds);
 }
 
 void trav_emit(const int2* frontier, int64_t nf, CellArrays cells, const uint4* kinds, const uint4* off,
                int64_t base_m2l, int64_t base_m2p, int64_t base_p2p, int2* m2l, int2* m2p, int2* p2p,
                int2* next, hipStream_t s) {
     if (nf <= 0) return;
-    k_trav_emit<<<grid(nf), 256, 0, s>>>(frontier, nf, cells, kinds, off, base_m2l, base_m2p, base_p2p, m2l,
+    k_trav_emit<<<grid(nf, 4 * kEPW), 256, 0, s>>>(frontier, nf, cells, kinds, off, base_m2l, base_m2p, base_p2p, m2l,
                                          m2p, p2p, next);
 }
 
