@@ -249,12 +249,13 @@ struct GemmPlan {
     int32_t nrows;           // rows (targets) over all classes
     int32_t zcell;           // a cell index whose multipole row is all zero (absent sources read it)
 };
-// slot groups for J slots per class: each group's operators (J/G blocks of
-// 64 KB at storage width 128) should stay well inside one XCD's 4 MB L2
+// slot groups for J slots per class: each group's operators (J/G <= 64
+// blocks of 64 KB at storage width 128; 36 at theta = 0.4) should stay
+// inside one XCD's 4 MB L2, and fewer groups mean fewer partial rows to sum
 int gemm_slot_groups(int J);
-// a group holds at most J / G + 1 slots (33 with G = 8 ceil(J / 256)); the GEMM
+// a group holds at most J / G + 1 slots (65 with G = 8 ceil(J / 512)); the GEMM
 // kernels stage a group's slots and operator ids in LDS arrays of this size
-constexpr int kGemmMaxGroupSlots = 64;
+constexpr int kGemmMaxGroupSlots = 80;
 // act[tile * J + k], k < nact[tile]: the slots of tile `tile` that some row uses
 void tile_slots(const int32_t* gather, GemmPlan plan, int NT, int ntiles, int32_t* act, int32_t* nact,
                 hipStream_t s);

@@ -274,7 +274,7 @@ int gemm_tile_cols(int p) {
     }
 }
 
-int gemm_slot_groups(int J) { return 8 * std::max(1, (J + 255) / 256); }
+int gemm_slot_groups(int J) { return 8 * std::max(1, (J + 511) / 512); }
 
 void m2l_reduce_groups(const float* part, GemmPlan plan, const uint32_t* rowcell, int KP, int K, float* L,
                        hipStream_t s) {
