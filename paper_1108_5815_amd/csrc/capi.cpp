@@ -91,6 +91,7 @@ struct fmm_ctx_s {
     Buf inner, leafpos;  // non-leaf cells in cell order; leaves before each cell
     Buf m2pflag;         // per leaf: cell-particle sources on the leaf or an ancestor
     Buf m2lslot;         // per cell-cell pair: its GEMM slot or -1
+    Buf tbounds;         // tree build: octant boundaries of the cells of a level
     Buf has_fast, rkey, rval, rkey2, rval2, rowof, gather, general, gtg, gsr, goff, tact, tnact, m2l_part, Msplit, nbucket, kinds;
     // pairs outside the same-level tables, batched by class
     ClsPlan cp;
@@ -132,7 +133,7 @@ struct fmm_ctx_s {
                       &d_h, &d_rc, &d_mlp, &M, &L, &nearb, &tune_pts, &tune_out, &d_mlp_m, &d_mlp_v,
                       &d_grad, &d_grad_rec, &d_loss_rec, &d_feat, &d_kind, &d_tgt, &d_table, &d_Thi, &d_Tlo,
                       &d_seg, &d_bt, &d_pb, &d_box, &d_frame, &inst, &bsort, &tact, &tnact,
-                      &leaves_cls, &inner, &leafpos, &m2pflag, &m2lslot, &lkey, &lval, &lkey2, &lval2, &at_out, &m2l_part, &Msplit, &nbucket, &kinds, &ckey, &ckey2, &cval, &cval2,
+                      &leaves_cls, &inner, &leafpos, &m2pflag, &m2lslot, &tbounds, &lkey, &lval, &lkey2, &lval2, &at_out, &m2l_part, &Msplit, &nbucket, &kinds, &ckey, &ckey2, &cval, &cval2,
                       &chead, &choff, &cstart, &cpos, &csrcs, &cnt_t, &ctbase, &ctile, &cT, &cskip, &cls_part};
         for (Buf* b : all) bufs.push_back(b);
     }
@@ -426,7 +427,8 @@ void build_forest_impl(fmm_ctx c, int32_t nseg, const int64_t* hseg, int dtype, 
         uint32_t* nsplit = need<uint32_t>(c, c->tmp1, m + 1);
         uint32_t* choff = need<uint32_t>(c, c->tmp2, m + 1);
         CellArrays ca = cells_of(c);
-        tree_count(keys, ca, c0, c1, L, ncrit, nsplit, s);
+        int32_t* tbnd = need<int32_t>(c, c->tbounds, (size_t)m * 7 + 1);
+        tree_count(keys, ca, c0, c1, L, ncrit, nsplit, tbnd, s);
         scan_u32(nsplit, choff, (uint32_t*)(d6 + 12), m, ws, s);
         check_launch("tree count");
         uint32_t* hh = (uint32_t*)host_stage(c);
@@ -434,7 +436,7 @@ void build_forest_impl(fmm_ctx c, int32_t nseg, const int64_t* hseg, int dtype, 
         uint32_t nnew = hh[0];
         if ((size_t)c1 + nnew > c->c_begin.cap / sizeof(int32_t)) ensure_cells(c, (size_t)c1 + nnew, c1);
         ca = cells_of(c);
-        tree_emit(keys, ca, c0, c1, L, nsplit, choff, s);
+        tree_emit(ca, c0, c1, L, nsplit, choff, (const int32_t*)c->tbounds.p, s);
         check_launch("tree emit");
         c->lvl.push_back(c1);
         total = c1 + (int32_t)nnew;

@@ -83,11 +83,12 @@ void permute_points(const void* x, const void* y, const void* z, const void* q, 
                     int64_t n, const uint32_t* idx, float4* pts, hipStream_t s);
 // one level of the adaptive tree: cells [c0, c1) at level L.  nsplit[c-c0] =
 // number of children of cell c (0 if it does not split).
+// bounds: [c1 - c0][7] octant boundaries of the cells that split (scratch)
 void tree_count(const uint64_t* keys, CellArrays cells, int32_t c0, int32_t c1, int L,
-                int32_t ncrit, uint32_t* nsplit, hipStream_t s);
+                int32_t ncrit, uint32_t* nsplit, int32_t* bounds, hipStream_t s);
 // child_off = exclusive scan of nsplit; children get ids c1 + child_off[c-c0]
-void tree_emit(const uint64_t* keys, CellArrays cells, int32_t c0, int32_t c1, int L,
-               const uint32_t* nsplit, const uint32_t* child_off, hipStream_t s);
+void tree_emit(CellArrays cells, int32_t c0, int32_t c1, int L, const uint32_t* nsplit,
+               const uint32_t* child_off, const int32_t* bounds, hipStream_t s);
 void cell_geometry(CellArrays cells, int32_t ncell, const int64_t* seg, int nseg, const Frame* fr, hipStream_t s);
 
 // sum over (tgt, src) pairs of n_t * n_s (both = 1) or n_t (both = 0) into *out (device)

@@ -153,40 +153,75 @@ __global__ void k_permute(const F* __restrict__ x, const F* __restrict__ y, cons
 }
 
 // first index in [lo, hi) with keys[i] >= v
-__device__ inline int32_t lower_bound_u64(const uint64_t* keys, int32_t lo, int32_t hi, uint64_t v) {
-    while (lo < hi) {
-        int32_t mid = lo + ((hi - lo) >> 1);
-        if (keys[mid] < v) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
-
-__device__ inline void octant_bounds(const uint64_t* keys, int32_t b, int32_t e, uint64_t prefix,
-                                     int L, int32_t bnd[9]) {
-    int sh = 3 * (20 - L);  // bit position of the level-(L+1) digit
-    bnd[0] = b;
-    bnd[8] = e;
-    for (int o = 1; o < 8; o++) bnd[o] = lower_bound_u64(keys, b, e, ((prefix << 3) | (uint64_t)o) << sh);
-}
-
-__global__ void k_tree_count(const uint64_t* __restrict__ keys, CellArrays cells, int32_t c0,
-                             int32_t c1, int L, int32_t ncrit, uint32_t* __restrict__ nsplit) {
-    int32_t c = c0 + (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (c >= c1) return;
-    int32_t b = cells.begin[c], e = cells.end[c];
+// Cells of level L that split: one wave per cell finds the 7 octant
+// boundaries (bnd[o] = first index whose key is >= the smallest key of octant
+// o) with 64-ary searches run side by side: each round every lane samples one
+// position per open interval and a ballot per octant shrinks it 64-fold, so a
+// cell of 4M keys needs 4 rounds of independent loads instead of 7 binary
+// searches of 22 dependent ones.  The boundaries are kept for the emit pass.
+__global__ __launch_bounds__(256) void k_tree_count(const uint64_t* __restrict__ keys, CellArrays cells, int32_t c0,
+                                                    int32_t c1, int L, int32_t ncrit, uint32_t* __restrict__ nsplit,
+                                                    int32_t* __restrict__ bounds) {
+    const int lane = threadIdx.x & 63;
+    const int32_t c = c0 + (int32_t)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    if (c >= c1) return;  // wave-uniform
+    const int32_t b = cells.begin[c], e = cells.end[c];
     uint32_t cnt = 0;
     if (e - b > ncrit && L < kMaxLevel) {
-        int32_t bnd[9];
-        octant_bounds(keys, b, e, cells.prefix[c], L, bnd);
-        for (int o = 0; o < 8; o++) cnt += bnd[o + 1] > bnd[o] ? 1u : 0u;
+        const int sh = 3 * (20 - L);  // bit position of the level-(L+1) digit
+        const uint64_t pre3 = cells.prefix[c] << 3;
+        int32_t lo[7], hi[7];
+#pragma unroll
+        for (int o = 0; o < 7; o++) {
+            lo[o] = b;
+            hi[o] = e;
+        }
+        bool open = true;
+        while (open) {
+            uint64_t kv[7];
+#pragma unroll
+            for (int o = 0; o < 7; o++) {
+                const int64_t span = hi[o] - lo[o];
+                kv[o] = span > 0 ? keys[lo[o] + (int32_t)((span * lane) >> 6)] : 0ull;
+            }
+            open = false;
+#pragma unroll
+            for (int o = 0; o < 7; o++) {
+                const int64_t span = hi[o] - lo[o];
+                if (span <= 0) continue;
+                const uint64_t tgt = (pre3 | (uint64_t)(o + 1)) << sh;
+                const int nb = __popcll(__ballot(kv[o] < tgt));  // samples below the boundary
+                if (nb == 0) {
+                    hi[o] = lo[o];  // key[lo] >= tgt
+                } else {
+                    const int32_t below = lo[o] + (int32_t)((span * (nb - 1)) >> 6);
+                    const int32_t above = nb < 64 ? lo[o] + (int32_t)((span * nb) >> 6) : hi[o];
+                    lo[o] = below + 1;
+                    hi[o] = above;
+                }
+                if (hi[o] > lo[o]) open = true;
+            }
+        }
+        int32_t prev = b;
+#pragma unroll
+        for (int o = 0; o < 7; o++) {
+            cnt += lo[o] > prev ? 1u : 0u;
+            prev = lo[o];
+        }
+        cnt += e > prev ? 1u : 0u;
+        if (lane < 7) {
+            int32_t v = lo[0];
+#pragma unroll
+            for (int o = 1; o < 7; o++)
+                if (lane == o) v = lo[o];
+            bounds[(int64_t)(c - c0) * 7 + lane] = v;
+        }
     }
-    nsplit[c - c0] = cnt;
+    if (lane == 0) nsplit[c - c0] = cnt;
 }
 
-__global__ void k_tree_emit(const uint64_t* __restrict__ keys, CellArrays cells, int32_t c0,
-                            int32_t c1, int L, const uint32_t* __restrict__ nsplit,
-                            const uint32_t* __restrict__ off) {
+__global__ void k_tree_emit(CellArrays cells, int32_t c0, int32_t c1, int L, const uint32_t* __restrict__ nsplit,
+                            const uint32_t* __restrict__ off, const int32_t* __restrict__ bounds) {
     int32_t c = c0 + (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
     if (c >= c1) return;
     uint32_t cnt = nsplit[c - c0];
@@ -199,8 +234,11 @@ __global__ void k_tree_emit(const uint64_t* __restrict__ keys, CellArrays cells,
     cells.child[c] = first;
     cells.nchild[c] = (int32_t)cnt;
     int32_t bnd[9];
-    uint64_t prefix = cells.prefix[c];
-    octant_bounds(keys, cells.begin[c], cells.end[c], prefix, L, bnd);
+    bnd[0] = cells.begin[c];
+    bnd[8] = cells.end[c];
+#pragma unroll
+    for (int o = 1; o < 8; o++) bnd[o] = bounds[(int64_t)(c - c0) * 7 + o - 1];
+    const uint64_t prefix = cells.prefix[c];
     int32_t k = first;
     for (int o = 0; o < 8; o++) {
         if (bnd[o + 1] <= bnd[o]) continue;
@@ -290,17 +328,18 @@ void permute_points(const void* x, const void* y, const void* z, const void* q, 
 }
 
 void tree_count(const uint64_t* keys, CellArrays cells, int32_t c0, int32_t c1, int L, int32_t ncrit,
-                uint32_t* nsplit, hipStream_t s) {
+                uint32_t* nsplit, int32_t* bounds, hipStream_t s) {
     int32_t m = c1 - c0;
     if (m <= 0) return;
-    k_tree_count<<<(m + 255) / 256, 256, 0, s>>>(keys, cells, c0, c1, L, ncrit, nsplit);
+    k_tree_count<<<(unsigned)(((int64_t)m * 64 + 255) / 256), 256, 0, s>>>(keys, cells, c0, c1, L, ncrit, nsplit,
+                                                                          bounds);
 }
 
-void tree_emit(const uint64_t* keys, CellArrays cells, int32_t c0, int32_t c1, int L,
-               const uint32_t* nsplit, const uint32_t* child_off, hipStream_t s) {
+void tree_emit(CellArrays cells, int32_t c0, int32_t c1, int L, const uint32_t* nsplit, const uint32_t* child_off,
+               const int32_t* bounds, hipStream_t s) {
     int32_t m = c1 - c0;
     if (m <= 0) return;
-    k_tree_emit<<<(m + 255) / 256, 256, 0, s>>>(keys, cells, c0, c1, L, nsplit, child_off);
+    k_tree_emit<<<(m + 255) / 256, 256, 0, s>>>(cells, c0, c1, L, nsplit, child_off, bounds);
 }
 
 void cell_geometry(CellArrays cells, int32_t ncell, const int64_t* seg, int nseg, const Frame* fr, hipStream_t s) {
