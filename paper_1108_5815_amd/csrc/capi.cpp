@@ -123,6 +123,10 @@ struct fmm_ctx_s {
 
     // pinned host staging
     void* host = nullptr;
+    // per-level counts written by the scan kernels straight into mapped,
+    // coherent host memory (the host only synchronises: no copy launch)
+    uint32_t* hcount = nullptr;
+    uint32_t* hcount_dev = nullptr;
 
     fmm_ctx_s() {
         Buf* all[] = {&keys, &keys2, &idx, &idx2, &pts, &ws, &small, &c_begin, &c_end, &c_parent, &c_child,
@@ -201,6 +205,19 @@ T* need_keep(fmm_ctx c, Buf& b, size_t count, size_t keep_count) {
 void* host_stage(fmm_ctx c) {
     if (!c->host) ck(hipHostMalloc(&c->host, 1 << 16, hipHostMallocDefault), "hipHostMalloc");
     return c->host;
+}
+
+// device pointer of 16 mapped host counters (read by the host after a sync)
+uint32_t* mapped_counts(fmm_ctx c) {
+    if (!c->hcount) {
+        void* h = nullptr;
+        ck(hipHostMalloc(&h, 256, hipHostMallocMapped | hipHostMallocCoherent), "hipHostMalloc");
+        c->hcount = (uint32_t*)h;
+        void* d = nullptr;
+        ck(hipHostGetDevicePointer(&d, h, 0), "hipHostGetDevicePointer");
+        c->hcount_dev = (uint32_t*)d;
+    }
+    return c->hcount_dev;
 }
 
 template <class T>
@@ -429,11 +446,10 @@ void build_forest_impl(fmm_ctx c, int32_t nseg, const int64_t* hseg, int dtype, 
         CellArrays ca = cells_of(c);
         int32_t* tbnd = need<int32_t>(c, c->tbounds, (size_t)m * 7 + 1);
         tree_count(keys, ca, c0, c1, L, ncrit, nsplit, tbnd, s);
-        scan_u32(nsplit, choff, (uint32_t*)(d6 + 12), m, ws, s);
+        scan_u32(nsplit, choff, mapped_counts(c), m, ws, s);
         check_launch("tree count");
-        uint32_t* hh = (uint32_t*)host_stage(c);
-        to_host<uint32_t>(c, hh, d6 + 12, 1);
-        uint32_t nnew = hh[0];
+        ck(hipStreamSynchronize(s), "sync");
+        uint32_t nnew = c->hcount[0];
         if ((size_t)c1 + nnew > c->c_begin.cap / sizeof(int32_t)) ensure_cells(c, (size_t)c1 + nnew, c1);
         ca = cells_of(c);
         tree_emit(ca, c0, c1, L, nsplit, choff, (const int32_t*)c->tbounds.p, s);
@@ -668,10 +684,10 @@ void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
         fr = (int2*)c->fr0.p;
         uint4* kinds = need<uint4>(c, c->kinds, nf);
         trav_count(fr, nf, ca, tp, cnt, kinds, s);
-        scan_u32x4(cnt, off, (uint4*)(d6 + 16), nf, ws, s);
+        scan_u32x4(cnt, off, (uint4*)mapped_counts(c), nf, ws, s);
         check_launch("traverse count");
-        uint32_t* hh = (uint32_t*)host_stage(c);
-        to_host<uint32_t>(c, hh, d6 + 16, 4);
+        ck(hipStreamSynchronize(s), "sync");
+        const uint32_t* hh = c->hcount;
         int64_t add[4] = {hh[0], hh[1], hh[2], hh[3]};
         int2* lists[3];
         for (int k = 0; k < 3; k++)
@@ -952,6 +968,7 @@ void fmm_destroy(fmm_ctx c) {
     for (hipEvent_t e : {c->e_fork, c->e_join, c->e_p2p0, c->e_p2p1})
         if (e) (void)hipEventDestroy(e);
     if (c->host) (void)hipHostFree(c->host);
+    if (c->hcount) (void)hipHostFree(c->hcount);
     delete c;
 }
 

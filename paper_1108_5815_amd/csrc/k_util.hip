@@ -96,6 +96,7 @@ __global__ void k_scan_reduce(const T* __restrict__ in, int64_t n, T* __restrict
 template <class T>
 __global__ void k_scan_partials(T* part, int64_t nb, T* total) {
     __shared__ uint32_t lds[SB / 64];
+    uint32_t carries[Ops<T>::C];
     for (int c = 0; c < Ops<T>::C; c++) {
         uint32_t carry = 0;
         for (int64_t b0 = 0; b0 < nb; b0 += SB) {
@@ -110,12 +111,14 @@ __global__ void k_scan_partials(T* part, int64_t nb, T* total) {
             }
             carry += tot;
         }
-        if (threadIdx.x == 0 && total) {
-            T t = *total;
-            Ops<T>::set(t, c, carry);
-            *total = t;
-        }
+        carries[c] = carry;
         __syncthreads();
+    }
+    // one store of the totals (total may be mapped host memory)
+    if (threadIdx.x == 0 && total) {
+        T t;
+        for (int c = 0; c < Ops<T>::C; c++) Ops<T>::set(t, c, carries[c]);
+        *total = t;
     }
 }
 
