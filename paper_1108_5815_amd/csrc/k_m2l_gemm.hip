@@ -291,7 +291,7 @@ void m2l_gemm(const float* T, const int32_t* offid, const int32_t* gather, const
         case 32: launch<32, 128, 1, 4, 16>(T, offid, gather, plan, M, part, s); break;
         case 64: launch<64, 128, 2, 2, 16>(T, offid, gather, plan, M, part, s); break;
         case 96: launch<96, 128, 3, 4, 8>(T, offid, gather, plan, M, part, s); break;
-        case 128: launch<128, 64, 4, 1, 16>(T, offid, gather, plan, M, part, s); break;
+        case 128: launch<128, 64, 4, 1, 8>(T, offid, gather, plan, M, part, s); break;
         case 192: launch<192, 64, 2, 2, 8>(T, offid, gather, plan, M, part, s); break;
         case 256: launch<256, 64, 4, 1, 8>(T, offid, gather, plan, M, part, s); break;
         default: return;
