@@ -92,7 +92,7 @@ struct fmm_ctx_s {
     Buf m2pflag;         // per leaf: cell-particle sources on the leaf or an ancestor
     Buf m2lslot;         // per cell-cell pair: its GEMM slot or -1
     Buf tbounds;         // tree build: octant boundaries of the cells of a level
-    Buf has_fast, rkey, rval, rkey2, rval2, rowof, gather, general, gtg, gsr, goff, tact, tnact, m2l_part, Msplit, nbucket, kinds;
+    Buf has_fast, rkey, rval, rkey2, rval2, rowof, gather, gtg, gsr, goff, tact, tnact, m2l_part, Msplit, nbucket, kinds;
     // pairs outside the same-level tables, batched by class
     ClsPlan cp;
     Buf ckey, ckey2, cval, cval2, chead, choff, cstart, cpos, csrcs, cnt_t, ctbase, ctile, cT, cskip, cls_part;
@@ -133,7 +133,7 @@ struct fmm_ctx_s {
                       &c_nchild, &c_level, &c_prefix, &c_geo, &c_ctr, &leaves, &tmp1, &tmp2, &fr0, &fr1,
                       &cnt, &off4, &raw[0], &raw[1], &raw[2], &tgt[0], &tgt[1], &tgt[2], &src[0], &src[1],
                       &src[2], &off[0], &off[1], &off[2], &tgt2, &src2, &d_slot, &d_offid, &d_T, &has_fast,
-                      &rkey, &rval, &rkey2, &rval2, &rowof, &gather, &general, &gtg, &gsr, &goff, &d_m2m, &d_l2l, &d_w, &d_g,
+                      &rkey, &rval, &rkey2, &rval2, &rowof, &gather, &gtg, &gsr, &goff, &d_m2m, &d_l2l, &d_w, &d_g,
                       &d_h, &d_rc, &d_mlp, &M, &L, &nearb, &tune_pts, &tune_out, &d_mlp_m, &d_mlp_v,
                       &d_grad, &d_grad_rec, &d_loss_rec, &d_feat, &d_kind, &d_tgt, &d_table, &d_Thi, &d_Tlo,
                       &d_seg, &d_bt, &d_pb, &d_box, &d_frame, &inst, &bsort, &tact, &tnact,
@@ -730,13 +730,12 @@ void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
     c->ngeneral = 0;
     int64_t nm = c->nlist[0];
     const int2* pr0 = (const int2*)c->raw[0].p;  // cell-cell pairs as emitted
-    uint32_t* gen = need<uint32_t>(c, c->general, nm + 1);
+    int16_t* slot16 = need<int16_t>(c, c->m2lslot, nm + 1);  // per pair: GEMM slot, -1 outside the tables
     if (c->gemm_on) {
         upload_plan(c, p, theta);
         int R = c->plan.R, J = c->plan.J;
         uint32_t* hf = need<uint32_t>(c, c->has_fast, nc);
         ck(hipMemsetAsync(hf, 0, (size_t)nc * 4, s), "memset");
-        int16_t* slot16 = need<int16_t>(c, c->m2lslot, nm + 1);
         m2l_mark_targets(pr0, nm, ca, (int32_t*)c->d_slot.p, R, hf, slot16, s);
         uint32_t* rk = need<uint32_t>(c, c->rkey, nc);
         uint32_t* rv = need<uint32_t>(c, c->rval, nc);
@@ -771,7 +770,7 @@ void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
         const int64_t ngather = (int64_t)tiles * tc * J;
         int32_t* ga = need<int32_t>(c, c->gather, (size_t)std::max<int64_t>(ngather, 1));
         fill_i32(ga, -1, ngather, s);
-        m2l_fill_gather(pr0, (const int16_t*)c->m2lslot.p, nm, ro, J, tc, ga, gen, s);
+        m2l_fill_gather(pr0, slot16, nm, ro, J, tc, ga, s);
         check_launch("m2l gather");
         int32_t* act = need<int32_t>(c, c->tact, (size_t)std::max(tiles, 1) * J);
         int32_t* nact = need<int32_t>(c, c->tnact, (size_t)std::max(tiles, 1));
@@ -780,7 +779,7 @@ void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
         tile_slots(ga, c->gp, tc, tiles, act, nact, s);
         check_launch("m2l tile slots");
     } else if (nm > 0) {
-        fill_i32((int32_t*)gen, 1, nm, s);
+        fill_i32((int32_t*)slot16, -1, (nm + 1) / 2, s);  // two -1 slots per word
     }
     // pairs outside the GEMM tables, compacted in list order
     const int64_t nct = compact_tiles(nm);
@@ -789,7 +788,7 @@ void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
     if (nm > 0) {
         size_t wsg = scan_ws_bytes(nct);
         if (wsg > c->ws.cap) ws = need<char>(c, c->ws, wsg);
-        flag_counts(gen, nm, tcnt, s);
+        flag_counts(slot16, nm, tcnt, s);
         scan_u32(tcnt, tbase, (uint32_t*)(d6 + 12), nct, ws, s);
         uint32_t* hg = (uint32_t*)host_stage(c);
         to_host<uint32_t>(c, hg, d6 + 12, 1);
@@ -799,7 +798,7 @@ void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
         int64_t ng = c->ngeneral;
         uint32_t* gt = need<uint32_t>(c, c->gtg, ng + 1);
         uint32_t* gs = need<uint32_t>(c, c->gsr, ng + 1);
-        if (ng > 0) compact_pairs(pr0, gen, tbase, nm, gt, gs, s);
+        if (ng > 0) compact_pairs(pr0, slot16, tbase, nm, gt, gs, s);
         sort_into(nullptr, ng, c->gtg, c->gsr, c->goff);
     }
     build_classes(c, p);

@@ -142,11 +142,10 @@ struct GemmPlan;
 //   rowof     [ncell] tile * NT + column of the target's GEMM row, or -1
 //   gather    [ntiles][J][NT] source cell or -1 (per tile and slot, the
 //             tile's NT columns contiguous; padding columns stay -1)
-//   general   flag per pair (1 = not handled by the GEMM)
 void m2l_mark_targets(const int2* pairs, int64_t n, CellArrays cells, const int32_t* slot_of, int R,
                       uint32_t* has_fast, int16_t* slot, hipStream_t s);
 void m2l_fill_gather(const int2* pairs, const int16_t* slot, int64_t n, const int32_t* rowof, int32_t J, int NT,
-                     int32_t* gather, uint32_t* general, hipStream_t s);
+                     int32_t* gather, hipStream_t s);
 // row keys of the M2L GEMM: (octant class << kRowMissBits) | missing slots
 // (densest first); cells without same-level pairs get class 8
 constexpr int kRowMissBits = 10;
@@ -155,12 +154,13 @@ void row_class_keys(const uint32_t* nfast, CellArrays cells, int32_t ncell, int3
                     uint32_t* val, hipStream_t s);
 // rowof[rowcell[r]] = tile * NT + column of GEMM row r (plan's class tables set)
 void rows_inverse(const uint32_t* rowcell, int64_t nrows, GemmPlan plan, int NT, int32_t* rowof, hipStream_t s);
-// keep the pairs whose flag is set, in order: flags are counted per tile of
-// 4096 (flag_counts, compact_tiles(n) counts), tbase = exclusive scan of the
-// counts, then compact_pairs writes each tile's pairs from its base
+// keep the pairs whose slot is -1 (outside the GEMM tables), in order: they
+// are counted per tile of 4096 (flag_counts, compact_tiles(n) counts), tbase =
+// exclusive scan of the counts, then compact_pairs writes each tile's pairs
+// from its base
 int64_t compact_tiles(int64_t n);
-void flag_counts(const uint32_t* flag, int64_t n, uint32_t* cnt, hipStream_t s);
-void compact_pairs(const int2* pairs, const uint32_t* flag, const uint32_t* tbase, int64_t n, uint32_t* otgt,
+void flag_counts(const int16_t* slot, int64_t n, uint32_t* cnt, hipStream_t s);
+void compact_pairs(const int2* pairs, const int16_t* slot, const uint32_t* tbase, int64_t n, uint32_t* otgt,
                    uint32_t* osrc, hipStream_t s);
 // out9[c] = first index of the sorted class keys with key >= c, c = 0..8
 // out9[c] = first index whose key >> shift is >= c, c = 0..8

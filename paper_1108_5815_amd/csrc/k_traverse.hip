@@ -308,8 +308,7 @@ __global__ __launch_bounds__(256) void k_mark_targets(const int2* __restrict__ p
 }
 
 __global__ void k_fill_gather(const int2* __restrict__ pairs, const int16_t* __restrict__ slot, int64_t n,
-                              const int32_t* __restrict__ rowof, int32_t J, int NT, int32_t* __restrict__ gather,
-                              uint32_t* __restrict__ general) {
+                              const int32_t* __restrict__ rowof, int32_t J, int NT, int32_t* __restrict__ gather) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int32_t sl = slot[i];
@@ -318,9 +317,6 @@ __global__ void k_fill_gather(const int2* __restrict__ pairs, const int16_t* __r
         const int32_t pr_row = rowof[pr.x];  // tile * NT + column
         const int32_t tile = pr_row / NT;
         gather[((int64_t)tile * J + sl) * NT + (pr_row - tile * NT)] = pr.y;
-        general[i] = 0u;
-    } else {
-        general[i] = 1u;
     }
 }
 
@@ -438,9 +434,9 @@ void tile_slots(const int32_t* gather, GemmPlan plan, int NT, int ntiles, int32_
 }
 
 void m2l_fill_gather(const int2* pairs, const int16_t* slot, int64_t n, const int32_t* rowof, int32_t J, int NT,
-                     int32_t* gather, uint32_t* general, hipStream_t s) {
+                     int32_t* gather, hipStream_t s) {
     if (n <= 0) return;
-    k_fill_gather<<<grid(n), 256, 0, s>>>(pairs, slot, n, rowof, J, NT, gather, general);
+    k_fill_gather<<<grid(n), 256, 0, s>>>(pairs, slot, n, rowof, J, NT, gather);
 }
 
 void row_class_keys(const uint32_t* nfast, CellArrays cells, int32_t ncell, int32_t J, uint32_t* key, uint32_t* val,
@@ -509,16 +505,17 @@ namespace {
 // flags in tiles of kCompactTile = 4 waves x 16 rounds x 64 lanes, in order
 constexpr int kCompactTile = 4096;
 
-__device__ inline uint32_t wave_flag_count(const uint32_t* __restrict__ flag, int64_t n, int64_t base, int lane) {
+// a pair is kept when its slot is -1 (outside the tables)
+__device__ inline uint32_t wave_flag_count(const int16_t* __restrict__ flag, int64_t n, int64_t base, int lane) {
     uint32_t c = 0;
     for (int r = 0; r < 16; r++) {
         const int64_t g = base + r * 64 + lane;
-        c += (uint32_t)__popcll(__ballot(g < n && flag[g] != 0u));
+        c += (uint32_t)__popcll(__ballot(g < n && flag[g] < 0));
     }
     return c;
 }
 
-__global__ __launch_bounds__(256) void k_flag_counts(const uint32_t* __restrict__ flag, int64_t n,
+__global__ __launch_bounds__(256) void k_flag_counts(const int16_t* __restrict__ flag, int64_t n,
                                                      uint32_t* __restrict__ cnt) {
     __shared__ uint32_t wsum[4];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -530,7 +527,7 @@ __global__ __launch_bounds__(256) void k_flag_counts(const uint32_t* __restrict_
 
 // flagged pairs of each tile written from the tile's base, in index order
 __global__ __launch_bounds__(256) void k_compact_pairs(const int2* __restrict__ pairs,
-                                                       const uint32_t* __restrict__ flag, const uint32_t* __restrict__ tbase,
+                                                       const int16_t* __restrict__ flag, const uint32_t* __restrict__ tbase,
                                                        int64_t n, uint32_t* __restrict__ otgt,
                                                        uint32_t* __restrict__ osrc) {
     __shared__ uint32_t wsum[4];
@@ -544,7 +541,7 @@ __global__ __launch_bounds__(256) void k_compact_pairs(const int2* __restrict__ 
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     for (int r = 0; r < 16; r++) {
         const int64_t g = base + r * 64 + lane;
-        const bool f = g < n && flag[g] != 0u;
+        const bool f = g < n && flag[g] < 0;
         const uint64_t m = __ballot(f);
         if (f) {
             const uint32_t pos = off + (uint32_t)__popcll(m & lt);
@@ -560,12 +557,12 @@ __global__ __launch_bounds__(256) void k_compact_pairs(const int2* __restrict__ 
 
 int64_t compact_tiles(int64_t n) { return (n + kCompactTile - 1) / kCompactTile; }
 
-void flag_counts(const uint32_t* flag, int64_t n, uint32_t* cnt, hipStream_t s) {
+void flag_counts(const int16_t* flag, int64_t n, uint32_t* cnt, hipStream_t s) {
     if (n <= 0) return;
     k_flag_counts<<<(unsigned)compact_tiles(n), 256, 0, s>>>(flag, n, cnt);
 }
 
-void compact_pairs(const int2* pairs, const uint32_t* flag, const uint32_t* tbase, int64_t n, uint32_t* otgt,
+void compact_pairs(const int2* pairs, const int16_t* flag, const uint32_t* tbase, int64_t n, uint32_t* otgt,
                    uint32_t* osrc, hipStream_t s) {
     if (n <= 0) return;
     k_compact_pairs<<<(unsigned)compact_tiles(n), 256, 0, s>>>(pairs, flag, tbase, n, otgt, osrc);
