@@ -172,9 +172,20 @@ void scan_impl(const T* in, T* out, T* total, int64_t n, void* ws, hipStream_t s
 // ------------------------------------------------------------------ radix sort
 constexpr int RB = 256;
 constexpr int RW = RB / 64;
-constexpr int RR = 16;
-constexpr int RT = RB * RR;
+constexpr int RR = 16;       // rounds of 64 keys per wave for small and medium sorts
+constexpr int RRmax = 64;    // for large sorts
+constexpr int RT = RB * RR;  // smallest tile (sizes the workspace)
 constexpr int kMaxDigitBits = 11;
+constexpr int kRsBatch = 8;  // rounds whose keys are loaded together (divides RR)
+
+// Rounds per wave: each block writes (hist) and reads (scatter) one count per
+// digit, strided by the number of blocks, so large sorts take longer tiles to
+// keep those scattered accesses few, while keeping >= 2048 blocks.
+int rs_rounds(int64_t n) {
+    int rr = RR;
+    while (rr < RRmax && n >= (int64_t)RB * rr * 2 * 2048) rr *= 2;
+    return rr;
+}
 
 // digit of `w` bits at `shift`, counted in 2^DB buckets (w <= DB)
 template <class K>
@@ -182,17 +193,44 @@ __device__ inline uint32_t digit_of(K k, int shift, uint32_t mask) {
     return (uint32_t)(k >> shift) & mask;
 }
 
+// Adds a wave's digits to the counts h[]: the lanes hold consecutive keys
+// (valid lanes first), and keys often repeat in runs (pairs of one target
+// sit side by side), so each run of equal digits adds its length with one
+// atomic from its first lane instead of one conflicting atomic per lane.
+__device__ inline void add_digit_runs(uint32_t* h, uint32_t d, bool valid, int lane) {
+    const uint32_t prev = __shfl_up(d, 1, 64);
+    const bool head = valid && (lane == 0 || prev != d);
+    const uint64_t heads = __ballot(head);
+    const uint64_t vmask = __ballot(valid);
+    if (head) {
+        const uint64_t above = heads & ~((2ull << lane) - 1ull);
+        const int end = above ? __builtin_ctzll(above) : __popcll(vmask);
+        atomicAdd(&h[d], (uint32_t)(end - lane));
+    }
+}
+
 template <class K, int DB>
 __global__ void k_rs_hist(const K* __restrict__ keys, int64_t n, int shift, uint32_t mask,
-                          uint32_t* __restrict__ ghist, int64_t nb) {
+                          uint32_t* __restrict__ ghist, int64_t nb, int rr) {
     constexpr int ND = 1 << DB;
     __shared__ uint32_t h[ND];
     for (int d = threadIdx.x; d < ND; d += RB) h[d] = 0;
     __syncthreads();
-    int64_t base = (int64_t)blockIdx.x * RT;
-    for (int i = threadIdx.x; i < RT; i += RB) {
-        int64_t g = base + i;
-        if (g < n) atomicAdd(&h[digit_of(keys[g], shift, mask)], 1u);
+    const int tile = RB * rr;
+    int64_t base = (int64_t)blockIdx.x * tile;
+    const int lane = threadIdx.x & 63;
+    for (int i0 = threadIdx.x; i0 < tile; i0 += RB * kRsBatch) {
+        K kb[kRsBatch];
+#pragma unroll
+        for (int j = 0; j < kRsBatch; j++) {
+            const int64_t g = base + i0 + j * RB;
+            kb[j] = g < n ? keys[g] : K(0);
+        }
+#pragma unroll
+        for (int j = 0; j < kRsBatch; j++) {
+            const bool valid = base + i0 + j * RB < n;
+            add_digit_runs(h, valid ? digit_of(kb[j], shift, mask) : 0u, valid, lane);
+        }
     }
     __syncthreads();
     for (int d = threadIdx.x; d < ND; d += RB) ghist[(int64_t)d * nb + blockIdx.x] = h[d];
@@ -201,16 +239,25 @@ __global__ void k_rs_hist(const K* __restrict__ keys, int64_t n, int shift, uint
 template <class K, int DB>
 __global__ void k_rs_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
                              K* __restrict__ kout, uint32_t* __restrict__ vout, int64_t n,
-                             int shift, uint32_t mask, const uint32_t* __restrict__ goff, int64_t nb) {
+                             int shift, uint32_t mask, const uint32_t* __restrict__ goff, int64_t nb, int rr) {
     constexpr int ND = 1 << DB;
     __shared__ uint32_t wc[RW][ND];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int i = threadIdx.x; i < RW * ND; i += RB) (&wc[0][0])[i] = 0;
     __syncthreads();
-    const int64_t wbase = (int64_t)blockIdx.x * RT + (int64_t)w * (RR * 64);
-    for (int r = 0; r < RR; r++) {
-        int64_t g = wbase + r * 64 + lane;
-        if (g < n) atomicAdd(&wc[w][digit_of(kin[g], shift, mask)], 1u);
+    const int64_t wbase = (int64_t)blockIdx.x * (RB * rr) + (int64_t)w * (rr * 64);
+    for (int r0 = 0; r0 < rr; r0 += kRsBatch) {
+        K kb[kRsBatch];
+#pragma unroll
+        for (int j = 0; j < kRsBatch; j++) {
+            const int64_t g = wbase + (r0 + j) * 64 + lane;
+            kb[j] = g < n ? kin[g] : K(0);
+        }
+#pragma unroll
+        for (int j = 0; j < kRsBatch; j++) {
+            const bool valid = wbase + (r0 + j) * 64 + lane < n;
+            add_digit_runs(wc[w], valid ? digit_of(kb[j], shift, mask) : 0u, valid, lane);
+        }
     }
     __syncthreads();
     for (int d = threadIdx.x; d < ND; d += RB) {
@@ -223,43 +270,49 @@ __global__ void k_rs_scatter(const K* __restrict__ kin, const uint32_t* __restri
     }
     __syncthreads();
     const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-    for (int r = 0; r < RR; r++) {
-        int64_t g = wbase + r * 64 + lane;
-        bool valid = g < n;
-        K k = 0;
-        uint32_t v = 0, d = 0;
-        if (valid) {
-            k = kin[g];
-            v = vin[g];
-            d = digit_of(k, shift, mask);
-        }
-        uint64_t same = __ballot(valid);
+    for (int r0 = 0; r0 < rr; r0 += kRsBatch) {
+        K kb[kRsBatch];
+        uint32_t vb[kRsBatch];
 #pragma unroll
-        for (int b = 0; b < DB; b++) {
-            bool bit = (d >> b) & 1u;
-            uint64_t bb = __ballot(valid && bit);
-            same &= bit ? bb : ~bb;
+        for (int j = 0; j < kRsBatch; j++) {
+            const int64_t g = wbase + (r0 + j) * 64 + lane;
+            kb[j] = g < n ? kin[g] : K(0);
+            vb[j] = g < n ? vin[g] : 0u;
         }
-        uint32_t rank = (uint32_t)__popcll(same & lt);
-        uint32_t basev = valid ? wc[w][d] : 0u;
-        if (valid) {
-            kout[basev + rank] = k;
-            vout[basev + rank] = v;
+#pragma unroll
+        for (int j = 0; j < kRsBatch; j++) {
+            const bool valid = wbase + (r0 + j) * 64 + lane < n;
+            const K k = kb[j];
+            const uint32_t v = vb[j];
+            const uint32_t d = valid ? digit_of(k, shift, mask) : 0u;
+            uint64_t same = __ballot(valid);
+#pragma unroll
+            for (int b = 0; b < DB; b++) {
+                bool bit = (d >> b) & 1u;
+                uint64_t bb = __ballot(valid && bit);
+                same &= bit ? bb : ~bb;
+            }
+            uint32_t rank = (uint32_t)__popcll(same & lt);
+            uint32_t basev = valid ? wc[w][d] : 0u;
+            if (valid) {
+                kout[basev + rank] = k;
+                vout[basev + rank] = v;
+            }
+            bool leader = valid && ((same >> lane) == 1ull);
+            if (leader) wc[w][d] = basev + (uint32_t)__popcll(same);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
         }
-        bool leader = valid && ((same >> lane) == 1ull);
-        if (leader) wc[w][d] = basev + (uint32_t)__popcll(same);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
     }
 }
 
 template <class K, int DB>
-void rs_pass(const K* ki, const uint32_t* vi, K* ko, uint32_t* vo, int64_t n, int sh, int w, int64_t nb,
+void rs_pass(const K* ki, const uint32_t* vi, K* ko, uint32_t* vo, int64_t n, int sh, int w, int64_t nb, int rr,
              uint32_t* ghist, uint32_t* goff, void* sws, hipStream_t s) {
     const uint32_t mask = (1u << w) - 1u;
-    k_rs_hist<K, DB><<<(unsigned)nb, RB, 0, s>>>(ki, n, sh, mask, ghist, nb);
+    k_rs_hist<K, DB><<<(unsigned)nb, RB, 0, s>>>(ki, n, sh, mask, ghist, nb, rr);
     scan_impl<uint32_t>(ghist, goff, nullptr, (int64_t)(1 << DB) * nb, sws, s);
-    k_rs_scatter<K, DB><<<(unsigned)nb, RB, 0, s>>>(ki, vi, ko, vo, n, sh, mask, goff, nb);
+    k_rs_scatter<K, DB><<<(unsigned)nb, RB, 0, s>>>(ki, vi, ko, vo, n, sh, mask, goff, nb, rr);
 }
 
 // LSD passes of at most kMaxDigitBits bits, the bits spread evenly over them
@@ -267,7 +320,8 @@ template <class K>
 void sort_impl(K* ka, uint32_t* va, K* kb, uint32_t* vb, int64_t n, int bit0, int bit1, void* ws,
                hipStream_t s) {
     if (n <= 1 || bit1 <= bit0) return;
-    int64_t nb = (n + RT - 1) / RT;
+    const int rr = rs_rounds(n);
+    const int64_t nb = (n + (int64_t)RB * rr - 1) / ((int64_t)RB * rr);
     uint32_t* ghist = (uint32_t*)ws;
     uint32_t* goff = ghist + ((size_t)1 << kMaxDigitBits) * nb;
     void* sws = goff + ((size_t)1 << kMaxDigitBits) * nb;
@@ -279,12 +333,12 @@ void sort_impl(K* ka, uint32_t* va, K* kb, uint32_t* vb, int64_t n, int bit0, in
     for (int ps = 0; ps < passes; ps++) {
         const int w = (bit1 - sh + (passes - ps) - 1) / (passes - ps);  // ceil(remaining / passes left)
         switch (w <= 6 ? 6 : w) {
-            case 6: rs_pass<K, 6>(ki, vi, ko, vo, n, sh, w, nb, ghist, goff, sws, s); break;
-            case 7: rs_pass<K, 7>(ki, vi, ko, vo, n, sh, w, nb, ghist, goff, sws, s); break;
-            case 8: rs_pass<K, 8>(ki, vi, ko, vo, n, sh, w, nb, ghist, goff, sws, s); break;
-            case 9: rs_pass<K, 9>(ki, vi, ko, vo, n, sh, w, nb, ghist, goff, sws, s); break;
-            case 10: rs_pass<K, 10>(ki, vi, ko, vo, n, sh, w, nb, ghist, goff, sws, s); break;
-            default: rs_pass<K, 11>(ki, vi, ko, vo, n, sh, w, nb, ghist, goff, sws, s); break;
+            case 6: rs_pass<K, 6>(ki, vi, ko, vo, n, sh, w, nb, rr, ghist, goff, sws, s); break;
+            case 7: rs_pass<K, 7>(ki, vi, ko, vo, n, sh, w, nb, rr, ghist, goff, sws, s); break;
+            case 8: rs_pass<K, 8>(ki, vi, ko, vo, n, sh, w, nb, rr, ghist, goff, sws, s); break;
+            case 9: rs_pass<K, 9>(ki, vi, ko, vo, n, sh, w, nb, rr, ghist, goff, sws, s); break;
+            case 10: rs_pass<K, 10>(ki, vi, ko, vo, n, sh, w, nb, rr, ghist, goff, sws, s); break;
+            default: rs_pass<K, 11>(ki, vi, ko, vo, n, sh, w, nb, rr, ghist, goff, sws, s); break;
         }
         sh += w;
         K* tk = ki; ki = ko; ko = tk;

@@ -261,3 +261,28 @@ def test_schedules_are_identical():
         out.append((phi.cpu().numpy(), E.cpu().numpy()))
     for k in (1, 2):
         assert np.array_equal(out[0][0], out[k][0]) and np.array_equal(out[0][1], out[k][1])
+
+
+def test_large_sort_stable_permutation():
+    """34,000,001 points (the radix sort's longest tiles, a ragged last tile) with
+    a block of 40,000 coincident points spanning several tiles: the sorted keys
+    are the oracle's keys of the permuted points, non-decreasing, the
+    permutation is one, and equal keys keep their input order."""
+    n = 34_000_001
+    x, y, z = synth.uniform_cube(n, 31)
+    x[100_000:140_000] = x[7]; y[100_000:140_000] = y[7]; z[100_000:140_000] = z[7]
+    q = np.ones(n)
+    xs, ys, zs = (as_input(a, torch.float32) for a in (x, y, z))
+    f = _fmm()
+    f.build_tree(*(torch.tensor(a, dtype=torch.float32, device="cuda:0") for a in (x, y, z, q)), 64)
+    torch.cuda.synchronize()
+    lo, side = ora.bbox(xs, ys, zs)
+    ko = ora.morton(xs, ys, zs, lo, side)
+    del xs, ys, zs
+    kg, pg = f.keys()
+    assert np.array_equal(np.bincount(pg, minlength=n), np.ones(n, dtype=np.int64))
+    assert np.array_equal(kg, ko[pg])
+    assert np.all(kg[1:] >= kg[:-1])
+    tie = kg[1:] == kg[:-1]
+    assert tie.sum() >= 39_999
+    assert np.all(pg[1:][tie] > pg[:-1][tie])
