@@ -257,7 +257,8 @@ int gemm_slot_groups(int J);
 // a group holds at most J / G + 1 slots (65 with G = 8 ceil(J / 512)); the GEMM
 // kernels stage a group's slots and operator ids in LDS arrays of this size
 constexpr int kGemmMaxGroupSlots = 80;
-// act[tile * J + k], k < nact[tile]: the slots of tile `tile` that some row uses
+// act[tile * J + k], k < nact[tile]: the slots of tile `tile` that some row
+// uses; NT (the tile width from gemm_tile_cols) is 64 or 128
 void tile_slots(const int32_t* gather, GemmPlan plan, int NT, int ntiles, int32_t* act, int32_t* nact,
                 hipStream_t s);
 // part: G * nrows * KP floats of per-group partial locals, summed into L in group order

@@ -365,15 +365,22 @@ __global__ __launch_bounds__(256) void k_tile_slots(const int32_t* __restrict__ 
     const int32_t* gt = gather + (size_t)tile * J * NT;  // [slot][NT] of this tile
     int base = 0;
     for (int j0 = 0; j0 < J; j0 += 256) {
-        // slot j is used if any of the tile's NT entries is a source (padding is -1):
-        // each wave tests whole slots with coalesced reads
-        for (int jj = w; jj < 256; jj += 4) {
-            const int j = j0 + jj;
-            bool a = false;
-            if (j < J)
-                for (int r = lane; r < NT; r += 64) a = a || gt[(size_t)j * NT + r] >= 0;
-            const uint64_t m = __ballot(a);
-            if (lane == 0) used[jj] = m != 0ull;
+        // slot j is used if any of the tile's NT (64 or 128) entries is a
+        // source (padding is -1): each wave tests whole slots with coalesced
+        // reads, eight slots' reads in flight at once
+        for (int jb = w; jb < 256; jb += 32) {
+            int32_t v[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                const int j = j0 + jb + 4 * u;
+                const int32_t* row = gt + (size_t)j * NT;
+                v[u] = j < J ? (NT > 64 ? max(row[lane], row[64 + lane]) : row[lane]) : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                const uint64_t m = __ballot(v[u] >= 0);
+                if (lane == 0) used[jb + 4 * u] = m != 0ull;
+            }
         }
         __syncthreads();
         const bool a = used[threadIdx.x] != 0;
