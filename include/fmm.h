@@ -61,11 +61,16 @@ typedef enum {
 
 typedef enum {
     FMM_PREC_FP32 = 0,       /* FP32 kernels, FP64 per-target final sum */
-    FMM_PREC_SPLIT_BF16 = 1, /* as FP32, but same-level M2L as three BF16 products per
+    FMM_PREC_SPLIT_BF16 = 1  /* as FP32, but same-level M2L as three BF16 products per
                                 FP32 product (hi*hi + hi*lo + lo*hi) on the matrix cores
                                 with FP32 accumulation; p <= 12 */
-    FMM_PREC_FP64 = 2        /* reserved: not implemented (FMM_ERR_UNSUPPORTED) */
 } fmm_precision;
+/* There is no FP64 evaluation form: FP64 inputs and outputs are accepted
+ * (FMM_F64), the quantisation and the per-target final sum are FP64, and the
+ * expansion and particle-particle arithmetic is FP32.  Its rounding (about
+ * 1e-7 relative) bounds the attainable accuracy: orders whose truncation
+ * error lies below that gain nothing.  Any other precision value gives
+ * FMM_ERR_INVALID_ARG. */
 
 typedef enum { FMM_F32 = 0, FMM_F64 = 1 } fmm_dtype;
 
@@ -86,6 +91,22 @@ const char *fmm_last_error(fmm_ctx ctx);
 
 /* Re-bind the context to another stream of the same device. */
 fmm_status fmm_set_stream(fmm_ctx ctx, void *hip_stream);
+
+/*
+ * Device-memory hook for the context's internal buffers (tree, lists,
+ * expansions, tables, work space).  alloc(bytes, user) returns device memory
+ * of the context's device aligned to at least 256 bytes, or NULL on failure;
+ * free_fn(ptr, user) releases it.  The context calls both from the thread
+ * that makes the fmm_* call, and synchronises its stream before freeing.
+ * Passing alloc = free_fn = NULL restores hipMalloc / hipFree.  Buffers
+ * already held keep the routine that allocated them and are released by it.
+ * A NULL return turns the call that needed the memory into
+ * FMM_ERR_OUT_OF_MEMORY; the context stays valid and a later call may retry.
+ * Setting only one of the two routines gives FMM_ERR_INVALID_ARG.
+ */
+typedef void *(*fmm_alloc_fn)(size_t bytes, void *user);
+typedef void (*fmm_free_fn)(void *ptr, void *user);
+fmm_status fmm_set_allocator(fmm_ctx ctx, fmm_alloc_fn alloc, fmm_free_fn free_fn, void *user);
 
 /*
  * Tree build (paper: "Hierarchical N-body algorithms", clustering into a
@@ -122,9 +143,12 @@ fmm_status fmm_build_tree(fmm_ctx ctx, int64_t n, int dtype, const void *x, cons
 fmm_status fmm_traverse(fmm_ctx ctx, int32_t p, double theta, int32_t policy);
 
 /*
- * Evaluation: P2M at leaves, M2M upward, M2L / M2P / P2P over the lists,
- * L2L downward, L2P at leaves, and the per-target sum, written in the
- * caller's original particle order.
+ * Evaluation (paper: "Hierarchical N-body algorithms" for the upward and
+ * downward passes of the FMM and the treecode; "Hybrid treecode/FMM
+ * algorithm" and "Results" for the cell-cell, cell-particle and
+ * particle-particle interactions of the lists): P2M at leaves, M2M upward,
+ * M2L / M2P / P2P over the lists, L2L downward, L2P at leaves, and the
+ * per-target sum, written in the caller's original particle order.
  *   precision  an fmm_precision
  *   out_dtype  element type of the outputs (FMM_F32 or FMM_F64)
  *   phi, ex, ey, ez  device arrays of n values (caller-owned); E = -grad phi
@@ -222,6 +246,25 @@ fmm_status fmm_costmodel_set_weights(fmm_ctx ctx, const float *weights);
 fmm_status fmm_costmodel_loss_grad(fmm_ctx ctx, const float *weights, int32_t n_rec, const float *features,
                                    const int32_t *kinds, const float *targets, float *loss, float *grad);
 
+/*
+ * Persist the cost model: a versioned text file holding the weights (exact,
+ * as hexadecimal floats), the order, theta and precision it was trained for
+ * (-1 where unknown, e.g. after fmm_costmodel_set_weights), the name of the
+ * device whose kernel timings trained it, the final training loss, the
+ * timed unit costs (if set) and the tile shapes and schedule in use.  This
+ * keeps the learned choices of a device fixed across processes, where
+ * retraining on fresh timings would give slightly different choices.
+ * save: FMM_ERR_STATE without a model, FMM_ERR_DEVICE if the file cannot be
+ * written.  load(path, p, precision): the file must come from a device of
+ * the same name and, unless the argument is -1, have been trained for that
+ * order and precision; otherwise FMM_ERR_INVALID_ARG (also for a missing,
+ * unreadable or malformed file, or another format version) and the context
+ * keeps its model.  On success the weights, unit costs (when the file has
+ * them), tile shapes and schedule replace the context's.
+ */
+fmm_status fmm_costmodel_save(fmm_ctx ctx, const char *path);
+fmm_status fmm_costmodel_load(fmm_ctx ctx, const char *path, int32_t p, int32_t precision);
+
 /* The choice table the traversal reads for (p, theta): 9 x 81 x 81 x 4
  * entries (level difference + 4, quarter-octave bucket of n_t, of n_s,
  * distance-ratio bin), each 0 M2L, 1 M2P or 2 P2P; host array. */
@@ -238,6 +281,16 @@ fmm_status fmm_get_sizes(fmm_ctx ctx, int64_t *n_cells, int64_t *n_m2l, int64_t 
  * batched same-level GEMM (matrix cores) and those converted one by one
  * (mixed levels or offsets outside the per-octant tables).  NULL allowed. */
 fmm_status fmm_get_m2l_split(fmm_ctx ctx, int64_t *n_batched, int64_t *n_general);
+
+/*
+ * Same-level M2L batching for (p, theta), needing no context or device: the
+ * number of accepted same-level offsets per octant class (*slots: the slot
+ * count of each target's GEMM row, 189 at theta = 0.5, 567 at 0.4; it grows
+ * as theta^-3) and whether the batched matrix-core GEMM is used (*batched:
+ * 1 if p has a matrix-core tiling and *slots <= 4096, else 0; all cell-cell
+ * pairs then go through the class-batched path).  Either pointer may be NULL.
+ */
+fmm_status fmm_m2l_slots(int32_t p, double theta, int32_t *slots, int32_t *batched);
 
 /* Shape of the batched same-level M2L after the last traversal: the number
  * of GEMM tiles (targets of one octant class, 64 or 128 per tile), tiles x

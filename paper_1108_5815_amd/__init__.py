@@ -6,4 +6,4 @@ pointers and sizes.  PyTorch supplies device memory and the stream.
 """
 from .binding import (FMM, FMMError, LIST_M2L, LIST_M2P, LIST_P2P, POLICY_FMM,  # noqa: F401
                       POLICY_HYBRID_MLP, POLICY_HYBRID_TIMED, POLICY_TREECODE, PREC_FP32,
-                      PREC_FP64, PREC_SPLIT_BF16, lib, library_path)
+                      PREC_SPLIT_BF16, lib, library_path, m2l_slots)

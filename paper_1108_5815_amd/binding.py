@@ -14,7 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libfmm.so")
 
 POLICY_FMM, POLICY_TREECODE, POLICY_HYBRID_TIMED, POLICY_HYBRID_MLP = 0, 1, 2, 3
-PREC_FP32, PREC_SPLIT_BF16, PREC_FP64 = 0, 1, 2
+PREC_FP32, PREC_SPLIT_BF16 = 0, 1
 F32, F64 = 0, 1
 LIST_M2L, LIST_M2P, LIST_P2P = 0, 1, 2
 MLP_PARAMS = 4803
@@ -81,6 +81,10 @@ def lib():
         "fmm_autotune": ([vp, i32, i32], ctypes.c_int),
         "fmm_get_tile_config": ([vp, vp, vp], ctypes.c_int),
         "fmm_set_tile_config": ([vp, vp], ctypes.c_int),
+        "fmm_set_allocator": ([vp, vp, vp, vp], ctypes.c_int),
+        "fmm_costmodel_save": ([vp, ctypes.c_char_p], ctypes.c_int),
+        "fmm_costmodel_load": ([vp, ctypes.c_char_p, i32, i32], ctypes.c_int),
+        "fmm_m2l_slots": ([i32, dbl, vp, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -92,6 +96,19 @@ def lib():
 
 def _ptr(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+def m2l_slots(p: int, theta: float):
+    """(slots per octant class, 1 if the batched same-level GEMM is used) for (p, theta); no device needed."""
+    j, b = ctypes.c_int32(), ctypes.c_int32()
+    st = lib().fmm_m2l_slots(int(p), float(theta), ctypes.byref(j), ctypes.byref(b))
+    if st != 0:
+        raise FMMError(st, "fmm_m2l_slots failed")
+    return j.value, b.value
 
 
 class FMM:
@@ -115,6 +132,31 @@ class FMM:
         if getattr(self, "h", None):
             lib().fmm_destroy(self.h)
             self.h = None
+        self._hooks = None
+
+    def set_allocator(self, alloc=None, free=None):
+        """Route the context's device buffers through alloc(nbytes) -> int
+        pointer (0 on failure) and free(ptr); None for both restores hipMalloc."""
+        if alloc is None and free is None:
+            self._ck(lib().fmm_set_allocator(self.h, None, None, None))
+            return
+        a = ALLOC_FN(lambda nbytes, user: int(alloc(int(nbytes))) or None)
+        f = FREE_FN(lambda ptr, user: free(int(ptr)))
+        self._ck(lib().fmm_set_allocator(self.h, ctypes.cast(a, ctypes.c_void_p), ctypes.cast(f, ctypes.c_void_p),
+                                         None))
+        # the library keeps the raw function pointers: hold the trampolines
+        # (and any earlier ones, whose buffers are still released through them)
+        if getattr(self, "_hooks", None) is None:
+            self._hooks = []
+        self._hooks.append((a, f))
+
+    def use_torch_allocator(self):
+        """Allocate the context's device buffers from torch's caching allocator
+        on the context's device and the current stream."""
+        t = self._torch
+        dev = self.device
+        self.set_allocator(lambda n: t.cuda.caching_allocator_alloc(n, dev),
+                           lambda ptr: t.cuda.caching_allocator_delete(ptr))
 
     def __del__(self):
         try:
@@ -265,6 +307,13 @@ class FMM:
         self._ck(lib().fmm_costmodel_loss_grad(self.h, _ptr(w), k.size, _ptr(f), _ptr(k), _ptr(t), _ptr(loss),
                                                _ptr(g)))
         return float(loss[0]), g
+
+    def costmodel_save(self, path: str):
+        self._ck(lib().fmm_costmodel_save(self.h, os.fsencode(path)))
+
+    def costmodel_load(self, path: str, p: int = -1, precision: int = -1):
+        """Load a saved model; p / precision = -1 accept any order / precision."""
+        self._ck(lib().fmm_costmodel_load(self.h, os.fsencode(path), int(p), int(precision)))
 
     def costmodel_table(self, p: int, theta: float):
         tab = np.zeros(MLP_TABLE, np.uint8)

@@ -30,6 +30,8 @@ namespace {
 struct Buf {
     void* p = nullptr;
     size_t cap = 0;
+    fmm_free_fn release = nullptr;  // the routine of the allocator that gave p (null: hipFree)
+    void* user = nullptr;
 };
 
 enum { PH_KEYS, PH_SORT, PH_TREE, PH_TRAV, PH_LISTS, PH_UP, PH_M2L, PH_M2LG, PH_DOWN, PH_P2P, PH_FAR, PH_N };
@@ -41,6 +43,10 @@ struct fmm_ctx_s {
     hipStream_t stream = nullptr;
     std::string err;
     std::vector<Buf*> bufs;
+    // caller's device-memory hook (null: hipMalloc / hipFree)
+    fmm_alloc_fn ualloc = nullptr;
+    fmm_free_fn ufree = nullptr;
+    void* uuser = nullptr;
 
     // timing
     bool timing = false;
@@ -110,6 +116,9 @@ struct fmm_ctx_s {
     // learned cost model: weights, Adam moments, training records, choice table
     Buf d_mlp, d_mlp_m, d_mlp_v, d_grad, d_grad_rec, d_loss_rec, d_feat, d_kind, d_tgt, d_table;
     bool mlp_ready = false;
+    // what the model was trained for (-1 / NaN where unknown)
+    int cm_p = -1, cm_precision = -1, cm_records = 0;
+    double cm_theta = -1, cm_loss = NAN, cm_seconds = NAN;
     int mlp_version = 0, table_version = -1, table_p = -1;
     double table_theta = -1;
     std::vector<float> rec_feat, rec_tgt;
@@ -158,6 +167,39 @@ void ck(hipError_t e, const char* what) {
 
 void check_launch(const char* what) { ck(hipGetLastError(), what); }
 
+// device memory through the caller's hook, or hipMalloc
+void dev_alloc(fmm_ctx c, Buf& b, size_t nb) {
+    void* np = nullptr;
+    if (c->ualloc) {
+        np = c->ualloc(nb, c->uuser);
+        if (!np) fail(FMM_ERR_OUT_OF_MEMORY, "the allocator hook returned no memory for " + std::to_string(nb) + " bytes");
+        b.release = c->ufree;
+        b.user = c->uuser;
+    } else {
+        hipError_t e = hipMalloc(&np, nb);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            fail(FMM_ERR_OUT_OF_MEMORY, "device allocation of " + std::to_string(nb) + " bytes failed");
+        }
+        b.release = nullptr;
+        b.user = nullptr;
+    }
+    b.p = np;
+    b.cap = nb;
+}
+
+// release a buffer with the routine that allocated it (the stream must have passed every use)
+void dev_release(Buf& b) {
+    if (b.p) {
+        if (b.release) b.release(b.p, b.user);
+        else (void)hipFree(b.p);
+    }
+    b.p = nullptr;
+    b.cap = 0;
+    b.release = nullptr;
+    b.user = nullptr;
+}
+
 // grow-only device buffer; contents are not preserved
 template <class T>
 T* need(fmm_ctx c, Buf& b, size_t count) {
@@ -165,18 +207,9 @@ T* need(fmm_ctx c, Buf& b, size_t count) {
     if (b.cap >= bytes) return (T*)b.p;
     if (b.p) {
         ck(hipStreamSynchronize(c->stream), "sync");
-        ck(hipFree(b.p), "hipFree");
+        dev_release(b);
     }
-    b.p = nullptr;
-    b.cap = 0;
-    size_t nb = bytes + bytes / 4;
-    hipError_t e = hipMalloc(&b.p, nb);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        b.p = nullptr;
-        fail(FMM_ERR_OUT_OF_MEMORY, "device allocation of " + std::to_string(nb) + " bytes failed");
-    }
-    b.cap = nb;
+    dev_alloc(c, b, bytes + bytes / 4);
     return (T*)b.p;
 }
 
@@ -185,20 +218,15 @@ template <class T>
 T* need_keep(fmm_ctx c, Buf& b, size_t count, size_t keep_count) {
     size_t bytes = std::max<size_t>(count * sizeof(T), 256);
     if (b.cap >= bytes) return (T*)b.p;
-    size_t nb = bytes + bytes / 2;
-    void* np = nullptr;
-    hipError_t e = hipMalloc(&np, nb);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        fail(FMM_ERR_OUT_OF_MEMORY, "device allocation of " + std::to_string(nb) + " bytes failed");
-    }
-    if (b.p && keep_count) ck(hipMemcpyAsync(np, b.p, keep_count * sizeof(T), hipMemcpyDeviceToDevice, c->stream), "copy");
+    Buf nbuf;
+    dev_alloc(c, nbuf, bytes + bytes / 2);
+    if (b.p && keep_count)
+        ck(hipMemcpyAsync(nbuf.p, b.p, keep_count * sizeof(T), hipMemcpyDeviceToDevice, c->stream), "copy");
     if (b.p) {
         ck(hipStreamSynchronize(c->stream), "sync");
-        ck(hipFree(b.p), "hipFree");
+        dev_release(b);
     }
-    b.p = np;
-    b.cap = nb;
+    b = nbuf;
     return (T*)b.p;
 }
 
@@ -594,7 +622,7 @@ void build_classes(fmm_ctx c, int p) {
     int32_t* tile_cls = need<int32_t>(c, c->ctile, std::max<size_t>(ntiles, 1));
     cls_tiles(nt, tb, (int32_t)ncls, tile_cls, s);
     float* T = need<float>(c, c->cT, (size_t)ncls * KP * KP);
-    ck(hipMemsetAsync(T, 0, (size_t)ncls * KP * KP * sizeof(float), s), "memset");
+    fill_zero(T, (size_t)ncls * KP * KP * sizeof(float), s);
     cls_ops(keys, start, (int32_t)ncls, p, KP, (const float*)c->d_w.p, T, s);
     if (nb < ng) cls_skip(pos, ng, nb, need<uint8_t>(c, c->cskip, ng), s);
     check_launch("m2l classes: operators");
@@ -724,7 +752,9 @@ void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
     // cell-cell list: kept in emission order; same-level pairs go to the GEMM
     // gather table, the rest are compacted and grouped by target
     c->m2l_sorted = false;
-    c->gemm_on = m2l_gemm_supported(p) && c->nlist[0] > 0;
+    // the per-pair slot is stored in 16 bits and the gather table grows with
+    // the slot count: small theta sends every cell-cell pair to the class path
+    c->gemm_on = m2l_gemm_supported(p) && c->nlist[0] > 0 && m2l_plan_slots(theta) <= kGemmMaxSlots;
     c->ntiles = 0;
     c->nrows = 0;
     c->ngeneral = 0;
@@ -733,9 +763,10 @@ void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
     int16_t* slot16 = need<int16_t>(c, c->m2lslot, nm + 1);  // per pair: GEMM slot, -1 outside the tables
     if (c->gemm_on) {
         upload_plan(c, p, theta);
+        if (m2l_bf16_supported(p)) upload_plan_bf16(c);
         int R = c->plan.R, J = c->plan.J;
         uint32_t* hf = need<uint32_t>(c, c->has_fast, nc);
-        ck(hipMemsetAsync(hf, 0, (size_t)nc * 4, s), "memset");
+        fill_zero(hf, (size_t)nc * 4, s);
         m2l_mark_targets(pr0, nm, ca, (int32_t*)c->d_slot.p, R, hf, slot16, s);
         uint32_t* rk = need<uint32_t>(c, c->rkey, nc);
         uint32_t* rv = need<uint32_t>(c, c->rval, nc);
@@ -820,8 +851,8 @@ void run_p2p(fmm_ctx c, double4* near, hipStream_t st) {
 // ------------------------------------------------------------------ evaluate
 void evaluate_impl(fmm_ctx c, int32_t precision, int32_t out_dtype, void* phi, void* ex, void* ey, void* ez) {
     if (!c->traversed) fail(FMM_ERR_STATE, "fmm_evaluate before fmm_traverse");
-    if (precision < 0 || precision > 2) fail(FMM_ERR_INVALID_ARG, "unknown precision");
-    if (precision == FMM_PREC_FP64) fail(FMM_ERR_UNSUPPORTED, "FMM_PREC_FP64 is not implemented");
+    if (precision != FMM_PREC_FP32 && precision != FMM_PREC_SPLIT_BF16)
+        fail(FMM_ERR_INVALID_ARG, "precision must be FMM_PREC_FP32 or FMM_PREC_SPLIT_BF16");
     if (precision == FMM_PREC_SPLIT_BF16 && !m2l_bf16_supported(c->p))
         fail(FMM_ERR_UNSUPPORTED, "split-BF16 M2L is implemented for p <= 12");
     if (out_dtype != FMM_F32 && out_dtype != FMM_F64) fail(FMM_ERR_INVALID_ARG, "out_dtype must be F32 or F64");
@@ -829,13 +860,12 @@ void evaluate_impl(fmm_ctx c, int32_t precision, int32_t out_dtype, void* phi, v
     if (c->n == 0) return;
     hipStream_t s = c->stream;
     int p = c->p, KP = kpad(p);
-    if (precision == FMM_PREC_SPLIT_BF16 && c->gemm_on) upload_plan_bf16(c);
     int32_t nc = c->ncell;
     CellArrays ca = cells_of(c);
     Tables tb = tables_of(c);
     // one extra, all-zero multipole row (index nc): the M2L GEMM reads it for absent sources
     float* M = need<float>(c, c->M, (size_t)(nc + 1) * KP);
-    ck(hipMemsetAsync(M + (size_t)nc * KP, 0, (size_t)KP * sizeof(float), s), "memset");
+    fill_zero(M + (size_t)nc * KP, (size_t)KP * sizeof(float), s);
     c->gp.zcell = nc;
     float* L = need<float>(c, c->L, (size_t)nc * KP);
     double4* nr = need<double4>(c, c->nearb, c->n);
@@ -867,7 +897,7 @@ void evaluate_impl(fmm_ctx c, int32_t precision, int32_t out_dtype, void* phi, v
         m2m(ca, inr, lpos, c->lvl[Lv], c->lvl[Lv + 1], c->ncell, c->nleaf, p, KP, tb, M, s);
     check_launch("upward");
     if (sched == 2) fork_p2p();
-    ck(hipMemsetAsync(L, 0, (size_t)nc * KP * sizeof(float), s), "memset");
+    fill_zero(L, (size_t)nc * KP * sizeof(float), s);
     mark(c, PH_M2L);
     if (c->gemm_on && c->ntiles > 0)
     {
@@ -956,8 +986,7 @@ void fmm_destroy(fmm_ctx c) {
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
-    for (Buf* b : c->bufs)
-        if (b->p) (void)hipFree(b->p);
+    for (Buf* b : c->bufs) dev_release(*b);
     for (int k = 0; k <= PH_N; k++)
         if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
     if (c->s2) {
@@ -1082,6 +1111,9 @@ fmm_status fmm_tune(fmm_ctx c, int32_t p, int32_t precision) {
             fmm_ctx t;
             ~Del() { fmm_destroy(t); }
         } del{t};
+        t->ualloc = c->ualloc;
+        t->ufree = c->ufree;
+        t->uuser = c->uuser;
         t->timing = true;
         t->schedule = 0;  // each kernel timed alone
         double tm[2][PH_N] = {};
@@ -1153,6 +1185,9 @@ static void gen_records(fmm_ctx c, int p, double theta, int precision, uint64_t 
         fmm_ctx t;
         ~Del() { fmm_destroy(t); }
     } del{t};
+    t->ualloc = c->ualloc;
+    t->ufree = c->ufree;
+    t->uuser = c->uuser;
     t->timing = true;
     t->schedule = 0;  // each kernel timed alone
     // measured log2 ns per cell pair, per leaf size: same-level M2L, mixed-level
@@ -1268,8 +1303,8 @@ static double mlp_fit(fmm_ctx c, int B, const float* feat, const int32_t* kind, 
     int32_t* dk = need<int32_t>(c, c->d_kind, B);
     float* dt = need<float>(c, c->d_tgt, B);
     to_dev(c, dw, w.data(), kMlpParams);
-    ck(hipMemsetAsync(dm, 0, kMlpParams * 4, c->stream), "memset");
-    ck(hipMemsetAsync(dv, 0, kMlpParams * 4, c->stream), "memset");
+    fill_zero(dm, kMlpParams * 4, c->stream);
+    fill_zero(dv, kMlpParams * 4, c->stream);
     to_dev(c, df, feat, (size_t)B * 6);
     to_dev(c, dk, kind, B);
     to_dev(c, dt, tgt, B);
@@ -1296,9 +1331,16 @@ fmm_status fmm_costmodel_train(fmm_ctx c, int32_t p, double theta, int32_t preci
             fail(FMM_ERR_UNSUPPORTED, "training is implemented for FP32 and split-BF16");
         if (precision == FMM_PREC_SPLIT_BF16 && !m2l_bf16_supported(p))
             fail(FMM_ERR_UNSUPPORTED, "split-BF16 M2L is implemented for p <= 12");
+        auto t0 = std::chrono::steady_clock::now();
         gen_records(c, p, theta, precision, seed);
         double l = mlp_fit(c, (int)c->rec_kind.size(), c->rec_feat.data(), c->rec_kind.data(), c->rec_tgt.data(),
                            epochs, 3e-3, seed);
+        c->cm_p = p;
+        c->cm_theta = theta;
+        c->cm_precision = precision;
+        c->cm_loss = l;
+        c->cm_records = (int)c->rec_kind.size();
+        c->cm_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         if (final_loss) *final_loss = l;
     });
 }
@@ -1309,6 +1351,12 @@ fmm_status fmm_costmodel_fit(fmm_ctx c, int32_t n_rec, const float* features, co
         if (n_rec < 1 || !features || !kinds || !targets) fail(FMM_ERR_INVALID_ARG, "bad records");
         if (epochs < 1 || !(lr > 0)) fail(FMM_ERR_INVALID_ARG, "bad optimiser settings");
         double l = mlp_fit(c, n_rec, features, kinds, targets, epochs, lr, seed);
+        c->cm_p = -1;
+        c->cm_theta = -1;
+        c->cm_precision = -1;
+        c->cm_loss = l;
+        c->cm_records = n_rec;
+        c->cm_seconds = NAN;
         if (final_loss) *final_loss = l;
     });
 }
@@ -1344,7 +1392,145 @@ fmm_status fmm_costmodel_set_weights(fmm_ctx c, const float* w) {
         to_dev(c, need<float>(c, c->d_mlp, kMlpParams), w, kMlpParams);
         c->mlp_ready = true;
         c->mlp_version++;
+        c->cm_p = -1;
+        c->cm_theta = -1;
+        c->cm_precision = -1;
+        c->cm_loss = NAN;
+        c->cm_records = 0;
+        c->cm_seconds = NAN;
     });
+}
+
+namespace {
+// the device a cost model was timed on: architecture and compute-unit count
+std::string device_key(int device) {
+    hipDeviceProp_t prop;
+    ck(hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties");
+    std::string arch = prop.gcnArchName;
+    size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch = arch.substr(0, colon);
+    return arch + "/" + std::to_string(prop.multiProcessorCount) + "cu";
+}
+
+const char kModelMagic[] = "fmm-costmodel";
+const int kModelVersion = 1;
+}  // namespace
+
+fmm_status fmm_costmodel_save(fmm_ctx c, const char* path) {
+    return guarded(c, [&] {
+        if (!path) fail(FMM_ERR_INVALID_ARG, "null path");
+        if (!c->mlp_ready) fail(FMM_ERR_STATE, "no cost model");
+        std::vector<float> w(kMlpParams);
+        to_host<float>(c, w.data(), c->d_mlp.p, kMlpParams);
+        std::string tmp = std::string(path) + ".tmp";
+        FILE* f = std::fopen(tmp.c_str(), "w");
+        if (!f) fail(FMM_ERR_DEVICE, std::string("cannot write ") + path);
+        std::fprintf(f, "%s %d\n", kModelMagic, kModelVersion);
+        std::fprintf(f, "device %s\n", device_key(c->device).c_str());
+        std::fprintf(f, "p %d\ntheta %a\nprecision %d\n", c->cm_p, c->cm_theta, c->cm_precision);
+        std::fprintf(f, "loss %a\nrecords %d\ntraining_seconds %a\n", c->cm_loss, c->cm_records, c->cm_seconds);
+        if (c->costs_set) std::fprintf(f, "costs %a %a %a\n", c->costs[0], c->costs[1], c->costs[2]);
+        else std::fprintf(f, "costs none\n");
+        std::fprintf(f, "p2p_tpl");
+        for (int k = 0; k < kLeafClasses; k++) std::fprintf(f, " %d", c->p2p_tpl[k]);
+        std::fprintf(f, "\nschedule %d\nweights %d\n", c->schedule, kMlpParams);
+        for (int i = 0; i < kMlpParams; i++) std::fprintf(f, "%a%c", (double)w[i], (i % 8 == 7) ? '\n' : ' ');
+        std::fprintf(f, "\nend\n");
+        bool ok = std::ferror(f) == 0;
+        ok = (std::fclose(f) == 0) && ok;
+        if (!ok || std::rename(tmp.c_str(), path) != 0) {
+            std::remove(tmp.c_str());
+            fail(FMM_ERR_DEVICE, std::string("cannot write ") + path);
+        }
+    });
+}
+
+fmm_status fmm_costmodel_load(fmm_ctx c, const char* path, int32_t p, int32_t precision) {
+    return guarded(c, [&] {
+        if (!path) fail(FMM_ERR_INVALID_ARG, "null path");
+        FILE* f = std::fopen(path, "r");
+        if (!f) fail(FMM_ERR_INVALID_ARG, std::string("cannot read ") + path);
+        struct Close {
+            FILE* f;
+            ~Close() { std::fclose(f); }
+        } cl{f};
+        auto bad = [&](const char* what) { fail(FMM_ERR_INVALID_ARG, std::string(path) + ": " + what); };
+        char word[64], dev[256];
+        int ver = 0;
+        if (std::fscanf(f, "%63s %d", word, &ver) != 2 || std::strcmp(word, kModelMagic) != 0) bad("not a cost model");
+        if (ver != kModelVersion) bad("unsupported format version");
+        if (std::fscanf(f, " device %255s", dev) != 1) bad("missing device");
+        int mp = -1, mprec = -1, nrec = 0, nw = 0, sched = 0;
+        double mth = -1, loss = NAN, secs = NAN;
+        if (std::fscanf(f, " p %d theta %la precision %d loss %la records %d training_seconds %la", &mp, &mth, &mprec,
+                        &loss, &nrec, &secs) != 6)
+            bad("malformed header");
+        double cst[3] = {0, 0, 0};
+        bool has_costs = false;
+        char cw[32];
+        if (std::fscanf(f, " costs %31s", cw) != 1) bad("missing costs");
+        if (std::strcmp(cw, "none") != 0) {
+            cst[0] = std::strtod(cw, nullptr);
+            if (std::fscanf(f, "%la %la", &cst[1], &cst[2]) != 2) bad("malformed costs");
+            has_costs = true;
+            for (double v : cst)
+                if (!(v > 0) || !std::isfinite(v)) bad("unit costs must be > 0");
+        }
+        int tpl[kLeafClasses];
+        if (std::fscanf(f, " p2p_tpl") != 0) bad("missing tile shapes");
+        for (int k = 0; k < kLeafClasses; k++)
+            if (std::fscanf(f, "%d", &tpl[k]) != 1 || (tpl[k] != 1 && tpl[k] != 2 && tpl[k] != 4)) bad("bad tile shapes");
+        if (std::fscanf(f, " schedule %d weights %d", &sched, &nw) != 2 || sched < 0 || sched > 2) bad("bad schedule");
+        if (nw != kMlpParams) bad("weight count does not match this network");
+        std::vector<float> w(kMlpParams);
+        for (int i = 0; i < kMlpParams; i++) {
+            double v;
+            if (std::fscanf(f, "%la", &v) != 1 || !std::isfinite(v)) bad("malformed weights");
+            w[i] = (float)v;
+        }
+        if (std::fscanf(f, " %63s", word) != 1 || std::strcmp(word, "end") != 0) bad("truncated file");
+        const std::string here = device_key(c->device);
+        if (here != dev) bad((std::string("trained on ") + dev + ", this device is " + here).c_str());
+        if (p >= 0 && p != mp) bad(("trained for p = " + std::to_string(mp) + ", not " + std::to_string(p)).c_str());
+        if (precision >= 0 && precision != mprec)
+            bad(("trained for precision " + std::to_string(mprec) + ", not " + std::to_string(precision)).c_str());
+        to_dev(c, need<float>(c, c->d_mlp, kMlpParams), w.data(), kMlpParams);
+        c->mlp_ready = true;
+        c->mlp_version++;
+        c->cm_p = mp;
+        c->cm_theta = mth;
+        c->cm_precision = mprec;
+        c->cm_loss = loss;
+        c->cm_records = nrec;
+        c->cm_seconds = secs;
+        if (has_costs) {
+            for (int k = 0; k < 3; k++) c->costs[k] = cst[k];
+            c->costs_set = true;
+        }
+        for (int k = 0; k < kLeafClasses; k++) c->p2p_tpl[k] = tpl[k];
+        c->schedule = sched;
+    });
+}
+
+fmm_status fmm_set_allocator(fmm_ctx c, fmm_alloc_fn alloc, fmm_free_fn free_fn, void* user) {
+    return guarded(c, [&] {
+        if ((alloc == nullptr) != (free_fn == nullptr)) fail(FMM_ERR_INVALID_ARG, "set both routines or neither");
+        c->ualloc = alloc;
+        c->ufree = free_fn;
+        c->uuser = alloc ? user : nullptr;
+    });
+}
+
+fmm_status fmm_m2l_slots(int32_t p, double theta, int32_t* slots, int32_t* batched) {
+    if (p < 0 || p > FMM_P_MAX || !(theta > 0.0 && theta < 1.0)) return FMM_ERR_INVALID_ARG;
+    try {
+        const int J = m2l_plan_slots(theta);
+        if (slots) *slots = J;
+        if (batched) *batched = (m2l_gemm_supported(p) && J <= kGemmMaxSlots) ? 1 : 0;
+    } catch (...) {
+        return FMM_ERR_OUT_OF_MEMORY;
+    }
+    return FMM_OK;
 }
 
 fmm_status fmm_costmodel_loss_grad(fmm_ctx c, const float* w, int32_t n_rec, const float* features,

@@ -55,6 +55,9 @@ void sort_u32(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* va
               int bit0, int bit1, void* ws, hipStream_t s);
 
 void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+// zero `bytes` (a multiple of 4) from p (4-byte aligned) with a kernel, not a
+// memset node, so that a captured graph replays it like any other launch
+void fill_zero(void* p, size_t bytes, hipStream_t s);
 // artificial particles for the kernel pre-calculation: uniform in [0,1)^3, charges +-1
 void artificial_points(int64_t n, uint64_t seed, float* x, float* y, float* z, float* q, hipStream_t s);
 void iota_u32(uint32_t* p, int64_t n, hipStream_t s);

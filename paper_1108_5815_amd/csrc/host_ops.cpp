@@ -258,6 +258,25 @@ void build_tables(int p, HostTables& t) {
     }
 }
 
+int m2l_plan_slots(double theta) {
+    double theta2 = theta * theta;
+    int omax = 0;
+    while (theta2 * (double)((omax + 1) * (omax + 1)) < 1.0) omax++;
+    // octant class 0 (target at the low corner of its parent): offsets
+    // o = 2O + c_s over the parent offsets O that are not accepted
+    int J = 0;
+    for (int a = -omax; a <= omax; a++)
+        for (int b = -omax; b <= omax; b++)
+            for (int c = -omax; c <= omax; c++) {
+                if (!(theta2 * (double)(a * a + b * b + c * c) < 1.0)) continue;
+                for (int cs = 0; cs < 8; cs++) {
+                    int o0 = 2 * a + (cs & 1), o1 = 2 * b + ((cs >> 1) & 1), o2 = 2 * c + ((cs >> 2) & 1);
+                    if (1.0 <= theta2 * (double)(o0 * o0 + o1 * o1 + o2 * o2)) J++;
+                }
+            }
+    return J;
+}
+
 void build_m2l_plan(int p, double theta, M2LPlan& plan) {
     double theta2 = theta * theta;
     int omax = 0;

@@ -55,6 +55,11 @@ void split_bf16_kblocked(const std::vector<float>& T, size_t noff, int KP, std::
 
 void build_tables(int p, HostTables& t);
 void build_m2l_plan(int p, double theta, M2LPlan& plan);
+// J of build_m2l_plan for theta, counted without building operators
+int m2l_plan_slots(double theta);
+// the batched same-level GEMM is used up to this many slots per octant class
+// (a pair's slot is stored in 16 bits; the gather table holds J entries per target)
+constexpr int kGemmMaxSlots = 4096;
 
 // Real-form operator of a general M2L: Ltilde = T Mtilde with source radius
 // ratio rs/rt and offset (source centre - target centre) / rt.  Row-major K x K.

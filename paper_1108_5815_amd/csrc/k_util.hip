@@ -355,6 +355,20 @@ __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
     if (i < n) p[i] = v;
 }
 
+// words [0, n4) as 16-byte stores from the first 16-byte boundary, the
+// words before it (head) and after the last whole vector one by one
+__global__ void k_zero(uint32_t* p, int64_t n, int64_t head) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nv = (n - head) / 4;
+    if (i < nv) {
+        uint4 z = make_uint4(0, 0, 0, 0);
+        *(uint4*)(p + head + 4 * i) = z;
+    }
+    if (i < head) p[i] = 0;
+    const int64_t tail = head + 4 * nv;
+    if (i < n - tail) p[tail + i] = 0;
+}
+
 __global__ void k_iota_u32(uint32_t* p, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = (uint32_t)i;
@@ -395,6 +409,15 @@ void sort_u32(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, int64_t n,
 void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
     if (n <= 0) return;
     k_fill_i32<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, v, n);
+}
+
+void fill_zero(void* p, size_t bytes, hipStream_t s) {
+    const int64_t n = (int64_t)(bytes / 4);
+    if (n <= 0) return;
+    int64_t head = (int64_t)((16 - ((uintptr_t)p & 15)) & 15) / 4;
+    if (head > n) head = n;
+    const int64_t threads = std::max<int64_t>((n - head) / 4, 4);
+    k_zero<<<(unsigned)((threads + 255) / 256), 256, 0, s>>>((uint32_t*)p, n, head);
 }
 
 void iota_u32(uint32_t* p, int64_t n, hipStream_t s) {

@@ -39,3 +39,41 @@ def test_binding_names_match_header():
     src = open(binding.__file__).read()
     for n in declared_functions():
         assert f'"{n}"' in src, n
+
+
+def test_m2l_slot_count_and_gemm_guard():
+    """Slots of the batched same-level M2L (accepted offsets per octant class):
+    189 at theta = 0.5 (the 3x3x3 neighbour list of the parent, minus the 27
+    near children) and 567 at 0.4.  The per-pair slot is stored in 16 bits and
+    the gather table holds one entry per slot and target, so small theta (more
+    than 4096 slots) must send every pair to the class-batched path rather
+    than wrap the slot."""
+    from paper_1108_5815_amd import m2l_slots
+    assert m2l_slots(10, 0.5) == (189, 1)
+    assert m2l_slots(10, 0.4) == (567, 1)
+    j08, b08 = m2l_slots(10, 0.08)
+    assert j08 > 32767 and b08 == 0
+    j2, b2 = m2l_slots(10, 0.2)
+    assert j2 <= 4096 and b2 == 1
+    assert m2l_slots(16, 0.5) == (189, 0)       # no matrix-core tiling at storage width 320
+    # grows as theta^-3: brute-force count of class 0 (target at its parent's low corner)
+    for theta in (0.5, 0.3, 0.15):
+        t2 = theta * theta
+        om = 0
+        while t2 * (om + 1) ** 2 < 1.0:
+            om += 1
+        J = 0
+        rng = range(-om, om + 1)
+        for a in rng:
+            for b in rng:
+                for c in rng:
+                    if t2 * (a * a + b * b + c * c) < 1.0:
+                        for cs in range(8):
+                            o = (2 * a + (cs & 1), 2 * b + (cs >> 1 & 1), 2 * c + (cs >> 2 & 1))
+                            J += 1.0 <= t2 * (o[0] ** 2 + o[1] ** 2 + o[2] ** 2)
+        assert m2l_slots(10, theta)[0] == J
+
+
+def test_precision_enum_has_no_fp64_form():
+    src = open(HEADER).read()
+    assert "FMM_PREC_FP64" not in src

@@ -96,8 +96,8 @@ def test_bf16_unsupported_orders():
         assert e.value.status == 5
         f.evaluate(0)                    # FP32 still works on the same lists
     with pytest.raises(FMMError) as e:
-        f.evaluate(2)                    # FP64 is reserved
-    assert e.value.status == 5
+        f.evaluate(2)                    # no such precision form
+    assert e.value.status == 1
 
 
 def test_full_size_plummer4m_p10_bf16_sampled():
