@@ -83,8 +83,7 @@ def lib():
         L.ora_traverse_table.argtypes = [vp, ctypes.c_double, vp]
         L.ora_mlp_forward.argtypes = [vp, vp, vp]
         L.ora_mlp_loss_grad.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp, vp]
-        L.ora_mlp_forward_f32.argtypes = [vp, vp, vp]
-        L.ora_mlp_table.argtypes = [vp, ctypes.c_int, ctypes.c_float, vp, vp]
+        L.ora_mlp_table64.argtypes = [vp, ctypes.c_int, ctypes.c_double, vp, vp, vp]
         L.ora_interleave.restype = ctypes.c_uint64
         L.ora_interleave.argtypes = [ctypes.c_uint64] * 3
         _lib = L
@@ -337,18 +336,14 @@ def mlp_loss_grad(w, feat, kind, tgt):
     return float(loss[0]), g
 
 
-def mlp_forward_f32(w, f):
-    w = np.ascontiguousarray(w, np.float32)
-    f = np.ascontiguousarray(f, np.float32)
-    y = np.zeros(3, np.float32)
-    lib().ora_mlp_forward_f32(_p(w), _p(f), _p(y))
-    return y
-
-
-def mlp_table(w, p, theta):
-    """(choices[9,81,81,4] uint8, margin[9,81,81,4] float32) in FP32."""
-    w = np.ascontiguousarray(w, np.float32)
+def mlp_table64(w, p, theta):
+    """(choices, margin, bound), each [9,81,81,4]: the FP64 least-time kind over
+    the quantised feature grid, the gap between the two least outputs, and a
+    bound on the FP32 evaluation error of the outputs."""
+    w = _f64(w)
     tab = np.zeros(9 * 81 * 81 * 4, np.uint8)
-    mar = np.zeros(9 * 81 * 81 * 4, np.float32)
-    lib().ora_mlp_table(_p(w), int(p), float(theta), _p(tab), _p(mar))
-    return tab.reshape(9, 81, 81, 4), mar.reshape(9, 81, 81, 4)
+    mar = np.zeros(9 * 81 * 81 * 4)
+    bnd = np.zeros(9 * 81 * 81 * 4)
+    lib().ora_mlp_table64(_p(w), int(p), float(theta), _p(tab), _p(mar), _p(bnd))
+    sh = (9, 81, 81, 4)
+    return tab.reshape(sh), mar.reshape(sh), bnd.reshape(sh)

@@ -11,9 +11,12 @@
  *
  *  - ora_mlp_forward / ora_mlp_loss_grad: FP64, the plain definitions
  *    (backpropagation written out layer by layer).
- *  - ora_mlp_forward_f32 / ora_mlp_table: FP32 with the accumulation order
- *    a = b; a = fma(w_k, x_k, a) for k ascending, so that the kernel-kind
- *    decision is taken in the kernel's precision.
+ *  - ora_mlp_table64: the choice (least predicted log time) over the
+ *    quantised feature grid from the FP64 forward, with the gap between the
+ *    two least outputs and a bound on how far an FP32 evaluation of the same
+ *    network (any summation order, features rounded to FP32) can move each
+ *    output.  A decision whose gap exceeds twice the bound is the same in any
+ *    FP32 evaluation; closer ones are ties at FP32 resolution.
  */
 #include <math.h>
 #include <stdint.h>
@@ -102,49 +105,82 @@ void ora_mlp_loss_grad(const double *w, int B, const double *feat, const int32_t
     *loss = L;
 }
 
-void ora_mlp_forward_f32(const float *w, const float *f, float *y)
+/* Standard forward error of an FP32 dot product plus bias (Higham, Accuracy
+ * and Stability of Numerical Algorithms, 2nd ed., section 3.1): with unit
+ * roundoff u = 2^-24 and gamma_n = n u / (1 - n u), evaluating
+ * b + sum_k w_k x_k over K terms in any order errs by at most
+ * gamma_{K+1} (|b| + sum_k |w_k| |x_k|); inputs already off by e_k add
+ * sum_k |w_k| e_k.  ReLU does not increase an error. */
+static double gamma_n(int n)
 {
-    float h1[H];
-    for (int i = 0; i < H; i++) {
-        float a = w[OB1 + i];
-        for (int k = 0; k < F; k++) a = fmaf(w[OW1 + i * F + k], f[k], a);
-        h1[i] = fmaxf(a, 0.f);
-    }
-    float o[O] = {w[OB3], w[OB3 + 1], w[OB3 + 2]};
-    for (int i = 0; i < H; i++) {
-        float a = w[OB2 + i];
-        for (int k = 0; k < H; k++) a = fmaf(w[OW2 + i * H + k], h1[k], a);
-        a = fmaxf(a, 0.f);
-        for (int j = 0; j < O; j++) o[j] = fmaf(w[OW3 + j * H + i], a, o[j]);
-    }
-    for (int j = 0; j < O; j++) y[j] = o[j];
+    const double u = ldexp(1.0, -24);
+    return n * u / (1.0 - n * u);
 }
 
-/* Decision grid: entry ((dl+4)*81 + bt)*81 + bs)*4 + bq with features
- * (dl/2, (bt/4)/8, (bs/4)/8, p/10, (bq+0.5)/4, theta); least predicted log
- * time wins, ties to the earlier kind.  `margin` receives the gap between
- * the two smallest outputs (may be NULL). */
-void ora_mlp_table(const float *w, int p, float theta, uint8_t *table, float *margin)
+/* FP64 forward with a bound e[j] on each output's FP32 evaluation error */
+static void forward_bound(const double *w, const double *f, double *y, double *e)
+{
+    const double u = ldexp(1.0, -24);
+    double h1[H], e1[H], h2[H], e2[H], ef[F];
+    for (int k = 0; k < F; k++) ef[k] = u * fabs(f[k]);
+    for (int i = 0; i < H; i++) {
+        double a = w[OB1 + i], mag = fabs(w[OB1 + i]), prop = 0;
+        for (int k = 0; k < F; k++) {
+            double wk = w[OW1 + i * F + k];
+            a += wk * f[k];
+            mag += fabs(wk) * (fabs(f[k]) + ef[k]);
+            prop += fabs(wk) * ef[k];
+        }
+        h1[i] = a > 0 ? a : 0;
+        e1[i] = prop + gamma_n(F + 1) * mag;
+    }
+    for (int i = 0; i < H; i++) {
+        double a = w[OB2 + i], mag = fabs(w[OB2 + i]), prop = 0;
+        for (int k = 0; k < H; k++) {
+            double wk = w[OW2 + i * H + k];
+            a += wk * h1[k];
+            mag += fabs(wk) * (h1[k] + e1[k]);
+            prop += fabs(wk) * e1[k];
+        }
+        h2[i] = a > 0 ? a : 0;
+        e2[i] = prop + gamma_n(H + 1) * mag;
+    }
+    for (int j = 0; j < O; j++) {
+        double a = w[OB3 + j], mag = fabs(w[OB3 + j]), prop = 0;
+        for (int k = 0; k < H; k++) {
+            double wk = w[OW3 + j * H + k];
+            a += wk * h2[k];
+            mag += fabs(wk) * (h2[k] + e2[k]);
+            prop += fabs(wk) * e2[k];
+        }
+        y[j] = a;
+        e[j] = prop + gamma_n(H + 1) * mag;
+    }
+}
+
+/* Decision grid: entry ((dl+4)*81 + bt)*81 + bs)*4 + bq holds the features
+ * (dl/2, (bt/4)/8, (bs/4)/8, p/10, (bq+0.5)/4, theta), dl in [-4, 4],
+ * bt, bs in [0, 80], bq in [0, 3]; the least predicted log time wins, ties
+ * to the earlier kind.  margin = gap between the two least outputs;
+ * bound = largest FP32 error bound of the three outputs. */
+void ora_mlp_table64(const double *w, int p, double theta, uint8_t *table, double *margin, double *bound)
 {
     int e = 0;
     for (int dl = -4; dl <= 4; dl++)
         for (int bt = 0; bt < 81; bt++)
             for (int bs = 0; bs < 81; bs++)
                 for (int bq = 0; bq < 4; bq++, e++) {
-                    float f[F] = {(float)dl / 2.f, ((float)bt / 4.f) / 8.f, ((float)bs / 4.f) / 8.f,
-                                  (float)p / 10.f, ((float)bq + 0.5f) / 4.f, theta};
-                    float y[O];
-                    ora_mlp_forward_f32(w, f, y);
+                    double f[F] = {dl / 2.0, (bt / 4.0) / 8.0, (bs / 4.0) / 8.0, p / 10.0, (bq + 0.5) / 4.0, theta};
+                    double y[O], eo[O];
+                    forward_bound(w, f, y, eo);
                     int k = 0;
-                    float best = y[0];
-                    if (y[1] < best) { best = y[1]; k = 1; }
-                    if (y[2] < best) { best = y[2]; k = 2; }
+                    if (y[1] < y[k]) k = 1;
+                    if (y[2] < y[k]) k = 2;
+                    double second = INFINITY;
+                    for (int j = 0; j < O; j++)
+                        if (j != k && y[j] < second) second = y[j];
                     table[e] = (uint8_t)k;
-                    if (margin) {
-                        float second = INFINITY;
-                        for (int j = 0; j < O; j++)
-                            if (j != k && y[j] < second) second = y[j];
-                        margin[e] = second - best;
-                    }
+                    margin[e] = second - y[k];
+                    bound[e] = fmax(eo[0], fmax(eo[1], eo[2]));
                 }
 }

@@ -70,24 +70,54 @@ def test_loss_is_mean_squared_error(ora):
     assert abs(loss - ref) < 1e-14 * max(1.0, ref)
 
 
-def test_fp32_forward_close_to_fp64(ora):
-    w = seeded_weights(7)
-    feat, _, _ = seeded_records(8, 5)
-    for r in range(5):
-        y64 = ora.mlp_forward(w, feat[r])
-        y32 = ora.mlp_forward_f32(w.astype(np.float32), feat[r].astype(np.float32))
-        w32 = w.astype(np.float32).astype(np.float64)
-        ref = ora.mlp_forward(w32, feat[r].astype(np.float32).astype(np.float64))
-        assert np.allclose(y32, ref, rtol=1e-5, atol=1e-5)
-        assert np.allclose(y64, ref, rtol=1e-6, atol=1e-6)
+def _grid_features(p, theta):
+    """The quantised feature grid of the choice table, [9,81,81,4,6], FP64."""
+    dl, bt, bs, bq = np.meshgrid(np.arange(-4, 5), np.arange(81), np.arange(81), np.arange(4), indexing="ij")
+    f = np.stack([dl / 2.0, bt / 4.0 / 8.0, bs / 4.0 / 8.0, np.full(dl.shape, p / 10.0), (bq + 0.5) / 4.0,
+                  np.full(dl.shape, theta)], axis=-1)
+    return f
 
 
-def test_table_picks_argmin(ora):
-    w = seeded_weights(9).astype(np.float32)
-    tab, mar = ora.mlp_table(w, 10, 0.4)
+def _np_forward(w, f, dtype):
+    """The network as three library matrix products in `dtype`."""
+    w = np.asarray(w, dtype)
+    f = np.asarray(f, dtype).reshape(-1, F)
+    W1, b1 = w[OW1:OB1].reshape(H, F), w[OB1:OW2]
+    W2, b2 = w[OW2:OB2].reshape(H, H), w[OB2:OW3]
+    W3, b3 = w[OW3:OB3].reshape(3, H), w[OB3:OB3 + 3]
+    h1 = np.maximum(f @ W1.T + b1, 0)
+    h2 = np.maximum(h1 @ W2.T + b2, 0)
+    return h2 @ W3.T + b3
+
+
+def test_table64_is_the_argmin_of_the_forward(ora):
+    w = seeded_weights(9).astype(np.float32).astype(np.float64)
+    tab, mar, bnd = ora.mlp_table64(w, 10, 0.4)
     assert tab.shape == (9, 81, 81, 4) and set(np.unique(tab)) <= {0, 1, 2}
+    y = _np_forward(w, _grid_features(10, 0.4), np.float64).reshape(9, 81, 81, 4, 3)
+    ys = np.sort(y, axis=-1)
+    clear = (ys[..., 1] - ys[..., 0]) > 1e-12
+    assert np.array_equal(tab[clear], np.argmin(y, axis=-1)[clear])
+    assert np.allclose(mar, ys[..., 1] - ys[..., 0], rtol=0, atol=1e-12)
+    # spot checks through the oracle's own scalar forward
     for (dl, bt, bs, bq) in [(0, 0, 0, 0), (8, 80, 3, 3), (4, 17, 40, 2), (2, 60, 60, 1)]:
-        f = np.array([(dl - 4) / 2, bt / 4 / 8, bs / 4 / 8, 1.0, (bq + 0.5) / 4, 0.4], np.float32)
-        y = ora.mlp_forward_f32(w, f)
-        assert tab[dl, bt, bs, bq] == int(np.argmin(y))
-        assert mar[dl, bt, bs, bq] >= 0
+        f = np.array([(dl - 4) / 2, bt / 4 / 8, bs / 4 / 8, 1.0, (bq + 0.5) / 4, 0.4])
+        assert tab[dl, bt, bs, bq] == int(np.argmin(ora.mlp_forward(w, f)))
+
+
+def test_fp32_error_bound_holds(ora):
+    """An FP32 evaluation (library matrix products, features rounded to FP32)
+    stays within the oracle's bound of the FP64 outputs everywhere, and the
+    bound is tight enough to decide nearly every entry."""
+    for seed, p, theta in ((9, 10, 0.4), (31, 8, 0.5)):
+        w = seeded_weights(seed).astype(np.float32)
+        tab, mar, bnd = ora.mlp_table64(w, p, theta)
+        f = _grid_features(p, theta)
+        y64 = _np_forward(w.astype(np.float64), f, np.float64).reshape(9, 81, 81, 4, 3)
+        y32 = _np_forward(w, f.astype(np.float32), np.float32).astype(np.float64).reshape(9, 81, 81, 4, 3)
+        err = np.abs(y32 - y64).max(axis=-1)
+        assert np.all(err <= bnd), float((err / bnd).max())
+        assert np.median(bnd) < 1e-3
+        decided = mar > 2 * bnd
+        assert decided.mean() > 0.99
+        assert np.array_equal(np.argmin(y32, axis=-1)[decided], tab[decided])

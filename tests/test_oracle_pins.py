@@ -167,6 +167,62 @@ def test_coverage_exactly_once(ora, policy, costs, theta):
         assert L[0][0].size == 0
 
 
+def _mac_accepts(c, a, b, theta):
+    R2 = float(np.sum((c["centre_h"][a] - c["centre_h"][b]) ** 2))
+    rr = float(c["radius_h"][a] + c["radius_h"][b])
+    return rr * rr <= theta * theta * R2
+
+
+@pytest.mark.parametrize("policy,costs", [(0, (0, 0, 0)), (2, (50.0, 4.0, 1.0))])
+@pytest.mark.parametrize("theta", [0.5, 0.4])
+def test_split_the_larger_cell_on_adaptive_tree(ora, policy, costs, theta):
+    """The paper's dual traversal splits the larger cell of each pair that
+    fails the criterion ("Dual tree traversal"); with cubes, larger = lower
+    level, both on a tie, and a leaf cannot split.  Two consequences checked on
+    an adaptive tree with many level differences:
+    - every emitted pair has equal levels, or its larger (lower-level) cell is
+      a leaf (a larger non-leaf cell is never kept while the smaller splits);
+    - every emitted pair other than the root pair has a parent pair, one split
+      away (each split side replaced by its parent cell), that failed the
+      criterion, is not a pair of leaves, and whose split sides are exactly
+      the lower-level non-leaf cells (both at equal levels).
+    Splitting only one cell on a tie fails both checks.  (With ties split
+    both, two non-leaf cells of a visited pair always have equal levels, so
+    "larger" only ever decides between a leaf and a non-leaf cell.)"""
+    x, y, z = synth.plummer(5000, 33)
+    t = ora.Tree(x, y, z, 8)
+    t.traverse(theta, policy, costs)
+    L = t.lists()
+    c = t.cells()
+    lev, par = c["level"].astype(np.int64), c["parent"].astype(np.int64)
+    leaf = c["nchild"] == 0
+    ctr, rad = c["centre_h"].astype(np.float64), c["radius_h"].astype(np.float64)
+    pairs = np.concatenate([np.stack(L[k], axis=1) for k in (0, 1, 2)]).astype(np.int64)
+    a, b = pairs[:, 0], pairs[:, 1]
+    neq = lev[a] != lev[b]
+    big = np.where(lev[a] < lev[b], a, b)
+    assert np.all(leaf[big[neq]])
+    unequal = int(neq.sum())
+    keep = ~((a == 0) & (b == 0))
+    a, b = a[keep], b[keep]
+
+    def consistent(pa, pb, how_a, how_b):
+        """Candidate parents (pa, pb) whose rule splits exactly the given sides."""
+        valid = (pa >= 0) & (pb >= 0)
+        pa_, pb_ = np.where(valid, pa, 0), np.where(valid, pb, 0)
+        R2 = np.sum((ctr[pa_] - ctr[pb_]) ** 2, axis=1)
+        rr = rad[pa_] + rad[pb_]
+        fails = ~(rr * rr <= theta * theta * R2)
+        sa = ~leaf[pa_] & (leaf[pb_] | (lev[pa_] <= lev[pb_]))
+        sb = ~leaf[pb_] & (leaf[pa_] | (lev[pb_] <= lev[pa_]))
+        return valid & fails & ~(leaf[pa_] & leaf[pb_]) & (sa == how_a) & (sb == how_b)
+
+    ok = consistent(par[a], par[b], True, True) | consistent(par[a], b, True, False) | \
+        consistent(a, par[b], False, True)
+    assert np.all(ok), pairs[keep][~ok][:5]
+    assert unequal > 100       # the tree really mixes levels
+
+
 def grid_points(m):
     g = np.arange(m) / (m - 1.0)
     X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
