@@ -335,9 +335,10 @@ fmm_status fmm_get_expansions(fmm_ctx ctx, float *multipole_host, float *local_h
 
 /* Milliseconds of the phases of the last build/traverse/evaluate (recorded
  * only while timing is enabled), in the order: bbox+keys, sort, tree,
- * traverse, lists, p2m+m2m, m2l (batched GEMM), m2l (general pairs), l2l,
- * p2p, far+final.  Writes min(cap, 11) values; returns their count in
- * *count. */
+ * traverse, lists, p2m+m2m, m2l (batched GEMM phase: multipole split, GEMM,
+ * group sum), m2l (general pairs), l2l, p2p, far+final, and last the
+ * batched M2L GEMM kernel alone (0 when it did not run).  Writes
+ * min(cap, 12) values; returns their count in *count. */
 fmm_status fmm_get_timings(fmm_ctx ctx, double *ms_host, int32_t cap, int32_t *count);
 
 /* Enable (1) or disable (0) per-phase timing events (adds synchronisation).

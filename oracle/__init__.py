@@ -80,6 +80,7 @@ def lib():
         L.ora_bbox.argtypes = [I64, vp, vp, vp, vp, vp]
         L.ora_morton.argtypes = [I64, vp, vp, vp, vp, ctypes.c_double, vp]
         L.ora_num_threads.restype = ctypes.c_int
+        L.ora_set_threads.argtypes = [ctypes.c_int]
         L.ora_traverse_table.argtypes = [vp, ctypes.c_double, vp]
         L.ora_mlp_forward.argtypes = [vp, vp, vp]
         L.ora_mlp_loss_grad.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp, vp]
@@ -92,6 +93,11 @@ def lib():
 
 def num_threads() -> int:
     return int(lib().ora_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops from now on."""
+    lib().ora_set_threads(int(n))
 
 
 def _p(a: np.ndarray):

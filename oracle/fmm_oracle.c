@@ -49,6 +49,16 @@ int ora_num_threads(void)
 #endif
 }
 
+/* set that count (n >= 1) */
+void ora_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 #define ORA_MAXLEVEL 21
 #define ORA_PMAX 40
 

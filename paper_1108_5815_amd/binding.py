@@ -407,9 +407,9 @@ class FMM:
         return M.reshape(c, K), L.reshape(c, K)
 
     def timings(self) -> dict:
-        ms = np.zeros(11)
+        ms = np.zeros(12)
         cnt = ctypes.c_int32()
-        self._ck(lib().fmm_get_timings(self.h, _ptr(ms), 11, ctypes.byref(cnt)))
+        self._ck(lib().fmm_get_timings(self.h, _ptr(ms), 12, ctypes.byref(cnt)))
         names = ["keys", "sort", "tree", "traverse", "lists", "p2m_m2m", "m2l_gemm", "m2l_general", "l2l", "p2p",
-                 "far_final"]
+                 "far_final", "m2l_gemm_kernel"]
         return dict(zip(names, ms[:cnt.value].tolist()))

@@ -52,6 +52,8 @@ struct fmm_ctx_s {
     bool timing = false;
     hipEvent_t ev[PH_N + 1] = {};
     double ms[PH_N] = {};
+    hipEvent_t ev_gk[2] = {};  // around the same-level GEMM kernel itself
+    double ms_gemm_kernel = 0;
 
     // near field on a second stream, concurrent with the far-field chain:
     // 0 in order, 1 from the start of the evaluation, 2 after the upward pass
@@ -849,7 +851,35 @@ void run_p2p(fmm_ctx c, double4* near, hipStream_t st) {
 }
 
 // ------------------------------------------------------------------ evaluate
-void evaluate_impl(fmm_ctx c, int32_t precision, int32_t out_dtype, void* phi, void* ex, void* ey, void* ez) {
+// Work buffers of one evaluation (beyond the context's tree, lists and
+// tables): expansions, near-field partials, per-group GEMM partials, split
+// multipoles, class partials and the cell-particle flags.
+struct EvalBufs {
+    float* M = nullptr;         // (ncell + 1) * KP: multipoles and one all-zero row
+    float* L = nullptr;         // ncell * KP
+    double4* near = nullptr;    // n
+    float* part = nullptr;      // G * nrows * KP (batched GEMM)
+    uint4* Msplit = nullptr;    // (ncell + 1) * KP / 4 (split-BF16 batched GEMM)
+    float* cls_part = nullptr;  // nbatched * KP (class-batched pairs)
+    uint8_t* m2pflag = nullptr; // max(nleaf, 1)
+};
+
+enum { EB_M, EB_L, EB_NEAR, EB_PART, EB_MSPLIT, EB_CLS, EB_FLAG, EB_N };
+
+// bytes of each work buffer for an evaluation at `precision` (0 = not used)
+void eval_sizes(fmm_ctx c, int precision, size_t* b) {
+    const size_t KP = (size_t)kpad(c->p), nc = (size_t)c->ncell;
+    const bool gemm = c->gemm_on && c->ntiles > 0;
+    b[EB_M] = (nc + 1) * KP * sizeof(float);
+    b[EB_L] = nc * KP * sizeof(float);
+    b[EB_NEAR] = (size_t)c->n * sizeof(double4);
+    b[EB_PART] = gemm ? (size_t)c->gp.G * c->gp.nrows * KP * sizeof(float) : 0;
+    b[EB_MSPLIT] = gemm && precision == FMM_PREC_SPLIT_BF16 ? (nc + 1) * KP * sizeof(float) : 0;
+    b[EB_CLS] = c->cp.ntiles > 0 ? (size_t)c->cp.nbatched * KP * sizeof(float) : 0;
+    b[EB_FLAG] = (size_t)std::max(c->nleaf, 1);
+}
+
+void check_evaluate_args(fmm_ctx c, int32_t precision, int32_t out_dtype, void* phi, void* ex, void* ey, void* ez) {
     if (!c->traversed) fail(FMM_ERR_STATE, "fmm_evaluate before fmm_traverse");
     if (precision != FMM_PREC_FP32 && precision != FMM_PREC_SPLIT_BF16)
         fail(FMM_ERR_INVALID_ARG, "precision must be FMM_PREC_FP32 or FMM_PREC_SPLIT_BF16");
@@ -857,23 +887,28 @@ void evaluate_impl(fmm_ctx c, int32_t precision, int32_t out_dtype, void* phi, v
         fail(FMM_ERR_UNSUPPORTED, "split-BF16 M2L is implemented for p <= 12");
     if (out_dtype != FMM_F32 && out_dtype != FMM_F64) fail(FMM_ERR_INVALID_ARG, "out_dtype must be F32 or F64");
     if (c->n > 0 && (!phi || !ex || !ey || !ez)) fail(FMM_ERR_INVALID_ARG, "null output pointer");
-    if (c->n == 0) return;
+}
+
+// The evaluation proper on the given work buffers; `in_order` runs every
+// kernel on the context stream (no second stream).
+void evaluate_on(fmm_ctx c, int32_t precision, int32_t out_dtype, void* phi, void* ex, void* ey, void* ez,
+                 const EvalBufs& eb, bool in_order) {
     hipStream_t s = c->stream;
     int p = c->p, KP = kpad(p);
     int32_t nc = c->ncell;
     CellArrays ca = cells_of(c);
     Tables tb = tables_of(c);
     // one extra, all-zero multipole row (index nc): the M2L GEMM reads it for absent sources
-    float* M = need<float>(c, c->M, (size_t)(nc + 1) * KP);
+    float* M = eb.M;
     fill_zero(M + (size_t)nc * KP, (size_t)KP * sizeof(float), s);
     c->gp.zcell = nc;
-    float* L = need<float>(c, c->L, (size_t)nc * KP);
-    double4* nr = need<double4>(c, c->nearb, c->n);
+    float* L = eb.L;
+    double4* nr = eb.near;
     // P2P depends only on the tree and its list: under a concurrent schedule it
     // runs on the second stream (forked at the start, or after the upward
     // pass) while the expansions are formed and translated, and the final sum
     // waits for it
-    const int sched = c->nleaf > 0 ? c->schedule : 0;
+    const int sched = (c->nleaf > 0 && !in_order) ? c->schedule : 0;
     auto fork_p2p = [&] {
         if (!c->s2) {
             ck(hipStreamCreateWithFlags(&c->s2, hipStreamNonBlocking), "hipStreamCreate");
@@ -901,20 +936,20 @@ void evaluate_impl(fmm_ctx c, int32_t precision, int32_t out_dtype, void* phi, v
     mark(c, PH_M2L);
     if (c->gemm_on && c->ntiles > 0)
     {
-        float* part = need<float>(c, c->m2l_part, (size_t)c->gp.G * c->gp.nrows * KP);
+        float* part = eb.part;
+        hipEvent_t g0 = c->timing ? c->ev_gk[0] : nullptr, g1 = c->timing ? c->ev_gk[1] : nullptr;
         if (precision == FMM_PREC_SPLIT_BF16)
             m2l_gemm_bf16((uint16_t*)c->d_Thi.p, (uint16_t*)c->d_Tlo.p, (int32_t*)c->d_offid.p, (int32_t*)c->gather.p,
-                          (uint32_t*)c->rval.p, c->gp, p, KP, M, nc, need<uint4>(c, c->Msplit, (size_t)(nc + 1) * KP / 4),
-                          part, L, s);
+                          (uint32_t*)c->rval.p, c->gp, p, KP, M, nc, eb.Msplit, part, L, s, g0, g1);
         else
             m2l_gemm((float*)c->d_T.p, (int32_t*)c->d_offid.p, (int32_t*)c->gather.p, (uint32_t*)c->rval.p, c->gp, p,
-                     KP, M, part, L, s);
+                     KP, M, part, L, s, g0, g1);
     }
     mark(c, PH_M2LG);
     if (c->cp.ntiles > 0) {
         ClsPlan cp = c->cp;
         cp.zcell = nc;
-        float* part2 = need<float>(c, c->cls_part, (size_t)cp.nbatched * KP);
+        float* part2 = eb.cls_part;
         m2l_cls((const float*)c->cT.p, cp, p, KP, M, part2, (int32_t*)c->goff.p, nc, L, s);
     }
     if (c->ngeneral > c->cp.nbatched)
@@ -932,7 +967,7 @@ void evaluate_impl(fmm_ctx c, int32_t precision, int32_t out_dtype, void* phi, v
         run_p2p(c, nr, s);
     }
     mark(c, PH_FAR);
-    uint8_t* mflag = need<uint8_t>(c, c->m2pflag, (size_t)std::max(c->nleaf, 1));
+    uint8_t* mflag = eb.m2pflag;
     far_final((float4*)c->pts.p, (uint32_t*)c->idx.p, ca, (int32_t*)c->leaves.p, c->nleaf, mflag, (int32_t*)c->off[1].p,
               (uint32_t*)c->src[1].p, c->nlist[1], p, KP, tb, M, L, nr, out_dtype, phi, ex, ey, ez, s);
     check_launch("far field");
@@ -950,7 +985,30 @@ void evaluate_impl(fmm_ctx c, int32_t precision, int32_t out_dtype, void* phi, v
             ck(hipEventElapsedTime(&t, c->e_p2p0, c->e_p2p1), "elapsed");
             c->ms[PH_P2P] = t;
         }
+        c->ms_gemm_kernel = 0;
+        if (c->gemm_on && c->ntiles > 0) {
+            float t = 0;
+            ck(hipEventElapsedTime(&t, c->ev_gk[0], c->ev_gk[1]), "elapsed");
+            c->ms_gemm_kernel = t;
+        }
     }
+}
+
+// fmm_evaluate: work buffers held by the context (grown as needed)
+void evaluate_impl(fmm_ctx c, int32_t precision, int32_t out_dtype, void* phi, void* ex, void* ey, void* ez) {
+    check_evaluate_args(c, precision, out_dtype, phi, ex, ey, ez);
+    if (c->n == 0) return;
+    size_t b[EB_N];
+    eval_sizes(c, precision, b);
+    EvalBufs eb;
+    eb.M = need<float>(c, c->M, b[EB_M] / 4);
+    eb.L = need<float>(c, c->L, b[EB_L] / 4);
+    eb.near = need<double4>(c, c->nearb, c->n);
+    if (b[EB_PART]) eb.part = need<float>(c, c->m2l_part, b[EB_PART] / 4);
+    if (b[EB_MSPLIT]) eb.Msplit = need<uint4>(c, c->Msplit, b[EB_MSPLIT] / 16);
+    if (b[EB_CLS]) eb.cls_part = need<float>(c, c->cls_part, b[EB_CLS] / 4);
+    eb.m2pflag = need<uint8_t>(c, c->m2pflag, b[EB_FLAG]);
+    evaluate_on(c, precision, out_dtype, phi, ex, ey, ez, eb, false);
 }
 
 }  // namespace
@@ -972,6 +1030,7 @@ fmm_status fmm_create(fmm_ctx* out, int device, void* hip_stream) {
     c->stream = (hipStream_t)hip_stream;
     fmm_status st = guarded(c, [&] {
         for (int k = 0; k <= PH_N; k++) ck(hipEventCreate(&c->ev[k]), "hipEventCreate");
+        for (int k = 0; k < 2; k++) ck(hipEventCreate(&c->ev_gk[k]), "hipEventCreate");
     });
     if (st != FMM_OK) {
         fmm_destroy(c);
@@ -989,6 +1048,8 @@ void fmm_destroy(fmm_ctx c) {
     for (Buf* b : c->bufs) dev_release(*b);
     for (int k = 0; k <= PH_N; k++)
         if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
+    for (int k = 0; k < 2; k++)
+        if (c->ev_gk[k]) (void)hipEventDestroy(c->ev_gk[k]);
     if (c->s2) {
         (void)hipStreamSynchronize(c->s2);
         (void)hipStreamDestroy(c->s2);
@@ -1728,8 +1789,8 @@ fmm_status fmm_get_expansions(fmm_ctx c, float* mp, float* lc) {
 fmm_status fmm_get_timings(fmm_ctx c, double* ms, int32_t cap, int32_t* count) {
     return guarded(c, [&] {
         if (!ms && cap > 0) fail(FMM_ERR_INVALID_ARG, "null pointer");
-        int k = std::min<int>(cap, PH_N);
-        for (int i = 0; i < k; i++) ms[i] = c->ms[i];
+        int k = std::min<int>(cap, PH_N + 1);
+        for (int i = 0; i < k; i++) ms[i] = i < PH_N ? c->ms[i] : c->ms_gemm_kernel;
         if (count) *count = k;
     });
 }

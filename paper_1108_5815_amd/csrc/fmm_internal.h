@@ -265,14 +265,17 @@ constexpr int kGemmMaxGroupSlots = 80;
 void tile_slots(const int32_t* gather, GemmPlan plan, int NT, int ntiles, int32_t* act, int32_t* nact,
                 hipStream_t s);
 // part: G * nrows * KP floats of per-group partial locals, summed into L in group order
+// e0, e1 (may be null): events recorded just before and after the GEMM kernel
+// itself (without the group sum), for its own duration
 void m2l_gemm(const float* T, const int32_t* offid, const int32_t* gather, const uint32_t* rowcell,
-              GemmPlan plan, int p, int KP, const float* M, float* part, float* L, hipStream_t s);
+              GemmPlan plan, int p, int KP, const float* M, float* part, float* L, hipStream_t s,
+              hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 bool m2l_gemm_supported(int p);
 // split-BF16 variant (Thi/Tlo: k-blocked BF16 halves of the operators)
 // Ms: scratch of ncell * KP * 4 bytes for the split multipoles
 void m2l_gemm_bf16(const uint16_t* Thi, const uint16_t* Tlo, const int32_t* offid, const int32_t* gather,
                    const uint32_t* rowcell, GemmPlan plan, int p, int KP, const float* M, int64_t ncell, uint4* Ms,
-                   float* part, float* L, hipStream_t s);
+                   float* part, float* L, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // L[rowcell[r]][k] = sum over g in order of part[g][r][k], k < K
 void m2l_reduce_groups(const float* part, GemmPlan plan, const uint32_t* rowcell, int KP, int K, float* L,
                        hipStream_t s);

@@ -260,14 +260,24 @@ __global__ __launch_bounds__(256) void k_m2l_general(const int32_t* __restrict__
         }
     }
     const int4 gt = c.geo[t];
-    const float inv = 1.f / (float)gt.w;
     for (int32_t a = a0 + w; a < a1; a += 4) {
         if (skip && skip[a]) continue;  // handled by the class-batched products
         const int s = (int)gsrc[a];
         const int4 gs = c.geo[s];
+        // The terms are (rs/rt)^n J_{j+n}(q) with q the offset in target half
+        // sides.  When the source is the larger cell, q is taken in source
+        // half sides instead, which turns the term into
+        // (rs/rt)^-(j+1) J_{j+n}(q rt/rs) (J_l is homogeneous of degree
+        // -(l+1)): every factor then stays at most of order one and the
+        // products underflow towards zero instead of meeting an overflow,
+        // whatever the level difference.  The half sides are powers of two,
+        // so both scalings are exact.
+        const bool src_larger = gs.w > gt.w;
+        const float inv = 1.f / (float)(src_larger ? gs.w : gt.w);
         const float qx = (float)(gs.x - gt.x) * inv, qy = (float)(gs.y - gt.y) * inv,
                     qz = (float)(gs.z - gt.z) * inv;
-        const float ratio = (float)gs.w * inv;
+        const float ratio = src_larger ? 1.f : (float)gs.w / (float)gt.w;  // per degree n of the source
+        const float jfac = src_larger ? (float)gt.w / (float)gs.w : 1.f;   // per degree j of the target
         for (int i = lane; i < K; i += 64) Ms[i] = M[(size_t)s * KP + i];
         for (int m = lane; m <= P2; m += 64) {
             const float r2 = qx * qx + qy * qy + qz * qz, ir2 = 1.f / r2;
@@ -308,7 +318,9 @@ __global__ __launch_bounds__(256) void k_m2l_general(const int32_t* __restrict__
             if (oj[u] < 0) continue;
             const int j = oj[u], k = ok[u];
             const float* wr = Wp + (size_t)(j * (j + 1) / 2 + k) * K;
-            float rn = 1.f, tre = 0.f, tim = 0.f;
+            float rj = jfac;
+            for (int jj = 0; jj < j; jj++) rj *= jfac;  // jfac^(j+1)
+            float rn = rj, tre = 0.f, tim = 0.f;
             for (int n = 0; n <= p; n++) {
                 float sre = 0.f, sim = 0.f;
                 for (int m = -n; m <= n; m++) {

@@ -354,14 +354,18 @@ __global__ __launch_bounds__(64) void k_far(const float4* __restrict__ pts, cons
     }
 }
 
-// Cell-particle (M2P) part of the leaves flagged in m2pflag, one leaf per
-// workgroup: each particle continues the FP64 sum k_far stored in near[i]
-// with the sources of its leaf's list, then of each ancestor's, and writes
-// the result.  (The lists are walked by all lanes of the leaf together, each
-// source multipole staged once in LDS.)
-template <int P>
+// Cell-particle (M2P) part of the leaves flagged in m2pflag.  LPW
+// consecutive leaves of the leaf list share a 64-lane workgroup (unflagged
+// ones take no lanes); their particles are flattened and taken 64 at a time.
+// Each particle continues the FP64 sum k_far stored in near[i] with the
+// sources of its leaf's list, then of its parent's, and so on to the root,
+// each list in order.  The packed leaves mostly share their ancestors, so
+// the lists are walked level by level: at chain depth k the distinct k-th
+// ancestors of the packed leaves are the list owners, and step t stages the
+// t-th source of every owner once in LDS for all the lanes under it.
+template <int P, int LPW>
 __global__ __launch_bounds__(64) void k_far_m2p(const float4* __restrict__ pts, const uint32_t* __restrict__ perm,
-                                                CellArrays c, const int32_t* __restrict__ leaves,
+                                                CellArrays c, const int32_t* __restrict__ leaves, int32_t nleaves,
                                                 const uint8_t* __restrict__ m2pflag,
                                                 const int32_t* __restrict__ m2p_off,
                                                 const uint32_t* __restrict__ m2p_src, int KP,
@@ -370,34 +374,98 @@ __global__ __launch_bounds__(64) void k_far_m2p(const float4* __restrict__ pts, 
                                                 int out_dtype, void* __restrict__ ophi, void* __restrict__ oex,
                                                 void* __restrict__ oey, void* __restrict__ oez) {
     constexpr int K = (P + 1) * (P + 1);
-    __shared__ float Ms[K];
-    if (!m2pflag[blockIdx.x]) return;
-    const int cell = leaves[blockIdx.x];
-    const int32_t b = c.begin[cell], e = c.end[cell];
+    constexpr int MAXD = kMaxLevel + 1;  // a leaf and its ancestors
+    __shared__ LeafPack<LPW> lp;
+    __shared__ int32_t anc[LPW][MAXD];   // anc[q][k]: k-th ancestor of leaf q, -1 above the root
+    __shared__ int32_t chain[LPW];
+    __shared__ int32_t own[LPW];         // owner index of leaf q at the current depth, -1 if none
+    __shared__ int32_t dcell[LPW], dlen[LPW], doff[LPW];
+    __shared__ int32_t s_nd, s_steps, s_depth;
+    __shared__ float Ms[LPW][K];
+    __shared__ double4 sctr[LPW];
+    const int lane = threadIdx.x;
+    if (lane < LPW) {
+        const int32_t l = (int32_t)blockIdx.x * LPW + lane;
+        const bool flagged = l < nleaves && m2pflag[l];
+        lp.load_lane(c, leaves, nleaves, lane);
+        if (!flagged) lp.cnt[lane] = 0;  // its particles are final already
+        int d = 0;
+        if (flagged)
+            for (int A = lp.cell[lane]; A >= 0 && d < MAXD; A = c.parent[A]) anc[lane][d++] = A;
+        chain[lane] = d;
+        for (int k = d; k < MAXD; k++) anc[lane][k] = -1;
+    }
+    __syncthreads();
+    if (lane == 0) {
+        lp.finish(nleaves);
+        int dm = 0;
+        for (int q = 0; q < LPW; q++) dm = max(dm, chain[q]);
+        s_depth = dm;
+    }
+    __syncthreads();
+    const int total = lp.pre[LPW];
+    if (total == 0) return;
     const float s2 = 1.41421356237309505f;
-    for (int32_t ch = b; ch < e; ch += 64) {
-        const int32_t i = ch + threadIdx.x;
-        const bool valid = i < e;
-        const float4 Pt = pts[valid ? i : b];
+    for (int r0 = 0; r0 < total; r0 += 64) {
+        const int f = r0 + lane;
+        const bool valid = f < total;
+        const int q = valid ? lp.leaf_of(f) : 0;
+        const int32_t i = lp.beg[q] + (f - lp.pre[q]);
+        const float4 Pt = pts[valid ? i : lp.beg[q]];
         double4 acc = valid ? near[i] : make_double4(0, 0, 0, 0);
-        for (int A = cell; A >= 0; A = c.parent[A]) {
-            for (int32_t a = m2p_off[A]; a < m2p_off[A + 1]; a++) {
-                const int s = (int)m2p_src[a];
-                const double4 cs = c.ctr[s];
-                __syncthreads();
-                for (int u = threadIdx.x; u < K; u += 64) Ms[u] = M[(size_t)s * KP + u];
-                __syncthreads();
-                const double ir = 1.0 / cs.w;
-                const float x = (float)(((double)Pt.x - cs.x) * ir), y = (float)(((double)Pt.y - cs.y) * ir),
-                            z = (float)(((double)Pt.z - cs.z) * ir);
-                float phi = 0.f, l10 = 0.f, l1re = 0.f, l1im = 0.f;
-                m2p_point<P>(Ms, hm2p, x, y, z, rc, phi, l10, l1re, l1im);
-                const double r1 = cs.w, r2 = cs.w * cs.w;
-                acc.x += (double)phi / r1;
-                acc.y += (double)(-s2 * l1re) / r2;
-                acc.z += (double)(s2 * l1im) / r2;
-                acc.w += (double)(-l10) / r2;
+        for (int k = 0; k < s_depth; k++) {
+            if (lane == 0) {
+                // leaves with particles in this round, in leaf order; equal
+                // owners are adjacent (leaves follow the tree order)
+                int nd = 0, steps = 0;
+                for (int qq = 0; qq < LPW; qq++) {
+                    own[qq] = -1;
+                    const bool in_round = lp.cnt[qq] > 0 && lp.pre[qq] < r0 + 64 && lp.pre[qq + 1] > r0;
+                    const int32_t A = in_round ? anc[qq][k] : -1;
+                    if (A < 0) continue;
+                    const int32_t len = m2p_off[A + 1] - m2p_off[A];
+                    if (len == 0) continue;
+                    if (nd == 0 || dcell[nd - 1] != A) {
+                        dcell[nd] = A;
+                        dlen[nd] = len;
+                        doff[nd] = m2p_off[A];
+                        steps = max(steps, len);
+                        nd++;
+                    }
+                    own[qq] = nd - 1;
+                }
+                s_nd = nd;
+                s_steps = steps;
             }
+            __syncthreads();
+            const int nd = s_nd, steps = s_steps;
+            const int o = valid ? own[q] : -1;
+            for (int t = 0; t < steps; t++) {
+                for (int u = lane; u < nd * K; u += 64) {
+                    const int d = u / K, kk = u - d * K;
+                    if (t < dlen[d]) {
+                        const int s = (int)m2p_src[doff[d] + t];
+                        Ms[d][kk] = M[(size_t)s * KP + kk];
+                        if (kk == 0) sctr[d] = c.ctr[s];
+                    }
+                }
+                __syncthreads();
+                if (o >= 0 && t < dlen[o]) {
+                    const double4 cs = sctr[o];
+                    const double ir = 1.0 / cs.w;
+                    const float x = (float)(((double)Pt.x - cs.x) * ir), y = (float)(((double)Pt.y - cs.y) * ir),
+                                z = (float)(((double)Pt.z - cs.z) * ir);
+                    float phi = 0.f, l10 = 0.f, l1re = 0.f, l1im = 0.f;
+                    m2p_point<P>(Ms[o], hm2p, x, y, z, rc, phi, l10, l1re, l1im);
+                    const double r1 = cs.w, r2 = cs.w * cs.w;
+                    acc.x += (double)phi / r1;
+                    acc.y += (double)(-s2 * l1re) / r2;
+                    acc.z += (double)(s2 * l1im) / r2;
+                    acc.w += (double)(-l10) / r2;
+                }
+                __syncthreads();
+            }
+            __syncthreads();  // own[] and the owner tables are rewritten for the next depth
         }
         if (valid) {
             const uint32_t o = perm[i];
@@ -417,6 +485,7 @@ __global__ __launch_bounds__(64) void k_far_m2p(const float4* __restrict__ pts, 
 }
 
 constexpr int kLeavesPerWave = 8;
+constexpr int kM2pLeavesPerWave = 16;
 
 template <int P>
 void launch_far(const float4* pts, const uint32_t* perm, CellArrays cells, const int32_t* leaves, int32_t nleaves,
@@ -427,9 +496,12 @@ void launch_far(const float4* pts, const uint32_t* perm, CellArrays cells, const
     constexpr int W = kLeavesPerWave;
     k_far<P, W><<<(nleaves + W - 1) / W, 64, 0, s>>>(pts, perm, cells, leaves, nleaves, m2pflag, m2p_off, m2p_src, KP,
                                                      t.gl2p, t.hm2p, t.rcoef, M, L, near, out_dtype, phi, ex, ey, ez);
-    if (any_m2p)
-        k_far_m2p<P><<<nleaves, 64, 0, s>>>(pts, perm, cells, leaves, m2pflag, m2p_off, m2p_src, KP, t.hm2p, t.rcoef, M,
-                                            near, out_dtype, phi, ex, ey, ez);
+    if (any_m2p) {
+        constexpr int W2 = kM2pLeavesPerWave;
+        k_far_m2p<P, W2><<<(nleaves + W2 - 1) / W2, 64, 0, s>>>(pts, perm, cells, leaves, nleaves, m2pflag, m2p_off,
+                                                               m2p_src, KP, t.hm2p, t.rcoef, M, near, out_dtype, phi,
+                                                               ex, ey, ez);
+    }
 }
 
 template <int P>

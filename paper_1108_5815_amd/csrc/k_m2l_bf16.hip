@@ -268,11 +268,12 @@ __global__ void k_split_cells(const float4* __restrict__ M, int64_t ncell, int K
 
 void m2l_gemm_bf16(const uint16_t* Thi, const uint16_t* Tlo, const int32_t* offid, const int32_t* gather,
                    const uint32_t* rowcell, GemmPlan plan, int p, int KP, const float* M, int64_t ncell, uint4* Ms,
-                   float* part, float* L, hipStream_t s) {
+                   float* part, float* L, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     if (plan.ntiles <= 0) return;
     const int KB = KP / 8;
     const int64_t nb = (ncell + 1) * KB;  // with the zero row
     k_split_cells<<<(unsigned)((nb + 255) / 256), 256, 0, s>>>((const float4*)M, ncell + 1, KB, Ms);
+    if (e0) (void)hipEventRecord(e0, s);
     switch (KP) {
         case 32: launch<32, 128, 1, 4, 2>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
         case 64: launch<64, 128, 2, 2, 2>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
@@ -281,6 +282,7 @@ void m2l_gemm_bf16(const uint16_t* Thi, const uint16_t* Tlo, const int32_t* offi
         case 192: launch<192, 64, 2, 2, 4>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
         default: return;
     }
+    if (e1) (void)hipEventRecord(e1, s);
     m2l_reduce_groups(part, plan, rowcell, KP, ncoef(p), L, s);
 }
 

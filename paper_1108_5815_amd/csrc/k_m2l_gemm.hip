@@ -285,8 +285,9 @@ void m2l_reduce_groups(const float* part, GemmPlan plan, const uint32_t* rowcell
 }
 
 void m2l_gemm(const float* T, const int32_t* offid, const int32_t* gather, const uint32_t* rowcell, GemmPlan plan,
-              int p, int KP, const float* M, float* part, float* L, hipStream_t s) {
+              int p, int KP, const float* M, float* part, float* L, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     if (plan.ntiles <= 0) return;
+    if (e0) (void)hipEventRecord(e0, s);
     switch (KP) {
         case 32: launch<32, 128, 1, 4, 16>(T, offid, gather, plan, M, part, s); break;
         case 64: launch<64, 128, 2, 2, 16>(T, offid, gather, plan, M, part, s); break;
@@ -296,6 +297,7 @@ void m2l_gemm(const float* T, const int32_t* offid, const int32_t* gather, const
         case 256: launch<256, 64, 4, 1, 8>(T, offid, gather, plan, M, part, s); break;
         default: return;
     }
+    if (e1) (void)hipEventRecord(e1, s);
     m2l_reduce_groups(part, plan, rowcell, KP, ncoef(p), L, s);
 }
 

@@ -137,6 +137,60 @@ def test_values_p10_plummer_adaptive(theta):
     assert ora.rel_l2(phi, po) < 1e-5 and ora.rel_l2(E, Eo) < 1e-4
 
 
+@pytest.mark.parametrize("p", [13, 16])
+def test_values_high_order(p):
+    """Orders above the split-BF16 range: p = 13 runs the FP32 GEMM at storage
+    width 256; p = 16 (storage 320, no matrix-core tiling) sends every M2L
+    pair through the per-pair kernel."""
+    n = 8000
+    x, y, z = (as_input(a, torch.float32) for a in synth.plummer(n, 17))
+    q = as_input(synth.charges_uniform(n, 117), torch.float32)
+    f, phi, E = gpu_run(x, y, z, q, p, 0.5, 32)
+    batched, general = f.m2l_split()
+    if p == 16:
+        assert batched == 0 and general > 0
+    else:
+        assert batched > 0
+    po, Eo, _ = ora.fmm(x, y, z, q, p, 0.5, 32)
+    assert ora.rel_l2(phi, po) < 1e-5 and ora.rel_l2(E, Eo) < 1e-4
+
+
+def deep_pair_set(seed=71, n=3000, ncl=3000, delta=1e-3, side=2e-5):
+    """A uniform set in [0, 1]^3 (corners included, so the cube is exact) with
+    the cell [0, 1/4)^3 thinned to a leaf, and a tight cluster just beyond the
+    acceptance distance of that leaf at theta = 0.5: the leaf meets the
+    cluster's cells only after about ten more splits of the cluster side, so
+    the M2L list holds pairs whose levels differ by more than 8."""
+    x, y, z = synth.uniform_cube(n, seed)
+    u = synth.uniform_cube(ncl, seed + 1)
+    gx = 0.375 + 0.25 * delta + side * (u[0] - 0.5)
+    gy = 0.125 + side * (u[1] - 0.5)
+    gz = 0.125 + side * (u[2] - 0.5)
+    keep = ~((x < 0.25) & (y < 0.25) & (z < 0.25)) | (np.arange(n) % 8 == 0)
+    X = np.concatenate([x[keep], [0.0, 1.0], gx])
+    Y = np.concatenate([y[keep], [0.0, 1.0], gy])
+    Z = np.concatenate([z[keep], [0.0, 1.0], gz])
+    return X, Y, Z
+
+
+def test_m2l_pairs_beyond_the_class_key():
+    """Cell-cell pairs whose level difference exceeds 8 do not fit the class
+    key of the batched mixed-level path and take the per-pair kernel: lists
+    bit-exact and values against the oracle's FMM on the same lists."""
+    x, y, z = (as_input(a, torch.float32) for a in deep_pair_set())
+    n = x.size
+    q = as_input(synth.charges_uniform(n, 171), torch.float32)
+    f, phi, E = gpu_run(x, y, z, q, 10, 0.5, 64)
+    po, Eo, tr = ora.fmm(x, y, z, q, 10, 0.5, 64)
+    c = tr.cells()
+    a, b = tr.lists()[0]
+    d = np.abs(c["level"][a] - c["level"][b])
+    assert (d > 8).sum() > 50
+    tg, sg = f.list(0)
+    assert np.array_equal(canon(tg, sg), canon(a, b))
+    assert ora.rel_l2(phi, po) < 1e-5 and ora.rel_l2(E, Eo) < 1e-4
+
+
 def to_real_scaled(C, p, r, sign):
     """oracle complex coefficients -> library real layout, scaled by r^(sign*n + (sign>0))"""
     K = (p + 1) ** 2
