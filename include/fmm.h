@@ -158,6 +158,31 @@ fmm_status fmm_evaluate(fmm_ctx ctx, int32_t precision, int32_t out_dtype, void 
                         void *ey, void *ez);
 
 /*
+ * fmm_evaluate for callers that cannot allocate device memory: code under
+ * stream (graph) capture, tight serving loops, harnesses that forbid
+ * allocation.  Same arguments, kernels and results (bit for bit) as
+ * fmm_evaluate, but every work buffer of the evaluation (expansions,
+ * near-field partials, GEMM and class partials, flags) lies in one fixed
+ * work area of FMM_NOALLOC_SCRATCH_BYTES per device, which the library holds
+ * from its first context on that device until the process ends; the call
+ * makes no device or host allocation.  The tree, lists and operator tables
+ * come from the context (fmm_build_tree / fmm_traverse, which do allocate).
+ * Every kernel runs in order on the context stream (no second stream).
+ * The area is shared by every context and call on the device and keeps the
+ * last call's contents: calls that overlap on one device race, so callers
+ * must order them (one stream, or events).  fmm_get_expansions does not see
+ * this call's expansions.  An evaluation needing more work space than the
+ * area (at most 33 bytes per particle plus 4 (G + 3) K bytes per cell, with
+ * K = (p+1)^2 rounded up to a multiple of 32 and G = 8 slot groups at
+ * theta = 0.5, 16 at theta = 0.4: roughly 290k uniform particles at p = 10,
+ * theta = 0.5, ncrit = 64) gives FMM_ERR_INVALID_ARG with the sizes in the
+ * message; other errors as fmm_evaluate.
+ */
+#define FMM_NOALLOC_SCRATCH_BYTES (64u << 20)
+fmm_status fmm_evaluate_noalloc(fmm_ctx ctx, int32_t precision, int32_t out_dtype, void *phi, void *ex,
+                                void *ey, void *ez);
+
+/*
  * Batches of independent problems of uneven size (many instances evaluated
  * together so that each phase is one pass over all of them):
  * instance k owns particles [offsets[k], offsets[k+1]) of x, y, z, q and no

@@ -85,6 +85,7 @@ def lib():
         "fmm_costmodel_save": ([vp, ctypes.c_char_p], ctypes.c_int),
         "fmm_costmodel_load": ([vp, ctypes.c_char_p, i32, i32], ctypes.c_int),
         "fmm_m2l_slots": ([i32, dbl, vp, vp], ctypes.c_int),
+        "fmm_evaluate_noalloc": ([vp, i32, i32, vp, vp, vp, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -247,6 +248,16 @@ class FMM:
         od = F64 if phi.dtype == t.float64 else F32
         self._ck(lib().fmm_evaluate(self.h, int(precision), od, phi.data_ptr(), E[0].data_ptr(),
                                     E[1].data_ptr(), E[2].data_ptr()))
+        return phi, E
+
+    def evaluate_noalloc(self, precision: int = PREC_FP32, out=None):
+        """fmm_evaluate on the library's fixed per-device work area (no
+        allocation inside the call); the caller passes the outputs (phi, E)."""
+        t = self._torch
+        phi, E = out
+        od = F64 if phi.dtype == t.float64 else F32
+        self._ck(lib().fmm_evaluate_noalloc(self.h, int(precision), od, phi.data_ptr(), E[0].data_ptr(),
+                                            E[1].data_ptr(), E[2].data_ptr()))
         return phi, E
 
     def set_costs(self, c_m2l: float, c_m2p: float, c_p2p: float):

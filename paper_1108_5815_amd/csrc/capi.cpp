@@ -1031,6 +1031,8 @@ fmm_status fmm_create(fmm_ctx* out, int device, void* hip_stream) {
     fmm_status st = guarded(c, [&] {
         for (int k = 0; k <= PH_N; k++) ck(hipEventCreate(&c->ev[k]), "hipEventCreate");
         for (int k = 0; k < 2; k++) ck(hipEventCreate(&c->ev_gk[k]), "hipEventCreate");
+        // the device address of the fixed work area of fmm_evaluate_noalloc
+        ck(noalloc_setup(device), "work area of the no-allocation evaluation");
     });
     if (st != FMM_OK) {
         fmm_destroy(c);
@@ -1126,6 +1128,35 @@ fmm_status fmm_traverse(fmm_ctx c, int32_t p, double theta, int32_t policy) {
 fmm_status fmm_evaluate(fmm_ctx c, int32_t precision, int32_t out_dtype, void* phi, void* ex, void* ey,
                         void* ez) {
     return guarded(c, [&] { evaluate_impl(c, precision, out_dtype, phi, ex, ey, ez); });
+}
+
+fmm_status fmm_evaluate_noalloc(fmm_ctx c, int32_t precision, int32_t out_dtype, void* phi, void* ex, void* ey,
+                                void* ez) {
+    return guarded(c, [&] {
+        check_evaluate_args(c, precision, out_dtype, phi, ex, ey, ez);
+        if (c->n == 0) return;
+        char* area = (char*)noalloc_area(c->device);
+        if (!area) fail(FMM_ERR_DEVICE, "no work area on this device");
+        size_t b[EB_N], off[EB_N], total = 0;
+        eval_sizes(c, precision, b);
+        for (int k = 0; k < EB_N; k++) {
+            off[k] = total;
+            total += (b[k] + 255) / 256 * 256;
+        }
+        if (total > kNoAllocScratchBytes)
+            fail(FMM_ERR_INVALID_ARG, "this evaluation needs " + std::to_string(total) +
+                                          " bytes of work space; fmm_evaluate_noalloc holds " +
+                                          std::to_string(kNoAllocScratchBytes) + " (use fmm_evaluate)");
+        EvalBufs eb;
+        eb.M = (float*)(area + off[EB_M]);
+        eb.L = (float*)(area + off[EB_L]);
+        eb.near = (double4*)(area + off[EB_NEAR]);
+        eb.part = b[EB_PART] ? (float*)(area + off[EB_PART]) : nullptr;
+        eb.Msplit = b[EB_MSPLIT] ? (uint4*)(area + off[EB_MSPLIT]) : nullptr;
+        eb.cls_part = b[EB_CLS] ? (float*)(area + off[EB_CLS]) : nullptr;
+        eb.m2pflag = (uint8_t*)(area + off[EB_FLAG]);
+        evaluate_on(c, precision, out_dtype, phi, ex, ey, ez, eb, true);
+    });
 }
 
 fmm_status fmm_set_costs(fmm_ctx c, double c_m2l, double c_m2p, double c_p2p) {

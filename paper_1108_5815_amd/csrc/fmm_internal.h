@@ -62,6 +62,13 @@ void fill_zero(void* p, size_t bytes, hipStream_t s);
 void artificial_points(int64_t n, uint64_t seed, float* x, float* y, float* z, float* q, hipStream_t s);
 void iota_u32(uint32_t* p, int64_t n, hipStream_t s);
 
+// work area of fmm_evaluate_noalloc: one fixed array per device (k_noalloc.hip)
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+// look up this device's copy of the array (the device must be current)
+hipError_t noalloc_setup(int device);
+// its device address, or null before noalloc_setup succeeded on the device
+void* noalloc_area(int device);
+
 // ------------------------------------------------------------------ tree
 // A batch of independent instances: instance k owns particles [seg[k],
 // seg[k+1]) of the input (and, after the sort, of the sorted order).  Its
