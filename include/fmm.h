@@ -74,6 +74,21 @@ typedef enum {
 
 typedef enum { FMM_F32 = 0, FMM_F64 = 1 } fmm_dtype;
 
+/* Expansion family of the far field (paper: "Hybrid treecode/FMM
+ * algorithm": spherical-harmonic kernels with the ability to switch to
+ * Cartesian expansions when the required accuracy is low; "Introduction to
+ * treecodes & FMM": treecodes use Taylor series in Cartesian coordinates,
+ * typically p = 3).  Spherical: Greengard-Rokhlin harmonics, (p+1)^2
+ * coefficients, any p <= FMM_P_MAX.  Cartesian: Taylor coefficients of
+ * 1/|x - y| in multi-indices |k| <= p, (p+1)(p+2)(p+3)/6 coefficients,
+ * p <= 6, M2L truncated at |m| + |k| <= p.  Auto: Cartesian for the orders
+ * up to a given one (the low-accuracy range), spherical above. */
+typedef enum {
+    FMM_EXPANSION_SPHERICAL = 0,
+    FMM_EXPANSION_CARTESIAN = 1,
+    FMM_EXPANSION_AUTO = 2
+} fmm_expansion;
+
 enum { FMM_LIST_M2L = 0, FMM_LIST_M2P = 1, FMM_LIST_P2P = 2 };
 
 /* Largest supported expansion order. */
@@ -127,6 +142,30 @@ fmm_status fmm_set_allocator(fmm_ctx ctx, fmm_alloc_fn alloc, fmm_free_fn free_f
  */
 fmm_status fmm_build_tree(fmm_ctx ctx, int64_t n, int dtype, const void *x, const void *y,
                           const void *z, const void *q, int32_t ncrit);
+
+/*
+ * Targets that differ from the sources (paper: "Dual tree traversal": the
+ * traversal pairs a target tree with a source tree, and the method also
+ * handles targets and sources that are not the same particles).  Builds a
+ * target tree over (tx, ty, tz) and a source tree over (sx, sy, sz) with
+ * charges q, both inside one bounding cube (that of all the points, as
+ * fmm_build_tree would give it), each sorted and split as fmm_build_tree
+ * does.  fmm_traverse then starts from the pair (target root, source root),
+ * so every list pairs a target-tree cell with a source-tree cell, and
+ * fmm_evaluate writes the potential and field at the n_targets targets due to
+ * all sources (a source at the same point as a target is skipped).
+ *   n_targets, n_sources  >= 0, sum < 2^31 (either may be 0)
+ *   tx, ty, tz            device arrays of n_targets values
+ *   sx, sy, sz, q         device arrays of n_sources values
+ * Copies the inputs into the context (they may be reused once the stream
+ * has passed the call).  Introspection reports the two trees as a forest:
+ * the target root is cell 0 and the source root cell 1 (when both sets are
+ * non-empty); keys and permutation cover the targets then the sources.
+ * Errors as fmm_build_tree.
+ */
+fmm_status fmm_build_tree_ts(fmm_ctx ctx, int dtype, int64_t n_targets, const void *tx, const void *ty,
+                             const void *tz, int64_t n_sources, const void *sx, const void *sy, const void *sz,
+                             const void *q, int32_t ncrit);
 
 /*
  * Dual tree traversal (paper: "Dual tree traversal"; "Results" for the
@@ -207,6 +246,20 @@ fmm_status fmm_evaluate_batch(fmm_ctx ctx, int32_t n_inst, const int64_t *offset
                               const void *x, const void *y, const void *z, const void *q, int32_t ncrit,
                               int32_t p, double theta, int32_t policy, int32_t precision, int32_t out_dtype,
                               void *phi, void *ex, void *ey, void *ez);
+
+/*
+ * Expansion family of the following traversals (and their evaluations):
+ * FMM_EXPANSION_SPHERICAL (the default), FMM_EXPANSION_CARTESIAN (then
+ * fmm_traverse gives FMM_ERR_UNSUPPORTED for p > 6), or FMM_EXPANSION_AUTO,
+ * which takes the Cartesian family when p <= auto_cartesian_max_p (in
+ * [-1, 6]; -1 never; ignored for the other two) and the spherical one
+ * otherwise.  The family is fixed at fmm_traverse; fmm_get_expansion
+ * reports the family of the last traversal.  Both families give the method
+ * its usual accuracy at a given (p, theta); the Cartesian M2L truncation
+ * (|m| + |k| <= p) is somewhat looser than the spherical one.
+ */
+fmm_status fmm_set_expansion(fmm_ctx ctx, int32_t expansion, int32_t auto_cartesian_max_p);
+fmm_status fmm_get_expansion(fmm_ctx ctx, int32_t *family);
 
 /*
  * Unit costs of the timed hybrid (paper: "Kernel pre-calculation"): the
@@ -355,7 +408,11 @@ fmm_status fmm_get_list(fmm_ctx ctx, int32_t kind, int32_t *tgt_host, int32_t *s
 /* Scaled expansions after fmm_evaluate: per cell (p+1)^2 reals, degree n at
  * offset n*n as [Re c_n^0, Re c_n^1, Im c_n^1, ..., Re c_n^n, Im c_n^n], in
  * the Greengard-Rokhlin normalisation, multipoles divided by r^n and locals
- * multiplied by r^(n+1) (r = cell half side).  Host arrays n_cells*(p+1)^2. */
+ * multiplied by r^(n+1) (r = cell half side).  Host arrays n_cells*(p+1)^2.
+ * Cartesian family: per cell (p+1)(p+2)(p+3)/6 reals, multi-index
+ * (k1, k2, k3) at n(n+1)(n+2)/6 + (n-k1)(n-k1+1)/2 + k3 (n = |k|), the
+ * multipole M_k = sum q (s - x)^k divided by r^|k| and the local L_m (phi =
+ * sum L_m (x - t)^m) multiplied by r^(|m|+1). */
 fmm_status fmm_get_expansions(fmm_ctx ctx, float *multipole_host, float *local_host);
 
 /* Milliseconds of the phases of the last build/traverse/evaluate (recorded

@@ -52,6 +52,8 @@ def lib():
         vp = ctypes.c_void_p
         L.ora_build.restype = vp
         L.ora_build.argtypes = [I64, vp, vp, vp, ctypes.c_int32]
+        L.ora_build_ts.restype = vp
+        L.ora_build_ts.argtypes = [I64, vp, vp, vp, I64, ctypes.c_int32]
         L.ora_ncells.restype = I64
         L.ora_ncells.argtypes = [vp]
         L.ora_list_size.restype = I64
@@ -85,6 +87,19 @@ def lib():
         L.ora_mlp_forward.argtypes = [vp, vp, vp]
         L.ora_mlp_loss_grad.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp, vp]
         L.ora_mlp_table64.argtypes = [vp, ctypes.c_int, ctypes.c_double, vp, vp, vp]
+        L.ora_cart_count.restype = ctypes.c_int
+        L.ora_cart_count.argtypes = [ctypes.c_int]
+        L.ora_cart_index.restype = ctypes.c_int
+        L.ora_cart_index.argtypes = [ctypes.c_int] * 3
+        L.ora_cart_taylor.argtypes = [ctypes.c_int, vp, vp]
+        L.ora_cart_p2m.argtypes = [ctypes.c_int, vp, I64, vp, vp, vp, vp, vp]
+        L.ora_cart_m2m.argtypes = [ctypes.c_int, vp, vp, vp]
+        L.ora_cart_m2l.argtypes = [ctypes.c_int, vp, vp, vp]
+        L.ora_cart_l2l.argtypes = [ctypes.c_int, vp, vp, vp]
+        L.ora_cart_l2p.argtypes = [ctypes.c_int, vp, vp, vp, vp, vp]
+        L.ora_cart_m2p.argtypes = [ctypes.c_int, vp, vp, vp, vp, vp]
+        L.ora_evaluate_cart.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp, vp]
+        L.ora_get_expansions_cart.argtypes = [vp, vp, vp]
         L.ora_interleave.restype = ctypes.c_uint64
         L.ora_interleave.argtypes = [ctypes.c_uint64] * 3
         _lib = L
@@ -227,17 +242,92 @@ def local_series(p, L, centre, x) -> float:
     return float(lib().ora_local_series(p, _p(L), _p(_f64(centre)), _p(_f64(x))))
 
 
+# ---------------------------------------------------------------- Cartesian expansions
+def cart_count(p: int) -> int:
+    """Coefficients of a Cartesian expansion of order p: multi-indices |k| <= p."""
+    return int(lib().ora_cart_count(int(p)))
+
+
+def cart_index(a: int, b: int, c: int) -> int:
+    """Position of multi-index (a, b, c) in the graded order."""
+    return int(lib().ora_cart_index(int(a), int(b), int(c)))
+
+
+def cart_taylor(P: int, R) -> np.ndarray:
+    """a_n(R) = (1/n!) d^n (1/|R|) for |n| <= P."""
+    a = np.zeros(cart_count(P))
+    lib().ora_cart_taylor(int(P), _p(_f64(R)), _p(a))
+    return a
+
+
+def cart_p2m(p, centre, xyz, q):
+    xyz = np.asarray(xyz, dtype=np.float64)
+    x, y, z = (_f64(xyz[:, d]) for d in range(3))
+    M = np.zeros(cart_count(p))
+    lib().ora_cart_p2m(int(p), _p(_f64(centre)), x.size, _p(x), _p(y), _p(z), _p(_f64(q)), _p(M))
+    return M
+
+
+def cart_m2m(p, M, d):
+    """M re-centred by d = new centre - old centre."""
+    out = np.zeros(cart_count(p))
+    lib().ora_cart_m2m(int(p), _p(_f64(M)), _p(_f64(d)), _p(out))
+    return out
+
+
+def cart_m2l(p, M, R):
+    """Local about t of the multipole M about s, R = t - s."""
+    out = np.zeros(cart_count(p))
+    lib().ora_cart_m2l(int(p), _p(_f64(M)), _p(_f64(R)), _p(out))
+    return out
+
+
+def cart_l2l(p, L, d):
+    """L re-centred by d = new centre - old centre."""
+    out = np.zeros(cart_count(p))
+    lib().ora_cart_l2l(int(p), _p(_f64(L)), _p(_f64(d)), _p(out))
+    return out
+
+
+def cart_l2p(p, L, centre, x):
+    phi = np.zeros(1)
+    e = np.zeros(3)
+    lib().ora_cart_l2p(int(p), _p(_f64(L)), _p(_f64(centre)), _p(_f64(x)), _p(phi), _p(e))
+    return float(phi[0]), e
+
+
+def cart_m2p(p, M, centre, x):
+    phi = np.zeros(1)
+    e = np.zeros(3)
+    lib().ora_cart_m2p(int(p), _p(_f64(M)), _p(_f64(centre)), _p(_f64(x)), _p(phi), _p(e))
+    return float(phi[0]), e
+
+
 # ---------------------------------------------------------------- full method
 class Tree:
     """Tree, lists and evaluation of one particle set (handle over the C oracle)."""
 
-    def __init__(self, x, y, z, ncrit: int):
+    def __init__(self, x, y, z, ncrit: int, n_targets: int = -1):
+        """One set (n_targets = -1), or targets = the first n_targets points
+        and sources = the rest, as two trees in one cube."""
         self.x, self.y, self.z = map(_f64, (x, y, z))
         self.n = self.x.size
         self.ncrit = int(ncrit)
-        self.h = lib().ora_build(self.n, _p(self.x), _p(self.y), _p(self.z), self.ncrit)
+        self.nt = int(n_targets)
+        if self.nt < 0:
+            self.h = lib().ora_build(self.n, _p(self.x), _p(self.y), _p(self.z), self.ncrit)
+        else:
+            self.h = lib().ora_build_ts(self.n, _p(self.x), _p(self.y), _p(self.z), self.nt, self.ncrit)
         self.ncell = int(lib().ora_ncells(self.h))
         self.p = None
+
+    @classmethod
+    def targets_sources(cls, targets, sources, ncrit: int):
+        """Trees of distinct target and source points (each an (n, 3) array)."""
+        t = np.asarray(targets, np.float64).reshape(-1, 3)
+        s = np.asarray(sources, np.float64).reshape(-1, 3)
+        a = np.concatenate([t, s])
+        return cls(a[:, 0], a[:, 1], a[:, 2], ncrit, n_targets=t.shape[0])
 
     def __del__(self):
         h = getattr(self, "h", None)
@@ -290,11 +380,32 @@ class Tree:
         return out
 
     def evaluate(self, p: int, q):
+        """(phi, E) of every particle; with separate sets q holds the sources'
+        charges and the result is the targets'."""
         q = _f64(q)
-        phi, ex, ey, ez = (np.zeros(self.n) for _ in range(4))
+        nout = self.n if self.nt < 0 else self.nt
+        phi, ex, ey, ez = (np.zeros(nout) for _ in range(4))
         lib().ora_evaluate(self.h, int(p), _p(q), _p(phi), _p(ex), _p(ey), _p(ez))
         self.p = int(p)
         return phi, np.stack([ex, ey, ez], axis=1)
+
+    def evaluate_cart(self, p: int, q):
+        """As evaluate, with Cartesian (Taylor) expansions of order p."""
+        q = _f64(q)
+        nout = self.n if self.nt < 0 else self.nt
+        phi, ex, ey, ez = (np.zeros(nout) for _ in range(4))
+        lib().ora_evaluate_cart(self.h, int(p), _p(q), _p(phi), _p(ex), _p(ey), _p(ez))
+        self.pc = int(p)
+        return phi, np.stack([ex, ey, ez], axis=1)
+
+    def expansions_cart(self):
+        """Cartesian multipoles M_k = sum q (s - x)^k and locals of every cell
+        (graded order, cart_index) after evaluate_cart."""
+        K = cart_count(self.pc)
+        M = np.zeros(self.ncell * K)
+        L = np.zeros(self.ncell * K)
+        lib().ora_get_expansions_cart(self.h, _p(M), _p(L))
+        return M.reshape(self.ncell, K), L.reshape(self.ncell, K)
 
     def expansions(self):
         K = ncoef(self.p)

@@ -22,7 +22,11 @@
  *  - spherical-harmonic multipole and local expansions and their translations
  *    ("Hybrid treecode/FMM algorithm"; "Results": all methods use spherical
  *    harmonics).  The paper prints no formulas; the expansions follow
- *    Greengard & Rokhlin, Acta Numerica 6 (1997), theorems 3.2-3.5.
+ *    Greengard & Rokhlin, Acta Numerica 6 (1997), theorems 3.2-3.5;
+ *  - Cartesian (Taylor) expansions, the family the hybrid switches to at low
+ *    accuracy ("Hybrid treecode/FMM algorithm"), on the same tree and lists;
+ *  - targets that differ from the sources: a target tree and a source tree
+ *    in one cube, traversed as a pair ("Dual tree traversal").
  *
  * Readings taken where the paper is silent are listed in the design notes
  * and repeated at each function.  Every floating-point value is IEEE FP64;
@@ -176,11 +180,12 @@ void ora_morton(int64_t n, const double *x, const double *y, const double *z,
 /* ------------------------------------------------------------------ */
 /* Sort: ascending by (key, original index).                           */
 /* ------------------------------------------------------------------ */
-typedef struct { uint64_t key; int64_t idx; } kv_t;
+typedef struct { uint64_t key; int64_t idx; int seg; } kv_t;
 
 static int kv_cmp(const void *a, const void *b)
 {
     const kv_t *u = (const kv_t *)a, *v = (const kv_t *)b;
+    if (u->seg != v->seg) return u->seg < v->seg ? -1 : 1;
     if (u->key < v->key) return -1;
     if (u->key > v->key) return 1;
     return (u->idx < v->idx) ? -1 : (u->idx > v->idx);
@@ -206,6 +211,8 @@ enum { POL_FMM = 0, POL_TREECODE = 1, POL_HYBRID = 2 };
 
 typedef struct {
     int64_t n;
+    int64_t nt;       /* targets != sources: particles [0, nt) of the input are the targets, the rest the
+                         sources (two trees in one cube); -1 when targets and sources are the same set */
     double lo[3], side;
     uint64_t *skey;   /* sorted keys */
     int64_t *perm;    /* perm[k] = original index of the k-th sorted particle */
@@ -223,6 +230,9 @@ typedef struct {
     /* expansions after evaluate (full m = -n..n storage) */
     int p;
     cplx *M, *L;
+    /* Cartesian expansions after ora_evaluate_cart */
+    int pc;
+    double *Mc, *Lc;
 } ora_t;
 
 static void grow_cells(ora_t *h)
@@ -260,15 +270,16 @@ static void prefix_anchor(uint64_t prefix, int L, int64_t a[3])
  * octant order; a cell at level 21 never splits.  Cells are numbered in
  * breadth-first order, which is (level, key) order.
  */
-void *ora_build(int64_t n, const double *x, const double *y, const double *z, int32_t ncrit)
+static void *build_core(int64_t n, const double *x, const double *y, const double *z, int32_t ncrit, int64_t nt)
 {
     ora_t *h = (ora_t *)calloc(1, sizeof(ora_t));
     h->n = n;
+    h->nt = nt;
     ora_bbox(n, x, y, z, h->lo, &h->side);
     uint64_t *key = (uint64_t *)malloc((size_t)(n ? n : 1) * sizeof(uint64_t));
     ora_morton(n, x, y, z, h->lo, h->side, key);
     kv_t *kv = (kv_t *)malloc((size_t)(n ? n : 1) * sizeof(kv_t));
-    for (int64_t i = 0; i < n; i++) { kv[i].key = key[i]; kv[i].idx = i; }
+    for (int64_t i = 0; i < n; i++) { kv[i].key = key[i]; kv[i].idx = i; kv[i].seg = (nt >= 0 && i >= nt); }
     qsort(kv, (size_t)n, sizeof(kv_t), kv_cmp);
     h->skey = key;
     h->perm = (int64_t *)malloc((size_t)(n ? n : 1) * sizeof(int64_t));
@@ -283,11 +294,17 @@ void *ora_build(int64_t n, const double *x, const double *y, const double *z, in
     free(kv);
 
     h->ncell = 0;
-    if (n > 0) {
+    /* one root per non-empty set: the whole set, or the targets then the sources */
+    int64_t seg[3] = {0, nt >= 0 ? nt : n, n};
+    int nseg = nt >= 0 ? 2 : 1;
+    for (int g = 0; g < nseg; g++) {
+        if (seg[g + 1] == seg[g]) continue;
         grow_cells(h);
-        h->level[0] = 0; h->begin[0] = 0; h->end[0] = (int32_t)n; h->parent[0] = -1;
-        h->prefix[0] = 0; h->first_child[0] = -1; h->nchild[0] = 0;
-        h->ncell = 1;
+        int64_t r = h->ncell++;
+        h->level[r] = 0; h->begin[r] = (int32_t)seg[g]; h->end[r] = (int32_t)seg[g + 1]; h->parent[r] = -1;
+        h->prefix[r] = 0; h->first_child[r] = -1; h->nchild[r] = 0;
+    }
+    if (h->ncell > 0) {
         for (int64_t c = 0; c < h->ncell; c++) {
             int L = h->level[c];
             int32_t b = h->begin[c], e = h->end[c];
@@ -327,6 +344,24 @@ void *ora_build(int64_t n, const double *x, const double *y, const double *z, in
         h->rphys[c] = (double)r * (h->side / 4194304.0);
     }
     return h;
+}
+
+void *ora_build(int64_t n, const double *x, const double *y, const double *z, int32_t ncrit)
+{
+    return build_core(n, x, y, z, ncrit, -1);
+}
+
+/*
+ * Targets and sources that differ ("Dual tree traversal": the traversal pairs
+ * a target tree with a source tree): particles [0, nt) of x, y, z are the
+ * targets and [nt, n) the sources.  Both trees share one bounding cube (that
+ * of all points), so their cells compare geometrically; each set is sorted
+ * and split on its own (targets first), cell 0 is the target root and the
+ * next root the source root.
+ */
+void *ora_build_ts(int64_t n, const double *x, const double *y, const double *z, int64_t nt, int32_t ncrit)
+{
+    return build_core(n, x, y, z, ncrit, nt);
 }
 
 int64_t ora_ncells(void *hv) { return ((ora_t *)hv)->ncell; }
@@ -439,10 +474,16 @@ void ora_traverse(void *hv, double theta, int policy, const double *costs)
     if (h->ncell == 0) return;
     double theta2 = theta * theta;
     plist_t stack = {0, 0, 0};
-    /* the root pair is treated as a newly formed pair */
-    int c0 = classify(h, 0, 0, theta2);
-    if (c0 == C_P2P) pl_push(&h->list[K_P2P], 0, 0);
-    else if (c0 == C_SPLIT) pl_push(&stack, 0, 0);
+    /* the root pair (target root, source root) is treated as a newly formed
+     * pair; with separate sets it exists only when both are non-empty */
+    int32_t rt = 0, rs = 0;
+    if (h->nt >= 0) {
+        if (h->nt == 0 || h->nt == h->n) return;
+        rs = 1;
+    }
+    int c0 = classify(h, rt, rs, theta2);
+    if (c0 == C_P2P) pl_push(&h->list[K_P2P], rt, rs);
+    else if (c0 == C_SPLIT) pl_push(&stack, rt, rs);
     while (stack.n > 0) {
         pair_t pr = stack.v[--stack.n];
         int32_t T = pr.t, S = pr.s;
@@ -747,8 +788,15 @@ void ora_evaluate(void *hv, int p, const double *q, double *phi, double *ex, dou
     h->M = (cplx *)calloc((size_t)(nc ? nc : 1) * K, sizeof(cplx));
     h->L = (cplx *)calloc((size_t)(nc ? nc : 1) * K, sizeof(cplx));
     if (n == 0) return;
+    /* with separate sets, q holds the sources' charges (targets carry none)
+     * and the outputs are the targets' */
+    const int64_t nt = h->nt;
     double *sq = (double *)malloc((size_t)n * sizeof(double));
-    for (int64_t k = 0; k < n; k++) sq[k] = q[h->perm[k]];
+    for (int64_t k = 0; k < n; k++) {
+        int64_t o = h->perm[k];
+        sq[k] = nt < 0 ? q[o] : (o < nt ? 0.0 : q[o - nt]);
+    }
+    const int64_t nout = nt < 0 ? n : nt;  /* sorted positions [0, nout) are the targets */
 
     /* P2M at every leaf */
     int64_t c;
@@ -804,7 +852,7 @@ void ora_evaluate(void *hv, int p, const double *q, double *phi, double *ex, dou
             for (int32_t i = h->begin[c]; i < h->end[c]; i++) leaf[i] = (int32_t)c;
     int64_t i;
 #pragma omp parallel for schedule(dynamic, 64)
-    for (i = 0; i < n; i++) {
+    for (i = 0; i < nout; i++) {
         double xi[3] = {h->px[i], h->py[i], h->pz[i]};
         int32_t t = leaf[i];
         double ph, e[3];
@@ -846,6 +894,308 @@ void ora_get_expansions(void *hv, cplx *M, cplx *L)
     memcpy(L, h->L, (size_t)h->ncell * K * sizeof(cplx));
 }
 
+/* ------------------------------------------------------------------ */
+/* Cartesian (Taylor) expansions.  The paper's hybrid method can switch */
+/* from spherical harmonics to Cartesian expansions when the required  */
+/* accuracy is low ("Hybrid treecode/FMM algorithm"); treecodes use     */
+/* Taylor series in Cartesian coordinates ("Introduction to treecodes   */
+/* & FMM").  The paper gives no formulas; these are the plain Taylor    */
+/* expansions of 1/|x - y|:                                            */
+/*   a_n(R) = (1/n!) d^n/dR^n (1/|R|)   (multi-index n, n! = n1!n2!n3!) */
+/*   f(R + w) = sum_n a_n(R) w^n                                        */
+/* with, for |n| >= 1 (terms with a negative index dropped),            */
+/*   |R|^2 a_n = -((2|n|-1)/|n|) sum_i R_i a_{n-e_i}                   */
+/*              - ((|n|-1)/|n|) sum_i a_{n-2e_i},   a_0 = 1/|R|,       */
+/* the Taylor-coefficient recurrence of 1/|R| (cf. Duan & Krasny, J.    */
+/* Comput. Chem. 22 (2001); written here for derivatives in R).         */
+/* Multipole about centre s: M_k = sum_j q_j (s - x_j)^k, |k| <= p.    */
+/* Local about t: phi(t + u) = sum_m L_m u^m, |m| <= p, from           */
+/*   L_m = sum_{|m|+|k|<=p} C(m,k) a_{m+k}(t - s) M_k,                 */
+/*   C(m,k) = prod_i (m_i + k_i)! / (m_i! k_i!).                       */
+/* Coefficients are stored in graded order: degree n = 0..p, within a  */
+/* degree by k1 descending, then k2 descending.                        */
+/* ------------------------------------------------------------------ */
+int ora_cart_count(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
+
+int ora_cart_index(int a, int b, int c)
+{
+    int n = a + b + c;
+    return n * (n + 1) * (n + 2) / 6 + (n - a) * (n - a + 1) / 2 + (n - a - b);
+}
+
+static double rpow(double x, int e)
+{
+    double r = 1.0;
+    for (int i = 0; i < e; i++) r *= x;
+    return r;
+}
+
+static double binom_d(int n, int k)
+{
+    double r = 1.0;
+    for (int i = 1; i <= k; i++) r = r * (double)(n - k + i) / (double)i;
+    return r;
+}
+
+/* a_n(R) for |n| <= P into a[ora_cart_index(n)] */
+void ora_cart_taylor(int P, const double *R, double *a)
+{
+    double r2 = R[0] * R[0] + R[1] * R[1] + R[2] * R[2];
+    a[0] = 1.0 / sqrt(r2);
+    for (int n = 1; n <= P; n++)
+        for (int i = n; i >= 0; i--)
+            for (int j = n - i; j >= 0; j--) {
+                int k = n - i - j;
+                int e[3] = {i, j, k};
+                double s1 = 0.0, s2 = 0.0;
+                for (int d = 0; d < 3; d++) {
+                    if (e[d] >= 1) {
+                        e[d] -= 1;
+                        s1 += R[d] * a[ora_cart_index(e[0], e[1], e[2])];
+                        e[d] += 1;
+                    }
+                    if (e[d] >= 2) {
+                        e[d] -= 2;
+                        s2 += a[ora_cart_index(e[0], e[1], e[2])];
+                        e[d] += 2;
+                    }
+                }
+                a[ora_cart_index(i, j, k)] = -((2.0 * n - 1.0) / n * s1 + (n - 1.0) / n * s2) / r2;
+            }
+}
+
+/* P2M about c: M_k = sum_j q_j (c - x_j)^k */
+void ora_cart_p2m(int p, const double *c, int64_t n, const double *x, const double *y, const double *z,
+                  const double *q, double *M)
+{
+    int K = ora_cart_count(p);
+    for (int i = 0; i < K; i++) M[i] = 0.0;
+    for (int64_t j = 0; j < n; j++) {
+        double v[3] = {c[0] - x[j], c[1] - y[j], c[2] - z[j]};
+        for (int m = 0; m <= p; m++)
+            for (int a = m; a >= 0; a--)
+                for (int b = m - a; b >= 0; b--) {
+                    int cc = m - a - b;
+                    M[ora_cart_index(a, b, cc)] += q[j] * rpow(v[0], a) * rpow(v[1], b) * rpow(v[2], cc);
+                }
+    }
+}
+
+/* M2M: Mo (about s) re-centred at s' = s + d (d = new centre - old centre), added into Mn:
+ * Mn_k += sum_{a <= k} binom(k, a) Mo_a d^(k - a) */
+void ora_cart_m2m(int p, const double *Mo, const double *d, double *Mn)
+{
+    for (int n = 0; n <= p; n++)
+        for (int k1 = n; k1 >= 0; k1--)
+            for (int k2 = n - k1; k2 >= 0; k2--) {
+                int k3 = n - k1 - k2;
+                double s = 0.0;
+                for (int a1 = 0; a1 <= k1; a1++)
+                    for (int a2 = 0; a2 <= k2; a2++)
+                        for (int a3 = 0; a3 <= k3; a3++)
+                            s += binom_d(k1, a1) * binom_d(k2, a2) * binom_d(k3, a3) *
+                                 Mo[ora_cart_index(a1, a2, a3)] * rpow(d[0], k1 - a1) * rpow(d[1], k2 - a2) *
+                                 rpow(d[2], k3 - a3);
+                Mn[ora_cart_index(k1, k2, k3)] += s;
+            }
+}
+
+/* M2L: L_m += sum_{|m|+|k|<=p} C(m,k) a_{m+k}(R) M_k, R = t - s */
+void ora_cart_m2l(int p, const double *M, const double *R, double *L)
+{
+    int K2 = ora_cart_count(p);
+    double *a = (double *)malloc((size_t)K2 * sizeof(double));
+    ora_cart_taylor(p, R, a);
+    for (int nm = 0; nm <= p; nm++)
+        for (int m1 = nm; m1 >= 0; m1--)
+            for (int m2 = nm - m1; m2 >= 0; m2--) {
+                int m3 = nm - m1 - m2;
+                double s = 0.0;
+                for (int nk = 0; nk + nm <= p; nk++)
+                    for (int k1 = nk; k1 >= 0; k1--)
+                        for (int k2 = nk - k1; k2 >= 0; k2--) {
+                            int k3 = nk - k1 - k2;
+                            double C = binom_d(m1 + k1, k1) * binom_d(m2 + k2, k2) * binom_d(m3 + k3, k3);
+                            s += C * a[ora_cart_index(m1 + k1, m2 + k2, m3 + k3)] * M[ora_cart_index(k1, k2, k3)];
+                        }
+                L[ora_cart_index(m1, m2, m3)] += s;
+            }
+    free(a);
+}
+
+/* L2L: Lo (about t) re-centred at t' = t + d, added into Ln:
+ * Ln_m' += sum_{m >= m'} binom(m, m') Lo_m d^(m - m') */
+void ora_cart_l2l(int p, const double *Lo, const double *d, double *Ln)
+{
+    for (int n = 0; n <= p; n++)
+        for (int a1 = n; a1 >= 0; a1--)
+            for (int a2 = n - a1; a2 >= 0; a2--) {
+                int a3 = n - a1 - a2;
+                double s = 0.0;
+                for (int nm = n; nm <= p; nm++)
+                    for (int m1 = nm; m1 >= 0; m1--)
+                        for (int m2 = nm - m1; m2 >= 0; m2--) {
+                            int m3 = nm - m1 - m2;
+                            if (m1 < a1 || m2 < a2 || m3 < a3) continue;
+                            s += binom_d(m1, a1) * binom_d(m2, a2) * binom_d(m3, a3) * Lo[ora_cart_index(m1, m2, m3)] *
+                                 rpow(d[0], m1 - a1) * rpow(d[1], m2 - a2) * rpow(d[2], m3 - a3);
+                        }
+                Ln[ora_cart_index(a1, a2, a3)] += s;
+            }
+}
+
+/* L2P: phi = sum_m L_m (x - t)^m, E = -grad phi */
+void ora_cart_l2p(int p, const double *L, const double *t, const double *x, double *phi, double *E)
+{
+    double u[3] = {x[0] - t[0], x[1] - t[1], x[2] - t[2]};
+    double ph = 0.0, g[3] = {0.0, 0.0, 0.0};
+    for (int n = 0; n <= p; n++)
+        for (int m1 = n; m1 >= 0; m1--)
+            for (int m2 = n - m1; m2 >= 0; m2--) {
+                int m3 = n - m1 - m2;
+                double Lm = L[ora_cart_index(m1, m2, m3)];
+                ph += Lm * rpow(u[0], m1) * rpow(u[1], m2) * rpow(u[2], m3);
+                if (m1 > 0) g[0] += m1 * Lm * rpow(u[0], m1 - 1) * rpow(u[1], m2) * rpow(u[2], m3);
+                if (m2 > 0) g[1] += m2 * Lm * rpow(u[0], m1) * rpow(u[1], m2 - 1) * rpow(u[2], m3);
+                if (m3 > 0) g[2] += m3 * Lm * rpow(u[0], m1) * rpow(u[1], m2) * rpow(u[2], m3 - 1);
+            }
+    *phi = ph;
+    E[0] = -g[0]; E[1] = -g[1]; E[2] = -g[2];
+}
+
+/* M2P: phi = sum_k a_k(x - s) M_k, d phi/dx_i = sum_k (k_i + 1) a_{k + e_i}(x - s) M_k */
+void ora_cart_m2p(int p, const double *M, const double *s, const double *x, double *phi, double *E)
+{
+    double R[3] = {x[0] - s[0], x[1] - s[1], x[2] - s[2]};
+    double *a = (double *)malloc((size_t)ora_cart_count(p + 1) * sizeof(double));
+    ora_cart_taylor(p + 1, R, a);
+    double ph = 0.0, g[3] = {0.0, 0.0, 0.0};
+    for (int n = 0; n <= p; n++)
+        for (int k1 = n; k1 >= 0; k1--)
+            for (int k2 = n - k1; k2 >= 0; k2--) {
+                int k3 = n - k1 - k2;
+                double Mk = M[ora_cart_index(k1, k2, k3)];
+                ph += a[ora_cart_index(k1, k2, k3)] * Mk;
+                g[0] += (k1 + 1) * a[ora_cart_index(k1 + 1, k2, k3)] * Mk;
+                g[1] += (k2 + 1) * a[ora_cart_index(k1, k2 + 1, k3)] * Mk;
+                g[2] += (k3 + 1) * a[ora_cart_index(k1, k2, k3 + 1)] * Mk;
+            }
+    free(a);
+    *phi = ph;
+    E[0] = -g[0]; E[1] = -g[1]; E[2] = -g[2];
+}
+
+/* The whole evaluation with Cartesian expansions of order p, on the same
+ * tree and lists as ora_evaluate (P2M at leaves, M2M upward, M2L, L2L
+ * downward, L2P + M2P + P2P per target, targets != sources as there). */
+void ora_evaluate_cart(void *hv, int p, const double *q, double *phi, double *ex, double *ey, double *ez)
+{
+    ora_t *h = (ora_t *)hv;
+    int64_t n = h->n, nc = h->ncell;
+    int K = ora_cart_count(p);
+    h->pc = p;
+    free(h->Mc); free(h->Lc);
+    h->Mc = (double *)calloc((size_t)(nc ? nc : 1) * K, sizeof(double));
+    h->Lc = (double *)calloc((size_t)(nc ? nc : 1) * K, sizeof(double));
+    if (n == 0) return;
+    const int64_t nt = h->nt;
+    double *sq = (double *)malloc((size_t)n * sizeof(double));
+    for (int64_t k = 0; k < n; k++) {
+        int64_t o = h->perm[k];
+        sq[k] = nt < 0 ? q[o] : (o < nt ? 0.0 : q[o - nt]);
+    }
+    const int64_t nout = nt < 0 ? n : nt;
+    int64_t c;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (c = 0; c < nc; c++) {
+        if (!is_leaf(h, (int32_t)c)) continue;
+        int32_t b = h->begin[c], e = h->end[c];
+        ora_cart_p2m(p, &h->cphys[3 * c], e - b, h->px + b, h->py + b, h->pz + b, sq + b, h->Mc + c * K);
+    }
+    int maxl = 0;
+    for (c = 0; c < nc; c++) if (h->level[c] > maxl) maxl = h->level[c];
+    for (int L = maxl - 1; L >= 0; L--) {
+#pragma omp parallel for schedule(dynamic, 4)
+        for (c = 0; c < nc; c++) {
+            if (h->level[c] != L || is_leaf(h, (int32_t)c)) continue;
+            for (int32_t ch = h->first_child[c]; ch < h->first_child[c] + h->nchild[c]; ch++) {
+                double d[3] = {h->cphys[3 * c] - h->cphys[3 * ch], h->cphys[3 * c + 1] - h->cphys[3 * ch + 1],
+                               h->cphys[3 * c + 2] - h->cphys[3 * ch + 2]};
+                ora_cart_m2m(p, h->Mc + (int64_t)ch * K, d, h->Mc + c * K);
+            }
+        }
+    }
+    csr_t cm2l, cm2p, cp2p;
+    build_csr(h, &h->list[K_M2L], &cm2l);
+    build_csr(h, &h->list[K_M2P], &cm2p);
+    build_csr(h, &h->list[K_P2P], &cp2p);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (c = 0; c < nc; c++) {
+        for (int64_t a = cm2l.off[c]; a < cm2l.off[c + 1]; a++) {
+            int32_t s = cm2l.src[a];
+            double R[3] = {h->cphys[3 * c] - h->cphys[3 * s], h->cphys[3 * c + 1] - h->cphys[3 * s + 1],
+                           h->cphys[3 * c + 2] - h->cphys[3 * s + 2]};
+            ora_cart_m2l(p, h->Mc + (int64_t)s * K, R, h->Lc + c * K);
+        }
+    }
+    for (int L = 1; L <= maxl; L++) {
+#pragma omp parallel for schedule(dynamic, 4)
+        for (c = 0; c < nc; c++) {
+            if (h->level[c] != L) continue;
+            int32_t P = h->parent[c];
+            double d[3] = {h->cphys[3 * c] - h->cphys[3 * P], h->cphys[3 * c + 1] - h->cphys[3 * P + 1],
+                           h->cphys[3 * c + 2] - h->cphys[3 * P + 2]};
+            ora_cart_l2l(p, h->Lc + (int64_t)P * K, d, h->Lc + c * K);
+        }
+    }
+    int32_t *leaf = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    for (c = 0; c < nc; c++)
+        if (is_leaf(h, (int32_t)c))
+            for (int32_t i = h->begin[c]; i < h->end[c]; i++) leaf[i] = (int32_t)c;
+    int64_t i;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (i = 0; i < nout; i++) {
+        double xi[3] = {h->px[i], h->py[i], h->pz[i]};
+        int32_t t = leaf[i];
+        double ph, e[3];
+        ora_cart_l2p(p, h->Lc + (int64_t)t * K, &h->cphys[3 * t], xi, &ph, e);
+        double P = ph, F[3] = {e[0], e[1], e[2]};
+        for (int32_t A = t; A >= 0; A = h->parent[A]) {
+            for (int64_t a = cm2p.off[A]; a < cm2p.off[A + 1]; a++) {
+                int32_t s = cm2p.src[a];
+                ora_cart_m2p(p, h->Mc + (int64_t)s * K, &h->cphys[3 * s], xi, &ph, e);
+                P += ph; F[0] += e[0]; F[1] += e[1]; F[2] += e[2];
+            }
+            for (int64_t a = cp2p.off[A]; a < cp2p.off[A + 1]; a++) {
+                int32_t s = cp2p.src[a];
+                for (int32_t j = h->begin[s]; j < h->end[s]; j++) {
+                    if (j == i) continue;
+                    double dx = xi[0] - h->px[j], dy = xi[1] - h->py[j], dz = xi[2] - h->pz[j];
+                    double r2 = dx * dx + dy * dy + dz * dz;
+                    if (r2 == 0.0) continue;
+                    double r = sqrt(r2);
+                    P += sq[j] / r;
+                    double f = sq[j] / (r2 * r);
+                    F[0] += f * dx; F[1] += f * dy; F[2] += f * dz;
+                }
+            }
+        }
+        int64_t o = h->perm[i];
+        phi[o] = P; ex[o] = F[0]; ey[o] = F[1]; ez[o] = F[2];
+    }
+    free(leaf); free(sq);
+    free(cm2l.off); free(cm2l.src); free(cm2p.off); free(cm2p.src); free(cp2p.off); free(cp2p.src);
+}
+
+/* Cartesian expansions of every cell after ora_evaluate_cart */
+void ora_get_expansions_cart(void *hv, double *M, double *L)
+{
+    ora_t *h = (ora_t *)hv;
+    size_t K = (size_t)ora_cart_count(h->pc);
+    memcpy(M, h->Mc, (size_t)h->ncell * K * sizeof(double));
+    memcpy(L, h->Lc, (size_t)h->ncell * K * sizeof(double));
+}
+
 void ora_free(void *hv)
 {
     ora_t *h = (ora_t *)hv;
@@ -854,7 +1204,7 @@ void ora_free(void *hv)
     free(h->level); free(h->begin); free(h->end); free(h->parent); free(h->first_child);
     free(h->nchild); free(h->prefix); free(h->ch); free(h->rh); free(h->cphys); free(h->rphys);
     for (int k = 0; k < 3; k++) free(h->list[k].v);
-    free(h->M); free(h->L);
+    free(h->M); free(h->L); free(h->Mc); free(h->Lc);
     free(h);
 }
 

@@ -14,6 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libfmm.so")
 
 POLICY_FMM, POLICY_TREECODE, POLICY_HYBRID_TIMED, POLICY_HYBRID_MLP = 0, 1, 2, 3
+EXPANSION_SPHERICAL, EXPANSION_CARTESIAN, EXPANSION_AUTO = 0, 1, 2
 PREC_FP32, PREC_SPLIT_BF16 = 0, 1
 F32, F64 = 0, 1
 LIST_M2L, LIST_M2P, LIST_P2P = 0, 1, 2
@@ -51,6 +52,7 @@ def lib():
         "fmm_set_stream": ([vp, vp], ctypes.c_int),
         "fmm_build_tree": ([vp, i64, ctypes.c_int, vp, vp, vp, vp, i32], ctypes.c_int),
         "fmm_build_tree_batch": ([vp, i32, vp, ctypes.c_int, vp, vp, vp, vp, i32], ctypes.c_int),
+        "fmm_build_tree_ts": ([vp, ctypes.c_int, i64, vp, vp, vp, i64, vp, vp, vp, vp, i32], ctypes.c_int),
         "fmm_evaluate_batch": ([vp, i32, vp, ctypes.c_int, vp, vp, vp, vp, i32, i32, dbl, i32, i32, i32,
                                 vp, vp, vp, vp], ctypes.c_int),
         "fmm_get_bboxes": ([vp, i32, vp], ctypes.c_int),
@@ -85,6 +87,8 @@ def lib():
         "fmm_costmodel_save": ([vp, ctypes.c_char_p], ctypes.c_int),
         "fmm_costmodel_load": ([vp, ctypes.c_char_p, i32, i32], ctypes.c_int),
         "fmm_m2l_slots": ([i32, dbl, vp, vp], ctypes.c_int),
+        "fmm_set_expansion": ([vp, i32, i32], ctypes.c_int),
+        "fmm_get_expansion": ([vp, vp], ctypes.c_int),
         "fmm_evaluate_noalloc": ([vp, i32, i32, vp, vp, vp, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
@@ -174,8 +178,25 @@ class FMM:
     def build_tree(self, x, y, z, q, ncrit: int):
         dt = self._check_inputs(x, y, z, q)
         self.n = x.numel()
+        self.n_all = self.n
         self._ck(lib().fmm_build_tree(self.h, self.n, dt, x.data_ptr(), y.data_ptr(), z.data_ptr(),
                                       q.data_ptr(), int(ncrit)))
+
+    def build_tree_ts(self, targets, sources, q, ncrit: int):
+        """Target tree over targets = (tx, ty, tz) and source tree over
+        sources = (sx, sy, sz) with charges q, in one cube; evaluate then
+        returns the targets' potential and field."""
+        tx, ty, tz = targets
+        sx, sy, sz = sources
+        dt = self._check_inputs(tx, ty, tz, tx)
+        if sx.numel() > 0:
+            if self._check_inputs(sx, sy, sz, q) != dt:
+                raise ValueError("targets and sources must share one dtype")
+        nt, ns = tx.numel(), sx.numel()
+        self.n = nt
+        self._ck(lib().fmm_build_tree_ts(self.h, dt, nt, tx.data_ptr(), ty.data_ptr(), tz.data_ptr(), ns,
+                                         sx.data_ptr(), sy.data_ptr(), sz.data_ptr(), q.data_ptr(), int(ncrit)))
+        self.n_all = nt + ns
 
     def _check_inputs(self, x, y, z, q):
         t = self._torch
@@ -200,6 +221,7 @@ class FMM:
         dt = self._check_inputs(x, y, z, q)
         off = self._offsets(offsets, x.numel())
         self.n = x.numel()
+        self.n_all = self.n
         self._ck(lib().fmm_build_tree_batch(self.h, off.size - 1, _ptr(off), dt, x.data_ptr(), y.data_ptr(),
                                             z.data_ptr(), q.data_ptr(), int(ncrit)))
         self.n_inst = off.size - 1
@@ -219,6 +241,7 @@ class FMM:
             phi, E = out
         od = F64 if phi.dtype == t.float64 else F32
         self.n = n
+        self.n_all = n
         self._ck(lib().fmm_evaluate_batch(self.h, off.size - 1, _ptr(off), dt, x.data_ptr(), y.data_ptr(),
                                           z.data_ptr(), q.data_ptr(), int(ncrit), int(p), float(theta),
                                           int(policy), int(precision), od, phi.data_ptr(), E[0].data_ptr(),
@@ -259,6 +282,17 @@ class FMM:
         self._ck(lib().fmm_evaluate_noalloc(self.h, int(precision), od, phi.data_ptr(), E[0].data_ptr(),
                                             E[1].data_ptr(), E[2].data_ptr()))
         return phi, E
+
+    def set_expansion(self, expansion: int, auto_cartesian_max_p: int = 3):
+        """Expansion family of the following traversals (EXPANSION_*); with
+        EXPANSION_AUTO the Cartesian family is taken for p <= auto_cartesian_max_p."""
+        self._ck(lib().fmm_set_expansion(self.h, int(expansion), int(auto_cartesian_max_p)))
+
+    def expansion(self) -> int:
+        """Family of the last traversal (EXPANSION_SPHERICAL or EXPANSION_CARTESIAN)."""
+        v = ctypes.c_int32()
+        self._ck(lib().fmm_get_expansion(self.h, ctypes.byref(v)))
+        return v.value
 
     def set_costs(self, c_m2l: float, c_m2p: float, c_p2p: float):
         self._ck(lib().fmm_set_costs(self.h, float(c_m2l), float(c_m2p), float(c_p2p)))
@@ -386,8 +420,9 @@ class FMM:
         return lo, float(side[0])
 
     def keys(self):
-        k = np.zeros(self.n, dtype=np.uint64)
-        perm = np.zeros(self.n, dtype=np.int32)
+        n = getattr(self, "n_all", self.n)
+        k = np.zeros(n, dtype=np.uint64)
+        perm = np.zeros(n, dtype=np.int32)
         self._ck(lib().fmm_get_keys(self.h, _ptr(k), _ptr(perm)))
         return k, perm
 
@@ -411,7 +446,8 @@ class FMM:
 
     def expansions(self):
         c = self.sizes()["cells"]
-        K = (self.p + 1) ** 2
+        p = self.p
+        K = (p + 1) * (p + 2) * (p + 3) // 6 if self.expansion() == EXPANSION_CARTESIAN else (p + 1) ** 2
         M = np.zeros(c * K, np.float32)
         L = np.zeros(c * K, np.float32)
         self._ck(lib().fmm_get_expansions(self.h, _ptr(M), _ptr(L)))

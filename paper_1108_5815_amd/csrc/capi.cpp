@@ -67,6 +67,12 @@ struct fmm_ctx_s {
     int32_t ncrit = 0;
     double lo[3] = {0, 0, 0}, side = 1;  // instance 0's bounding cube
     bool built = false, traversed = false;
+    // targets != sources: the input's first n_targets particles (instance 0)
+    // are the targets, the rest (instance 1) the sources, in one shared cube;
+    // -1 when targets and sources are the same particles
+    int64_t n_targets = -1;
+    Buf ts_stage, tleaves;
+    int32_t ntleaf = 0;
     // batch: instance offsets, frames, roots (cells [0, nroot))
     std::vector<int64_t> hseg;
     std::vector<Frame> frames;
@@ -80,6 +86,13 @@ struct fmm_ctx_s {
     std::vector<int32_t> lvl;  // cells of level L: [lvl[L], lvl[L+1])
     Buf keys, keys2, idx, idx2, pts, ws, small;
     Buf c_begin, c_end, c_parent, c_child, c_nchild, c_level, c_prefix, c_geo, c_ctr, leaves, tmp1, tmp2;
+
+    // expansion family: requested (FMM_EXPANSION_*), the order up to which
+    // FMM_EXPANSION_AUTO takes the Cartesian family, and the family of the
+    // last traversal (kFamilySpherical or kFamilyCartesian)
+    int expansion = 0, auto_cart_max_p = 3, fam = kFamilySpherical;
+    HostTables ht_cart;
+    int tables_p = -1, tables_fam = -1;
 
     // traversal
     int p = -1;
@@ -149,7 +162,8 @@ struct fmm_ctx_s {
                       &d_grad, &d_grad_rec, &d_loss_rec, &d_feat, &d_kind, &d_tgt, &d_table, &d_Thi, &d_Tlo,
                       &d_seg, &d_bt, &d_pb, &d_box, &d_frame, &inst, &bsort, &tact, &tnact,
                       &leaves_cls, &inner, &leafpos, &m2pflag, &m2lslot, &tbounds, &lkey, &lval, &lkey2, &lval2, &at_out, &m2l_part, &Msplit, &nbucket, &kinds, &ckey, &ckey2, &cval, &cval2,
-                      &chead, &choff, &cstart, &cpos, &csrcs, &cnt_t, &ctbase, &ctile, &cT, &cskip, &cls_part};
+                      &chead, &choff, &cstart, &cpos, &csrcs, &cnt_t, &ctbase, &ctile, &cT, &cskip, &cls_part,
+                      &ts_stage, &tleaves};
         for (Buf* b : all) bufs.push_back(b);
     }
 };
@@ -303,6 +317,10 @@ Tables tables_of(fmm_ctx c) {
     return t;
 }
 
+// coefficients per cell and row stride of the current family and order
+int c_k(fmm_ctx c) { return c->fam == kFamilyCartesian ? (c->p + 1) * (c->p + 2) * (c->p + 3) / 6 : ncoef(c->p); }
+int c_kp(fmm_ctx c) { return c->fam == kFamilyCartesian ? kpad_cart(c->p) : kpad(c->p); }
+
 template <class F>
 fmm_status guarded(fmm_ctx c, F f) {
     if (!c) return FMM_ERR_INVALID_ARG;
@@ -335,7 +353,7 @@ int bits_for(int64_t v) {
 // the batch of one.  Each instance gets its own bounding cube, keys relative
 // to it, and its own root; the sort orders by (instance, key, input index).
 void build_forest_impl(fmm_ctx c, int32_t nseg, const int64_t* hseg, int dtype, const void* x, const void* y,
-                       const void* z, const void* q, int32_t ncrit) {
+                       const void* z, const void* q, int32_t ncrit, bool shared_frame = false) {
     if (nseg < 1 || !hseg) fail(FMM_ERR_INVALID_ARG, "need at least one instance");
     if (hseg[0] != 0) fail(FMM_ERR_INVALID_ARG, "offsets[0] must be 0");
     for (int32_t k = 0; k < nseg; k++)
@@ -347,6 +365,8 @@ void build_forest_impl(fmm_ctx c, int32_t nseg, const int64_t* hseg, int dtype, 
     if (n > 0 && (!x || !y || !z || !q)) fail(FMM_ERR_INVALID_ARG, "null input pointer");
     c->built = false;
     c->traversed = false;
+    c->n_targets = -1;
+    c->ntleaf = 0;
     c->n = n;
     c->dtype = dtype;
     c->ncrit = ncrit;
@@ -395,6 +415,24 @@ void build_forest_impl(fmm_ctx c, int32_t nseg, const int64_t* hseg, int dtype, 
     uint32_t bad = 0;
     to_host<uint32_t>(c, &bad, dbad, 1);
     if (bad) fail(FMM_ERR_INVALID_ARG, "non-finite coordinate in input");
+    if (shared_frame) {
+        // one cube around every instance's points: their cells then compare geometrically
+        bool any = false;
+        double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+        for (int32_t k = 0; k < nseg; k++) {
+            if (hseg[k + 1] == hseg[k]) continue;
+            for (int d = 0; d < 3; d++) {
+                lo[d] = any ? std::min(lo[d], hb[k * 6 + d]) : hb[k * 6 + d];
+                hi[d] = any ? std::max(hi[d], hb[k * 6 + 3 + d]) : hb[k * 6 + 3 + d];
+            }
+            any = true;
+        }
+        for (int32_t k = 0; k < nseg; k++)
+            for (int d = 0; d < 3; d++) {
+                hb[k * 6 + d] = lo[d];
+                hb[k * 6 + 3 + d] = hi[d];
+            }
+    }
     for (int32_t k = 0; k < nseg; k++) {
         if (hseg[k + 1] == hseg[k]) continue;
         Frame& f = c->frames[k];
@@ -545,20 +583,27 @@ void build_tree_impl(fmm_ctx c, int64_t n, int dtype, const void* x, const void*
 
 // ------------------------------------------------------------------ traverse
 void upload_tables(fmm_ctx c, int p) {
-    if (c->ht.p == p) return;
-    build_tables(p, c->ht);
-    HostTables& t = c->ht;
+    HostTables& t = c->fam == kFamilyCartesian ? c->ht_cart : c->ht;
+    if (t.p != p) {
+        if (c->fam == kFamilyCartesian) build_tables_cart(p, t);
+        else build_tables(p, t);
+    }
+    // the device tables hold one family at a time
+    if (c->tables_p == p && c->tables_fam == c->fam) return;
     to_dev(c, need<float>(c, c->d_m2m, t.m2m.size()), t.m2m.data(), t.m2m.size());
     to_dev(c, need<float>(c, c->d_l2l, t.l2l.size()), t.l2l.data(), t.l2l.size());
     to_dev(c, need<float>(c, c->d_w, t.wm2l.size()), t.wm2l.data(), t.wm2l.size());
     to_dev(c, need<float>(c, c->d_g, t.gl2p.size()), t.gl2p.data(), t.gl2p.size());
     to_dev(c, need<float>(c, c->d_h, t.hm2p.size()), t.hm2p.data(), t.hm2p.size());
     to_dev(c, need<float>(c, c->d_rc, t.rcoef.size()), t.rcoef.data(), t.rcoef.size());
+    c->tables_p = p;
+    c->tables_fam = c->fam;
 }
 
 void upload_plan(fmm_ctx c, int p, double theta) {
-    if (c->plan.p == p && c->plan.theta == theta) return;
-    build_m2l_plan(p, theta, c->plan);
+    const bool cart = c->fam == kFamilyCartesian;
+    if (c->plan.p == p && c->plan.theta == theta && c->plan.cartesian == cart) return;
+    build_m2l_plan(p, theta, c->plan, cart);
     M2LPlan& pl = c->plan;
     to_dev(c, need<int32_t>(c, c->d_slot, pl.slot_of.size()), pl.slot_of.data(), pl.slot_of.size());
     to_dev(c, need<int32_t>(c, c->d_offid, pl.offid.size()), pl.offid.data(), pl.offid.size());
@@ -570,7 +615,8 @@ void upload_plan(fmm_ctx c, int p, double theta) {
 void upload_plan_bf16(fmm_ctx c) {
     if (c->plan_bf16) return;
     std::vector<uint16_t> hi, lo;
-    split_bf16_kblocked(c->plan.T, c->plan.offsets.size(), kpad(c->plan.p), hi, lo);
+    split_bf16_kblocked(c->plan.T, c->plan.offsets.size(), c->plan.cartesian ? kpad_cart(c->plan.p) : kpad(c->plan.p),
+                        hi, lo);
     to_dev(c, need<uint16_t>(c, c->d_Thi, hi.size()), hi.data(), hi.size());
     to_dev(c, need<uint16_t>(c, c->d_Tlo, lo.size()), lo.data(), lo.size());
     c->plan_bf16 = true;
@@ -581,7 +627,7 @@ void upload_plan_bf16(fmm_ctx c) {
 void build_classes(fmm_ctx c, int p) {
     c->cp = ClsPlan{};
     const int64_t ng = c->ngeneral;
-    const int KP = kpad(p);
+    const int KP = c_kp(c);
     const int NT = cls_tile_cols(KP);
     if (ng <= 0 || NT <= 0) return;
     hipStream_t s = c->stream;
@@ -625,7 +671,8 @@ void build_classes(fmm_ctx c, int p) {
     cls_tiles(nt, tb, (int32_t)ncls, tile_cls, s);
     float* T = need<float>(c, c->cT, (size_t)ncls * KP * KP);
     fill_zero(T, (size_t)ncls * KP * KP * sizeof(float), s);
-    cls_ops(keys, start, (int32_t)ncls, p, KP, (const float*)c->d_w.p, T, s);
+    if (c->fam == kFamilyCartesian) cls_ops_cart(keys, start, (int32_t)ncls, p, KP, T, s);
+    else cls_ops(keys, start, (int32_t)ncls, p, KP, (const float*)c->d_w.p, T, s);
     if (nb < ng) cls_skip(pos, ng, nb, need<uint8_t>(c, c->cskip, ng), s);
     check_launch("m2l classes: operators");
     ClsPlan& cp = c->cp;
@@ -648,7 +695,18 @@ void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
         fail(FMM_ERR_STATE, "timed hybrid needs unit costs (fmm_tune or fmm_set_costs)");
     if (policy == FMM_POLICY_HYBRID_MLP && !c->mlp_ready)
         fail(FMM_ERR_STATE, "learned hybrid needs a trained cost model");
+    // expansion family: spherical harmonics, or the Cartesian Taylor series
+    // the hybrid method switches to at low accuracy ("Hybrid treecode/FMM
+    // algorithm"): asked for, or chosen by order under FMM_EXPANSION_AUTO
+    int fam = kFamilySpherical;
+    if (c->expansion == FMM_EXPANSION_CARTESIAN) {
+        if (p > kMaxPCart) fail(FMM_ERR_UNSUPPORTED, "Cartesian expansions are implemented for p <= 6");
+        fam = kFamilyCartesian;
+    } else if (c->expansion == FMM_EXPANSION_AUTO && p <= c->auto_cart_max_p && p <= kMaxPCart) {
+        fam = kFamilyCartesian;
+    }
     c->traversed = false;
+    c->fam = fam;
     c->p = p;
     c->theta = theta;
     c->policy = policy;
@@ -694,7 +752,13 @@ void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
     std::vector<int32_t> rch(nr);
     to_host<int32_t>(c, rch.data(), c->c_nchild.p, nr);
     std::vector<int2> self, start;
-    for (int32_t r = 0; r < nr; r++) (rch[r] == 0 ? self : start).push_back(make_int2(r, r));
+    if (c->n_targets < 0) {
+        for (int32_t r = 0; r < nr; r++) (rch[r] == 0 ? self : start).push_back(make_int2(r, r));
+    } else if (nr == 2) {
+        // (target root, source root); the cube is shared, so the pair never
+        // passes the criterion: two leaves interact directly, else split
+        (rch[0] == 0 && rch[1] == 0 ? self : start).push_back(make_int2(0, 1));
+    }
     int2* fr = need<int2>(c, c->fr0, std::max<size_t>(1024, start.size()));
     if (!self.empty()) {
         int2* r = need<int2>(c, c->raw[2], self.size());
@@ -756,7 +820,7 @@ void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
     c->m2l_sorted = false;
     // the per-pair slot is stored in 16 bits and the gather table grows with
     // the slot count: small theta sends every cell-cell pair to the class path
-    c->gemm_on = m2l_gemm_supported(p) && c->nlist[0] > 0 && m2l_plan_slots(theta) <= kGemmMaxSlots;
+    c->gemm_on = m2l_gemm_supported_kp(c_kp(c)) && c->nlist[0] > 0 && m2l_plan_slots(theta) <= kGemmMaxSlots;
     c->ntiles = 0;
     c->nrows = 0;
     c->ngeneral = 0;
@@ -765,7 +829,7 @@ void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
     int16_t* slot16 = need<int16_t>(c, c->m2lslot, nm + 1);  // per pair: GEMM slot, -1 outside the tables
     if (c->gemm_on) {
         upload_plan(c, p, theta);
-        if (m2l_bf16_supported(p)) upload_plan_bf16(c);
+        if (m2l_bf16_supported_kp(c_kp(c))) upload_plan_bf16(c);
         int R = c->plan.R, J = c->plan.J;
         uint32_t* hf = need<uint32_t>(c, c->has_fast, nc);
         fill_zero(hf, (size_t)nc * 4, s);
@@ -784,7 +848,7 @@ void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
         int32_t* h9 = (int32_t*)host_stage(c);
         to_host<int32_t>(c, h9, d9, 9);
         int tiles = 0;
-        const int tc = gemm_tile_cols(p);
+        const int tc = gemm_tile_cols_kp(c_kp(c));
         for (int k = 0; k < 9; k++) {
             c->gp.class_row0[k] = h9[k];
             c->gp.class_tile0[k] = tiles;
@@ -839,13 +903,19 @@ void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
     c->traversed = true;
 }
 
+// Whether every particle pair of P2P must skip r = 0: FP64 inputs (distinct
+// points can round to one FP32 point), and distinct target and source sets
+// (a target may coincide with a source, in any pair of leaves).  Otherwise
+// only a leaf with itself can hold coincident points.
+int p2p_guard_all(fmm_ctx c) { return (c->dtype == FMM_F64 || c->n_targets >= 0) ? 1 : 0; }
+
 // P2P over the leaves of each size class with that class's tile shape
 void run_p2p(fmm_ctx c, double4* near, hipStream_t st) {
     for (int k = 0; k < kLeafClasses; k++) {
         const int32_t b = c->leaf_cls[k], e = c->leaf_cls[k + 1];
         if (e <= b) continue;
         p2p((float4*)c->pts.p, cells_of(c), (int32_t*)c->leaves_cls.p + b, e - b, (int32_t*)c->off[2].p,
-            (uint32_t*)c->src[2].p, c->dtype == FMM_F64 ? 1 : 0, c->p2p_tpl[k], near, st);
+            (uint32_t*)c->src[2].p, p2p_guard_all(c), c->p2p_tpl[k], near, st);
     }
     check_launch("p2p");
 }
@@ -868,7 +938,7 @@ enum { EB_M, EB_L, EB_NEAR, EB_PART, EB_MSPLIT, EB_CLS, EB_FLAG, EB_N };
 
 // bytes of each work buffer for an evaluation at `precision` (0 = not used)
 void eval_sizes(fmm_ctx c, int precision, size_t* b) {
-    const size_t KP = (size_t)kpad(c->p), nc = (size_t)c->ncell;
+    const size_t KP = (size_t)c_kp(c), nc = (size_t)c->ncell;
     const bool gemm = c->gemm_on && c->ntiles > 0;
     b[EB_M] = (nc + 1) * KP * sizeof(float);
     b[EB_L] = nc * KP * sizeof(float);
@@ -883,8 +953,8 @@ void check_evaluate_args(fmm_ctx c, int32_t precision, int32_t out_dtype, void* 
     if (!c->traversed) fail(FMM_ERR_STATE, "fmm_evaluate before fmm_traverse");
     if (precision != FMM_PREC_FP32 && precision != FMM_PREC_SPLIT_BF16)
         fail(FMM_ERR_INVALID_ARG, "precision must be FMM_PREC_FP32 or FMM_PREC_SPLIT_BF16");
-    if (precision == FMM_PREC_SPLIT_BF16 && !m2l_bf16_supported(c->p))
-        fail(FMM_ERR_UNSUPPORTED, "split-BF16 M2L is implemented for p <= 12");
+    if (precision == FMM_PREC_SPLIT_BF16 && !m2l_bf16_supported_kp(c_kp(c)))
+        fail(FMM_ERR_UNSUPPORTED, "split-BF16 M2L is implemented for storage widths up to 192 (spherical p <= 12)");
     if (out_dtype != FMM_F32 && out_dtype != FMM_F64) fail(FMM_ERR_INVALID_ARG, "out_dtype must be F32 or F64");
     if (c->n > 0 && (!phi || !ex || !ey || !ez)) fail(FMM_ERR_INVALID_ARG, "null output pointer");
 }
@@ -894,7 +964,7 @@ void check_evaluate_args(fmm_ctx c, int32_t precision, int32_t out_dtype, void* 
 void evaluate_on(fmm_ctx c, int32_t precision, int32_t out_dtype, void* phi, void* ex, void* ey, void* ez,
                  const EvalBufs& eb, bool in_order) {
     hipStream_t s = c->stream;
-    int p = c->p, KP = kpad(p);
+    const int p = c->p, KP = c_kp(c), K = c_k(c), fam = c->fam;
     int32_t nc = c->ncell;
     CellArrays ca = cells_of(c);
     Tables tb = tables_of(c);
@@ -924,12 +994,12 @@ void evaluate_on(fmm_ctx c, int32_t precision, int32_t out_dtype, void* phi, voi
     };
     if (sched == 1) fork_p2p();
     mark(c, PH_UP);
-    p2m((float4*)c->pts.p, ca, (int32_t*)c->leaves.p, c->nleaf, p, KP, tb.rcoef, M, s);
+    p2m((float4*)c->pts.p, ca, (int32_t*)c->leaves.p, c->nleaf, fam, p, KP, tb.rcoef, M, s);
     int nlev = (int)c->lvl.size() - 1;
     const int32_t* inr = (const int32_t*)c->inner.p;
     const uint32_t* lpos = (const uint32_t*)c->leafpos.p;
     for (int Lv = nlev - 2; Lv >= 0; Lv--)
-        m2m(ca, inr, lpos, c->lvl[Lv], c->lvl[Lv + 1], c->ncell, c->nleaf, p, KP, tb, M, s);
+        m2m(ca, inr, lpos, c->lvl[Lv], c->lvl[Lv + 1], c->ncell, c->nleaf, K, KP, tb, M, s);
     check_launch("upward");
     if (sched == 2) fork_p2p();
     fill_zero(L, (size_t)nc * KP * sizeof(float), s);
@@ -940,9 +1010,9 @@ void evaluate_on(fmm_ctx c, int32_t precision, int32_t out_dtype, void* phi, voi
         hipEvent_t g0 = c->timing ? c->ev_gk[0] : nullptr, g1 = c->timing ? c->ev_gk[1] : nullptr;
         if (precision == FMM_PREC_SPLIT_BF16)
             m2l_gemm_bf16((uint16_t*)c->d_Thi.p, (uint16_t*)c->d_Tlo.p, (int32_t*)c->d_offid.p, (int32_t*)c->gather.p,
-                          (uint32_t*)c->rval.p, c->gp, p, KP, M, nc, eb.Msplit, part, L, s, g0, g1);
+                          (uint32_t*)c->rval.p, c->gp, K, KP, M, nc, eb.Msplit, part, L, s, g0, g1);
         else
-            m2l_gemm((float*)c->d_T.p, (int32_t*)c->d_offid.p, (int32_t*)c->gather.p, (uint32_t*)c->rval.p, c->gp, p,
+            m2l_gemm((float*)c->d_T.p, (int32_t*)c->d_offid.p, (int32_t*)c->gather.p, (uint32_t*)c->rval.p, c->gp, K,
                      KP, M, part, L, s, g0, g1);
     }
     mark(c, PH_M2LG);
@@ -950,15 +1020,19 @@ void evaluate_on(fmm_ctx c, int32_t precision, int32_t out_dtype, void* phi, voi
         ClsPlan cp = c->cp;
         cp.zcell = nc;
         float* part2 = eb.cls_part;
-        m2l_cls((const float*)c->cT.p, cp, p, KP, M, part2, (int32_t*)c->goff.p, nc, L, s);
+        m2l_cls((const float*)c->cT.p, cp, K, KP, M, part2, (int32_t*)c->goff.p, nc, L, s);
     }
-    if (c->ngeneral > c->cp.nbatched)
-        m2l_general((int32_t*)c->goff.p, (uint32_t*)c->gsr.p, ca, nc, p, KP, tb, M, L,
-                    c->cp.nbatched > 0 ? (const uint8_t*)c->cskip.p : nullptr, s);
+    if (c->ngeneral > c->cp.nbatched) {
+        const uint8_t* skip = c->cp.nbatched > 0 ? (const uint8_t*)c->cskip.p : nullptr;
+        if (fam == kFamilyCartesian)
+            m2l_general_cart((int32_t*)c->goff.p, (uint32_t*)c->gsr.p, ca, nc, p, KP, M, L, skip, s);
+        else
+            m2l_general((int32_t*)c->goff.p, (uint32_t*)c->gsr.p, ca, nc, p, KP, tb, M, L, skip, s);
+    }
     check_launch("m2l");
     mark(c, PH_DOWN);
     for (int Lv = 0; Lv + 1 < nlev; Lv++)
-        l2l(ca, inr, lpos, c->lvl[Lv], c->lvl[Lv + 1], c->ncell, c->nleaf, p, KP, tb, L, s);
+        l2l(ca, inr, lpos, c->lvl[Lv], c->lvl[Lv + 1], c->ncell, c->nleaf, K, KP, tb, L, s);
     check_launch("downward");
     mark(c, PH_P2P);
     if (sched) {
@@ -968,8 +1042,11 @@ void evaluate_on(fmm_ctx c, int32_t precision, int32_t out_dtype, void* phi, voi
     }
     mark(c, PH_FAR);
     uint8_t* mflag = eb.m2pflag;
-    far_final((float4*)c->pts.p, (uint32_t*)c->idx.p, ca, (int32_t*)c->leaves.p, c->nleaf, mflag, (int32_t*)c->off[1].p,
-              (uint32_t*)c->src[1].p, c->nlist[1], p, KP, tb, M, L, nr, out_dtype, phi, ex, ey, ez, s);
+    // the outputs are the targets': with distinct sets, only the target tree's leaves
+    const bool ts = c->n_targets >= 0;
+    far_final((float4*)c->pts.p, (uint32_t*)c->idx.p, ca, ts ? (int32_t*)c->tleaves.p : (int32_t*)c->leaves.p,
+              ts ? c->ntleaf : c->nleaf, mflag, (int32_t*)c->off[1].p,
+              (uint32_t*)c->src[1].p, c->nlist[1], fam, p, KP, tb, M, L, nr, out_dtype, phi, ex, ey, ez, s);
     check_launch("far field");
     mark(c, PH_N);
     if (c->timing) {
@@ -1091,6 +1168,57 @@ fmm_status fmm_build_tree(fmm_ctx c, int64_t n, int dtype, const void* x, const 
     });
 }
 
+fmm_status fmm_build_tree_ts(fmm_ctx c, int dtype, int64_t n_targets, const void* tx, const void* ty,
+                             const void* tz, int64_t n_sources, const void* sx, const void* sy, const void* sz,
+                             const void* q, int32_t ncrit) {
+    return guarded(c, [&] {
+        if (n_targets < 0 || n_sources < 0 || n_targets + n_sources >= ((int64_t)1 << 31))
+            fail(FMM_ERR_INVALID_ARG, "particle counts out of range");
+        if (dtype != FMM_F32 && dtype != FMM_F64) fail(FMM_ERR_INVALID_ARG, "dtype must be FMM_F32 or FMM_F64");
+        if ((n_targets > 0 && (!tx || !ty || !tz)) || (n_sources > 0 && (!sx || !sy || !sz || !q)))
+            fail(FMM_ERR_INVALID_ARG, "null input pointer");
+        const int64_t n = n_targets + n_sources;
+        const size_t es = dtype == FMM_F64 ? 8 : 4;
+        // the two sets side by side (targets first), targets with zero charge
+        char* st = need<char>(c, c->ts_stage, 4 * (size_t)std::max<int64_t>(n, 1) * es);
+        char* X[4] = {st, st + n * es, st + 2 * n * es, st + 3 * n * es};
+        const void* T[3] = {tx, ty, tz};
+        const void* S[4] = {sx, sy, sz, q};
+        for (int d = 0; d < 3; d++) {
+            if (n_targets > 0)
+                ck(hipMemcpyAsync(X[d], T[d], n_targets * es, hipMemcpyDeviceToDevice, c->stream), "copy");
+            if (n_sources > 0)
+                ck(hipMemcpyAsync(X[d] + n_targets * es, S[d], n_sources * es, hipMemcpyDeviceToDevice, c->stream),
+                   "copy");
+        }
+        if (n_targets > 0) fill_zero(X[3], n_targets * es, c->stream);
+        if (n_sources > 0)
+            ck(hipMemcpyAsync(X[3] + n_targets * es, q, n_sources * es, hipMemcpyDeviceToDevice, c->stream), "copy");
+        const int64_t seg[3] = {0, n_targets, n};
+        build_forest_impl(c, 2, seg, dtype, X[0], X[1], X[2], X[3], ncrit, true);
+        c->n_targets = n_targets;
+        // the leaves holding targets, for the final sum
+        const int32_t nl = c->nleaf;
+        int32_t* tl = need<int32_t>(c, c->tleaves, std::max(nl, 1));
+        c->ntleaf = 0;
+        if (nl > 0 && n_targets > 0) {
+            uint32_t* flag = need<uint32_t>(c, c->tmp1, nl + 1);
+            uint32_t* pos = need<uint32_t>(c, c->tmp2, nl + 1);
+            size_t wsn = scan_ws_bytes(nl);
+            void* ws = wsn > c->ws.cap ? need<char>(c, c->ws, wsn) : c->ws.p;
+            double* d6 = (double*)c->small.p;
+            target_leaf_flags(cells_of(c), (const int32_t*)c->leaves.p, nl, (int32_t)n_targets, flag, c->stream);
+            scan_u32(flag, pos, (uint32_t*)(d6 + 12), nl, ws, c->stream);
+            target_leaf_write((const int32_t*)c->leaves.p, flag, pos, nl, tl, c->stream);
+            check_launch("target leaves");
+            uint32_t cnt = 0;
+            to_host<uint32_t>(c, &cnt, d6 + 12, 1);
+            c->ntleaf = (int32_t)cnt;
+        }
+        build_timings(c);
+    });
+}
+
 fmm_status fmm_build_tree_batch(fmm_ctx c, int32_t n_inst, const int64_t* offsets, int dtype, const void* x,
                                 const void* y, const void* z, const void* q, int32_t ncrit) {
     return guarded(c, [&] {
@@ -1159,6 +1287,25 @@ fmm_status fmm_evaluate_noalloc(fmm_ctx c, int32_t precision, int32_t out_dtype,
     });
 }
 
+fmm_status fmm_set_expansion(fmm_ctx c, int32_t expansion, int32_t auto_cartesian_max_p) {
+    return guarded(c, [&] {
+        if (expansion < FMM_EXPANSION_SPHERICAL || expansion > FMM_EXPANSION_AUTO)
+            fail(FMM_ERR_INVALID_ARG, "unknown expansion family");
+        if (expansion == FMM_EXPANSION_AUTO && (auto_cartesian_max_p < -1 || auto_cartesian_max_p > kMaxPCart))
+            fail(FMM_ERR_INVALID_ARG, "the Cartesian range of FMM_EXPANSION_AUTO must lie in [-1, 6]");
+        c->expansion = expansion;
+        if (expansion == FMM_EXPANSION_AUTO) c->auto_cart_max_p = auto_cartesian_max_p;
+    });
+}
+
+fmm_status fmm_get_expansion(fmm_ctx c, int32_t* family) {
+    return guarded(c, [&] {
+        if (!family) fail(FMM_ERR_INVALID_ARG, "null pointer");
+        if (!c->traversed) fail(FMM_ERR_STATE, "no traversal");
+        *family = c->fam == kFamilyCartesian ? FMM_EXPANSION_CARTESIAN : FMM_EXPANSION_SPHERICAL;
+    });
+}
+
 fmm_status fmm_set_costs(fmm_ctx c, double c_m2l, double c_m2p, double c_p2p) {
     return guarded(c, [&] {
         if (!(c_m2l > 0) || !(c_m2p > 0) || !(c_p2p > 0)) fail(FMM_ERR_INVALID_ARG, "unit costs must be > 0");
@@ -1206,6 +1353,8 @@ fmm_status fmm_tune(fmm_ctx c, int32_t p, int32_t precision) {
         t->ualloc = c->ualloc;
         t->ufree = c->ufree;
         t->uuser = c->uuser;
+        t->expansion = c->expansion;
+        t->auto_cart_max_p = c->auto_cart_max_p;
         t->timing = true;
         t->schedule = 0;  // each kernel timed alone
         double tm[2][PH_N] = {};
@@ -1280,6 +1429,8 @@ static void gen_records(fmm_ctx c, int p, double theta, int precision, uint64_t 
     t->ualloc = c->ualloc;
     t->ufree = c->ufree;
     t->uuser = c->uuser;
+    t->expansion = c->expansion;
+    t->auto_cart_max_p = c->auto_cart_max_p;
     t->timing = true;
     t->schedule = 0;  // each kernel timed alone
     // measured log2 ns per cell pair, per leaf size: same-level M2L, mixed-level
@@ -1803,7 +1954,7 @@ fmm_status fmm_get_list(fmm_ctx c, int32_t kind, int32_t* tgt, int32_t* src) {
 fmm_status fmm_get_expansions(fmm_ctx c, float* mp, float* lc) {
     return guarded(c, [&] {
         if (!c->traversed || !c->M.p) fail(FMM_ERR_STATE, "no evaluation");
-        int K = ncoef(c->p), KP = kpad(c->p);
+        int K = c_k(c), KP = c_kp(c);
         size_t m = c->ncell;
         std::vector<float> tmp(m * KP);
         if (mp) {
@@ -1860,7 +2011,7 @@ fmm_status fmm_autotune(fmm_ctx c, int32_t precision, int32_t reps) {
             for (int tpl : {1, 2, 4}) {
                 double t = timed([&] {
                     p2p((float4*)c->pts.p, cells_of(c), (int32_t*)c->leaves_cls.p + b, e - b, (int32_t*)c->off[2].p,
-                        (uint32_t*)c->src[2].p, c->dtype == FMM_F64 ? 1 : 0, tpl, nr, s);
+                        (uint32_t*)c->src[2].p, p2p_guard_all(c), tpl, nr, s);
                     check_launch("p2p");
                 });
                 if (t < best) {

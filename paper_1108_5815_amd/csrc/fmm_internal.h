@@ -24,6 +24,10 @@ namespace fmm {
 
 constexpr int kMaxP = 16;
 constexpr int kMaxLevel = 21;
+// expansion families: spherical harmonics (any p <= kMaxP) and Cartesian
+// Taylor series (p <= kMaxPCart; cart.h)
+constexpr int kFamilySpherical = 0, kFamilyCartesian = 1;
+constexpr int kMaxPCart = 6;
 
 struct CellArrays {
     int32_t* begin;
@@ -177,6 +181,12 @@ void compact_pairs(const int2* pairs, const int16_t* slot, const uint32_t* tbase
 void class_bounds(const uint32_t* key_sorted, int64_t n, int shift, int32_t* out9, hipStream_t s);
 // leaf cells (nchild == 0) in cell order; flag/pos are scratch of ncell entries
 void leaf_flags(CellArrays cells, int32_t ncell, uint32_t* flag, hipStream_t s);
+// targets != sources: flag[i] = 1 for the leaves (of the list) holding
+// sorted particles below nt; out[pos[i]] = leaves[i] for the flagged ones
+void target_leaf_flags(CellArrays cells, const int32_t* leaves, int32_t nleaf, int32_t nt, uint32_t* flag,
+                       hipStream_t s);
+void target_leaf_write(const int32_t* leaves, const uint32_t* flag, const uint32_t* pos, int32_t nleaf, int32_t* out,
+                       hipStream_t s);
 // leaves[pos[i]] = i for leaves, inner[i - pos[i]] = i for the other cells
 void leaf_write(CellArrays cells, int32_t ncell, const uint32_t* pos, int32_t* leaves, int32_t* inner,
                 hipStream_t s);
@@ -191,17 +201,18 @@ struct Tables {
     const float* hm2p;   // [2][K] gradient weights of M2P
     const float* rcoef;  // recurrence constants, see expansions kernels
 };
-void p2m(const float4* pts, CellArrays cells, const int32_t* leaves, int32_t nleaves, int p,
+void p2m(const float4* pts, CellArrays cells, const int32_t* leaves, int32_t nleaves, int family, int p,
          int KP, const float* rc, float* M, hipStream_t s);
 // One level of octant translations: the parents are the non-leaf cells of
 // cells [c0, c1) (one tree level), listed in `inner` (non-leaf cells in cell
 // order); leafpos[i] = number of leaves among cells [0, i) (i < ncell), nleaf
 // in all.  m2m: parents' multipoles from their children; l2l: children's
 // locals += translated parent local.
+// (K coefficients per cell, row stride KP)
 void m2m(CellArrays cells, const int32_t* inner, const uint32_t* leafpos, int32_t c0, int32_t c1, int32_t ncell,
-         int32_t nleaf, int p, int KP, Tables t, float* M, hipStream_t s);
+         int32_t nleaf, int K, int KP, Tables t, float* M, hipStream_t s);
 void l2l(CellArrays cells, const int32_t* inner, const uint32_t* leafpos, int32_t c0, int32_t c1, int32_t ncell,
-         int32_t nleaf, int p, int KP, Tables t, float* L, hipStream_t s);
+         int32_t nleaf, int K, int KP, Tables t, float* L, hipStream_t s);
 // M2L of the pairs outside the batched GEMM, given as a CSR list by target,
 // one pair at a time (pairs with skip[a] != 0 are left out; skip may be null)
 void m2l_general(const int32_t* goff, const uint32_t* gsrc, CellArrays cells, int32_t ncell, int p, int KP,
@@ -232,13 +243,13 @@ void cls_ops(const uint64_t* key, const int32_t* start, int32_t ncls, int p, int
              hipStream_t s);
 void cls_skip(const int32_t* pos, int64_t ng, int32_t nbatched, uint8_t* skip, hipStream_t s);
 // the class GEMMs into part (nbatched x KP) and the per-target sums into L
-void m2l_cls(const float* T, const ClsPlan& cp, int p, int KP, const float* M, float* part, const int32_t* goff,
+void m2l_cls(const float* T, const ClsPlan& cp, int K, int KP, const float* M, float* part, const int32_t* goff,
              int32_t ncell, float* L, hipStream_t s);
 // m2pflag: scratch of nleaves bytes; n_m2p: cell-particle pairs in the list;
 // near is updated in place for the leaves with cell-particle sources
 void far_final(const float4* pts, const uint32_t* perm, CellArrays cells, const int32_t* leaves,
                int32_t nleaves, uint8_t* m2pflag, const int32_t* m2p_off, const uint32_t* m2p_src, int64_t n_m2p,
-               int p, int KP, Tables t, const float* M, const float* L, double4* near, int out_dtype,
+               int family, int p, int KP, Tables t, const float* M, const float* L, double4* near, int out_dtype,
                void* phi, void* ex, void* ey, void* ez, hipStream_t s);
 void p2p(const float4* pts, CellArrays cells, const int32_t* leaves, int32_t nleaves,
          const int32_t* p2p_off, const uint32_t* p2p_src, int guard_all, int tpl, double4* near,
@@ -275,18 +286,26 @@ void tile_slots(const int32_t* gather, GemmPlan plan, int NT, int ntiles, int32_
 // e0, e1 (may be null): events recorded just before and after the GEMM kernel
 // itself (without the group sum), for its own duration
 void m2l_gemm(const float* T, const int32_t* offid, const int32_t* gather, const uint32_t* rowcell,
-              GemmPlan plan, int p, int KP, const float* M, float* part, float* L, hipStream_t s,
+              GemmPlan plan, int K, int KP, const float* M, float* part, float* L, hipStream_t s,
               hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 bool m2l_gemm_supported(int p);
+bool m2l_gemm_supported_kp(int KP);  // by storage width
 // split-BF16 variant (Thi/Tlo: k-blocked BF16 halves of the operators)
 // Ms: scratch of ncell * KP * 4 bytes for the split multipoles
 void m2l_gemm_bf16(const uint16_t* Thi, const uint16_t* Tlo, const int32_t* offid, const int32_t* gather,
-                   const uint32_t* rowcell, GemmPlan plan, int p, int KP, const float* M, int64_t ncell, uint4* Ms,
+                   const uint32_t* rowcell, GemmPlan plan, int K, int KP, const float* M, int64_t ncell, uint4* Ms,
                    float* part, float* L, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // L[rowcell[r]][k] = sum over g in order of part[g][r][k], k < K
 void m2l_reduce_groups(const float* part, GemmPlan plan, const uint32_t* rowcell, int KP, int K, float* L,
                        hipStream_t s);
 bool m2l_bf16_supported(int p);
+bool m2l_bf16_supported_kp(int KP);
 int gemm_tile_cols(int p);  // targets per GEMM tile for order p
+int gemm_tile_cols_kp(int KP);  // the same by storage width
+
+// Cartesian counterparts of cls_ops and m2l_general (k_cart.hip)
+void cls_ops_cart(const uint64_t* key, const int32_t* start, int32_t ncls, int p, int KP, float* T, hipStream_t s);
+void m2l_general_cart(const int32_t* goff, const uint32_t* gsrc, CellArrays cells, int32_t ncell, int p, int KP,
+                      const float* M, float* L, const uint8_t* skip, hipStream_t s);
 
 }  // namespace fmm

@@ -277,7 +277,123 @@ int m2l_plan_slots(double theta) {
     return J;
 }
 
-void build_m2l_plan(int p, double theta, M2LPlan& plan) {
+namespace {
+
+// Cartesian operators (multi-indices in graded order, see cart.h)
+int cidx(int a, int b, int c) {
+    int n = a + b + c;
+    return n * (n + 1) * (n + 2) / 6 + (b + c) * (b + c + 1) / 2 + c;
+}
+
+double binom(int n, int k) {
+    double r = 1.0;
+    for (int i = 1; i <= k; i++) r = r * (double)(n - k + i) / (double)i;
+    return r;
+}
+
+template <class F>
+void for_multi(int p, F f) {
+    for (int n = 0; n <= p; n++)
+        for (int a = n; a >= 0; a--)
+            for (int b = n - a; b >= 0; b--) f(n, a, b, n - a - b);
+}
+
+// Taylor coefficients a_n(R) of 1/|R|, |n| <= P (the recurrence of cart.h in FP64)
+void taylor(int P, const double R[3], std::vector<double>& a) {
+    a.assign((size_t)(P + 1) * (P + 2) * (P + 3) / 6, 0.0);
+    const double r2 = R[0] * R[0] + R[1] * R[1] + R[2] * R[2];
+    a[0] = 1.0 / std::sqrt(r2);
+    for_multi(P, [&](int n, int i, int j, int k) {
+        if (n == 0) return;
+        double s1 = 0.0, s2 = 0.0;
+        if (i >= 1) s1 += R[0] * a[cidx(i - 1, j, k)];
+        if (j >= 1) s1 += R[1] * a[cidx(i, j - 1, k)];
+        if (k >= 1) s1 += R[2] * a[cidx(i, j, k - 1)];
+        if (i >= 2) s2 += a[cidx(i - 2, j, k)];
+        if (j >= 2) s2 += a[cidx(i, j - 2, k)];
+        if (k >= 2) s2 += a[cidx(i, j, k - 2)];
+        a[cidx(i, j, k)] = -((2.0 * n - 1.0) / n * s1 + (n - 1.0) / n * s2) / r2;
+    });
+}
+
+double sgnpow(const double v[3], int a, int b, int c) {
+    double r = 1.0;
+    for (int e = 0; e < a; e++) r *= v[0];
+    for (int e = 0; e < b; e++) r *= v[1];
+    for (int e = 0; e < c; e++) r *= v[2];
+    return r;
+}
+
+// scaled M2M of a child at rc*sig from its parent's centre: M~'_k =
+// sum_{a<=k} binom(k,a) (-sig)^(k-a) 2^-|k| M~_a  (row-major out x in)
+void m2m_operator_cart(int p, const double sig[3], std::vector<double>& Mt) {
+    const int K = (p + 1) * (p + 2) * (p + 3) / 6;
+    Mt.assign((size_t)K * K, 0.0);
+    const double ms[3] = {-sig[0], -sig[1], -sig[2]};
+    for_multi(p, [&](int n, int k1, int k2, int k3) {
+        for (int a1 = 0; a1 <= k1; a1++)
+            for (int a2 = 0; a2 <= k2; a2++)
+                for (int a3 = 0; a3 <= k3; a3++)
+                    Mt[(size_t)cidx(k1, k2, k3) * K + cidx(a1, a2, a3)] =
+                        binom(k1, a1) * binom(k2, a2) * binom(k3, a3) * sgnpow(ms, k1 - a1, k2 - a2, k3 - a3) *
+                        std::ldexp(1.0, -n);
+    });
+}
+
+// scaled L2L to a child at rc*sig: L~'_m' = sum_{m>=m'} binom(m,m') sig^(m-m') 2^-(|m|+1) L~_m
+void l2l_operator_cart(int p, const double sig[3], std::vector<double>& Mt) {
+    const int K = (p + 1) * (p + 2) * (p + 3) / 6;
+    Mt.assign((size_t)K * K, 0.0);
+    for_multi(p, [&](int, int a1, int a2, int a3) {
+        for_multi(p, [&](int nm, int m1, int m2, int m3) {
+            if (m1 < a1 || m2 < a2 || m3 < a3) return;
+            Mt[(size_t)cidx(a1, a2, a3) * K + cidx(m1, m2, m3)] =
+                binom(m1, a1) * binom(m2, a2) * binom(m3, a3) * sgnpow(sig, m1 - a1, m2 - a2, m3 - a3) *
+                std::ldexp(1.0, -(nm + 1));
+        });
+    });
+}
+
+// scaled same-level M2L with the source centre at q (target half sides) from
+// the target's: L~_m = sum_{|m|+|k|<=p} C(m,k) a_{m+k}(-q) M~_k
+void m2l_operator_cart(int p, const double q[3], std::vector<double>& Mt) {
+    const int K = (p + 1) * (p + 2) * (p + 3) / 6;
+    Mt.assign((size_t)K * K, 0.0);
+    const double R[3] = {-q[0], -q[1], -q[2]};
+    std::vector<double> a;
+    taylor(p, R, a);
+    for_multi(p, [&](int nm, int m1, int m2, int m3) {
+        for_multi(p - nm, [&](int, int k1, int k2, int k3) {
+            const double C = binom(m1 + k1, k1) * binom(m2 + k2, k2) * binom(m3 + k3, k3);
+            Mt[(size_t)cidx(m1, m2, m3) * K + cidx(k1, k2, k3)] = C * a[cidx(m1 + k1, m2 + k2, m3 + k3)];
+        });
+    });
+}
+
+}  // namespace
+
+void build_tables_cart(int p, HostTables& t) {
+    if (p < 0 || p > 8) throw std::invalid_argument("order out of range");
+    const int K = (p + 1) * (p + 2) * (p + 3) / 6;
+    t = HostTables{};
+    t.p = p;
+    t.K = K;
+    t.KP = kpad_cart(p);
+    t.m2m.assign((size_t)8 * K * K, 0.f);
+    t.l2l.assign((size_t)8 * K * K, 0.f);
+    std::vector<double> Mt;
+    for (int oct = 0; oct < 8; oct++) {
+        double sig[3] = {(oct & 1) ? 1.0 : -1.0, (oct & 2) ? 1.0 : -1.0, (oct & 4) ? 1.0 : -1.0};
+        m2m_operator_cart(p, sig, Mt);
+        for (int j = 0; j < K; j++)
+            for (int k = 0; k < K; k++) t.m2m[((size_t)oct * K + k) * K + j] = (float)Mt[(size_t)j * K + k];
+        l2l_operator_cart(p, sig, Mt);
+        for (int j = 0; j < K; j++)
+            for (int k = 0; k < K; k++) t.l2l[((size_t)oct * K + k) * K + j] = (float)Mt[(size_t)j * K + k];
+    }
+}
+
+void build_m2l_plan(int p, double theta, M2LPlan& plan, bool cartesian) {
     double theta2 = theta * theta;
     int omax = 0;
     while (theta2 * (double)((omax + 1) * (omax + 1)) < 1.0) omax++;
@@ -291,6 +407,7 @@ void build_m2l_plan(int p, double theta, M2LPlan& plan) {
     int W = 2 * R + 1;
     plan.p = p;
     plan.theta = theta;
+    plan.cartesian = cartesian;
     plan.R = R;
     plan.slot_of.assign((size_t)8 * W * W * W, -1);
     std::map<std::array<int, 3>, int> uid;
@@ -326,14 +443,15 @@ void build_m2l_plan(int p, double theta, M2LPlan& plan) {
             size_t ix = ((size_t)(o[0] + R) * W + (o[1] + R)) * W + (o[2] + R);
             plan.slot_of[(size_t)ct * W * W * W + ix] = s;
         }
-    int K = (p + 1) * (p + 1);
-    int KP = kpad(p);
+    int K = cartesian ? (p + 1) * (p + 2) * (p + 3) / 6 : (p + 1) * (p + 1);
+    int KP = cartesian ? kpad_cart(p) : kpad(p);
     size_t noff = plan.offsets.size();
     plan.T.assign(noff * KP * KP, 0.f);
     std::vector<double> Mt;
     for (size_t o = 0; o < noff; o++) {
         double q[3] = {2.0 * plan.offsets[o][0], 2.0 * plan.offsets[o][1], 2.0 * plan.offsets[o][2]};
-        m2l_operator(p, q, 1.0, Mt);
+        if (cartesian) m2l_operator_cart(p, q, Mt);
+        else m2l_operator(p, q, 1.0, Mt);
         for (int j = 0; j < K; j++)
             for (int k = 0; k < K; k++) plan.T[(o * KP + k) * KP + j] = (float)Mt[(size_t)j * K + k];
     }

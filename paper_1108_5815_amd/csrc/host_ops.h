@@ -11,12 +11,15 @@ namespace fmm {
 // Row stride of the coefficient arrays for order p: (p+1)^2 rounded up to a
 // multiple of 32, except that 160 and 224 become 192 and 256 so that every
 // stride has a matrix-core tiling (see k_m2l_gemm.hip).
-inline int kpad(int p) {
-    int k = (((p + 1) * (p + 1) + 31) / 32) * 32;
+inline int kpad_n(int K) {
+    int k = ((K + 31) / 32) * 32;
     if (k == 160) return 192;
     if (k == 224) return 256;
     return k;
 }
+inline int kpad(int p) { return kpad_n((p + 1) * (p + 1)); }
+// the same for Cartesian expansions: (p+1)(p+2)(p+3)/6 coefficients
+inline int kpad_cart(int p) { return kpad_n((p + 1) * (p + 2) * (p + 3) / 6); }
 
 // Recurrence constants shared by the harmonic kernels (float table):
 //   A(n,m) = (2n-1)/sqrt((n-m)(n+m)),  B(n,m) = sqrt((n-m-1)(n+m-1)/((n-m)(n+m)))
@@ -38,6 +41,7 @@ struct HostTables {
 
 struct M2LPlan {
     int p = -1;
+    bool cartesian = false;
     double theta = 0;
     int R = 0;                               // offsets lie in [-R, R]^3
     int J = 0;                               // accepted offsets per octant class
@@ -54,7 +58,10 @@ void split_bf16_kblocked(const std::vector<float>& T, size_t noff, int KP, std::
                          std::vector<uint16_t>& lo);
 
 void build_tables(int p, HostTables& t);
-void build_m2l_plan(int p, double theta, M2LPlan& plan);
+// Cartesian: m2m and l2l only (the other tables stay empty), K = (p+1)(p+2)(p+3)/6
+void build_tables_cart(int p, HostTables& t);
+// cartesian: operators of the Cartesian family (same offsets and slots)
+void build_m2l_plan(int p, double theta, M2LPlan& plan, bool cartesian = false);
 // J of build_m2l_plan for theta, counted without building operators
 int m2l_plan_slots(double theta);
 // the batched same-level GEMM is used up to this many slots per octant class

@@ -394,13 +394,13 @@ void translate_level(CellArrays cells, const int32_t* inner, const uint32_t* lea
 }
 
 void m2m(CellArrays cells, const int32_t* inner, const uint32_t* leafpos, int32_t c0, int32_t c1, int32_t ncell,
-         int32_t nleaf, int p, int KP, Tables t, float* M, hipStream_t s) {
-    translate_level<true>(cells, inner, leafpos, c0, c1, ncell, nleaf, (p + 1) * (p + 1), KP, t.m2m, M, s);
+         int32_t nleaf, int K, int KP, Tables t, float* M, hipStream_t s) {
+    translate_level<true>(cells, inner, leafpos, c0, c1, ncell, nleaf, K, KP, t.m2m, M, s);
 }
 
 void l2l(CellArrays cells, const int32_t* inner, const uint32_t* leafpos, int32_t c0, int32_t c1, int32_t ncell,
-         int32_t nleaf, int p, int KP, Tables t, float* L, hipStream_t s) {
-    translate_level<false>(cells, inner, leafpos, c0, c1, ncell, nleaf, (p + 1) * (p + 1), KP, t.l2l, L, s);
+         int32_t nleaf, int K, int KP, Tables t, float* L, hipStream_t s) {
+    translate_level<false>(cells, inner, leafpos, c0, c1, ncell, nleaf, K, KP, t.l2l, L, s);
 }
 
 void m2l_general(const int32_t* goff, const uint32_t* gsrc, CellArrays cells, int32_t ncell, int p, int KP,

@@ -13,6 +13,7 @@
 // each solid harmonic is consumed by the contraction as soon as the Cartesian
 // recurrence produces it: nothing per particle goes to LDS, only the leaf's
 // local expansion and the current source multipole (read as broadcasts).
+#include "cart.h"
 #include "fmm_internal.h"
 
 namespace fmm {
@@ -156,6 +157,106 @@ __device__ inline void m2p_point(const float* Ms, const float* __restrict__ h, f
     });
 }
 
+// Expansion families, each giving the per-particle pieces of the kernels
+// below at x-hat = (x - c)/r: a P2M row (q times the coefficients of one
+// particle, scaled), and L2P / M2P as (phi, E) of the scaled expansion:
+// the particle's potential is .x / r and its field (.y, .z, .w) / r^2.
+struct Sph {
+    template <int P>
+    static constexpr int K = (P + 1) * (P + 1);
+    template <int P>
+    __device__ static void p2m_row(float x, float y, float z, float qc, float* row, const float* __restrict__ rc) {
+        regular_walk_t<P>(x, y, z, rc, [&](int n, int m, float re, float im) {
+            if (m == 0) {
+                row[n * n] = qc * re;
+            } else {
+                row[n * n + 2 * m - 1] = qc * re;
+                row[n * n + 2 * m] = -qc * im;
+            }
+        });
+    }
+    template <int P>
+    __device__ static float4 l2p(const float* Lt, float x, float y, float z, const float* __restrict__ g,
+                                 const float* __restrict__ rc) {
+        const float s2 = 1.41421356237309505f;
+        float phi = 0.f, l10 = 0.f, l1re = 0.f, l1im = 0.f;
+        l2p_point<P>(Lt, g, x, y, z, rc, phi, l10, l1re, l1im);
+        return make_float4(phi, -s2 * l1re, s2 * l1im, -l10);
+    }
+    template <int P>
+    __device__ static float4 m2p(const float* Ms, float x, float y, float z, const float* __restrict__ h,
+                                 const float* __restrict__ rc) {
+        const float s2 = 1.41421356237309505f;
+        float phi = 0.f, l10 = 0.f, l1re = 0.f, l1im = 0.f;
+        m2p_point<P>(Ms, h, x, y, z, rc, phi, l10, l1re, l1im);
+        return make_float4(phi, -s2 * l1re, s2 * l1im, -l10);
+    }
+};
+
+// Cartesian: M~_k = sum q (-x-hat)^k, phi-hat = sum_m L~_m x-hat^m for a local,
+// sum_k a_k(x-hat) M~_k for a multipole (cart.h); E = -grad phi
+struct Cart {
+    template <int P>
+    static constexpr int K = cart::count(P);
+    template <int P>
+    __device__ static void p2m_row(float x, float y, float z, float qc, float* row, const float* __restrict__) {
+        float px[P + 1], py[P + 1], pz[P + 1];
+        cart::powers<P>(-x, px);
+        cart::powers<P>(-y, py);
+        cart::powers<P>(-z, pz);
+#pragma unroll
+        for (int n = 0; n <= P; n++)
+#pragma unroll
+            for (int a = n; a >= 0; a--)
+#pragma unroll
+                for (int b = n - a; b >= 0; b--) row[cart::index(a, b, n - a - b)] = qc * (px[a] * py[b] * pz[n - a - b]);
+    }
+    template <int P>
+    __device__ static float4 l2p(const float* Lt, float x, float y, float z, const float* __restrict__,
+                                 const float* __restrict__) {
+        float px[P + 1], py[P + 1], pz[P + 1];
+        cart::powers<P>(x, px);
+        cart::powers<P>(y, py);
+        cart::powers<P>(z, pz);
+        float phi = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+#pragma unroll
+        for (int n = 0; n <= P; n++)
+#pragma unroll
+            for (int a = n; a >= 0; a--)
+#pragma unroll
+                for (int b = n - a; b >= 0; b--) {
+                    const int c = n - a - b;
+                    const float L = Lt[cart::index(a, b, c)];
+                    phi += L * (px[a] * py[b] * pz[c]);
+                    if (a > 0) gx += (float)a * L * (px[a - 1] * py[b] * pz[c]);
+                    if (b > 0) gy += (float)b * L * (px[a] * py[b - 1] * pz[c]);
+                    if (c > 0) gz += (float)c * L * (px[a] * py[b] * pz[c - 1]);
+                }
+        return make_float4(phi, -gx, -gy, -gz);
+    }
+    template <int P>
+    __device__ static float4 m2p(const float* Ms, float x, float y, float z, const float* __restrict__,
+                                 const float* __restrict__) {
+        float a[cart::count(P + 1)];
+        cart::taylor<P + 1, float>(x, y, z, a);
+        float phi = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+#pragma unroll
+        for (int n = 0; n <= P; n++)
+#pragma unroll
+            for (int i = n; i >= 0; i--)
+#pragma unroll
+                for (int j = n - i; j >= 0; j--) {
+                    const int k = n - i - j;
+                    const float M = Ms[cart::index(i, j, k)];
+                    phi += a[cart::index(i, j, k)] * M;
+                    gx += (float)(i + 1) * a[cart::index(i + 1, j, k)] * M;
+                    gy += (float)(j + 1) * a[cart::index(i, j + 1, k)] * M;
+                    gz += (float)(k + 1) * a[cart::index(i, j, k + 1)] * M;
+                }
+        return make_float4(phi, -gx, -gy, -gz);
+    }
+};
+
 // Leaves [w LPW, w LPW + LPW) of the leaf list per 64-lane workgroup, their
 // particles flattened (leaf by leaf, in particle order) and taken 64 at a
 // time: leaves hold ~20 particles on average, so one leaf per wave would
@@ -203,11 +304,11 @@ struct LeafPack {
 // P2M: each lane writes q * conj(S(x-c)/r) of one particle into its LDS row,
 // then each leaf's rows are summed column by column in particle order,
 // continuing across rounds (one sequential sum per coefficient and leaf).
-template <int P, int LPW>
+template <int P, int LPW, class X>
 __global__ __launch_bounds__(64) void k_p2m(const float4* __restrict__ pts, CellArrays c,
                                             const int32_t* __restrict__ leaves, int32_t nleaves, int KP,
                                             const float* __restrict__ rc, float* __restrict__ M) {
-    constexpr int K = (P + 1) * (P + 1);
+    constexpr int K = X::template K<P>;
     constexpr int CH = K <= 128 ? 64 : 32;  // rows per round
     constexpr int STR = K | 1;
     constexpr int NU = (K + 63) / 64;
@@ -236,14 +337,7 @@ __global__ __launch_bounds__(64) void k_p2m(const float4* __restrict__ pts, Cell
                         z = (float)(((double)Pt.z - ct.z) * ir);
             const float qc = Pt.w;
             float* row = rows + lane * STR;
-            regular_walk_t<P>(x, y, z, rc, [&](int n, int m, float re, float im) {
-                if (m == 0) {
-                    row[n * n] = qc * re;
-                } else {
-                    row[n * n + 2 * m - 1] = qc * re;
-                    row[n * n + 2 * m] = -qc * im;
-                }
-            });
+            X::template p2m_row<P>(x, y, z, qc, row, rc);
         }
         __syncthreads();
 #pragma unroll
@@ -285,7 +379,7 @@ __global__ void k_m2p_flags(CellArrays c, const int32_t* __restrict__ leaves, in
 // Far field and final sum for every particle: near part (FP64) + L2P of its
 // leaf's local + M2P of the sources paired with its leaf or an ancestor (in
 // that order, as one sequential FP64 sum), written in the caller's order.
-template <int P, int LPW>
+template <int P, int LPW, class X>
 __global__ __launch_bounds__(64) void k_far(const float4* __restrict__ pts, const uint32_t* __restrict__ perm,
                                             CellArrays c, const int32_t* __restrict__ leaves, int32_t nleaves,
                                             const uint8_t* __restrict__ m2pflag,
@@ -295,7 +389,7 @@ __global__ __launch_bounds__(64) void k_far(const float4* __restrict__ pts, cons
                                             const float* __restrict__ L, double4* __restrict__ near,
                                             int out_dtype, void* __restrict__ ophi, void* __restrict__ oex,
                                             void* __restrict__ oey, void* __restrict__ oez) {
-    constexpr int K = (P + 1) * (P + 1);
+    constexpr int K = X::template K<P>;
     __shared__ float Lt[LPW][K];
     __shared__ LeafPack<LPW> lp;
     __shared__ uint8_t s_m2p[LPW];
@@ -313,7 +407,6 @@ __global__ __launch_bounds__(64) void k_far(const float4* __restrict__ pts, cons
         Lt[q][k] = q < lp.nq ? L[(size_t)lp.cell[q] * KP + k] : 0.f;
     }
     __syncthreads();
-    const float s2 = 1.41421356237309505f;
     const int total = lp.pre[LPW];
     for (int r0 = 0; r0 < total; r0 += 64) {
         const int f = r0 + lane;
@@ -327,13 +420,12 @@ __global__ __launch_bounds__(64) void k_far(const float4* __restrict__ pts, cons
             const double ir = 1.0 / ct.w;
             const float x = (float)(((double)Pt.x - ct.x) * ir), y = (float)(((double)Pt.y - ct.y) * ir),
                         z = (float)(((double)Pt.z - ct.z) * ir);
-            float phi = 0.f, l10 = 0.f, l1re = 0.f, l1im = 0.f;
-            l2p_point<P>(Lt[q], gl2p, x, y, z, rc, phi, l10, l1re, l1im);
+            const float4 v = X::template l2p<P>(Lt[q], x, y, z, gl2p, rc);
             const double r1 = ct.w, r2 = ct.w * ct.w;
-            acc.x += (double)phi / r1;
-            acc.y += (double)(-s2 * l1re) / r2;
-            acc.z += (double)(s2 * l1im) / r2;
-            acc.w += (double)(-l10) / r2;
+            acc.x += (double)v.x / r1;
+            acc.y += (double)v.y / r2;
+            acc.z += (double)v.z / r2;
+            acc.w += (double)v.w / r2;
         }
         if (valid && s_m2p[q]) {
             near[i] = acc;  // cell-particle sources follow (k_far_m2p)
@@ -363,7 +455,7 @@ __global__ __launch_bounds__(64) void k_far(const float4* __restrict__ pts, cons
 // the lists are walked level by level: at chain depth k the distinct k-th
 // ancestors of the packed leaves are the list owners, and step t stages the
 // t-th source of every owner once in LDS for all the lanes under it.
-template <int P, int LPW>
+template <int P, int LPW, class X>
 __global__ __launch_bounds__(64) void k_far_m2p(const float4* __restrict__ pts, const uint32_t* __restrict__ perm,
                                                 CellArrays c, const int32_t* __restrict__ leaves, int32_t nleaves,
                                                 const uint8_t* __restrict__ m2pflag,
@@ -373,7 +465,7 @@ __global__ __launch_bounds__(64) void k_far_m2p(const float4* __restrict__ pts, 
                                                 const float* __restrict__ M, const double4* __restrict__ near,
                                                 int out_dtype, void* __restrict__ ophi, void* __restrict__ oex,
                                                 void* __restrict__ oey, void* __restrict__ oez) {
-    constexpr int K = (P + 1) * (P + 1);
+    constexpr int K = X::template K<P>;
     constexpr int MAXD = kMaxLevel + 1;  // a leaf and its ancestors
     __shared__ LeafPack<LPW> lp;
     __shared__ int32_t anc[LPW][MAXD];   // anc[q][k]: k-th ancestor of leaf q, -1 above the root
@@ -405,7 +497,6 @@ __global__ __launch_bounds__(64) void k_far_m2p(const float4* __restrict__ pts, 
     __syncthreads();
     const int total = lp.pre[LPW];
     if (total == 0) return;
-    const float s2 = 1.41421356237309505f;
     for (int r0 = 0; r0 < total; r0 += 64) {
         const int f = r0 + lane;
         const bool valid = f < total;
@@ -455,13 +546,12 @@ __global__ __launch_bounds__(64) void k_far_m2p(const float4* __restrict__ pts, 
                     const double ir = 1.0 / cs.w;
                     const float x = (float)(((double)Pt.x - cs.x) * ir), y = (float)(((double)Pt.y - cs.y) * ir),
                                 z = (float)(((double)Pt.z - cs.z) * ir);
-                    float phi = 0.f, l10 = 0.f, l1re = 0.f, l1im = 0.f;
-                    m2p_point<P>(Ms[o], hm2p, x, y, z, rc, phi, l10, l1re, l1im);
+                    const float4 v = X::template m2p<P>(Ms[o], x, y, z, hm2p, rc);
                     const double r1 = cs.w, r2 = cs.w * cs.w;
-                    acc.x += (double)phi / r1;
-                    acc.y += (double)(-s2 * l1re) / r2;
-                    acc.z += (double)(s2 * l1im) / r2;
-                    acc.w += (double)(-l10) / r2;
+                    acc.x += (double)v.x / r1;
+                    acc.y += (double)v.y / r2;
+                    acc.z += (double)v.z / r2;
+                    acc.w += (double)v.w / r2;
                 }
                 __syncthreads();
             }
@@ -487,91 +577,120 @@ __global__ __launch_bounds__(64) void k_far_m2p(const float4* __restrict__ pts, 
 constexpr int kLeavesPerWave = 8;
 constexpr int kM2pLeavesPerWave = 16;
 
-template <int P>
+template <int P, class X>
 void launch_far(const float4* pts, const uint32_t* perm, CellArrays cells, const int32_t* leaves, int32_t nleaves,
                 uint8_t* m2pflag, const int32_t* m2p_off, const uint32_t* m2p_src, int KP, Tables t, const float* M,
                 const float* L, double4* near, int out_dtype, void* phi, void* ex, void* ey, void* ez, bool any_m2p,
                 hipStream_t s) {
     k_m2p_flags<<<(nleaves + 255) / 256, 256, 0, s>>>(cells, leaves, nleaves, m2p_off, m2pflag);
     constexpr int W = kLeavesPerWave;
-    k_far<P, W><<<(nleaves + W - 1) / W, 64, 0, s>>>(pts, perm, cells, leaves, nleaves, m2pflag, m2p_off, m2p_src, KP,
-                                                     t.gl2p, t.hm2p, t.rcoef, M, L, near, out_dtype, phi, ex, ey, ez);
+    k_far<P, W, X><<<(nleaves + W - 1) / W, 64, 0, s>>>(pts, perm, cells, leaves, nleaves, m2pflag, m2p_off, m2p_src,
+                                                        KP, t.gl2p, t.hm2p, t.rcoef, M, L, near, out_dtype, phi, ex,
+                                                        ey, ez);
     if (any_m2p) {
         constexpr int W2 = kM2pLeavesPerWave;
-        k_far_m2p<P, W2><<<(nleaves + W2 - 1) / W2, 64, 0, s>>>(pts, perm, cells, leaves, nleaves, m2pflag, m2p_off,
-                                                               m2p_src, KP, t.hm2p, t.rcoef, M, near, out_dtype, phi,
-                                                               ex, ey, ez);
+        k_far_m2p<P, W2, X><<<(nleaves + W2 - 1) / W2, 64, 0, s>>>(pts, perm, cells, leaves, nleaves, m2pflag,
+                                                                  m2p_off, m2p_src, KP, t.hm2p, t.rcoef, M, near,
+                                                                  out_dtype, phi, ex, ey, ez);
     }
 }
 
-template <int P>
+template <int P, class X>
 void launch_p2m(const float4* pts, CellArrays cells, const int32_t* leaves, int32_t nleaves, int KP, const float* rc,
                 float* M, hipStream_t s) {
     constexpr int W = kLeavesPerWave;
-    k_p2m<P, W><<<(nleaves + W - 1) / W, 64, 0, s>>>(pts, cells, leaves, nleaves, KP, rc, M);
+    k_p2m<P, W, X><<<(nleaves + W - 1) / W, 64, 0, s>>>(pts, cells, leaves, nleaves, KP, rc, M);
 }
 
 }  // namespace
 
 void far_final(const float4* pts, const uint32_t* perm, CellArrays cells, const int32_t* leaves, int32_t nleaves,
-               uint8_t* m2pflag, const int32_t* m2p_off, const uint32_t* m2p_src, int64_t n_m2p, int p, int KP,
-               Tables t, const float* M, const float* L, double4* near, int out_dtype, void* phi, void* ex, void* ey,
-               void* ez, hipStream_t s) {
+               uint8_t* m2pflag, const int32_t* m2p_off, const uint32_t* m2p_src, int64_t n_m2p, int family, int p,
+               int KP, Tables t, const float* M, const float* L, double4* near, int out_dtype, void* phi, void* ex,
+               void* ey, void* ez, hipStream_t s) {
     if (nleaves <= 0) return;
-#define FMM_FAR_CASE(PP)                                                                                         \
-    case PP:                                                                                                     \
-        launch_far<PP>(pts, perm, cells, leaves, nleaves, m2pflag, m2p_off, m2p_src, KP, t, M, L, near, out_dtype, \
-                       phi, ex, ey, ez, n_m2p > 0, s);                                                           \
+#define FMM_FAR_CASE(PP, XX)                                                                                      \
+    case PP:                                                                                                      \
+        launch_far<PP, XX>(pts, perm, cells, leaves, nleaves, m2pflag, m2p_off, m2p_src, KP, t, M, L, near,       \
+                           out_dtype, phi, ex, ey, ez, n_m2p > 0, s);                                            \
         break;
+    if (family == kFamilyCartesian) {
+        switch (p) {
+            FMM_FAR_CASE(0, Cart)
+            FMM_FAR_CASE(1, Cart)
+            FMM_FAR_CASE(2, Cart)
+            FMM_FAR_CASE(3, Cart)
+            FMM_FAR_CASE(4, Cart)
+            FMM_FAR_CASE(5, Cart)
+            FMM_FAR_CASE(6, Cart)
+            default:
+                break;
+        }
+        return;
+    }
     switch (p) {
-        FMM_FAR_CASE(0)
-        FMM_FAR_CASE(1)
-        FMM_FAR_CASE(2)
-        FMM_FAR_CASE(3)
-        FMM_FAR_CASE(4)
-        FMM_FAR_CASE(5)
-        FMM_FAR_CASE(6)
-        FMM_FAR_CASE(7)
-        FMM_FAR_CASE(8)
-        FMM_FAR_CASE(9)
-        FMM_FAR_CASE(10)
-        FMM_FAR_CASE(11)
-        FMM_FAR_CASE(12)
-        FMM_FAR_CASE(13)
-        FMM_FAR_CASE(14)
-        FMM_FAR_CASE(15)
-        FMM_FAR_CASE(16)
+        FMM_FAR_CASE(0, Sph)
+        FMM_FAR_CASE(1, Sph)
+        FMM_FAR_CASE(2, Sph)
+        FMM_FAR_CASE(3, Sph)
+        FMM_FAR_CASE(4, Sph)
+        FMM_FAR_CASE(5, Sph)
+        FMM_FAR_CASE(6, Sph)
+        FMM_FAR_CASE(7, Sph)
+        FMM_FAR_CASE(8, Sph)
+        FMM_FAR_CASE(9, Sph)
+        FMM_FAR_CASE(10, Sph)
+        FMM_FAR_CASE(11, Sph)
+        FMM_FAR_CASE(12, Sph)
+        FMM_FAR_CASE(13, Sph)
+        FMM_FAR_CASE(14, Sph)
+        FMM_FAR_CASE(15, Sph)
+        FMM_FAR_CASE(16, Sph)
         default:
             break;
     }
 #undef FMM_FAR_CASE
 }
 
-void p2m(const float4* pts, CellArrays cells, const int32_t* leaves, int32_t nleaves, int p, int KP, const float* rc,
-         float* M, hipStream_t s) {
+void p2m(const float4* pts, CellArrays cells, const int32_t* leaves, int32_t nleaves, int family, int p, int KP,
+         const float* rc, float* M, hipStream_t s) {
     if (nleaves <= 0) return;
-#define FMM_P2M_CASE(PP)                                              \
-    case PP:                                                          \
-        launch_p2m<PP>(pts, cells, leaves, nleaves, KP, rc, M, s); \
+#define FMM_P2M_CASE(PP, XX)                                              \
+    case PP:                                                              \
+        launch_p2m<PP, XX>(pts, cells, leaves, nleaves, KP, rc, M, s);    \
         break;
+    if (family == kFamilyCartesian) {
+        switch (p) {
+            FMM_P2M_CASE(0, Cart)
+            FMM_P2M_CASE(1, Cart)
+            FMM_P2M_CASE(2, Cart)
+            FMM_P2M_CASE(3, Cart)
+            FMM_P2M_CASE(4, Cart)
+            FMM_P2M_CASE(5, Cart)
+            FMM_P2M_CASE(6, Cart)
+            default:
+                break;
+        }
+        return;
+    }
     switch (p) {
-        FMM_P2M_CASE(0)
-        FMM_P2M_CASE(1)
-        FMM_P2M_CASE(2)
-        FMM_P2M_CASE(3)
-        FMM_P2M_CASE(4)
-        FMM_P2M_CASE(5)
-        FMM_P2M_CASE(6)
-        FMM_P2M_CASE(7)
-        FMM_P2M_CASE(8)
-        FMM_P2M_CASE(9)
-        FMM_P2M_CASE(10)
-        FMM_P2M_CASE(11)
-        FMM_P2M_CASE(12)
-        FMM_P2M_CASE(13)
-        FMM_P2M_CASE(14)
-        FMM_P2M_CASE(15)
-        FMM_P2M_CASE(16)
+        FMM_P2M_CASE(0, Sph)
+        FMM_P2M_CASE(1, Sph)
+        FMM_P2M_CASE(2, Sph)
+        FMM_P2M_CASE(3, Sph)
+        FMM_P2M_CASE(4, Sph)
+        FMM_P2M_CASE(5, Sph)
+        FMM_P2M_CASE(6, Sph)
+        FMM_P2M_CASE(7, Sph)
+        FMM_P2M_CASE(8, Sph)
+        FMM_P2M_CASE(9, Sph)
+        FMM_P2M_CASE(10, Sph)
+        FMM_P2M_CASE(11, Sph)
+        FMM_P2M_CASE(12, Sph)
+        FMM_P2M_CASE(13, Sph)
+        FMM_P2M_CASE(14, Sph)
+        FMM_P2M_CASE(15, Sph)
+        FMM_P2M_CASE(16, Sph)
         default:
             break;
     }

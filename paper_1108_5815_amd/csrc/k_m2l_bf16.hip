@@ -267,7 +267,7 @@ __global__ void k_split_cells(const float4* __restrict__ M, int64_t ncell, int K
 }  // namespace
 
 void m2l_gemm_bf16(const uint16_t* Thi, const uint16_t* Tlo, const int32_t* offid, const int32_t* gather,
-                   const uint32_t* rowcell, GemmPlan plan, int p, int KP, const float* M, int64_t ncell, uint4* Ms,
+                   const uint32_t* rowcell, GemmPlan plan, int K, int KP, const float* M, int64_t ncell, uint4* Ms,
                    float* part, float* L, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     if (plan.ntiles <= 0) return;
     const int KB = KP / 8;
@@ -283,12 +283,11 @@ void m2l_gemm_bf16(const uint16_t* Thi, const uint16_t* Tlo, const int32_t* offi
         default: return;
     }
     if (e1) (void)hipEventRecord(e1, s);
-    m2l_reduce_groups(part, plan, rowcell, KP, ncoef(p), L, s);
+    m2l_reduce_groups(part, plan, rowcell, KP, K, L, s);
 }
 
-bool m2l_bf16_supported(int p) {
-    const int kp = kpad(p);
-    return kp == 32 || kp == 64 || kp == 96 || kp == 128 || kp == 192;
-}
+bool m2l_bf16_supported(int p) { return m2l_bf16_supported_kp(kpad(p)); }
+
+bool m2l_bf16_supported_kp(int kp) { return kp == 32 || kp == 64 || kp == 96 || kp == 128 || kp == 192; }
 
 }  // namespace fmm

@@ -367,7 +367,7 @@ void cls_skip(const int32_t* pos, int64_t ng, int32_t nbatched, uint8_t* skip, h
     k_cls_skip<<<grid(ng), 256, 0, s>>>(pos, ng, nbatched, skip);
 }
 
-void m2l_cls(const float* T, const ClsPlan& cp, int p, int KP, const float* M, float* part, const int32_t* goff,
+void m2l_cls(const float* T, const ClsPlan& cp, int K, int KP, const float* M, float* part, const int32_t* goff,
              int32_t ncell, float* L, hipStream_t s) {
     if (cp.ntiles <= 0) return;
     switch (KP) {
@@ -379,7 +379,6 @@ void m2l_cls(const float* T, const ClsPlan& cp, int p, int KP, const float* M, f
         case 256: launch<256, 64, 4, 1>(T, cp, M, part, s); break;
         default: return;
     }
-    const int K = (p + 1) * (p + 1);
     k_cls_reduce<<<grid((int64_t)ncell * KP), 256, 0, s>>>(goff, cp.pos, cp.nbatched, ncell, KP, K, part, L);
 }
 

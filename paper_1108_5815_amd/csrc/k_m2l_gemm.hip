@@ -264,10 +264,13 @@ void launch(const float* T, const int32_t* offid, const int32_t* gather, GemmPla
 }  // namespace
 
 bool m2l_gemm_supported(int p) { return gemm_tile_cols(p) > 0; }
+bool m2l_gemm_supported_kp(int KP) { return gemm_tile_cols_kp(KP) > 0; }
 
 // targets per tile for the storage width of order p (0 = no GEMM path)
-int gemm_tile_cols(int p) {
-    switch (kpad(p)) {
+int gemm_tile_cols(int p) { return gemm_tile_cols_kp(kpad(p)); }
+
+int gemm_tile_cols_kp(int KP) {
+    switch (KP) {
         case 32: case 64: case 96: return 128;
         case 128: case 192: case 256: return 64;
         default: return 0;
@@ -285,7 +288,7 @@ void m2l_reduce_groups(const float* part, GemmPlan plan, const uint32_t* rowcell
 }
 
 void m2l_gemm(const float* T, const int32_t* offid, const int32_t* gather, const uint32_t* rowcell, GemmPlan plan,
-              int p, int KP, const float* M, float* part, float* L, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+              int K, int KP, const float* M, float* part, float* L, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     if (plan.ntiles <= 0) return;
     if (e0) (void)hipEventRecord(e0, s);
     switch (KP) {
@@ -298,7 +301,7 @@ void m2l_gemm(const float* T, const int32_t* offid, const int32_t* gather, const
         default: return;
     }
     if (e1) (void)hipEventRecord(e1, s);
-    m2l_reduce_groups(part, plan, rowcell, KP, ncoef(p), L, s);
+    m2l_reduce_groups(part, plan, rowcell, KP, K, L, s);
 }
 
 }  // namespace fmm

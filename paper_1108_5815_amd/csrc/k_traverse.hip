@@ -491,7 +491,32 @@ __global__ void k_leaf_write(CellArrays c, int32_t ncell, const uint32_t* __rest
     else inner[i - (int32_t)pos[i]] = i;
 }
 
+// leaves holding target particles (sorted positions below nt)
+__global__ void k_target_leaf_flags(CellArrays c, const int32_t* __restrict__ leaves, int32_t nleaf, int32_t nt,
+                                    uint32_t* __restrict__ flag) {
+    int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < nleaf) flag[i] = c.begin[leaves[i]] < nt ? 1u : 0u;
+}
+
+__global__ void k_target_leaf_write(const int32_t* __restrict__ leaves, const uint32_t* __restrict__ flag,
+                                    const uint32_t* __restrict__ pos, int32_t nleaf, int32_t* __restrict__ out) {
+    int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < nleaf && flag[i]) out[pos[i]] = leaves[i];
+}
+
 }  // namespace
+
+void target_leaf_flags(CellArrays cells, const int32_t* leaves, int32_t nleaf, int32_t nt, uint32_t* flag,
+                       hipStream_t s) {
+    if (nleaf <= 0) return;
+    k_target_leaf_flags<<<(nleaf + 255) / 256, 256, 0, s>>>(cells, leaves, nleaf, nt, flag);
+}
+
+void target_leaf_write(const int32_t* leaves, const uint32_t* flag, const uint32_t* pos, int32_t nleaf, int32_t* out,
+                       hipStream_t s) {
+    if (nleaf <= 0) return;
+    k_target_leaf_write<<<(nleaf + 255) / 256, 256, 0, s>>>(leaves, flag, pos, nleaf, out);
+}
 
 void class_bounds(const uint32_t* key_sorted, int64_t n, int shift, int32_t* out9, hipStream_t s) {
     k_class_bounds<<<1, 64, 0, s>>>(key_sorted, n, shift, out9);

@@ -498,3 +498,72 @@ def test_fmm_scale_covariance(ora):
         assert np.array_equal(L1[k][0], L2[k][0]) and np.array_equal(L1[k][1], L2[k][1])
     assert np.allclose(phi2, phi / 4, rtol=1e-13, atol=0)
     assert np.allclose(E2, E / 16, rtol=1e-12, atol=1e-14 * np.abs(E).max())
+
+
+# ---------------------------------------------------------------- targets != sources
+def _ts_sets(nt=600, ns=800, seed=41):
+    t = np.stack(synth.uniform_cube(nt, seed), 1) * 1.6 - 0.3        # overlaps the shell and its inside
+    s = np.stack(synth.sphere_shell(ns, seed + 1), 1)
+    q = synth.charges_uniform(ns, seed + 2)
+    return t, s, q
+
+
+@pytest.mark.parametrize("policy,costs", [(0, (0, 0, 0)), (1, (0, 0, 0)), (2, (50.0, 4.0, 1.0))])
+@pytest.mark.parametrize("theta", [0.5, 0.4])
+def test_ts_coverage_exactly_once(ora, policy, costs, theta):
+    """Separate target and source trees ("Dual tree traversal"): every
+    (target, source) particle pair is covered by exactly one emitted
+    interaction, every list pairs a target-tree cell with a source-tree cell,
+    and accepted pairs satisfy the criterion."""
+    t, s, q = _ts_sets()
+    tr = ora.Tree.targets_sources(t, s, 6)
+    tr.traverse(theta, policy, costs)
+    L = tr.lists()
+    c = tr.cells()
+    nt, ns = t.shape[0], s.shape[0]
+    is_t = c["begin"] < nt
+    cnt = np.zeros((nt, ns), np.int64)
+    for k in (0, 1, 2):
+        for a, b in zip(*L[k]):
+            assert is_t[a] and not is_t[b]
+            if k != 2:
+                assert _mac_accepts(c, a, b, theta)
+            cnt[c["begin"][a]:c["end"][a], c["begin"][b] - nt:c["end"][b] - nt] += 1
+    assert np.all(cnt == 1)
+
+
+def test_ts_values_against_direct_and_same_set(ora):
+    """The potential and field at the targets due to the sources match the
+    direct sum within the method's error, the error falls with p, and with the
+    targets equal to the sources the two-tree evaluation equals the one-tree
+    evaluation bit for bit."""
+    t, s, q = _ts_sets(1500, 2000, 5)
+    pd, Ed = ora.direct_st(s, q, t)
+    errs = []
+    for p in (4, 8, 12):
+        tr = ora.Tree.targets_sources(t, s, 16)
+        tr.traverse(0.5, 0)
+        phi, E = tr.evaluate(p, q)
+        errs.append(ora.rel_l2(phi, pd))
+        if p == 12:
+            assert ora.rel_l2(phi, pd) < 1e-6 and ora.rel_l2(E, Ed) < 1e-5
+    assert errs[0] > errs[1] > errs[2]
+    x, y, z = synth.plummer(3000, 7)
+    qq = synth.charges_uniform(3000, 8)
+    P = np.stack([x, y, z], 1)
+    two = ora.Tree.targets_sources(P, P, 16)
+    two.traverse(0.5, 0)
+    ph2, E2 = two.evaluate(8, qq)
+    po, Eo, _ = ora.fmm(x, y, z, qq, 8, 0.5, 16)
+    assert np.array_equal(ph2, po) and np.array_equal(E2, Eo)
+
+
+def test_ts_empty_sides(ora):
+    t, s, q = _ts_sets(50, 70)
+    none = ora.Tree.targets_sources(t, s[:0], 8)
+    none.traverse(0.5, 0)
+    phi, E = none.evaluate(6, q[:0])
+    assert phi.size == 50 and np.all(phi == 0) and np.all(E == 0)
+    only_src = ora.Tree.targets_sources(t[:0], s, 8)
+    only_src.traverse(0.5, 0)
+    assert all(only_src.lists()[k][0].size == 0 for k in (0, 1, 2))
