@@ -56,7 +56,10 @@ typedef enum {
     FMM_POLICY_FMM = 0,
     FMM_POLICY_TREECODE = 1,
     FMM_POLICY_HYBRID_TIMED = 2, /* unit costs from fmm_tune() or fmm_set_costs() */
-    FMM_POLICY_HYBRID_MLP = 3    /* learned cost model */
+    FMM_POLICY_HYBRID_MLP = 3    /* learned cost model, with the timed unit costs (when set) as its
+                                    fallback: they decide the pairs whose two least predicted costs
+                                    lie within 1/8 (log2 units) of each other, and every pair when
+                                    no model is loaded */
 } fmm_policy;
 
 typedef enum {
@@ -262,6 +265,35 @@ fmm_status fmm_set_expansion(fmm_ctx ctx, int32_t expansion, int32_t auto_cartes
 fmm_status fmm_get_expansion(fmm_ctx ctx, int32_t *family);
 
 /*
+ * M2L of the accepted cell pairs outside the batched same-level GEMM (mixed
+ * levels, or same-level pairs whose parents were at different levels): the
+ * paper chooses between translation schemes per pair ("Dual tree
+ * traversal": rotation-based or plane-wave translations; "Introduction to
+ * treecodes & FMM": fast translations cost p^4 or less instead of p^6).
+ *   FMM_M2L_CLASS_DENSE    (default) pairs grouped by (level difference,
+ *                          offset) into classes, one operator per class and
+ *                          matrix-core products per class; pairs outside the
+ *                          class key one by one with the dense O(p^4) kernel
+ *   FMM_M2L_CLASS_ROTATION as above, the pairs outside the key by rotation
+ *   FMM_M2L_PAIR_DENSE     every such pair one by one, dense
+ *   FMM_M2L_PAIR_ROTATION  every such pair one by one by rotation: the
+ *                          multipole rotated to the offset's axis, translated
+ *                          along it (orders m decouple), rotated back, O(p^3)
+ * The Cartesian family always takes the class products and its dense
+ * per-pair kernel.  Results differ by rounding only.  fmm_autotune times the
+ * four on the current lists and keeps the fastest.  Setting it after a
+ * traversal regroups that traversal's pairs.
+ */
+enum {
+    FMM_M2L_CLASS_DENSE = 0,
+    FMM_M2L_CLASS_ROTATION = 1,
+    FMM_M2L_PAIR_DENSE = 2,
+    FMM_M2L_PAIR_ROTATION = 3
+};
+fmm_status fmm_set_m2l_kernel(fmm_ctx ctx, int32_t kind);
+fmm_status fmm_get_m2l_kernel(fmm_ctx ctx, int32_t *kind);
+
+/*
  * Unit costs of the timed hybrid (paper: "Kernel pre-calculation"): the
  * modelled time of an accepted pair is c_m2l for M2L, c_m2p * n_t for M2P and
  * (c_p2p * n_t) * n_s for P2P (n_t, n_s = particles of the target and source
@@ -345,7 +377,11 @@ fmm_status fmm_costmodel_load(fmm_ctx ctx, const char *path, int32_t p, int32_t 
 
 /* The choice table the traversal reads for (p, theta): 9 x 81 x 81 x 4
  * entries (level difference + 4, quarter-octave bucket of n_t, of n_s,
- * distance-ratio bin), each 0 M2L, 1 M2P or 2 P2P; host array. */
+ * distance-ratio bin), each 0 M2L, 1 M2P or 2 P2P; host array.  With unit
+ * costs set, an entry whose two least predictions (log2 ns) differ by less
+ * than 1/8 holds the timed choice at the bucket's counts n = 2^(bucket/4)
+ * (c_m2l, c_m2p n_t, (c_p2p n_t) n_s in FP64; least wins, ties to M2L, then
+ * M2P). */
 #define FMM_MLP_TABLE (9 * 81 * 81 * 4)
 fmm_status fmm_costmodel_table(fmm_ctx ctx, int32_t p, double theta, uint8_t *table);
 
@@ -441,9 +477,11 @@ fmm_status fmm_set_overlap(fmm_ctx ctx, int32_t schedule);
  * lists (e.g. the batch about to be evaluated repeatedly).  Leaves fall in
  * four size classes (at most 8, 16, 32 or more particles); for each class it
  * times the P2P kernel with 1, 2 and 4 targets per lane (`reps` launches
- * each, events on the context stream) and keeps the fastest, then times
- * fmm_evaluate at `precision` under the three schedules of fmm_set_overlap
- * and keeps the fastest.  The schedule does not change results; the
+ * each, events on the context stream) and keeps the fastest; if the lists
+ * hold M2L pairs outside the same-level GEMM (spherical family) it times
+ * fmm_evaluate under the four kinds of fmm_set_m2l_kernel and keeps the
+ * fastest; then it times fmm_evaluate at `precision` under the three
+ * schedules of fmm_set_overlap and keeps the fastest.  The schedule does not change results; the
  * tile shape changes how each target's P2P sum is split into FP32 partials,
  * so results move by rounding only (each choice is itself deterministic).
  * Requires a completed traversal.  Default before tuning: 4 targets per lane,

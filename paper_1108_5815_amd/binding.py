@@ -15,6 +15,7 @@ _LIB_PATH = os.path.join(_HERE, "libfmm.so")
 
 POLICY_FMM, POLICY_TREECODE, POLICY_HYBRID_TIMED, POLICY_HYBRID_MLP = 0, 1, 2, 3
 EXPANSION_SPHERICAL, EXPANSION_CARTESIAN, EXPANSION_AUTO = 0, 1, 2
+M2L_CLASS_DENSE, M2L_CLASS_ROTATION, M2L_PAIR_DENSE, M2L_PAIR_ROTATION = 0, 1, 2, 3
 PREC_FP32, PREC_SPLIT_BF16 = 0, 1
 F32, F64 = 0, 1
 LIST_M2L, LIST_M2P, LIST_P2P = 0, 1, 2
@@ -88,6 +89,8 @@ def lib():
         "fmm_costmodel_load": ([vp, ctypes.c_char_p, i32, i32], ctypes.c_int),
         "fmm_m2l_slots": ([i32, dbl, vp, vp], ctypes.c_int),
         "fmm_set_expansion": ([vp, i32, i32], ctypes.c_int),
+        "fmm_set_m2l_kernel": ([vp, i32], ctypes.c_int),
+        "fmm_get_m2l_kernel": ([vp, vp], ctypes.c_int),
         "fmm_get_expansion": ([vp, vp], ctypes.c_int),
         "fmm_evaluate_noalloc": ([vp, i32, i32, vp, vp, vp, vp], ctypes.c_int),
     }
@@ -288,6 +291,15 @@ class FMM:
         EXPANSION_AUTO the Cartesian family is taken for p <= auto_cartesian_max_p."""
         self._ck(lib().fmm_set_expansion(self.h, int(expansion), int(auto_cartesian_max_p)))
 
+    def set_m2l_kernel(self, kind: int):
+        """Kernel of the M2L pairs outside the same-level GEMM (M2L_*)."""
+        self._ck(lib().fmm_set_m2l_kernel(self.h, int(kind)))
+
+    def m2l_kernel(self) -> int:
+        v = ctypes.c_int32()
+        self._ck(lib().fmm_get_m2l_kernel(self.h, ctypes.byref(v)))
+        return v.value
+
     def expansion(self) -> int:
         """Family of the last traversal (EXPANSION_SPHERICAL or EXPANSION_CARTESIAN)."""
         v = ctypes.c_int32()
@@ -383,7 +395,7 @@ class FMM:
         tpl = np.zeros(4, np.int32)
         ov = ctypes.c_int32()
         self._ck(lib().fmm_get_tile_config(self.h, _ptr(tpl), ctypes.byref(ov)))
-        return {"p2p_targets_per_lane": tpl.tolist(), "schedule": int(ov.value)}
+        return {"p2p_targets_per_lane": tpl.tolist(), "schedule": int(ov.value), "m2l_kernel": self.m2l_kernel()}
 
     def set_tile_config(self, tpl):
         a = np.ascontiguousarray(np.asarray(tpl, dtype=np.int32))

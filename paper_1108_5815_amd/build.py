@@ -16,7 +16,7 @@ OUT = os.path.join(HERE, "libfmm.so")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 
 SOURCES = ["k_util.hip", "k_tree.hip", "k_traverse.hip", "k_expand.hip", "k_far.hip", "k_p2p.hip", "k_mlp.hip",
-           "k_m2l_gemm.hip", "k_m2l_bf16.hip", "k_m2l_cls.hip", "k_work.hip", "k_noalloc.hip", "k_cart.hip", "host_ops.cpp", "capi.cpp"]
+           "k_m2l_gemm.hip", "k_m2l_bf16.hip", "k_m2l_cls.hip", "k_work.hip", "k_noalloc.hip", "k_cart.hip", "k_m2l_rot.hip", "host_ops.cpp", "capi.cpp"]
 
 ARCH = os.environ.get("FMM_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-Wno-unused-result",

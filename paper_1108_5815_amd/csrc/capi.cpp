@@ -126,7 +126,9 @@ struct fmm_ctx_s {
 
     // operator tables
     HostTables ht;
-    Buf d_m2m, d_l2l, d_w, d_g, d_h, d_rc;
+    Buf d_m2m, d_l2l, d_w, d_g, d_h, d_rc, d_wrot;
+    // M2L of the cell pairs outside the same-level GEMM (FMM_M2L_*)
+    int m2l_kind = 0;
 
     // learned cost model: weights, Adam moments, training records, choice table
     Buf d_mlp, d_mlp_m, d_mlp_v, d_grad, d_grad_rec, d_loss_rec, d_feat, d_kind, d_tgt, d_table;
@@ -134,7 +136,7 @@ struct fmm_ctx_s {
     // what the model was trained for (-1 / NaN where unknown)
     int cm_p = -1, cm_precision = -1, cm_records = 0;
     double cm_theta = -1, cm_loss = NAN, cm_seconds = NAN;
-    int mlp_version = 0, table_version = -1, table_p = -1;
+    int mlp_version = 0, table_version = -1, table_p = -1, costs_version = 0, table_costs_version = -1;
     double table_theta = -1;
     std::vector<float> rec_feat, rec_tgt;
     std::vector<int32_t> rec_kind;
@@ -163,7 +165,7 @@ struct fmm_ctx_s {
                       &d_seg, &d_bt, &d_pb, &d_box, &d_frame, &inst, &bsort, &tact, &tnact,
                       &leaves_cls, &inner, &leafpos, &m2pflag, &m2lslot, &tbounds, &lkey, &lval, &lkey2, &lval2, &at_out, &m2l_part, &Msplit, &nbucket, &kinds, &ckey, &ckey2, &cval, &cval2,
                       &chead, &choff, &cstart, &cpos, &csrcs, &cnt_t, &ctbase, &ctile, &cT, &cskip, &cls_part,
-                      &ts_stage, &tleaves};
+                      &ts_stage, &tleaves, &d_wrot};
         for (Buf* b : all) bufs.push_back(b);
     }
 };
@@ -314,6 +316,7 @@ Tables tables_of(fmm_ctx c) {
     t.gl2p = (const float*)c->d_g.p;
     t.hm2p = (const float*)c->d_h.p;
     t.rcoef = (const float*)c->d_rc.p;
+    t.wax = (const float*)c->d_wrot.p;
     return t;
 }
 
@@ -596,6 +599,7 @@ void upload_tables(fmm_ctx c, int p) {
     to_dev(c, need<float>(c, c->d_g, t.gl2p.size()), t.gl2p.data(), t.gl2p.size());
     to_dev(c, need<float>(c, c->d_h, t.hm2p.size()), t.hm2p.data(), t.hm2p.size());
     to_dev(c, need<float>(c, c->d_rc, t.rcoef.size()), t.rcoef.data(), t.rcoef.size());
+    to_dev(c, need<float>(c, c->d_wrot, t.wrot.size()), t.wrot.data(), t.wrot.size());
     c->tables_p = p;
     c->tables_fam = c->fam;
 }
@@ -626,6 +630,9 @@ void upload_plan_bf16(fmm_ctx c) {
 // goff) keyed by class, sorted, and given one operator per class.
 void build_classes(fmm_ctx c, int p) {
     c->cp = ClsPlan{};
+    // the per-pair kinds take every pair outside the same-level GEMM one by one
+    if (c->fam == kFamilySpherical && (c->m2l_kind == FMM_M2L_PAIR_DENSE || c->m2l_kind == FMM_M2L_PAIR_ROTATION))
+        return;
     const int64_t ng = c->ngeneral;
     const int KP = c_kp(c);
     const int NT = cls_tile_cols(KP);
@@ -693,8 +700,11 @@ void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
     if (policy < 0 || policy > 3) fail(FMM_ERR_INVALID_ARG, "unknown policy");
     if (policy == FMM_POLICY_HYBRID_TIMED && !c->costs_set)
         fail(FMM_ERR_STATE, "timed hybrid needs unit costs (fmm_tune or fmm_set_costs)");
-    if (policy == FMM_POLICY_HYBRID_MLP && !c->mlp_ready)
-        fail(FMM_ERR_STATE, "learned hybrid needs a trained cost model");
+    // the timed pre-calculation stands in for a learned model that is missing
+    if (policy == FMM_POLICY_HYBRID_MLP && !c->mlp_ready) {
+        if (!c->costs_set) fail(FMM_ERR_STATE, "learned hybrid needs a trained cost model (or unit costs to fall back on)");
+        policy = FMM_POLICY_HYBRID_TIMED;
+    }
     // expansion family: spherical harmonics, or the Cartesian Taylor series
     // the hybrid method switches to at low accuracy ("Hybrid treecode/FMM
     // algorithm"): asked for, or chosen by order under FMM_EXPANSION_AUTO
@@ -728,12 +738,15 @@ void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
     tp.mlp_table = nullptr;
     tp.nbucket = nullptr;
     if (policy == FMM_POLICY_HYBRID_MLP) {
-        if (c->table_p != p || c->table_theta != theta || c->table_version != c->mlp_version) {
-            mlp_table((const float*)c->d_mlp.p, p, (float)theta, need<uint8_t>(c, c->d_table, kMlpTable), s);
+        if (c->table_p != p || c->table_theta != theta || c->table_version != c->mlp_version ||
+            c->table_costs_version != c->costs_version) {
+            mlp_table((const float*)c->d_mlp.p, p, (float)theta, c->costs_set ? c->costs : nullptr,
+                      need<uint8_t>(c, c->d_table, kMlpTable), s);
             check_launch("cost model table");
             c->table_p = p;
             c->table_theta = theta;
             c->table_version = c->mlp_version;
+            c->table_costs_version = c->costs_version;
         }
         tp.mlp_table = (const uint8_t*)c->d_table.p;
         uint8_t* nb = need<uint8_t>(c, c->nbucket, nc);
@@ -1026,6 +1039,8 @@ void evaluate_on(fmm_ctx c, int32_t precision, int32_t out_dtype, void* phi, voi
         const uint8_t* skip = c->cp.nbatched > 0 ? (const uint8_t*)c->cskip.p : nullptr;
         if (fam == kFamilyCartesian)
             m2l_general_cart((int32_t*)c->goff.p, (uint32_t*)c->gsr.p, ca, nc, p, KP, M, L, skip, s);
+        else if (c->m2l_kind == FMM_M2L_CLASS_ROTATION || c->m2l_kind == FMM_M2L_PAIR_ROTATION)
+            m2l_rotation((int32_t*)c->goff.p, (uint32_t*)c->gsr.p, ca, nc, p, KP, tb.wax, M, L, skip, s);
         else
             m2l_general((int32_t*)c->goff.p, (uint32_t*)c->gsr.p, ca, nc, p, KP, tb, M, L, skip, s);
     }
@@ -1298,6 +1313,23 @@ fmm_status fmm_set_expansion(fmm_ctx c, int32_t expansion, int32_t auto_cartesia
     });
 }
 
+fmm_status fmm_set_m2l_kernel(fmm_ctx c, int32_t kind) {
+    return guarded(c, [&] {
+        if (kind < FMM_M2L_CLASS_DENSE || kind > FMM_M2L_PAIR_ROTATION) fail(FMM_ERR_INVALID_ARG, "unknown M2L kind");
+        const bool rebuild = c->traversed && c->m2l_kind != kind;
+        c->m2l_kind = kind;
+        // the class batching of the current lists follows the new kind
+        if (rebuild) build_classes(c, c->p);
+    });
+}
+
+fmm_status fmm_get_m2l_kernel(fmm_ctx c, int32_t* kind) {
+    return guarded(c, [&] {
+        if (!kind) fail(FMM_ERR_INVALID_ARG, "null pointer");
+        *kind = c->m2l_kind;
+    });
+}
+
 fmm_status fmm_get_expansion(fmm_ctx c, int32_t* family) {
     return guarded(c, [&] {
         if (!family) fail(FMM_ERR_INVALID_ARG, "null pointer");
@@ -1313,6 +1345,7 @@ fmm_status fmm_set_costs(fmm_ctx c, double c_m2l, double c_m2p, double c_p2p) {
         c->costs[1] = c_m2p;
         c->costs[2] = c_p2p;
         c->costs_set = true;
+        c->costs_version++;
     });
 }
 
@@ -1397,6 +1430,7 @@ fmm_status fmm_tune(fmm_ctx c, int32_t p, int32_t precision) {
         c->costs[1] = c_m2p;
         c->costs[2] = c_p2p;
         c->costs_set = true;
+        c->costs_version++;
     });
 }
 
@@ -1749,6 +1783,7 @@ fmm_status fmm_costmodel_load(fmm_ctx c, const char* path, int32_t p, int32_t pr
         if (has_costs) {
             for (int k = 0; k < 3; k++) c->costs[k] = cst[k];
             c->costs_set = true;
+            c->costs_version++;
         }
         for (int k = 0; k < kLeafClasses; k++) c->p2p_tpl[k] = tpl[k];
         c->schedule = sched;
@@ -1807,11 +1842,12 @@ fmm_status fmm_costmodel_table(fmm_ctx c, int32_t p, double theta, uint8_t* tabl
         if (!c->mlp_ready) fail(FMM_ERR_STATE, "no cost model");
         if (p < 0 || p > FMM_P_MAX || !(theta > 0.0 && theta < 1.0)) fail(FMM_ERR_INVALID_ARG, "bad p or theta");
         uint8_t* d = need<uint8_t>(c, c->d_table, kMlpTable);
-        mlp_table((const float*)c->d_mlp.p, p, (float)theta, d, c->stream);
+        mlp_table((const float*)c->d_mlp.p, p, (float)theta, c->costs_set ? c->costs : nullptr, d, c->stream);
         check_launch("cost model table");
         c->table_p = p;
         c->table_theta = theta;
         c->table_version = c->mlp_version;
+        c->table_costs_version = c->costs_version;
         to_host<uint8_t>(c, table, d, kMlpTable);
     });
 }
@@ -2020,10 +2056,27 @@ fmm_status fmm_autotune(fmm_ctx c, int32_t precision, int32_t reps) {
                 }
             }
         }
-        // schedule: P2P concurrent with the far field, or everything in order
         float* o = need<float>(c, c->at_out, (size_t)4 * c->n);
         const bool timing = c->timing;
         c->timing = false;
+        // kernel of the M2L pairs outside the same-level GEMM: class-batched
+        // matrix-core products or one pair at a time, dense or by rotation
+        if (c->ngeneral > 0 && c->fam == kFamilySpherical) {
+            double bestk = INFINITY;
+            int pick = c->m2l_kind;
+            for (int kind = FMM_M2L_CLASS_DENSE; kind <= FMM_M2L_PAIR_ROTATION; kind++) {
+                c->m2l_kind = kind;
+                build_classes(c, c->p);
+                double t = timed([&] { evaluate_impl(c, precision, FMM_F32, o, o + c->n, o + 2 * c->n, o + 3 * c->n); });
+                if (t < bestk) {
+                    bestk = t;
+                    pick = kind;
+                }
+            }
+            c->m2l_kind = pick;
+            build_classes(c, c->p);
+        }
+        // schedule: P2P concurrent with the far field, or everything in order
         double best = INFINITY;
         int pick = 0;
         for (int sc = 0; sc < 3; sc++) {

@@ -123,7 +123,10 @@ void mlp_adam(float* w, float* m, float* v, const float* g, int step, float lr, 
 // returns the particle count; writes the particles if x is not null
 int64_t clustered_points(int L, int per, int per_lo, uint64_t seed, float* x, float* y, float* z, float* q,
                          hipStream_t s);
-void mlp_table(const float* w, int p, float theta, uint8_t* table, hipStream_t s);
+// costs (may be null): timed unit costs for the entries whose two least
+// predictions lie within kMlpFallbackMargin log2 units of each other
+constexpr float kMlpFallbackMargin = 0.125f;
+void mlp_table(const float* w, int p, float theta, const double* costs, uint8_t* table, hipStream_t s);
 
 // ------------------------------------------------------------------ traversal
 struct TravParams {
@@ -200,6 +203,7 @@ struct Tables {
     const float* gl2p;   // [2][K] gradient weights of L2P, (k) x (n, m+n)
     const float* hm2p;   // [2][K] gradient weights of M2P
     const float* rcoef;  // recurrence constants, see expansions kernels
+    const float* wax;    // [p+1][p+1][p+1] axial M2L weights of the rotation-based M2L
 };
 void p2m(const float4* pts, CellArrays cells, const int32_t* leaves, int32_t nleaves, int family, int p,
          int KP, const float* rc, float* M, hipStream_t s);
@@ -302,6 +306,11 @@ bool m2l_bf16_supported(int p);
 bool m2l_bf16_supported_kp(int KP);
 int gemm_tile_cols(int p);  // targets per GEMM tile for order p
 int gemm_tile_cols_kp(int KP);  // the same by storage width
+
+// M2L of the same pairs as m2l_general, one pair at a time through a
+// rotation to the offset's axis (k_m2l_rot.hip; spherical family)
+void m2l_rotation(const int32_t* goff, const uint32_t* gsrc, CellArrays cells, int32_t ncell, int p, int KP,
+                  const float* Wax, const float* M, float* L, const uint8_t* skip, hipStream_t s);
 
 // Cartesian counterparts of cls_ops and m2l_general (k_cart.hip)
 void cls_ops_cart(const uint64_t* key, const int32_t* start, int32_t ncls, int p, int KP, float* T, hipStream_t s);

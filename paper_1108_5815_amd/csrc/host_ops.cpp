@@ -243,6 +243,14 @@ void build_tables(int p, HostTables& t) {
                        (Nnm(n, m) * Nnm(1, k));
                 t.hm2p[(size_t)k * K + n * n + n + m] = (float)h.real();
             }
+    // axial M2L (offset along +z): L_j^k = sum_n W(j,n,k) M_n^k / rho^(j+n+1),
+    // theorem 3.4 at polar angle 0, W = (-1)^(k+n) (j+n)! / (N(n,k) N(j,k))
+    t.wrot.assign((size_t)(p + 1) * (p + 1) * (p + 1), 0.f);
+    for (int j = 0; j <= p; j++)
+        for (int n = 0; n <= p; n++)
+            for (int k = 0; k <= std::min(j, n); k++)
+                t.wrot[((size_t)j * (p + 1) + n) * (p + 1) + k] =
+                    (float)((((k + n) & 1) ? -1.0 : 1.0) * fact(j + n) / (Nnm(n, k) * Nnm(j, k)));
     t.rcoef.assign(kRcSize, 0.f);
     for (int n = 0; n <= kRcN; n++)
         for (int m = 0; m <= n; m++) {

@@ -37,6 +37,7 @@ struct HostTables {
     std::vector<float> gl2p;   // [2][K]
     std::vector<float> hm2p;   // [2][K]
     std::vector<float> rcoef;  // kRcSize
+    std::vector<float> wrot;   // [p+1][p+1][p+1]: axial M2L weights W(j, n, k) of the rotation-based M2L
 };
 
 struct M2LPlan {

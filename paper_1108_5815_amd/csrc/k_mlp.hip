@@ -169,7 +169,13 @@ __global__ void k_clustered(int L, int per, int per_lo, uint64_t seed, float* __
 
 // Evaluate the network over the quantised feature grid of the traversal:
 // entry (dl, bt, bs, bq) -> kind of least predicted log time (ties: M2L, M2P).
-__global__ void k_mlp_table(const float* __restrict__ w, int p, float theta, uint8_t* __restrict__ table) {
+// Where the two least predictions lie within kMlpFallbackMargin (log2 units)
+// and unit costs are given (cost[3] > 0), the entry takes the timed
+// pre-calculation's choice at the bucket's particle counts instead: c_m2l,
+// c_m2p n_t, (c_p2p n_t) n_s in FP64 with n = 2^(bucket / 4), least wins,
+// ties to M2L, then M2P.
+__global__ void k_mlp_table(const float* __restrict__ w, int p, float theta, double c_m2l, double c_m2p,
+                            double c_p2p, int use_costs, uint8_t* __restrict__ table) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= kMlpTable) return;
     int rem = e;
@@ -205,7 +211,24 @@ __global__ void k_mlp_table(const float* __restrict__ w, int p, float theta, uin
         best = o[1];
         k = 1;
     }
-    if (o[2] < best) k = 2;
+    if (o[2] < best) {
+        best = o[2];
+        k = 2;
+    }
+    float second = INFINITY;
+    for (int j = 0; j < O; j++)
+        if (j != k) second = fminf(second, o[j]);
+    if (use_costs && second - best < kMlpFallbackMargin) {
+        const double nt = exp2((double)bt / kMlpNsub), ns = exp2((double)bs / kMlpNsub);
+        const double c0 = c_m2l, c1 = c_m2p * nt, c2 = (c_p2p * nt) * ns;
+        k = 0;
+        double b = c0;
+        if (c1 < b) {
+            b = c1;
+            k = 1;
+        }
+        if (c2 < b) k = 2;
+    }
     table[e] = (uint8_t)k;
 }
 
@@ -230,8 +253,9 @@ int64_t clustered_points(int L, int per, int per_lo, uint64_t seed, float* x, fl
     return (ncells / 2) * per_lo + (ncells / 2) * per;
 }
 
-void mlp_table(const float* w, int p, float theta, uint8_t* table, hipStream_t s) {
-    k_mlp_table<<<(kMlpTable + 255) / 256, 256, 0, s>>>(w, p, theta, table);
+void mlp_table(const float* w, int p, float theta, const double* costs, uint8_t* table, hipStream_t s) {
+    k_mlp_table<<<(kMlpTable + 255) / 256, 256, 0, s>>>(w, p, theta, costs ? costs[0] : 0.0, costs ? costs[1] : 0.0,
+                                                         costs ? costs[2] : 0.0, costs ? 1 : 0, table);
 }
 
 }  // namespace fmm
