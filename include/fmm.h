@@ -193,7 +193,9 @@ fmm_status fmm_traverse(fmm_ctx ctx, int32_t p, double theta, int32_t policy);
  * per-target sum, written in the caller's original particle order.
  *   precision  an fmm_precision
  *   out_dtype  element type of the outputs (FMM_F32 or FMM_F64)
- *   phi, ex, ey, ez  device arrays of n values (caller-owned); E = -grad phi
+ *   phi, ex, ey, ez  device arrays of n values (caller-owned); E = -grad phi;
+ *              n_targets values after fmm_build_tree_ts; may be NULL when
+ *              that count is zero, else NULL is FMM_ERR_INVALID_ARG
  * Requires a completed traversal.  Asynchronous on the context stream.
  */
 fmm_status fmm_evaluate(fmm_ctx ctx, int32_t precision, int32_t out_dtype, void *phi, void *ex,
@@ -476,8 +478,10 @@ fmm_status fmm_set_overlap(fmm_ctx ctx, int32_t schedule);
  * Autotuner for tile shapes and schedule, on the context's current tree and
  * lists (e.g. the batch about to be evaluated repeatedly).  Leaves fall in
  * four size classes (at most 8, 16, 32 or more particles); for each class it
- * times the P2P kernel with 1, 2 and 4 targets per lane (`reps` launches
- * each, events on the context stream) and keeps the fastest; if the lists
+ * times the P2P kernel's tile shapes (`reps` launches each, events on the
+ * context stream) and keeps the fastest: 1, 2 or 4 targets per lane with
+ * every operation on the vector ALUs, or 0, one target per lane with the
+ * sums over sources on the matrix cores (FP32 rank-1 updates); if the lists
  * hold M2L pairs outside the same-level GEMM (spherical family) it times
  * fmm_evaluate under the four kinds of fmm_set_m2l_kernel and keeps the
  * fastest; then it times fmm_evaluate at `precision` under the three
@@ -491,8 +495,9 @@ fmm_status fmm_autotune(fmm_ctx ctx, int32_t precision, int32_t reps);
 
 /* The tile shapes in use (p2p_tpl[4], host) and the schedule (*overlap, as
  * fmm_set_overlap);
- * either pointer may be NULL.  fmm_set_tile_config sets the shapes (each 1, 2
- * or 4). */
+ * either pointer may be NULL.  fmm_set_tile_config sets the shapes (each 0
+ * for the matrix-core form, or 1, 2 or 4 targets per lane); any other value
+ * is FMM_ERR_INVALID_ARG and leaves the shapes unchanged. */
 fmm_status fmm_get_tile_config(fmm_ctx ctx, int32_t *p2p_tpl, int32_t *overlap);
 fmm_status fmm_set_tile_config(fmm_ctx ctx, const int32_t *p2p_tpl);
 

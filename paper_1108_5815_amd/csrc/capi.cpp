@@ -145,7 +145,7 @@ struct fmm_ctx_s {
     Buf M, L, nearb;
 
     // kernel pre-calculation inputs/outputs
-    Buf tune_pts, tune_out, at_out;
+    Buf tune_pts, tune_out, at_out, rhist;
 
     // pinned host staging
     void* host = nullptr;
@@ -165,7 +165,7 @@ struct fmm_ctx_s {
                       &d_seg, &d_bt, &d_pb, &d_box, &d_frame, &inst, &bsort, &tact, &tnact,
                       &leaves_cls, &inner, &leafpos, &m2pflag, &m2lslot, &tbounds, &lkey, &lval, &lkey2, &lval2, &at_out, &m2l_part, &Msplit, &nbucket, &kinds, &ckey, &ckey2, &cval, &cval2,
                       &chead, &choff, &cstart, &cpos, &csrcs, &cnt_t, &ctbase, &ctile, &cT, &cskip, &cls_part,
-                      &ts_stage, &tleaves, &d_wrot};
+                      &ts_stage, &tleaves, &d_wrot, &rhist};
         for (Buf* b : all) bufs.push_back(b);
     }
 };
@@ -969,7 +969,9 @@ void check_evaluate_args(fmm_ctx c, int32_t precision, int32_t out_dtype, void* 
     if (precision == FMM_PREC_SPLIT_BF16 && !m2l_bf16_supported_kp(c_kp(c)))
         fail(FMM_ERR_UNSUPPORTED, "split-BF16 M2L is implemented for storage widths up to 192 (spherical p <= 12)");
     if (out_dtype != FMM_F32 && out_dtype != FMM_F64) fail(FMM_ERR_INVALID_ARG, "out_dtype must be F32 or F64");
-    if (c->n > 0 && (!phi || !ex || !ey || !ez)) fail(FMM_ERR_INVALID_ARG, "null output pointer");
+    // one output per particle, or per target when targets and sources differ
+    const int64_t nout = c->n_targets >= 0 ? c->n_targets : c->n;
+    if (nout > 0 && (!phi || !ex || !ey || !ez)) fail(FMM_ERR_INVALID_ARG, "null output pointer");
 }
 
 // The evaluation proper on the given work buffers; `in_order` runs every
@@ -1183,53 +1185,59 @@ fmm_status fmm_build_tree(fmm_ctx c, int64_t n, int dtype, const void* x, const 
     });
 }
 
+// Target tree and source tree in one cube (targets first, with zero charge).
+void build_tree_ts_impl(fmm_ctx c, int dtype, int64_t n_targets, const void* tx, const void* ty, const void* tz,
+                        int64_t n_sources, const void* sx, const void* sy, const void* sz, const void* q,
+                        int32_t ncrit) {
+    if (n_targets < 0 || n_sources < 0 || n_targets + n_sources >= ((int64_t)1 << 31))
+        fail(FMM_ERR_INVALID_ARG, "particle counts out of range");
+    if (dtype != FMM_F32 && dtype != FMM_F64) fail(FMM_ERR_INVALID_ARG, "dtype must be FMM_F32 or FMM_F64");
+    if ((n_targets > 0 && (!tx || !ty || !tz)) || (n_sources > 0 && (!sx || !sy || !sz || !q)))
+        fail(FMM_ERR_INVALID_ARG, "null input pointer");
+    const int64_t n = n_targets + n_sources;
+    const size_t es = dtype == FMM_F64 ? 8 : 4;
+    // the two sets side by side (targets first), targets with zero charge
+    char* st = need<char>(c, c->ts_stage, 4 * (size_t)std::max<int64_t>(n, 1) * es);
+    char* X[4] = {st, st + n * es, st + 2 * n * es, st + 3 * n * es};
+    const void* T[3] = {tx, ty, tz};
+    const void* S[4] = {sx, sy, sz, q};
+    for (int d = 0; d < 3; d++) {
+        if (n_targets > 0) ck(hipMemcpyAsync(X[d], T[d], n_targets * es, hipMemcpyDeviceToDevice, c->stream), "copy");
+        if (n_sources > 0)
+            ck(hipMemcpyAsync(X[d] + n_targets * es, S[d], n_sources * es, hipMemcpyDeviceToDevice, c->stream),
+               "copy");
+    }
+    if (n_targets > 0) fill_zero(X[3], n_targets * es, c->stream);
+    if (n_sources > 0)
+        ck(hipMemcpyAsync(X[3] + n_targets * es, q, n_sources * es, hipMemcpyDeviceToDevice, c->stream), "copy");
+    const int64_t seg[3] = {0, n_targets, n};
+    build_forest_impl(c, 2, seg, dtype, X[0], X[1], X[2], X[3], ncrit, true);
+    c->n_targets = n_targets;
+    // the leaves holding targets, for the final sum
+    const int32_t nl = c->nleaf;
+    int32_t* tl = need<int32_t>(c, c->tleaves, std::max(nl, 1));
+    c->ntleaf = 0;
+    if (nl > 0 && n_targets > 0) {
+        uint32_t* flag = need<uint32_t>(c, c->tmp1, nl + 1);
+        uint32_t* pos = need<uint32_t>(c, c->tmp2, nl + 1);
+        size_t wsn = scan_ws_bytes(nl);
+        void* ws = wsn > c->ws.cap ? need<char>(c, c->ws, wsn) : c->ws.p;
+        double* d6 = (double*)c->small.p;
+        target_leaf_flags(cells_of(c), (const int32_t*)c->leaves.p, nl, (int32_t)n_targets, flag, c->stream);
+        scan_u32(flag, pos, (uint32_t*)(d6 + 12), nl, ws, c->stream);
+        target_leaf_write((const int32_t*)c->leaves.p, flag, pos, nl, tl, c->stream);
+        check_launch("target leaves");
+        uint32_t cnt = 0;
+        to_host<uint32_t>(c, &cnt, d6 + 12, 1);
+        c->ntleaf = (int32_t)cnt;
+    }
+}
+
 fmm_status fmm_build_tree_ts(fmm_ctx c, int dtype, int64_t n_targets, const void* tx, const void* ty,
                              const void* tz, int64_t n_sources, const void* sx, const void* sy, const void* sz,
                              const void* q, int32_t ncrit) {
     return guarded(c, [&] {
-        if (n_targets < 0 || n_sources < 0 || n_targets + n_sources >= ((int64_t)1 << 31))
-            fail(FMM_ERR_INVALID_ARG, "particle counts out of range");
-        if (dtype != FMM_F32 && dtype != FMM_F64) fail(FMM_ERR_INVALID_ARG, "dtype must be FMM_F32 or FMM_F64");
-        if ((n_targets > 0 && (!tx || !ty || !tz)) || (n_sources > 0 && (!sx || !sy || !sz || !q)))
-            fail(FMM_ERR_INVALID_ARG, "null input pointer");
-        const int64_t n = n_targets + n_sources;
-        const size_t es = dtype == FMM_F64 ? 8 : 4;
-        // the two sets side by side (targets first), targets with zero charge
-        char* st = need<char>(c, c->ts_stage, 4 * (size_t)std::max<int64_t>(n, 1) * es);
-        char* X[4] = {st, st + n * es, st + 2 * n * es, st + 3 * n * es};
-        const void* T[3] = {tx, ty, tz};
-        const void* S[4] = {sx, sy, sz, q};
-        for (int d = 0; d < 3; d++) {
-            if (n_targets > 0)
-                ck(hipMemcpyAsync(X[d], T[d], n_targets * es, hipMemcpyDeviceToDevice, c->stream), "copy");
-            if (n_sources > 0)
-                ck(hipMemcpyAsync(X[d] + n_targets * es, S[d], n_sources * es, hipMemcpyDeviceToDevice, c->stream),
-                   "copy");
-        }
-        if (n_targets > 0) fill_zero(X[3], n_targets * es, c->stream);
-        if (n_sources > 0)
-            ck(hipMemcpyAsync(X[3] + n_targets * es, q, n_sources * es, hipMemcpyDeviceToDevice, c->stream), "copy");
-        const int64_t seg[3] = {0, n_targets, n};
-        build_forest_impl(c, 2, seg, dtype, X[0], X[1], X[2], X[3], ncrit, true);
-        c->n_targets = n_targets;
-        // the leaves holding targets, for the final sum
-        const int32_t nl = c->nleaf;
-        int32_t* tl = need<int32_t>(c, c->tleaves, std::max(nl, 1));
-        c->ntleaf = 0;
-        if (nl > 0 && n_targets > 0) {
-            uint32_t* flag = need<uint32_t>(c, c->tmp1, nl + 1);
-            uint32_t* pos = need<uint32_t>(c, c->tmp2, nl + 1);
-            size_t wsn = scan_ws_bytes(nl);
-            void* ws = wsn > c->ws.cap ? need<char>(c, c->ws, wsn) : c->ws.p;
-            double* d6 = (double*)c->small.p;
-            target_leaf_flags(cells_of(c), (const int32_t*)c->leaves.p, nl, (int32_t)n_targets, flag, c->stream);
-            scan_u32(flag, pos, (uint32_t*)(d6 + 12), nl, ws, c->stream);
-            target_leaf_write((const int32_t*)c->leaves.p, flag, pos, nl, tl, c->stream);
-            check_launch("target leaves");
-            uint32_t cnt = 0;
-            to_host<uint32_t>(c, &cnt, d6 + 12, 1);
-            c->ntleaf = (int32_t)cnt;
-        }
+        build_tree_ts_impl(c, dtype, n_targets, tx, ty, tz, n_sources, sx, sy, sz, q, ncrit);
         build_timings(c);
     });
 }
@@ -1448,7 +1456,10 @@ static void mlp_features(float* f, int dl, double nt, double ns, int p, double t
 // particle sets whose leaves all hold `per` particles give homogeneous pair
 // batches; the FMM policy times same-level M2L (GEMM) and P2P per cell pair,
 // the treecode policy M2P per cell pair, and a set whose lower half is one
-// level deeper times the mixed-level M2L pairs of its interface.
+// level deeper times the mixed-level M2L pairs of its interface.  Target and
+// source sets on one lattice with different leaf sizes (a target tree and a
+// source tree) time P2P and M2P off the diagonal n_t != n_s.  Each measured
+// batch also records which distance-ratio bins its pairs fall in.
 static void gen_records(fmm_ctx c, int p, double theta, int precision, uint64_t seed) {
     c->rec_feat.clear();
     c->rec_kind.clear();
@@ -1467,12 +1478,33 @@ static void gen_records(fmm_ctx c, int p, double theta, int precision, uint64_t 
     t->auto_cart_max_p = c->auto_cart_max_p;
     t->timing = true;
     t->schedule = 0;  // each kernel timed alone
-    // measured log2 ns per cell pair, per leaf size: same-level M2L, mixed-level
-    // M2L, M2P, P2P (NaN = not measured)
     const int pers[] = {2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096};
     const int NS = (int)(sizeof(pers) / sizeof(pers[0]));
-    std::vector<double> Tm2l(NS, NAN), Tgen(NS, NAN), Tm2p(NS, NAN), Tp2p(NS, NAN);
+    // one measurement: log2 ns per cell pair and the fractions of its pairs
+    // in each distance-ratio bin (value NaN = not measured)
+    struct Meas {
+        double v = NAN;
+        double bins[kMlpBq] = {};
+    };
+    // diagonal (n_t = n_s): same-level M2L, mixed-level M2L, M2P, P2P per leaf size
+    std::vector<Meas> Tm2l(NS), Tgen(NS), Tm2p(NS), Tp2p(NS);
+    // off the diagonal, targets pers[i] and sources pers[j]: M2P, P2P at [i NS + j]
+    std::vector<Meas> Om2p(NS * NS), Op2p(NS * NS);
     auto lg = [](double ms, int64_t units) { return units > 0 && ms > 0 ? std::log2(ms * 1e6 / (double)units) : NAN; };
+    unsigned long long* dh = need<unsigned long long>(c, c->rhist, kMlpBq);
+    auto meas = [&](double v, int kind) {
+        Meas m;
+        m.v = v;
+        if (!std::isfinite(v)) return m;
+        ratio_hist((const int2*)t->raw[kind].p, t->nlist[kind], cells_of(t), theta, dh, c->stream);
+        check_launch("ratio bins");
+        unsigned long long hh[kMlpBq];
+        to_host<unsigned long long>(c, hh, dh, kMlpBq);
+        double tot = 0;
+        for (int b = 0; b < kMlpBq; b++) tot += (double)hh[b];
+        for (int b = 0; b < kMlpBq; b++) m.bins[b] = tot > 0 ? (double)hh[b] / tot : 0.0;
+        return m;
+    };
     auto timed = [&](int policy, double* tm) {
         traverse_impl(t, p, theta, policy);
         float* out = need<float>(c, c->tune_out, (size_t)4 * t->n);
@@ -1483,10 +1515,15 @@ static void gen_records(fmm_ctx c, int p, double theta, int precision, uint64_t 
                 for (int k = 0; k < PH_N; k++) tm[k] += t->ms[k] / 2;
         }
     };
+    // lattice level for a set of 2^(3L) leaves of `per` particles (plus another of per2)
+    auto level_for = [](int per, int per2, int64_t cap) {
+        int L = 7;
+        while (L > 1 && ((int64_t)1 << (3 * L)) * (per + per2) > cap) L--;
+        return L;
+    };
     for (int si = 0; si < NS; si++) {
         const int per = pers[si];
-        int L = 7;
-        while (L > 1 && ((int64_t)1 << (3 * L)) * per > ((int64_t)1 << 20)) L--;
+        const int L = level_for(per, 0, (int64_t)1 << 20);
         int64_t n = clustered_points(L, per, per, seed, nullptr, nullptr, nullptr, nullptr, c->stream);
         float* pts = need<float>(c, c->tune_pts, (size_t)4 * n);
         clustered_points(L, per, per, seed, pts, pts + n, pts + 2 * n, pts + 3 * n, c->stream);
@@ -1494,10 +1531,10 @@ static void gen_records(fmm_ctx c, int p, double theta, int precision, uint64_t 
         build_tree_impl(t, n, FMM_F32, pts, pts + n, pts + 2 * n, pts + 3 * n, per);
         double tf[PH_N], tt[PH_N];
         timed(FMM_POLICY_FMM, tf);
-        Tm2l[si] = lg(tf[PH_M2L], t->nlist[0] - t->ngeneral);
-        Tp2p[si] = lg(tf[PH_P2P], t->nlist[2]);
+        Tm2l[si] = meas(lg(tf[PH_M2L], t->nlist[0] - t->ngeneral), 0);
+        Tp2p[si] = meas(lg(tf[PH_P2P], t->nlist[2]), 2);
         timed(FMM_POLICY_TREECODE, tt);
-        Tm2p[si] = lg(tt[PH_FAR] - tf[PH_FAR], t->nlist[1]);
+        Tm2p[si] = meas(lg(tt[PH_FAR] - tf[PH_FAR], t->nlist[1]), 1);
         // mixed levels: the lower half one level deeper
         int L2 = L;
         while (L2 > 1 && ((int64_t)1 << (3 * L2 - 1)) * 9 * per > ((int64_t)1 << 21)) L2--;
@@ -1507,40 +1544,74 @@ static void gen_records(fmm_ctx c, int p, double theta, int precision, uint64_t 
         check_launch("clustered points");
         build_tree_impl(t, n2, FMM_F32, pts, pts + n2, pts + 2 * n2, pts + 3 * n2, per);
         timed(FMM_POLICY_FMM, tf);
-        Tgen[si] = lg(tf[PH_M2LG], t->ngeneral);
-    }
-    // Records.  Measured directly: the diagonal (n_t = n_s, equal levels; mixed
-    // levels for M2L).  The rest follow from how the kernels' work scales,
-    // stated here as the model's invariances: no kernel's cost depends on the
-    // distance ratio; M2L's does not depend on the particle counts and M2P's
-    // not on n_s; P2P's log cost is additive in log n_t and log n_s, so an
-    // off-diagonal pair gets the mean of the two diagonal log costs; only M2L
-    // depends on the level difference.
-    auto nearest = [&](const std::vector<double>& T, int i) {
-        for (int d = 0; d < NS; d++) {
-            if (i - d >= 0 && std::isfinite(T[i - d])) return T[i - d];
-            if (i + d < NS && std::isfinite(T[i + d])) return T[i + d];
+        Tgen[si] = meas(lg(tf[PH_M2LG], t->ngeneral), 0);
+        // off the diagonal: targets with `per` per leaf, sources with 4x fewer
+        // or more on the same lattice; a leaf size ncrit in [max, 8 min) stops
+        // both trees at that lattice
+        for (int sj : {si - 2, si + 2}) {
+            if (sj < 0 || sj >= NS) continue;
+            const int ps = pers[sj];
+            const int Lo = level_for(per, ps, (int64_t)1 << 21);
+            const int64_t nt = clustered_points(Lo, per, per, seed + 2, nullptr, nullptr, nullptr, nullptr, c->stream);
+            const int64_t ns = clustered_points(Lo, ps, ps, seed + 3, nullptr, nullptr, nullptr, nullptr, c->stream);
+            float* tp = need<float>(c, c->tune_pts, (size_t)4 * (nt + ns));
+            float* sp = tp + 4 * nt;
+            clustered_points(Lo, per, per, seed + 2, tp, tp + nt, tp + 2 * nt, tp + 3 * nt, c->stream);
+            clustered_points(Lo, ps, ps, seed + 3, sp, sp + ns, sp + 2 * ns, sp + 3 * ns, c->stream);
+            check_launch("clustered points");
+            build_tree_ts_impl(t, FMM_F32, nt, tp, tp + nt, tp + 2 * nt, ns, sp, sp + ns, sp + 2 * ns, sp + 3 * ns,
+                               std::max(per, ps));
+            timed(FMM_POLICY_FMM, tf);
+            Op2p[si * NS + sj] = meas(lg(tf[PH_P2P], t->nlist[2]), 2);
+            timed(FMM_POLICY_TREECODE, tt);
+            Om2p[si * NS + sj] = meas(lg(tt[PH_FAR] - tf[PH_FAR], t->nlist[1]), 1);
         }
-        return (double)NAN;
+    }
+    // Records.  Measured: the diagonal (n_t = n_s, equal levels; mixed levels
+    // for M2L) and P2P and M2P at n_s = n_t / 4 and 4 n_t, each at the
+    // distance-ratio bins its pairs occupy (bins holding at least 5% of the
+    // batch).  The rest of the grid follows from how the kernels' work
+    // scales, stated here as the model's invariances: no kernel's cost depends
+    // on the distance ratio; M2L's does not depend on the particle counts and
+    // M2P's not on n_s; P2P's log cost is additive in log n_t and log n_s, so
+    // an unmeasured off-diagonal pair gets the mean of the two diagonal log
+    // costs; only M2L depends on the level difference.
+    auto nearest = [&](const std::vector<Meas>& T, int i) {
+        for (int d = 0; d < NS; d++) {
+            if (i - d >= 0 && std::isfinite(T[i - d].v)) return T[i - d];
+            if (i + d < NS && std::isfinite(T[i + d].v)) return T[i + d];
+        }
+        return Meas{};
+    };
+    auto emit = [&](int dl, int i, int j, int kind, const Meas& m, double v) {
+        if (!std::isfinite(v)) return;
+        for (int b = 0; b < kMlpBq; b++) {
+            if (m.bins[b] < 0.05) continue;
+            float f[6];
+            mlp_features(f, dl, pers[i], pers[j], p, theta);
+            f[4] = ((float)b + 0.5f) / (float)kMlpBq;
+            c->rec_feat.insert(c->rec_feat.end(), f, f + 6);
+            c->rec_kind.push_back(kind);
+            c->rec_tgt.push_back((float)v);
+        }
     };
     const int dls[] = {-4, -2, -1, 0, 1, 2, 4};
-    const float ratios[] = {0.125f, 0.875f};
     for (int i = 0; i < NS; i++)
         for (int j = std::max(0, i - 3); j <= std::min(NS - 1, i + 3); j++)
-            for (int dl : dls)
-                for (float fr : ratios) {
-                    float f[6];
-                    mlp_features(f, dl, pers[i], pers[j], p, theta);
-                    f[4] = fr;
-                    double tv[3] = {dl == 0 ? nearest(Tm2l, i) : nearest(Tgen, i), nearest(Tm2p, i),
-                                    0.5 * (nearest(Tp2p, i) + nearest(Tp2p, j))};
-                    for (int k = 0; k < 3; k++) {
-                        if (!std::isfinite(tv[k])) continue;
-                        c->rec_feat.insert(c->rec_feat.end(), f, f + 6);
-                        c->rec_kind.push_back(k);
-                        c->rec_tgt.push_back((float)tv[k]);
-                    }
+            for (int dl : dls) {
+                const Meas ml = dl == 0 ? nearest(Tm2l, i) : nearest(Tgen, i);
+                emit(dl, i, j, 0, ml, ml.v);
+                const Meas& om = Om2p[i * NS + j];
+                const Meas mp = std::isfinite(om.v) ? om : nearest(Tm2p, i);
+                emit(dl, i, j, 1, mp, mp.v);
+                const Meas& op = Op2p[i * NS + j];
+                if (std::isfinite(op.v)) {
+                    emit(dl, i, j, 2, op, op.v);
+                } else {
+                    const Meas a = nearest(Tp2p, i), b2 = nearest(Tp2p, j);
+                    emit(dl, i, j, 2, a, 0.5 * (a.v + b2.v));
                 }
+            }
 }
 
 static void mlp_init(std::vector<float>& w, uint64_t seed, float out_bias) {
@@ -1756,7 +1827,7 @@ fmm_status fmm_costmodel_load(fmm_ctx c, const char* path, int32_t p, int32_t pr
         int tpl[kLeafClasses];
         if (std::fscanf(f, " p2p_tpl") != 0) bad("missing tile shapes");
         for (int k = 0; k < kLeafClasses; k++)
-            if (std::fscanf(f, "%d", &tpl[k]) != 1 || (tpl[k] != 1 && tpl[k] != 2 && tpl[k] != 4)) bad("bad tile shapes");
+            if (std::fscanf(f, "%d", &tpl[k]) != 1 || (tpl[k] != 0 && tpl[k] != 1 && tpl[k] != 2 && tpl[k] != 4)) bad("bad tile shapes");
         if (std::fscanf(f, " schedule %d weights %d", &sched, &nw) != 2 || sched < 0 || sched > 2) bad("bad schedule");
         if (nw != kMlpParams) bad("weight count does not match this network");
         std::vector<float> w(kMlpParams);
@@ -2044,7 +2115,7 @@ fmm_status fmm_autotune(fmm_ctx c, int32_t precision, int32_t reps) {
             const int32_t b = c->leaf_cls[k], e = c->leaf_cls[k + 1];
             if (e <= b) continue;
             double best = INFINITY;
-            for (int tpl : {1, 2, 4}) {
+            for (int tpl : {0, 1, 2, 4}) {
                 double t = timed([&] {
                     p2p((float4*)c->pts.p, cells_of(c), (int32_t*)c->leaves_cls.p + b, e - b, (int32_t*)c->off[2].p,
                         (uint32_t*)c->src[2].p, p2p_guard_all(c), tpl, nr, s);
@@ -2104,8 +2175,8 @@ fmm_status fmm_set_tile_config(fmm_ctx c, const int32_t* p2p_tpl) {
     return guarded(c, [&] {
         if (!p2p_tpl) fail(FMM_ERR_INVALID_ARG, "null pointer");
         for (int k = 0; k < kLeafClasses; k++)
-            if (p2p_tpl[k] != 1 && p2p_tpl[k] != 2 && p2p_tpl[k] != 4)
-                fail(FMM_ERR_INVALID_ARG, "targets per lane must be 1, 2 or 4");
+            if (p2p_tpl[k] != 0 && p2p_tpl[k] != 1 && p2p_tpl[k] != 2 && p2p_tpl[k] != 4)
+                fail(FMM_ERR_INVALID_ARG, "P2P tile shape must be 0 (matrix cores) or 1, 2, 4 targets per lane");
         for (int k = 0; k < kLeafClasses; k++) c->p2p_tpl[k] = p2p_tpl[k];
     });
 }

@@ -7,24 +7,36 @@
 // Layout: target-parallel, one wave per target leaf and no cross-wave
 // reduction (the scheme the paper credits to Nyland et al., "Early
 // application of GPUs").  Leaves hold fewer particles than a wave has lanes,
-// so the wave is cut into G lane groups of `span` lanes; each lane holds TPL
-// targets (register blocking: one source read feeds TPL interactions) and the
-// groups split the sources.  The source cells of the leaf's list are
-// concatenated into one stream: 64 list entries at a time are fetched
-// lane-parallel, a wave prefix sum over their sizes maps stream positions to
-// cells, and the wave copies the stream into an LDS chunk with all lanes
-// busy.  Each group then takes a contiguous, equal share of the chunk, reads
-// it from LDS (one address per group, a broadcast), accumulates in FP32 and
-// adds the chunk's partial into FP64 per-target sums; the groups are summed
-// in group order at the end, so results do not depend on timing.
+// so the wave is cut into G lane groups; the groups split the sources.  The
+// source cells of the leaf's list are concatenated into one stream: 64 list
+// entries at a time are fetched lane-parallel, a wave prefix sum over their
+// sizes maps stream positions to cells, and the wave copies the stream into
+// an LDS chunk with all lanes busy.  Each group then takes a contiguous,
+// equal share of the chunk, reads it from LDS (one address per group, a
+// broadcast), accumulates in FP32 and adds the chunk's partial into FP64
+// per-target sums; the groups are summed in group order at the end, so
+// results do not depend on timing.
 //
-// TPL (1, 2 or 4) is a tile shape chosen per leaf-size class by the
-// library's autotuner; leaves are launched grouped by class.
+// Two tile shapes, chosen per leaf-size class by the library's autotuner
+// (leaves are launched grouped by class):
+//  - vector (TPL = 1, 2 or 4 targets per lane): every operation on the VALU,
+//    one source read feeding TPL interactions;
+//  - matrix core (TPL = 0): one target per lane; the VALU forms only the
+//    pair's 1/r and 1/r^3, and the sums over sources run as rank-1 updates on
+//    v_mfma_f32_4x4x1f32 (16 blocks of 4 targets x 4 columns per
+//    instruction): phi from A = 1/r against B = q, and the field from
+//    A = 1/r^3 against B = (q, q x~, q y~, q z~), the source's charge and
+//    charge-weighted position relative to an origin in the target leaf,
+//    giving E = x~_i sum(q/r^3) - sum(q x~/r^3).  The relative origin keeps
+//    the cancellation of that difference to about eps_32 (|x~_i| + |x~_j|)/r
+//    of a pair's field.
 //
 // Only the leaf's own cell (or every cell for FP64 input, where distinct
 // points may round to one FP32 point) needs the r = 0 guard: it is staged as
 // a chunk of its own and left out of the stream.
 #include "fmm_internal.h"
+
+#include <type_traits>
 
 namespace fmm {
 namespace {
@@ -214,6 +226,191 @@ __global__ __launch_bounds__(64) void k_p2p(const float4* __restrict__ pts, Cell
     }
 }
 
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// 1/r of one pair (0 for coincident points when guarded; +inf padding gives 0)
+template <bool GUARD>
+__device__ inline float pair_inv(const float3 P, const float4 Q) {
+    const float dx = P.x - Q.x, dy = P.y - Q.y, dz = P.z - Q.z;
+    const float r2 = dx * dx + dy * dy + dz * dz;
+    const float inv = __builtin_amdgcn_rsqf(r2);
+    return GUARD ? (r2 > 0.f ? inv : 0.f) : inv;
+}
+
+// Sources [j0, j0 + m) of a staged chunk against the lane's target on the
+// matrix cores.  Lane l is row l%4 of block l/4 for A and column l%4 for B;
+// all lanes of a block walk the same sources.  Returns the FP32 partials
+// (D registers: row r of the lane's block, column l%4).
+template <bool GUARD>
+__device__ inline void chunk_mfma(const float4* buf, const float* bq, int j0, int m, int comp, const float3 P,
+                                  v4f& sp, v4f& se) {
+    v4f p0 = {0.f, 0.f, 0.f, 0.f}, p1 = p0, e0 = p0, e1 = p0;
+    int jj = 0;
+    for (; jj + 3 < m; jj += 4) {
+        const int j = j0 + jj;
+        const float4 Q0 = buf[j], Q1 = buf[j + 1], Q2 = buf[j + 2], Q3 = buf[j + 3];
+        const float b0 = bq[4 * j + comp], b1 = bq[4 * j + 4 + comp], b2 = bq[4 * j + 8 + comp],
+                    b3 = bq[4 * j + 12 + comp];
+        const float i0 = pair_inv<GUARD>(P, Q0), i1 = pair_inv<GUARD>(P, Q1);
+        const float i2 = pair_inv<GUARD>(P, Q2), i3 = pair_inv<GUARD>(P, Q3);
+        p0 = __builtin_amdgcn_mfma_f32_4x4x1f32(i0, b0, p0, 0, 0, 0);
+        e0 = __builtin_amdgcn_mfma_f32_4x4x1f32(i0 * i0 * i0, b0, e0, 0, 0, 0);
+        p1 = __builtin_amdgcn_mfma_f32_4x4x1f32(i1, b1, p1, 0, 0, 0);
+        e1 = __builtin_amdgcn_mfma_f32_4x4x1f32(i1 * i1 * i1, b1, e1, 0, 0, 0);
+        p0 = __builtin_amdgcn_mfma_f32_4x4x1f32(i2, b2, p0, 0, 0, 0);
+        e0 = __builtin_amdgcn_mfma_f32_4x4x1f32(i2 * i2 * i2, b2, e0, 0, 0, 0);
+        p1 = __builtin_amdgcn_mfma_f32_4x4x1f32(i3, b3, p1, 0, 0, 0);
+        e1 = __builtin_amdgcn_mfma_f32_4x4x1f32(i3 * i3 * i3, b3, e1, 0, 0, 0);
+    }
+    for (; jj < m; jj++) {
+        const int j = j0 + jj;
+        const float i0 = pair_inv<GUARD>(P, buf[j]);
+        const float b0 = bq[4 * j + comp];
+        p0 = __builtin_amdgcn_mfma_f32_4x4x1f32(i0, b0, p0, 0, 0, 0);
+        e0 = __builtin_amdgcn_mfma_f32_4x4x1f32(i0 * i0 * i0, b0, e0, 0, 0, 0);
+    }
+    sp = p0 + p1;
+    se = e0 + e1;
+}
+
+template <bool GUARD_ALL>
+__global__ __launch_bounds__(64) void k_p2p_mfma(const float4* __restrict__ pts, CellArrays c,
+                                                 const int32_t* __restrict__ leaves,
+                                                 const int32_t* __restrict__ off, const uint32_t* __restrict__ src,
+                                                 double4* __restrict__ near) {
+    constexpr int CH = 256;        // staged sources per chunk
+    constexpr int CHP = CH + 16;   // room for the padding that evens the group shares
+    __shared__ float4 buf[CHP];    // source (x, y, z, q)
+    __shared__ float4 bqv[CHP];    // source (q, q x~, q y~, q z~)
+    __shared__ int s_pref[65];
+    __shared__ int s_beg[64];
+    static_assert(CHP * sizeof(float4) >= 64 * 5 * sizeof(double), "reduction does not fit the chunk");
+    const float* bq = reinterpret_cast<const float*>(bqv);
+    const int cell = leaves[blockIdx.x];
+    const int32_t b = c.begin[cell], e = c.end[cell];
+    const int lane = threadIdx.x;
+    const int blk = lane >> 2, row = lane & 3;  // A row and B/D column within the 4x4 block
+    const float4 O = pts[b];                    // origin of the relative positions
+    const float INF = __builtin_inff();
+
+    auto stage = [&](int k, const float4 v) {
+        buf[k] = v;
+        bqv[k] = make_float4(v.w, v.w * (v.x - O.x), v.w * (v.y - O.y), v.w * (v.z - O.z));
+    };
+
+    for (int32_t t0 = b; t0 < e; t0 += 64) {
+        const int ntc = min(e - t0, 64);
+        const int nbk = (ntc + 3) >> 2;  // blocks of 4 targets per group
+        const int G = 16 / nbk;          // groups of nbk blocks
+        const int g = blk / nbk;
+        const bool active = g < G;
+        const int gg = active ? g : 0;   // idle blocks repeat group 0's work, results unused
+        const int ti = (blk - g * nbk) * 4 + row;
+        const float4 v = pts[t0 + ((active && ti < ntc) ? ti : 0)];
+        const float3 P = make_float3(v.x, v.y, v.z);
+        double ap[4] = {0.0, 0.0, 0.0, 0.0}, ae[4] = {0.0, 0.0, 0.0, 0.0};
+
+        // the group shares of a staged chunk of n sources: m each, padded with
+        // zero-charge points at infinity (their 1/r is 0)
+        auto flush = [&](int n, auto guard) {
+            constexpr bool GD = decltype(guard)::value;
+            const int m = (n + G - 1) / G;
+            for (int k = n + lane; k < G * m; k += 64) {
+                buf[k] = make_float4(INF, INF, INF, 0.f);
+                bqv[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+            __syncthreads();
+            v4f sp, se;
+            chunk_mfma<GD>(buf, bq, gg * m, m, row, P, sp, se);
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                ap[r] += sp[r];
+                ae[r] += se[r];
+            }
+            __syncthreads();
+        };
+
+        // (1) the leaf's own cell, guarded (left out of the stream below)
+        if (!GUARD_ALL) {
+            for (int32_t s0 = b; s0 < e; s0 += CH) {
+                const int n = min(e - s0, CH);
+                for (int k = lane; k < n; k += 64) stage(k, pts[s0 + k]);
+                flush(n, std::true_type{});
+            }
+        }
+
+        // (2) every other source cell of the leaf's and its ancestors' lists
+        int fill = 0;
+        for (int A = cell; A >= 0; A = c.parent[A]) {
+            const int32_t a1 = off[A + 1];
+            for (int32_t a0 = off[A]; a0 < a1; a0 += 64) {
+                const int nb = min(a1 - a0, 64);
+                int sb = 0, ns = 0;
+                if (lane < nb) {
+                    const int s = (int)src[a0 + lane];
+                    if (GUARD_ALL || s != cell) {
+                        sb = c.begin[s];
+                        ns = c.end[s] - sb;
+                    }
+                }
+                const int incl = wave_inclusive_scan(ns, lane);
+                const int tot = __shfl(incl, 63, 64);
+                s_pref[lane + 1] = incl;
+                if (lane == 0) s_pref[0] = 0;
+                s_beg[lane] = sb;
+                __syncthreads();
+                for (int done = 0; done < tot;) {
+                    const int take = min(tot - done, CH - fill);
+                    for (int k = lane; k < take; k += 64) {
+                        const int el = done + k;
+                        int lo = 0, hi = 64;
+#pragma unroll
+                        for (int it = 0; it < 6; it++) {
+                            const int mid = (lo + hi) >> 1;
+                            if (s_pref[mid] <= el) lo = mid;
+                            else hi = mid;
+                        }
+                        stage(fill + k, pts[s_beg[lo] + (el - s_pref[lo])]);
+                    }
+                    fill += take;
+                    done += take;
+                    if (fill == CH) {
+                        flush(CH, std::integral_constant<bool, GUARD_ALL>{});
+                        fill = 0;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        if (fill > 0) flush(fill, std::integral_constant<bool, GUARD_ALL>{});
+
+        // (3) sum the groups in group order, through the chunk's LDS: slot
+        // 4 blk + r holds target (blk - g nbk) 4 + r of group g
+        double* red = reinterpret_cast<double*>(buf);
+        if (active) {
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                red[(4 * blk + r) * 5 + 1 + row] = ae[r];
+                if (row == 0) red[(4 * blk + r) * 5] = ap[r];
+            }
+        }
+        __syncthreads();
+        if (lane < ntc) {
+            double s[5];
+#pragma unroll
+            for (int k = 0; k < 5; k++) s[k] = red[lane * 5 + k];
+            for (int h = 1; h < G; h++)
+#pragma unroll
+                for (int k = 0; k < 5; k++) s[k] += red[(h * nbk * 4 + lane) * 5 + k];
+            const float4 T = pts[t0 + lane];
+            const double xt = (double)(T.x - O.x), yt = (double)(T.y - O.y), zt = (double)(T.z - O.z);
+            near[t0 + lane] = make_double4(s[0], xt * s[1] - s[2], yt * s[1] - s[3], zt * s[1] - s[4]);
+        }
+        __syncthreads();
+    }
+}
+
 // P2P size class of a leaf: at most 8, 16, 32 or more targets
 __global__ void k_leaf_class(CellArrays c, const int32_t* __restrict__ leaves, int32_t nleaf,
                              uint32_t* __restrict__ key, uint32_t* __restrict__ val) {
@@ -223,6 +420,14 @@ __global__ void k_leaf_class(CellArrays c, const int32_t* __restrict__ leaves, i
     const int32_t nt = c.end[cell] - c.begin[cell];
     key[i] = nt <= 8 ? 0u : nt <= 16 ? 1u : nt <= 32 ? 2u : 3u;
     val[i] = (uint32_t)cell;
+}
+
+void launch_mfma(const float4* pts, CellArrays cells, const int32_t* leaves, int32_t nleaves, const int32_t* off,
+                 const uint32_t* src, int guard_all, double4* near, hipStream_t s) {
+    if (guard_all)
+        k_p2p_mfma<true><<<nleaves, 64, 0, s>>>(pts, cells, leaves, off, src, near);
+    else
+        k_p2p_mfma<false><<<nleaves, 64, 0, s>>>(pts, cells, leaves, off, src, near);
 }
 
 template <int TPL>
@@ -246,6 +451,7 @@ void p2p(const float4* pts, CellArrays cells, const int32_t* leaves, int32_t nle
          const uint32_t* p2p_src, int guard_all, int tpl, double4* near, hipStream_t s) {
     if (nleaves <= 0) return;
     switch (tpl) {
+        case 0: launch_mfma(pts, cells, leaves, nleaves, p2p_off, p2p_src, guard_all, near, s); break;
         case 1: launch<1>(pts, cells, leaves, nleaves, p2p_off, p2p_src, guard_all, near, s); break;
         case 2: launch<2>(pts, cells, leaves, nleaves, p2p_off, p2p_src, guard_all, near, s); break;
         default: launch<4>(pts, cells, leaves, nleaves, p2p_off, p2p_src, guard_all, near, s); break;

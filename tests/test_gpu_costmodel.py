@@ -113,6 +113,11 @@ def test_train_on_own_timings_and_accuracy():
     print("records", kind.size, "final loss", loss)
     assert kind.size >= 12 and set(np.unique(kind)) == {0, 1, 2}
     assert loss < 0.25          # log2 units: within ~20% of the measured per-pair time
+    # measured off-diagonal particle-particle records (n_s = n_t / 4 and 4 n_t,
+    # feature gap log2(4) / 8) and more than one distance-ratio bin
+    gap = np.abs(feat[:, 1] - feat[:, 2])
+    assert np.any((kind == 2) & np.isclose(gap, 0.25, atol=1e-6))
+    assert len(np.unique(np.round(feat[:, 4] * 8))) >= 2
     n = 200000
     x, y, z, q = plummer_inputs(n, 27)
     t = [torch.tensor(a, dtype=torch.float32, device="cuda:0") for a in (x, y, z, q)]

