@@ -363,8 +363,8 @@ fmm_status fmm_costmodel_loss_grad(fmm_ctx ctx, const float *weights, int32_t n_
  * as hexadecimal floats), the order, theta and precision it was trained for
  * (-1 where unknown, e.g. after fmm_costmodel_set_weights), the name of the
  * device whose kernel timings trained it, the final training loss, the
- * timed unit costs (if set) and the tile shapes and schedule in use.  This
- * keeps the learned choices of a device fixed across processes, where
+ * timed unit costs (if set) and the tile shapes, schedule and M2L kernel
+ * kind (fmm_set_m2l_kernel) in use.  This keeps the learned choices of a device fixed across processes, where
  * retraining on fresh timings would give slightly different choices.
  * save: FMM_ERR_STATE without a model, FMM_ERR_DEVICE if the file cannot be
  * written.  load(path, p, precision): the file must come from a device of
@@ -372,7 +372,8 @@ fmm_status fmm_costmodel_loss_grad(fmm_ctx ctx, const float *weights, int32_t n_
  * order and precision; otherwise FMM_ERR_INVALID_ARG (also for a missing,
  * unreadable or malformed file, or another format version) and the context
  * keeps its model.  On success the weights, unit costs (when the file has
- * them), tile shapes and schedule replace the context's.
+ * them), tile shapes, schedule and M2L kernel kind (when the file has it)
+ * replace the context's.
  */
 fmm_status fmm_costmodel_save(fmm_ctx ctx, const char *path);
 fmm_status fmm_costmodel_load(fmm_ctx ctx, const char *path, int32_t p, int32_t precision);

@@ -84,6 +84,9 @@ struct fmm_ctx_s {
     int p2p_tpl[kLeafClasses] = {4, 4, 4, 4};
     int32_t ncell = 0, nleaf = 0;
     std::vector<int32_t> lvl;  // cells of level L: [lvl[L], lvl[L+1])
+    int tree_levels = 0;       // levels the last build needed (its first empty level)
+    int trav_levels = 0;       // frontier levels the last traversal needed
+    int64_t trav_cap[4] = {0, 0, 0, 0};  // pair capacities of the three lists and the frontier
     Buf keys, keys2, idx, idx2, pts, ws, small;
     Buf c_begin, c_end, c_parent, c_child, c_nchild, c_level, c_prefix, c_geo, c_ctr, leaves, tmp1, tmp2;
 
@@ -145,14 +148,12 @@ struct fmm_ctx_s {
     Buf M, L, nearb;
 
     // kernel pre-calculation inputs/outputs
-    Buf tune_pts, tune_out, at_out, rhist;
+    Buf tune_pts, tune_out, at_out, rhist, d_lvl, d_trav;
 
     // pinned host staging
     void* host = nullptr;
     // per-level counts written by the scan kernels straight into mapped,
     // coherent host memory (the host only synchronises: no copy launch)
-    uint32_t* hcount = nullptr;
-    uint32_t* hcount_dev = nullptr;
 
     fmm_ctx_s() {
         Buf* all[] = {&keys, &keys2, &idx, &idx2, &pts, &ws, &small, &c_begin, &c_end, &c_parent, &c_child,
@@ -165,7 +166,7 @@ struct fmm_ctx_s {
                       &d_seg, &d_bt, &d_pb, &d_box, &d_frame, &inst, &bsort, &tact, &tnact,
                       &leaves_cls, &inner, &leafpos, &m2pflag, &m2lslot, &tbounds, &lkey, &lval, &lkey2, &lval2, &at_out, &m2l_part, &Msplit, &nbucket, &kinds, &ckey, &ckey2, &cval, &cval2,
                       &chead, &choff, &cstart, &cpos, &csrcs, &cnt_t, &ctbase, &ctile, &cT, &cskip, &cls_part,
-                      &ts_stage, &tleaves, &d_wrot, &rhist};
+                      &ts_stage, &tleaves, &d_wrot, &rhist, &d_lvl, &d_trav};
         for (Buf* b : all) bufs.push_back(b);
     }
 };
@@ -251,19 +252,6 @@ T* need_keep(fmm_ctx c, Buf& b, size_t count, size_t keep_count) {
 void* host_stage(fmm_ctx c) {
     if (!c->host) ck(hipHostMalloc(&c->host, 1 << 16, hipHostMallocDefault), "hipHostMalloc");
     return c->host;
-}
-
-// device pointer of 16 mapped host counters (read by the host after a sync)
-uint32_t* mapped_counts(fmm_ctx c) {
-    if (!c->hcount) {
-        void* h = nullptr;
-        ck(hipHostMalloc(&h, 256, hipHostMallocMapped | hipHostMallocCoherent), "hipHostMalloc");
-        c->hcount = (uint32_t*)h;
-        void* d = nullptr;
-        ck(hipHostGetDevicePointer(&d, h, 0), "hipHostGetDevicePointer");
-        c->hcount_dev = (uint32_t*)d;
-    }
-    return c->hcount_dev;
 }
 
 template <class T>
@@ -495,42 +483,70 @@ void build_forest_impl(fmm_ctx c, int32_t nseg, const int64_t* hseg, int dtype, 
         }
     const int32_t nroot = (int32_t)rb.size();
     c->nroot = nroot;
-    size_t cap = (size_t)std::max<int64_t>(1024, 2 * n / std::max(ncrit, 1) + 1024) + nroot;
-    ensure_cells(c, cap, 0);
-    {
-        std::vector<int32_t> neg(nroot, -1), zero(nroot, 0);
-        std::vector<uint64_t> z64(nroot, 0);
-        to_dev(c, c->c_begin.p, rb.data(), nroot);
-        to_dev(c, c->c_end.p, re.data(), nroot);
-        to_dev(c, c->c_parent.p, neg.data(), nroot);
-        to_dev(c, c->c_level.p, zero.data(), nroot);
-        to_dev(c, c->c_child.p, neg.data(), nroot);
-        to_dev(c, c->c_nchild.p, zero.data(), nroot);
-        to_dev(c, c->c_prefix.p, z64.data(), nroot);
+    // Levels run back to back on the device: each level's bounds and its
+    // count of new cells stay in device memory, and the host reads them once
+    // per window of levels (as many as the previous build needed, else 6).
+    // A level that would pass the cell capacity stops the tree; the arrays
+    // then grow and the build runs again.
+    size_t cap = std::max<size_t>(c->c_begin.cap / sizeof(int32_t),
+                                  (size_t)std::max<int64_t>(1024, 4 * n / std::max(ncrit, 1) + 1024) + nroot);
+    int32_t* dl = need<int32_t>(c, c->d_lvl, kMaxLevel + 8);  // level starts [0, kMaxLevel + 3), new-cell count, overflow
+    uint32_t* dnnew = (uint32_t*)(dl + kMaxLevel + 4);
+    uint32_t* dovf = dnnew + 1;
+    std::vector<int32_t> hl(kMaxLevel + 8, 0);
+    if (scan_dev_ws_bytes() > c->ws.cap) {
+        ws = need<char>(c, c->ws, scan_dev_ws_bytes());
+        d6 = (double*)c->small.p;
     }
-    int32_t total = nroot;
-    for (int L = 0; L < kMaxLevel + 1; L++) {
-        int32_t c0 = c->lvl[L], c1 = total;
-        int32_t m = c1 - c0;
-        uint32_t* nsplit = need<uint32_t>(c, c->tmp1, m + 1);
-        uint32_t* choff = need<uint32_t>(c, c->tmp2, m + 1);
-        CellArrays ca = cells_of(c);
-        int32_t* tbnd = need<int32_t>(c, c->tbounds, (size_t)m * 7 + 1);
-        tree_count(keys, ca, c0, c1, L, ncrit, nsplit, tbnd, s);
-        scan_u32(nsplit, choff, mapped_counts(c), m, ws, s);
-        check_launch("tree count");
-        ck(hipStreamSynchronize(s), "sync");
-        uint32_t nnew = c->hcount[0];
-        if ((size_t)c1 + nnew > c->c_begin.cap / sizeof(int32_t)) ensure_cells(c, (size_t)c1 + nnew, c1);
-        ca = cells_of(c);
-        tree_emit(ca, c0, c1, L, nsplit, choff, (const int32_t*)c->tbounds.p, s);
-        check_launch("tree emit");
-        c->lvl.push_back(c1);
-        total = c1 + (int32_t)nnew;
-        if (nnew == 0) break;
+    int lstar = 0;  // first empty level
+    for (;;) {
+        if (cap > (size_t)INT32_MAX) fail(FMM_ERR_UNSUPPORTED, "more than 2^31 cells");
+        ensure_cells(c, cap, 0);
+        {
+            std::vector<int32_t> neg(nroot, -1), zero(nroot, 0);
+            std::vector<uint64_t> z64(nroot, 0);
+            to_dev(c, c->c_begin.p, rb.data(), nroot);
+            to_dev(c, c->c_end.p, re.data(), nroot);
+            to_dev(c, c->c_parent.p, neg.data(), nroot);
+            to_dev(c, c->c_level.p, zero.data(), nroot);
+            to_dev(c, c->c_child.p, neg.data(), nroot);
+            to_dev(c, c->c_nchild.p, zero.data(), nroot);
+            to_dev(c, c->c_prefix.p, z64.data(), nroot);
+            std::vector<int32_t> h0(kMaxLevel + 8, 0);
+            h0[1] = nroot;
+            to_dev(c, dl, h0.data(), h0.size());
+        }
+        uint32_t* nsplit = need<uint32_t>(c, c->tmp1, cap + 1);
+        uint32_t* choff = need<uint32_t>(c, c->tmp2, cap + 1);
+        int32_t* tbnd = need<int32_t>(c, c->tbounds, cap * 7 + 1);
+        const CellArrays ca = cells_of(c);
+        int window = c->tree_levels > 0 ? c->tree_levels : 6;
+        int L = 0;
+        lstar = 0;
+        while (lstar == 0) {
+            for (int k = 0; k < window && L <= kMaxLevel; k++, L++) {
+                tree_count(keys, ca, dl, L, ncrit, nsplit, tbnd, (int32_t)cap, s);
+                scan_u32_dev(nsplit, choff, dnnew, DevCount{(const uint32_t*)(dl + L + 1), (const uint32_t*)(dl + L)},
+                             c->ws.p, s);
+                tree_emit(ca, dl, L, nsplit, choff, dnnew, tbnd, (int32_t)cap, dovf, s);
+            }
+            check_launch("tree levels");
+            to_host<int32_t>(c, hl.data(), dl, hl.size());
+            if (hl[kMaxLevel + 5] != 0) break;  // overflow
+            // levels [0, L) are done; the new cells of the last are [hl[L], hl[L + 1])
+            if (hl[L + 1] == hl[L]) {
+                lstar = 1;
+                while (hl[lstar + 1] != hl[lstar]) lstar++;
+            }
+            window = 6;
+        }
+        if (lstar > 0) break;
+        cap *= 2;
     }
+    c->tree_levels = lstar;
+    c->lvl.assign(hl.begin(), hl.begin() + lstar + 1);
+    const int32_t total = hl[lstar];
     c->ncell = total;
-    if (c->lvl.back() != total) c->lvl.push_back(total);
     need<int4>(c, c->c_geo, total);
     need<double4>(c, c->c_ctr, total);
     cell_geometry(cells_of(c), total, (const int64_t*)c->d_seg.p, nseg, (const Frame*)c->d_frame.p, s);
@@ -772,41 +788,61 @@ void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
         // passes the criterion: two leaves interact directly, else split
         (rch[0] == 0 && rch[1] == 0 ? self : start).push_back(make_int2(0, 1));
     }
-    int2* fr = need<int2>(c, c->fr0, std::max<size_t>(1024, start.size()));
-    if (!self.empty()) {
-        int2* r = need<int2>(c, c->raw[2], self.size());
-        to_dev(c, r, self.data(), self.size());
-        c->nlist[2] = (int64_t)self.size();
+    // Frontier levels run back to back on the device: the frontier size, the
+    // lists' running totals and the overflow bits stay in device memory, and
+    // the host reads them once per window of levels (as many as the previous
+    // traversal needed, else the bound 2 (levels) + 2: every level raises the
+    // sum of a pair's two cell levels).  A list or frontier that would pass
+    // its capacity ends the traversal; the buffers then grow and it runs
+    // again.
+    int64_t* cap = c->trav_cap;
+    if (cap[0] == 0) {
+        const int64_t per = std::min<int64_t>(m2l_plan_slots(theta), 4096) + 64;
+        for (int k = 0; k < 3; k++) cap[k] = std::max<int64_t>(1 << 16, per * nc);
+        cap[3] = std::max<int64_t>(1 << 16, 16 * nc);
     }
-    if (!start.empty()) to_dev(c, fr, start.data(), start.size());
-    int64_t nf = (int64_t)start.size();
-    while (nf > 0) {
-        size_t need_ws = scan_ws_bytes(nf);
-        if (need_ws > c->ws.cap) {
-            ck(hipStreamSynchronize(s), "sync");
-            ws = need<char>(c, c->ws, std::max(need_ws, c->ws.cap));
-        }
-        uint4* cnt = need<uint4>(c, c->cnt, nf);
-        uint4* off = need<uint4>(c, c->off4, nf);
-        fr = (int2*)c->fr0.p;
-        uint4* kinds = need<uint4>(c, c->kinds, nf);
-        trav_count(fr, nf, ca, tp, cnt, kinds, s);
-        scan_u32x4(cnt, off, (uint4*)mapped_counts(c), nf, ws, s);
-        check_launch("traverse count");
-        ck(hipStreamSynchronize(s), "sync");
-        const uint32_t* hh = c->hcount;
-        int64_t add[4] = {hh[0], hh[1], hh[2], hh[3]};
+    uint32_t* dt = need<uint32_t>(c, c->d_trav, 16);  // totals[3], frontier size, overflow, levels; scan total at 8
+    uint4* dadd = (uint4*)(dt + 8);
+    if (scan_dev_ws_bytes() > c->ws.cap) {
+        ws = need<char>(c, c->ws, scan_dev_ws_bytes());
+        d6 = (double*)c->small.p;
+    }
+    uint32_t h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (;;) {
+        cap[2] = std::max<int64_t>(cap[2], (int64_t)self.size());
+        cap[3] = std::max<int64_t>(cap[3], (int64_t)start.size());
         int2* lists[3];
-        for (int k = 0; k < 3; k++)
-            lists[k] = need_keep<int2>(c, c->raw[k], c->nlist[k] + add[k] + 1, c->nlist[k]);
-        int2* next = need<int2>(c, c->fr1, add[3] + 1);
-        trav_emit(fr, nf, ca, kinds, off, c->nlist[0], c->nlist[1], c->nlist[2], lists[0], lists[1], lists[2],
-                  next, s);
-        check_launch("traverse emit");
-        for (int k = 0; k < 3; k++) c->nlist[k] += add[k];
-        std::swap(c->fr0, c->fr1);
-        nf = add[3];
+        for (int k = 0; k < 3; k++) lists[k] = need<int2>(c, c->raw[k], cap[k] + 1);
+        int2* fa = need<int2>(c, c->fr0, cap[3] + 1);
+        int2* fb = need<int2>(c, c->fr1, cap[3] + 1);
+        uint4* cnt = need<uint4>(c, c->cnt, cap[3] + 1);
+        uint4* off = need<uint4>(c, c->off4, cap[3] + 1);
+        uint4* kinds = need<uint4>(c, c->kinds, cap[3] + 1);
+        if (!self.empty()) to_dev(c, lists[2], self.data(), self.size());
+        if (!start.empty()) to_dev(c, fa, start.data(), start.size());
+        const uint32_t h0[8] = {0, 0, (uint32_t)self.size(), (uint32_t)start.size(), 0, 0, 0, 0};
+        to_dev(c, dt, h0, 8);
+        const TravCaps tcap{cap[0], cap[1], cap[2], cap[3]};
+        int window = c->trav_levels > 0 ? c->trav_levels : 2 * std::max(c->tree_levels, 1) + 2;
+        for (;;) {
+            for (int k = 0; k < window; k++) {
+                trav_count(fa, dt + 3, cap[3], ca, tp, cnt, kinds, s);
+                scan_u32x4_dev(cnt, off, dadd, DevCount{dt + 3, nullptr}, c->ws.p, s);
+                trav_emit(fa, dt + 3, cap[3], ca, kinds, off, dt, dadd, tcap, lists[0], lists[1], lists[2], fb, dt + 4,
+                          dt + 5, s);
+                std::swap(fa, fb);
+            }
+            check_launch("traverse");
+            to_host<uint32_t>(c, h, dt, 8);
+            if (h[4] != 0 || h[3] == 0) break;
+            window = 4;
+        }
+        if (h[4] == 0) break;
+        for (int k = 0; k < 4; k++)
+            if (h[4] & (1u << k)) cap[k] *= 2;
     }
+    for (int k = 0; k < 3; k++) c->nlist[k] = h[k];
+    c->trav_levels = (int)h[5];
     mark(c, PH_LISTS);
     int bits = bits_for(nc);
     // split + stable sort by target + CSR offsets
@@ -1153,7 +1189,6 @@ void fmm_destroy(fmm_ctx c) {
     for (hipEvent_t e : {c->e_fork, c->e_join, c->e_p2p0, c->e_p2p1})
         if (e) (void)hipEventDestroy(e);
     if (c->host) (void)hipHostFree(c->host);
-    if (c->hcount) (void)hipHostFree(c->hcount);
     delete c;
 }
 
@@ -1781,7 +1816,7 @@ fmm_status fmm_costmodel_save(fmm_ctx c, const char* path) {
         else std::fprintf(f, "costs none\n");
         std::fprintf(f, "p2p_tpl");
         for (int k = 0; k < kLeafClasses; k++) std::fprintf(f, " %d", c->p2p_tpl[k]);
-        std::fprintf(f, "\nschedule %d\nweights %d\n", c->schedule, kMlpParams);
+        std::fprintf(f, "\nschedule %d\nm2l_kernel %d\nweights %d\n", c->schedule, c->m2l_kind, kMlpParams);
         for (int i = 0; i < kMlpParams; i++) std::fprintf(f, "%a%c", (double)w[i], (i % 8 == 7) ? '\n' : ' ');
         std::fprintf(f, "\nend\n");
         bool ok = std::ferror(f) == 0;
@@ -1828,7 +1863,16 @@ fmm_status fmm_costmodel_load(fmm_ctx c, const char* path, int32_t p, int32_t pr
         if (std::fscanf(f, " p2p_tpl") != 0) bad("missing tile shapes");
         for (int k = 0; k < kLeafClasses; k++)
             if (std::fscanf(f, "%d", &tpl[k]) != 1 || (tpl[k] != 0 && tpl[k] != 1 && tpl[k] != 2 && tpl[k] != 4)) bad("bad tile shapes");
-        if (std::fscanf(f, " schedule %d weights %d", &sched, &nw) != 2 || sched < 0 || sched > 2) bad("bad schedule");
+        if (std::fscanf(f, " schedule %d", &sched) != 1 || sched < 0 || sched > 2) bad("bad schedule");
+        // the M2L kind line is optional (files written before it existed lack it)
+        int mkind = -1;
+        if (std::fscanf(f, " %63s", word) != 1) bad("truncated file");
+        if (std::strcmp(word, "m2l_kernel") == 0) {
+            if (std::fscanf(f, "%d", &mkind) != 1 || mkind < FMM_M2L_CLASS_DENSE || mkind > FMM_M2L_PAIR_ROTATION)
+                bad("bad M2L kernel");
+            if (std::fscanf(f, " %63s", word) != 1) bad("truncated file");
+        }
+        if (std::strcmp(word, "weights") != 0 || std::fscanf(f, "%d", &nw) != 1) bad("missing weights");
         if (nw != kMlpParams) bad("weight count does not match this network");
         std::vector<float> w(kMlpParams);
         for (int i = 0; i < kMlpParams; i++) {
@@ -1858,6 +1902,7 @@ fmm_status fmm_costmodel_load(fmm_ctx c, const char* path, int32_t p, int32_t pr
         }
         for (int k = 0; k < kLeafClasses; k++) c->p2p_tpl[k] = tpl[k];
         c->schedule = sched;
+        if (mkind >= 0) c->m2l_kind = mkind;
     });
 }
 

@@ -49,6 +49,18 @@ size_t scan_ws_bytes(int64_t n);
 void scan_u32(const uint32_t* in, uint32_t* out, uint32_t* total, int64_t n, void* ws,
               hipStream_t s);
 void scan_u32x4(const uint4* in, uint4* out, uint4* total, int64_t n, void* ws, hipStream_t s);
+// An element count held in device memory, *hi - *lo (lo may be null), written
+// by an earlier kernel on the same stream.
+struct DevCount {
+    const uint32_t* hi;
+    const uint32_t* lo;
+    __device__ int64_t get() const { return (int64_t)*hi - (lo ? (int64_t)*lo : 0); }
+};
+// Exclusive scans of a device-held count of elements (at most the capacity of
+// in/out); the total goes to *total (device).  Workspace: scan_dev_ws_bytes().
+size_t scan_dev_ws_bytes();
+void scan_u32_dev(const uint32_t* in, uint32_t* out, uint32_t* total, DevCount n, void* ws, hipStream_t s);
+void scan_u32x4_dev(const uint4* in, uint4* out, uint4* total, DevCount n, void* ws, hipStream_t s);
 
 // Stable LSD radix sort on key bits [bit0, bit1), 8 bits per pass.  Result in
 // (keys_a, vals_a) on return; (keys_b, vals_b) is scratch of the same size.
@@ -95,14 +107,18 @@ void gather_sorted(const uint64_t* keys, const uint32_t* idx, const uint32_t* pe
                    uint32_t* idx2, hipStream_t s);
 void permute_points(const void* x, const void* y, const void* z, const void* q, int dtype,
                     int64_t n, const uint32_t* idx, float4* pts, hipStream_t s);
-// one level of the adaptive tree: cells [c0, c1) at level L.  nsplit[c-c0] =
-// number of children of cell c (0 if it does not split).
-// bounds: [c1 - c0][7] octant boundaries of the cells that split (scratch)
-void tree_count(const uint64_t* keys, CellArrays cells, int32_t c0, int32_t c1, int L,
-                int32_t ncrit, uint32_t* nsplit, int32_t* bounds, hipStream_t s);
-// child_off = exclusive scan of nsplit; children get ids c1 + child_off[c-c0]
-void tree_emit(CellArrays cells, int32_t c0, int32_t c1, int L, const uint32_t* nsplit,
-               const uint32_t* child_off, const int32_t* bounds, hipStream_t s);
+// one level of the adaptive tree: cells [c0, c1) = [lvl[L], lvl[L+1]) at
+// level L, bounds read from device memory.  nsplit[c-c0] = number of
+// children of cell c (0 if it does not split).
+// bounds: [c1 - c0][7] octant boundaries of the cells that split (scratch);
+// cap = cell capacity (every level is narrower)
+void tree_count(const uint64_t* keys, CellArrays cells, const int32_t* lvl, int L, int32_t ncrit,
+                uint32_t* nsplit, int32_t* bounds, int32_t cap, hipStream_t s);
+// child_off = exclusive scan of nsplit, *nnew its total; children get ids
+// c1 + child_off[c-c0]; writes lvl[L+2]; sets *ovf (and splits nothing) if
+// the level would pass cap cells
+void tree_emit(CellArrays cells, int32_t* lvl, int L, const uint32_t* nsplit, const uint32_t* child_off,
+               const uint32_t* nnew, const int32_t* bounds, int32_t cap, uint32_t* ovf, hipStream_t s);
 void cell_geometry(CellArrays cells, int32_t ncell, const int64_t* seg, int nseg, const Frame* fr, hipStream_t s);
 
 // sum over (tgt, src) pairs of n_t * n_s (both = 1) or n_t (both = 0) into *out (device)
@@ -145,11 +161,20 @@ struct TravParams {
 void cell_buckets(CellArrays cells, int32_t ncell, uint8_t* nbucket, hipStream_t s);
 // per frontier pair: counts of new (M2L, M2P, P2P, SPLIT) pairs, and the kind
 // of each child pair (2 bits each, at most 64 children, in emission order)
-void trav_count(const int2* frontier, int64_t nf, CellArrays cells, TravParams tp, uint4* cnt, uint4* kinds,
-                hipStream_t s);
-void trav_emit(const int2* frontier, int64_t nf, CellArrays cells, const uint4* kinds,
-               const uint4* off, int64_t base_m2l, int64_t base_m2p, int64_t base_p2p,
-               int2* m2l, int2* m2p, int2* p2p, int2* next, hipStream_t s);
+// The frontier size *nf, the lists' running totals tot[0..2] and the overflow
+// bits live in device memory; cap_frontier sizes the fixed grids.
+void trav_count(const int2* frontier, const uint32_t* nf, int64_t cap_frontier, CellArrays cells, TravParams tp,
+                uint4* cnt, uint4* kinds, hipStream_t s);
+// capacities of the three lists and of the next frontier, in pairs
+struct TravCaps {
+    int64_t m2l, m2p, p2p, next;
+};
+// emit at tot[k] + the scan offsets (total *add), then tot += *add, *nf =
+// the next frontier's size and *levels += 1 if the frontier was not empty; an
+// overflow sets bits in *ovf, writes nothing and sets *nf = 0
+void trav_emit(const int2* frontier, uint32_t* nf, int64_t cap_frontier, CellArrays cells, const uint4* kinds,
+               const uint4* off, uint32_t* tot, const uint4* add, TravCaps caps, int2* m2l, int2* m2p, int2* p2p,
+               int2* next, uint32_t* ovf, uint32_t* levels, hipStream_t s);
 void split_pairs(const int2* pairs, int64_t n, uint32_t* tgt, uint32_t* src, hipStream_t s);
 // offsets[c] = first index in the sorted target array with target >= c, c in [0, ncell]
 void csr_offsets(const uint32_t* tgt_sorted, int64_t n, int32_t ncell, int32_t* offsets,

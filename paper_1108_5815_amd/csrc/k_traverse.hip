@@ -18,6 +18,8 @@
 // levels are equal), only accepted pairs choose an interaction kind.
 #include "fmm_internal.h"
 
+#include <algorithm>
+
 #pragma clang fp contract(off)
 
 namespace fmm {
@@ -139,104 +141,151 @@ __device__ inline int entry_of(const EntryRanges& er, int c) {
     return lo;
 }
 
-__global__ __launch_bounds__(256) void k_trav_count(const int2* __restrict__ fr, int64_t nf, CellArrays c,
-                                                    TravParams tp, uint4* __restrict__ cnt,
+// The frontier holds *nfp entries (device memory); each wave takes kEPW of
+// them at a time, striding over the grid.
+__global__ __launch_bounds__(256) void k_trav_count(const int2* __restrict__ fr, const uint32_t* __restrict__ nfp,
+                                                    CellArrays c, TravParams tp, uint4* __restrict__ cnt,
                                                     uint4* __restrict__ kinds) {
     __shared__ EntryRanges s_er[4];
     __shared__ uint32_t s_n[4][kEPW][4];
     __shared__ unsigned long long s_lo[4][kEPW], s_hi[4][kEPW];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t f0 = ((int64_t)blockIdx.x * 4 + w) * kEPW;
-    if (f0 >= nf) return;  // wave-uniform; no block barrier below
-    EntryRanges& er = s_er[w];
-    if (lane < kEPW) {
+    const int64_t nf = *nfp;
+    const int64_t step = (int64_t)gridDim.x * 4 * kEPW;
+    // wave-uniform loop; no block barrier below
+    for (int64_t f0 = ((int64_t)blockIdx.x * 4 + w) * kEPW; f0 < nf; f0 += step) {
+        EntryRanges& er = s_er[w];
+        if (lane < kEPW) {
 #pragma unroll
-        for (int k = 0; k < 4; k++) s_n[w][lane][k] = 0;
-        s_lo[w][lane] = 0;
-        s_hi[w][lane] = 0;
-    }
-    const int total = wave_entries(fr, nf, f0, c, er, lane);
-    for (int r0 = 0; r0 < total; r0 += 64) {
-        const int ch = r0 + lane;
-        const bool valid = ch < total;
-        int e = 0, q = 0, k = 0;
-        if (valid) {
-            e = entry_of(er, ch);
-            q = ch - er.pre[e];
-            const int qt = (int)(((uint32_t)q * er.mns[e]) >> 16);
-            k = classify(c, er.t0[e] + qt, er.s0[e] + (q - qt * er.ns[e]), tp);
+            for (int k = 0; k < 4; k++) s_n[w][lane][k] = 0;
+            s_lo[w][lane] = 0;
+            s_hi[w][lane] = 0;
         }
-        // kinds of the round by ballot; the first lane of each entry in the
-        // round folds its entry's lanes into the entry's counts and masks
-        const uint64_t mv = __ballot(valid), m1 = __ballot(valid && (k & 1)), m2 = __ballot(valid && (k & 2));
-        if (valid && (q == 0 || lane == 0)) {
-            const int last = min(63, er.pre[e + 1] - r0 - 1);
-            const uint64_t upto = last == 63 ? ~0ull : ((1ull << (last + 1)) - 1ull);
-            const uint64_t rng = upto & ~((1ull << lane) - 1ull);
-            const uint64_t lo = m1 & rng, hi = m2 & rng, all = mv & rng;
-            s_n[w][e][KIND_M2L] += (uint32_t)__popcll(all & ~lo & ~hi);
-            s_n[w][e][KIND_M2P] += (uint32_t)__popcll(lo & ~hi);
-            s_n[w][e][KIND_P2P] += (uint32_t)__popcll(~lo & hi);
-            s_n[w][e][KIND_SPLIT] += (uint32_t)__popcll(lo & hi);
-            s_lo[w][e] |= (lo >> lane) << q;
-            s_hi[w][e] |= (hi >> lane) << q;
+        const int total = wave_entries(fr, nf, f0, c, er, lane);
+        for (int r0 = 0; r0 < total; r0 += 64) {
+            const int ch = r0 + lane;
+            const bool valid = ch < total;
+            int e = 0, q = 0, k = 0;
+            if (valid) {
+                e = entry_of(er, ch);
+                q = ch - er.pre[e];
+                const int qt = (int)(((uint32_t)q * er.mns[e]) >> 16);
+                k = classify(c, er.t0[e] + qt, er.s0[e] + (q - qt * er.ns[e]), tp);
+            }
+            // kinds of the round by ballot; the first lane of each entry in the
+            // round folds its entry's lanes into the entry's counts and masks
+            const uint64_t mv = __ballot(valid), m1 = __ballot(valid && (k & 1)), m2 = __ballot(valid && (k & 2));
+            if (valid && (q == 0 || lane == 0)) {
+                const int last = min(63, er.pre[e + 1] - r0 - 1);
+                const uint64_t upto = last == 63 ? ~0ull : ((1ull << (last + 1)) - 1ull);
+                const uint64_t rng = upto & ~((1ull << lane) - 1ull);
+                const uint64_t lo = m1 & rng, hi = m2 & rng, all = mv & rng;
+                s_n[w][e][KIND_M2L] += (uint32_t)__popcll(all & ~lo & ~hi);
+                s_n[w][e][KIND_M2P] += (uint32_t)__popcll(lo & ~hi);
+                s_n[w][e][KIND_P2P] += (uint32_t)__popcll(~lo & hi);
+                s_n[w][e][KIND_SPLIT] += (uint32_t)__popcll(lo & hi);
+                s_lo[w][e] |= (lo >> lane) << q;
+                s_hi[w][e] |= (hi >> lane) << q;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int64_t f = f0 + lane;
+        if (lane < kEPW && f < nf) {
+            cnt[f] = make_uint4(s_n[w][lane][0], s_n[w][lane][1], s_n[w][lane][2], s_n[w][lane][3]);
+            const unsigned long long lo = s_lo[w][lane], hi = s_hi[w][lane];
+            kinds[f] = make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
+        }
+        // the wave's LDS is reset and refilled by its next group of entries
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+// Children of the frontier's *nfp entries to the three lists (at their
+// running totals tot[0..2]) and the next frontier, at the offsets of the
+// scan whose total is *add.  If a list or the next frontier would pass its
+// capacity, nothing is written and the overflow bits are set (1, 2, 4: the
+// lists; 8: the frontier).
+__global__ __launch_bounds__(256) void k_trav_emit(const int2* __restrict__ fr, const uint32_t* __restrict__ nfp,
+                                                   CellArrays c, const uint4* __restrict__ kinds,
+                                                   const uint4* __restrict__ off, const uint32_t* __restrict__ tot,
+                                                   const uint4* __restrict__ add, TravCaps caps,
+                                                   int2* __restrict__ m2l, int2* __restrict__ m2p,
+                                                   int2* __restrict__ p2p, int2* __restrict__ next,
+                                                   uint32_t* __restrict__ ovf) {
+    __shared__ EntryRanges s_er[4];
+    __shared__ unsigned long long s_lo[4][kEPW], s_hi[4][kEPW];
+    __shared__ uint4 s_off[4][kEPW];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t nf = *nfp;
+    const uint4 a = *add;
+    const int64_t b0 = tot[0], b1 = tot[1], b2 = tot[2];
+    const uint32_t bits = (b0 + a.x > caps.m2l ? 1u : 0u) | (b1 + a.y > caps.m2p ? 2u : 0u) |
+                          (b2 + a.z > caps.p2p ? 4u : 0u) | ((int64_t)a.w > caps.next ? 8u : 0u);
+    if (bits) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) *ovf |= bits;
+        return;
+    }
+    const int64_t step = (int64_t)gridDim.x * 4 * kEPW;
+    // wave-uniform loop; no block barrier below
+    for (int64_t f0 = ((int64_t)blockIdx.x * 4 + w) * kEPW; f0 < nf; f0 += step) {
+        EntryRanges& er = s_er[w];
+        {
+            const int64_t f = f0 + lane;
+            if (lane < kEPW && f < nf) {
+                const uint4 kw = kinds[f];
+                s_lo[w][lane] = (unsigned long long)kw.x | ((unsigned long long)kw.y << 32);
+                s_hi[w][lane] = (unsigned long long)kw.z | ((unsigned long long)kw.w << 32);
+                s_off[w][lane] = off[f];
+            }
+        }
+        const int total = wave_entries(fr, nf, f0, c, er, lane);
+        for (int r0 = 0; r0 < total; r0 += 64) {
+            const int ch = r0 + lane;
+            if (ch < total) {
+                const int e = entry_of(er, ch);
+                const int q = ch - er.pre[e];
+                const int ns = er.ns[e];
+                const int qt = q / ns;
+                const int2 v = make_int2(er.t0[e] + qt, er.s0[e] + (q - qt * ns));
+                const unsigned long long lo = s_lo[w][e], hi = s_hi[w][e];
+                const int k = (int)((lo >> q) & 1ull) | ((int)((hi >> q) & 1ull) << 1);
+                const unsigned long long same = ((k & 1) ? lo : ~lo) & ((k & 2) ? hi : ~hi);
+                const uint32_t rank = (uint32_t)__popcll(same & ((1ull << q) - 1ull));
+                const uint4 o = s_off[w][e];
+                if (k == KIND_M2L) m2l[b0 + o.x + rank] = v;
+                else if (k == KIND_M2P) m2p[b1 + o.y + rank] = v;
+                else if (k == KIND_P2P) p2p[b2 + o.z + rank] = v;
+                else next[(int64_t)o.w + rank] = v;
+            }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const int64_t f = f0 + lane;
-    if (lane < kEPW && f < nf) {
-        cnt[f] = make_uint4(s_n[w][lane][0], s_n[w][lane][1], s_n[w][lane][2], s_n[w][lane][3]);
-        const unsigned long long lo = s_lo[w][lane], hi = s_hi[w][lane];
-        kinds[f] = make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
-    }
 }
 
-__global__ __launch_bounds__(256) void k_trav_emit(const int2* __restrict__ fr, int64_t nf, CellArrays c,
-                                                   const uint4* __restrict__ kinds, const uint4* __restrict__ off,
-                                                   int64_t b0, int64_t b1, int64_t b2, int2* __restrict__ m2l,
-                                                   int2* __restrict__ m2p, int2* __restrict__ p2p,
-                                                   int2* __restrict__ next) {
-    __shared__ EntryRanges s_er[4];
-    __shared__ unsigned long long s_lo[4][kEPW], s_hi[4][kEPW];
-    __shared__ uint4 s_off[4][kEPW];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t f0 = ((int64_t)blockIdx.x * 4 + w) * kEPW;
-    if (f0 >= nf) return;  // wave-uniform; no block barrier below
-    EntryRanges& er = s_er[w];
-    {
-        const int64_t f = f0 + lane;
-        if (lane < kEPW && f < nf) {
-            const uint4 kw = kinds[f];
-            s_lo[w][lane] = (unsigned long long)kw.x | ((unsigned long long)kw.y << 32);
-            s_hi[w][lane] = (unsigned long long)kw.z | ((unsigned long long)kw.w << 32);
-            s_off[w][lane] = off[f];
-        }
+// after an emit: running totals += the level's counts, frontier size = its
+// split pairs (0 after an overflow, which ends the traversal)
+__global__ void k_trav_advance(uint32_t* __restrict__ tot, const uint4* __restrict__ add, uint32_t* __restrict__ nf,
+                               const uint32_t* __restrict__ ovf, uint32_t* __restrict__ levels) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const uint4 a = *add;
+    if (*ovf) {
+        *nf = 0;
+        return;
     }
-    const int total = wave_entries(fr, nf, f0, c, er, lane);
-    for (int r0 = 0; r0 < total; r0 += 64) {
-        const int ch = r0 + lane;
-        if (ch < total) {
-            const int e = entry_of(er, ch);
-            const int q = ch - er.pre[e];
-            const int ns = er.ns[e];
-            const int qt = q / ns;
-            const int2 v = make_int2(er.t0[e] + qt, er.s0[e] + (q - qt * ns));
-            const unsigned long long lo = s_lo[w][e], hi = s_hi[w][e];
-            const int k = (int)((lo >> q) & 1ull) | ((int)((hi >> q) & 1ull) << 1);
-            const unsigned long long same = ((k & 1) ? lo : ~lo) & ((k & 2) ? hi : ~hi);
-            const uint32_t rank = (uint32_t)__popcll(same & ((1ull << q) - 1ull));
-            const uint4 o = s_off[w][e];
-            if (k == KIND_M2L) m2l[b0 + o.x + rank] = v;
-            else if (k == KIND_M2P) m2p[b1 + o.y + rank] = v;
-            else if (k == KIND_P2P) p2p[b2 + o.z + rank] = v;
-            else next[(int64_t)o.w + rank] = v;
-        }
-    }
+    if (*nf > 0) *levels += 1u;
+    tot[0] += a.x;
+    tot[1] += a.y;
+    tot[2] += a.z;
+    *nf = a.w;
 }
 
 __global__ void k_split_pairs(const int2* __restrict__ pairs, int64_t n, uint32_t* __restrict__ tgt,
@@ -409,18 +458,22 @@ void cell_buckets(CellArrays cells, int32_t ncell, uint8_t* nbucket, hipStream_t
     k_cell_buckets<<<grid(ncell), 256, 0, s>>>(cells, ncell, nbucket);
 }
 
-void trav_count(const int2* frontier, int64_t nf, CellArrays cells, TravParams tp, uint4* cnt, uint4* kinds,
-                hipStream_t s) {
-    if (nf <= 0) return;
-    k_trav_count<<<grid(nf, 4 * kEPW), 256, 0, s>>>(frontier, nf, cells, tp, cnt, kinds);
+// fixed grids sized for the frontier's capacity
+static unsigned trav_blocks(int64_t cap_frontier) {
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>((cap_frontier + 4 * kEPW - 1) / (4 * kEPW), 4096));
 }
 
-void trav_emit(const int2* frontier, int64_t nf, CellArrays cells, const uint4* kinds, const uint4* off,
-               int64_t base_m2l, int64_t base_m2p, int64_t base_p2p, int2* m2l, int2* m2p, int2* p2p,
-               int2* next, hipStream_t s) {
-    if (nf <= 0) return;
-    k_trav_emit<<<grid(nf, 4 * kEPW), 256, 0, s>>>(frontier, nf, cells, kinds, off, base_m2l, base_m2p, base_p2p, m2l,
-                                         m2p, p2p, next);
+void trav_count(const int2* frontier, const uint32_t* nf, int64_t cap_frontier, CellArrays cells, TravParams tp,
+                uint4* cnt, uint4* kinds, hipStream_t s) {
+    k_trav_count<<<trav_blocks(cap_frontier), 256, 0, s>>>(frontier, nf, cells, tp, cnt, kinds);
+}
+
+void trav_emit(const int2* frontier, uint32_t* nf, int64_t cap_frontier, CellArrays cells, const uint4* kinds,
+               const uint4* off, uint32_t* tot, const uint4* add, TravCaps caps, int2* m2l, int2* m2p, int2* p2p,
+               int2* next, uint32_t* ovf, uint32_t* levels, hipStream_t s) {
+    k_trav_emit<<<trav_blocks(cap_frontier), 256, 0, s>>>(frontier, nf, cells, kinds, off, tot, add, caps, m2l, m2p,
+                                                          p2p, next, ovf);
+    k_trav_advance<<<1, 64, 0, s>>>(tot, add, nf, ovf, levels);
 }
 
 void split_pairs(const int2* pairs, int64_t n, uint32_t* tgt, uint32_t* src, hipStream_t s) {

@@ -10,6 +10,8 @@
 // Cells are numbered level by level in key order (breadth-first).
 #include "fmm_internal.h"
 
+#include <algorithm>
+
 #pragma clang fp contract(off)
 
 namespace fmm {
@@ -159,72 +161,74 @@ __global__ void k_permute(const F* __restrict__ x, const F* __restrict__ y, cons
 // position per open interval and a ballot per octant shrinks it 64-fold, so a
 // cell of 4M keys needs 4 rounds of independent loads instead of 7 binary
 // searches of 22 dependent ones.  The boundaries are kept for the emit pass.
-__global__ __launch_bounds__(256) void k_tree_count(const uint64_t* __restrict__ keys, CellArrays cells, int32_t c0,
-                                                    int32_t c1, int L, int32_t ncrit, uint32_t* __restrict__ nsplit,
-                                                    int32_t* __restrict__ bounds) {
+// The level's cells are [lvl[L], lvl[L+1]) (device memory, written by the
+// previous level's emit); waves stride over them.
+__global__ __launch_bounds__(256) void k_tree_count(const uint64_t* __restrict__ keys, CellArrays cells,
+                                                    const int32_t* __restrict__ lvl, int L, int32_t ncrit,
+                                                    uint32_t* __restrict__ nsplit, int32_t* __restrict__ bounds) {
     const int lane = threadIdx.x & 63;
-    const int32_t c = c0 + (int32_t)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-    if (c >= c1) return;  // wave-uniform
-    const int32_t b = cells.begin[c], e = cells.end[c];
-    uint32_t cnt = 0;
-    if (e - b > ncrit && L < kMaxLevel) {
-        const int sh = 3 * (20 - L);  // bit position of the level-(L+1) digit
-        const uint64_t pre3 = cells.prefix[c] << 3;
-        int32_t lo[7], hi[7];
-#pragma unroll
-        for (int o = 0; o < 7; o++) {
-            lo[o] = b;
-            hi[o] = e;
-        }
-        bool open = true;
-        while (open) {
-            uint64_t kv[7];
+    const int32_t c0 = lvl[L], c1 = lvl[L + 1];
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t wv = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; wv < (int64_t)c1 - c0; wv += nw) {
+        const int32_t c = c0 + (int32_t)wv;  // wave-uniform
+        const int32_t b = cells.begin[c], e = cells.end[c];
+        uint32_t cnt = 0;
+        if (e - b > ncrit && L < kMaxLevel) {
+            const int sh = 3 * (20 - L);  // bit position of the level-(L+1) digit
+            const uint64_t pre3 = cells.prefix[c] << 3;
+            int32_t lo[7], hi[7];
 #pragma unroll
             for (int o = 0; o < 7; o++) {
-                const int64_t span = hi[o] - lo[o];
-                kv[o] = span > 0 ? keys[lo[o] + (int32_t)((span * lane) >> 6)] : 0ull;
+                lo[o] = b;
+                hi[o] = e;
             }
-            open = false;
+            bool open = true;
+            while (open) {
+                uint64_t kv[7];
 #pragma unroll
-            for (int o = 0; o < 7; o++) {
-                const int64_t span = hi[o] - lo[o];
-                if (span <= 0) continue;
-                const uint64_t tgt = (pre3 | (uint64_t)(o + 1)) << sh;
-                const int nb = __popcll(__ballot(kv[o] < tgt));  // samples below the boundary
-                if (nb == 0) {
-                    hi[o] = lo[o];  // key[lo] >= tgt
-                } else {
-                    const int32_t below = lo[o] + (int32_t)((span * (nb - 1)) >> 6);
-                    const int32_t above = nb < 64 ? lo[o] + (int32_t)((span * nb) >> 6) : hi[o];
-                    lo[o] = below + 1;
-                    hi[o] = above;
+                for (int o = 0; o < 7; o++) {
+                    const int64_t span = hi[o] - lo[o];
+                    kv[o] = span > 0 ? keys[lo[o] + (int32_t)((span * lane) >> 6)] : 0ull;
                 }
-                if (hi[o] > lo[o]) open = true;
+                open = false;
+#pragma unroll
+                for (int o = 0; o < 7; o++) {
+                    const int64_t span = hi[o] - lo[o];
+                    if (span <= 0) continue;
+                    const uint64_t tgt = (pre3 | (uint64_t)(o + 1)) << sh;
+                    const int nb = __popcll(__ballot(kv[o] < tgt));  // samples below the boundary
+                    if (nb == 0) {
+                        hi[o] = lo[o];  // key[lo] >= tgt
+                    } else {
+                        const int32_t below = lo[o] + (int32_t)((span * (nb - 1)) >> 6);
+                        const int32_t above = nb < 64 ? lo[o] + (int32_t)((span * nb) >> 6) : hi[o];
+                        lo[o] = below + 1;
+                        hi[o] = above;
+                    }
+                    if (hi[o] > lo[o]) open = true;
+                }
+            }
+            int32_t prev = b;
+#pragma unroll
+            for (int o = 0; o < 7; o++) {
+                cnt += lo[o] > prev ? 1u : 0u;
+                prev = lo[o];
+            }
+            cnt += e > prev ? 1u : 0u;
+            if (lane < 7) {
+                int32_t v = lo[0];
+#pragma unroll
+                for (int o = 1; o < 7; o++)
+                    if (lane == o) v = lo[o];
+                bounds[(int64_t)(c - c0) * 7 + lane] = v;
             }
         }
-        int32_t prev = b;
-#pragma unroll
-        for (int o = 0; o < 7; o++) {
-            cnt += lo[o] > prev ? 1u : 0u;
-            prev = lo[o];
-        }
-        cnt += e > prev ? 1u : 0u;
-        if (lane < 7) {
-            int32_t v = lo[0];
-#pragma unroll
-            for (int o = 1; o < 7; o++)
-                if (lane == o) v = lo[o];
-            bounds[(int64_t)(c - c0) * 7 + lane] = v;
-        }
+        if (lane == 0) nsplit[c - c0] = cnt;
     }
-    if (lane == 0) nsplit[c - c0] = cnt;
 }
 
-__global__ void k_tree_emit(CellArrays cells, int32_t c0, int32_t c1, int L, const uint32_t* __restrict__ nsplit,
-                            const uint32_t* __restrict__ off, const int32_t* __restrict__ bounds) {
-    int32_t c = c0 + (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (c >= c1) return;
-    uint32_t cnt = nsplit[c - c0];
+__device__ inline void emit_cell(CellArrays cells, int32_t c, int32_t c0, int32_t c1, int L, uint32_t cnt,
+                                 const uint32_t* __restrict__ off, const int32_t* __restrict__ bounds) {
     if (cnt == 0) {
         cells.child[c] = -1;
         cells.nchild[c] = 0;
@@ -251,6 +255,25 @@ __global__ void k_tree_emit(CellArrays cells, int32_t c0, int32_t c1, int L, con
         cells.nchild[k] = 0;
         k++;
     }
+}
+
+// Children of the level's cells at lvl[L+1] + off; writes lvl[L+2].  If the
+// new level would pass the cell capacity, nothing splits, lvl[L+2] = lvl[L+1]
+// (the tree stops) and *ovf is set: the caller grows the arrays and builds
+// again.
+__global__ void k_tree_emit(CellArrays cells, int32_t* __restrict__ lvl, int L, const uint32_t* __restrict__ nsplit,
+                            const uint32_t* __restrict__ off, const uint32_t* __restrict__ nnew_p,
+                            const int32_t* __restrict__ bounds, int32_t cap, uint32_t* __restrict__ ovf) {
+    const int32_t c0 = lvl[L], c1 = lvl[L + 1];
+    const uint32_t nnew = *nnew_p;
+    const bool fits = (int64_t)c1 + nnew <= (int64_t)cap;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        lvl[L + 2] = fits ? c1 + (int32_t)nnew : c1;
+        if (!fits) *ovf = 1u;
+    }
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)c1 - c0; i += stride)
+        emit_cell(cells, c0 + (int32_t)i, c0, c1, L, fits ? nsplit[i] : 0u, off, bounds);
 }
 
 __global__ void k_geometry(CellArrays cells, int32_t ncell, const int64_t* __restrict__ seg, int nseg,
@@ -327,19 +350,17 @@ void permute_points(const void* x, const void* y, const void* z, const void* q, 
                                            (const float*)q, n, idx, pts);
 }
 
-void tree_count(const uint64_t* keys, CellArrays cells, int32_t c0, int32_t c1, int L, int32_t ncrit,
-                uint32_t* nsplit, int32_t* bounds, hipStream_t s) {
-    int32_t m = c1 - c0;
-    if (m <= 0) return;
-    k_tree_count<<<(unsigned)(((int64_t)m * 64 + 255) / 256), 256, 0, s>>>(keys, cells, c0, c1, L, ncrit, nsplit,
-                                                                          bounds);
+// fixed grids sized for the widest level the capacity allows
+void tree_count(const uint64_t* keys, CellArrays cells, const int32_t* lvl, int L, int32_t ncrit, uint32_t* nsplit,
+                int32_t* bounds, int32_t cap, hipStream_t s) {
+    const int64_t blocks = std::min<int64_t>(((int64_t)cap + 3) / 4, 2048);
+    k_tree_count<<<(unsigned)blocks, 256, 0, s>>>(keys, cells, lvl, L, ncrit, nsplit, bounds);
 }
 
-void tree_emit(CellArrays cells, int32_t c0, int32_t c1, int L, const uint32_t* nsplit, const uint32_t* child_off,
-               const int32_t* bounds, hipStream_t s) {
-    int32_t m = c1 - c0;
-    if (m <= 0) return;
-    k_tree_emit<<<(m + 255) / 256, 256, 0, s>>>(cells, c0, c1, L, nsplit, child_off, bounds);
+void tree_emit(CellArrays cells, int32_t* lvl, int L, const uint32_t* nsplit, const uint32_t* child_off,
+               const uint32_t* nnew, const int32_t* bounds, int32_t cap, uint32_t* ovf, hipStream_t s) {
+    const int64_t blocks = std::min<int64_t>(((int64_t)cap + 255) / 256, 1024);
+    k_tree_emit<<<(unsigned)blocks, 256, 0, s>>>(cells, lvl, L, nsplit, child_off, nnew, bounds, cap, ovf);
 }
 
 void cell_geometry(CellArrays cells, int32_t ncell, const int64_t* seg, int nseg, const Frame* fr, hipStream_t s) {

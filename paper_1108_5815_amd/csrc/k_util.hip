@@ -350,6 +350,78 @@ void sort_impl(K* ka, uint32_t* va, K* kb, uint32_t* vb, int64_t n, int bit0, in
     }
 }
 
+
+// Scans over a count held in device memory (written by an earlier kernel on
+// the stream, so the host launches them without reading it): a fixed grid of
+// SG workgroups, each taking a contiguous run of tiles.
+constexpr int SG = 256;
+
+template <class T>
+__global__ void k_scand_reduce(const T* __restrict__ in, DevCount cnt, T* __restrict__ part) {
+    __shared__ uint32_t lds[SB / 64];
+    const int64_t n = cnt.get();
+    const int64_t ntile = (n + ST - 1) / ST, per = (ntile + SG - 1) / SG;
+    const int64_t g0 = (int64_t)blockIdx.x * per * ST, g1 = min(g0 + per * ST, n);
+    T out;
+    for (int c = 0; c < Ops<T>::C; c++) {
+        uint32_t acc = 0;
+        for (int64_t g = g0 + threadIdx.x; g < g1; g += SB) acc += Ops<T>::get(in[g], c);
+        uint32_t tot;
+        block_excl_u32(acc, lds, &tot);
+        Ops<T>::set(out, c, tot);
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = out;
+}
+
+template <class T>
+__global__ void k_scand_down(const T* __restrict__ in, T* __restrict__ out, DevCount cnt,
+                             const T* __restrict__ part) {
+    __shared__ uint32_t lds[SB / 64];
+    const int64_t n = cnt.get();
+    const int64_t ntile = (n + ST - 1) / ST, per = (ntile + SG - 1) / SG;
+    const int64_t t0 = (int64_t)blockIdx.x * per, t1 = min(t0 + per, ntile);
+    uint32_t carry[Ops<T>::C];
+    const T pb = part[blockIdx.x];
+    for (int c = 0; c < Ops<T>::C; c++) carry[c] = Ops<T>::get(pb, c);
+    for (int64_t tile = t0; tile < t1; tile++) {  // uniform over the workgroup
+        const int64_t base = tile * ST + (int64_t)threadIdx.x * SI;
+        T v[SI], res[SI];
+#pragma unroll
+        for (int j = 0; j < SI; j++) {
+            const int64_t g = base + j;
+            if (g < n) v[j] = in[g];
+            else
+                for (int c = 0; c < Ops<T>::C; c++) Ops<T>::set(v[j], c, 0u);
+        }
+        for (int c = 0; c < Ops<T>::C; c++) {
+            uint32_t sum = 0;
+#pragma unroll
+            for (int j = 0; j < SI; j++) sum += Ops<T>::get(v[j], c);
+            uint32_t tot;
+            uint32_t run = block_excl_u32(sum, lds, &tot) + carry[c];
+#pragma unroll
+            for (int j = 0; j < SI; j++) {
+                Ops<T>::set(res[j], c, run);
+                run += Ops<T>::get(v[j], c);
+            }
+            carry[c] += tot;
+        }
+#pragma unroll
+        for (int j = 0; j < SI; j++) {
+            const int64_t g = base + j;
+            if (g < n) out[g] = res[j];
+        }
+    }
+}
+
+template <class T>
+void scand_impl(const T* in, T* out, T* total, DevCount n, void* ws, hipStream_t s) {
+    T* part = (T*)ws;
+    k_scand_reduce<T><<<SG, SB, 0, s>>>(in, n, part);
+    k_scan_partials<T><<<1, SB, 0, s>>>(part, SG, total);
+    k_scand_down<T><<<SG, SB, 0, s>>>(in, out, n, part);
+}
+
 __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -388,6 +460,16 @@ void scan_u32(const uint32_t* in, uint32_t* out, uint32_t* total, int64_t n, voi
 
 void scan_u32x4(const uint4* in, uint4* out, uint4* total, int64_t n, void* ws, hipStream_t s) {
     scan_impl<uint4>(in, out, total, n, ws, s);
+}
+
+size_t scan_dev_ws_bytes() { return (size_t)SG * sizeof(uint4) + 256; }
+
+void scan_u32_dev(const uint32_t* in, uint32_t* out, uint32_t* total, DevCount n, void* ws, hipStream_t s) {
+    scand_impl<uint32_t>(in, out, total, n, ws, s);
+}
+
+void scan_u32x4_dev(const uint4* in, uint4* out, uint4* total, DevCount n, void* ws, hipStream_t s) {
+    scand_impl<uint4>(in, out, total, n, ws, s);
 }
 
 size_t sort_ws_bytes(int64_t n) {
