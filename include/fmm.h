@@ -363,8 +363,8 @@ fmm_status fmm_costmodel_loss_grad(fmm_ctx ctx, const float *weights, int32_t n_
  * as hexadecimal floats), the order, theta and precision it was trained for
  * (-1 where unknown, e.g. after fmm_costmodel_set_weights), the name of the
  * device whose kernel timings trained it, the final training loss, the
- * timed unit costs (if set) and the tile shapes, schedule and M2L kernel
- * kind (fmm_set_m2l_kernel) in use.  This keeps the learned choices of a device fixed across processes, where
+ * timed unit costs (if set) and the tile shapes, schedule, M2L kernel kind
+ * (fmm_set_m2l_kernel) and M2L tile width (fmm_set_m2l_tile) in use.  This keeps the learned choices of a device fixed across processes, where
  * retraining on fresh timings would give slightly different choices.
  * save: FMM_ERR_STATE without a model, FMM_ERR_DEVICE if the file cannot be
  * written.  load(path, p, precision): the file must come from a device of
@@ -372,8 +372,8 @@ fmm_status fmm_costmodel_loss_grad(fmm_ctx ctx, const float *weights, int32_t n_
  * order and precision; otherwise FMM_ERR_INVALID_ARG (also for a missing,
  * unreadable or malformed file, or another format version) and the context
  * keeps its model.  On success the weights, unit costs (when the file has
- * them), tile shapes, schedule and M2L kernel kind (when the file has it)
- * replace the context's.
+ * them), tile shapes, schedule, M2L kernel kind and tile width (when the
+ * file has them) replace the context's.
  */
 fmm_status fmm_costmodel_save(fmm_ctx ctx, const char *path);
 fmm_status fmm_costmodel_load(fmm_ctx ctx, const char *path, int32_t p, int32_t precision);
@@ -485,14 +485,28 @@ fmm_status fmm_set_overlap(fmm_ctx ctx, int32_t schedule);
  * sums over sources on the matrix cores (FP32 rank-1 updates); if the lists
  * hold M2L pairs outside the same-level GEMM (spherical family) it times
  * fmm_evaluate under the four kinds of fmm_set_m2l_kernel and keeps the
- * fastest; then it times fmm_evaluate at `precision` under the three
- * schedules of fmm_set_overlap and keeps the fastest.  The schedule does not change results; the
- * tile shape changes how each target's P2P sum is split into FP32 partials,
- * so results move by rounding only (each choice is itself deterministic).
+ * fastest; where the M2L GEMM has two tile widths it times both
+ * (fmm_set_m2l_tile) and keeps the faster; then it times fmm_evaluate at
+ * `precision` under the three schedules of fmm_set_overlap and keeps the
+ * fastest.  The schedule and the M2L tile width do not change results; the
+ * P2P tile shape and the M2L kind change how sums are split into FP32
+ * partials, so results move by rounding only (each choice is itself
+ * deterministic).
  * Requires a completed traversal.  Default before tuning: 4 targets per lane,
  * schedule 2.
  */
 fmm_status fmm_autotune(fmm_ctx ctx, int32_t precision, int32_t reps);
+
+/* Targets per tile of the same-level M2L GEMM (one octant class per tile):
+ * 64 or 128 where the coefficient storage width is 128 (spherical p = 10),
+ * 0 = the width's default (64); other widths have one tiling and ignore it.
+ * Takes effect at the next fmm_traverse (fmm_autotune also rebuilds the
+ * current tables when it picks a width).  Wider tiles load each translation
+ * operator once for more targets.  get: the width of the current tables
+ * (after a traversal with GEMM pairs), else the one asked for.  Any other
+ * value is FMM_ERR_INVALID_ARG. */
+fmm_status fmm_set_m2l_tile(fmm_ctx ctx, int32_t cols);
+fmm_status fmm_get_m2l_tile(fmm_ctx ctx, int32_t *cols);
 
 /* The tile shapes in use (p2p_tpl[4], host) and the schedule (*overlap, as
  * fmm_set_overlap);

@@ -91,6 +91,8 @@ def lib():
         "fmm_set_expansion": ([vp, i32, i32], ctypes.c_int),
         "fmm_set_m2l_kernel": ([vp, i32], ctypes.c_int),
         "fmm_get_m2l_kernel": ([vp, vp], ctypes.c_int),
+        "fmm_set_m2l_tile": ([vp, i32], ctypes.c_int),
+        "fmm_get_m2l_tile": ([vp, vp], ctypes.c_int),
         "fmm_get_expansion": ([vp, vp], ctypes.c_int),
         "fmm_evaluate_noalloc": ([vp, i32, i32, vp, vp, vp, vp], ctypes.c_int),
     }
@@ -300,6 +302,15 @@ class FMM:
         self._ck(lib().fmm_get_m2l_kernel(self.h, ctypes.byref(v)))
         return v.value
 
+    def set_m2l_tile(self, cols: int):
+        """Targets per M2L GEMM tile (0, 64 or 128); used from the next traverse."""
+        self._ck(lib().fmm_set_m2l_tile(self.h, int(cols)))
+
+    def m2l_tile(self) -> int:
+        v = ctypes.c_int32()
+        self._ck(lib().fmm_get_m2l_tile(self.h, ctypes.byref(v)))
+        return int(v.value)
+
     def expansion(self) -> int:
         """Family of the last traversal (EXPANSION_SPHERICAL or EXPANSION_CARTESIAN)."""
         v = ctypes.c_int32()
@@ -387,7 +398,8 @@ class FMM:
         self._ck(lib().fmm_set_overlap(self.h, sc))
 
     def autotune(self, precision: int = PREC_FP32, reps: int = 3):
-        """Pick P2P tile shapes per leaf-size class and the schedule by timing."""
+        """Pick P2P tile shapes per leaf-size class, the M2L kernel kind and GEMM
+        tile width, and the schedule, by timing."""
         self._ck(lib().fmm_autotune(self.h, int(precision), int(reps)))
         return self.tile_config()
 
@@ -395,7 +407,8 @@ class FMM:
         tpl = np.zeros(4, np.int32)
         ov = ctypes.c_int32()
         self._ck(lib().fmm_get_tile_config(self.h, _ptr(tpl), ctypes.byref(ov)))
-        return {"p2p_targets_per_lane": tpl.tolist(), "schedule": int(ov.value), "m2l_kernel": self.m2l_kernel()}
+        return {"p2p_targets_per_lane": tpl.tolist(), "schedule": int(ov.value), "m2l_kernel": self.m2l_kernel(),
+                "m2l_tile": self.m2l_tile()}
 
     def set_tile_config(self, tpl):
         a = np.ascontiguousarray(np.asarray(tpl, dtype=np.int32))

@@ -85,6 +85,7 @@ struct fmm_ctx_s {
     int32_t ncell = 0, nleaf = 0;
     std::vector<int32_t> lvl;  // cells of level L: [lvl[L], lvl[L+1])
     int tree_levels = 0;       // levels the last build needed (its first empty level)
+    int gemm_nt = 0;           // M2L GEMM targets per tile asked for (0: the width's default)
     int trav_levels = 0;       // frontier levels the last traversal needed
     int64_t trav_cap[4] = {0, 0, 0, 0};  // pair capacities of the three lists and the frontier
     Buf keys, keys2, idx, idx2, pts, ws, small;
@@ -709,6 +710,38 @@ void build_classes(fmm_ctx c, int p) {
     cp.pos = pos;
 }
 
+// GEMM tiles of tc targets over the rows of the M2L GEMM (rows sorted by
+// class and density in rval, class bounds in gp.class_row0): the row -> tile
+// map, the gather table and each tile's used slots.  Run by the traversal,
+// and again by the autotuner for another tile width on the same lists.
+void gemm_tiles(fmm_ctx c, int tc) {
+    hipStream_t s = c->stream;
+    const int J = c->gp.J;
+    const int32_t nc = c->ncell;
+    int tiles = 0;
+    for (int k = 0; k < 9; k++) {
+        c->gp.class_tile0[k] = tiles;
+        if (k < 8) tiles += (c->gp.class_row0[k + 1] - c->gp.class_row0[k] + tc - 1) / tc;
+    }
+    c->gp.ntiles = tiles;
+    c->gp.nt = tc;
+    c->ntiles = tiles;
+    int32_t* ro = need<int32_t>(c, c->rowof, nc);
+    fill_i32(ro, -1, nc, s);
+    rows_inverse((const uint32_t*)c->rval.p, c->nrows, c->gp, tc, ro, s);
+    const int64_t ngather = (int64_t)tiles * tc * J;
+    int32_t* ga = need<int32_t>(c, c->gather, (size_t)std::max<int64_t>(ngather, 1));
+    fill_i32(ga, -1, ngather, s);
+    m2l_fill_gather((const int2*)c->raw[0].p, (const int16_t*)c->m2lslot.p, c->nlist[0], ro, J, tc, ga, s);
+    check_launch("m2l gather");
+    int32_t* act = need<int32_t>(c, c->tact, (size_t)std::max(tiles, 1) * J);
+    int32_t* nact = need<int32_t>(c, c->tnact, (size_t)std::max(tiles, 1));
+    c->gp.act = act;
+    c->gp.nact = nact;
+    tile_slots(ga, c->gp, tc, tiles, act, nact, s);
+    check_launch("m2l tile slots");
+}
+
 void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
     if (!c->built) fail(FMM_ERR_STATE, "fmm_traverse before fmm_build_tree");
     if (p < 0 || p > FMM_P_MAX) fail(FMM_ERR_INVALID_ARG, "p out of range");
@@ -896,34 +929,14 @@ void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
         check_launch("m2l classes");
         int32_t* h9 = (int32_t*)host_stage(c);
         to_host<int32_t>(c, h9, d9, 9);
-        int tiles = 0;
-        const int tc = gemm_tile_cols_kp(c_kp(c));
-        for (int k = 0; k < 9; k++) {
-            c->gp.class_row0[k] = h9[k];
-            c->gp.class_tile0[k] = tiles;
-            if (k < 8) tiles += (h9[k + 1] - h9[k] + tc - 1) / tc;
-        }
+        for (int k = 0; k < 9; k++) c->gp.class_row0[k] = h9[k];
         c->gp.J = J;
         c->gp.G = gemm_slot_groups(J);
         if (J / c->gp.G + 1 > kGemmMaxGroupSlots) fail(FMM_ERR_UNSUPPORTED, "M2L slot groups exceed the staged size");
-        c->gp.ntiles = tiles;
         c->gp.nrows = h9[8];
-        c->ntiles = tiles;
         c->nrows = h9[8];
-        int32_t* ro = need<int32_t>(c, c->rowof, nc);
-        fill_i32(ro, -1, nc, s);
-        rows_inverse(rv, c->nrows, c->gp, tc, ro, s);
-        const int64_t ngather = (int64_t)tiles * tc * J;
-        int32_t* ga = need<int32_t>(c, c->gather, (size_t)std::max<int64_t>(ngather, 1));
-        fill_i32(ga, -1, ngather, s);
-        m2l_fill_gather(pr0, slot16, nm, ro, J, tc, ga, s);
-        check_launch("m2l gather");
-        int32_t* act = need<int32_t>(c, c->tact, (size_t)std::max(tiles, 1) * J);
-        int32_t* nact = need<int32_t>(c, c->tnact, (size_t)std::max(tiles, 1));
-        c->gp.act = act;
-        c->gp.nact = nact;
-        tile_slots(ga, c->gp, tc, tiles, act, nact, s);
-        check_launch("m2l tile slots");
+        const int kp = c_kp(c);
+        gemm_tiles(c, gemm_tile_width_ok(kp, c->gemm_nt) ? c->gemm_nt : gemm_tile_cols_kp(kp));
     } else if (nm > 0) {
         fill_i32((int32_t*)slot16, -1, (nm + 1) / 2, s);  // two -1 slots per word
     }
@@ -1816,7 +1829,8 @@ fmm_status fmm_costmodel_save(fmm_ctx c, const char* path) {
         else std::fprintf(f, "costs none\n");
         std::fprintf(f, "p2p_tpl");
         for (int k = 0; k < kLeafClasses; k++) std::fprintf(f, " %d", c->p2p_tpl[k]);
-        std::fprintf(f, "\nschedule %d\nm2l_kernel %d\nweights %d\n", c->schedule, c->m2l_kind, kMlpParams);
+        std::fprintf(f, "\nschedule %d\nm2l_kernel %d\nm2l_tile %d\nweights %d\n", c->schedule, c->m2l_kind, c->gemm_nt,
+                     kMlpParams);
         for (int i = 0; i < kMlpParams; i++) std::fprintf(f, "%a%c", (double)w[i], (i % 8 == 7) ? '\n' : ' ');
         std::fprintf(f, "\nend\n");
         bool ok = std::ferror(f) == 0;
@@ -1865,11 +1879,15 @@ fmm_status fmm_costmodel_load(fmm_ctx c, const char* path, int32_t p, int32_t pr
             if (std::fscanf(f, "%d", &tpl[k]) != 1 || (tpl[k] != 0 && tpl[k] != 1 && tpl[k] != 2 && tpl[k] != 4)) bad("bad tile shapes");
         if (std::fscanf(f, " schedule %d", &sched) != 1 || sched < 0 || sched > 2) bad("bad schedule");
         // the M2L kind line is optional (files written before it existed lack it)
-        int mkind = -1;
+        int mkind = -1, mtile = -1;
         if (std::fscanf(f, " %63s", word) != 1) bad("truncated file");
         if (std::strcmp(word, "m2l_kernel") == 0) {
             if (std::fscanf(f, "%d", &mkind) != 1 || mkind < FMM_M2L_CLASS_DENSE || mkind > FMM_M2L_PAIR_ROTATION)
                 bad("bad M2L kernel");
+            if (std::fscanf(f, " %63s", word) != 1) bad("truncated file");
+        }
+        if (std::strcmp(word, "m2l_tile") == 0) {
+            if (std::fscanf(f, "%d", &mtile) != 1 || (mtile != 0 && mtile != 64 && mtile != 128)) bad("bad M2L tile");
             if (std::fscanf(f, " %63s", word) != 1) bad("truncated file");
         }
         if (std::strcmp(word, "weights") != 0 || std::fscanf(f, "%d", &nw) != 1) bad("missing weights");
@@ -1903,6 +1921,7 @@ fmm_status fmm_costmodel_load(fmm_ctx c, const char* path, int32_t p, int32_t pr
         for (int k = 0; k < kLeafClasses; k++) c->p2p_tpl[k] = tpl[k];
         c->schedule = sched;
         if (mkind >= 0) c->m2l_kind = mkind;
+        if (mtile >= 0) c->gemm_nt = mtile;
     });
 }
 
@@ -2192,6 +2211,23 @@ fmm_status fmm_autotune(fmm_ctx c, int32_t precision, int32_t reps) {
             c->m2l_kind = pick;
             build_classes(c, c->p);
         }
+        // targets per tile of the same-level M2L GEMM, where the storage
+        // width has more than one tiling: the tables are rebuilt on the same
+        // lists for each
+        if (c->gemm_on && c->gp.ntiles > 0 && gemm_tile_width_ok(c_kp(c), 64) && gemm_tile_width_ok(c_kp(c), 128)) {
+            double bestw = INFINITY;
+            int pick = c->gp.nt;
+            for (int nt : {64, 128}) {
+                if (nt != c->gp.nt) gemm_tiles(c, nt);
+                double t = timed([&] { evaluate_impl(c, precision, FMM_F32, o, o + c->n, o + 2 * c->n, o + 3 * c->n); });
+                if (t < bestw) {
+                    bestw = t;
+                    pick = nt;
+                }
+            }
+            if (pick != c->gp.nt) gemm_tiles(c, pick);
+            c->gemm_nt = pick;
+        }
         // schedule: P2P concurrent with the far field, or everything in order
         double best = INFINITY;
         int pick = 0;
@@ -2205,6 +2241,20 @@ fmm_status fmm_autotune(fmm_ctx c, int32_t precision, int32_t reps) {
         }
         c->timing = timing;
         c->schedule = pick;
+    });
+}
+
+fmm_status fmm_set_m2l_tile(fmm_ctx c, int32_t cols) {
+    return guarded(c, [&] {
+        if (cols != 0 && cols != 64 && cols != 128) fail(FMM_ERR_INVALID_ARG, "M2L tile width must be 0, 64 or 128");
+        c->gemm_nt = cols;
+    });
+}
+
+fmm_status fmm_get_m2l_tile(fmm_ctx c, int32_t* cols) {
+    return guarded(c, [&] {
+        if (!cols) fail(FMM_ERR_INVALID_ARG, "null pointer");
+        *cols = c->gemm_on && c->gp.ntiles > 0 ? c->gp.nt : c->gemm_nt;
     });
 }
 

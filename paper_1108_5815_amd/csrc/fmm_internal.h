@@ -303,7 +303,11 @@ struct GemmPlan {
     int32_t ntiles;          // tiles
     int32_t nrows;           // rows (targets) over all classes
     int32_t zcell;           // a cell index whose multipole row is all zero (absent sources read it)
+    int32_t nt;              // targets per tile (gemm_tile_cols_kp, or another width gemm_tile_width_ok accepts)
 };
+// whether the GEMM kernels at storage width KP have a tiling of nt targets
+// per tile (64 or 128 at width 128; the default width elsewhere)
+bool gemm_tile_width_ok(int KP, int nt);
 // slot groups for J slots per class: each group's operators (J/G <= 64
 // blocks of 64 KB at storage width 128; 36 at theta = 0.4) should stay
 // inside one XCD's 4 MB L2, and fewer groups mean fewer partial rows to sum

@@ -277,6 +277,11 @@ int gemm_tile_cols_kp(int KP) {
     }
 }
 
+bool gemm_tile_width_ok(int KP, int nt) {
+    if (KP == 128) return nt == 64 || nt == 128;
+    return nt > 0 && nt == gemm_tile_cols_kp(KP);
+}
+
 int gemm_slot_groups(int J) { return 8 * std::max(1, (J + 511) / 512); }
 
 void m2l_reduce_groups(const float* part, GemmPlan plan, const uint32_t* rowcell, int KP, int K, float* L,
@@ -295,7 +300,10 @@ void m2l_gemm(const float* T, const int32_t* offid, const int32_t* gather, const
         case 32: launch<32, 128, 1, 4, 16>(T, offid, gather, plan, M, part, s); break;
         case 64: launch<64, 128, 2, 2, 16>(T, offid, gather, plan, M, part, s); break;
         case 96: launch<96, 128, 3, 4, 8>(T, offid, gather, plan, M, part, s); break;
-        case 128: launch<128, 64, 4, 1, 8>(T, offid, gather, plan, M, part, s); break;
+        case 128:
+            if (plan.nt == 128) launch<128, 128, 4, 1, 8>(T, offid, gather, plan, M, part, s);
+            else launch<128, 64, 4, 1, 8>(T, offid, gather, plan, M, part, s);
+            break;
         case 192: launch<192, 64, 2, 2, 8>(T, offid, gather, plan, M, part, s); break;
         case 256: launch<256, 64, 4, 1, 8>(T, offid, gather, plan, M, part, s); break;
         default: return;
