@@ -481,8 +481,9 @@ fmm_status fmm_set_overlap(fmm_ctx ctx, int32_t schedule);
  * four size classes (at most 8, 16, 32 or more particles); for each class it
  * times the P2P kernel's tile shapes (`reps` launches each, events on the
  * context stream) and keeps the fastest: 1, 2 or 4 targets per lane with
- * every operation on the vector ALUs, or 0, one target per lane with the
- * sums over sources on the matrix cores (FP32 rank-1 updates); if the lists
+ * every operation on the vector ALUs, or -1, -2, -4: that many targets per
+ * lane with the sums over sources on the matrix cores (FP32 rank-1 updates
+ * on v_mfma_f32_4x4x1f32; the vector ALUs form only 1/r and 1/r^3); if the lists
  * hold M2L pairs outside the same-level GEMM (spherical family) it times
  * fmm_evaluate under the four kinds of fmm_set_m2l_kernel and keeps the
  * fastest; where the M2L GEMM has two tile widths it times both
@@ -510,9 +511,10 @@ fmm_status fmm_get_m2l_tile(fmm_ctx ctx, int32_t *cols);
 
 /* The tile shapes in use (p2p_tpl[4], host) and the schedule (*overlap, as
  * fmm_set_overlap);
- * either pointer may be NULL.  fmm_set_tile_config sets the shapes (each 0
- * for the matrix-core form, or 1, 2 or 4 targets per lane); any other value
- * is FMM_ERR_INVALID_ARG and leaves the shapes unchanged. */
+ * either pointer may be NULL.  fmm_set_tile_config sets the shapes (each 1,
+ * 2 or 4 targets per lane on the vector ALUs, or -1, -2, -4 for the
+ * matrix-core form); any other value is FMM_ERR_INVALID_ARG and leaves the
+ * shapes unchanged. */
 fmm_status fmm_get_tile_config(fmm_ctx ctx, int32_t *p2p_tpl, int32_t *overlap);
 fmm_status fmm_set_tile_config(fmm_ctx ctx, const int32_t *p2p_tpl);
 

@@ -969,6 +969,10 @@ void traverse_impl(fmm_ctx c, int32_t p, double theta, int32_t policy) {
 // points can round to one FP32 point), and distinct target and source sets
 // (a target may coincide with a source, in any pair of leaves).  Otherwise
 // only a leaf with itself can hold coincident points.
+// P2P tile shapes: t targets per lane on the vector ALUs (t = 1, 2, 4), or
+// -t for the matrix-core form
+bool p2p_shape_ok(int t) { return t == 1 || t == 2 || t == 4 || t == -1 || t == -2 || t == -4; }
+
 int p2p_guard_all(fmm_ctx c) { return (c->dtype == FMM_F64 || c->n_targets >= 0) ? 1 : 0; }
 
 // P2P over the leaves of each size class with that class's tile shape
@@ -1595,8 +1599,12 @@ static void gen_records(fmm_ctx c, int p, double theta, int precision, uint64_t 
         Tgen[si] = meas(lg(tf[PH_M2LG], t->ngeneral), 0);
         // off the diagonal: targets with `per` per leaf, sources with 4x fewer
         // or more on the same lattice; a leaf size ncrit in [max, 8 min) stops
-        // both trees at that lattice
-        for (int sj : {si - 2, si + 2}) {
+        // both trees at that lattice.  Two trees pay costs one tree does not
+        // (every particle pair guarded against r = 0), so the same two-tree
+        // run at n_s = n_t anchors them: a record is the one-tree diagonal
+        // cost times the measured two-tree ratio.
+        double ts_diag[2] = {NAN, NAN};  // two-tree log2 costs at n_s = n_t: P2P, M2P
+        for (int sj : {si, si - 2, si + 2}) {
             if (sj < 0 || sj >= NS) continue;
             const int ps = pers[sj];
             const int Lo = level_for(per, ps, (int64_t)1 << 21);
@@ -1610,13 +1618,23 @@ static void gen_records(fmm_ctx c, int p, double theta, int precision, uint64_t 
             build_tree_ts_impl(t, FMM_F32, nt, tp, tp + nt, tp + 2 * nt, ns, sp, sp + ns, sp + 2 * ns, sp + 3 * ns,
                                std::max(per, ps));
             timed(FMM_POLICY_FMM, tf);
-            Op2p[si * NS + sj] = meas(lg(tf[PH_P2P], t->nlist[2]), 2);
+            Meas mp2p = meas(lg(tf[PH_P2P], t->nlist[2]), 2);
             timed(FMM_POLICY_TREECODE, tt);
-            Om2p[si * NS + sj] = meas(lg(tt[PH_FAR] - tf[PH_FAR], t->nlist[1]), 1);
+            Meas mm2p = meas(lg(tt[PH_FAR] - tf[PH_FAR], t->nlist[1]), 1);
+            if (sj == si) {
+                ts_diag[0] = mp2p.v;
+                ts_diag[1] = mm2p.v;
+                continue;
+            }
+            mp2p.v += Tp2p[si].v - ts_diag[0];
+            mm2p.v += Tm2p[si].v - ts_diag[1];
+            Op2p[si * NS + sj] = mp2p;
+            Om2p[si * NS + sj] = mm2p;
         }
     }
     // Records.  Measured: the diagonal (n_t = n_s, equal levels; mixed levels
-    // for M2L) and P2P and M2P at n_s = n_t / 4 and 4 n_t, each at the
+    // for M2L) and P2P and M2P at n_s = n_t / 4 and 4 n_t (anchored as
+    // above; NaN wherever a measurement is missing), each at the
     // distance-ratio bins its pairs occupy (bins holding at least 5% of the
     // batch).  The rest of the grid follows from how the kernels' work
     // scales, stated here as the model's invariances: no kernel's cost depends
@@ -1876,7 +1894,7 @@ fmm_status fmm_costmodel_load(fmm_ctx c, const char* path, int32_t p, int32_t pr
         int tpl[kLeafClasses];
         if (std::fscanf(f, " p2p_tpl") != 0) bad("missing tile shapes");
         for (int k = 0; k < kLeafClasses; k++)
-            if (std::fscanf(f, "%d", &tpl[k]) != 1 || (tpl[k] != 0 && tpl[k] != 1 && tpl[k] != 2 && tpl[k] != 4)) bad("bad tile shapes");
+            if (std::fscanf(f, "%d", &tpl[k]) != 1 || !p2p_shape_ok(tpl[k])) bad("bad tile shapes");
         if (std::fscanf(f, " schedule %d", &sched) != 1 || sched < 0 || sched > 2) bad("bad schedule");
         // the M2L kind line is optional (files written before it existed lack it)
         int mkind = -1, mtile = -1;
@@ -2179,7 +2197,7 @@ fmm_status fmm_autotune(fmm_ctx c, int32_t precision, int32_t reps) {
             const int32_t b = c->leaf_cls[k], e = c->leaf_cls[k + 1];
             if (e <= b) continue;
             double best = INFINITY;
-            for (int tpl : {0, 1, 2, 4}) {
+            for (int tpl : {1, 2, 4, -1, -2, -4}) {
                 double t = timed([&] {
                     p2p((float4*)c->pts.p, cells_of(c), (int32_t*)c->leaves_cls.p + b, e - b, (int32_t*)c->off[2].p,
                         (uint32_t*)c->src[2].p, p2p_guard_all(c), tpl, nr, s);
@@ -2270,8 +2288,8 @@ fmm_status fmm_set_tile_config(fmm_ctx c, const int32_t* p2p_tpl) {
     return guarded(c, [&] {
         if (!p2p_tpl) fail(FMM_ERR_INVALID_ARG, "null pointer");
         for (int k = 0; k < kLeafClasses; k++)
-            if (p2p_tpl[k] != 0 && p2p_tpl[k] != 1 && p2p_tpl[k] != 2 && p2p_tpl[k] != 4)
-                fail(FMM_ERR_INVALID_ARG, "P2P tile shape must be 0 (matrix cores) or 1, 2, 4 targets per lane");
+            if (!p2p_shape_ok(p2p_tpl[k]))
+                fail(FMM_ERR_INVALID_ARG, "P2P tile shape must be 1, 2 or 4 (vector ALUs) or -1, -2, -4 (matrix cores)");
         for (int k = 0; k < kLeafClasses; k++) c->p2p_tpl[k] = p2p_tpl[k];
     });
 }

@@ -17,14 +17,14 @@
 // per-target sums; the groups are summed in group order at the end, so
 // results do not depend on timing.
 //
-// Two tile shapes, chosen per leaf-size class by the library's autotuner
+// Two forms of tile, chosen per leaf-size class by the library's autotuner
 // (leaves are launched grouped by class):
-//  - vector (TPL = 1, 2 or 4 targets per lane): every operation on the VALU,
-//    one source read feeding TPL interactions;
-//  - matrix core (TPL = 0): one target per lane; the VALU forms only the
-//    pair's 1/r and 1/r^3, and the sums over sources run as rank-1 updates on
-//    v_mfma_f32_4x4x1f32 (16 blocks of 4 targets x 4 columns per
-//    instruction): phi from A = 1/r against B = q, and the field from
+//  - vector (shape TPL = 1, 2 or 4 targets per lane): every operation on the
+//    VALU, one source read feeding TPL interactions;
+//  - matrix core (shape -TPL, TPL = 1, 2 or 4 targets per lane): the VALU
+//    forms only each pair's 1/r and 1/r^3, and the sums over sources run as
+//    rank-1 updates on v_mfma_f32_4x4x1f32 (16 blocks of 4 targets x 4
+//    columns per instruction): phi from A = 1/r against B = q, and the field from
 //    A = 1/r^3 against B = (q, q x~, q y~, q z~), the source's charge and
 //    charge-weighted position relative to an origin in the target leaf,
 //    giving E = x~_i sum(q/r^3) - sum(q x~/r^3).  The relative origin keeps
@@ -238,54 +238,82 @@ __device__ inline float pair_inv(const float3 P, const float4 Q) {
     return GUARD ? (r2 > 0.f ? inv : 0.f) : inv;
 }
 
-// Sources [j0, j0 + m) of a staged chunk against the lane's target on the
-// matrix cores.  Lane l is row l%4 of block l/4 for A and column l%4 for B;
-// all lanes of a block walk the same sources.  Returns the FP32 partials
-// (D registers: row r of the lane's block, column l%4).
-template <bool GUARD>
-__device__ inline void chunk_mfma(const float4* buf, const float* bq, int j0, int m, int comp, const float3 P,
-                                  v4f& sp, v4f& se) {
-    v4f p0 = {0.f, 0.f, 0.f, 0.f}, p1 = p0, e0 = p0, e1 = p0;
+// Sources [j0, j0 + m) of a staged chunk against the lane's TPL targets on
+// the matrix cores.  Lane l is row l%4 of block l/4 for A and column l%4 for
+// B; all lanes of a block walk the same sources.  Returns the FP32 partials
+// per target set k (D registers: row r of the lane's block, column l%4).
+// With one or two target sets, two accumulator sets alternate by source so
+// that consecutive products do not wait for each other.
+template <int TPL, bool GUARD>
+__device__ inline void chunk_mfma(const float4* buf, const float* bq, int j0, int m, int comp, const float3 (&P)[TPL],
+                                  v4f (&sp)[TPL], v4f (&se)[TPL]) {
+    constexpr int NSET = TPL >= 4 ? 1 : 2;
+    v4f pa[NSET][TPL], ea[NSET][TPL];
+#pragma unroll
+    for (int u = 0; u < NSET; u++)
+#pragma unroll
+        for (int k = 0; k < TPL; k++) {
+            pa[u][k] = v4f{0.f, 0.f, 0.f, 0.f};
+            ea[u][k] = v4f{0.f, 0.f, 0.f, 0.f};
+        }
     int jj = 0;
-    for (; jj + 3 < m; jj += 4) {
+    for (; jj + 1 < m; jj += 2) {
         const int j = j0 + jj;
-        const float4 Q0 = buf[j], Q1 = buf[j + 1], Q2 = buf[j + 2], Q3 = buf[j + 3];
-        const float b0 = bq[4 * j + comp], b1 = bq[4 * j + 4 + comp], b2 = bq[4 * j + 8 + comp],
-                    b3 = bq[4 * j + 12 + comp];
-        const float i0 = pair_inv<GUARD>(P, Q0), i1 = pair_inv<GUARD>(P, Q1);
-        const float i2 = pair_inv<GUARD>(P, Q2), i3 = pair_inv<GUARD>(P, Q3);
-        p0 = __builtin_amdgcn_mfma_f32_4x4x1f32(i0, b0, p0, 0, 0, 0);
-        e0 = __builtin_amdgcn_mfma_f32_4x4x1f32(i0 * i0 * i0, b0, e0, 0, 0, 0);
-        p1 = __builtin_amdgcn_mfma_f32_4x4x1f32(i1, b1, p1, 0, 0, 0);
-        e1 = __builtin_amdgcn_mfma_f32_4x4x1f32(i1 * i1 * i1, b1, e1, 0, 0, 0);
-        p0 = __builtin_amdgcn_mfma_f32_4x4x1f32(i2, b2, p0, 0, 0, 0);
-        e0 = __builtin_amdgcn_mfma_f32_4x4x1f32(i2 * i2 * i2, b2, e0, 0, 0, 0);
-        p1 = __builtin_amdgcn_mfma_f32_4x4x1f32(i3, b3, p1, 0, 0, 0);
-        e1 = __builtin_amdgcn_mfma_f32_4x4x1f32(i3 * i3 * i3, b3, e1, 0, 0, 0);
+        const float4 Q0 = buf[j], Q1 = buf[j + 1];
+        const float b0 = bq[4 * j + comp], b1 = bq[4 * j + 4 + comp];
+#pragma unroll
+        for (int k = 0; k < TPL; k++) {
+            const float i0 = pair_inv<GUARD>(P[k], Q0);
+            pa[0][k] = __builtin_amdgcn_mfma_f32_4x4x1f32(i0, b0, pa[0][k], 0, 0, 0);
+            ea[0][k] = __builtin_amdgcn_mfma_f32_4x4x1f32(i0 * i0 * i0, b0, ea[0][k], 0, 0, 0);
+        }
+#pragma unroll
+        for (int k = 0; k < TPL; k++) {
+            const float i1 = pair_inv<GUARD>(P[k], Q1);
+            pa[NSET - 1][k] = __builtin_amdgcn_mfma_f32_4x4x1f32(i1, b1, pa[NSET - 1][k], 0, 0, 0);
+            ea[NSET - 1][k] = __builtin_amdgcn_mfma_f32_4x4x1f32(i1 * i1 * i1, b1, ea[NSET - 1][k], 0, 0, 0);
+        }
     }
-    for (; jj < m; jj++) {
+    if (jj < m) {
         const int j = j0 + jj;
-        const float i0 = pair_inv<GUARD>(P, buf[j]);
+        const float4 Q0 = buf[j];
         const float b0 = bq[4 * j + comp];
-        p0 = __builtin_amdgcn_mfma_f32_4x4x1f32(i0, b0, p0, 0, 0, 0);
-        e0 = __builtin_amdgcn_mfma_f32_4x4x1f32(i0 * i0 * i0, b0, e0, 0, 0, 0);
+#pragma unroll
+        for (int k = 0; k < TPL; k++) {
+            const float i0 = pair_inv<GUARD>(P[k], Q0);
+            pa[0][k] = __builtin_amdgcn_mfma_f32_4x4x1f32(i0, b0, pa[0][k], 0, 0, 0);
+            ea[0][k] = __builtin_amdgcn_mfma_f32_4x4x1f32(i0 * i0 * i0, b0, ea[0][k], 0, 0, 0);
+        }
     }
-    sp = p0 + p1;
-    se = e0 + e1;
+#pragma unroll
+    for (int k = 0; k < TPL; k++) {
+        sp[k] = pa[0][k];
+        se[k] = ea[0][k];
+        if (NSET > 1) {
+            sp[k] += pa[NSET - 1][k];
+            se[k] += ea[NSET - 1][k];
+        }
+    }
 }
 
-template <bool GUARD_ALL>
+// Matrix-core form with TPL targets per lane.  A pass covers up to 64 TPL
+// targets: span4 lanes (a multiple of 4) per group, lane li of a group holds
+// targets li + k span4, and G = 64 / span4 groups split the sources.  The
+// FP64 per-target sums live in LDS (slot g span4 TPL + target, 5 values:
+// phi, sum q/r^3, sum q x~/r^3, ...), each value owned by one lane.
+template <int TPL, bool GUARD_ALL>
 __global__ __launch_bounds__(64) void k_p2p_mfma(const float4* __restrict__ pts, CellArrays c,
                                                  const int32_t* __restrict__ leaves,
                                                  const int32_t* __restrict__ off, const uint32_t* __restrict__ src,
                                                  double4* __restrict__ near) {
     constexpr int CH = 256;        // staged sources per chunk
     constexpr int CHP = CH + 16;   // room for the padding that evens the group shares
+    constexpr int NT = 64 * TPL;   // targets per pass
     __shared__ float4 buf[CHP];    // source (x, y, z, q)
     __shared__ float4 bqv[CHP];    // source (q, q x~, q y~, q z~)
+    __shared__ double red[NT * 5];
     __shared__ int s_pref[65];
     __shared__ int s_beg[64];
-    static_assert(CHP * sizeof(float4) >= 64 * 5 * sizeof(double), "reduction does not fit the chunk");
     const float* bq = reinterpret_cast<const float*>(bqv);
     const int cell = leaves[blockIdx.x];
     const int32_t b = c.begin[cell], e = c.end[cell];
@@ -299,20 +327,27 @@ __global__ __launch_bounds__(64) void k_p2p_mfma(const float4* __restrict__ pts,
         bqv[k] = make_float4(v.w, v.w * (v.x - O.x), v.w * (v.y - O.y), v.w * (v.z - O.z));
     };
 
-    for (int32_t t0 = b; t0 < e; t0 += 64) {
-        const int ntc = min(e - t0, 64);
-        const int nbk = (ntc + 3) >> 2;  // blocks of 4 targets per group
-        const int G = 16 / nbk;          // groups of nbk blocks
+    for (int32_t t0 = b; t0 < e; t0 += NT) {
+        const int ntc = min(e - t0, NT);
+        const int nbk = ((ntc + TPL - 1) / TPL + 3) >> 2;  // blocks of 4 lanes per group
+        const int span4 = 4 * nbk;
+        const int G = 16 / nbk;                            // groups of nbk blocks
         const int g = blk / nbk;
         const bool active = g < G;
-        const int gg = active ? g : 0;   // idle blocks repeat group 0's work, results unused
-        const int ti = (blk - g * nbk) * 4 + row;
-        const float4 v = pts[t0 + ((active && ti < ntc) ? ti : 0)];
-        const float3 P = make_float3(v.x, v.y, v.z);
-        double ap[4] = {0.0, 0.0, 0.0, 0.0}, ae[4] = {0.0, 0.0, 0.0, 0.0};
+        const int gg = active ? g : 0;  // idle blocks repeat group 0's work, results unused
+        const int bb = blk - g * nbk;   // block within the group
+        float3 P[TPL];
+#pragma unroll
+        for (int k = 0; k < TPL; k++) {
+            const int t = bb * 4 + row + k * span4;
+            const float4 v = pts[t0 + ((active && t < ntc) ? t : 0)];
+            P[k] = make_float3(v.x, v.y, v.z);
+        }
+        for (int i = lane; i < G * span4 * TPL * 5; i += 64) red[i] = 0.0;
 
         // the group shares of a staged chunk of n sources: m each, padded with
-        // zero-charge points at infinity (their 1/r is 0)
+        // zero-charge points at infinity (their 1/r is 0); the FP32 partials
+        // are added into the FP64 sums in LDS
         auto flush = [&](int n, auto guard) {
             constexpr bool GD = decltype(guard)::value;
             const int m = (n + G - 1) / G;
@@ -321,12 +356,17 @@ __global__ __launch_bounds__(64) void k_p2p_mfma(const float4* __restrict__ pts,
                 bqv[k] = make_float4(0.f, 0.f, 0.f, 0.f);
             }
             __syncthreads();
-            v4f sp, se;
-            chunk_mfma<GD>(buf, bq, gg * m, m, row, P, sp, se);
+            v4f sp[TPL], se[TPL];
+            chunk_mfma<TPL, GD>(buf, bq, gg * m, m, row, P, sp, se);
+            if (active) {
 #pragma unroll
-            for (int r = 0; r < 4; r++) {
-                ap[r] += sp[r];
-                ae[r] += se[r];
+                for (int k = 0; k < TPL; k++)
+#pragma unroll
+                    for (int r = 0; r < 4; r++) {
+                        double* slot = red + (g * span4 * TPL + bb * 4 + r + k * span4) * 5;
+                        slot[1 + row] += (double)se[k][r];
+                        if (row == 0) slot[0] += (double)sp[k][r];
+                    }
             }
             __syncthreads();
         };
@@ -385,27 +425,17 @@ __global__ __launch_bounds__(64) void k_p2p_mfma(const float4* __restrict__ pts,
         }
         if (fill > 0) flush(fill, std::integral_constant<bool, GUARD_ALL>{});
 
-        // (3) sum the groups in group order, through the chunk's LDS: slot
-        // 4 blk + r holds target (blk - g nbk) 4 + r of group g
-        double* red = reinterpret_cast<double*>(buf);
-        if (active) {
+        // (3) sum the groups in group order
+        for (int t = lane; t < ntc; t += 64) {
+            double sum[5];
 #pragma unroll
-            for (int r = 0; r < 4; r++) {
-                red[(4 * blk + r) * 5 + 1 + row] = ae[r];
-                if (row == 0) red[(4 * blk + r) * 5] = ap[r];
-            }
-        }
-        __syncthreads();
-        if (lane < ntc) {
-            double s[5];
-#pragma unroll
-            for (int k = 0; k < 5; k++) s[k] = red[lane * 5 + k];
+            for (int k = 0; k < 5; k++) sum[k] = red[t * 5 + k];
             for (int h = 1; h < G; h++)
 #pragma unroll
-                for (int k = 0; k < 5; k++) s[k] += red[(h * nbk * 4 + lane) * 5 + k];
-            const float4 T = pts[t0 + lane];
+                for (int k = 0; k < 5; k++) sum[k] += red[(h * span4 * TPL + t) * 5 + k];
+            const float4 T = pts[t0 + t];
             const double xt = (double)(T.x - O.x), yt = (double)(T.y - O.y), zt = (double)(T.z - O.z);
-            near[t0 + lane] = make_double4(s[0], xt * s[1] - s[2], yt * s[1] - s[3], zt * s[1] - s[4]);
+            near[t0 + t] = make_double4(sum[0], xt * sum[1] - sum[2], yt * sum[1] - sum[3], zt * sum[1] - sum[4]);
         }
         __syncthreads();
     }
@@ -422,12 +452,13 @@ __global__ void k_leaf_class(CellArrays c, const int32_t* __restrict__ leaves, i
     val[i] = (uint32_t)cell;
 }
 
+template <int TPL>
 void launch_mfma(const float4* pts, CellArrays cells, const int32_t* leaves, int32_t nleaves, const int32_t* off,
                  const uint32_t* src, int guard_all, double4* near, hipStream_t s) {
     if (guard_all)
-        k_p2p_mfma<true><<<nleaves, 64, 0, s>>>(pts, cells, leaves, off, src, near);
+        k_p2p_mfma<TPL, true><<<nleaves, 64, 0, s>>>(pts, cells, leaves, off, src, near);
     else
-        k_p2p_mfma<false><<<nleaves, 64, 0, s>>>(pts, cells, leaves, off, src, near);
+        k_p2p_mfma<TPL, false><<<nleaves, 64, 0, s>>>(pts, cells, leaves, off, src, near);
 }
 
 template <int TPL>
@@ -451,7 +482,9 @@ void p2p(const float4* pts, CellArrays cells, const int32_t* leaves, int32_t nle
          const uint32_t* p2p_src, int guard_all, int tpl, double4* near, hipStream_t s) {
     if (nleaves <= 0) return;
     switch (tpl) {
-        case 0: launch_mfma(pts, cells, leaves, nleaves, p2p_off, p2p_src, guard_all, near, s); break;
+        case -1: launch_mfma<1>(pts, cells, leaves, nleaves, p2p_off, p2p_src, guard_all, near, s); break;
+        case -2: launch_mfma<2>(pts, cells, leaves, nleaves, p2p_off, p2p_src, guard_all, near, s); break;
+        case -4: launch_mfma<4>(pts, cells, leaves, nleaves, p2p_off, p2p_src, guard_all, near, s); break;
         case 1: launch<1>(pts, cells, leaves, nleaves, p2p_off, p2p_src, guard_all, near, s); break;
         case 2: launch<2>(pts, cells, leaves, nleaves, p2p_off, p2p_src, guard_all, near, s); break;
         default: launch<4>(pts, cells, leaves, nleaves, p2p_off, p2p_src, guard_all, near, s); break;

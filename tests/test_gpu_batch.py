@@ -204,14 +204,14 @@ def test_autotune_choices_and_accuracy():
     f.build_tree_batch(off, dev(x), dev(y), dev(z), dev(q), 64)
     f.traverse(8, 0.5, 0)
     cfg = f.autotune(0, reps=2)
-    assert all(t in (0, 1, 2, 4) for t in cfg["p2p_targets_per_lane"])
+    assert all(t in (1, 2, 4, -1, -2, -4) for t in cfg["p2p_targets_per_lane"])
     phi, E = f.evaluate(out_dtype=torch.float64)
     phi, E = phi.cpu().numpy(), E.cpu().numpy().T
     for k in (1, 4):
         b, e = int(off[k]), int(off[k + 1])
         po, Eo, _ = ora.fmm(x[b:e], y[b:e], z[b:e], q[b:e], 8, 0.5, 64)
         assert ora.rel_l2(phi[b:e], po) < 1e-5 and ora.rel_l2(E[b:e], Eo) < 1e-4
-    for tpl in ([0, 0, 0, 0], [1, 1, 1, 1], [2, 2, 2, 2], [4, 4, 4, 4]):
+    for tpl in ([-1] * 4, [-4] * 4, [1, 1, 1, 1], [2, 2, 2, 2], [4, 4, 4, 4]):
         f.set_tile_config(tpl)
         p2, _ = f.evaluate(out_dtype=torch.float64)
         assert ora.rel_l2(p2.cpu().numpy(), phi) < 1e-6

@@ -96,7 +96,7 @@ def test_costmodel_save_load_roundtrip(tmp_path):
     assert e.value.status == 4
     f.costmodel_fit(*_records(), epochs=200, lr=3e-3, seed=5)
     f.set_costs(0.4, 0.3, 0.001)
-    f.set_tile_config([1, 2, 0, 4])
+    f.set_tile_config([1, 2, -2, 4])
     f.set_overlap(1)
     f.set_m2l_kernel(3)
     f.set_m2l_tile(128)
@@ -106,7 +106,7 @@ def test_costmodel_save_load_roundtrip(tmp_path):
     g.costmodel_load(path)                     # any p, any precision
     assert np.array_equal(g.costmodel_weights(), f.costmodel_weights())
     assert np.array_equal(g.costs(), f.costs())
-    assert g.tile_config() == {"p2p_targets_per_lane": [1, 2, 0, 4], "schedule": 1, "m2l_kernel": 3, "m2l_tile": 128}
+    assert g.tile_config() == {"p2p_targets_per_lane": [1, 2, -2, 4], "schedule": 1, "m2l_kernel": 3, "m2l_tile": 128}
     assert np.array_equal(g.costmodel_table(10, 0.4), f.costmodel_table(10, 0.4))
     text = open(path).read()
     assert text.startswith("fmm-costmodel 1\n") and "\np -1\n" in text

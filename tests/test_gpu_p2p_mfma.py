@@ -1,6 +1,7 @@
-"""The P2P kernel's matrix-core form (tile shape 0: one target per lane, the
-sums over sources as FP32 rank-1 updates on v_mfma_f32_4x4x1f32) against the
-oracle's direct sum and FMM, and against the vector form on the same lists.
+"""The P2P kernel's matrix-core form (tile shapes -1, -2, -4: that many
+targets per lane, the sums over sources as FP32 rank-1 updates on
+v_mfma_f32_4x4x1f32) against the oracle's direct sum and FMM, and against the
+vector form on the same lists.
 
 Cases: every interaction forced to particle-particle sums (the whole
 evaluation is then a direct sum through the P2P lists, ancestors' lists
@@ -55,30 +56,32 @@ def test_all_pairs_direct_plummer():
     tg = np.random.default_rng(63).choice(n, 2000, replace=False)
     po, Eo = ora.direct(x, y, z, q, tg)
     errs = {}
-    for tpl in (0, 4):
+    for tpl in (-1, -2, -4, 4):
         phi, E = _run(f, tpl)
         errs[tpl] = (ora.rel_l2(phi[tg], po), ora.rel_l2(E[tg], Eo))
     print("direct sum through P2P lists, rel L2 (phi, E):", errs)
-    assert errs[0][0] < 2e-6 and errs[0][1] < 2e-5
-    assert errs[4][0] < 2e-6 and errs[4][1] < 2e-5
+    for tpl, (ep, eE) in errs.items():
+        assert ep < 2e-6 and eE < 2e-5, tpl
 
 
+@pytest.mark.parametrize("shape", [-1, -2, -4])
 @pytest.mark.parametrize("ncrit", [1, 3, 13, 27, 64])
-def test_leaf_sizes_against_oracle(ncrit):
+def test_leaf_sizes_against_oracle(ncrit, shape):
     n = 4000 if ncrit > 3 else 1500
     x, y, z = (_f32(a) for a in synth.uniform_cube(n, 70 + ncrit))
     q = _f32(synth.charges_uniform(n, 71 + ncrit))
     f = _tree(x, y, z, q, ncrit)
     f.traverse(6, 0.5, 0)
-    phi0, E0 = _run(f, 0)
+    phi0, E0 = _run(f, shape)
     phi1, E1 = _run(f, 1)
     po, Eo, _ = ora.fmm(x, y, z, q, 6, 0.5, ncrit)
     assert ora.rel_l2(phi0, po) < 1e-5 and ora.rel_l2(E0, Eo) < 1e-4
     assert ora.rel_l2(phi0, phi1) < 2e-6 and ora.rel_l2(E0, E1) < 2e-5
 
 
+@pytest.mark.parametrize("shape", [-1, -4])
 @pytest.mark.parametrize("dt", [torch.float32, torch.float64], ids=["f32", "f64"])
-def test_big_coincident_leaf(dt):
+def test_big_coincident_leaf(dt, shape):
     """300 coincident points stop the tree at the level limit: their leaf
     holds more than a wave of targets; coincident pairs contribute nothing."""
     n = 3000
@@ -89,7 +92,7 @@ def test_big_coincident_leaf(dt):
     f.set_costs(1.0, 1.0, 1e-9)
     f.traverse(4, 0.5, 2)
     assert f.sizes()["m2l"] == 0
-    phi, E = _run(f, 0)
+    phi, E = _run(f, shape)
     po, Eo = ora.direct(x, y, z, q)
     assert ora.rel_l2(phi, po) < 2e-6 and ora.rel_l2(E, Eo) < 2e-5
     phi4, E4 = _run(f, 4)
@@ -104,7 +107,7 @@ def test_targets_differ_from_sources():
     f = FMM(0)
     f.build_tree_ts([_dev(t[:, d]) for d in range(3)], [_dev(s[:, d]) for d in range(3)], _dev(q), 20)
     f.traverse(8, 0.5, 0)
-    phi, E = _run(f, 0)
+    phi, E = _run(f, -2)
     tr = ora.Tree.targets_sources(t, s, 20)
     tr.traverse(0.5, 0)
     po, Eo = tr.evaluate(8, q)
