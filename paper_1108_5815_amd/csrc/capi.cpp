@@ -149,7 +149,7 @@ struct fmm_ctx_s {
     Buf M, L, nearb;
 
     // kernel pre-calculation inputs/outputs
-    Buf tune_pts, tune_out, at_out, rhist, d_lvl, d_trav;
+    Buf tune_pts, tune_out, at_out, d_lvl, d_trav;
 
     // pinned host staging
     void* host = nullptr;
@@ -167,7 +167,7 @@ struct fmm_ctx_s {
                       &d_seg, &d_bt, &d_pb, &d_box, &d_frame, &inst, &bsort, &tact, &tnact,
                       &leaves_cls, &inner, &leafpos, &m2pflag, &m2lslot, &tbounds, &lkey, &lval, &lkey2, &lval2, &at_out, &m2l_part, &Msplit, &nbucket, &kinds, &ckey, &ckey2, &cval, &cval2,
                       &chead, &choff, &cstart, &cpos, &csrcs, &cnt_t, &ctbase, &ctile, &cT, &cskip, &cls_part,
-                      &ts_stage, &tleaves, &d_wrot, &rhist, &d_lvl, &d_trav};
+                      &ts_stage, &tleaves, &d_wrot, &d_lvl, &d_trav};
         for (Buf* b : all) bufs.push_back(b);
     }
 };
@@ -1510,8 +1510,7 @@ static void mlp_features(float* f, int dl, double nt, double ns, int p, double t
 // the treecode policy M2P per cell pair, and a set whose lower half is one
 // level deeper times the mixed-level M2L pairs of its interface.  Target and
 // source sets on one lattice with different leaf sizes (a target tree and a
-// source tree) time P2P and M2P off the diagonal n_t != n_s.  Each measured
-// batch also records which distance-ratio bins its pairs fall in.
+// source tree) time P2P and M2P off the diagonal n_t != n_s.
 static void gen_records(fmm_ctx c, int p, double theta, int precision, uint64_t seed) {
     c->rec_feat.clear();
     c->rec_kind.clear();
@@ -1532,31 +1531,16 @@ static void gen_records(fmm_ctx c, int p, double theta, int precision, uint64_t 
     t->schedule = 0;  // each kernel timed alone
     const int pers[] = {2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096};
     const int NS = (int)(sizeof(pers) / sizeof(pers[0]));
-    // one measurement: log2 ns per cell pair and the fractions of its pairs
-    // in each distance-ratio bin (value NaN = not measured)
+    // one measurement: log2 ns per cell pair (NaN = not measured)
     struct Meas {
         double v = NAN;
-        double bins[kMlpBq] = {};
     };
     // diagonal (n_t = n_s): same-level M2L, mixed-level M2L, M2P, P2P per leaf size
     std::vector<Meas> Tm2l(NS), Tgen(NS), Tm2p(NS), Tp2p(NS);
     // off the diagonal, targets pers[i] and sources pers[j]: M2P, P2P at [i NS + j]
     std::vector<Meas> Om2p(NS * NS), Op2p(NS * NS);
     auto lg = [](double ms, int64_t units) { return units > 0 && ms > 0 ? std::log2(ms * 1e6 / (double)units) : NAN; };
-    unsigned long long* dh = need<unsigned long long>(c, c->rhist, kMlpBq);
-    auto meas = [&](double v, int kind) {
-        Meas m;
-        m.v = v;
-        if (!std::isfinite(v)) return m;
-        ratio_hist((const int2*)t->raw[kind].p, t->nlist[kind], cells_of(t), theta, dh, c->stream);
-        check_launch("ratio bins");
-        unsigned long long hh[kMlpBq];
-        to_host<unsigned long long>(c, hh, dh, kMlpBq);
-        double tot = 0;
-        for (int b = 0; b < kMlpBq; b++) tot += (double)hh[b];
-        for (int b = 0; b < kMlpBq; b++) m.bins[b] = tot > 0 ? (double)hh[b] / tot : 0.0;
-        return m;
-    };
+    auto meas = [](double v, int) { return Meas{v}; };
     auto timed = [&](int policy, double* tm) {
         traverse_impl(t, p, theta, policy);
         float* out = need<float>(c, c->tune_out, (size_t)4 * t->n);
@@ -1634,11 +1618,11 @@ static void gen_records(fmm_ctx c, int p, double theta, int precision, uint64_t 
     }
     // Records.  Measured: the diagonal (n_t = n_s, equal levels; mixed levels
     // for M2L) and P2P and M2P at n_s = n_t / 4 and 4 n_t (anchored as
-    // above; NaN wherever a measurement is missing), each at the
-    // distance-ratio bins its pairs occupy (bins holding at least 5% of the
-    // batch).  The rest of the grid follows from how the kernels' work
-    // scales, stated here as the model's invariances: no kernel's cost depends
-    // on the distance ratio; M2L's does not depend on the particle counts and
+    // above; NaN wherever a measurement is missing).  The rest of the grid
+    // follows from how the kernels' work scales, stated here as the model's
+    // invariances: no kernel's work depends on the distance ratio (a record
+    // stands at every ratio bin, so the network sees each kind at the ratios
+    // where the traversal asks it); M2L's does not depend on the particle counts and
     // M2P's not on n_s; P2P's log cost is additive in log n_t and log n_s, so
     // an unmeasured off-diagonal pair gets the mean of the two diagonal log
     // costs; only M2L depends on the level difference.
@@ -1649,10 +1633,9 @@ static void gen_records(fmm_ctx c, int p, double theta, int precision, uint64_t 
         }
         return Meas{};
     };
-    auto emit = [&](int dl, int i, int j, int kind, const Meas& m, double v) {
+    auto emit = [&](int dl, int i, int j, int kind, const Meas&, double v) {
         if (!std::isfinite(v)) return;
         for (int b = 0; b < kMlpBq; b++) {
-            if (m.bins[b] < 0.05) continue;
             float f[6];
             mlp_features(f, dl, pers[i], pers[j], p, theta);
             f[4] = ((float)b + 0.5f) / (float)kMlpBq;

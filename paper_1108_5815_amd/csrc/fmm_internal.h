@@ -143,10 +143,6 @@ int64_t clustered_points(int L, int per, int per_lo, uint64_t seed, float* x, fl
 // predictions lie within kMlpFallbackMargin log2 units of each other
 constexpr float kMlpFallbackMargin = 0.125f;
 void mlp_table(const float* w, int p, float theta, const double* costs, uint8_t* table, hipStream_t s);
-// counts of cell pairs per distance-ratio bin of the cost model's features
-// (hist[kMlpBq], device, cleared first)
-void ratio_hist(const int2* pairs, int64_t m, CellArrays cells, double theta, unsigned long long* hist,
-                hipStream_t s);
 
 // ------------------------------------------------------------------ traversal
 struct TravParams {

@@ -235,31 +235,6 @@ __global__ void k_mlp_table(const float* __restrict__ w, int p, float theta, dou
 }
 
 
-// Histogram of the distance-ratio bins of cell pairs (the traversal's
-// feature: bin floor(kMlpBq ratio), ratio = ((r_t + r_s) / R) / theta on the
-// half-grid geometry, clamped to the last bin; coincident centres land there)
-__global__ void k_ratio_hist(const int2* __restrict__ pairs, int64_t m, CellArrays c, double theta,
-                             unsigned long long* __restrict__ hist) {
-    __shared__ unsigned int h[kMlpBq];
-    if (threadIdx.x < kMlpBq) h[threadIdx.x] = 0;
-    __syncthreads();
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
-        const int2 pr = pairs[i];
-        const int4 gt = c.geo[pr.x], gs = c.geo[pr.y];
-        const int64_t dx = (int64_t)gt.x - gs.x, dy = (int64_t)gt.y - gs.y, dz = (int64_t)gt.z - gs.z;
-        const int64_t R2 = dx * dx + dy * dy + dz * dz;
-        const int64_t rr = (int64_t)gt.w + gs.w;
-        int bq = kMlpBq - 1;
-        if (R2 > 0) {
-            const int b = (int)(sqrt((double)(rr * rr) / (double)R2) / theta * kMlpBq);
-            bq = b < 0 ? 0 : (b >= kMlpBq ? kMlpBq - 1 : b);
-        }
-        atomicAdd(&h[bq], 1u);
-    }
-    __syncthreads();
-    if (threadIdx.x < kMlpBq && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], (unsigned long long)h[threadIdx.x]);
-}
-
 }  // namespace
 
 void mlp_grad(const float* w, const float* feat, const int32_t* kind, const float* tgt, int B, float* grad_part,
@@ -279,14 +254,6 @@ int64_t clustered_points(int L, int per, int per_lo, uint64_t seed, float* x, fl
     const int64_t ncells = (int64_t)1 << (3 * L);
     if (x) k_clustered<<<(unsigned)ncells, 64, 0, s>>>(L, per, per_lo, seed, x, y, z, q);
     return (ncells / 2) * per_lo + (ncells / 2) * per;
-}
-
-void ratio_hist(const int2* pairs, int64_t m, CellArrays cells, double theta, unsigned long long* hist,
-                hipStream_t s) {
-    fill_zero(hist, kMlpBq * sizeof(unsigned long long), s);
-    if (m <= 0) return;
-    const int64_t nb = std::min<int64_t>((m + 255) / 256, 2048);
-    k_ratio_hist<<<(unsigned)nb, 256, 0, s>>>(pairs, m, cells, theta, hist);
 }
 
 void mlp_table(const float* w, int p, float theta, const double* costs, uint8_t* table, hipStream_t s) {
