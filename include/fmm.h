@@ -444,6 +444,15 @@ fmm_status fmm_get_cells(fmm_ctx ctx, int32_t *level, uint64_t *prefix, int32_t 
  * grouped by target in increasing order; host arrays of the list's size. */
 fmm_status fmm_get_list(fmm_ctx ctx, int32_t kind, int32_t *tgt_host, int32_t *src_host);
 
+/* Consistency checks on host copies of the context's state (a debugging
+ * aid, synchronous, O(n + cells + pairs)): the particle permutation and key
+ * order, every cell's particle range, parent, level and children (which
+ * must partition it), the leaf count, every list pair's cell indices, the
+ * per-target grouping and offsets of the cell-particle and particle-particle
+ * lists, and the GEMM gather table.  FMM_OK, or FMM_ERR_STATE with the first
+ * violation in fmm_last_error (also without a tree). */
+fmm_status fmm_validate(fmm_ctx ctx);
+
 /* Scaled expansions after fmm_evaluate: per cell (p+1)^2 reals, degree n at
  * offset n*n as [Re c_n^0, Re c_n^1, Im c_n^1, ..., Re c_n^n, Im c_n^n], in
  * the Greengard-Rokhlin normalisation, multipoles divided by r^n and locals

@@ -92,6 +92,7 @@ def lib():
         "fmm_set_m2l_kernel": ([vp, i32], ctypes.c_int),
         "fmm_get_m2l_kernel": ([vp, vp], ctypes.c_int),
         "fmm_set_m2l_tile": ([vp, i32], ctypes.c_int),
+        "fmm_validate": ([vp], ctypes.c_int),
         "fmm_get_m2l_tile": ([vp, vp], ctypes.c_int),
         "fmm_get_expansion": ([vp, vp], ctypes.c_int),
         "fmm_evaluate_noalloc": ([vp, i32, i32, vp, vp, vp, vp], ctypes.c_int),
@@ -310,6 +311,10 @@ class FMM:
         v = ctypes.c_int32()
         self._ck(lib().fmm_get_m2l_tile(self.h, ctypes.byref(v)))
         return int(v.value)
+
+    def validate(self):
+        """Check the tree, lists and GEMM tables on host copies (raises FMMError)."""
+        self._ck(lib().fmm_validate(self.h))
 
     def expansion(self) -> int:
         """Family of the last traversal (EXPANSION_SPHERICAL or EXPANSION_CARTESIAN)."""

@@ -2101,6 +2101,96 @@ fmm_status fmm_get_cells(fmm_ctx c, int32_t* level, uint64_t* prefix, int32_t* b
     });
 }
 
+// Consistency checks of the context's tree, lists and GEMM tables on host
+// copies (a debugging aid: every index the kernels follow is checked against
+// the array it indexes).
+fmm_status fmm_validate(fmm_ctx c) {
+    return guarded(c, [&] {
+        if (!c->built) fail(FMM_ERR_STATE, "no tree");
+        const int64_t n = c->n;
+        const int32_t nc = c->ncell;
+        auto bad = [&](const std::string& what) { fail(FMM_ERR_STATE, ("validate: " + what).c_str()); };
+        // the permutation and, for one instance, the key order
+        if (n > 0) {
+            std::vector<uint32_t> idx(n);
+            std::vector<uint64_t> key(n);
+            to_host<uint32_t>(c, idx.data(), c->idx.p, n);
+            to_host<uint64_t>(c, key.data(), c->keys.p, n);
+            std::vector<uint8_t> seen(n, 0);
+            for (int64_t i = 0; i < n; i++) {
+                if (idx[i] >= (uint64_t)n || seen[idx[i]]) bad("permutation is not a permutation");
+                seen[idx[i]] = 1;
+            }
+            if (c->hseg.size() == 2)
+                for (int64_t i = 1; i < n; i++)
+                    if (key[i] < key[i - 1]) bad("keys out of order at " + std::to_string(i));
+        }
+        std::vector<int32_t> b(nc), e(nc), par(nc), ch(nc), nch(nc), lev(nc);
+        if (nc > 0) {
+            to_host<int32_t>(c, b.data(), c->c_begin.p, nc);
+            to_host<int32_t>(c, e.data(), c->c_end.p, nc);
+            to_host<int32_t>(c, par.data(), c->c_parent.p, nc);
+            to_host<int32_t>(c, ch.data(), c->c_child.p, nc);
+            to_host<int32_t>(c, nch.data(), c->c_nchild.p, nc);
+            to_host<int32_t>(c, lev.data(), c->c_level.p, nc);
+        }
+        int32_t leaves = 0;
+        for (int32_t i = 0; i < nc; i++) {
+            const std::string at = " (cell " + std::to_string(i) + ")";
+            if (!(0 <= b[i] && b[i] < e[i] && e[i] <= n)) bad("empty or out-of-range particle range" + at);
+            if (lev[i] < 0 || lev[i] > kMaxLevel) bad("level out of range" + at);
+            if (i < c->nroot) {
+                if (par[i] != -1 || lev[i] != 0) bad("root with a parent or a level" + at);
+            } else if (par[i] < 0 || par[i] >= i || lev[i] != lev[par[i]] + 1) {
+                bad("parent not an earlier cell one level up" + at);
+            }
+            if (nch[i] < 0 || nch[i] > 8) bad("child count out of range" + at);
+            if (nch[i] == 0) {
+                leaves++;
+                continue;
+            }
+            if (ch[i] <= i || (int64_t)ch[i] + nch[i] > nc) bad("children out of range" + at);
+            int32_t at_p = b[i];
+            for (int32_t k = ch[i]; k < ch[i] + nch[i]; k++) {
+                if (par[k] != i || b[k] != at_p) bad("children do not partition the parent" + at);
+                at_p = e[k];
+            }
+            if (at_p != e[i]) bad("children do not cover the parent" + at);
+        }
+        if (leaves != c->nleaf) bad("leaf count " + std::to_string(leaves) + " != " + std::to_string(c->nleaf));
+        if (!c->traversed) return;
+        for (int k = 0; k < 3; k++) {
+            const int64_t m = c->nlist[k];
+            if (m == 0) continue;
+            std::vector<int2> pr(m);
+            to_host<int2>(c, pr.data(), c->raw[k].p, m);
+            for (int64_t i = 0; i < m; i++)
+                if (pr[i].x < 0 || pr[i].x >= nc || pr[i].y < 0 || pr[i].y >= nc)
+                    bad("list " + std::to_string(k) + " pair " + std::to_string(i) + " out of range");
+            if (k == 0) continue;
+            std::vector<uint32_t> tg(m);
+            std::vector<int32_t> of((size_t)nc + 1);
+            to_host<uint32_t>(c, tg.data(), c->tgt[k].p, m);
+            to_host<int32_t>(c, of.data(), c->off[k].p, (size_t)nc + 1);
+            for (int64_t i = 1; i < m; i++)
+                if (tg[i] < tg[i - 1]) bad("list " + std::to_string(k) + " not grouped by target");
+            if (of[0] != 0 || of[nc] != m) bad("list " + std::to_string(k) + " offsets do not span the list");
+            for (int32_t i = 0; i < nc; i++)
+                if (of[i] > of[i + 1]) bad("list " + std::to_string(k) + " offsets not monotone");
+        }
+        if (c->gemm_on && c->gp.ntiles > 0) {
+            const int64_t ng = (int64_t)c->gp.ntiles * c->gp.nt * c->gp.J;
+            std::vector<int32_t> ga(ng);
+            to_host<int32_t>(c, ga.data(), c->gather.p, ng);
+            for (int64_t i = 0; i < ng; i++)
+                if (ga[i] < -1 || ga[i] >= nc) bad("gather entry out of range");
+            for (int k = 0; k < 8; k++)
+                if (c->gp.class_row0[k] > c->gp.class_row0[k + 1]) bad("GEMM class rows not monotone");
+            if (c->gp.class_row0[8] != c->gp.nrows || c->gp.nrows > nc) bad("GEMM rows out of range");
+        }
+    });
+}
+
 fmm_status fmm_get_list(fmm_ctx c, int32_t kind, int32_t* tgt, int32_t* src) {
     return guarded(c, [&] {
         if (!c->traversed) fail(FMM_ERR_STATE, "no traversal");
