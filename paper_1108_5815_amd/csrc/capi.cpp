@@ -1622,16 +1622,29 @@ static void gen_records(fmm_ctx c, int p, double theta, int precision, uint64_t 
     // follows from how the kernels' work scales, stated here as the model's
     // invariances: no kernel's work depends on the distance ratio (a record
     // stands at every ratio bin, so the network sees each kind at the ratios
-    // where the traversal asks it); M2L's does not depend on the particle counts and
-    // M2P's not on n_s; P2P's log cost is additive in log n_t and log n_s, so
-    // an unmeasured off-diagonal pair gets the mean of the two diagonal log
-    // costs; only M2L depends on the level difference.
+    // where the traversal asks it); M2L's does not depend on the particle
+    // counts; P2P's and M2P's log costs are piecewise linear in log n_s at
+    // fixed n_t between the measured points n_t / 4, n_t and 4 n_t (the
+    // measured slope on that side; the mean of the two diagonal log costs
+    // where a side was not measured); only M2L depends on the level
+    // difference.
     auto nearest = [&](const std::vector<Meas>& T, int i) {
         for (int d = 0; d < NS; d++) {
             if (i - d >= 0 && std::isfinite(T[i - d].v)) return T[i - d];
             if (i + d < NS && std::isfinite(T[i + d].v)) return T[i + d];
         }
         return Meas{};
+    };
+    // log2 cost at (n_t, n_s) = (pers[i], pers[j]) from the diagonal D and the
+    // measured points O at j = i -+ 2: linear in j on the side of j
+    auto along_ns = [&](const std::vector<Meas>& D, const std::vector<Meas>& O, int i, int j, bool mean_fallback) {
+        const double d = nearest(D, i).v;
+        if (j == i) return d;
+        const int side = j > i ? 2 : -2;
+        const int a = i + side;
+        if (a >= 0 && a < NS && std::isfinite(O[i * NS + a].v) && std::isfinite(d))
+            return d + (O[i * NS + a].v - d) * (double)(j - i) / (double)side;
+        return mean_fallback ? 0.5 * (d + nearest(D, j).v) : d;
     };
     auto emit = [&](int dl, int i, int j, int kind, const Meas&, double v) {
         if (!std::isfinite(v)) return;
@@ -1650,16 +1663,8 @@ static void gen_records(fmm_ctx c, int p, double theta, int precision, uint64_t 
             for (int dl : dls) {
                 const Meas ml = dl == 0 ? nearest(Tm2l, i) : nearest(Tgen, i);
                 emit(dl, i, j, 0, ml, ml.v);
-                const Meas& om = Om2p[i * NS + j];
-                const Meas mp = std::isfinite(om.v) ? om : nearest(Tm2p, i);
-                emit(dl, i, j, 1, mp, mp.v);
-                const Meas& op = Op2p[i * NS + j];
-                if (std::isfinite(op.v)) {
-                    emit(dl, i, j, 2, op, op.v);
-                } else {
-                    const Meas a = nearest(Tp2p, i), b2 = nearest(Tp2p, j);
-                    emit(dl, i, j, 2, a, 0.5 * (a.v + b2.v));
-                }
+                emit(dl, i, j, 1, Meas{}, along_ns(Tm2p, Om2p, i, j, false));
+                emit(dl, i, j, 2, Meas{}, along_ns(Tp2p, Op2p, i, j, true));
             }
 }
 
