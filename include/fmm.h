@@ -325,10 +325,12 @@ fmm_status fmm_tune(fmm_ctx ctx, int32_t p, int32_t precision);
 #define FMM_MLP_PARAMS 4803
 
 /* Generate timing records with the library's own kernels on artificial
- * clustered particle sets (homogeneous leaves of 2..256 particles; a
- * two-level set for mixed-level M2L), then train on the GPU with the
- * library's forward/backward/Adam kernels (full batch, `epochs` steps,
- * learning rate 3e-3, weights initialised from `seed`).  Enables
+ * clustered particle sets (homogeneous leaves of 2..4096 particles; a
+ * two-level set for mixed-level M2L; target and source trees with 4x fewer
+ * or more particles per source leaf for P2P and M2P off the diagonal),
+ * then train on the GPU with the library's forward/backward/Adam kernels
+ * (full batch, `epochs` steps, step 3e-2 decayed by a cosine to 1/20 of it,
+ * weights initialised from `seed`).  Enables
  * FMM_POLICY_HYBRID_MLP.  The timings are taken with the M2L kernel of
  * `precision` (FMM_PREC_FP32 or FMM_PREC_SPLIT_BF16), which evaluations using
  * the model should then use.  *final_loss (may be NULL) receives the mean
@@ -338,7 +340,8 @@ fmm_status fmm_costmodel_train(fmm_ctx ctx, int32_t p, double theta, int32_t pre
                                uint64_t seed, double *final_loss);
 
 /* Train on caller-given records (host arrays): features[n_rec][6],
- * kinds[n_rec] in {0 M2L, 1 M2P, 2 P2P}, targets[n_rec] = log2 ns. */
+ * kinds[n_rec] in {0 M2L, 1 M2P, 2 P2P}, targets[n_rec] = log2 ns; Adam
+ * with step lr at the first epoch, decayed by a cosine to lr / 20. */
 fmm_status fmm_costmodel_fit(fmm_ctx ctx, int32_t n_rec, const float *features, const int32_t *kinds,
                              const float *targets, int32_t epochs, double lr, uint64_t seed,
                              double *final_loss);

@@ -1559,7 +1559,7 @@ static void gen_records(fmm_ctx c, int p, double theta, int precision, uint64_t 
     };
     for (int si = 0; si < NS; si++) {
         const int per = pers[si];
-        const int L = level_for(per, 0, (int64_t)1 << 20);
+        const int L = level_for(per, 0, (int64_t)1 << 19);
         int64_t n = clustered_points(L, per, per, seed, nullptr, nullptr, nullptr, nullptr, c->stream);
         float* pts = need<float>(c, c->tune_pts, (size_t)4 * n);
         clustered_points(L, per, per, seed, pts, pts + n, pts + 2 * n, pts + 3 * n, c->stream);
@@ -1573,7 +1573,7 @@ static void gen_records(fmm_ctx c, int p, double theta, int precision, uint64_t 
         Tm2p[si] = meas(lg(tt[PH_FAR] - tf[PH_FAR], t->nlist[1]), 1);
         // mixed levels: the lower half one level deeper
         int L2 = L;
-        while (L2 > 1 && ((int64_t)1 << (3 * L2 - 1)) * 9 * per > ((int64_t)1 << 21)) L2--;
+        while (L2 > 1 && ((int64_t)1 << (3 * L2 - 1)) * 9 * per > ((int64_t)1 << 20)) L2--;
         int64_t n2 = clustered_points(L2, per, 8 * per, seed + 1, nullptr, nullptr, nullptr, nullptr, c->stream);
         pts = need<float>(c, c->tune_pts, (size_t)4 * n2);
         clustered_points(L2, per, 8 * per, seed + 1, pts, pts + n2, pts + 2 * n2, pts + 3 * n2, c->stream);
@@ -1591,7 +1591,7 @@ static void gen_records(fmm_ctx c, int p, double theta, int precision, uint64_t 
         for (int sj : {si, si - 2, si + 2}) {
             if (sj < 0 || sj >= NS) continue;
             const int ps = pers[sj];
-            const int Lo = level_for(per, ps, (int64_t)1 << 21);
+            const int Lo = level_for(per, ps, (int64_t)1 << 19);
             const int64_t nt = clustered_points(Lo, per, per, seed + 2, nullptr, nullptr, nullptr, nullptr, c->stream);
             const int64_t ns = clustered_points(Lo, ps, ps, seed + 3, nullptr, nullptr, nullptr, nullptr, c->stream);
             float* tp = need<float>(c, c->tune_pts, (size_t)4 * (nt + ns));
@@ -1710,9 +1710,11 @@ static double mlp_fit(fmm_ctx c, int B, const float* feat, const int32_t* kind, 
     to_dev(c, df, feat, (size_t)B * 6);
     to_dev(c, dk, kind, B);
     to_dev(c, dt, tgt, B);
+    // Adam with a cosine-decayed step: lr at the first epoch, lr / 20 at the last
     for (int e = 1; e <= epochs; e++) {
+        const double decay = 0.05 + 0.95 * 0.5 * (1.0 + std::cos(M_PI * (double)(e - 1) / (double)epochs));
         mlp_grad(dw, df, dk, dt, B, dgr, dlr, dg, dg + kMlpParams, c->stream);
-        mlp_adam(dw, dm, dv, dg, e, (float)lr, c->stream);
+        mlp_adam(dw, dm, dv, dg, e, (float)(lr * decay), c->stream);
     }
     mlp_grad(dw, df, dk, dt, B, dgr, dlr, dg, dg + kMlpParams, c->stream);
     check_launch("cost model training");
@@ -1736,7 +1738,7 @@ fmm_status fmm_costmodel_train(fmm_ctx c, int32_t p, double theta, int32_t preci
         auto t0 = std::chrono::steady_clock::now();
         gen_records(c, p, theta, precision, seed);
         double l = mlp_fit(c, (int)c->rec_kind.size(), c->rec_feat.data(), c->rec_kind.data(), c->rec_tgt.data(),
-                           epochs, 3e-3, seed);
+                           epochs, 3e-2, seed);
         c->cm_p = p;
         c->cm_theta = theta;
         c->cm_precision = precision;
