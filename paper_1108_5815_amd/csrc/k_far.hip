@@ -473,9 +473,12 @@ __global__ __launch_bounds__(64) void k_far_m2p(const float4* __restrict__ pts, 
     __shared__ int32_t own[LPW];         // owner index of leaf q at the current depth, -1 if none
     __shared__ int32_t dcell[LPW], dlen[LPW], doff[LPW];
     __shared__ int32_t s_nd, s_steps, s_depth;
+    __shared__ int32_t aoff[LPW][MAXD], alen[LPW][MAXD];  // list of anc[q][k]: offset, length (0 if none)
+    __shared__ uint32_t s_dmask;                          // depths where some packed leaf's ancestor has a list
     __shared__ float Ms[LPW][K];
     __shared__ double4 sctr[LPW];
     const int lane = threadIdx.x;
+    if (lane == 0) s_dmask = 0u;
     if (lane < LPW) {
         const int32_t l = (int32_t)blockIdx.x * LPW + lane;
         const bool flagged = l < nleaves && m2pflag[l];
@@ -486,6 +489,20 @@ __global__ __launch_bounds__(64) void k_far_m2p(const float4* __restrict__ pts, 
             for (int A = lp.cell[lane]; A >= 0 && d < MAXD; A = c.parent[A]) anc[lane][d++] = A;
         chain[lane] = d;
         for (int k = d; k < MAXD; k++) anc[lane][k] = -1;
+    }
+    __syncthreads();
+    // every (leaf, depth) list bound at once, lane-parallel
+    for (int u = lane; u < LPW * MAXD; u += 64) {
+        const int q = u / MAXD, k = u - q * MAXD;
+        const int32_t A = anc[q][k];
+        int32_t o = 0, len = 0;
+        if (A >= 0) {
+            o = m2p_off[A];
+            len = m2p_off[A + 1] - o;
+        }
+        aoff[q][k] = o;
+        alen[q][k] = len;
+        if (len > 0) atomicOr(&s_dmask, 1u << k);
     }
     __syncthreads();
     if (lane == 0) {
@@ -505,6 +522,7 @@ __global__ __launch_bounds__(64) void k_far_m2p(const float4* __restrict__ pts, 
         const float4 Pt = pts[valid ? i : lp.beg[q]];
         double4 acc = valid ? near[i] : make_double4(0, 0, 0, 0);
         for (int k = 0; k < s_depth; k++) {
+            if (!((s_dmask >> k) & 1u)) continue;  // no list at this depth (uniform)
             if (lane == 0) {
                 // leaves with particles in this round, in leaf order; equal
                 // owners are adjacent (leaves follow the tree order)
@@ -514,12 +532,12 @@ __global__ __launch_bounds__(64) void k_far_m2p(const float4* __restrict__ pts, 
                     const bool in_round = lp.cnt[qq] > 0 && lp.pre[qq] < r0 + 64 && lp.pre[qq + 1] > r0;
                     const int32_t A = in_round ? anc[qq][k] : -1;
                     if (A < 0) continue;
-                    const int32_t len = m2p_off[A + 1] - m2p_off[A];
+                    const int32_t len = alen[qq][k];
                     if (len == 0) continue;
                     if (nd == 0 || dcell[nd - 1] != A) {
                         dcell[nd] = A;
                         dlen[nd] = len;
-                        doff[nd] = m2p_off[A];
+                        doff[nd] = aoff[qq][k];
                         steps = max(steps, len);
                         nd++;
                     }
