@@ -1646,17 +1646,18 @@ static void gen_records(fmm_ctx c, int p, double theta, int precision, uint64_t 
             return d + (O[i * NS + a].v - d) * (double)(j - i) / (double)side;
         return mean_fallback ? 0.5 * (d + nearest(D, j).v) : d;
     };
-    auto emit = [&](int dl, int i, int j, int kind, const Meas&, double v) {
+    auto emit_n = [&](int dl, double nt, double ns, int kind, double v) {
         if (!std::isfinite(v)) return;
         for (int b = 0; b < kMlpBq; b++) {
             float f[6];
-            mlp_features(f, dl, pers[i], pers[j], p, theta);
+            mlp_features(f, dl, nt, ns, p, theta);
             f[4] = ((float)b + 0.5f) / (float)kMlpBq;
             c->rec_feat.insert(c->rec_feat.end(), f, f + 6);
             c->rec_kind.push_back(kind);
             c->rec_tgt.push_back((float)v);
         }
     };
+    auto emit = [&](int dl, int i, int j, int kind, const Meas&, double v) { emit_n(dl, pers[i], pers[j], kind, v); };
     const int dls[] = {-4, -2, -1, 0, 1, 2, 4};
     for (int i = 0; i < NS; i++)
         for (int j = std::max(0, i - 3); j <= std::min(NS - 1, i + 3); j++)
@@ -1666,6 +1667,26 @@ static void gen_records(fmm_ctx c, int p, double theta, int precision, uint64_t 
                 emit(dl, i, j, 1, Meas{}, along_ns(Tm2p, Om2p, i, j, false));
                 emit(dl, i, j, 2, Meas{}, along_ns(Tp2p, Op2p, i, j, true));
             }
+    // Outside the measured leaf sizes the records follow how the work
+    // scales, so that the network is anchored over the whole table (up to
+    // 2^20 particles a cell) instead of extrapolating: above the largest
+    // size P2P's cost grows as n_t n_s and M2P's as n_t from the last
+    // measured point, M2L's stays; below the smallest (one particle) the
+    // per-pair overheads dominate and the smallest measured costs stand.
+    const int top = NS - 1;
+    const int lt = (int)std::lround(std::log2((double)pers[top])), lb = (int)std::lround(std::log2((double)pers[0]));
+    for (int a = 0; a <= 20; a++)
+        for (int b = a - 3; b <= a + 3; b++) {
+            if (b < 0 || b > 20 || (a >= lb && a <= lt && b >= lb && b <= lt)) continue;
+            const double nt = std::ldexp(1.0, a), ns = std::ldexp(1.0, b);
+            const int ia = std::min(std::max(a, lb), lt) - lb, ib = std::min(std::max(b, lb), lt) - lb;
+            const double up_t = std::max(0, a - lt), up_s = std::max(0, b - lt);
+            for (int dl : dls) {
+                emit_n(dl, nt, ns, 0, (dl == 0 ? nearest(Tm2l, ia) : nearest(Tgen, ia)).v);
+                emit_n(dl, nt, ns, 1, along_ns(Tm2p, Om2p, ia, ib, false) + up_t);
+                emit_n(dl, nt, ns, 2, along_ns(Tp2p, Op2p, ia, ib, true) + up_t + up_s);
+            }
+        }
 }
 
 static void mlp_init(std::vector<float>& w, uint64_t seed, float out_bias) {

@@ -89,6 +89,16 @@ def test_plummer4m_learned_lists_and_headline_accuracy():
     lo = tr.lists()
     print("learned lists", [lo[k][0].size for k in (0, 1, 2)])
     _list_parity(f, lo, tr.ncell)
+    # the trained network's choices stay within reach of the timed ones: its
+    # particle-particle and cell-particle work is at most twice the timed policy's
+    learned_work = f.work()
+    f.tune(p, PREC_SPLIT_BF16)
+    f.traverse(p, theta, 2)
+    timed_work = f.work()
+    print("work learned", learned_work, "timed", timed_work)
+    assert learned_work["p2p_particle_pairs"] <= 2 * timed_work["p2p_particle_pairs"]
+    assert learned_work["m2p_targets"] <= 2 * timed_work["m2p_targets"] + 1000000
+    f.traverse(p, theta, 3)
     phi, E = f.evaluate(PREC_SPLIT_BF16, out_dtype=torch.float64)
     torch.cuda.synchronize()
     pd, Ed = ora.direct(x, y, z, q, tg)
