@@ -1529,7 +1529,10 @@ static void gen_records(fmm_ctx c, int p, double theta, int precision, uint64_t 
     t->auto_cart_max_p = c->auto_cart_max_p;
     t->timing = true;
     t->schedule = 0;  // each kernel timed alone
-    const int pers[] = {2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096};
+    // leaf sizes measured: up to 128 particles, where a set of at most 2^19
+    // particles still has 4096 leaves to fill the GPU (larger leaves would
+    // time a nearly idle device); larger sizes follow the work scaling below
+    const int pers[] = {2, 4, 8, 16, 32, 64, 128};
     const int NS = (int)(sizeof(pers) / sizeof(pers[0]));
     // one measurement: log2 ns per cell pair (NaN = not measured)
     struct Meas {
@@ -1671,8 +1674,9 @@ static void gen_records(fmm_ctx c, int p, double theta, int precision, uint64_t 
     // scales, so that the network is anchored over the whole table (up to
     // 2^20 particles a cell) instead of extrapolating: above the largest
     // size P2P's cost grows as n_t n_s and M2P's as n_t from the last
-    // measured point, M2L's stays; below the smallest (one particle) the
-    // per-pair overheads dominate and the smallest measured costs stand.
+    // measured point, M2L's (which does not depend on the counts) stays;
+    // below the smallest (one particle) the per-pair overheads dominate and
+    // the smallest measured costs stand.
     const int top = NS - 1;
     const int lt = (int)std::lround(std::log2((double)pers[top])), lb = (int)std::lround(std::log2((double)pers[0]));
     for (int a = 0; a <= 20; a++)
