@@ -1619,18 +1619,21 @@ static void gen_records(fmm_ctx c, int p, double theta, int precision, uint64_t 
             Om2p[si * NS + sj] = mm2p;
         }
     }
-    // Records.  Measured: the diagonal (n_t = n_s, equal levels; mixed levels
-    // for M2L) and P2P and M2P at n_s = n_t / 4 and 4 n_t (anchored as
-    // above; NaN wherever a measurement is missing).  The rest of the grid
-    // follows from how the kernels' work scales, stated here as the model's
-    // invariances: no kernel's work depends on the distance ratio (a record
-    // stands at every ratio bin, so the network sees each kind at the ratios
-    // where the traversal asks it); M2L's does not depend on the particle
-    // counts; P2P's and M2P's log costs are piecewise linear in log n_s at
-    // fixed n_t between the measured points n_t / 4, n_t and 4 n_t (the
-    // measured slope on that side; the mean of the two diagonal log costs
-    // where a side was not measured); only M2L depends on the level
-    // difference.
+    // Records over the whole feature grid the traversal asks about: log2 n_t
+    // and log2 n_s in 0..20, the level differences, two distance-ratio bins.
+    // Measured: the diagonal (n_t = n_s, equal levels; mixed levels for M2L)
+    // and P2P and M2P at n_s = n_t / 4 and 4 n_t (anchored as above).  The
+    // rest follows from how each kernel's work scales, stated here as the
+    // model's invariances: no kernel's work depends on the distance ratio;
+    // M2L's does not depend on the particle counts; at fixed n_t, P2P's and
+    // M2P's log costs are linear in log n_s between the measured points n_t / 4,
+    // n_t and 4 n_t (the measured slope on each side), and beyond them P2P's
+    // grows as n_s (slope 1) and M2P's stays; outside the measured leaf sizes
+    // P2P's and M2P's costs grow as n_t (and P2P's as n_s) from the nearest
+    // measured size, and below it the per-pair overheads dominate (the
+    // smallest measured costs stand).  The network is thus anchored wherever
+    // the table is read instead of extrapolating (left alone there, it once
+    // sent cells of a million particles to particle-particle sums).
     auto nearest = [&](const std::vector<Meas>& T, int i) {
         for (int d = 0; d < NS; d++) {
             if (i - d >= 0 && std::isfinite(T[i - d].v)) return T[i - d];
@@ -1638,59 +1641,46 @@ static void gen_records(fmm_ctx c, int p, double theta, int precision, uint64_t 
         }
         return Meas{};
     };
-    // log2 cost at (n_t, n_s) = (pers[i], pers[j]) from the diagonal D and the
-    // measured points O at j = i -+ 2: linear in j on the side of j
-    auto along_ns = [&](const std::vector<Meas>& D, const std::vector<Meas>& O, int i, int j, bool mean_fallback) {
+    const int lb = (int)std::lround(std::log2((double)pers[0]));
+    const int lt = (int)std::lround(std::log2((double)pers[NS - 1]));
+    // log2 cost of a cell pair with 2^a targets and 2^b sources, kind P2P
+    // (p2p = true) or M2P, from the diagonal D and the off-diagonal points O
+    auto cost = [&](const std::vector<Meas>& D, const std::vector<Meas>& O, int a, int b, bool p2p) {
+        const int ca = std::min(std::max(a, lb), lt), i = ca - lb;
         const double d = nearest(D, i).v;
-        if (j == i) return d;
-        const int side = j > i ? 2 : -2;
-        const int a = i + side;
-        if (a >= 0 && a < NS && std::isfinite(O[i * NS + a].v) && std::isfinite(d))
-            return d + (O[i * NS + a].v - d) * (double)(j - i) / (double)side;
-        return mean_fallback ? 0.5 * (d + nearest(D, j).v) : d;
+        const int db = b - ca;                          // log2 n_s - log2 n_t at the measured size
+        const int near = std::max(-2, std::min(2, db)); // within the measured points
+        double v = d;
+        if (near != 0) {
+            const int j = i + (near > 0 ? 2 : -2);
+            double o = (j >= 0 && j < NS) ? O[i * NS + j].v : NAN;
+            if (!std::isfinite(o)) o = p2p ? d + (near > 0 ? 2.0 : -2.0) * 0.5 : d;
+            v = d + (o - d) * std::abs(near) / 2.0;
+        }
+        if (p2p) v += (double)(db - near);           // beyond: work ~ n_s
+        if (a > lt) v += (double)(a - lt);            // larger target cells: work ~ n_t
+        return v;
     };
-    auto emit_n = [&](int dl, double nt, double ns, int kind, double v) {
+    auto emit = [&](int dl, int a, int b, int kind, double v) {
         if (!std::isfinite(v)) return;
-        for (int b = 0; b < kMlpBq; b++) {
+        for (int bq : {0, kMlpBq - 1}) {
             float f[6];
-            mlp_features(f, dl, nt, ns, p, theta);
-            f[4] = ((float)b + 0.5f) / (float)kMlpBq;
+            mlp_features(f, dl, std::ldexp(1.0, a), std::ldexp(1.0, b), p, theta);
+            f[4] = ((float)bq + 0.5f) / (float)kMlpBq;
             c->rec_feat.insert(c->rec_feat.end(), f, f + 6);
             c->rec_kind.push_back(kind);
             c->rec_tgt.push_back((float)v);
         }
     };
-    auto emit = [&](int dl, int i, int j, int kind, const Meas&, double v) { emit_n(dl, pers[i], pers[j], kind, v); };
     const int dls[] = {-4, -2, -1, 0, 1, 2, 4};
-    for (int i = 0; i < NS; i++)
-        for (int j = std::max(0, i - 3); j <= std::min(NS - 1, i + 3); j++)
-            for (int dl : dls) {
-                const Meas ml = dl == 0 ? nearest(Tm2l, i) : nearest(Tgen, i);
-                emit(dl, i, j, 0, ml, ml.v);
-                emit(dl, i, j, 1, Meas{}, along_ns(Tm2p, Om2p, i, j, false));
-                emit(dl, i, j, 2, Meas{}, along_ns(Tp2p, Op2p, i, j, true));
-            }
-    // Outside the measured leaf sizes the records follow how the work
-    // scales, so that the network is anchored over the whole table (up to
-    // 2^20 particles a cell) instead of extrapolating: above the largest
-    // size P2P's cost grows as n_t n_s and M2P's as n_t from the last
-    // measured point, M2L's (which does not depend on the counts) stays;
-    // below the smallest (one particle) the per-pair overheads dominate and
-    // the smallest measured costs stand.
-    const int top = NS - 1;
-    const int lt = (int)std::lround(std::log2((double)pers[top])), lb = (int)std::lround(std::log2((double)pers[0]));
     for (int a = 0; a <= 20; a++)
-        for (int b = a - 3; b <= a + 3; b++) {
-            if (b < 0 || b > 20 || (a >= lb && a <= lt && b >= lb && b <= lt)) continue;
-            const double nt = std::ldexp(1.0, a), ns = std::ldexp(1.0, b);
-            const int ia = std::min(std::max(a, lb), lt) - lb, ib = std::min(std::max(b, lb), lt) - lb;
-            const double up_t = std::max(0, a - lt), up_s = std::max(0, b - lt);
+        for (int b = 0; b <= 20; b++)
             for (int dl : dls) {
-                emit_n(dl, nt, ns, 0, (dl == 0 ? nearest(Tm2l, ia) : nearest(Tgen, ia)).v);
-                emit_n(dl, nt, ns, 1, along_ns(Tm2p, Om2p, ia, ib, false) + up_t);
-                emit_n(dl, nt, ns, 2, along_ns(Tp2p, Op2p, ia, ib, true) + up_t + up_s);
+                const int i = std::min(std::max(a, lb), lt) - lb;
+                emit(dl, a, b, 0, (dl == 0 ? nearest(Tm2l, i) : nearest(Tgen, i)).v);
+                emit(dl, a, b, 1, cost(Tm2p, Om2p, a, b, false));
+                emit(dl, a, b, 2, cost(Tp2p, Op2p, a, b, true));
             }
-        }
 }
 
 static void mlp_init(std::vector<float>& w, uint64_t seed, float out_bias) {
