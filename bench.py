@@ -224,6 +224,8 @@ def run_batch(args):
     import synth
     from paper_1108_5815_amd import FMM
     x, y, z, q, off, kinds, tg, w = synth.make_batch(args.workload, args.n_inst)
+    if args.p is not None:
+        w["p"] = args.p
     n, p, theta, ncrit = w["n"], w["p"], w["theta"], w["ncrit"]
     dev = "cuda:0"
     X, Y, Z, Q = (torch.tensor(a, dtype=torch.float32, device=dev) for a in (x, y, z, q))
@@ -389,6 +391,7 @@ def main():
     ap.add_argument("--workload", default="plummer4m_p10")
     ap.add_argument("--n", type=int, default=None, help="override particle count")
     ap.add_argument("--n-inst", type=int, default=None, help="batch workloads: first n instances only")
+    ap.add_argument("--p", type=int, default=None, help="override the workload's expansion order")
     ap.add_argument("--policy", type=int, default=3, help="0 fmm, 1 treecode, 2 timed hybrid, 3 learned hybrid")
     ap.add_argument("--precision", type=int, default=1, help="0 fp32, 1 split-bf16 M2L")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain (timed FP32) comparison")
@@ -422,6 +425,8 @@ def main():
         run_batch(args)
         return
     x, y, z, q, tg, w = synth.make_workload(args.workload, args.n)
+    if args.p is not None:
+        w["p"] = args.p
     n, p = w["n"], w["p"]
     dev = "cuda:0"
     X, Y, Z, Q = (torch.tensor(a, dtype=torch.float32, device=dev) for a in (x, y, z, q))
