@@ -81,7 +81,7 @@ def prepare_costmodel(f, w, precision, args):
                 "final_loss_log2": float.fromhex(meta["loss"]) if meta.get("loss", "nan") not in ("nan", "-nan")
                 else None, "records": int(meta.get("records", 0))}
     t0 = time.perf_counter()
-    loss = f.costmodel_train(p, theta, epochs=8000, seed=7, precision=precision)
+    loss = f.costmodel_train(p, theta, epochs=6000, seed=7, precision=precision)
     prep = {"costmodel": "trained", "training_s": time.perf_counter() - t0, "final_loss_log2": loss,
             "records": int(f.costmodel_records()[1].size)}
     if args.save_costmodel:

@@ -327,8 +327,8 @@ fmm_status fmm_tune(fmm_ctx ctx, int32_t p, int32_t precision);
 /* Generate timing records with the library's own kernels on artificial
  * clustered particle sets (homogeneous leaves of 2..128 particles; a
  * two-level set for mixed-level M2L; target and source trees with 4x fewer
- * or more particles per source leaf for P2P and M2P off the diagonal; the
- * rest of the feature grid from how each kind's work scales),
+ * or more particles per source leaf for P2P off the diagonal; the rest of
+ * the feature grid from how each kind's work scales),
  * then train on the GPU with the library's forward/backward/Adam kernels
  * (full batch, `epochs` steps, step 3e-2 decayed by a cosine to 1/20 of it,
  * weights initialised from `seed`).  Enables

@@ -334,7 +334,7 @@ class FMM:
         self._ck(lib().fmm_tune(self.h, int(p), int(precision)))
 
     # ------------------------------------------------------------ learned cost model
-    def costmodel_train(self, p: int, theta: float, epochs: int = 8000, seed: int = 1,
+    def costmodel_train(self, p: int, theta: float, epochs: int = 6000, seed: int = 1,
                         precision: int = PREC_FP32) -> float:
         loss = ctypes.c_double()
         self._ck(lib().fmm_costmodel_train(self.h, int(p), float(theta), int(precision), int(epochs), int(seed),

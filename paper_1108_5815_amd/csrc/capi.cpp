@@ -1510,7 +1510,8 @@ static void mlp_features(float* f, int dl, double nt, double ns, int p, double t
 // the treecode policy M2P per cell pair, and a set whose lower half is one
 // level deeper times the mixed-level M2L pairs of its interface.  Target and
 // source sets on one lattice with different leaf sizes (a target tree and a
-// source tree) time P2P and M2P off the diagonal n_t != n_s.
+// source tree) time P2P off the diagonal n_t != n_s (an M2P evaluation reads
+// only the source's multipole, so its cost does not depend on n_s).
 static void gen_records(fmm_ctx c, int p, double theta, int precision, uint64_t seed) {
     c->rec_feat.clear();
     c->rec_kind.clear();
@@ -1540,18 +1541,20 @@ static void gen_records(fmm_ctx c, int p, double theta, int precision, uint64_t 
     };
     // diagonal (n_t = n_s): same-level M2L, mixed-level M2L, M2P, P2P per leaf size
     std::vector<Meas> Tm2l(NS), Tgen(NS), Tm2p(NS), Tp2p(NS);
-    // off the diagonal, targets pers[i] and sources pers[j]: M2P, P2P at [i NS + j]
+    // off the diagonal, targets pers[i] and sources pers[j]: P2P at [i NS + j]
+    // (M2P's stay unmeasured: its cost does not depend on n_s)
     std::vector<Meas> Om2p(NS * NS), Op2p(NS * NS);
     auto lg = [](double ms, int64_t units) { return units > 0 && ms > 0 ? std::log2(ms * 1e6 / (double)units) : NAN; };
     auto meas = [](double v, int) { return Meas{v}; };
-    auto timed = [&](int policy, double* tm) {
+    // a warm-up evaluation, then the mean of `reps` timed ones
+    auto timed = [&](int policy, double* tm, int reps) {
         traverse_impl(t, p, theta, policy);
         float* out = need<float>(c, c->tune_out, (size_t)4 * t->n);
         for (int k = 0; k < PH_N; k++) tm[k] = 0;
-        for (int rep = 0; rep < 3; rep++) {
+        for (int rep = 0; rep <= reps; rep++) {
             evaluate_impl(t, precision, FMM_F32, out, out + t->n, out + 2 * t->n, out + 3 * t->n);
             if (rep > 0)
-                for (int k = 0; k < PH_N; k++) tm[k] += t->ms[k] / 2;
+                for (int k = 0; k < PH_N; k++) tm[k] += t->ms[k] / reps;
         }
     };
     // lattice level for a set of 2^(3L) leaves of `per` particles (plus another of per2)
@@ -1569,10 +1572,10 @@ static void gen_records(fmm_ctx c, int p, double theta, int precision, uint64_t 
         check_launch("clustered points");
         build_tree_impl(t, n, FMM_F32, pts, pts + n, pts + 2 * n, pts + 3 * n, per);
         double tf[PH_N], tt[PH_N];
-        timed(FMM_POLICY_FMM, tf);
+        timed(FMM_POLICY_FMM, tf, 2);
         Tm2l[si] = meas(lg(tf[PH_M2L], t->nlist[0] - t->ngeneral), 0);
         Tp2p[si] = meas(lg(tf[PH_P2P], t->nlist[2]), 2);
-        timed(FMM_POLICY_TREECODE, tt);
+        timed(FMM_POLICY_TREECODE, tt, 1);  // M2P-heavy lists: one timed run is ample work
         Tm2p[si] = meas(lg(tt[PH_FAR] - tf[PH_FAR], t->nlist[1]), 1);
         // mixed levels: the lower half one level deeper
         int L2 = L;
@@ -1582,7 +1585,7 @@ static void gen_records(fmm_ctx c, int p, double theta, int precision, uint64_t 
         clustered_points(L2, per, 8 * per, seed + 1, pts, pts + n2, pts + 2 * n2, pts + 3 * n2, c->stream);
         check_launch("clustered points");
         build_tree_impl(t, n2, FMM_F32, pts, pts + n2, pts + 2 * n2, pts + 3 * n2, per);
-        timed(FMM_POLICY_FMM, tf);
+        timed(FMM_POLICY_FMM, tf, 2);
         Tgen[si] = meas(lg(tf[PH_M2LG], t->ngeneral), 0);
         // off the diagonal: targets with `per` per leaf, sources with 4x fewer
         // or more on the same lattice; a leaf size ncrit in [max, 8 min) stops
@@ -1590,7 +1593,7 @@ static void gen_records(fmm_ctx c, int p, double theta, int precision, uint64_t 
         // (every particle pair guarded against r = 0), so the same two-tree
         // run at n_s = n_t anchors them: a record is the one-tree diagonal
         // cost times the measured two-tree ratio.
-        double ts_diag[2] = {NAN, NAN};  // two-tree log2 costs at n_s = n_t: P2P, M2P
+        double ts_diag[1] = {NAN};  // two-tree log2 P2P cost at n_s = n_t
         for (int sj : {si, si - 2, si + 2}) {
             if (sj < 0 || sj >= NS) continue;
             const int ps = pers[sj];
@@ -1604,31 +1607,26 @@ static void gen_records(fmm_ctx c, int p, double theta, int precision, uint64_t 
             check_launch("clustered points");
             build_tree_ts_impl(t, FMM_F32, nt, tp, tp + nt, tp + 2 * nt, ns, sp, sp + ns, sp + 2 * ns, sp + 3 * ns,
                                std::max(per, ps));
-            timed(FMM_POLICY_FMM, tf);
+            timed(FMM_POLICY_FMM, tf, 2);
             Meas mp2p = meas(lg(tf[PH_P2P], t->nlist[2]), 2);
-            timed(FMM_POLICY_TREECODE, tt);
-            Meas mm2p = meas(lg(tt[PH_FAR] - tf[PH_FAR], t->nlist[1]), 1);
             if (sj == si) {
                 ts_diag[0] = mp2p.v;
-                ts_diag[1] = mm2p.v;
                 continue;
             }
             mp2p.v += Tp2p[si].v - ts_diag[0];
-            mm2p.v += Tm2p[si].v - ts_diag[1];
             Op2p[si * NS + sj] = mp2p;
-            Om2p[si * NS + sj] = mm2p;
         }
     }
     // Records over the whole feature grid the traversal asks about: log2 n_t
     // and log2 n_s in 0..20, the level differences, two distance-ratio bins.
     // Measured: the diagonal (n_t = n_s, equal levels; mixed levels for M2L)
-    // and P2P and M2P at n_s = n_t / 4 and 4 n_t (anchored as above).  The
+    // and P2P at n_s = n_t / 4 and 4 n_t (anchored as above).  The
     // rest follows from how each kernel's work scales, stated here as the
     // model's invariances: no kernel's work depends on the distance ratio;
-    // M2L's does not depend on the particle counts; at fixed n_t, P2P's and
-    // M2P's log costs are linear in log n_s between the measured points n_t / 4,
-    // n_t and 4 n_t (the measured slope on each side), and beyond them P2P's
-    // grows as n_s (slope 1) and M2P's stays; outside the measured leaf sizes
+    // M2L's does not depend on the particle counts, nor M2P's on n_s; at
+    // fixed n_t, P2P's log cost is linear in log n_s between the measured
+    // points n_t / 4, n_t and 4 n_t (the measured slope on each side), and
+    // beyond them grows as n_s (slope 1); outside the measured leaf sizes
     // P2P's and M2P's costs grow as n_t (and P2P's as n_s) from the nearest
     // measured size, and below it the per-pair overheads dominate (the
     // smallest measured costs stand).  The network is thus anchored wherever

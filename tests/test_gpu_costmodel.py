@@ -108,7 +108,7 @@ def plummer_inputs(n, seed):
 
 def test_train_on_own_timings_and_accuracy():
     f = fmm()
-    loss = f.costmodel_train(10, 0.4, epochs=8000, seed=7)
+    loss = f.costmodel_train(10, 0.4, epochs=6000, seed=7)
     feat, kind, tgt = f.costmodel_records()
     print("records", kind.size, "final loss", loss)
     assert kind.size >= 12 and set(np.unique(kind)) == {0, 1, 2}
@@ -161,7 +161,7 @@ def test_gain_of_learned_model(precision):
     t = [torch.tensor(a, dtype=torch.float32, device="cuda:0") for a in (x, y, z, q)]
     f = fmm()
     f.tune(10, precision)
-    f.costmodel_train(10, 0.4, epochs=8000, seed=7, precision=precision)
+    f.costmodel_train(10, 0.4, epochs=6000, seed=7, precision=precision)
     out = (torch.empty(n, device="cuda:0"), torch.empty((3, n), device="cuda:0"))
     res = {name: _median_rate(f, t, n, pol, precision, out) for name, pol in
            (("fmm", 0), ("timed", 2), ("learned", 3))}
@@ -222,7 +222,7 @@ def test_learned_split_bf16_plummer16m_p12():
     x, y, z, q, tg, w = synth.make_workload("plummer16m_p12")
     x, y, z, q = (np.asarray(a, np.float32).astype(np.float64) for a in (x, y, z, q))
     f = fmm()
-    f.costmodel_train(12, 0.4, epochs=8000, seed=7, precision=1)
+    f.costmodel_train(12, 0.4, epochs=6000, seed=7, precision=1)
     t = [torch.tensor(a, dtype=torch.float32, device="cuda:0") for a in (x, y, z, q)]
     f.build_tree(*t, w["ncrit"])
     f.traverse(12, 0.4, 3)

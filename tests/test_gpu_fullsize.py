@@ -81,7 +81,7 @@ def test_plummer4m_learned_lists_and_headline_accuracy():
     from paper_1108_5815_amd import PREC_SPLIT_BF16
     f, tr, (x, y, z, q, tg, w) = _build("plummer4m_p10")
     p, theta = w["p"], w["theta"]
-    f.costmodel_train(p, theta, epochs=8000, seed=7, precision=PREC_SPLIT_BF16)
+    f.costmodel_train(p, theta, epochs=6000, seed=7, precision=PREC_SPLIT_BF16)
     f.build_tree(*(torch.tensor(a, dtype=torch.float32, device="cuda:0") for a in (x, y, z, q)), w["ncrit"])
     f.traverse(p, theta, 3)
     table = f.costmodel_table(p, theta)
