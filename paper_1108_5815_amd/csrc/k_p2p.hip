@@ -11,11 +11,12 @@
 // source cells of the leaf's list are concatenated into one stream: 64 list
 // entries at a time are fetched lane-parallel, a wave prefix sum over their
 // sizes maps stream positions to cells, and the wave copies the stream into
-// an LDS chunk with all lanes busy.  Each group then takes a contiguous,
-// equal share of the chunk, reads it from LDS (one address per group, a
-// broadcast), accumulates in FP32 and adds the chunk's partial into FP64
-// per-target sums; the groups are summed in group order at the end, so
-// results do not depend on timing.
+// an LDS chunk with all lanes busy.  Group g of G then takes sources g,
+// g + G, g + 2G, ... of the chunk and reads them from LDS (one address per
+// group, a broadcast; at each step the groups read neighbouring addresses,
+// which lie in distinct banks), accumulates in FP32 and adds the chunk's
+// partial into FP64 per-target sums; the groups are summed in group order at
+// the end, so results do not depend on timing.
 //
 // Two forms of tile, chosen per leaf-size class by the library's autotuner
 // (leaves are launched grouped by class):
@@ -56,15 +57,16 @@ __device__ inline void interact(const float3 P, const float4 Q, float4& f) {
     f.z += qi3 * dz;
 }
 
-// Sources buf[j0, j1) against the lane's TPL targets, FP32 partials added to acc.
+// Sources g, g + G, g + 2G, ... of buf[0, n) (group g of G) against the
+// lane's TPL targets, FP32 partials added to acc.
 template <int TPL, bool GUARD>
-__device__ inline void chunk_sum(const float4* buf, int j0, int j1, const float3 (&P)[TPL], double4 (&acc)[TPL]) {
+__device__ inline void chunk_sum(const float4* buf, int g, int G, int n, const float3 (&P)[TPL], double4 (&acc)[TPL]) {
     float4 f[TPL];
 #pragma unroll
     for (int k = 0; k < TPL; k++) f[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-    int j = j0;
-    for (; j + 3 < j1; j += 4) {
-        const float4 Q0 = buf[j], Q1 = buf[j + 1], Q2 = buf[j + 2], Q3 = buf[j + 3];
+    int j = g;
+    for (; j + 3 * G < n; j += 4 * G) {
+        const float4 Q0 = buf[j], Q1 = buf[j + G], Q2 = buf[j + 2 * G], Q3 = buf[j + 3 * G];
 #pragma unroll
         for (int k = 0; k < TPL; k++) {
             interact<GUARD>(P[k], Q0, f[k]);
@@ -73,7 +75,7 @@ __device__ inline void chunk_sum(const float4* buf, int j0, int j1, const float3
             interact<GUARD>(P[k], Q3, f[k]);
         }
     }
-    for (; j < j1; j++) {
+    for (; j < n; j += G) {
         const float4 Q = buf[j];
 #pragma unroll
         for (int k = 0; k < TPL; k++) interact<GUARD>(P[k], Q, f[k]);
@@ -125,11 +127,6 @@ __global__ __launch_bounds__(64) void k_p2p(const float4* __restrict__ pts, Cell
             P[k] = make_float3(v.x, v.y, v.z);
             acc[k] = make_double4(0.0, 0.0, 0.0, 0.0);
         }
-        // group g's equal share of a staged chunk of n sources
-        auto share = [&](int n, int& j0, int& j1) {
-            j0 = (g * n) / G;
-            j1 = ((g + 1) * n) / G;
-        };
 
         // (1) the leaf's own cell, guarded (left out of the stream below)
         if (!GUARD_ALL) {
@@ -137,9 +134,7 @@ __global__ __launch_bounds__(64) void k_p2p(const float4* __restrict__ pts, Cell
                 const int n = min(e - s0, CH);
                 for (int k = lane; k < n; k += 64) buf[k] = pts[s0 + k];
                 __syncthreads();
-                int j0, j1;
-                share(n, j0, j1);
-                if (active) chunk_sum<TPL, true>(buf, j0, j1, P, acc);
+                if (active) chunk_sum<TPL, true>(buf, g, G, n, P, acc);
                 __syncthreads();
             }
         }
@@ -182,9 +177,7 @@ __global__ __launch_bounds__(64) void k_p2p(const float4* __restrict__ pts, Cell
                     done += take;
                     if (fill == CH) {
                         __syncthreads();
-                        int j0, j1;
-                        share(CH, j0, j1);
-                        if (active) chunk_sum<TPL, GUARD_ALL>(buf, j0, j1, P, acc);
+                        if (active) chunk_sum<TPL, GUARD_ALL>(buf, g, G, CH, P, acc);
                         fill = 0;
                         __syncthreads();
                     }
@@ -194,9 +187,7 @@ __global__ __launch_bounds__(64) void k_p2p(const float4* __restrict__ pts, Cell
         }
         if (fill > 0) {
             __syncthreads();
-            int j0, j1;
-            share(fill, j0, j1);
-            if (active) chunk_sum<TPL, GUARD_ALL>(buf, j0, j1, P, acc);
+            if (active) chunk_sum<TPL, GUARD_ALL>(buf, g, G, fill, P, acc);
             __syncthreads();
         }
 
