@@ -54,16 +54,22 @@ __device__ inline void gemm_item(const GemmPlan& plan, int& tile, int& g) {
     g = (int)(b & 7u) + 8 * (int)(rest / (unsigned)plan.ntiles);
 }
 
-template <int KP, int NT, int RW, int CW, int NQ>
-__global__ __launch_bounds__(64 * RW * CW) void k_m2l_bf16(const uint4* __restrict__ Thi, const uint4* __restrict__ Tlo,
+// Waves: RW row blocks x CW column blocks x KSP parts of K.  With KSP = 2 two
+// waves share each (row block, column block), each summing the products of
+// one half of K, and the halves are added once at the tile's end: every
+// operator fragment is then loaded by one wave of the workgroup, so a tile of
+// 128 targets halves the operator bytes per product at two waves per SIMD.
+template <int KP, int NT, int RW, int CW, int NQ, int KSP>
+__global__ __launch_bounds__(64 * RW * CW * KSP) void k_m2l_bf16(const uint4* __restrict__ Thi, const uint4* __restrict__ Tlo,
                                                   const int32_t* __restrict__ offid,
                                                   const int32_t* __restrict__ gather, GemmPlan plan,
                                                   const uint4* __restrict__ Ms, float* __restrict__ part) {
     constexpr int KB = KP / 8;          // 8-wide K blocks
     constexpr int KS = KP / 16;         // MFMA K steps (16 values each)
+    constexpr int KSW = KS / KSP;       // K steps of one wave
     constexpr int RB = KP / 32, CB = NT / 32;
-    constexpr int NTH = 64 * RW * CW;   // lanes of the workgroup
-    static_assert(RB % RW == 0 && CB % CW == 0, "wave grid");
+    constexpr int NTH = 64 * RW * CW * KSP;  // lanes of the workgroup
+    static_assert(RB % RW == 0 && CB % CW == 0 && KS % KSP == 0, "wave grid");
     constexpr int NRB = RB / RW, NCB = CB / CW;
     constexpr int STR = KB + 1;         // LDS row stride in 16-byte units
     constexpr int HL = NT * STR;        // one half (hi or lo) of a source tile
@@ -81,7 +87,7 @@ __global__ __launch_bounds__(64 * RW * CW) void k_m2l_bf16(const uint4* __restri
     const int J = plan.J;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int l32 = lane & 31, h = lane >> 5;
-    const int wr = w % RW, wc = w / RW;
+    const int wr = w % RW, wc = (w / RW) % CW, wk = w / (RW * CW);
     // this group's slots [g J / G, (g + 1) J / G), restricted to those some row
     // of the tile uses: fixed slot ranges make each row's partial independent
     // of the other rows of its tile
@@ -141,8 +147,8 @@ __global__ __launch_bounds__(64 * RW * CW) void k_m2l_bf16(const uint4* __restri
     // slot (SC steps each): the next part (of this slot, or the first part of
     // the next slot) loads while the current part computes, so operator loads
     // run one part ahead.  Step s, half h of the wave -> K block 2s + h.
-    constexpr int SC = KS / NQ;
-    static_assert(KS % NQ == 0, "slot parts");
+    constexpr int SC = KSW / NQ;
+    static_assert(KSW % NQ == 0, "slot parts");
     u32x4 ah[2][NRB][SC], al[2][NRB][SC];
     auto load_A = [&](int op, int half, int buf) {
         const size_t base = (size_t)op * KB * KP;
@@ -150,7 +156,7 @@ __global__ __launch_bounds__(64 * RW * CW) void k_m2l_bf16(const uint4* __restri
         for (int r = 0; r < NRB; r++)
 #pragma unroll
             for (int s = 0; s < SC; s++) {
-                const size_t ix = base + (size_t)(2 * (half * SC + s) + h) * KP + (wr + RW * r) * 32 + l32;
+                const size_t ix = base + (size_t)(2 * (wk * KSW + half * SC + s) + h) * KP + (wr + RW * r) * 32 + l32;
                 ah[buf][r][s] = reinterpret_cast<const u32x4*>(Thi)[ix];
                 al[buf][r][s] = reinterpret_cast<const u32x4*>(Tlo)[ix];
             }
@@ -158,7 +164,7 @@ __global__ __launch_bounds__(64 * RW * CW) void k_m2l_bf16(const uint4* __restri
     auto compute = [&](int bbuf, int half, int abuf) {
 #pragma unroll
         for (int s = 0; s < SC; s++) {
-            const int st = half * SC + s;
+            const int st = wk * KSW + half * SC + s;
 #pragma unroll
             for (int b = 0; b < NCB; b++) {
                 const int col = (wc + CW * b) * 32 + l32;
@@ -224,6 +230,29 @@ __global__ __launch_bounds__(64 * RW * CW) void k_m2l_bf16(const uint4* __restri
             }
         }
     }
+    if constexpr (KSP == 2) {
+        // the second half of K adds its sums to the first's through the LDS
+        // tile (every wave is past the slot loop's last barrier)
+        static_assert(RW * CW * NRB * NCB * 16 * 64 * 4 <= (int)sizeof(Bs), "K reduction fits the tile");
+        float* red = reinterpret_cast<float*>(&Bs[0][0]);
+        const int wi = wr + RW * wc;
+        if (wk == 1) {
+#pragma unroll
+            for (int i = 0; i < NRB; i++)
+#pragma unroll
+                for (int b = 0; b < NCB; b++)
+#pragma unroll
+                    for (int r = 0; r < 16; r++) red[(((wi * NRB + i) * NCB + b) * 16 + r) * 64 + lane] = acc[i][b][r];
+        }
+        __syncthreads();
+        if (wk == 1) return;
+#pragma unroll
+        for (int i = 0; i < NRB; i++)
+#pragma unroll
+            for (int b = 0; b < NCB; b++)
+#pragma unroll
+                for (int r = 0; r < 16; r++) acc[i][b][r] += red[(((wi * NRB + i) * NCB + b) * 16 + r) * 64 + lane];
+    }
     // partial locals of this group (zero when it has no slots)
 #pragma unroll
     for (int b = 0; b < NCB; b++) {
@@ -237,11 +266,11 @@ __global__ __launch_bounds__(64 * RW * CW) void k_m2l_bf16(const uint4* __restri
     }
 }
 
-template <int KP, int NT, int RW, int CW, int NQ>
+template <int KP, int NT, int RW, int CW, int NQ, int KSP = 1>
 void launch(const uint16_t* Thi, const uint16_t* Tlo, const int32_t* offid, const int32_t* gather, GemmPlan plan,
             const uint4* Ms, float* part, hipStream_t s) {
-    k_m2l_bf16<KP, NT, RW, CW, NQ><<<plan.ntiles * plan.G, 64 * RW * CW, 0, s>>>((const uint4*)Thi, (const uint4*)Tlo, offid,
-                                                                         gather, plan, Ms, part);
+    k_m2l_bf16<KP, NT, RW, CW, NQ, KSP><<<plan.ntiles * plan.G, 64 * RW * CW * KSP, 0, s>>>(
+        (const uint4*)Thi, (const uint4*)Tlo, offid, gather, plan, Ms, part);
 }
 
 // Multipoles of every cell split into bf16 hi and lo: Ms[cell][0][kb] = hi of
@@ -283,7 +312,7 @@ void m2l_gemm_bf16(const uint16_t* Thi, const uint16_t* Tlo, const int32_t* offi
         case 64: launch<64, 128, 2, 2, 2>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
         case 96: launch<96, 128, 3, 4, 2>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
         case 128:
-            if (plan.nt == 128) launch<128, 128, 4, 1, 4>(Thi, Tlo, offid, gather, plan, Ms, part, s);
+            if (plan.nt == 128) launch<128, 128, 4, 1, 2, 2>(Thi, Tlo, offid, gather, plan, Ms, part, s);
             else launch<128, 64, 4, 1, 4>(Thi, Tlo, offid, gather, plan, Ms, part, s);
             break;
         case 192: launch<192, 64, 2, 2, 4>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
