@@ -502,11 +502,10 @@ fmm_status fmm_set_overlap(fmm_ctx ctx, int32_t schedule);
  * fastest; where the M2L GEMM has two tile widths it times both
  * (fmm_set_m2l_tile) and keeps the faster; then it times fmm_evaluate at
  * `precision` under the three schedules of fmm_set_overlap and keeps the
- * fastest.  The schedule does not change results, nor does the M2L tile
- * width in FP32; the P2P tile shape, the M2L kind and the tile width in
- * split-BF16 (the 128-wide tiles sum each half of K apart) change how sums
- * are split into FP32 partials, so results move by rounding only (each
- * choice is itself deterministic).
+ * fastest.  The schedule and the M2L tile width do not change results; the
+ * P2P tile shape and the M2L kind change how sums are split into FP32
+ * partials, so results move by rounding only (each choice is itself
+ * deterministic).
  * Requires a completed traversal.  Default before tuning: 4 targets per lane,
  * schedule 2.
  */
@@ -517,9 +516,7 @@ fmm_status fmm_autotune(fmm_ctx ctx, int32_t precision, int32_t reps);
  * 0 = the width's default (64); other widths have one tiling and ignore it.
  * Takes effect at the next fmm_traverse (fmm_autotune also rebuilds the
  * current tables when it picks a width).  Wider tiles load each translation
- * operator once for more targets; in split-BF16 two waves then share each
- * block of products, one per half of K, and their sums are added at the end
- * (values move by rounding against 64-wide tiles).  get: the width of the current tables
+ * operator once for more targets.  get: the width of the current tables
  * (after a traversal with GEMM pairs), else the one asked for.  Any other
  * value is FMM_ERR_INVALID_ARG. */
 fmm_status fmm_set_m2l_tile(fmm_ctx ctx, int32_t cols);

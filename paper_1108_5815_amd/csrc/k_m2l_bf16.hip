@@ -56,9 +56,11 @@ __device__ inline void gemm_item(const GemmPlan& plan, int& tile, int& g) {
 
 // Waves: RW row blocks x CW column blocks x KSP parts of K.  With KSP = 2 two
 // waves share each (row block, column block), each summing the products of
-// one half of K, and the halves are added once at the tile's end: every
-// operator fragment is then loaded by one wave of the workgroup, so a tile of
-// 128 targets halves the operator bytes per product at two waves per SIMD.
+// one half of K, and the halves are added once at the tile's end: a wave
+// holds half the operator fragments and accumulators, so at storage width 128
+// tiles of 64 targets run four waves per SIMD (two workgroups of eight per
+// CU), and tiles of 128 load each operator fragment once per workgroup.  A
+// row's sums, and their order, are the same at both widths.
 template <int KP, int NT, int RW, int CW, int NQ, int KSP>
 __global__ __launch_bounds__(64 * RW * CW * KSP) void k_m2l_bf16(const uint4* __restrict__ Thi, const uint4* __restrict__ Tlo,
                                                   const int32_t* __restrict__ offid,
@@ -313,7 +315,7 @@ void m2l_gemm_bf16(const uint16_t* Thi, const uint16_t* Tlo, const int32_t* offi
         case 96: launch<96, 128, 3, 4, 2>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
         case 128:
             if (plan.nt == 128) launch<128, 128, 4, 1, 2, 2>(Thi, Tlo, offid, gather, plan, Ms, part, s);
-            else launch<128, 64, 4, 1, 4>(Thi, Tlo, offid, gather, plan, Ms, part, s);
+            else launch<128, 64, 4, 1, 2, 2>(Thi, Tlo, offid, gather, plan, Ms, part, s);
             break;
         case 192: launch<192, 64, 2, 2, 4>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
         default: return;

@@ -1,10 +1,8 @@
 """Tile width of the same-level M2L GEMM (fmm_set_m2l_tile): at storage width
-128 (p = 10) tiles of 64 and of 128 targets give identical FP32 values (a
-row's products and their order do not depend on which other rows share its
-tile: slots a row does not use read the all-zero row); in split-BF16 the
-128-wide tiles sum each half of K in its own wave and add the halves at the
-end, so the two widths agree to rounding.  Both agree with the oracle's FMM,
-and the autotuner keeps one of the two."""
+128 (p = 10) tiles of 64 and of 128 targets give identical values in both
+precisions (a row's products and their order do not depend on which other
+rows share its tile: slots a row does not use read the all-zero row), agree
+with the oracle's FMM, and the autotuner keeps one of the two."""
 import numpy as np
 import pytest
 
@@ -44,12 +42,7 @@ def test_tile_widths_identical(precision):
         out[cols] = (phi.cpu().numpy(), E.cpu().numpy(), shape)
     print("gemm shapes", out[64][2], out[128][2])
     assert out[128][2]["tiles"] < out[64][2]["tiles"]
-    if precision == 0:
-        assert np.array_equal(out[64][0], out[128][0]) and np.array_equal(out[64][1], out[128][1])
-    else:
-        # two partial sums over K instead of one: FP32 rounding of the accumulation order only
-        assert ora.rel_l2(out[128][0], out[64][0]) < 1e-6
-        assert ora.rel_l2(out[128][1].T, out[64][1].T) < 1e-6
+    assert np.array_equal(out[64][0], out[128][0]) and np.array_equal(out[64][1], out[128][1])
     po, Eo, _ = ora.fmm(x, y, z, q, 10, 0.5, 64)
     tol = 1e-5 if precision == 0 else 2e-5
     assert ora.rel_l2(out[128][0], po) < tol and ora.rel_l2(out[128][1].T, Eo) < 10 * tol
