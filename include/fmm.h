@@ -499,10 +499,9 @@ fmm_status fmm_set_overlap(fmm_ctx ctx, int32_t schedule);
  * on v_mfma_f32_4x4x1f32; the vector ALUs form only 1/r and 1/r^3); if the lists
  * hold M2L pairs outside the same-level GEMM (spherical family) it times
  * fmm_evaluate under the four kinds of fmm_set_m2l_kernel and keeps the
- * fastest; where the M2L GEMM has two tile widths it times both
- * (fmm_set_m2l_tile) and keeps the faster; then it times fmm_evaluate at
- * `precision` under the three schedules of fmm_set_overlap and keeps the
- * fastest.  The schedule and the M2L tile width do not change results; the
+ * fastest; then it times fmm_evaluate at `precision` under each tile width
+ * of the M2L GEMM (where it has two, fmm_set_m2l_tile) and each of the three
+ * schedules of fmm_set_overlap, and keeps the fastest pair.  The schedule and the M2L tile width do not change results; the
  * P2P tile shape and the M2L kind change how sums are split into FP32
  * partials, so results move by rounding only (each choice is itself
  * deterministic).

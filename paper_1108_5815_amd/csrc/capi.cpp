@@ -2322,33 +2322,30 @@ fmm_status fmm_autotune(fmm_ctx c, int32_t precision, int32_t reps) {
             c->m2l_kind = pick;
             build_classes(c, c->p);
         }
-        // targets per tile of the same-level M2L GEMM, where the storage
-        // width has more than one tiling: the tables are rebuilt on the same
-        // lists for each
-        if (c->gemm_on && c->gp.ntiles > 0 && gemm_tile_width_ok(c_kp(c), 64) && gemm_tile_width_ok(c_kp(c), 128)) {
-            double bestw = INFINITY;
-            int pick = c->gp.nt;
-            for (int nt : {64, 128}) {
-                if (nt != c->gp.nt) gemm_tiles(c, nt);
+        // targets per tile of the same-level M2L GEMM (where the storage
+        // width has more than one tiling; the tables are rebuilt on the same
+        // lists for each) and schedule, timed together: how well the GEMM
+        // shares the chip with a concurrent P2P depends on its tile
+        std::vector<int> widths{0};  // 0: the current tables only
+        if (c->gemm_on && c->gp.ntiles > 0 && gemm_tile_width_ok(c_kp(c), 64) && gemm_tile_width_ok(c_kp(c), 128))
+            widths = {64, 128};
+        double best = INFINITY;
+        int pick = 0, pick_nt = 0;
+        for (int nt : widths) {
+            if (nt != 0 && nt != c->gp.nt) gemm_tiles(c, nt);
+            for (int sc = 0; sc < 3; sc++) {
+                c->schedule = sc;
                 double t = timed([&] { evaluate_impl(c, precision, FMM_F32, o, o + c->n, o + 2 * c->n, o + 3 * c->n); });
-                if (t < bestw) {
-                    bestw = t;
-                    pick = nt;
+                if (t < best) {
+                    best = t;
+                    pick = sc;
+                    pick_nt = nt;
                 }
             }
-            if (pick != c->gp.nt) gemm_tiles(c, pick);
-            c->gemm_nt = pick;
         }
-        // schedule: P2P concurrent with the far field, or everything in order
-        double best = INFINITY;
-        int pick = 0;
-        for (int sc = 0; sc < 3; sc++) {
-            c->schedule = sc;
-            double t = timed([&] { evaluate_impl(c, precision, FMM_F32, o, o + c->n, o + 2 * c->n, o + 3 * c->n); });
-            if (t < best) {
-                best = t;
-                pick = sc;
-            }
+        if (pick_nt != 0) {
+            if (pick_nt != c->gp.nt) gemm_tiles(c, pick_nt);
+            c->gemm_nt = pick_nt;
         }
         c->timing = timing;
         c->schedule = pick;
