@@ -182,8 +182,8 @@ struct GemmPlan;
 // pairs as emitted, (target, source)); slot: per pair, its slot or -1.
 //   slot_of   lookup table [8][(2R+1)^3] (offset -> slot or -1)
 //   rowof     [ncell] tile * NT + column of the target's GEMM row, or -1
-//   gather    [ntiles][J][NT] source cell or -1 (per tile and slot, the
-//             tile's NT columns contiguous; padding columns stay -1)
+//   gather    [ntiles][NT][J] source cell or -1 (per tile and column, the
+//             column's J slots contiguous; absent entries stay -1)
 void m2l_mark_targets(const int2* pairs, int64_t n, CellArrays cells, const int32_t* slot_of, int R,
                       uint32_t* has_fast, int16_t* slot, hipStream_t s);
 void m2l_fill_gather(const int2* pairs, const int16_t* slot, int64_t n, const int32_t* rowof, int32_t J, int NT,

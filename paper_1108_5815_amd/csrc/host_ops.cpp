@@ -431,7 +431,9 @@ void build_m2l_plan(int p, double theta, M2LPlan& plan, bool cartesian) {
                 int o2 = o[0] * o[0] + o[1] * o[1] + o[2] * o[2];
                 if (1.0 <= theta2 * (double)o2) L.push_back(o);
             }
-        std::sort(L.begin(), L.end());
+        // slots in generation order: the (up to) eight children of one parent
+        // offset are consecutive, so the M2L pairs of one target and one
+        // split source parent fill neighbouring entries of the gather table
         per[ct] = L;
         if (ct == 0) plan.J = (int)L.size();
         if ((int)L.size() != plan.J) throw std::runtime_error("asymmetric offset classes");

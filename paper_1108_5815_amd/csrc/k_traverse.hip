@@ -368,8 +368,7 @@ __global__ void k_fill_gather(const int2* __restrict__ pairs, const int16_t* __r
     const int2 pr = pairs[i];  // read with the slot: almost every pair is in the tables
     if (sl >= 0) {
         const int32_t pr_row = rowof[pr.x];  // tile * NT + column
-        const int32_t tile = pr_row / NT;
-        gather[((int64_t)tile * J + sl) * NT + (pr_row - tile * NT)] = pr.y;
+        gather[(int64_t)pr_row * J + sl] = pr.y;
     }
 }
 
@@ -410,39 +409,33 @@ __global__ void k_rows_inverse(const uint32_t* __restrict__ rowcell, int64_t nro
 __global__ __launch_bounds__(256) void k_tile_slots(const int32_t* __restrict__ gather, GemmPlan plan, int NT,
                                                     int32_t* __restrict__ act, int32_t* __restrict__ nact) {
     __shared__ int32_t wtot[4];
-    __shared__ uint8_t used[256];
     const int tile = blockIdx.x;
     const int J = plan.J;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    const int32_t* gt = gather + (size_t)tile * J * NT;  // [slot][NT] of this tile
+    const int32_t* gt = gather + (size_t)tile * NT * J;  // [NT][J] of this tile
     int base = 0;
     for (int j0 = 0; j0 < J; j0 += 256) {
-        // slot j is used if any of the tile's NT (64 or 128) entries is a
-        // source (padding is -1): each wave tests whole slots with coalesced
-        // reads, eight slots' reads in flight at once
-        for (int jb = w; jb < 256; jb += 32) {
-            int32_t v[8];
+        // slot j is used if any of the tile's NT (64 or 128) columns holds a
+        // source (padding is -1): each thread tests one slot, the block reads
+        // a column's slots coalesced, eight columns' reads in flight at once
+        const int j = j0 + (int)threadIdx.x;
+        bool a = false;
+        if (j < J) {
+            for (int c0 = 0; c0 < NT; c0 += 8) {
+                int32_t v[8];
 #pragma unroll
-            for (int u = 0; u < 8; u++) {
-                const int j = j0 + jb + 4 * u;
-                const int32_t* row = gt + (size_t)j * NT;
-                v[u] = j < J ? (NT > 64 ? max(row[lane], row[64 + lane]) : row[lane]) : -1;
-            }
+                for (int u = 0; u < 8; u++) v[u] = gt[(size_t)(c0 + u) * J + j];
 #pragma unroll
-            for (int u = 0; u < 8; u++) {
-                const uint64_t m = __ballot(v[u] >= 0);
-                if (lane == 0) used[jb + 4 * u] = m != 0ull;
+                for (int u = 0; u < 8; u++) a = a || v[u] >= 0;
             }
         }
-        __syncthreads();
-        const bool a = used[threadIdx.x] != 0;
         const uint64_t m = __ballot(a);
         if (lane == 0) wtot[w] = __popcll(m);
         __syncthreads();
         int off = base;
         for (int q = 0; q < w; q++) off += wtot[q];
-        if (a) act[(size_t)tile * J + off + __popcll(m & below)] = j0 + (int)threadIdx.x;
+        if (a) act[(size_t)tile * J + off + __popcll(m & below)] = j;
         base += wtot[0] + wtot[1] + wtot[2] + wtot[3];
         __syncthreads();
     }
