@@ -117,7 +117,7 @@ struct fmm_ctx_s {
     Buf m2pflag;         // per leaf: cell-particle sources on the leaf or an ancestor
     Buf m2lslot;         // per cell-cell pair: its GEMM slot or -1
     Buf tbounds;         // tree build: octant boundaries of the cells of a level
-    Buf has_fast, rkey, rval, rkey2, rval2, rowof, gather, gtg, gsr, goff, tact, tnact, m2l_part, Msplit, nbucket, kinds;
+    Buf has_fast, rkey, rval, rkey2, rval2, rowof, gather, gathercol, gtg, gsr, goff, tact, tnact, m2l_part, Msplit, nbucket, kinds;
     // pairs outside the same-level tables, batched by class
     ClsPlan cp;
     Buf ckey, ckey2, cval, cval2, chead, choff, cstart, cpos, csrcs, cnt_t, ctbase, ctile, cT, cskip, cls_part;
@@ -161,7 +161,7 @@ struct fmm_ctx_s {
                       &c_nchild, &c_level, &c_prefix, &c_geo, &c_ctr, &leaves, &tmp1, &tmp2, &fr0, &fr1,
                       &cnt, &off4, &raw[0], &raw[1], &raw[2], &tgt[0], &tgt[1], &tgt[2], &src[0], &src[1],
                       &src[2], &off[0], &off[1], &off[2], &tgt2, &src2, &d_slot, &d_offid, &d_T, &has_fast,
-                      &rkey, &rval, &rkey2, &rval2, &rowof, &gather, &gtg, &gsr, &goff, &d_m2m, &d_l2l, &d_w, &d_g,
+                      &rkey, &rval, &rkey2, &rval2, &rowof, &gather, &gathercol, &gtg, &gsr, &goff, &d_m2m, &d_l2l, &d_w, &d_g,
                       &d_h, &d_rc, &d_mlp, &M, &L, &nearb, &tune_pts, &tune_out, &d_mlp_m, &d_mlp_v,
                       &d_grad, &d_grad_rec, &d_loss_rec, &d_feat, &d_kind, &d_tgt, &d_table, &d_Thi, &d_Tlo,
                       &d_seg, &d_bt, &d_pb, &d_box, &d_frame, &inst, &bsort, &tact, &tnact,
@@ -730,15 +730,16 @@ void gemm_tiles(fmm_ctx c, int tc) {
     fill_i32(ro, -1, nc, s);
     rows_inverse((const uint32_t*)c->rval.p, c->nrows, c->gp, tc, ro, s);
     const int64_t ngather = (int64_t)tiles * tc * J;
+    int32_t* gcol = need<int32_t>(c, c->gathercol, (size_t)std::max<int64_t>(ngather, 1));
     int32_t* ga = need<int32_t>(c, c->gather, (size_t)std::max<int64_t>(ngather, 1));
-    fill_i32(ga, -1, ngather, s);
-    m2l_fill_gather((const int2*)c->raw[0].p, (const int16_t*)c->m2lslot.p, c->nlist[0], ro, J, tc, ga, s);
+    fill_i32(gcol, -1, ngather, s);
+    m2l_fill_gather((const int2*)c->raw[0].p, (const int16_t*)c->m2lslot.p, c->nlist[0], ro, J, tc, gcol, s);
     check_launch("m2l gather");
     int32_t* act = need<int32_t>(c, c->tact, (size_t)std::max(tiles, 1) * J);
     int32_t* nact = need<int32_t>(c, c->tnact, (size_t)std::max(tiles, 1));
     c->gp.act = act;
     c->gp.nact = nact;
-    tile_slots(ga, c->gp, tc, tiles, act, nact, s);
+    tile_transpose(gcol, c->gp, tc, tiles, ga, act, nact, s);
     check_launch("m2l tile slots");
 }
 

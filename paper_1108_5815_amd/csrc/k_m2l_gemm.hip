@@ -121,14 +121,14 @@ __global__ __launch_bounds__(64 * RW * CW) void k_m2l_gemm(const float* __restri
     // complete in issue order, and a load count that depends on the path
     // would force the wait for one operator chunk to drain every later load.
     f32x4 breg[BV];
-    // gathered sources: the tile's source indices (gather[tile][NT][J], a
-    // column's slots contiguous, absent entries -1) are loaded one slot
+    // gathered sources: the tile's source indices of a slot are contiguous
+    // (gather[tile][slot][NT], padding columns -1) and are loaded one slot
     // before the data; the data loads read the zero row for absent sources
     int sidx[BV];
     auto load_idx = [&](int i) {
-        const int32_t* gk = gather + (size_t)tile * NT * J + s_slot[min(i, n - 1)];
+        const int32_t* gk = gather + ((size_t)tile * J + s_slot[min(i, n - 1)]) * NT;
 #pragma unroll
-        for (int v = 0; v < BV; v++) sidx[v] = gk[(size_t)((threadIdx.x + NTH * v) / (KP / 4)) * J];
+        for (int v = 0; v < BV; v++) sidx[v] = gk[(threadIdx.x + NTH * v) / (KP / 4)];
     };
     auto load_data = [&]() {
 #pragma unroll

@@ -402,41 +402,49 @@ __global__ void k_rows_inverse(const uint32_t* __restrict__ rowcell, int64_t nro
     rowof[rowcell[r]] = tile * NT + local % NT;
 }
 
-// Active slots of each GEMM tile (NT consecutive rows of one octant class):
-// the slots at which at least one row of the tile has a same-level source, in
-// slot order.  The GEMM runs over these only; a slot no row uses would add a
-// zero column block.
-__global__ __launch_bounds__(256) void k_tile_slots(const int32_t* __restrict__ gather, GemmPlan plan, int NT,
-                                                    int32_t* __restrict__ act, int32_t* __restrict__ nact) {
-    __shared__ int32_t wtot[4];
+// Gather table of each GEMM tile (NT consecutive rows of one octant class)
+// from column order ([NT][J], as the fill writes it: the pairs one split
+// parent pair emits for one target are neighbouring slots of its column) to
+// slot order ([J][NT], as the GEMM reads it: a slot's NT sources in one
+// read), through LDS in chunks of 64 slots, both sides coalesced; and the
+// tile's active slots (at least one column holds a source), in slot order.
+// The GEMM runs over these only; a slot no row uses would add a zero block.
+__global__ __launch_bounds__(256) void k_tile_transpose(const int32_t* __restrict__ gcol, GemmPlan plan, int NT,
+                                                        int32_t* __restrict__ gather, int32_t* __restrict__ act,
+                                                        int32_t* __restrict__ nact) {
+    __shared__ int32_t blk[128][65];  // [column][slot of the chunk], padded against bank conflicts
+    __shared__ uint8_t used[64];
     const int tile = blockIdx.x;
     const int J = plan.J;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    const int32_t* gt = gather + (size_t)tile * NT * J;  // [NT][J] of this tile
-    int base = 0;
-    for (int j0 = 0; j0 < J; j0 += 256) {
-        // slot j is used if any of the tile's NT (64 or 128) columns holds a
-        // source (padding is -1): each thread tests one slot, the block reads
-        // a column's slots coalesced, eight columns' reads in flight at once
-        const int j = j0 + (int)threadIdx.x;
-        bool a = false;
-        if (j < J) {
-            for (int c0 = 0; c0 < NT; c0 += 8) {
-                int32_t v[8];
-#pragma unroll
-                for (int u = 0; u < 8; u++) v[u] = gt[(size_t)(c0 + u) * J + j];
-#pragma unroll
-                for (int u = 0; u < 8; u++) a = a || v[u] >= 0;
-            }
+    const int32_t* src = gcol + (size_t)tile * NT * J;
+    int32_t* dst = gather + (size_t)tile * J * NT;
+    int base = 0;  // meaningful in wave 0, which compacts
+    for (int j0 = 0; j0 < J; j0 += 64) {
+        const int nj = min(64, J - j0);
+        for (int e = threadIdx.x; e < NT * 64; e += 256) {
+            const int c = e >> 6, jj = e & 63;
+            blk[c][jj] = jj < nj ? src[(size_t)c * J + j0 + jj] : -1;
         }
-        const uint64_t m = __ballot(a);
-        if (lane == 0) wtot[w] = __popcll(m);
         __syncthreads();
-        int off = base;
-        for (int q = 0; q < w; q++) off += wtot[q];
-        if (a) act[(size_t)tile * J + off + __popcll(m & below)] = j;
-        base += wtot[0] + wtot[1] + wtot[2] + wtot[3];
+        for (int e = threadIdx.x; e < nj * NT; e += 256) {
+            const int jj = e / NT, c = e - jj * NT;
+            dst[(size_t)(j0 + jj) * NT + c] = blk[c][jj];
+        }
+        for (int jj = w; jj < 64; jj += 4) {
+            bool a = false;
+            for (int c = lane; c < NT; c += 64) a = a || blk[c][jj] >= 0;
+            const uint64_t m = __ballot(a);
+            if (lane == 0) used[jj] = (jj < nj && m != 0ull) ? 1 : 0;
+        }
+        __syncthreads();
+        if (w == 0) {
+            const bool a = used[lane] != 0;
+            const uint64_t m = __ballot(a);
+            if (a) act[(size_t)tile * J + base + __popcll(m & below)] = j0 + lane;
+            base += __popcll(m);
+        }
         __syncthreads();
     }
     if (threadIdx.x == 0) nact[tile] = base;
@@ -484,10 +492,10 @@ void m2l_mark_targets(const int2* pairs, int64_t n, CellArrays cells, const int3
     k_mark_targets<<<grid(n), 256, 0, s>>>(pairs, n, cells, slot_of, R, has_fast, slot);
 }
 
-void tile_slots(const int32_t* gather, GemmPlan plan, int NT, int ntiles, int32_t* act, int32_t* nact,
-                hipStream_t s) {
+void tile_transpose(const int32_t* gcol, GemmPlan plan, int NT, int ntiles, int32_t* gather, int32_t* act,
+                    int32_t* nact, hipStream_t s) {
     if (ntiles <= 0) return;
-    k_tile_slots<<<ntiles, 256, 0, s>>>(gather, plan, NT, act, nact);
+    k_tile_transpose<<<ntiles, 256, 0, s>>>(gcol, plan, NT, gather, act, nact);
 }
 
 void m2l_fill_gather(const int2* pairs, const int16_t* slot, int64_t n, const int32_t* rowof, int32_t J, int NT,
