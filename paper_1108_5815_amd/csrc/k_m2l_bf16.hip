@@ -312,12 +312,12 @@ void m2l_gemm_bf16(const uint16_t* Thi, const uint16_t* Tlo, const int32_t* offi
     switch (KP) {
         case 32: launch<32, 128, 1, 4, 2>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
         case 64: launch<64, 128, 2, 2, 2>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
-        case 96: launch<96, 128, 3, 4, 2>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
+        case 96: launch<96, 128, 3, 2, 3, 2>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
         case 128:
             if (plan.nt == 128) launch<128, 128, 4, 1, 2, 2>(Thi, Tlo, offid, gather, plan, Ms, part, s);
             else launch<128, 64, 4, 1, 2, 2>(Thi, Tlo, offid, gather, plan, Ms, part, s);
             break;
-        case 192: launch<192, 64, 2, 2, 4>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
+        case 192: launch<192, 64, 6, 1, 3, 2>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
         default: return;
     }
     if (e1) (void)hipEventRecord(e1, s);
