@@ -312,6 +312,10 @@ int gemm_slot_groups(int J);
 // a group holds at most J / G + 1 slots (65 with G = 8 ceil(J / 512)); the GEMM
 // kernels stage a group's slots and operator ids in LDS arrays of this size
 constexpr int kGemmMaxGroupSlots = 80;
+// split-BF16 GEMM: K steps (16 coefficients each) below this one hold
+// multipole coefficients of degree < 8 and take all three BF16 products; the
+// later steps drop a_lo b_hi (degree >= 8: k >= 64)
+constexpr int kBf16FullSteps = 4;
 // gather[tile][J][NT] from the filled gcol[tile][NT][J], and act[tile * J + k],
 // k < nact[tile]: the slots of tile `tile` that some row uses; NT (the tile
 // width from gemm_tile_cols) is 64 or 128

@@ -8,7 +8,13 @@
 // products on v_mfma_f32_32x32x16_bf16 with FP32 accumulation:
 //     a b ~ a_hi b_hi + a_hi b_lo + a_lo b_hi
 // The dropped a_lo b_lo term and the residual of the two-term split bound
-// the relative error of each product by about 2^-16.  The operators are split
+// the relative error of each product by about 2^-16.  For multipole
+// coefficients of degree 8 and up (index k >= 64) a_lo b_hi is dropped too
+// (two products, error 2^-9 of the product): summed over the local degrees,
+// a degree-n multipole term is of order x^n / (1 - x)^(n + 1) of the pair's
+// leading term, x the ratio of cell size to distance (about theta / 2 for the
+// pairs of these tables), the same decay that makes the expansion converge,
+// so those products carry only a small share of the result.  The operators are split
 // once on the host and stored k-blocked ([offset][KP/8][KP][8] bf16) so that
 // a lane's 8 consecutive K values for its row are one 16-byte load.  The
 // multipoles are split once per evaluation (k_split_cells: [cell][hi, lo]
@@ -152,85 +158,100 @@ __global__ __launch_bounds__(64 * RW * CW * KSP) void k_m2l_bf16(const uint4* __
     constexpr int SC = KSW / NQ;
     static_assert(KSW % NQ == 0, "slot parts");
     u32x4 ah[2][NRB][SC], al[2][NRB][SC];
-    auto load_A = [&](int op, int half, int buf) {
-        const size_t base = (size_t)op * KB * KP;
+
+    // The wave's loop, compiled once per half of K so that every step's
+    // product set is fixed at compile time (WK: the wave's half).
+    auto run = [&](auto WKc) {
+        constexpr int WK = decltype(WKc)::value;
+        auto load_A = [&](int op, int half, int buf) {
+            const size_t base = (size_t)op * KB * KP;
 #pragma unroll
-        for (int r = 0; r < NRB; r++)
+            for (int r = 0; r < NRB; r++)
+#pragma unroll
+                for (int s = 0; s < SC; s++) {
+                    const int st = WK * KSW + half * SC + s;
+                    const size_t ix = base + (size_t)(2 * st + h) * KP + (wr + RW * r) * 32 + l32;
+                    ah[buf][r][s] = reinterpret_cast<const u32x4*>(Thi)[ix];
+                    if (st < kBf16FullSteps) al[buf][r][s] = reinterpret_cast<const u32x4*>(Tlo)[ix];
+                }
+        };
+        auto compute = [&](int bbuf, int half, int abuf) {
 #pragma unroll
             for (int s = 0; s < SC; s++) {
-                const size_t ix = base + (size_t)(2 * (wk * KSW + half * SC + s) + h) * KP + (wr + RW * r) * 32 + l32;
-                ah[buf][r][s] = reinterpret_cast<const u32x4*>(Thi)[ix];
-                al[buf][r][s] = reinterpret_cast<const u32x4*>(Tlo)[ix];
+                const int st = WK * KSW + half * SC + s;
+#pragma unroll
+                for (int b = 0; b < NCB; b++) {
+                    const int col = (wc + CW * b) * 32 + l32;
+                    const u32x4 bh = Bs[bbuf][col * STR + 2 * st + h];
+                    const u32x4 bl = Bs[bbuf][HL + col * STR + 2 * st + h];
+                    const bf16x8 vbh = __builtin_bit_cast(bf16x8, bh);
+                    const bf16x8 vbl = __builtin_bit_cast(bf16x8, bl);
+#pragma unroll
+                    for (int i = 0; i < NRB; i++) {
+                        const bf16x8 vah = __builtin_bit_cast(bf16x8, ah[abuf][i][s]);
+                        acc[i][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vah, vbh, acc[i][b], 0, 0, 0);
+                        acc[i][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vah, vbl, acc[i][b], 0, 0, 0);
+                        if (st < kBf16FullSteps) {
+                            const bf16x8 val = __builtin_bit_cast(bf16x8, al[abuf][i][s]);
+                            acc[i][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(val, vbh, acc[i][b], 0, 0, 0);
+                        }
+                    }
+                }
             }
-    };
-    auto compute = [&](int bbuf, int half, int abuf) {
+        };
+
+        // slot i of the group; P0 = register buffer of its first part (buffers
+        // alternate by part, so with an odd number of parts the slots alternate
+        // too).  The next slot's gathers (the slowest loads) are issued after
+        // this slot's second operator part, so waiting for that part does not
+        // wait for them; they are needed only at the slot's end.
+        auto slot = [&](int i, auto P0) {
+            constexpr int p0 = decltype(P0)::value;
+            const int bb = i & 1;
+            const int op = s_op[i], op_next = s_op[min(i + 1, n - 1)];
 #pragma unroll
-        for (int s = 0; s < SC; s++) {
-            const int st = wk * KSW + half * SC + s;
-#pragma unroll
-            for (int b = 0; b < NCB; b++) {
-                const int col = (wc + CW * b) * 32 + l32;
-                const u32x4 bh = Bs[bbuf][col * STR + 2 * st + h];
-                const u32x4 bl = Bs[bbuf][HL + col * STR + 2 * st + h];
-                const bf16x8 vbh = __builtin_bit_cast(bf16x8, bh);
-                const bf16x8 vbl = __builtin_bit_cast(bf16x8, bl);
-#pragma unroll
-                for (int i = 0; i < NRB; i++) {
-                    const bf16x8 vah = __builtin_bit_cast(bf16x8, ah[abuf][i][s]);
-                    const bf16x8 val = __builtin_bit_cast(bf16x8, al[abuf][i][s]);
-                    acc[i][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vah, vbh, acc[i][b], 0, 0, 0);
-                    acc[i][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vah, vbl, acc[i][b], 0, 0, 0);
-                    acc[i][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(val, vbh, acc[i][b], 0, 0, 0);
+            for (int q = 0; q < NQ; q++) {
+                if (q + 1 < NQ) load_A(op, q + 1, (p0 + q + 1) & 1);
+                else load_A(op_next, 0, (p0 + q + 1) & 1);
+                if (q == 0) {
+                    load_data();      // slot i + 1 (indices loaded during slot i - 1)
+                    load_idx(i + 2);
+                }
+                // keep the loads ahead of this part's products (the scheduler
+                // would otherwise sink each load next to its first use); a wave
+                // issuing products is favoured over waves issuing loads (about 1%
+                // on the 4M-point Plummer lists)
+                __builtin_amdgcn_sched_barrier(0);
+                __builtin_amdgcn_s_setprio(1);
+                compute(bb, q, (p0 + q) & 1);
+                __builtin_amdgcn_s_setprio(0);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            store_B(bb ^ 1);          // past the last slot: a copy nobody reads
+            __syncthreads();
+        };
+        if (n > 0) {
+            load_idx(0);
+            load_data();
+            store_B(0);
+            load_idx(1);
+            load_A(s_op[0], 0, 0);
+            __syncthreads();
+            if constexpr (NQ % 2 == 0) {
+                for (int i = 0; i < n; i++) slot(i, std::integral_constant<int, 0>{});
+            } else {
+                for (int i = 0; i < n; i += 2) {
+                    slot(i, std::integral_constant<int, 0>{});
+                    if (i + 1 < n) slot(i + 1, std::integral_constant<int, 1>{});
                 }
             }
         }
     };
-
-    // slot i of the group; P0 = register buffer of its first part (buffers
-    // alternate by part, so with an odd number of parts the slots alternate
-    // too).  The next slot's gathers (the slowest loads) are issued after
-    // this slot's second operator part, so waiting for that part does not
-    // wait for them; they are needed only at the slot's end.
-    auto slot = [&](int i, auto P0) {
-        constexpr int p0 = decltype(P0)::value;
-        const int bb = i & 1;
-        const int op = s_op[i], op_next = s_op[min(i + 1, n - 1)];
-#pragma unroll
-        for (int q = 0; q < NQ; q++) {
-            if (q + 1 < NQ) load_A(op, q + 1, (p0 + q + 1) & 1);
-            else load_A(op_next, 0, (p0 + q + 1) & 1);
-            if (q == 0) {
-                load_data();      // slot i + 1 (indices loaded during slot i - 1)
-                load_idx(i + 2);
-            }
-            // keep the loads ahead of this part's products (the scheduler
-            // would otherwise sink each load next to its first use); a wave
-            // issuing products is favoured over waves issuing loads (about 1%
-            // on the 4M-point Plummer lists)
-            __builtin_amdgcn_sched_barrier(0);
-            __builtin_amdgcn_s_setprio(1);
-            compute(bb, q, (p0 + q) & 1);
-            __builtin_amdgcn_s_setprio(0);
-            __builtin_amdgcn_sched_barrier(0);
-        }
-        store_B(bb ^ 1);          // past the last slot: a copy nobody reads
-        __syncthreads();
-    };
-    if (n > 0) {
-        load_idx(0);
-        load_data();
-        store_B(0);
-        load_idx(1);
-        load_A(s_op[0], 0, 0);
-        __syncthreads();
-        if constexpr (NQ % 2 == 0) {
-            for (int i = 0; i < n; i++) slot(i, std::integral_constant<int, 0>{});
-        } else {
-            for (int i = 0; i < n; i += 2) {
-                slot(i, std::integral_constant<int, 0>{});
-                if (i + 1 < n) slot(i + 1, std::integral_constant<int, 1>{});
-            }
-        }
+    if constexpr (KSP == 2) {
+        if (wk == 0) run(std::integral_constant<int, 0>{});
+        else run(std::integral_constant<int, 1>{});
+    } else {
+        run(std::integral_constant<int, 0>{});
     }
     if constexpr (KSP == 2) {
         // the second half of K adds its sums to the first's through the LDS
