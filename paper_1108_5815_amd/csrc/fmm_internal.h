@@ -312,10 +312,12 @@ int gemm_slot_groups(int J);
 // a group holds at most J / G + 1 slots (65 with G = 8 ceil(J / 512)); the GEMM
 // kernels stage a group's slots and operator ids in LDS arrays of this size
 constexpr int kGemmMaxGroupSlots = 80;
-// split-BF16 GEMM: K steps (16 coefficients each) below this one hold
-// multipole coefficients of degree < 8 and take all three BF16 products; the
-// later steps drop a_lo b_hi (degree >= 8: k >= 64)
-constexpr int kBf16FullSteps = 4;
+// split-BF16 GEMM, by K step (16 multipole coefficients each): steps below
+// kBf16FullSteps (k < 32, degrees 0-5) take all three BF16 products, steps
+// below kBf16TwoSteps (k < 96) drop a_lo b_hi, and the rest (k >= 96,
+// degrees 9 and up) keep a_hi b_hi alone
+constexpr int kBf16FullSteps = 2;
+constexpr int kBf16TwoSteps = 6;
 // gather[tile][J][NT] from the filled gcol[tile][NT][J], and act[tile * J + k],
 // k < nact[tile]: the slots of tile `tile` that some row uses; NT (the tile
 // width from gemm_tile_cols) is 64 or 128

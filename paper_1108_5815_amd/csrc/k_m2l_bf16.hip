@@ -8,13 +8,14 @@
 // products on v_mfma_f32_32x32x16_bf16 with FP32 accumulation:
 //     a b ~ a_hi b_hi + a_hi b_lo + a_lo b_hi
 // The dropped a_lo b_lo term and the residual of the two-term split bound
-// the relative error of each product by about 2^-16.  For multipole
-// coefficients of degree 8 and up (index k >= 64) a_lo b_hi is dropped too
-// (two products, error 2^-9 of the product): summed over the local degrees,
-// a degree-n multipole term is of order x^n / (1 - x)^(n + 1) of the pair's
+// the relative error of each product by about 2^-16.  The precision is
+// graded by multipole degree: coefficients k >= 32 (degrees 5 and up) drop
+// a_lo b_hi (two products, error 2^-9 of the product), and k >= 96 (degrees 9
+// and up) keep a_hi b_hi alone (about 2^-8).  Summed over the local degrees, a
+// degree-n multipole term is of order x^n / (1 - x)^(n + 1) of the pair's
 // leading term, x the ratio of cell size to distance (about theta / 2 for the
 // pairs of these tables), the same decay that makes the expansion converge,
-// so those products carry only a small share of the result.  The operators are split
+// so the coarser products carry only a small share of the result.  The operators are split
 // once on the host and stored k-blocked ([offset][KP/8][KP][8] bf16) so that
 // a lane's 8 consecutive K values for its row are one 16-byte load.  The
 // multipoles are split once per evaluation (k_split_cells: [cell][hi, lo]
@@ -183,14 +184,15 @@ __global__ __launch_bounds__(64 * RW * CW * KSP) void k_m2l_bf16(const uint4* __
                 for (int b = 0; b < NCB; b++) {
                     const int col = (wc + CW * b) * 32 + l32;
                     const u32x4 bh = Bs[bbuf][col * STR + 2 * st + h];
-                    const u32x4 bl = Bs[bbuf][HL + col * STR + 2 * st + h];
                     const bf16x8 vbh = __builtin_bit_cast(bf16x8, bh);
-                    const bf16x8 vbl = __builtin_bit_cast(bf16x8, bl);
+                    bf16x8 vbl{};
+                    if (st < kBf16TwoSteps) vbl = __builtin_bit_cast(bf16x8, Bs[bbuf][HL + col * STR + 2 * st + h]);
 #pragma unroll
                     for (int i = 0; i < NRB; i++) {
                         const bf16x8 vah = __builtin_bit_cast(bf16x8, ah[abuf][i][s]);
                         acc[i][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vah, vbh, acc[i][b], 0, 0, 0);
-                        acc[i][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vah, vbl, acc[i][b], 0, 0, 0);
+                        if (st < kBf16TwoSteps)
+                            acc[i][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vah, vbl, acc[i][b], 0, 0, 0);
                         if (st < kBf16FullSteps) {
                             const bf16x8 val = __builtin_bit_cast(bf16x8, al[abuf][i][s]);
                             acc[i][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(val, vbh, acc[i][b], 0, 0, 0);
