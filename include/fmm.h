@@ -67,7 +67,7 @@ typedef enum {
     FMM_PREC_SPLIT_BF16 = 1  /* as FP32, but same-level M2L as BF16 products on the
                                 matrix cores with FP32 accumulation, graded by multipole
                                 degree: hi*hi + hi*lo + lo*hi for coefficient index
-                                k < 32, hi*hi + hi*lo below 96, hi*hi above; p <= 12 */
+                                k < 32, hi*hi + hi*lo below 48, hi*hi above; p <= 12 */
 } fmm_precision;
 /* There is no FP64 evaluation form: FP64 inputs and outputs are accepted
  * (FMM_F64), the quantisation and the per-target final sum are FP64, and the

@@ -314,10 +314,10 @@ int gemm_slot_groups(int J);
 constexpr int kGemmMaxGroupSlots = 80;
 // split-BF16 GEMM, by K step (16 multipole coefficients each): steps below
 // kBf16FullSteps (k < 32, degrees 0-5) take all three BF16 products, steps
-// below kBf16TwoSteps (k < 96) drop a_lo b_hi, and the rest (k >= 96,
-// degrees 9 and up) keep a_hi b_hi alone
+// below kBf16TwoSteps (k < 48) drop a_lo b_hi, and the rest (k >= 48,
+// degrees 6 and up) keep a_hi b_hi alone
 constexpr int kBf16FullSteps = 2;
-constexpr int kBf16TwoSteps = 6;
+constexpr int kBf16TwoSteps = 3;
 // gather[tile][J][NT] from the filled gcol[tile][NT][J], and act[tile * J + k],
 // k < nact[tile]: the slots of tile `tile` that some row uses; NT (the tile
 // width from gemm_tile_cols) is 64 or 128

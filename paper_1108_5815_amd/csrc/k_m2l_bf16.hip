@@ -10,7 +10,7 @@
 // The dropped a_lo b_lo term and the residual of the two-term split bound
 // the relative error of each product by about 2^-16.  The precision is
 // graded by multipole degree: coefficients k >= 32 (degrees 5 and up) drop
-// a_lo b_hi (two products, error 2^-9 of the product), and k >= 96 (degrees 9
+// a_lo b_hi (two products, error 2^-9 of the product), and k >= 48 (degrees 6
 // and up) keep a_hi b_hi alone (about 2^-8).  Summed over the local degrees, a
 // degree-n multipole term is of order x^n / (1 - x)^(n + 1) of the pair's
 // leading term, x the ratio of cell size to distance (about theta / 2 for the

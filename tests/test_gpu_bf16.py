@@ -6,7 +6,7 @@ Representing an FP32 value as a sum of two BF16 values keeps 16 significand
 bits: the low multipole degrees (coefficient index k < 32) take hi*hi + hi*lo +
 lo*hi (relative error of order 2^-16 per product), the higher degrees, whose
 share of the result decays like the expansion's terms, take hi*hi + hi*lo
-(k < 96, 2^-9) or hi*hi alone (2^-8); the bar stays the one of the
+(k < 48, 2^-9) or hi*hi alone (2^-8); the bar stays the one of the
 FP32 form: potential within 1e-5 and field within 1e-4 relative L2 of the
 oracle's FMM on the same lists at p = 10, and of the FP64 direct sum at the
 full 4,194,304-particle Plummer size on seeded targets; at p = 12 (storage
