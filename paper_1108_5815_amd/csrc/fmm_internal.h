@@ -318,6 +318,8 @@ constexpr int kGemmMaxGroupSlots = 80;
 // degrees 6 and up) keep a_hi b_hi alone
 constexpr int kBf16FullSteps = 2;
 constexpr int kBf16TwoSteps = 3;
+// lo blocks (8 coefficients each) of a split multipole row that any product reads
+constexpr int kBf16LoBlocks = 2 * kBf16TwoSteps;
 // gather[tile][J][NT] from the filled gcol[tile][NT][J], and act[tile * J + k],
 // k < nact[tile]: the slots of tile `tile` that some row uses; NT (the tile
 // width from gemm_tile_cols) is 64 or 128
@@ -332,7 +334,8 @@ void m2l_gemm(const float* T, const int32_t* offid, const int32_t* gather, const
 bool m2l_gemm_supported(int p);
 bool m2l_gemm_supported_kp(int KP);  // by storage width
 // split-BF16 variant (Thi/Tlo: k-blocked BF16 halves of the operators)
-// Ms: scratch of ncell * KP * 4 bytes for the split multipoles
+// Ms: scratch of (ncell + 1) * split_row_blocks(KP) * 16 bytes (at most
+// KP * 4 bytes a row) for the split multipoles
 void m2l_gemm_bf16(const uint16_t* Thi, const uint16_t* Tlo, const int32_t* offid, const int32_t* gather,
                    const uint32_t* rowcell, GemmPlan plan, int K, int KP, const float* M, int64_t ncell, uint4* Ms,
                    float* part, float* L, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
@@ -341,6 +344,7 @@ void m2l_reduce_groups(const float* part, GemmPlan plan, const uint32_t* rowcell
                        hipStream_t s);
 bool m2l_bf16_supported(int p);
 bool m2l_bf16_supported_kp(int KP);
+int split_row_blocks(int KP);  // 16-byte blocks per split multipole row (0: unsupported width)
 int gemm_tile_cols(int p);  // targets per GEMM tile for order p
 int gemm_tile_cols_kp(int KP);  // the same by storage width
 

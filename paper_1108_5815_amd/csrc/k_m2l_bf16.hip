@@ -18,9 +18,10 @@
 // so the coarser products carry only a small share of the result.  The operators are split
 // once on the host and stored k-blocked ([offset][KP/8][KP][8] bf16) so that
 // a lane's 8 consecutive K values for its row are one 16-byte load.  The
-// multipoles are split once per evaluation (k_split_cells: [cell][hi, lo]
-// [KP/8] blocks of 8 bf16), so staging a gathered source vector into LDS is a
-// plain copy.
+// multipoles are split once per evaluation (k_split_cells: per cell the KP/8
+// hi blocks of 8 bf16 and the lo blocks that products read), so staging a
+// gathered source row into LDS is a plain copy.
+#include <algorithm>
 #include <type_traits>
 
 #include "fmm_internal.h"
@@ -61,6 +62,10 @@ __device__ inline void gemm_item(const GemmPlan& plan, int& tile, int& g) {
     g = (int)(b & 7u) + 8 * (int)(rest / (unsigned)plan.ntiles);
 }
 
+// RS: 16-byte blocks per split multipole row (KP / 8 hi blocks, then the lo
+// blocks of the first kBf16LoBlocks * 8 coefficients, the only low parts a
+// product reads, then padding so that the workgroup's threads share a source
+// row set evenly).
 // Waves: RW row blocks x CW column blocks x KSP parts of K.  With KSP = 2 two
 // waves share each (row block, column block), each summing the products of
 // one half of K, and the halves are added once at the tile's end: a wave
@@ -68,7 +73,7 @@ __device__ inline void gemm_item(const GemmPlan& plan, int& tile, int& g) {
 // tiles of 64 targets run four waves per SIMD (two workgroups of eight per
 // CU), and tiles of 128 load each operator fragment once per workgroup.  A
 // row's sums, and their order, are the same at both widths.
-template <int KP, int NT, int RW, int CW, int NQ, int KSP>
+template <int KP, int NT, int RW, int CW, int NQ, int KSP, int RS>
 __global__ __launch_bounds__(64 * RW * CW * KSP) void k_m2l_bf16(const uint4* __restrict__ Thi, const uint4* __restrict__ Tlo,
                                                   const int32_t* __restrict__ offid,
                                                   const int32_t* __restrict__ gather, GemmPlan plan,
@@ -80,11 +85,14 @@ __global__ __launch_bounds__(64 * RW * CW * KSP) void k_m2l_bf16(const uint4* __
     constexpr int NTH = 64 * RW * CW * KSP;  // lanes of the workgroup
     static_assert(RB % RW == 0 && CB % CW == 0 && KS % KSP == 0, "wave grid");
     constexpr int NRB = RB / RW, NCB = CB / CW;
-    constexpr int STR = KB + 1;         // LDS row stride in 16-byte units
-    constexpr int HL = NT * STR;        // one half (hi or lo) of a source tile
-    constexpr int BV = NT * 2 * KB / NTH;  // 16-byte blocks per thread per source tile (hi and lo)
-    static_assert((NT * 2 * KB) % NTH == 0, "tile shape");
-    __shared__ u32x4 Bs[2][2 * HL];     // [buffer][hi tile, lo tile]
+    constexpr int LB = kBf16LoBlocks < KB ? kBf16LoBlocks : KB;  // lo blocks a product reads
+    constexpr int STR = KB + 1;         // LDS row stride of the hi tile, 16-byte units
+    constexpr int STRL = LB + 1;        // and of the lo tile
+    constexpr int HL = NT * STR;        // the hi tile
+    constexpr int HLL = NT * STRL;      // the lo tile
+    constexpr int BV = NT * RS / NTH;   // 16-byte blocks per thread per source row set
+    static_assert(RS >= KB + LB && (NT * RS) % NTH == 0, "tile shape");
+    __shared__ u32x4 Bs[2][HL + HLL];   // [buffer][hi tile, lo tile]
     __shared__ int32_t s_slot[kGemmMaxGroupSlots], s_op[kGemmMaxGroupSlots];
 
     int tile, g;
@@ -132,24 +140,24 @@ __global__ __launch_bounds__(64 * RW * CW * KSP) void k_m2l_bf16(const uint4* __
     auto load_idx = [&](int i) {
         const int32_t* gk = gather + ((size_t)tile * J + s_slot[min(i, n - 1)]) * NT;
 #pragma unroll
-        for (int v = 0; v < BV; v++) sidx[v] = gk[(threadIdx.x + NTH * v) / (2 * KB)];
+        for (int v = 0; v < BV; v++) sidx[v] = gk[(threadIdx.x + NTH * v) / RS];
     };
     auto load_data = [&]() {
 #pragma unroll
         for (int v = 0; v < BV; v++) {
             const int idx = threadIdx.x + NTH * v;
-            const int col = idx / (2 * KB), rem = idx - col * (2 * KB);
+            const int col = idx / RS, rem = idx - col * RS;
             const int s = sidx[v] >= 0 ? sidx[v] : plan.zcell;
-            breg[v] = reinterpret_cast<const u32x4*>(Ms)[(size_t)s * 2 * KB + rem];
+            breg[v] = reinterpret_cast<const u32x4*>(Ms)[(size_t)s * RS + rem];
         }
     };
     auto store_B = [&](int buf) {
 #pragma unroll
         for (int v = 0; v < BV; v++) {
             const int idx = threadIdx.x + NTH * v;
-            const int col = idx / (2 * KB), rem = idx - col * (2 * KB);
-            const int half = rem >= KB ? 1 : 0;
-            Bs[buf][half * HL + col * STR + rem - half * KB] = breg[v];
+            const int col = idx / RS, rem = idx - col * RS;
+            if (rem < KB) Bs[buf][col * STR + rem] = breg[v];
+            else if (rem < KB + LB) Bs[buf][HL + col * STRL + rem - KB] = breg[v];
         }
     };
     // operator fragments stream through two register buffers in NQ parts of a
@@ -186,7 +194,7 @@ __global__ __launch_bounds__(64 * RW * CW * KSP) void k_m2l_bf16(const uint4* __
                     const u32x4 bh = Bs[bbuf][col * STR + 2 * st + h];
                     const bf16x8 vbh = __builtin_bit_cast(bf16x8, bh);
                     bf16x8 vbl{};
-                    if (st < kBf16TwoSteps) vbl = __builtin_bit_cast(bf16x8, Bs[bbuf][HL + col * STR + 2 * st + h]);
+                    if (st < kBf16TwoSteps) vbl = __builtin_bit_cast(bf16x8, Bs[bbuf][HL + col * STRL + 2 * st + h]);
 #pragma unroll
                     for (int i = 0; i < NRB; i++) {
                         const bf16x8 vah = __builtin_bit_cast(bf16x8, ah[abuf][i][s]);
@@ -291,16 +299,19 @@ __global__ __launch_bounds__(64 * RW * CW * KSP) void k_m2l_bf16(const uint4* __
     }
 }
 
-template <int KP, int NT, int RW, int CW, int NQ, int KSP = 1>
+template <int KP, int NT, int RW, int CW, int NQ, int KSP, int RS>
 void launch(const uint16_t* Thi, const uint16_t* Tlo, const int32_t* offid, const int32_t* gather, GemmPlan plan,
             const uint4* Ms, float* part, hipStream_t s) {
-    k_m2l_bf16<KP, NT, RW, CW, NQ, KSP><<<plan.ntiles * plan.G, 64 * RW * CW * KSP, 0, s>>>(
+    k_m2l_bf16<KP, NT, RW, CW, NQ, KSP, RS><<<plan.ntiles * plan.G, 64 * RW * CW * KSP, 0, s>>>(
         (const uint4*)Thi, (const uint4*)Tlo, offid, gather, plan, Ms, part);
 }
 
-// Multipoles of every cell split into bf16 hi and lo: Ms[cell][0][kb] = hi of
-// coefficients 8 kb .. 8 kb + 7, Ms[cell][1][kb] = lo (round to nearest even).
-__global__ void k_split_cells(const float4* __restrict__ M, int64_t ncell, int KB, uint4* __restrict__ Ms) {
+// Multipoles of every cell split into bf16 hi and lo (round to nearest even):
+// Ms[cell][kb] = hi of coefficients 8 kb .. 8 kb + 7 (kb < KB), then
+// Ms[cell][KB + kb] = lo of the same for kb < LB, then zero blocks up to RS
+// per row.
+__global__ void k_split_cells(const float4* __restrict__ M, int64_t ncell, int KB, int LB, int RS,
+                              uint4* __restrict__ Ms) {
     // ncell rows including the trailing zero row
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ncell * KB) return;
@@ -318,29 +329,48 @@ __global__ void k_split_cells(const float4* __restrict__ M, int64_t ncell, int K
         return make_uint4((uint32_t)v[0] | ((uint32_t)v[1] << 16), (uint32_t)v[2] | ((uint32_t)v[3] << 16),
                           (uint32_t)v[4] | ((uint32_t)v[5] << 16), (uint32_t)v[6] | ((uint32_t)v[7] << 16));
     };
-    Ms[c * 2 * KB + kb] = pack(hi);
-    Ms[c * 2 * KB + KB + kb] = pack(lo);
+    uint4* row = Ms + c * RS;
+    row[kb] = pack(hi);
+    if (kb < LB) row[KB + kb] = pack(lo);
+    if (kb < RS - KB - LB) row[KB + LB + kb] = make_uint4(0u, 0u, 0u, 0u);
 }
 
 }  // namespace
+
+// 16-byte blocks per split multipole row, by storage width (the RS of the
+// launches below): KP / 8 hi blocks and min(kBf16LoBlocks, KP / 8) lo blocks,
+// padded so that every workgroup shape divides a tile's rows evenly
+int split_row_blocks(int KP) {
+    switch (KP) {
+        case 32: return 8;
+        case 64: return 14;
+        case 96: return 18;
+        case 128: return 24;
+        case 192: return 36;
+        default: return 0;
+    }
+}
 
 void m2l_gemm_bf16(const uint16_t* Thi, const uint16_t* Tlo, const int32_t* offid, const int32_t* gather,
                    const uint32_t* rowcell, GemmPlan plan, int K, int KP, const float* M, int64_t ncell, uint4* Ms,
                    float* part, float* L, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     if (plan.ntiles <= 0) return;
     const int KB = KP / 8;
+    const int LB = std::min(kBf16LoBlocks, KB);
+    const int RS = split_row_blocks(KP);
+    if (RS <= 0) return;
     const int64_t nb = (ncell + 1) * KB;  // with the zero row
-    k_split_cells<<<(unsigned)((nb + 255) / 256), 256, 0, s>>>((const float4*)M, ncell + 1, KB, Ms);
+    k_split_cells<<<(unsigned)((nb + 255) / 256), 256, 0, s>>>((const float4*)M, ncell + 1, KB, LB, RS, Ms);
     if (e0) (void)hipEventRecord(e0, s);
     switch (KP) {
-        case 32: launch<32, 128, 1, 4, 2>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
-        case 64: launch<64, 128, 2, 2, 2>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
-        case 96: launch<96, 128, 3, 2, 3, 2>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
+        case 32: launch<32, 128, 1, 4, 2, 1, 8>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
+        case 64: launch<64, 128, 2, 2, 2, 1, 14>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
+        case 96: launch<96, 128, 3, 2, 3, 2, 18>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
         case 128:
-            if (plan.nt == 128) launch<128, 128, 4, 1, 2, 2>(Thi, Tlo, offid, gather, plan, Ms, part, s);
-            else launch<128, 64, 4, 1, 2, 2>(Thi, Tlo, offid, gather, plan, Ms, part, s);
+            if (plan.nt == 128) launch<128, 128, 4, 1, 2, 2, 24>(Thi, Tlo, offid, gather, plan, Ms, part, s);
+            else launch<128, 64, 4, 1, 2, 2, 24>(Thi, Tlo, offid, gather, plan, Ms, part, s);
             break;
-        case 192: launch<192, 64, 6, 1, 3, 2>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
+        case 192: launch<192, 64, 6, 1, 3, 2, 36>(Thi, Tlo, offid, gather, plan, Ms, part, s); break;
         default: return;
     }
     if (e1) (void)hipEventRecord(e1, s);
