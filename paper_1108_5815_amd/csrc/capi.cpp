@@ -730,16 +730,18 @@ void gemm_tiles(fmm_ctx c, int tc) {
     fill_i32(ro, -1, nc, s);
     rows_inverse((const uint32_t*)c->rval.p, c->nrows, c->gp, tc, ro, s);
     const int64_t ngather = (int64_t)tiles * tc * J;
-    int32_t* gcol = need<int32_t>(c, c->gathercol, (size_t)std::max<int64_t>(ngather, 1));
+    const int Jp = (J + 3) & ~3;  // column rows of the fill table, 16-byte aligned
+    const int64_t ncol = (int64_t)tiles * tc * Jp;
+    int32_t* gcol = need<int32_t>(c, c->gathercol, (size_t)std::max<int64_t>(ncol, 1));
     int32_t* ga = need<int32_t>(c, c->gather, (size_t)std::max<int64_t>(ngather, 1));
-    fill_i32(gcol, -1, ngather, s);
-    m2l_fill_gather((const int2*)c->raw[0].p, (const int16_t*)c->m2lslot.p, c->nlist[0], ro, J, tc, gcol, s);
+    fill_i32(gcol, -1, ncol, s);
+    m2l_fill_gather((const int2*)c->raw[0].p, (const int16_t*)c->m2lslot.p, c->nlist[0], ro, Jp, gcol, s);
     check_launch("m2l gather");
     int32_t* act = need<int32_t>(c, c->tact, (size_t)std::max(tiles, 1) * J);
     int32_t* nact = need<int32_t>(c, c->tnact, (size_t)std::max(tiles, 1));
     c->gp.act = act;
     c->gp.nact = nact;
-    tile_transpose(gcol, c->gp, tc, tiles, ga, act, nact, s);
+    tile_transpose(gcol, c->gp, tc, Jp, tiles, ga, act, nact, s);
     check_launch("m2l tile slots");
 }
 

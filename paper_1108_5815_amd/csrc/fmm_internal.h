@@ -182,13 +182,14 @@ struct GemmPlan;
 // pairs as emitted, (target, source)); slot: per pair, its slot or -1.
 //   slot_of   lookup table [8][(2R+1)^3] (offset -> slot or -1)
 //   rowof     [ncell] tile * NT + column of the target's GEMM row, or -1
-//   gather    [ntiles][NT][J] source cell or -1, as filled (per tile and
-//             column, the column's J slots contiguous; absent entries stay
-//             -1); tile_transpose turns it into the GEMM's [ntiles][J][NT]
+//   gather    [ntiles][NT][Jp] source cell or -1, as filled (per tile and
+//             column, the column's slots contiguous, rows of Jp = J rounded
+//             up to a multiple of 4; absent entries stay -1); tile_transpose
+//             turns it into the GEMM's [ntiles][J][NT]
 void m2l_mark_targets(const int2* pairs, int64_t n, CellArrays cells, const int32_t* slot_of, int R,
                       uint32_t* has_fast, int16_t* slot, hipStream_t s);
-void m2l_fill_gather(const int2* pairs, const int16_t* slot, int64_t n, const int32_t* rowof, int32_t J, int NT,
-                     int32_t* gather, hipStream_t s);
+void m2l_fill_gather(const int2* pairs, const int16_t* slot, int64_t n, const int32_t* rowof, int32_t rowlen,
+                     int32_t* gcol, hipStream_t s);
 // row keys of the M2L GEMM: (octant class << kRowMissBits) | missing slots
 // (densest first); cells without same-level pairs get class 8
 constexpr int kRowMissBits = 10;
@@ -320,10 +321,11 @@ constexpr int kBf16FullSteps = 2;
 constexpr int kBf16TwoSteps = 3;
 // lo blocks (8 coefficients each) of a split multipole row that any product reads
 constexpr int kBf16LoBlocks = 2 * kBf16TwoSteps;
-// gather[tile][J][NT] from the filled gcol[tile][NT][J], and act[tile * J + k],
-// k < nact[tile]: the slots of tile `tile` that some row uses; NT (the tile
-// width from gemm_tile_cols) is 64 or 128
-void tile_transpose(const int32_t* gcol, GemmPlan plan, int NT, int ntiles, int32_t* gather, int32_t* act,
+// gather[tile][J][NT] from the filled gcol[tile][NT][Jp] (Jp: J rounded up
+// to a multiple of 4, the padding -1), and act[tile * J + k], k < nact[tile]:
+// the slots of tile `tile` that some row uses; NT (the tile width from
+// gemm_tile_cols) is 64 or 128
+void tile_transpose(const int32_t* gcol, GemmPlan plan, int NT, int Jp, int ntiles, int32_t* gather, int32_t* act,
                     int32_t* nact, hipStream_t s);
 // part: G * nrows * KP floats of per-group partial locals, summed into L in group order
 // e0, e1 (may be null): events recorded just before and after the GEMM kernel

@@ -360,15 +360,16 @@ __global__ __launch_bounds__(256) void k_mark_targets(const int2* __restrict__ p
     if (tail && t >= 0 && v > 0) atomicAdd(&nfast[t], (uint32_t)v);
 }
 
+// gcol[(tile * NT + column) * rowlen + slot] = source of each same-level pair
 __global__ void k_fill_gather(const int2* __restrict__ pairs, const int16_t* __restrict__ slot, int64_t n,
-                              const int32_t* __restrict__ rowof, int32_t J, int NT, int32_t* __restrict__ gather) {
+                              const int32_t* __restrict__ rowof, int32_t rowlen, int32_t* __restrict__ gcol) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int32_t sl = slot[i];
     const int2 pr = pairs[i];  // read with the slot: almost every pair is in the tables
     if (sl >= 0) {
         const int32_t pr_row = rowof[pr.x];  // tile * NT + column
-        gather[(int64_t)pr_row * J + sl] = pr.y;
+        gcol[(int64_t)pr_row * rowlen + sl] = pr.y;
     }
 }
 
@@ -403,34 +404,44 @@ __global__ void k_rows_inverse(const uint32_t* __restrict__ rowcell, int64_t nro
 }
 
 // Gather table of each GEMM tile (NT consecutive rows of one octant class)
-// from column order ([NT][J], as the fill writes it: the pairs one split
-// parent pair emits for one target are neighbouring slots of its column) to
-// slot order ([J][NT], as the GEMM reads it: a slot's NT sources in one
-// read), through LDS in chunks of 64 slots, both sides coalesced; and the
-// tile's active slots (at least one column holds a source), in slot order.
-// The GEMM runs over these only; a slot no row uses would add a zero block.
+// from column order ([NT][Jp], as the fill writes it, Jp = J rounded up to a
+// multiple of 4: the pairs one split parent pair emits for one target are
+// neighbouring slots of its column) to slot order ([J][NT], as the GEMM
+// reads it: a slot's NT sources in one read), through LDS in chunks of 64
+// slots, both sides in 16-byte accesses; and the tile's active slots (at
+// least one column holds a source), in slot order.  The GEMM runs over these
+// only; a slot no row uses would add a zero block.
 __global__ __launch_bounds__(256) void k_tile_transpose(const int32_t* __restrict__ gcol, GemmPlan plan, int NT,
-                                                        int32_t* __restrict__ gather, int32_t* __restrict__ act,
-                                                        int32_t* __restrict__ nact) {
+                                                        int Jp, int32_t* __restrict__ gather,
+                                                        int32_t* __restrict__ act, int32_t* __restrict__ nact) {
     __shared__ int32_t blk[128][65];  // [column][slot of the chunk], padded against bank conflicts
     __shared__ uint8_t used[64];
     const int tile = blockIdx.x;
     const int J = plan.J;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    const int32_t* src = gcol + (size_t)tile * NT * J;
+    const int32_t* src = gcol + (size_t)tile * NT * Jp;
     int32_t* dst = gather + (size_t)tile * J * NT;
+    const int NT4 = NT >> 2;
     int base = 0;  // meaningful in wave 0, which compacts
     for (int j0 = 0; j0 < J; j0 += 64) {
         const int nj = min(64, J - j0);
-        for (int e = threadIdx.x; e < NT * 64; e += 256) {
-            const int c = e >> 6, jj = e & 63;
-            blk[c][jj] = jj < nj ? src[(size_t)c * J + j0 + jj] : -1;
+        // read: 16 quads of slots per column (a quad past Jp reads as absent)
+        for (int e = threadIdx.x; e < NT * 16; e += 256) {
+            const int c = e >> 4, q4 = (e & 15) << 2;
+            int4 v = make_int4(-1, -1, -1, -1);
+            if (j0 + q4 < Jp) v = *reinterpret_cast<const int4*>(src + (size_t)c * Jp + j0 + q4);
+            blk[c][q4] = v.x;
+            blk[c][q4 + 1] = v.y;
+            blk[c][q4 + 2] = v.z;
+            blk[c][q4 + 3] = v.w;
         }
         __syncthreads();
-        for (int e = threadIdx.x; e < nj * NT; e += 256) {
-            const int jj = e / NT, c = e - jj * NT;
-            dst[(size_t)(j0 + jj) * NT + c] = blk[c][jj];
+        // write: per slot of the chunk, NT / 4 quads of columns
+        for (int e = threadIdx.x; e < nj * NT4; e += 256) {
+            const int jj = e / NT4, c4 = (e - jj * NT4) << 2;
+            *reinterpret_cast<int4*>(dst + (size_t)(j0 + jj) * NT + c4) =
+                make_int4(blk[c4][jj], blk[c4 + 1][jj], blk[c4 + 2][jj], blk[c4 + 3][jj]);
         }
         for (int jj = w; jj < 64; jj += 4) {
             bool a = false;
@@ -492,16 +503,16 @@ void m2l_mark_targets(const int2* pairs, int64_t n, CellArrays cells, const int3
     k_mark_targets<<<grid(n), 256, 0, s>>>(pairs, n, cells, slot_of, R, has_fast, slot);
 }
 
-void tile_transpose(const int32_t* gcol, GemmPlan plan, int NT, int ntiles, int32_t* gather, int32_t* act,
+void tile_transpose(const int32_t* gcol, GemmPlan plan, int NT, int Jp, int ntiles, int32_t* gather, int32_t* act,
                     int32_t* nact, hipStream_t s) {
     if (ntiles <= 0) return;
-    k_tile_transpose<<<ntiles, 256, 0, s>>>(gcol, plan, NT, gather, act, nact);
+    k_tile_transpose<<<ntiles, 256, 0, s>>>(gcol, plan, NT, Jp, gather, act, nact);
 }
 
-void m2l_fill_gather(const int2* pairs, const int16_t* slot, int64_t n, const int32_t* rowof, int32_t J, int NT,
-                     int32_t* gather, hipStream_t s) {
+void m2l_fill_gather(const int2* pairs, const int16_t* slot, int64_t n, const int32_t* rowof, int32_t rowlen,
+                     int32_t* gcol, hipStream_t s) {
     if (n <= 0) return;
-    k_fill_gather<<<grid(n), 256, 0, s>>>(pairs, slot, n, rowof, J, NT, gather);
+    k_fill_gather<<<grid(n), 256, 0, s>>>(pairs, slot, n, rowof, rowlen, gcol);
 }
 
 void row_class_keys(const uint32_t* nfast, CellArrays cells, int32_t ncell, int32_t J, uint32_t* key, uint32_t* val,
