@@ -306,11 +306,12 @@ struct GemmPlan {
 // whether the GEMM kernels at storage width KP have a tiling of nt targets
 // per tile (64 or 128 at width 128; the default width elsewhere)
 bool gemm_tile_width_ok(int KP, int nt);
-// slot groups for J slots per class: each group's operators (J/G <= 64
-// blocks of 64 KB at storage width 128; 36 at theta = 0.4) should stay
-// inside one XCD's 4 MB L2, and fewer groups mean fewer partial rows to sum
+// slot groups for J slots per class, a multiple of 8 (group g runs on XCD
+// g mod 8): fewer groups mean fewer partial rows to write and sum, smaller
+// ones keep each group's operators near one XCD's L2; at most 79 slots a
+// group (71 at theta = 0.4, G = 8)
 int gemm_slot_groups(int J);
-// a group holds at most J / G + 1 slots (65 with G = 8 ceil(J / 512)); the GEMM
+// a group holds at most J / G + 1 slots (80 with G = 8 ceil(J / 632)); the GEMM
 // kernels stage a group's slots and operator ids in LDS arrays of this size
 constexpr int kGemmMaxGroupSlots = 80;
 // split-BF16 GEMM, by K step (16 multipole coefficients each): steps below

@@ -282,7 +282,7 @@ bool gemm_tile_width_ok(int KP, int nt) {
     return nt > 0 && nt == gemm_tile_cols_kp(KP);
 }
 
-int gemm_slot_groups(int J) { return 8 * std::max(1, (J + 511) / 512); }
+int gemm_slot_groups(int J) { return 8 * std::max(1, (J + 631) / 632); }
 
 void m2l_reduce_groups(const float* part, GemmPlan plan, const uint32_t* rowcell, int KP, int K, float* L,
                        hipStream_t s) {
