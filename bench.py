@@ -150,19 +150,25 @@ def run_form(f, X, Y, Z, Q, phi, E, w, policy, precision, steps, warmup, args):
             "policy": POLICIES[policy], "precision": PRECISIONS[precision], "prep": prep}
 
 
-KERNEL_SOURCES = {"k_m2l_bf16": "k_m2l_bf16.hip", "k_m2l_gemm": "k_m2l_gemm.hip", "k_p2p": "k_p2p.hip"}
+# sources a kernel's recorded traffic depends on (the GEMM kernels' slot
+# groups are set in k_m2l_gemm.hip)
+KERNEL_SOURCES = {"k_m2l_bf16": ("k_m2l_bf16.hip", "k_m2l_gemm.hip"), "k_m2l_gemm": ("k_m2l_gemm.hip",),
+                  "k_p2p": ("k_p2p.hip",)}
 
 
 def measured_traffic(kernel, workload):
     """HBM bytes per launch from the committed hardware-counter summary
     (profiles/fmm_<workload>_traffic.md), or None when there is none or the
-    kernel's source changed since the counters were taken."""
+    kernel's sources changed since the counters were taken (the recorded key is
+    the SHA-256 of those source files, concatenated in order)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"fmm_{workload}_traffic.md")
     if kernel not in KERNEL_SOURCES or not os.path.exists(path):
         return None
-    src = os.path.join(ROOT, "paper_1108_5815_amd", "csrc", KERNEL_SOURCES[kernel])
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:12]
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        h.update(open(os.path.join(ROOT, "paper_1108_5815_amd", "csrc", f), "rb").read())
+    sha = h.hexdigest()[:12]
     for line in open(path):
         t = line.split()
         if len(t) == 5 and t[0] == "traffic_per_launch" and t[1] == kernel:
