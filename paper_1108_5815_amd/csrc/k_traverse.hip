@@ -309,18 +309,21 @@ __global__ void k_csr(const uint32_t* __restrict__ tgt, int64_t n, int32_t ncell
     off[c] = (int32_t)lo;
 }
 
-// slot of a same-level pair in its target's offset class, or -1.  Written
-// without branches so that the cell fields are all read at once and the
-// table read follows them: a pair waits out two memory latencies, not four.
+// slot of a same-level pair in its target's offset class, or -1.  Everything
+// comes from the two cells' half-grid geometry (centre and half side
+// r = 2^(21 - level)): equal levels are equal r, the root is r = 2^21, and
+// the target's octant within its parent is bit 1 of its centre / r per axis
+// (centre / r = 2 a + 1 for cell index a), so a pair reads two 16-byte cell
+// records and the table, each without waiting for another.
 __device__ inline int32_t fast_slot(const CellArrays& c, int32_t t, int32_t s, const int32_t* slot_of, int R) {
-    const int lv = c.level[t], ls = c.level[s];
     const int4 gt = c.geo[t], gs = c.geo[s];
-    const uint64_t pt = c.prefix[t];
     const int32_t side = max(2 * gt.w, 1);
     const int32_t ox = (gs.x - gt.x) / side, oy = (gs.y - gt.y) / side, oz = (gs.z - gt.z) / side;
-    const bool ok = lv >= 1 && ls == lv && ox >= -R && ox <= R && oy >= -R && oy <= R && oz >= -R && oz <= R;
+    const bool ok = gt.w < (1 << kMaxLevel) && gs.w == gt.w && ox >= -R && ox <= R && oy >= -R && oy <= R &&
+                    oz >= -R && oz <= R;
     const int W = 2 * R + 1;
-    const int cls = (int)(pt & 7u);
+    const int sh = __builtin_ctz((unsigned)max(gt.w, 1)) + 1;
+    const int cls = ((gt.x >> sh) & 1) | (((gt.y >> sh) & 1) << 1) | (((gt.z >> sh) & 1) << 2);
     const size_t at = ok ? (size_t)cls * W * W * W + ((size_t)(ox + R) * W + (oy + R)) * W + (oz + R) : 0;
     const int32_t sl = slot_of[at];
     return ok ? sl : -1;
